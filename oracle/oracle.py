@@ -1,0 +1,245 @@
+"""ctypes wrapper of the FP64 reference (test infrastructure only).
+
+Inputs are plain NumPy arrays; a scene object only needs the attributes of
+``paper_2301_01396_amd.scenes.Scene`` (duck-typed, nothing is imported from
+the product package).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xpbd_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile the reference with g++ (-O3, OpenMP, no fast-math)."""
+    cmd = ["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-shared",
+           "-o", _LIB + ".tmp", _SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+class _Scene(C.Structure):
+    _fields_ = [
+        ("n_verts", C.c_int32), ("rest", _dp), ("inv_mass", _dp),
+        ("n_dist", C.c_int32), ("dist_v", _ip),
+        ("n_bend", C.c_int32), ("bend_v", _ip),
+        ("n_tet", C.c_int32), ("tet_v", _ip), ("tet_nu", _dp),
+        ("contact", C.c_int32), ("contact_thickness", C.c_double),
+        ("contact_compliance", C.c_double),
+        ("n_sets", C.c_int32), ("set_type", _ip), ("set_off", _lp), ("set_items", _ip),
+        ("dt", C.c_double), ("substeps", C.c_int32), ("iterations", C.c_int32),
+        ("gravity", C.c_double * 3),
+        ("tet_gamma_one", C.c_int32), ("emulate_f32", C.c_int32), ("n_threads", C.c_int32),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [("dist_alpha", _dp), ("bend_alpha", _dp), ("tet_E", _dp),
+                ("f_ext", _dp), ("sphere", C.c_double * 4)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build_library()
+        lib = C.CDLL(_LIB)
+        lib.orc_forward.restype = C.c_int
+        lib.orc_adjoint.restype = C.c_int
+        lib.orc_adjoint_implicit.restype = C.c_int
+        lib.orc_constraint.restype = C.c_int
+        lib.orc_rest_data.restype = C.c_int
+        lib.orc_max_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+class OracleScene:
+    """Holds contiguous copies of a scene's arrays for the C reference."""
+
+    def __init__(self, sc, emulate_f32: bool = False, n_threads: int = 1,
+                 tet_gamma_one: bool = False, iterations: Optional[int] = None):
+        self.sc = sc
+        self.rest = np.ascontiguousarray(sc.rest, np.float64)
+        self.inv_mass = np.ascontiguousarray(sc.inv_mass, np.float64)
+        self.dist_v = np.ascontiguousarray(sc.dist_v, np.int32).reshape(-1)
+        self.bend_v = np.ascontiguousarray(sc.bend_v, np.int32).reshape(-1)
+        self.tet_v = np.ascontiguousarray(sc.tet_v, np.int32).reshape(-1)
+        self.tet_nu = np.ascontiguousarray(sc.tet_nu, np.float64)
+        st, off, items = sc.schedule_arrays()
+        self.set_type, self.set_off, self.set_items = st, off, items
+        s = _Scene()
+        s.n_verts = sc.n_verts
+        s.rest, s.inv_mass = _d(self.rest), _d(self.inv_mass)
+        s.n_dist, s.dist_v = sc.n_dist, self.dist_v.ctypes.data_as(_ip)
+        s.n_bend, s.bend_v = sc.n_bend, self.bend_v.ctypes.data_as(_ip)
+        s.n_tet, s.tet_v, s.tet_nu = sc.n_tet, self.tet_v.ctypes.data_as(_ip), _d(self.tet_nu)
+        s.contact = 1 if sc.contact else 0
+        s.contact_thickness = sc.contact_thickness
+        s.contact_compliance = sc.contact_compliance
+        s.n_sets = len(st)
+        s.set_type = st.ctypes.data_as(_ip)
+        s.set_off = off.ctypes.data_as(_lp)
+        s.set_items = items.ctypes.data_as(_ip)
+        s.dt = sc.dt
+        s.substeps = sc.substeps
+        s.iterations = sc.iterations if iterations is None else iterations
+        for a in range(3):
+            s.gravity[a] = sc.gravity[a]
+        s.tet_gamma_one = 1 if tet_gamma_one else 0
+        s.emulate_f32 = 1 if emulate_f32 else 0
+        s.n_threads = n_threads
+        self.s = s
+
+    def params(self, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None, sphere=None):
+        sc = self.sc
+        keep = []
+
+        def arr(a, default, n):
+            a = default if a is None else a
+            a = np.ascontiguousarray(a if a is not None else np.zeros(n), np.float64)
+            keep.append(a)
+            return a
+
+        p = _Params()
+        p.dist_alpha = _d(arr(dist_alpha, sc.dist_alpha, sc.n_dist))
+        p.bend_alpha = _d(arr(bend_alpha, sc.bend_alpha, sc.n_bend))
+        p.tet_E = _d(arr(tet_E, sc.tet_E, sc.n_tet))
+        f = sc.f_ext if f_ext is None else f_ext
+        if f is not None:
+            f = np.ascontiguousarray(f, np.float64)
+            keep.append(f)
+            p.f_ext = _d(f)
+        sph = sc.sphere if sphere is None else sphere
+        for a in range(4):
+            p.sphere[a] = float(sph[a])
+        return p, keep
+
+
+def forward(osc: OracleScene, n_frames: int, x0=None, v0=None, **params):
+    """Returns (x_frames (F,V,3), x_final, v_final)."""
+    sc = osc.sc
+    V = sc.n_verts
+    x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)
+    v0 = np.ascontiguousarray(sc.v0 if v0 is None else v0, np.float64)
+    p, keep = osc.params(**params)
+    xf = np.zeros((n_frames, V, 3))
+    xe = np.zeros((V, 3))
+    ve = np.zeros((V, 3))
+    rc = _load().orc_forward(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0),
+                             _d(xf), _d(xe), _d(ve))
+    if rc:
+        raise RuntimeError(f"orc_forward failed ({rc})")
+    return xf, xe, ve
+
+
+def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=None,
+            **params):
+    """Exact adjoint.  Returns dict of gradients (x0, v0, dist_alpha,
+    bend_alpha, tet_E, f_ext, sphere)."""
+    sc = osc.sc
+    V = sc.n_verts
+    x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)
+    v0 = np.ascontiguousarray(sc.v0 if v0 is None else v0, np.float64)
+    dLdx = np.ascontiguousarray(dLdx, np.float64).reshape(n_frames, V, 3)
+    dv = None if dLdv_final is None else np.ascontiguousarray(dLdv_final, np.float64)
+    p, keep = osc.params(**params)
+    g = {
+        "x0": np.zeros((V, 3)), "v0": np.zeros((V, 3)),
+        "dist_alpha": np.zeros(sc.n_dist), "bend_alpha": np.zeros(sc.n_bend),
+        "tet_E": np.zeros(sc.n_tet), "f_ext": np.zeros((n_frames, V, 3)),
+        "sphere": np.zeros(4),
+    }
+    rc = _load().orc_adjoint(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0), _d(dLdx),
+                             _d(dv), _d(g["x0"]), _d(g["v0"]), _d(g["dist_alpha"]),
+                             _d(g["bend_alpha"]), _d(g["tet_E"]), _d(g["f_ext"]),
+                             _d(g["sphere"]))
+    if rc:
+        raise RuntimeError(f"orc_adjoint failed ({rc})")
+    return g
+
+
+def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, **params):
+    """Converged-limit adjoint of Eq. adjointXPBD (tiny meshes)."""
+    sc = osc.sc
+    V = sc.n_verts
+    x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)
+    v0 = np.ascontiguousarray(sc.v0 if v0 is None else v0, np.float64)
+    dLdx = np.ascontiguousarray(dLdx, np.float64).reshape(n_frames, V, 3)
+    p, keep = osc.params(**params)
+    g = {"x0": np.zeros((V, 3)), "v0": np.zeros((V, 3)),
+         "dist_alpha": np.zeros(sc.n_dist), "bend_alpha": np.zeros(sc.n_bend),
+         "f_ext": np.zeros((n_frames, V, 3))}
+    rc = _load().orc_adjoint_implicit(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0),
+                                      _d(dLdx), _d(g["x0"]), _d(g["v0"]),
+                                      _d(g["dist_alpha"]), _d(g["bend_alpha"]), _d(g["f_ext"]))
+    if rc:
+        raise RuntimeError(f"orc_adjoint_implicit failed ({rc})")
+    return g
+
+
+def constraint(ctype: int, positions, aux, sphere=None, gdir=None, sub: int = 0):
+    """Evaluate one constraint: returns (C, grad[16], hv[16] or None, ok)."""
+    p = np.ascontiguousarray(positions, np.float64).reshape(-1)
+    aux = np.ascontiguousarray(np.atleast_1d(aux), np.float64)
+    sph = None if sphere is None else np.ascontiguousarray(sphere, np.float64)
+    gd = None if gdir is None else np.ascontiguousarray(gdir, np.float64)
+    c = C.c_double(0.0)
+    grad = np.zeros(16)
+    hv = np.zeros(16) if gd is not None else None
+    rc = _load().orc_constraint(ctype, sub, _d(p), _d(aux), _d(sph), _d(gd), C.byref(c),
+                                _d(grad), _d(hv))
+    return c.value, grad, hv, rc == 0
+
+
+def rest_data(osc: OracleScene):
+    sc = osc.sc
+    L = np.zeros(sc.n_dist)
+    th = np.zeros(sc.n_bend)
+    B = np.zeros((sc.n_tet, 9))
+    vol = np.zeros(sc.n_tet)
+    rc = _load().orc_rest_data(C.byref(osc.s), _d(L), _d(th), _d(B), _d(vol))
+    if rc:
+        raise RuntimeError("orc_rest_data failed")
+    return L, th, B.reshape(-1, 3, 3), vol
+
+
+def goal_l2(x_frames, targets, frame_mask):
+    """Goal of Sec. 4.1 with W = I on the masked frames and beta = 0:
+    phi = 1/2 sum_{f in mask} |x(f) - x*(f)|^2 (FP64), and d phi / d x(f)."""
+    x = np.asarray(x_frames, np.float64)
+    t = np.asarray(targets, np.float64)
+    m = np.asarray(frame_mask, bool)
+    d = np.where(m[:, None, None], x - t, 0.0)
+    return 0.5 * float(np.sum(d * d)), d

@@ -1,0 +1,434 @@
+"""Seeded synthetic scene generators shared by the GPU path and its FP64 checker.
+
+This module builds *inputs only*: mesh topology, rest positions, inverse
+masses, the ordered list of independent constraint sets (the Gauss-Seidel
+colour schedule), parameter fields, initial state and external-force fields.
+It holds none of the simulation's arithmetic (no constraint functions, no
+rest lengths, angles or rest-shape matrices, no projections): every consumer
+derives those from the rest positions on its own.
+
+Readings of the paper's unstated scene parameters (all marked "reading"):
+
+* Cloth grids lie in the plane y = 0, y is up, gravity is (0, -9.81, 0);
+  every quad (i, j)-(i+1, j+1) is split along that diagonal.
+* Bending uses one hinge per interior edge: hinge (v0, v1), wing v2 in the
+  triangle (v0, v1, v2) and wing v3 in the triangle (v1, v0, v3).  The paper
+  names a discrete bending term for cloth (Sec. "Cloth Material Parameter
+  Estimation") without a formula; the constraint is the signed dihedral angle.
+* Tet boxes split each cube into 5 tets, alternating the split with the
+  parity of (i + j + k) so neighbouring cubes conform; mass is lumped
+  (rho * V_e / 4 per incident tet corner), the y = 0 face is pinned.
+* The schedule is greedy first-fit colouring over batches of constraints
+  that are independent by construction, then each colour is sorted by its
+  smallest vertex index (locality).  Any schedule whose sets are vertex
+  disjoint is valid input; both consumers replay it in the same order.
+
+RNG: ``numpy.random.default_rng(seed)`` (PCG64), values drawn in the order
+written here.  Seeds: 1 parameters, 2 target parameters, 4 force field,
+5 keyframe force field, 6 serving arrivals.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+DIST, BEND, TET, CONTACT = 0, 1, 2, 3
+TYPE_NAMES = {DIST: "dist", BEND: "bend", TET: "tet", CONTACT: "contact"}
+GRAVITY = (0.0, -9.81, 0.0)
+
+
+@dataclass
+class Scene:
+    """One simulation problem: topology, schedule, options and parameters."""
+
+    rest: np.ndarray                      # (V, 3) float64 rest positions
+    inv_mass: np.ndarray                  # (V,) float64, 0 = pinned
+    dist_v: np.ndarray                    # (n_dist, 2) int32
+    bend_v: np.ndarray                    # (n_bend, 4) int32
+    tet_v: np.ndarray                     # (n_tet, 4) int32
+    tet_nu: np.ndarray                    # (n_tet,) float64 Poisson ratio
+    contact: bool = False
+    contact_thickness: float = 0.005
+    contact_compliance: float = 1e-9
+    # schedule: ordered independent sets of one constraint type each
+    set_type: List[int] = field(default_factory=list)
+    set_items: List[np.ndarray] = field(default_factory=list)
+    dt: float = 1.0 / 60.0
+    substeps: int = 1
+    iterations: int = 20
+    gravity: Tuple[float, float, float] = GRAVITY
+    n_frames: int = 1
+    # parameters (controls)
+    dist_alpha: Optional[np.ndarray] = None   # (n_dist,) compliance [m/N]
+    bend_alpha: Optional[np.ndarray] = None   # (n_bend,) compliance [1/(N m)]
+    tet_E: Optional[np.ndarray] = None        # (n_tet,) Young's modulus [Pa]
+    sphere: Tuple[float, float, float, float] = (0.0, -1e3, 0.0, 1.0)
+    f_ext: Optional[np.ndarray] = None        # (F, V, 3) per-vertex force [N]
+    x0: Optional[np.ndarray] = None           # (V, 3)
+    v0: Optional[np.ndarray] = None           # (V, 3)
+    name: str = ""
+
+    @property
+    def n_verts(self) -> int:
+        return int(self.rest.shape[0])
+
+    @property
+    def n_dist(self) -> int:
+        return int(self.dist_v.shape[0])
+
+    @property
+    def n_bend(self) -> int:
+        return int(self.bend_v.shape[0])
+
+    @property
+    def n_tet(self) -> int:
+        return int(self.tet_v.shape[0])
+
+    def schedule_arrays(self):
+        """Flatten the schedule to (set_type int32, set_offsets int64, set_items int32)."""
+        st = np.asarray(self.set_type, dtype=np.int32)
+        sizes = [len(s) for s in self.set_items]
+        off = np.zeros(len(sizes) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        items = (np.concatenate(self.set_items).astype(np.int32)
+                 if self.set_items else np.zeros(0, np.int32))
+        return st, off, items
+
+    def projections_per_iteration(self) -> int:
+        """Constraint evaluations in one Gauss-Seidel sweep (tets count D and H)."""
+        n = self.n_dist + self.n_bend + 2 * self.n_tet
+        if self.contact:
+            n += int(np.count_nonzero(self.inv_mass > 0))
+        return n
+
+    def projections_per_rollout(self, n_frames: Optional[int] = None) -> int:
+        f = self.n_frames if n_frames is None else n_frames
+        return self.projections_per_iteration() * self.iterations * self.substeps * f
+
+
+# ---------------------------------------------------------------- colouring
+
+def greedy_color(cverts: np.ndarray, batches: List[np.ndarray], n_verts: int) -> np.ndarray:
+    """Greedy first-fit colouring, visiting ``batches`` in order.
+
+    Each batch must be vertex-disjoint (independent by construction), so its
+    members are coloured simultaneously; the result equals sequential
+    first-fit in (batch, member) order.  At most 64 colours.
+    """
+    cverts = np.asarray(cverts)
+    vmask = np.zeros(n_verts, dtype=np.uint64)
+    color = np.full(cverts.shape[0], -1, dtype=np.int32)
+    for b in batches:
+        if len(b) == 0:
+            continue
+        cv = cverts[b]
+        used = np.bitwise_or.reduce(vmask[cv], axis=1)
+        if np.any(used == np.uint64(0xFFFFFFFFFFFFFFFF)):
+            raise ValueError("more than 64 colours needed")
+        free = (~used) & (used + np.uint64(1))
+        c = np.log2(free.astype(np.float64)).astype(np.int32)
+        color[b] = c
+        bits = np.left_shift(np.uint64(1), c.astype(np.uint64))
+        for col in range(cv.shape[1]):
+            vmask[cv[:, col]] |= bits
+    if np.any(color < 0):
+        raise ValueError("a constraint was not in any batch")
+    return color
+
+
+def sets_from_colors(cverts: np.ndarray, color: np.ndarray) -> List[np.ndarray]:
+    """One set per colour (ascending), each sorted by its smallest vertex."""
+    out = []
+    key = np.min(cverts, axis=1) if len(cverts) else np.zeros(0, np.int64)
+    for c in range(int(color.max()) + 1 if len(color) else 0):
+        idx = np.nonzero(color == c)[0]
+        if len(idx) == 0:
+            continue
+        idx = idx[np.argsort(key[idx], kind="stable")]
+        out.append(idx.astype(np.int32))
+    return out
+
+
+# ---------------------------------------------------------------- cloth grid
+
+def cloth_grid_topology(nr: int, nc: int):
+    """Edges (H, V, D in row-major order), hinges and independent batches."""
+    k = np.arange(nr * nc, dtype=np.int64).reshape(nr, nc)
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    eh = np.stack([k[:, :-1].ravel(), k[:, 1:].ravel()], 1)
+    ev = np.stack([k[:-1, :].ravel(), k[1:, :].ravel()], 1)
+    ed = np.stack([k[:-1, :-1].ravel(), k[1:, 1:].ravel()], 1)
+    dist_v = np.concatenate([eh, ev, ed]).astype(np.int32)
+    nh, nv = len(eh), len(ev)
+    # independent batches: H by column parity, V and D by row parity
+    bh_j = jj[:, :-1].ravel()
+    bv_i = ii[:-1, :].ravel()
+    bd_i = ii[:-1, :-1].ravel()
+    dist_batches = [np.nonzero(bh_j % 2 == p)[0] for p in (0, 1)]
+    dist_batches += [nh + np.nonzero(bv_i % 2 == p)[0] for p in (0, 1)]
+    dist_batches += [nh + nv + np.nonzero(bd_i % 2 == p)[0] for p in (0, 1)]
+
+    # hinges: (v0, v1) edge, v2 wing of triangle (v0, v1, v2), v3 of (v1, v0, v3)
+    hh = np.stack([k[1:-1, :-1], k[1:-1, 1:], k[2:, 1:], k[:-2, :-1]], -1).reshape(-1, 4)
+    hv = np.stack([k[:-1, 1:-1], k[1:, 1:-1], k[1:, 2:], k[:-1, :-2]], -1).reshape(-1, 4)
+    hd = np.stack([k[:-1, :-1], k[1:, 1:], k[:-1, 1:], k[1:, :-1]], -1).reshape(-1, 4)
+    bend_v = np.concatenate([hh, hv, hd]).astype(np.int32)
+    n_hh, n_hv = len(hh), len(hv)
+    hi, hj = ii[1:-1, :-1].ravel(), jj[1:-1, :-1].ravel()
+    vi, vj = ii[:-1, 1:-1].ravel(), jj[:-1, 1:-1].ravel()
+    di, dj = ii[:-1, :-1].ravel(), jj[:-1, :-1].ravel()
+    bend_batches = []
+    for a in range(3):
+        for b in range(2):
+            bend_batches.append(np.nonzero((hi % 3 == a) & (hj % 2 == b))[0])
+    for a in range(3):
+        for b in range(2):
+            bend_batches.append(n_hh + np.nonzero((vj % 3 == a) & (vi % 2 == b))[0])
+    for a in range(2):
+        for b in range(2):
+            bend_batches.append(n_hh + n_hv + np.nonzero((di % 2 == a) & (dj % 2 == b))[0])
+    return dist_v, dist_batches, bend_v, bend_batches
+
+
+def cloth_grid(nr: int, nc: int, spacing: float, origin=(0.0, 0.0, 0.0),
+               pinned=(), bending: bool = True, contact: bool = False) -> Scene:
+    """A flat nr x nc particle grid in y = 0, vertex k = i * nc + j at
+    origin + (j * spacing, 0, i * spacing); unit mass; ``pinned`` vertices
+    get inverse mass 0."""
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    rest = np.zeros((nr * nc, 3), dtype=np.float64)
+    rest[:, 0] = origin[0] + jj.ravel() * spacing
+    rest[:, 1] = origin[1]
+    rest[:, 2] = origin[2] + ii.ravel() * spacing
+    inv_mass = np.ones(nr * nc, dtype=np.float64)
+    for p in pinned:
+        inv_mass[p] = 0.0
+    dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
+    if not bending:
+        bend_v = np.zeros((0, 4), np.int32)
+        bend_batches = []
+    sc = Scene(rest=rest, inv_mass=inv_mass, dist_v=dist_v, bend_v=bend_v,
+               tet_v=np.zeros((0, 4), np.int32), tet_nu=np.zeros(0), contact=contact)
+    n_verts = nr * nc
+    dcol = greedy_color(dist_v, dist_batches, n_verts)
+    for s in sets_from_colors(dist_v, dcol):
+        sc.set_type.append(DIST)
+        sc.set_items.append(s)
+    if bending and len(bend_v):
+        bcol = greedy_color(bend_v, bend_batches, n_verts)
+        for s in sets_from_colors(bend_v, bcol):
+            sc.set_type.append(BEND)
+            sc.set_items.append(s)
+    if contact:
+        free = np.nonzero(inv_mass > 0)[0].astype(np.int32)
+        sc.set_type.append(CONTACT)
+        sc.set_items.append(free)
+    sc.x0 = rest.copy()
+    sc.v0 = np.zeros_like(rest)
+    return sc
+
+
+# ---------------------------------------------------------------- tet box
+
+# 5-tet split of a unit cube; corners indexed by (a, b, c) bits.  Even cubes
+# use corner tets at (000), (110), (101), (011); odd cubes the mirror set.
+_EVEN = [((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)),
+         ((1, 1, 0), (0, 1, 0), (1, 0, 0), (1, 1, 1)),
+         ((1, 0, 1), (0, 0, 1), (1, 1, 1), (1, 0, 0)),
+         ((0, 1, 1), (0, 1, 0), (0, 0, 1), (1, 1, 1)),
+         ((1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1))]
+_ODD = [((1, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1)),
+        ((0, 1, 0), (1, 1, 0), (0, 0, 0), (0, 1, 1)),
+        ((0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 0, 0)),
+        ((1, 1, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0)),
+        ((0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1))]
+
+
+def tet_box(n: int, size: float = 1.0, density: float = 1000.0,
+            pin_bottom: bool = True) -> Scene:
+    """n^3 cubes over [0, size]^3, 5 tets per cube, vertex (i, j, k) at
+    (i, j, k) * size / n with index (i * (n + 1) + j) * (n + 1) + k."""
+    n1 = n + 1
+    ii, jj, kk = np.meshgrid(np.arange(n1), np.arange(n1), np.arange(n1), indexing="ij")
+    rest = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1).astype(np.float64) * (size / n)
+
+    def vid(i, j, k):
+        return (i * n1 + j) * n1 + k
+
+    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    par = (ci + cj + ck) % 2
+    tets = np.zeros((len(ci), 5, 4), dtype=np.int64)
+    for t in range(5):
+        for c in range(4):
+            ea, eb, ec = _EVEN[t][c]
+            oa, ob, oc = _ODD[t][c]
+            ve = vid(ci + ea, cj + eb, ck + ec)
+            vo = vid(ci + oa, cj + ob, ck + oc)
+            tets[:, t, c] = np.where(par == 0, ve, vo)
+    tet_v = tets.reshape(-1, 4)
+    # orient every tet so that det[x1-x0, x2-x0, x3-x0] > 0 (mesh validity)
+    p = rest[tet_v]
+    d1, d2, d3 = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
+    vol6 = np.einsum("ij,ij->i", np.cross(d1, d2), d3)
+    neg = vol6 < 0
+    tet_v[neg, 2], tet_v[neg, 3] = tet_v[neg, 3].copy(), tet_v[neg, 2].copy()
+    vol = np.abs(vol6) / 6.0
+    mass = np.zeros(len(rest))
+    np.add.at(mass, tet_v.ravel(), np.repeat(density * vol / 4.0, 4))
+    inv_mass = 1.0 / mass
+    if pin_bottom:
+        inv_mass[rest[:, 1] == 0.0] = 0.0
+    tet_v = tet_v.astype(np.int32)
+    sc = Scene(rest=rest, inv_mass=inv_mass, dist_v=np.zeros((0, 2), np.int32),
+               bend_v=np.zeros((0, 4), np.int32), tet_v=tet_v,
+               tet_nu=np.full(len(tet_v), 0.3))
+    # batches: cube parity class (8) x tet slot (5) are vertex disjoint
+    cls = (ci % 2) * 4 + (cj % 2) * 2 + (ck % 2)
+    tid = np.arange(len(tet_v)).reshape(-1, 5)
+    batches = []
+    for c in range(8):
+        cubes = np.nonzero(cls == c)[0]
+        for t in range(5):
+            batches.append(tid[cubes, t])
+    col = greedy_color(tet_v, batches, len(rest))
+    for s in sets_from_colors(tet_v, col):
+        sc.set_type.append(TET)
+        sc.set_items.append(s)
+    sc.x0 = rest.copy()
+    sc.v0 = np.zeros_like(rest)
+    return sc
+
+
+# ---------------------------------------------------------------- parameter fields
+
+def lognormal(rng, mu, sigma, n):
+    return np.exp(rng.normal(mu, sigma, n))
+
+
+def force_field(seed: int, nr: int, nc: int, n_frames: int, amplitude: float = 2.0,
+                frames_period: int = 20) -> np.ndarray:
+    """Smooth per-vertex force sequence (F, V, 3).
+
+    Per component c: A * sum_m a_m sin(2 pi (p_m u + q_m v + r_m f / 20) + phi_m)
+    with u = j/(nc-1), v = i/(nr-1), p, q, r in {1, 2, 3}, a ~ N(0, 1),
+    phi ~ U[0, 2 pi).  Draw order: p, q, r, a, phi, each of shape (3, 4).
+    """
+    rng = np.random.default_rng(seed)
+    p = rng.integers(1, 4, size=(3, 4))
+    q = rng.integers(1, 4, size=(3, 4))
+    r = rng.integers(1, 4, size=(3, 4))
+    a = rng.standard_normal((3, 4))
+    phi = rng.uniform(0.0, 2.0 * np.pi, (3, 4))
+    u = (np.arange(nc) / max(nc - 1, 1))[None, :]
+    v = (np.arange(nr) / max(nr - 1, 1))[:, None]
+    out = np.zeros((n_frames, nr * nc, 3), dtype=np.float64)
+    for f in range(n_frames):
+        for c in range(3):
+            acc = np.zeros((nr, nc))
+            for m in range(4):
+                acc += a[c, m] * np.sin(2 * np.pi * (p[c, m] * u + q[c, m] * v
+                                                     + r[c, m] * (f + 1) / frames_period)
+                                        + phi[c, m])
+            out[f, :, c] = amplitude * acc.ravel()
+    return out
+
+
+def cloth_alpha(seed: int, n_dist: int, n_bend: int, mu=-16.0, sigma=0.5):
+    rng = np.random.default_rng(seed)
+    return lognormal(rng, mu, sigma, n_dist), lognormal(rng, mu, sigma, n_bend)
+
+
+def tet_material(seed: int, n_tet: int, nu=None):
+    """(E, nu): E ~ lognormal(ln 1e5, 0.3), then nu ~ U[0.3, 0.45]."""
+    rng = np.random.default_rng(seed)
+    E = lognormal(rng, np.log(1e5), 0.3, n_tet)
+    nu_draw = rng.uniform(0.3, 0.45, n_tet)
+    return E, (nu_draw if nu is None else nu)
+
+
+# ---------------------------------------------------------------- configurations
+
+def config_c1(n_frames: int = 60, target: bool = False) -> Scene:
+    """32x32 cloth over a 1 m square, corners of row 0 pinned, ~3k edges,
+    compliance 1e-7 * U[0.5, 2] per edge, dt 1/60, 1 substep, 20 iterations."""
+    n = 32
+    sc = cloth_grid(n, n, 1.0 / (n - 1), pinned=(0, n - 1), bending=False)
+    rng = np.random.default_rng(2 if target else 1)
+    sc.dist_alpha = 1e-7 * rng.uniform(0.5, 2.0, sc.n_dist)
+    sc.bend_alpha = np.zeros(0)
+    sc.tet_E = np.zeros(0)
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 1, 20, n_frames
+    sc.name = "cloth32_dist_fp64"
+    return sc
+
+
+def config_c2(n_frames: int = 30, target: bool = False, n: int = 256) -> Scene:
+    """256x256 cloth centred at the origin with distance + bending + sphere
+    contact (c = (0, -0.35, 0), R = 0.3), dt 1/60, 4 substeps, 30 iterations."""
+    sc = cloth_grid(n, n, 1.0 / (n - 1), origin=(-0.5, 0.0, -0.5), contact=True)
+    sc.dist_alpha, sc.bend_alpha = cloth_alpha(2 if target else 1, sc.n_dist, sc.n_bend)
+    sc.tet_E = np.zeros(0)
+    sc.sphere = (0.0, -0.35, 0.0, 0.3)
+    sc.contact_thickness, sc.contact_compliance = 0.005, 1e-9
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 4, 30, n_frames
+    sc.name = f"cloth{n}_dist_bend_sphere"
+    return sc
+
+
+def config_c3(n_frames: int = 20, target: bool = False, n: int = 64) -> Scene:
+    """64^3-cube tet box (5 tets per cube), bottom pinned, Neo-Hookean,
+    dt 1/60, 2 substeps, 20 iterations."""
+    sc = tet_box(n)
+    E, nu = tet_material(1, sc.n_tet)
+    if target:
+        E = tet_material(2, sc.n_tet, nu=nu)[0]
+    sc.tet_E, sc.tet_nu = E, nu
+    sc.dist_alpha, sc.bend_alpha = np.zeros(0), np.zeros(0)
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 2, 20, n_frames
+    sc.name = f"tetbox{n}_neohookean"
+    return sc
+
+
+def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4) -> Scene:
+    """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
+    distance + bending, per-frame per-vertex force controls, dt 1/60,
+    2 substeps, 20 iterations."""
+    sc = cloth_grid(nr, nc, 1.0 / (nc - 1), pinned=(0, nc - 1))
+    sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)
+    sc.tet_E = np.zeros(0)
+    sc.f_ext = force_field(force_seed, nr, nc, n_frames)
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 2, 20, n_frames
+    sc.name = f"cloth{nc}x{nr}_dist_bend_force"
+    return sc
+
+
+def small_cloth(n: int = 6, frames: int = 3, substeps: int = 2, iterations: int = 5,
+                sphere: bool = True, pinned=None, seed: int = 1) -> Scene:
+    """Tiny cloth with bending (and a sphere under it) for exact checks."""
+    pins = (0, n - 1) if pinned is None else pinned
+    sc = cloth_grid(n, n, 1.0 / (n - 1), origin=(-0.5, 0.0, -0.5), pinned=pins,
+                    contact=sphere)
+    rng = np.random.default_rng(seed)
+    sc.dist_alpha = 1e-6 * rng.uniform(0.5, 2.0, sc.n_dist)
+    sc.bend_alpha = 1e-3 * rng.uniform(0.5, 2.0, sc.n_bend)
+    sc.tet_E = np.zeros(0)
+    sc.sphere = (0.05, -0.28, -0.03, 0.3)
+    sc.contact_thickness, sc.contact_compliance = 0.005, 1e-7
+    sc.v0 = np.zeros_like(sc.rest)
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
+    sc.name = f"cloth{n}_small"
+    return sc
+
+
+def small_tets(n: int = 2, frames: int = 3, substeps: int = 2, iterations: int = 5,
+               seed: int = 1) -> Scene:
+    sc = tet_box(n, size=0.2)
+    E, nu = tet_material(seed, sc.n_tet)
+    sc.tet_E, sc.tet_nu = E * 0.05, nu
+    sc.dist_alpha, sc.bend_alpha = np.zeros(0), np.zeros(0)
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
+    sc.name = f"tetbox{n}_small"
+    return sc
