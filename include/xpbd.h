@@ -1,0 +1,206 @@
+/* xpbd.h - C ABI of the MI355X (gfx950) differentiable XPBD library.
+ *
+ * The library runs the XPBD forward step of DiffXPBD (Stuyck & Chen,
+ * arXiv 2301.01396) and its exact adjoint on one GPU.
+ *
+ *   Forward (Sec. 3.1, Eq. xpbd and the position update after it, inside the
+ *   implicit-Euler step of Eq. xpbdUpdateRule): each frame of length dt is
+ *   split into S substeps of length h = dt / S.  Each substep predicts
+ *   v += h (g + w f_ext), x += h v, resets the multipliers, runs K
+ *   Gauss-Seidel iterations over the ordered independent constraint sets of
+ *   the schedule, projecting each constraint j with
+ *       alpha~ = alpha_j / h^2,  D = sum_k w_k |grad_k C|^2 + alpha~,
+ *       dlambda = (-C - alpha~ lambda_j) / D,  lambda_j += dlambda,
+ *       x_k += w_k dlambda grad_k C,
+ *   then sets v = (x - x_prev) / h.
+ *
+ *   Adjoint: the exact reverse-mode derivative of that computation, through
+ *   every substep, iteration and projection (the adjoint-state recurrence of
+ *   the supplemental Sec. A, Eq. adjoint_state, with the gradient rule
+ *   Eq. gradientRule, applied to each projection using the partial
+ *   derivatives of Sec. 4.3).  Frames are recomputed from per-frame
+ *   checkpoints taken by the forward call, so memory is bounded by one
+ *   frame's record of projection inputs (Sec. 7 notes the linear-in-steps
+ *   memory of storing everything).
+ *
+ * Constraint types:
+ *   XPBD_DIST    C = |x_i - x_j| - L, L the rest length.
+ *   XPBD_BEND    signed dihedral angle minus its rest value, hinge (v0, v1),
+ *                wing v2 of triangle (v0, v1, v2), wing v3 of (v1, v0, v3)
+ *                (the paper's discrete bending term, Sec. 5.1).
+ *   XPBD_TET     stable Neo-Hookean in XPBD form (Sec. 5.2): deviatoric
+ *                C_D = sqrt(tr F^T F) then hydrostatic C_H = det F - gamma,
+ *                F = Ds Dm^-1, alpha_D = 1/(mu V), alpha_H = 1/(lambda V),
+ *                gamma = 1 + mu/lambda (or 1, option), separate multipliers.
+ *   XPBD_CONTACT one per vertex listed in the contact sets: a compliant
+ *                collision constraint keeping the separation from a sphere
+ *                (c, R) at least the thickness tau (Sec. 4.5):
+ *                C = |x - c| - R - tau, projected only while C < 0.
+ *
+ * Conventions for every entry point:
+ *   - Returns xpbd_status; never throws; never frees caller memory.
+ *   - Host arrays passed to xpbd_create are copied; the caller may free
+ *     them when it returns.
+ *   - Device pointers passed to forward/adjoint/goal belong to the caller and
+ *     must stay valid (and unchanged, for parameters) until the stream has
+ *     completed the call and, for parameters, until the matching adjoint.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t, NULL =
+ *     the default stream).  A kernel fault surfaces at a later call as
+ *     XPBD_ERR_HIP.
+ *   - Vectors are row-major [V][3] (or [F][V][3]) in the context's dtype.
+ *   - One context per host thread at a time.  On error, xpbd_last_error
+ *     returns a message.
+ */
+#ifndef XPBD_H
+#define XPBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xpbd_ctx_s* xpbd_ctx;
+
+typedef enum {
+  XPBD_OK = 0,
+  XPBD_ERR_INVALID = 1,   /* bad argument, mesh, or schedule */
+  XPBD_ERR_OOM = 2,       /* allocation failed or hbm_budget_bytes exceeded */
+  XPBD_ERR_HIP = 3,       /* HIP runtime error (includes earlier async faults) */
+  XPBD_ERR_STATE = 4,     /* adjoint without a matching forward */
+  XPBD_ERR_NONFINITE = 5  /* non-finite input parameter */
+} xpbd_status;
+
+typedef enum { XPBD_F32 = 0, XPBD_F64 = 1 } xpbd_dtype;
+typedef enum { XPBD_DIST = 0, XPBD_BEND = 1, XPBD_TET = 2, XPBD_CONTACT = 3 } xpbd_ctype;
+
+typedef struct {
+  int32_t n_verts;
+  const double* rest_pos;   /* host [V][3]: rest shape (rest lengths, angles, Dm) */
+  const double* inv_mass;   /* host [V]: inverse mass w, 0 = pinned (infinite mass) */
+} xpbd_mesh_desc;
+
+typedef struct {
+  int32_t n_dist; const int32_t* dist_v;   /* host [n_dist][2] */
+  int32_t n_bend; const int32_t* bend_v;   /* host [n_bend][4] hinge v0 v1, wings v2 v3 */
+  int32_t n_tet;  const int32_t* tet_v;    /* host [n_tet][4], positive rest volume */
+  const double* tet_nu;                    /* host [n_tet] Poisson ratio (fixed) */
+  int32_t contact;                         /* 1: contact sets may list free vertices */
+  double contact_thickness;                /* tau */
+  double contact_compliance;               /* alpha of every contact constraint */
+} xpbd_constraint_desc;
+
+/* One Gauss-Seidel iteration visits these sets in order.  Set s has type
+ * set_type[s] and items set_items[set_offsets[s] .. set_offsets[s+1]):
+ * constraint indices of that type (for XPBD_TET one item is both the D and
+ * the H projection; for XPBD_CONTACT an item is a vertex index).  Within a
+ * set no vertex may appear twice (the set is independent), every distance,
+ * bending and tet constraint must appear exactly once in the schedule, and a
+ * contact vertex at most once and only if its inverse mass is > 0.
+ * Otherwise xpbd_create returns XPBD_ERR_INVALID. */
+typedef struct {
+  int32_t n_sets;
+  const int32_t* set_type;     /* host [n_sets] xpbd_ctype */
+  const int64_t* set_offsets;  /* host [n_sets + 1] */
+  const int32_t* set_items;    /* host [set_offsets[n_sets]] */
+} xpbd_schedule_desc;
+
+typedef struct {
+  double dt;                 /* frame length (> 0) */
+  int32_t substeps;          /* S >= 1 */
+  int32_t iterations;        /* K >= 0 */
+  double gravity[3];
+  xpbd_dtype dtype;          /* arithmetic and storage type of the state */
+  size_t hbm_budget_bytes;   /* 0 = no limit; else XPBD_ERR_OOM past it */
+  int32_t tet_gamma_one;     /* 1: gamma = 1 (the formula as printed); 0: 1 + mu/lambda */
+  int32_t tape_mode;         /* 0 auto, 1 record a whole frame, 2 one substep at a time */
+} xpbd_options;
+
+/* Validate and upload a problem.  Computes rest lengths, rest dihedral
+ * angles, Dm^-1 and rest volumes from rest_pos; reorders the items of each
+ * set (order inside an independent set does not change the result).
+ * Errors: XPBD_ERR_INVALID (indices out of range, a set that is not
+ * independent, a constraint missing from or repeated in the schedule,
+ * zero-length edge, degenerate rest triangle, non-positive rest volume,
+ * bad options), XPBD_ERR_OOM, XPBD_ERR_HIP.  *out is NULL on error. */
+xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* cons,
+                        const xpbd_schedule_desc* schedule, const xpbd_options* opt,
+                        xpbd_ctx* out);
+xpbd_status xpbd_destroy(xpbd_ctx ctx);
+
+/* Controls (Sec. 4.4): device arrays in the context dtype; NULL compliance
+ * arrays mean 0 (rigid); tet_E is required when there are tets. */
+typedef struct {
+  const void* dist_compliance;   /* device [n_dist] alpha (m/N) */
+  const void* bend_compliance;   /* device [n_bend] alpha */
+  const void* tet_E;             /* device [n_tet] Young's modulus (Pa) */
+  const void* f_ext;             /* device [F][V][3] per-vertex force, or NULL */
+  double sphere[4];              /* cx, cy, cz, R of the contact sphere */
+} xpbd_params;
+
+/* Roll out n_frames frames from (x0, v0) (device [V][3]; v0 of pinned
+ * vertices is ignored).  Writes the end-of-frame positions to x_frames
+ * (device [F][V][3], may be NULL) and the final state to x_final, v_final
+ * (device [V][3], may be NULL).  Keeps per-frame checkpoints for
+ * xpbd_adjoint.  Errors: XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP. */
+xpbd_status xpbd_forward(xpbd_ctx ctx, const void* x0, const void* v0, const xpbd_params* p,
+                         int32_t n_frames, void* x_frames, void* x_final, void* v_final,
+                         void* stream);
+
+/* Gradient outputs (device).  Any pointer may be NULL.  Parameter gradients
+ * are accumulated and returned in FP64; state-shaped ones in the ctx dtype.
+ * Pinned vertices get zero v0 and f_ext gradients. */
+typedef struct {
+  double* dist_compliance;   /* [n_dist] dL/dalpha */
+  double* bend_compliance;   /* [n_bend] dL/dalpha */
+  double* tet_E;             /* [n_tet] dL/dE (nu fixed) */
+  void* f_ext;               /* [F][V][3] dL/df_ext */
+  void* x0;                  /* [V][3] dL/dx0 */
+  void* v0;                  /* [V][3] dL/dv0 */
+  double* sphere;            /* [4] dL/d(cx, cy, cz, R) */
+} xpbd_grads;
+
+/* Exact adjoint of the preceding xpbd_forward on this context for a goal
+ * with gradient dLdx_frames (device [F][V][3], row f = dL/dx(end of frame
+ * f); frames with frame_mask[f] == 0 are not read; frame_mask is host [F]
+ * or NULL = all) plus dLdv_final (device [V][3] or NULL).  `p` must be the
+ * same parameters, with unchanged contents, as in that forward.
+ * Errors: XPBD_ERR_STATE (no forward, or different parameter pointers),
+ * XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP. */
+xpbd_status xpbd_adjoint(xpbd_ctx ctx, const xpbd_params* p, const void* dLdx_frames,
+                         const uint8_t* frame_mask, const void* dLdv_final,
+                         const xpbd_grads* out, void* stream);
+
+/* Goal of Sec. 4.1 with W = I on the frames where frame_mask[f] != 0 and
+ * beta = 0: phi = 1/2 sum_f |x(f) - x*(f)|^2 reduced in FP64 into *loss
+ * (device double), and dphi/dx(f) = x(f) - x*(f) on masked frames, 0
+ * elsewhere, into dLdx (device [F][V][3], may be NULL). */
+xpbd_status xpbd_goal_l2(xpbd_ctx ctx, const void* x_frames, const void* targets,
+                         const uint8_t* frame_mask, int32_t n_frames, double* loss,
+                         void* dLdx, void* stream);
+
+typedef struct {
+  int32_t n_verts, n_dist, n_bend, n_tet, n_contact, n_sets;
+  int64_t projections_per_iteration;   /* tets count D and H; contacts counted as evaluated */
+  int64_t device_bytes;                /* device memory held by the context now */
+  int64_t tape_bytes_per_iteration;    /* record of projection inputs, one iteration */
+  int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep) */
+} xpbd_info;
+xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
+
+/* Kernel timing for measurement: when enabled, every launch of the
+ * projection and reverse kernels is bracketed by HIP events on the call's
+ * stream; xpbd_profile_read synchronises them and returns, per kernel family
+ * (index = 2 * type for forward projections, 2 * type + 1 for reverse),
+ * the number of launches, total milliseconds and total items processed. */
+xpbd_status xpbd_profile_enable(xpbd_ctx ctx, int32_t on);
+xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[8], double ms[8], int64_t items[8]);
+
+const char* xpbd_last_error(xpbd_ctx ctx);
+const char* xpbd_status_string(xpbd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XPBD_H */

@@ -1,0 +1,927 @@
+// Host implementation of the C ABI in include/xpbd.h: problem validation,
+// device layout, the frame / substep / iteration / set loops that launch the
+// forward and reverse kernels, per-frame checkpoints and the record of
+// projection inputs replayed by the adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xpbd.h"
+#include "xpbd_kernels.hpp"
+
+using namespace xpbd;
+
+namespace {
+
+struct Fail {
+  xpbd_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(xpbd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Fail{st, buf};
+}
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) fail(XPBD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+inline unsigned nblocks(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct SetInfo {
+  int type;
+  int begin;   // first internal record of this set within its type's arrays
+  int count;
+  size_t tape_off;   // byte offset of this set's record inside one iteration
+};
+
+// bytes of the per-projection record per item, by type (scaled by sizeof T / 4)
+inline size_t tape_item_bytes(int type, size_t tsz) {
+  switch (type) {
+    case XPBD_DIST: return 4 * tsz;
+    case XPBD_BEND: return 10 * tsz;
+    case XPBD_TET: return 12 * tsz;
+    default: return 4 * tsz;
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct xpbd_ctx_s {
+  std::string err;
+  xpbd_dtype dtype;
+  size_t tsz;
+  int V = 0, n_dist = 0, n_bend = 0, n_tet = 0, n_contact = 0;
+  double dt, h;
+  int S, K;
+  double g[3];
+  size_t budget;
+  int gamma_one;
+  int tape_mode_opt;
+  int tape_mode_used = 0;
+  double tau = 0, alpha_c = 0;
+  std::vector<SetInfo> sets;
+  size_t iter_tape_bytes = 0;
+  int64_t proj_per_iter = 0;
+
+  // device memory registry
+  std::vector<DevBuf> bufs;
+  size_t dev_bytes = 0;
+
+  // persistent records (internal order)
+  int2* dist_idx = nullptr; void* dist_rest = nullptr; int* dist_perm = nullptr;
+  int4* bend_idx = nullptr; void* bend_theta0 = nullptr; int* bend_perm = nullptr;
+  int4* tet_idx = nullptr; void* tet_B = nullptr; int* tet_perm = nullptr; double* tet_nu = nullptr;
+  double* tet_vol = nullptr;
+  int* contact_vid = nullptr;
+  void* w = nullptr;              // [V] inverse mass (T)
+  // per forward
+  void* dist_at = nullptr; void* bend_at = nullptr;
+  void* tet_atD = nullptr; void* tet_atH = nullptr; void* tet_gamma = nullptr;
+  void* dist_lam = nullptr; void* bend_lam = nullptr; void* tet_lamD = nullptr; void* tet_lamH = nullptr;
+  void* contact_lam = nullptr;
+  void* X = nullptr; void* Vv = nullptr; void* Xp = nullptr;
+  int* flag = nullptr;
+  double* parts = nullptr; size_t parts_n = 0;
+  // checkpoints
+  void* ckX = nullptr; void* ckV = nullptr; int ck_frames = 0;
+  // adjoint
+  void* XB = nullptr; void* VB = nullptr;
+  void* dist_lamb = nullptr; void* dist_ab = nullptr; double* dist_acc = nullptr;
+  void* bend_lamb = nullptr; void* bend_ab = nullptr; double* bend_acc = nullptr;
+  void* tet_lambD = nullptr; void* tet_lambH = nullptr; void* tet_eb = nullptr; double* tet_acc = nullptr;
+  void* contact_lamb = nullptr; void* contact_sacc = nullptr;
+  void* tape = nullptr; size_t tape_cap = 0;
+
+  // forward bookkeeping for the adjoint
+  bool have_forward = false;
+  int fwd_frames = 0;
+  xpbd_params fwd_params{};
+
+  // profiling
+  int prof_stride = 0;
+  int64_t prof_counter = 0;
+  struct Ev { hipEvent_t a, b; int fam; int64_t items; };
+  std::vector<Ev> ev_pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  int64_t prof_launch[8] = {0};
+  double prof_ms[8] = {0};
+  int64_t prof_items[8] = {0};
+
+  ~xpbd_ctx_s() {
+    for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+    for (auto& e : ev_pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
+
+  void* alloc(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    size_t b = align256(bytes);
+    if (budget && dev_bytes + b > budget)
+      fail(XPBD_ERR_OOM, "device memory budget of %zu bytes exceeded (%zu in use, %zu requested)", budget,
+           dev_bytes, b);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(XPBD_ERR_OOM, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+    }
+    bufs.push_back({p, b});
+    dev_bytes += b;
+    return p;
+  }
+  void release(void*& p) {
+    if (!p) return;
+    for (auto it = bufs.begin(); it != bufs.end(); ++it)
+      if (it->p == p) {
+        (void)hipFree(p);
+        dev_bytes -= it->n;
+        bufs.erase(it);
+        break;
+      }
+    p = nullptr;
+  }
+  template <class U> void upload(void* dst, const std::vector<U>& v) {
+    if (!v.empty()) HIPCHK(hipMemcpy(dst, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
+  }
+};
+
+namespace {
+
+// ===================================================================== rest data (host, FP64)
+
+struct H3 { double x, y, z; };
+inline H3 hsub(H3 a, H3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double hdot(H3 a, H3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline H3 hcross(H3 a, H3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline H3 hv(const double* p, int k) { return {p[3 * k], p[3 * k + 1], p[3 * k + 2]}; }
+
+// signed dihedral angle of hinge (p0, p1) with wings p2, p3; false if degenerate
+bool rest_dihedral(H3 p0, H3 p1, H3 p2, H3 p3, double* th) {
+  H3 e = hsub(p1, p0), a = hsub(p2, p0), b = hsub(p3, p0);
+  H3 n1 = hcross(e, a), n2 = hcross(b, e);
+  double le2 = hdot(e, e);
+  if (!(le2 > 0) || !(hdot(n1, n1) > 0) || !(hdot(n2, n2) > 0)) return false;
+  *th = std::atan2(hdot(hcross(n1, n2), e) / std::sqrt(le2), hdot(n1, n2));
+  return true;
+}
+
+// Dm^-1 (row-major) and rest volume; false if det <= 0
+bool rest_tet(H3 p0, H3 p1, H3 p2, H3 p3, double B[9], double* vol) {
+  H3 c0 = hsub(p1, p0), c1 = hsub(p2, p0), c2 = hsub(p3, p0);
+  // Dm = [c0 c1 c2]; det = c0 . (c1 x c2); inverse rows = (c1 x c2, c2 x c0, c0 x c1) / det
+  H3 r0 = hcross(c1, c2), r1 = hcross(c2, c0), r2 = hcross(c0, c1);
+  double det = hdot(c0, r0);
+  if (!(det > 0)) return false;
+  const H3 rows[3] = {r0, r1, r2};
+  for (int r = 0; r < 3; ++r) {
+    B[3 * r + 0] = rows[r].x / det;
+    B[3 * r + 1] = rows[r].y / det;
+    B[3 * r + 2] = rows[r].z / det;
+  }
+  *vol = det / 6.0;
+  return true;
+}
+
+template <class T> std::vector<T> cast_vec(const std::vector<double>& v) {
+  std::vector<T> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+  return o;
+}
+
+// ===================================================================== profiling
+
+void prof_begin(xpbd_ctx c, hipStream_t st, int fam, int64_t items, xpbd_ctx_s::Ev* out, bool* on) {
+  *on = false;
+  if (!c->prof_stride) return;
+  if ((c->prof_counter++ % c->prof_stride) != 0) return;
+  hipEvent_t a, b;
+  if (!c->ev_free.empty()) {
+    a = c->ev_free.back().first;
+    b = c->ev_free.back().second;
+    c->ev_free.pop_back();
+  } else {
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+  }
+  HIPCHK(hipEventRecord(a, st));
+  *out = {a, b, fam, items};
+  *on = true;
+}
+void prof_end(xpbd_ctx c, hipStream_t st, xpbd_ctx_s::Ev& e, bool on) {
+  if (!on) return;
+  HIPCHK(hipEventRecord(e.b, st));
+  c->ev_pending.push_back(e);
+}
+
+// ===================================================================== launches
+
+template <class T> struct Ops {
+  using V4 = Vec4<T>;
+
+  static void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(XPBD_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+
+  static Sphere<T> sphere(xpbd_ctx c, const double* s) {
+    return Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
+  }
+
+  // one forward projection launch of set si
+  static void project(xpbd_ctx c, const SetInfo& si, bool first, V4* tape, const double* sph, hipStream_t st) {
+    if (si.count == 0) return;
+    unsigned nb = nblocks(si.count);
+    V4* X = (V4*)c->X;
+    xpbd_ctx_s::Ev ev;
+    bool on;
+    prof_begin(c, st, 2 * si.type, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
+#define XPBD_LAUNCH(KERN, ...)                                                          \
+  do {                                                                                  \
+    if (first) {                                                                        \
+      if (tape) KERN<T, true, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                \
+      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                    \
+    } else {                                                                            \
+      if (tape) KERN<T, false, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);               \
+      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                   \
+    }                                                                                   \
+  } while (0)
+    switch (si.type) {
+      case XPBD_DIST:
+        XPBD_LAUNCH(k_dist, c->dist_idx, (const T*)c->dist_rest, (const T*)c->dist_at, (T*)c->dist_lam, X,
+                    si.begin, si.count, tape);
+        break;
+      case XPBD_BEND:
+        XPBD_LAUNCH(k_bend, c->bend_idx, (const T*)c->bend_theta0, (const T*)c->bend_at, (T*)c->bend_lam, X,
+                    si.begin, si.count, tape);
+        break;
+      case XPBD_TET: {
+        TetRec<T> R{c->tet_idx, (const T*)c->tet_B, (const T*)c->tet_atD, (const T*)c->tet_atH,
+                    (const T*)c->tet_gamma, c->n_tet};
+        XPBD_LAUNCH(k_tet, R, (T*)c->tet_lamD, (T*)c->tet_lamH, X, si.begin, si.count, tape);
+        break;
+      }
+      default:
+        XPBD_LAUNCH(k_contact, c->contact_vid, (T*)c->contact_lam, X, si.begin, si.count, sphere(c, sph), tape);
+        break;
+    }
+#undef XPBD_LAUNCH
+    check_launch();
+    prof_end(c, st, ev, on);
+  }
+
+  static void reverse(xpbd_ctx c, const SetInfo& si, bool first, bool last, const V4* tape, const double* sph,
+                      hipStream_t st) {
+    if (si.count == 0) return;
+    unsigned nb = nblocks(si.count);
+    V4* XB = (V4*)c->XB;
+    xpbd_ctx_s::Ev ev;
+    bool on;
+    prof_begin(c, st, 2 * si.type + 1, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
+#define XPBD_LAUNCH(KERN, ...)                                                          \
+  do {                                                                                  \
+    if (first) {                                                                        \
+      if (last) KERN<T, true, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                \
+      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                    \
+    } else {                                                                            \
+      if (last) KERN<T, false, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);               \
+      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                   \
+    }                                                                                   \
+  } while (0)
+    switch (si.type) {
+      case XPBD_DIST:
+        XPBD_LAUNCH(k_dist_rev, c->dist_idx, (const T*)c->dist_rest, (const T*)c->dist_at, XB, (T*)c->dist_lamb,
+                    (T*)c->dist_ab, c->dist_acc, si.begin, si.count, tape);
+        break;
+      case XPBD_BEND:
+        XPBD_LAUNCH(k_bend_rev, c->bend_idx, (const T*)c->bend_theta0, (const T*)c->bend_at, XB,
+                    (T*)c->bend_lamb, (T*)c->bend_ab, c->bend_acc, si.begin, si.count, tape);
+        break;
+      case XPBD_TET: {
+        TetRec<T> R{c->tet_idx, (const T*)c->tet_B, (const T*)c->tet_atD, (const T*)c->tet_atH,
+                    (const T*)c->tet_gamma, c->n_tet};
+        XPBD_LAUNCH(k_tet_rev, R, XB, (T*)c->tet_lambD, (T*)c->tet_lambH, (T*)c->tet_eb, c->tet_acc, si.begin,
+                    si.count, tape);
+        break;
+      }
+      default:
+        XPBD_LAUNCH(k_contact_rev, c->contact_vid, XB, (T*)c->contact_lamb, (V4*)c->contact_sacc, si.begin,
+                    si.count, sphere(c, sph), tape);
+        break;
+    }
+#undef XPBD_LAUNCH
+    check_launch();
+    prof_end(c, st, ev, on);
+  }
+
+  // tape pointer of set k, iteration it, substep slot s (within the tape buffer)
+  static V4* tape_at(xpbd_ctx c, int slot, int it, const SetInfo& si) {
+    char* base = (char*)c->tape + ((size_t)slot * c->K + it) * c->iter_tape_bytes + si.tape_off;
+    return (V4*)base;
+  }
+
+  // one substep of Eq. xpbdUpdateRule; tape slot < 0 means no record
+  static void substep(xpbd_ctx c, const T* f, const double* sph, int slot, hipStream_t st) {
+    const int V = c->V;
+    T h = (T)c->h;
+    k_predict<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->X, (V4*)c->Vv, (V4*)c->Xp, f, h, (T)c->g[0], (T)c->g[1],
+                                                (T)c->g[2], V);
+    check_launch();
+    for (int it = 0; it < c->K; ++it)
+      for (const SetInfo& si : c->sets)
+        project(c, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, sph, st);
+    k_velocity<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (V4*)c->Vv, (const V4*)c->Xp,
+                                                 (T)(1.0 / c->h), V);
+    check_launch();
+  }
+
+  static void reverse_substep(xpbd_ctx c, T* fbar, const double* sph, double* dsph, int slot, hipStream_t st) {
+    const int V = c->V;
+    T h = (T)c->h, ih = (T)(1.0 / c->h);
+    k_rev_velocity<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const V4*)c->VB, ih, V);
+    check_launch();
+    for (int it = c->K - 1; it >= 0; --it)
+      for (int k = (int)c->sets.size() - 1; k >= 0; --k) {
+        const SetInfo& si = c->sets[k];
+        reverse(c, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), sph, st);
+      }
+    if (c->K > 0 && dsph)
+      for (const SetInfo& si : c->sets)
+        if (si.type == XPBD_CONTACT && si.count > 0) {
+          k_sphere_reduce<T><<<1, 1024, 0, st>>>((const V4*)c->contact_sacc, si.begin, si.count, dsph);
+          check_launch();
+        }
+    k_rev_predict<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, fbar, h, ih, V);
+    check_launch();
+  }
+
+  template <class U> static void fill(U* p, U v, size_t n, hipStream_t st) {
+    if (!n || !p) return;
+    k_fill<U><<<nblocks(n), kBlock, 0, st>>>(p, v, n);
+    check_launch();
+  }
+
+  static void gather_params(xpbd_ctx c, const xpbd_params* p, hipStream_t st) {
+    HIPCHK(hipMemsetAsync(c->flag, 0, sizeof(int), st));
+    double ih2 = 1.0 / (c->h * c->h);
+    if (c->n_dist)
+      k_gather_alpha<T><<<nblocks(c->n_dist), kBlock, 0, st>>>((const T*)p->dist_compliance, c->dist_perm,
+                                                               (T*)c->dist_at, (T)ih2, c->n_dist, c->flag);
+    if (c->n_bend)
+      k_gather_alpha<T><<<nblocks(c->n_bend), kBlock, 0, st>>>((const T*)p->bend_compliance, c->bend_perm,
+                                                               (T*)c->bend_at, (T)ih2, c->n_bend, c->flag);
+    if (c->n_tet)
+      k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_perm, c->tet_nu,
+                                                            c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
+                                                            (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
+    check_launch();
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flag) fail(XPBD_ERR_NONFINITE, "a compliance or Young's modulus is negative, zero (E) or not finite");
+    for (int a = 0; a < 4; ++a)
+      if (!std::isfinite(p->sphere[a])) fail(XPBD_ERR_NONFINITE, "sphere parameter %d is not finite", a);
+  }
+
+  static void forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_params* p, int F, void* xf,
+                      void* x_final, void* v_final, hipStream_t st) {
+    const int V = c->V;
+    const size_t vb = (size_t)V * sizeof(V4);
+    if (c->ck_frames < F) {
+      c->release(c->ckX);
+      c->release(c->ckV);
+      c->ck_frames = 0;
+      c->ckX = c->alloc((size_t)F * vb);
+      c->ckV = c->alloc((size_t)F * vb);
+      c->ck_frames = F;
+    }
+    gather_params(c, p, st);
+    k_pack<T><<<nblocks(V), kBlock, 0, st>>>((const T*)x0, (const T*)v0, (const T*)c->w, (V4*)c->X, (V4*)c->Vv, V);
+    check_launch();
+    for (int f = 0; f < F; ++f) {
+      HIPCHK(hipMemcpyAsync((char*)c->ckX + f * vb, c->X, vb, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync((char*)c->ckV + f * vb, c->Vv, vb, hipMemcpyDeviceToDevice, st));
+      const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
+      for (int s = 0; s < c->S; ++s) substep(c, ff, p->sphere, -1, st);
+      if (xf) {
+        k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (T*)xf + (size_t)f * 3 * V, V);
+        check_launch();
+      }
+    }
+    if (x_final) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (T*)x_final, V);
+    if (v_final) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->Vv, (T*)v_final, V);
+    check_launch();
+  }
+
+  static void restore(xpbd_ctx c, int f, hipStream_t st) {
+    const size_t vb = (size_t)c->V * sizeof(V4);
+    HIPCHK(hipMemcpyAsync(c->X, (char*)c->ckX + f * vb, vb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->Vv, (char*)c->ckV + f * vb, vb, hipMemcpyDeviceToDevice, st));
+  }
+
+  static void adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx, const uint8_t* mask, const void* dLdv,
+                      const xpbd_grads* out, int mode, hipStream_t st) {
+    const int V = c->V, F = c->fwd_frames, S = c->S;
+    // gradients wrt the per-constraint parameters accumulate in FP64
+    fill<double>(c->dist_acc, 0.0, c->n_dist, st);
+    fill<double>(c->bend_acc, 0.0, c->n_bend, st);
+    fill<double>(c->tet_acc, 0.0, c->n_tet, st);
+    if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
+    if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
+    // parameters used by the recomputation (same as the forward's)
+    gather_params(c, p, st);
+    k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
+    check_launch();
+    for (int f = F - 1; f >= 0; --f) {
+      if (dLdx && (!mask || mask[f])) {
+        k_adj_inject<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);
+        check_launch();
+      }
+      const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
+      T* fb = out->f_ext ? (T*)out->f_ext + (size_t)f * 3 * V : nullptr;
+      if (mode == 1) {
+        restore(c, f, st);
+        for (int s = 0; s < S; ++s) substep(c, ff, p->sphere, s, st);
+        for (int s = S - 1; s >= 0; --s) reverse_substep(c, fb, p->sphere, out->sphere, s, st);
+      } else {
+        for (int s = S - 1; s >= 0; --s) {
+          restore(c, f, st);
+          for (int q = 0; q < s; ++q) substep(c, ff, p->sphere, -1, st);
+          substep(c, ff, p->sphere, 0, st);
+          reverse_substep(c, fb, p->sphere, out->sphere, 0, st);
+        }
+      }
+    }
+    if (out->x0) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->XB, (T*)out->x0, V);
+    if (out->v0) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->VB, (T*)out->v0, V);
+    check_launch();
+    double ih2 = 1.0 / (c->h * c->h);
+    if (out->dist_compliance && c->n_dist)
+      k_scatter_alpha_grad<<<nblocks(c->n_dist), kBlock, 0, st>>>(c->dist_acc, c->dist_perm, out->dist_compliance,
+                                                                  ih2, c->n_dist);
+    if (out->bend_compliance && c->n_bend)
+      k_scatter_alpha_grad<<<nblocks(c->n_bend), kBlock, 0, st>>>(c->bend_acc, c->bend_perm, out->bend_compliance,
+                                                                  ih2, c->n_bend);
+    if (out->tet_E && c->n_tet)
+      k_scatter_E_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_E,
+                                                                out->tet_E, c->n_tet);
+    check_launch();
+  }
+
+  static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, int F, double* loss,
+                   void* dLdx, hipStream_t st) {
+    const size_t n = (size_t)3 * c->V;
+    const size_t nb = nblocks(n);
+    if (c->parts_n < nb * F) {
+      c->release(*(void**)&c->parts);
+      c->parts = (double*)c->alloc(nb * F * sizeof(double));
+      c->parts_n = nb * F;
+    }
+    for (int f = 0; f < F; ++f) {
+      int on = mask ? (mask[f] != 0) : 1;
+      k_goal<T><<<nb, kBlock, 0, st>>>((const T*)xf + f * n, (const T*)tg + f * n,
+                                       dLdx ? (T*)dLdx + f * n : nullptr, n, on, c->parts + f * nb);
+    }
+    check_launch();
+    if (loss) k_sum_parts<<<1, 1024, 0, st>>>(c->parts, nb * F, loss, 0);
+    check_launch();
+  }
+};
+
+// ===================================================================== create
+
+void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, const xpbd_schedule_desc* sd,
+           const xpbd_options* o) {
+  if (!m || !cd || !sd || !o) fail(XPBD_ERR_INVALID, "null descriptor");
+  if (o->dtype != XPBD_F32 && o->dtype != XPBD_F64) fail(XPBD_ERR_INVALID, "bad dtype");
+  if (!(o->dt > 0) || o->substeps < 1 || o->iterations < 0) fail(XPBD_ERR_INVALID, "bad dt/substeps/iterations");
+  if (m->n_verts <= 0 || !m->rest_pos || !m->inv_mass) fail(XPBD_ERR_INVALID, "empty mesh");
+  if (cd->n_dist < 0 || cd->n_bend < 0 || cd->n_tet < 0) fail(XPBD_ERR_INVALID, "negative counts");
+  if ((cd->n_dist && !cd->dist_v) || (cd->n_bend && !cd->bend_v) || (cd->n_tet && (!cd->tet_v || !cd->tet_nu)))
+    fail(XPBD_ERR_INVALID, "missing constraint arrays");
+  if (o->tape_mode < 0 || o->tape_mode > 2) fail(XPBD_ERR_INVALID, "bad tape_mode");
+  c->dtype = o->dtype;
+  c->tsz = o->dtype == XPBD_F32 ? 4 : 8;
+  c->V = m->n_verts;
+  c->n_dist = cd->n_dist;
+  c->n_bend = cd->n_bend;
+  c->n_tet = cd->n_tet;
+  c->dt = o->dt;
+  c->S = o->substeps;
+  c->K = o->iterations;
+  c->h = o->dt / o->substeps;
+  for (int a = 0; a < 3; ++a) c->g[a] = o->gravity[a];
+  c->budget = o->hbm_budget_bytes;
+  c->gamma_one = o->tet_gamma_one ? 1 : 0;
+  c->tape_mode_opt = o->tape_mode;
+  c->tau = cd->contact_thickness;
+  c->alpha_c = cd->contact_compliance;
+  const int V = c->V;
+  for (int k = 0; k < V; ++k) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(m->rest_pos[3 * k + a])) fail(XPBD_ERR_INVALID, "rest position %d not finite", k);
+    if (!(m->inv_mass[k] >= 0) || !std::isfinite(m->inv_mass[k])) fail(XPBD_ERR_INVALID, "bad inverse mass at %d", k);
+  }
+  auto check_idx = [&](const int32_t* v, int n, int k, const char* what) {
+    for (int64_t i = 0; i < (int64_t)n * k; ++i)
+      if (v[i] < 0 || v[i] >= V) fail(XPBD_ERR_INVALID, "%s index out of range", what);
+  };
+  check_idx(cd->dist_v, cd->n_dist, 2, "distance");
+  check_idx(cd->bend_v, cd->n_bend, 4, "bending");
+  check_idx(cd->tet_v, cd->n_tet, 4, "tet");
+  for (int t = 0; t < cd->n_tet; ++t)
+    if (!(cd->tet_nu[t] > -1.0 && cd->tet_nu[t] < 0.5)) fail(XPBD_ERR_INVALID, "Poisson ratio of tet %d out of range", t);
+
+  // ---- schedule: validate, then lay out internal order set by set
+  if (sd->n_sets < 0 || (sd->n_sets > 0 && (!sd->set_type || !sd->set_offsets || !sd->set_items)))
+    fail(XPBD_ERR_INVALID, "bad schedule");
+  std::vector<int> seen_d(c->n_dist, 0), seen_b(c->n_bend, 0), seen_t(c->n_tet, 0), seen_c(V, 0);
+  std::vector<int> stamp(V, -1);
+  std::vector<int> perm_d, perm_b, perm_t, vid_c;
+  perm_d.reserve(c->n_dist);
+  perm_b.reserve(c->n_bend);
+  perm_t.reserve(c->n_tet);
+  if (sd->n_sets > 0 && sd->set_offsets[0] != 0) fail(XPBD_ERR_INVALID, "set_offsets[0] must be 0");
+  for (int s = 0; s < sd->n_sets; ++s) {
+    int ty = sd->set_type[s];
+    int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
+    if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
+    if (ty < 0 || ty > 3) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
+    if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
+    // order items inside the set by their smallest vertex (locality)
+    std::vector<std::pair<int, int>> items;
+    items.reserve(e - b);
+    for (int64_t q = b; q < e; ++q) {
+      int it = sd->set_items[q];
+      const int32_t* vv = nullptr;
+      int nv = 1, lim = V;
+      if (ty == XPBD_DIST) { lim = c->n_dist; nv = 2; }
+      else if (ty == XPBD_BEND) { lim = c->n_bend; nv = 4; }
+      else if (ty == XPBD_TET) { lim = c->n_tet; nv = 4; }
+      if (it < 0 || it >= lim) fail(XPBD_ERR_INVALID, "set %d: item %d out of range", s, it);
+      if (ty == XPBD_DIST) vv = cd->dist_v + 2 * (int64_t)it;
+      else if (ty == XPBD_BEND) vv = cd->bend_v + 4 * (int64_t)it;
+      else if (ty == XPBD_TET) vv = cd->tet_v + 4 * (int64_t)it;
+      int key = INT32_MAX;
+      for (int k = 0; k < nv; ++k) {
+        int v = vv ? vv[k] : it;
+        if (stamp[v] == s) fail(XPBD_ERR_INVALID, "set %d is not independent: vertex %d appears twice", s, v);
+        stamp[v] = s;
+        key = std::min(key, v);
+      }
+      int* seen = ty == XPBD_DIST ? &seen_d[it] : ty == XPBD_BEND ? &seen_b[it] : ty == XPBD_TET ? &seen_t[it] : &seen_c[it];
+      if (*seen) fail(XPBD_ERR_INVALID, "constraint %d of type %d appears twice in the schedule", it, ty);
+      *seen = 1;
+      if (ty == XPBD_CONTACT && !(m->inv_mass[it] > 0))
+        fail(XPBD_ERR_INVALID, "contact on pinned vertex %d", it);
+      items.push_back({key, it});
+    }
+    std::stable_sort(items.begin(), items.end());
+    SetInfo si{};
+    si.type = ty;
+    si.count = (int)items.size();
+    std::vector<int>& dst = ty == XPBD_DIST ? perm_d : ty == XPBD_BEND ? perm_b : ty == XPBD_TET ? perm_t : vid_c;
+    si.begin = (int)dst.size();
+    for (auto& pr : items) dst.push_back(pr.second);
+    c->sets.push_back(si);
+  }
+  for (int i = 0; i < c->n_dist; ++i) if (!seen_d[i]) fail(XPBD_ERR_INVALID, "distance constraint %d not scheduled", i);
+  for (int i = 0; i < c->n_bend; ++i) if (!seen_b[i]) fail(XPBD_ERR_INVALID, "bending constraint %d not scheduled", i);
+  for (int i = 0; i < c->n_tet; ++i) if (!seen_t[i]) fail(XPBD_ERR_INVALID, "tet %d not scheduled", i);
+  c->n_contact = (int)vid_c.size();
+  // per-iteration record layout
+  size_t off = 0;
+  for (SetInfo& si : c->sets) {
+    si.tape_off = off;
+    off += align256(tape_item_bytes(si.type, c->tsz) * (size_t)si.count);
+    c->proj_per_iter += si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count;
+  }
+  c->iter_tape_bytes = off;
+
+  // ---- rest data in internal order (FP64 on the host)
+  std::vector<int2> didx(c->n_dist);
+  std::vector<double> drest(c->n_dist);
+  for (int i = 0; i < c->n_dist; ++i) {
+    int u = perm_d[i];
+    int a = cd->dist_v[2 * u], b = cd->dist_v[2 * u + 1];
+    H3 r = hsub(hv(m->rest_pos, a), hv(m->rest_pos, b));
+    double L = std::sqrt(hdot(r, r));
+    if (!(L > 0)) fail(XPBD_ERR_INVALID, "distance constraint %d has zero rest length", u);
+    didx[i] = make_int2(a, b);
+    drest[i] = L;
+  }
+  std::vector<int4> bidx(c->n_bend);
+  std::vector<double> btheta(c->n_bend);
+  for (int i = 0; i < c->n_bend; ++i) {
+    int u = perm_b[i];
+    const int32_t* q = cd->bend_v + 4 * (int64_t)u;
+    double th;
+    if (!rest_dihedral(hv(m->rest_pos, q[0]), hv(m->rest_pos, q[1]), hv(m->rest_pos, q[2]), hv(m->rest_pos, q[3]), &th))
+      fail(XPBD_ERR_INVALID, "bending constraint %d has a degenerate rest hinge", u);
+    bidx[i] = make_int4(q[0], q[1], q[2], q[3]);
+    btheta[i] = th;
+  }
+  std::vector<int4> tidx(c->n_tet);
+  std::vector<double> tB((size_t)9 * c->n_tet), tvol(c->n_tet), tnu(c->n_tet);
+  for (int i = 0; i < c->n_tet; ++i) {
+    int u = perm_t[i];
+    const int32_t* q = cd->tet_v + 4 * (int64_t)u;
+    double B[9], vol;
+    if (!rest_tet(hv(m->rest_pos, q[0]), hv(m->rest_pos, q[1]), hv(m->rest_pos, q[2]), hv(m->rest_pos, q[3]), B, &vol))
+      fail(XPBD_ERR_INVALID, "tet %d has non-positive rest volume", u);
+    tidx[i] = make_int4(q[0], q[1], q[2], q[3]);
+    for (int r = 0; r < 9; ++r) tB[(size_t)r * c->n_tet + i] = B[r];
+    tvol[i] = vol;
+    tnu[i] = cd->tet_nu[u];
+  }
+
+  // ---- device allocations
+  const size_t T_ = c->tsz;
+  const size_t V4b = 4 * T_;
+  c->w = c->alloc(V * T_);
+  c->X = c->alloc(V * V4b);
+  c->Vv = c->alloc(V * V4b);
+  c->Xp = c->alloc(V * V4b);
+  c->flag = (int*)c->alloc(sizeof(int));
+  std::vector<double> wv(m->inv_mass, m->inv_mass + V);
+  auto up_T = [&](void* dst, const std::vector<double>& v) {
+    if (c->dtype == XPBD_F32) c->upload(dst, cast_vec<float>(v));
+    else c->upload(dst, v);
+  };
+  up_T(c->w, wv);
+  if (c->n_dist) {
+    int n = c->n_dist;
+    c->dist_idx = (int2*)c->alloc(n * sizeof(int2));
+    c->dist_rest = c->alloc(n * T_);
+    c->dist_perm = (int*)c->alloc(n * sizeof(int));
+    c->dist_at = c->alloc(n * T_);
+    c->dist_lam = c->alloc(n * T_);
+    c->upload(c->dist_idx, didx);
+    up_T(c->dist_rest, drest);
+    c->upload(c->dist_perm, perm_d);
+  }
+  if (c->n_bend) {
+    int n = c->n_bend;
+    c->bend_idx = (int4*)c->alloc(n * sizeof(int4));
+    c->bend_theta0 = c->alloc(n * T_);
+    c->bend_perm = (int*)c->alloc(n * sizeof(int));
+    c->bend_at = c->alloc(n * T_);
+    c->bend_lam = c->alloc(n * T_);
+    c->upload(c->bend_idx, bidx);
+    up_T(c->bend_theta0, btheta);
+    c->upload(c->bend_perm, perm_b);
+  }
+  if (c->n_tet) {
+    int n = c->n_tet;
+    c->tet_idx = (int4*)c->alloc(n * sizeof(int4));
+    c->tet_B = c->alloc((size_t)9 * n * T_);
+    c->tet_perm = (int*)c->alloc(n * sizeof(int));
+    c->tet_nu = (double*)c->alloc(n * sizeof(double));
+    c->tet_vol = (double*)c->alloc(n * sizeof(double));
+    c->tet_atD = c->alloc(n * T_);
+    c->tet_atH = c->alloc(n * T_);
+    c->tet_gamma = c->alloc(n * T_);
+    c->tet_lamD = c->alloc(n * T_);
+    c->tet_lamH = c->alloc(n * T_);
+    c->upload(c->tet_idx, tidx);
+    up_T(c->tet_B, tB);
+    c->upload(c->tet_perm, perm_t);
+    c->upload(c->tet_nu, tnu);
+    c->upload(c->tet_vol, tvol);
+  }
+  if (c->n_contact) {
+    int n = c->n_contact;
+    c->contact_vid = (int*)c->alloc(n * sizeof(int));
+    c->contact_lam = c->alloc(n * T_);
+    c->upload(c->contact_vid, vid_c);
+  }
+}
+
+// allocate the adjoint working set for a tape of `slots` substeps
+void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
+  const size_t T_ = c->tsz, V4b = 4 * T_;
+  if (!c->XB) {
+    c->XB = c->alloc(c->V * V4b);
+    c->VB = c->alloc(c->V * V4b);
+    if (c->n_dist) {
+      c->dist_lamb = c->alloc(c->n_dist * T_);
+      c->dist_ab = c->alloc(c->n_dist * T_);
+      c->dist_acc = (double*)c->alloc(c->n_dist * sizeof(double));
+    }
+    if (c->n_bend) {
+      c->bend_lamb = c->alloc(c->n_bend * T_);
+      c->bend_ab = c->alloc(c->n_bend * T_);
+      c->bend_acc = (double*)c->alloc(c->n_bend * sizeof(double));
+    }
+    if (c->n_tet) {
+      c->tet_lambD = c->alloc(c->n_tet * T_);
+      c->tet_lambH = c->alloc(c->n_tet * T_);
+      c->tet_eb = c->alloc(c->n_tet * T_);
+      c->tet_acc = (double*)c->alloc(c->n_tet * sizeof(double));
+    }
+    if (c->n_contact) {
+      c->contact_lamb = c->alloc(c->n_contact * T_);
+      c->contact_sacc = c->alloc(c->n_contact * V4b);
+    }
+  }
+  size_t need = (size_t)slots * c->K * c->iter_tape_bytes;
+  if (need > c->tape_cap) {
+    c->release(c->tape);
+    c->tape_cap = 0;
+    c->tape = c->alloc(need);
+    c->tape_cap = need;
+  }
+}
+
+template <class F> xpbd_status guarded(xpbd_ctx c, F&& fn) {
+  try {
+    fn();
+    if (c) c->err.clear();
+    return XPBD_OK;
+  } catch (const Fail& f) {
+    if (c) c->err = f.msg;
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return XPBD_ERR_OOM;
+  } catch (...) {
+    if (c) c->err = "unexpected exception";
+    return XPBD_ERR_HIP;
+  }
+}
+
+thread_local std::string g_create_err;
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* cons,
+                        const xpbd_schedule_desc* schedule, const xpbd_options* opt, xpbd_ctx* out) {
+  if (!out) return XPBD_ERR_INVALID;
+  *out = nullptr;
+  xpbd_ctx c = nullptr;
+  try {
+    c = new xpbd_ctx_s();
+  } catch (...) {
+    return XPBD_ERR_OOM;
+  }
+  xpbd_status st = guarded(c, [&] { build(c, mesh, cons, schedule, opt); });
+  if (st != XPBD_OK) {
+    g_create_err = c->err;
+    delete c;
+    return st;
+  }
+  *out = c;
+  return XPBD_OK;
+}
+
+xpbd_status xpbd_destroy(xpbd_ctx ctx) {
+  if (!ctx) return XPBD_ERR_INVALID;
+  delete ctx;
+  return XPBD_OK;
+}
+
+xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_params* p, int32_t n_frames,
+                         void* x_frames, void* x_final, void* v_final, void* stream) {
+  if (!c) return XPBD_ERR_INVALID;
+  return guarded(c, [&] {
+    if (!p || !x0 || !v0 || n_frames < 1) fail(XPBD_ERR_INVALID, "forward: null argument or n_frames < 1");
+    if (c->n_tet && !p->tet_E) fail(XPBD_ERR_INVALID, "forward: tet_E required");
+    c->have_forward = false;
+    hipStream_t st = (hipStream_t)stream;
+    if (c->dtype == XPBD_F32) Ops<float>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, st);
+    else Ops<double>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, st);
+    c->have_forward = true;
+    c->fwd_frames = n_frames;
+    c->fwd_params = *p;
+  });
+}
+
+xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_frames, const uint8_t* frame_mask,
+                         const void* dLdv_final, const xpbd_grads* out, void* stream) {
+  if (!c) return XPBD_ERR_INVALID;
+  return guarded(c, [&] {
+    if (!p || !out) fail(XPBD_ERR_INVALID, "adjoint: null argument");
+    if (!c->have_forward) fail(XPBD_ERR_STATE, "adjoint: no preceding forward on this context");
+    const xpbd_params& q = c->fwd_params;
+    if (q.dist_compliance != p->dist_compliance || q.bend_compliance != p->bend_compliance ||
+        q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0)
+      fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
+    int mode = c->tape_mode_opt;
+    if (mode == 0) {
+      // whole-frame record if it fits the budget (or, with no budget, free memory)
+      size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
+      size_t have = c->tape_cap;
+      size_t limit;
+      if (c->budget) limit = c->budget > c->dev_bytes ? c->budget - c->dev_bytes + have : 0;
+      else {
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        limit = fr + have > ((size_t)4 << 30) ? fr + have - ((size_t)4 << 30) : 0;
+      }
+      mode = frame_tape <= limit ? 1 : 2;
+    }
+    ensure_adjoint_buffers(c, mode == 1 ? c->S : 1);
+    c->tape_mode_used = mode;
+    hipStream_t st = (hipStream_t)stream;
+    if (c->dtype == XPBD_F32) Ops<float>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
+    else Ops<double>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
+  });
+}
+
+xpbd_status xpbd_goal_l2(xpbd_ctx c, const void* x_frames, const void* targets, const uint8_t* frame_mask,
+                         int32_t n_frames, double* loss, void* dLdx, void* stream) {
+  if (!c) return XPBD_ERR_INVALID;
+  return guarded(c, [&] {
+    if (!x_frames || !targets || n_frames < 1) fail(XPBD_ERR_INVALID, "goal: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (c->dtype == XPBD_F32) Ops<float>::goal(c, x_frames, targets, frame_mask, n_frames, loss, dLdx, st);
+    else Ops<double>::goal(c, x_frames, targets, frame_mask, n_frames, loss, dLdx, st);
+  });
+}
+
+xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
+  if (!c || !info) return XPBD_ERR_INVALID;
+  info->n_verts = c->V;
+  info->n_dist = c->n_dist;
+  info->n_bend = c->n_bend;
+  info->n_tet = c->n_tet;
+  info->n_contact = c->n_contact;
+  info->n_sets = (int32_t)c->sets.size();
+  info->projections_per_iteration = c->proj_per_iter;
+  info->device_bytes = (int64_t)c->dev_bytes;
+  info->tape_bytes_per_iteration = (int64_t)c->iter_tape_bytes;
+  info->tape_mode = c->tape_mode_used;
+  return XPBD_OK;
+}
+
+xpbd_status xpbd_profile_enable(xpbd_ctx c, int32_t on) {
+  if (!c || on < 0) return XPBD_ERR_INVALID;
+  c->prof_stride = on;
+  c->prof_counter = 0;
+  return XPBD_OK;
+}
+
+xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[8], double ms[8], int64_t items[8]) {
+  if (!c) return XPBD_ERR_INVALID;
+  return guarded(c, [&] {
+    for (auto& e : c->ev_pending) {
+      HIPCHK(hipEventSynchronize(e.b));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+      c->prof_launch[e.fam] += 1;
+      c->prof_ms[e.fam] += t;
+      c->prof_items[e.fam] += e.items;
+      c->ev_free.push_back({e.a, e.b});
+    }
+    c->ev_pending.clear();
+    for (int i = 0; i < 8; ++i) {
+      if (launches) launches[i] = c->prof_launch[i];
+      if (ms) ms[i] = c->prof_ms[i];
+      if (items) items[i] = c->prof_items[i];
+      c->prof_launch[i] = 0;
+      c->prof_ms[i] = 0;
+      c->prof_items[i] = 0;
+    }
+  });
+}
+
+const char* xpbd_last_error(xpbd_ctx c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+const char* xpbd_status_string(xpbd_status s) {
+  switch (s) {
+    case XPBD_OK: return "ok";
+    case XPBD_ERR_INVALID: return "invalid argument";
+    case XPBD_ERR_OOM: return "out of memory";
+    case XPBD_ERR_HIP: return "HIP error";
+    case XPBD_ERR_STATE: return "invalid state";
+    case XPBD_ERR_NONFINITE: return "non-finite value";
+  }
+  return "unknown";
+}
+
+}  // extern "C"

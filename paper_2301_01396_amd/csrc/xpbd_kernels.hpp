@@ -1,0 +1,629 @@
+// HIP kernels of the XPBD forward sweeps and their exact adjoint (gfx950).
+//
+// One thread owns one constraint of an independent set, so the sets need
+// no atomics: vertex state is gathered and scattered as 16-byte (FP32) or
+// 32-byte (FP64) packed records {x, y, z, w} with w the inverse mass, and
+// the vertex adjoints as {xbar, ybar, zbar, w}.  Constraint records are
+// structure-of-arrays in schedule order, so every record load is coalesced.
+//
+// Forward kernels can record, per projection, exactly the inputs its
+// adjoint needs (the vertex differences and the multiplier before the
+// update); reverse kernels recompute C, grad C, D and dlambda from that
+// record bit for bit and apply the chain rule to
+//     dlambda = (-C - at lambda) / D,  lambda += dlambda,
+//     x_k += w_k dlambda grad_k C
+// (Eq. xpbd and the position update of Sec. 3.1), with the partials of
+// Sec. 4.3: the adjoint of grad C (through the position update and through
+// D = sum_k w_k |grad_k C|^2 + at), the Hessian-vector product it feeds,
+// and the compliance adjoint -dlbar (lambda + dlambda) / D.
+#pragma once
+#include "xpbd_device.hpp"
+
+namespace xpbd {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int thread_item(int count) {
+  int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  return t < count ? t : -1;
+}
+
+// ===================================================================== forward
+
+template <class T, bool FIRST, bool TAPE>
+__global__ __launch_bounds__(kBlock) void k_dist(const int2* __restrict__ idx, const T* __restrict__ rest,
+                                                 const T* __restrict__ at, T* __restrict__ lam,
+                                                 Vec4<T>* __restrict__ X, int begin, int count,
+                                                 Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int2 e = idx[j];
+  Vec4<T> a = X[e.x], b = X[e.y];
+  V3<T> r = xyz(a) - xyz(b);
+  T lb = FIRST ? T(0) : lam[j];
+  if (TAPE) tape[t] = Vec4<T>{r.x, r.y, r.z, lb};
+  DistEval<T> ev = dist_eval(r, rest[j]);
+  T a_t = at[j];
+  T D = a.w + b.w + a_t;
+  if (!ev.ok || !(D > T(0))) {
+    if (FIRST) lam[j] = T(0);
+    return;
+  }
+  T dl = (-ev.C - a_t * lb) / D;
+  lam[j] = lb + dl;
+  T sa = a.w * dl, sb = b.w * dl;
+  a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
+  b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
+  X[e.x] = a;
+  X[e.y] = b;
+}
+
+template <class T, bool FIRST, bool TAPE>
+__global__ __launch_bounds__(kBlock) void k_bend(const int4* __restrict__ idx, const T* __restrict__ theta0,
+                                                 const T* __restrict__ at, T* __restrict__ lam,
+                                                 Vec4<T>* __restrict__ X, int begin, int count,
+                                                 Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int4 q = idx[j];
+  Vec4<T> p[4] = {X[q.x], X[q.y], X[q.z], X[q.w]};
+  V3<T> e = xyz(p[1]) - xyz(p[0]), a = xyz(p[2]) - xyz(p[0]), b = xyz(p[3]) - xyz(p[0]);
+  T lb = FIRST ? T(0) : lam[j];
+  if (TAPE) {
+    tape[t] = Vec4<T>{e.x, e.y, e.z, lb};
+    tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
+    reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
+  }
+  BendEval<T> ev = bend_eval(e, a, b, theta0[j]);
+  T a_t = at[j];
+  T D = a_t;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) D += p[k].w * dot(ev.g[k], ev.g[k]);
+  if (!ev.ok || !(D > T(0))) {
+    if (FIRST) lam[j] = T(0);
+    return;
+  }
+  T dl = (-ev.C - a_t * lb) / D;
+  lam[j] = lb + dl;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T s = p[k].w * dl;
+    p[k].x += s * ev.g[k].x; p[k].y += s * ev.g[k].y; p[k].z += s * ev.g[k].z;
+  }
+  X[q.x] = p[0]; X[q.y] = p[1]; X[q.z] = p[2]; X[q.w] = p[3];
+}
+
+template <class T> struct TetRec {
+  const int4* idx;
+  const T* B;        // [9][n_tet] Dm^-1 row-major entries
+  const T* atD;      // [n_tet] alpha_D / h^2
+  const T* atH;      // [n_tet] alpha_H / h^2
+  const T* gamma;    // [n_tet]
+  int n;             // n_tet (stride of B)
+};
+
+template <class T> __device__ __forceinline__ M3<T> load_B(const T* B, int n, int j) {
+  M3<T> m;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m.m[r][c] = B[(size_t)(r * 3 + c) * n + j];
+  return m;
+}
+
+// One tet item = deviatoric projection then hydrostatic projection.  The
+// hydrostatic constraint is evaluated on the edge matrix updated in place by
+// the deviatoric correction (d_k += delta_{k} - delta_0).
+template <class T> struct TetStep {
+  TetEval<T> evD, evH;
+  bool appD, appH;
+  T DD, DH, dlD, dlH;
+  V3<T> dD[4], dH[4];     // position corrections of each projection
+};
+template <class T>
+__device__ __forceinline__ void tet_step(const V3<T> d0[3], const T w[4], const M3<T>& B, T atD, T atH, T gamma,
+                                         T lD, T lH, TetStep<T>& s) {
+  s.evD = tet_dev_eval(d0, B);
+  s.DD = atD;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.DD += w[k] * dot(s.evD.g[k], s.evD.g[k]);
+  s.appD = s.evD.ok && s.DD > T(0);
+  s.dlD = s.appD ? (-s.evD.C - atD * lD) / s.DD : T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.dD[k] = s.appD ? (w[k] * s.dlD) * s.evD.g[k] : V3<T>{T(0), T(0), T(0)};
+  V3<T> d1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d1[c] = d0[c] + (s.dD[c + 1] - s.dD[0]);
+  s.evH = tet_hyd_eval(d1, B, gamma);
+  s.DH = atH;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.DH += w[k] * dot(s.evH.g[k], s.evH.g[k]);
+  s.appH = s.DH > T(0);
+  s.dlH = s.appH ? (-s.evH.C - atH * lH) / s.DH : T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.dH[k] = s.appH ? (w[k] * s.dlH) * s.evH.g[k] : V3<T>{T(0), T(0), T(0)};
+}
+
+template <class T, bool FIRST, bool TAPE>
+__global__ __launch_bounds__(kBlock) void k_tet(TetRec<T> R, T* __restrict__ lamD, T* __restrict__ lamH,
+                                                Vec4<T>* __restrict__ X, int begin, int count,
+                                                Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int4 q = R.idx[j];
+  Vec4<T> p[4] = {X[q.x], X[q.y], X[q.z], X[q.w]};
+  V3<T> d[3] = {xyz(p[1]) - xyz(p[0]), xyz(p[2]) - xyz(p[0]), xyz(p[3]) - xyz(p[0])};
+  T lD = FIRST ? T(0) : lamD[j];
+  T lH = FIRST ? T(0) : lamH[j];
+  if (TAPE) {
+    tape[t] = Vec4<T>{d[0].x, d[0].y, d[0].z, d[1].x};
+    tape[count + t] = Vec4<T>{d[1].y, d[1].z, d[2].x, d[2].y};
+    tape[2 * count + t] = Vec4<T>{d[2].z, lD, lH, T(0)};
+  }
+  M3<T> B = load_B(R.B, R.n, j);
+  T w[4] = {p[0].w, p[1].w, p[2].w, p[3].w};
+  TetStep<T> s;
+  tet_step(d, w, B, R.atD[j], R.atH[j], R.gamma[j], lD, lH, s);
+  lamD[j] = lD + s.dlD;
+  lamH[j] = lH + s.dlH;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    p[k].x = (p[k].x + s.dD[k].x) + s.dH[k].x;
+    p[k].y = (p[k].y + s.dD[k].y) + s.dH[k].y;
+    p[k].z = (p[k].z + s.dD[k].z) + s.dH[k].z;
+  }
+  X[q.x] = p[0]; X[q.y] = p[1]; X[q.z] = p[2]; X[q.w] = p[3];
+}
+
+template <class T> struct Sphere { T cx, cy, cz, R, tau, at; };
+
+template <class T, bool FIRST, bool TAPE>
+__global__ __launch_bounds__(kBlock) void k_contact(const int* __restrict__ vid, T* __restrict__ lam,
+                                                    Vec4<T>* __restrict__ X, int begin, int count, Sphere<T> S,
+                                                    Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int v = vid[j];
+  Vec4<T> p = X[v];
+  T lb = FIRST ? T(0) : lam[j];
+  if (TAPE) tape[t] = Vec4<T>{p.x, p.y, p.z, lb};
+  ContactEval<T> ev = contact_eval(V3<T>{p.x - S.cx, p.y - S.cy, p.z - S.cz}, S.R, S.tau);
+  T D = p.w + S.at;
+  if (!ev.ok || !(ev.C < T(0)) || !(D > T(0))) {
+    if (FIRST) lam[j] = T(0);
+    return;
+  }
+  T dl = (-ev.C - S.at * lb) / D;
+  lam[j] = lb + dl;
+  T s = p.w * dl;
+  p.x += s * ev.n.x; p.y += s * ev.n.y; p.z += s * ev.n.z;
+  X[v] = p;
+}
+
+// ===================================================================== reverse
+// Adjoint of one projection given the adjoints of its outputs.  Inputs:
+// gradient g_k, weights w_k, D, dlambda, lambda_before, at; x̄_k (in/out).
+// Returns dlbar; writes gbar_k (adjoint of grad_k C).
+template <class T, int N>
+__device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T D, T dl, T lbar, const V3<T> xb[N],
+                                          V3<T> gb[N]) {
+  T dlb = lbar;
+#pragma unroll
+  for (int k = 0; k < N; ++k) dlb += w[k] * dot(g[k], xb[k]);
+  T c = T(2) * dlb * dl / D;
+#pragma unroll
+  for (int k = 0; k < N; ++k) gb[k] = {w[k] * (dl * xb[k].x - c * g[k].x), w[k] * (dl * xb[k].y - c * g[k].y),
+                                      w[k] * (dl * xb[k].z - c * g[k].z)};
+  return dlb;
+}
+
+template <class T, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_dist_rev(const int2* __restrict__ idx, const T* __restrict__ rest,
+                                                     const T* __restrict__ at, Vec4<T>* __restrict__ XB,
+                                                     T* __restrict__ lamb, T* __restrict__ abar,
+                                                     double* __restrict__ acc, int begin, int count,
+                                                     const Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int2 e = idx[j];
+  Vec4<T> tp = tape[t];
+  T lbar = FIRST ? T(0) : lamb[j];
+  T ab = FIRST ? T(0) : abar[j];
+  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, rest[j]);
+  Vec4<T> A = XB[e.x], Bv = XB[e.y];
+  T a_t = at[j];
+  T D = A.w + Bv.w + a_t;
+  if (ev.ok && D > T(0)) {
+    T lb = tp.w;
+    T dl = (-ev.C - a_t * lb) / D;
+    V3<T> xa = xyz(A), xb = xyz(Bv);
+    T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
+    // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
+    // along n and vanishes under P, leaving dl * P (w_i xa - w_j xb) / |r|.
+    V3<T> u = A.w * xa - Bv.w * xb;
+    T un = dot(ev.n, u);
+    T s = dl / ev.len;
+    V3<T> hv = {s * (u.x - un * ev.n.x), s * (u.y - un * ev.n.y), s * (u.z - un * ev.n.z)};
+    T Cb = -dlb / D;
+    lbar = lbar - dlb * a_t / D;
+    ab = ab - dlb * (lb + dl) / D;
+    A.x += Cb * ev.n.x + hv.x; A.y += Cb * ev.n.y + hv.y; A.z += Cb * ev.n.z + hv.z;
+    Bv.x -= Cb * ev.n.x + hv.x; Bv.y -= Cb * ev.n.y + hv.y; Bv.z -= Cb * ev.n.z + hv.z;
+    XB[e.x] = A;
+    XB[e.y] = Bv;
+  }
+  if (LAST) {
+    acc[j] += (double)ab;
+  } else {
+    lamb[j] = lbar;
+    abar[j] = ab;
+  }
+}
+
+template <class T, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_bend_rev(const int4* __restrict__ idx, const T* __restrict__ theta0,
+                                                     const T* __restrict__ at, Vec4<T>* __restrict__ XB,
+                                                     T* __restrict__ lamb, T* __restrict__ abar,
+                                                     double* __restrict__ acc, int begin, int count,
+                                                     const Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int4 q = idx[j];
+  Vec4<T> tA = tape[t], tB = tape[count + t];
+  Vec2<T> tC = reinterpret_cast<const Vec2<T>*>(tape + 2 * count)[t];
+  V3<T> e = {tA.x, tA.y, tA.z}, a = {tB.x, tB.y, tB.z}, b = {tB.w, tC.x, tC.y};
+  T lb = tA.w;
+  T lbar = FIRST ? T(0) : lamb[j];
+  T ab = FIRST ? T(0) : abar[j];
+  BendEval<T> ev = bend_eval(e, a, b, theta0[j]);
+  Vec4<T> P[4] = {XB[q.x], XB[q.y], XB[q.z], XB[q.w]};
+  T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
+  T a_t = at[j];
+  T D = a_t;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) D += w[k] * dot(ev.g[k], ev.g[k]);
+  if (ev.ok && D > T(0)) {
+    T dl = (-ev.C - a_t * lb) / D;
+    V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
+    V3<T> gb[4], hv[4];
+    T dlb = proj_adjoint<T, 4>(ev.g, w, D, dl, lbar, xb, gb);
+    bend_hvp(e, a, b, gb, hv);
+    T Cb = -dlb / D;
+    lbar = lbar - dlb * a_t / D;
+    ab = ab - dlb * (lb + dl) / D;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      P[k].x += Cb * ev.g[k].x + hv[k].x;
+      P[k].y += Cb * ev.g[k].y + hv[k].y;
+      P[k].z += Cb * ev.g[k].z + hv[k].z;
+    }
+    XB[q.x] = P[0]; XB[q.y] = P[1]; XB[q.z] = P[2]; XB[q.w] = P[3];
+  }
+  if (LAST) {
+    acc[j] += (double)ab;
+  } else {
+    lamb[j] = lbar;
+    abar[j] = ab;
+  }
+}
+
+// tet: ebar accumulates sum over projections of (atbar_D at_D + atbar_H at_H),
+// i.e. alphabar_D alpha_D + alphabar_H alpha_H, whence dL/dE = -ebar / E.
+template <class T, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_tet_rev(TetRec<T> R, Vec4<T>* __restrict__ XB, T* __restrict__ lambD,
+                                                    T* __restrict__ lambH, T* __restrict__ ebar,
+                                                    double* __restrict__ acc, int begin, int count,
+                                                    const Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int4 q = R.idx[j];
+  Vec4<T> t0 = tape[t], t1 = tape[count + t], t2 = tape[2 * count + t];
+  V3<T> d[3] = {{t0.x, t0.y, t0.z}, {t0.w, t1.x, t1.y}, {t1.z, t1.w, t2.x}};
+  T lD = t2.y, lH = t2.z;
+  Vec4<T> P[4] = {XB[q.x], XB[q.y], XB[q.z], XB[q.w]};
+  T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
+  M3<T> B = load_B(R.B, R.n, j);
+  T atD = R.atD[j], atH = R.atH[j];
+  TetStep<T> s;
+  tet_step(d, w, B, atD, atH, R.gamma[j], lD, lH, s);
+  T lbD = FIRST ? T(0) : lambD[j];
+  T lbH = FIRST ? T(0) : lambH[j];
+  T eb = FIRST ? T(0) : ebar[j];
+  V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
+  V3<T> gb[4], hv[4];
+  if (s.appH) {
+    T dlb = proj_adjoint<T, 4>(s.evH.g, w, s.DH, s.dlH, lbH, xb, gb);
+    tet_hyd_hvp(s.evH, B, gb, hv);
+    T Cb = -dlb / s.DH;
+    lbH = lbH - dlb * atH / s.DH;
+    eb = eb - dlb * (lH + s.dlH) / s.DH * atH;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evH.g[k] + hv[k]);
+  }
+  if (s.appD) {
+    T dlb = proj_adjoint<T, 4>(s.evD.g, w, s.DD, s.dlD, lbD, xb, gb);
+    tet_dev_hvp(s.evD, B, gb, hv);
+    T Cb = -dlb / s.DD;
+    lbD = lbD - dlb * atD / s.DD;
+    eb = eb - dlb * (lD + s.dlD) / s.DD * atD;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evD.g[k] + hv[k]);
+  }
+  if (s.appD || s.appH) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { P[k].x = xb[k].x; P[k].y = xb[k].y; P[k].z = xb[k].z; }
+    XB[q.x] = P[0]; XB[q.y] = P[1]; XB[q.z] = P[2]; XB[q.w] = P[3];
+  }
+  if (LAST) {
+    acc[j] += (double)eb;
+  } else {
+    lambD[j] = lbD;
+    lambH[j] = lbH;
+    ebar[j] = eb;
+  }
+}
+
+// contact: also accumulates the sphere adjoint (cbar, Rbar) per contact
+template <class T, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_contact_rev(const int* __restrict__ vid, Vec4<T>* __restrict__ XB,
+                                                        T* __restrict__ lamb, Vec4<T>* __restrict__ sacc,
+                                                        int begin, int count, Sphere<T> S,
+                                                        const Vec4<T>* __restrict__ tape) {
+  int t = thread_item(count);
+  if (t < 0) return;
+  int j = begin + t;
+  int v = vid[j];
+  Vec4<T> tp = tape[t];
+  T lbar = FIRST ? T(0) : lamb[j];
+  Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : sacc[j];
+  ContactEval<T> ev = contact_eval(V3<T>{tp.x - S.cx, tp.y - S.cy, tp.z - S.cz}, S.R, S.tau);
+  Vec4<T> P = XB[v];
+  T D = P.w + S.at;
+  if (ev.ok && ev.C < T(0) && D > T(0)) {
+    T lb = tp.w;
+    T dl = (-ev.C - S.at * lb) / D;
+    V3<T> xb = xyz(P);
+    T dlb = lbar + P.w * dot(ev.n, xb);
+    T c = T(2) * dlb * dl / D;
+    V3<T> gb = {P.w * (dl * xb.x - c * ev.n.x), P.w * (dl * xb.y - c * ev.n.y), P.w * (dl * xb.z - c * ev.n.z)};
+    T gn = dot(ev.n, gb);
+    T inv = T(1) / ev.d;
+    V3<T> hv = {inv * (gb.x - gn * ev.n.x), inv * (gb.y - gn * ev.n.y), inv * (gb.z - gn * ev.n.z)};
+    T Cb = -dlb / D;
+    lbar = lbar - dlb * S.at / D;
+    P.x += Cb * ev.n.x + hv.x; P.y += Cb * ev.n.y + hv.y; P.z += Cb * ev.n.z + hv.z;
+    XB[v] = P;
+    // C = |x - c| - R - tau: dC/dc = -n, dC/dR = -1, d(grad_x C)/dc = -P/|x-c|
+    sa.x -= Cb * ev.n.x + hv.x; sa.y -= Cb * ev.n.y + hv.y; sa.z -= Cb * ev.n.z + hv.z;
+    sa.w -= Cb;
+  }
+  if (!LAST) lamb[j] = lbar;
+  sacc[j] = sa;
+}
+
+// ===================================================================== per-vertex kernels
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pack(const T* __restrict__ x0, const T* __restrict__ v0,
+                                                 const T* __restrict__ w, Vec4<T>* __restrict__ X,
+                                                 Vec4<T>* __restrict__ Vv, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  T wk = w[k];
+  X[k] = Vec4<T>{x0[3 * k], x0[3 * k + 1], x0[3 * k + 2], wk};
+  if (wk > T(0)) Vv[k] = Vec4<T>{v0[3 * k], v0[3 * k + 1], v0[3 * k + 2], T(0)};
+  else Vv[k] = Vec4<T>{T(0), T(0), T(0), T(0)};
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_unpack(const Vec4<T>* __restrict__ X, T* __restrict__ out, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> p = X[k];
+  out[3 * k] = p.x; out[3 * k + 1] = p.y; out[3 * k + 2] = p.z;
+}
+
+// substep start: x_prev = x; v += h (g + w f) for free vertices; x += h v
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_predict(Vec4<T>* __restrict__ X, Vec4<T>* __restrict__ Vv,
+                                                    Vec4<T>* __restrict__ Xp, const T* __restrict__ f, T h,
+                                                    T gx, T gy, T gz, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> x = X[k], v = Vv[k];
+  Xp[k] = x;
+  if (x.w > T(0)) {
+    T fx = T(0), fy = T(0), fz = T(0);
+    if (f) { fx = f[3 * k]; fy = f[3 * k + 1]; fz = f[3 * k + 2]; }
+    v.x += h * (gx + x.w * fx);
+    v.y += h * (gy + x.w * fy);
+    v.z += h * (gz + x.w * fz);
+    Vv[k] = v;
+  }
+  x.x += h * v.x; x.y += h * v.y; x.z += h * v.z;
+  X[k] = x;
+}
+
+// substep end: v = (x - x_prev) / h
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_velocity(const Vec4<T>* __restrict__ X, Vec4<T>* __restrict__ Vv,
+                                                     const Vec4<T>* __restrict__ Xp, T inv_h, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> x = X[k], xp = Xp[k];
+  Vv[k] = Vec4<T>{(x.x - xp.x) * inv_h, (x.y - xp.y) * inv_h, (x.z - xp.z) * inv_h, T(0)};
+}
+
+// adjoint state init: xbar = 0 (keeping w), vbar = dL/dv_final or 0
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_adj_init(Vec4<T>* __restrict__ XB, Vec4<T>* __restrict__ VB,
+                                                     const T* __restrict__ w, const T* __restrict__ dv, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  XB[k] = Vec4<T>{T(0), T(0), T(0), w[k]};
+  if (dv) VB[k] = Vec4<T>{dv[3 * k], dv[3 * k + 1], dv[3 * k + 2], T(0)};
+  else VB[k] = Vec4<T>{T(0), T(0), T(0), T(0)};
+}
+
+// xbar += dL/dx(f)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_adj_inject(Vec4<T>* __restrict__ XB, const T* __restrict__ g, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> p = XB[k];
+  p.x += g[3 * k]; p.y += g[3 * k + 1]; p.z += g[3 * k + 2];
+  XB[k] = p;
+}
+
+// reverse of v = (x - x_prev)/h, first half: xbar += vbar / h
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_rev_velocity(Vec4<T>* __restrict__ XB, const Vec4<T>* __restrict__ VB,
+                                                         T inv_h, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> p = XB[k], v = VB[k];
+  p.x += v.x * inv_h; p.y += v.y * inv_h; p.z += v.z * inv_h;
+  XB[k] = p;
+}
+
+// reverse of the prediction plus the x_prev half of the velocity update:
+//   vbar_mid = h xbar (free), fbar += h w vbar_mid, xbar = xbar - vbar_old / h,
+//   vbar = vbar_mid
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_rev_predict(Vec4<T>* __restrict__ XB, Vec4<T>* __restrict__ VB,
+                                                        T* __restrict__ fbar, T h, T inv_h, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> p = XB[k], v = VB[k];
+  Vec4<T> vm = {T(0), T(0), T(0), T(0)};
+  if (p.w > T(0)) { vm.x = h * p.x; vm.y = h * p.y; vm.z = h * p.z; }
+  if (fbar) {
+    T s = h * p.w;
+    fbar[3 * k] += s * vm.x; fbar[3 * k + 1] += s * vm.y; fbar[3 * k + 2] += s * vm.z;
+  }
+  p.x -= v.x * inv_h; p.y -= v.y * inv_h; p.z -= v.z * inv_h;
+  XB[k] = p;
+  VB[k] = vm;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ p, T v, size_t n) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ===================================================================== parameters
+
+__device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
+
+// at[i] = alpha[perm[i]] / h^2 (internal order);  flag |= non-finite
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather_alpha(const T* __restrict__ alpha, const int* __restrict__ perm,
+                                                         T* __restrict__ at, T inv_h2, int n, int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T a = alpha ? alpha[perm[i]] : T(0);
+  if (!finite_d((double)a) || a < T(0)) *flag = 1;
+  at[i] = a * inv_h2;
+}
+
+// per tet: mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu)),
+// atD = 1/(mu V h^2), atH = 1/(lambda V h^2), gamma = 1 + mu/lambda (or 1)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather_tet(const T* __restrict__ E, const int* __restrict__ perm,
+                                                       const double* __restrict__ nu, const double* __restrict__ vol,
+                                                       T* __restrict__ atD, T* __restrict__ atH, T* __restrict__ gam,
+                                                       double inv_h2, int gamma_one, int n, int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double e = (double)E[perm[i]];
+  if (!finite_d(e) || !(e > 0.0)) *flag = 1;
+  double v = nu[i], V = vol[i];
+  double mu = e / (2.0 * (1.0 + v));
+  double la = e * v / ((1.0 + v) * (1.0 - 2.0 * v));
+  atD[i] = (T)(inv_h2 / (mu * V));
+  atH[i] = (T)(inv_h2 / (la * V));
+  gam[i] = gamma_one ? T(1) : (T)(1.0 + mu / la);
+}
+
+// gradient scatter: out[perm[i]] = acc[i] * scale     (dist, bend)
+__global__ __launch_bounds__(kBlock) void k_scatter_alpha_grad(const double* __restrict__ acc, const int* __restrict__ perm,
+                                                               double* __restrict__ out, double scale, int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  out[perm[i]] = acc[i] * scale;
+}
+// dL/dE = -ebar / E
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scatter_E_grad(const double* __restrict__ acc, const int* __restrict__ perm,
+                                                           const T* __restrict__ E, double* __restrict__ out, int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int u = perm[i];
+  out[u] = -acc[i] / (double)E[u];
+}
+
+// deterministic single-block reduction of the per-contact sphere adjoints
+// into the FP64 sphere gradient
+template <class T>
+__global__ __launch_bounds__(1024) void k_sphere_reduce(const Vec4<T>* __restrict__ sacc, int begin, int count,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[4][1024];
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    Vec4<T> v = sacc[begin + i];
+    s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
+  }
+  sh[0][threadIdx.x] = s0; sh[1][threadIdx.x] = s1; sh[2][threadIdx.x] = s2; sh[3][threadIdx.x] = s3;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4 && out) out[threadIdx.x] += sh[threadIdx.x][0];
+}
+
+// FP64 goal: per-block partial sums of 1/2 |x - x*|^2 on masked frames, and
+// dL/dx = x - x* (0 on unmasked frames)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_goal(const T* __restrict__ x, const T* __restrict__ tg,
+                                                 T* __restrict__ g, size_t n, int on, double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double s = 0.0;
+  if (i < n) {
+    double d = on ? (double)x[i] - (double)tg[i] : 0.0;
+    if (g) g[i] = on ? (T)(x[i] - tg[i]) : T(0);
+    s = 0.5 * d * d;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ __launch_bounds__(1024) void k_sum_parts(const double* __restrict__ part, size_t n, double* __restrict__ out,
+                                                    int accumulate) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += 1024) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = accumulate ? *out + sh[0] : sh[0];
+}
+
+}  // namespace xpbd

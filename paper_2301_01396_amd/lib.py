@@ -1,0 +1,292 @@
+"""ctypes binding of ``libxpbd.so`` (declared in include/xpbd.h).
+
+Argument marshalling only: every step of the simulation and its adjoint runs
+in the library's HIP kernels.  PyTorch provides device memory and the
+stream.  Loading fails loudly when the library is not built; there is no
+other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxpbd.so")
+
+XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE = range(6)
+F32, F64 = 0, 1
+EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
+           "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
+           "xpbd_status_string")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+_vp = C.c_void_p
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("rest_pos", _dp), ("inv_mass", _dp)]
+
+
+class ConstraintDesc(C.Structure):
+    _fields_ = [("n_dist", C.c_int32), ("dist_v", _ip), ("n_bend", C.c_int32), ("bend_v", _ip),
+                ("n_tet", C.c_int32), ("tet_v", _ip), ("tet_nu", _dp), ("contact", C.c_int32),
+                ("contact_thickness", C.c_double), ("contact_compliance", C.c_double)]
+
+
+class ScheduleDesc(C.Structure):
+    _fields_ = [("n_sets", C.c_int32), ("set_type", _ip), ("set_offsets", _lp), ("set_items", _ip)]
+
+
+class Options(C.Structure):
+    _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("iterations", C.c_int32),
+                ("gravity", C.c_double * 3), ("dtype", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
+                ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
+                ("sphere", C.c_double * 4)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
+                ("x0", _vp), ("v0", _vp), ("sphere", _vp)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_dist", C.c_int32), ("n_bend", C.c_int32), ("n_tet", C.c_int32),
+                ("n_contact", C.c_int32), ("n_sets", C.c_int32), ("projections_per_iteration", C.c_int64),
+                ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
+                ("tape_mode", C.c_int32)]
+
+
+class XPBDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"xpbd status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Open the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = C.CDLL(LIB_PATH)
+        lib.xpbd_create.restype = C.c_int
+        lib.xpbd_create.argtypes = [C.POINTER(MeshDesc), C.POINTER(ConstraintDesc), C.POINTER(ScheduleDesc),
+                                    C.POINTER(Options), C.POINTER(_vp)]
+        lib.xpbd_destroy.restype = C.c_int
+        lib.xpbd_destroy.argtypes = [_vp]
+        lib.xpbd_forward.restype = C.c_int
+        lib.xpbd_forward.argtypes = [_vp, _vp, _vp, C.POINTER(Params), C.c_int32, _vp, _vp, _vp, _vp]
+        lib.xpbd_adjoint.restype = C.c_int
+        lib.xpbd_adjoint.argtypes = [_vp, C.POINTER(Params), _vp, C.POINTER(C.c_uint8), _vp,
+                                     C.POINTER(Grads), _vp]
+        lib.xpbd_goal_l2.restype = C.c_int
+        lib.xpbd_goal_l2.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), C.c_int32, _vp, _vp, _vp]
+        lib.xpbd_get_info.restype = C.c_int
+        lib.xpbd_get_info.argtypes = [_vp, C.POINTER(Info)]
+        lib.xpbd_profile_enable.restype = C.c_int
+        lib.xpbd_profile_enable.argtypes = [_vp, C.c_int32]
+        lib.xpbd_profile_read.restype = C.c_int
+        lib.xpbd_profile_read.argtypes = [_vp, _lp, _dp, _lp]
+        lib.xpbd_last_error.restype = C.c_char_p
+        lib.xpbd_last_error.argtypes = [_vp]
+        lib.xpbd_status_string.restype = C.c_char_p
+        lib.xpbd_status_string.argtypes = [C.c_int]
+        _lib = lib
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Simulator:
+    """One problem (mesh, constraints, schedule, options) resident on a GPU."""
+
+    def __init__(self, scene, dtype: torch.dtype = torch.float32, device="cuda:0",
+                 hbm_budget_bytes: int = 0, tape_mode: int = 0, tet_gamma_one: bool = False,
+                 iterations: Optional[int] = None, substeps: Optional[int] = None):
+        self.lib = load()
+        self.scene = scene
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self._ctx = _vp()
+        rest = np.ascontiguousarray(scene.rest, np.float64)
+        inv_mass = np.ascontiguousarray(scene.inv_mass, np.float64)
+        dist_v = np.ascontiguousarray(scene.dist_v, np.int32)
+        bend_v = np.ascontiguousarray(scene.bend_v, np.int32)
+        tet_v = np.ascontiguousarray(scene.tet_v, np.int32)
+        tet_nu = np.ascontiguousarray(scene.tet_nu, np.float64)
+        st, off, items = scene.schedule_arrays()
+        m = MeshDesc(scene.n_verts, rest.ctypes.data_as(_dp), inv_mass.ctypes.data_as(_dp))
+        cd = ConstraintDesc(scene.n_dist, dist_v.ctypes.data_as(_ip), scene.n_bend, bend_v.ctypes.data_as(_ip),
+                            scene.n_tet, tet_v.ctypes.data_as(_ip), tet_nu.ctypes.data_as(_dp),
+                            1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance)
+        sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip))
+        o = Options()
+        o.dt = scene.dt
+        o.substeps = scene.substeps if substeps is None else substeps
+        o.iterations = scene.iterations if iterations is None else iterations
+        for a in range(3):
+            o.gravity[a] = scene.gravity[a]
+        o.dtype = F64 if dtype == torch.float64 else F32
+        o.hbm_budget_bytes = hbm_budget_bytes
+        o.tet_gamma_one = 1 if tet_gamma_one else 0
+        o.tape_mode = tape_mode
+        with torch.cuda.device(self.device):
+            rc = self.lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(self._ctx))
+        if rc != XPBD_OK:
+            raise XPBDError(rc, self.lib.xpbd_last_error(None).decode())
+        self._fwd_keep = None
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc):
+        if rc != XPBD_OK:
+            raise XPBDError(rc, self.lib.xpbd_last_error(self._ctx).decode())
+
+    def close(self):
+        if self._ctx:
+            self.lib.xpbd_destroy(self._ctx)
+            self._ctx = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tensor(self, a, dtype=None) -> torch.Tensor:
+        return torch.as_tensor(np.asarray(a), dtype=dtype or self.dtype, device=self.device).contiguous()
+
+    def _params(self, dist_alpha, bend_alpha, tet_E, f_ext, sphere):
+        p = Params()
+        p.dist_compliance = _ptr(dist_alpha)
+        p.bend_compliance = _ptr(bend_alpha)
+        p.tet_E = _ptr(tet_E)
+        p.f_ext = _ptr(f_ext)
+        sph = self.scene.sphere if sphere is None else sphere
+        sph = [float(v) for v in (sph.tolist() if hasattr(sph, "tolist") else sph)]
+        for a in range(4):
+            p.sphere[a] = sph[a]
+        return p
+
+    def _arg(self, t, shape):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            t = self.tensor(t)
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {self.dtype} tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    # ------------------------------------------------------------------ API
+    def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
+                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None):
+        """Roll out; returns (x_frames or None, x_final, v_final) on the device."""
+        sc = self.scene
+        V = sc.n_verts
+        x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
+        v0 = self._arg(sc.v0 if v0 is None else v0, (V, 3))
+        da = self._arg(sc.dist_alpha if dist_alpha is None else dist_alpha, (sc.n_dist,)) if sc.n_dist else None
+        ba = self._arg(sc.bend_alpha if bend_alpha is None else bend_alpha, (sc.n_bend,)) if sc.n_bend else None
+        te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet,)) if sc.n_tet else None
+        fe = f_ext if f_ext is not None else sc.f_ext
+        fe = self._arg(fe, (n_frames, V, 3)) if fe is not None else None
+        p = self._params(da, ba, te, fe, sphere)
+        xf = None
+        if frames:
+            xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
+                                                                           device=self.device)
+        xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        ve = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        rc = self.lib.xpbd_forward(self._ctx, _ptr(x0), _ptr(v0), C.byref(p), n_frames, _ptr(xf), _ptr(xe),
+                                   _ptr(ve), _stream_ptr(self.device))
+        self._check(rc)
+        self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames)
+        return xf, xe, ve
+
+    def adjoint(self, dLdx_frames=None, frame_mask=None, dLdv_final=None, want=None) -> Dict[str, torch.Tensor]:
+        """Exact adjoint of the last forward; returns a dict of gradients."""
+        if self._fwd_keep is None:
+            raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
+        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+        sc = self.scene
+        V = sc.n_verts
+        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere"))
+        dev, f64 = self.device, torch.float64
+        g = {}
+        if "x0" in want:
+            g["x0"] = torch.empty((V, 3), dtype=self.dtype, device=dev)
+        if "v0" in want:
+            g["v0"] = torch.empty((V, 3), dtype=self.dtype, device=dev)
+        if "dist_alpha" in want and sc.n_dist:
+            g["dist_alpha"] = torch.empty(sc.n_dist, dtype=f64, device=dev)
+        if "bend_alpha" in want and sc.n_bend:
+            g["bend_alpha"] = torch.empty(sc.n_bend, dtype=f64, device=dev)
+        if "tet_E" in want and sc.n_tet:
+            g["tet_E"] = torch.empty(sc.n_tet, dtype=f64, device=dev)
+        if "f_ext" in want:
+            g["f_ext"] = torch.empty((F, V, 3), dtype=self.dtype, device=dev)
+        if "sphere" in want:
+            g["sphere"] = torch.empty(4, dtype=f64, device=dev)
+        gr = Grads(*(_ptr(g.get(k)) for k in ("dist_alpha", "bend_alpha", "tet_E", "f_ext", "x0", "v0",
+                                              "sphere")))
+        dl = self._arg(dLdx_frames, (F, V, 3)) if dLdx_frames is not None else None
+        dv = self._arg(dLdv_final, (V, 3)) if dLdv_final is not None else None
+        mask_arr = None
+        mask_ptr = None
+        if frame_mask is not None:
+            mask_arr = np.ascontiguousarray(np.asarray(frame_mask, dtype=np.uint8))
+            if mask_arr.shape != (F,):
+                raise ValueError("frame_mask must have one entry per frame")
+            mask_ptr = mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = self.lib.xpbd_adjoint(self._ctx, C.byref(p), _ptr(dl), mask_ptr, _ptr(dv), C.byref(gr),
+                                   _stream_ptr(self.device))
+        self._check(rc)
+        return g
+
+    def goal_l2(self, x_frames: torch.Tensor, targets: torch.Tensor, frame_mask=None):
+        """FP64 goal 1/2 sum_{masked f} |x(f) - x*(f)|^2 and its gradient."""
+        F = x_frames.shape[0]
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        dL = torch.empty_like(x_frames)
+        mask_arr = None if frame_mask is None else np.ascontiguousarray(np.asarray(frame_mask, np.uint8))
+        mp = None if mask_arr is None else mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = self.lib.xpbd_goal_l2(self._ctx, _ptr(x_frames), _ptr(targets), mp, F, _ptr(loss), _ptr(dL),
+                                   _stream_ptr(self.device))
+        self._check(rc)
+        return loss, dL
+
+    def info(self) -> Dict[str, int]:
+        i = Info()
+        self._check(self.lib.xpbd_get_info(self._ctx, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def profile_enable(self, stride: int = 1):
+        self._check(self.lib.xpbd_profile_enable(self._ctx, stride))
+
+    def profile_read(self):
+        """Per kernel family (2*type fwd, 2*type+1 reverse): launches, ms, items."""
+        la = (C.c_int64 * 8)()
+        ms = (C.c_double * 8)()
+        it = (C.c_int64 * 8)()
+        self._check(self.lib.xpbd_profile_read(self._ctx, la, ms, it))
+        return list(la), list(ms), list(it)

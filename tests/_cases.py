@@ -1,0 +1,72 @@
+"""Shared helpers for GPU-versus-reference comparisons (test support only)."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def needs_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return float(np.linalg.norm(a))
+    return float(np.linalg.norm(a - b) / nb)
+
+
+def reference_case(sc, F, mask=None, seed=0, noise=0.01, f_ext=None, emulate_f32=False, n_threads=4):
+    """Forward, targets, goal gradient and exact adjoint from the reference."""
+    osc = O.OracleScene(sc, emulate_f32=emulate_f32, n_threads=n_threads)
+    kw = {} if f_ext is None else {"f_ext": f_ext}
+    xf, xe, ve = O.forward(osc, F, **kw)
+    rng = np.random.default_rng(seed)
+    tgt = xf + noise * rng.standard_normal(xf.shape)
+    if mask is None:
+        mask = np.ones(F, bool)
+    L, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, F, dL, **kw)
+    return {"x_frames": xf, "x_final": xe, "v_final": ve, "targets": tgt, "mask": mask, "loss": L,
+            "dL": dL, "grads": g}
+
+
+def gpu_case(sim, F, ref, f_ext=None):
+    """Same rollout, goal and adjoint through the C ABI."""
+    import torch
+    fe = None if f_ext is None else sim.tensor(f_ext)
+    xf, xe, ve = sim.forward(F, f_ext=fe)
+    loss, dL = sim.goal_l2(xf, sim.tensor(ref["targets"]), ref["mask"])
+    g = sim.adjoint(dL, ref["mask"])
+    torch.cuda.synchronize()
+    out = {"x_frames": xf.double().cpu().numpy(), "x_final": xe.double().cpu().numpy(),
+           "v_final": ve.double().cpu().numpy(), "loss": float(loss.cpu()), "grads": {}}
+    for k, v in g.items():
+        out["grads"][k] = v.double().cpu().numpy()
+    return out
+
+
+GROUPS = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere")
+
+
+def compare(sc, ref, got, pos_tol, grad_tol, groups=GROUPS, report=None):
+    errs = {"x_frames": rel(got["x_frames"], ref["x_frames"]), "v_final": rel(got["v_final"], ref["v_final"]),
+            "loss": abs(got["loss"] - ref["loss"]) / max(abs(ref["loss"]), 1e-300)}
+    for k in groups:
+        if k not in got["grads"] or k not in ref["grads"]:
+            continue
+        r = ref["grads"][k]
+        if r.size == 0 or np.linalg.norm(r) == 0:
+            continue
+        errs[k] = rel(got["grads"][k], r)
+    if report is not None:
+        report.update(errs)
+    assert errs["x_frames"] <= pos_tol, errs
+    for k in groups:
+        if k in errs:
+            assert errs[k] <= grad_tol, (k, errs)
+    return errs

@@ -1,0 +1,131 @@
+"""The C ABI library loads, exports every declared entry point, and rejects
+invalid problems before touching the device (runs without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_01396_amd import lib as L
+from paper_2301_01396_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "xpbd.h")).read()
+    return sorted(set(re.findall(r"\b(xpbd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared()
+    assert "xpbd_create" in names and "xpbd_adjoint" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_status_strings():
+    lib = L.load()
+    assert lib.xpbd_status_string(0) == b"ok"
+    assert lib.xpbd_status_string(4) == b"invalid state"
+
+
+def _create(sc, **opt):
+    lib = L.load()
+    rest = np.ascontiguousarray(sc.rest, np.float64)
+    im = np.ascontiguousarray(sc.inv_mass, np.float64)
+    dv = np.ascontiguousarray(sc.dist_v, np.int32)
+    bv = np.ascontiguousarray(sc.bend_v, np.int32)
+    tv = np.ascontiguousarray(sc.tet_v, np.int32)
+    nu = np.ascontiguousarray(sc.tet_nu, np.float64)
+    st, off, items = sc.schedule_arrays()
+    m = L.MeshDesc(sc.n_verts, rest.ctypes.data_as(L._dp), im.ctypes.data_as(L._dp))
+    cd = L.ConstraintDesc(sc.n_dist, dv.ctypes.data_as(L._ip), sc.n_bend, bv.ctypes.data_as(L._ip), sc.n_tet,
+                          tv.ctypes.data_as(L._ip), nu.ctypes.data_as(L._dp), 1 if sc.contact else 0,
+                          sc.contact_thickness, sc.contact_compliance)
+    sd = L.ScheduleDesc(len(st), st.ctypes.data_as(L._ip), off.ctypes.data_as(L._lp), items.ctypes.data_as(L._ip))
+    o = L.Options()
+    o.dt = opt.get("dt", sc.dt)
+    o.substeps = opt.get("substeps", sc.substeps)
+    o.iterations = opt.get("iterations", sc.iterations)
+    o.dtype = opt.get("dtype", 0)
+    o.tape_mode = opt.get("tape_mode", 0)
+    ctx = C.c_void_p()
+    rc = lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(ctx))
+    msg = lib.xpbd_last_error(None).decode()
+    return rc, ctx, msg
+
+
+def test_rejects_non_independent_set():
+    sc = scenes.small_cloth(n=4)
+    # put two edges sharing a vertex into one set
+    sc.set_items[0] = np.concatenate([sc.set_items[0], sc.set_items[1][:1]])
+    sc.set_items[1] = sc.set_items[1][1:]
+    rc, ctx, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "not independent" in msg
+
+
+def test_rejects_missing_and_repeated_constraints():
+    sc = scenes.small_cloth(n=4)
+    sc.set_items[0] = sc.set_items[0][1:]
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "not scheduled" in msg
+    sc = scenes.small_cloth(n=4)
+    sc.set_type.append(scenes.DIST)
+    sc.set_items.append(sc.set_items[0][:1].copy())
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "twice" in msg
+
+
+def test_rejects_bad_indices_and_geometry():
+    sc = scenes.small_cloth(n=4)
+    sc.dist_v = sc.dist_v.copy()
+    sc.dist_v[2, 1] = 99
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "out of range" in msg
+    sc = scenes.small_tets(n=1)
+    sc.tet_v = sc.tet_v.copy()
+    sc.tet_v[0, [2, 3]] = sc.tet_v[0, [3, 2]]      # inverted rest tet
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "rest volume" in msg
+
+
+def test_rejects_contact_on_pinned_vertex_and_bad_options():
+    sc = scenes.small_cloth(n=4)
+    sc.set_items[-1] = np.concatenate([sc.set_items[-1], [0]]).astype(np.int32)   # vertex 0 is pinned
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "pinned" in msg
+    sc = scenes.small_cloth(n=4)
+    assert _create(sc, substeps=0)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, dt=-1.0)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, dtype=7)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, tape_mode=3)[0] == L.XPBD_ERR_INVALID
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = L.load()
+    assert lib.xpbd_destroy(None) == L.XPBD_ERR_INVALID
+    p = L.Params()
+    assert lib.xpbd_forward(None, None, None, C.byref(p), 1, None, None, None, None) == L.XPBD_ERR_INVALID
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.small_cloth(n=6), lambda: scenes.small_tets(n=2),
+                                   lambda: scenes.config_c1(1)])
+def test_generated_schedules_are_valid_colorings(maker):
+    sc = maker()
+    st, off, items = sc.schedule_arrays()
+    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v}
+    seen = {k: np.zeros(len(v), int) for k, v in cv.items()}
+    for s in range(len(st)):
+        it = items[off[s]:off[s + 1]]
+        if st[s] == scenes.CONTACT:
+            verts = it
+        else:
+            verts = cv[st[s]][it].ravel()
+            seen[st[s]][it] += 1
+        assert len(np.unique(verts)) == len(verts)
+    for k, v in seen.items():
+        assert np.all(v == 1)

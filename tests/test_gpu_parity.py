@@ -1,0 +1,132 @@
+"""GPU (through the C ABI) against the FP64 reference, element by element.
+
+Tolerances: FP64 GPU runs, positions 1e-10 and gradients 1e-8 relative L2;
+FP32 GPU runs, positions 1e-5 and gradients 1e-3 relative L2 per parameter
+group (the reference is FP64 in both cases).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2301_01396_amd import scenes
+from tests._cases import compare, gpu_case, needs_gpu, reference_case, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(sc, dtype, **kw):
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    needs_gpu()
+    return Simulator(sc, dtype=torch.float64 if dtype == "f64" else torch.float32, **kw)
+
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_small_cloth_bending_contact(dtype, pos_tol, grad_tol):
+    sc = scenes.small_cloth(n=6, frames=3, substeps=2, iterations=5)
+    rng = np.random.default_rng(1)
+    f = 0.3 * rng.standard_normal((3, sc.n_verts, 3))
+    ref = reference_case(sc, 3, mask=np.array([0, 1, 1], bool), f_ext=f)
+    assert np.linalg.norm(ref["grads"]["sphere"]) > 0
+    got = gpu_case(_sim(sc, dtype), 3, ref, f_ext=f)
+    compare(sc, ref, got, pos_tol, grad_tol)
+
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_small_tets(dtype, pos_tol, grad_tol):
+    sc = scenes.small_tets(n=3, frames=3, substeps=2, iterations=5)
+    ref = reference_case(sc, 3, noise=1e-3)
+    got = gpu_case(_sim(sc, dtype), 3, ref)
+    compare(sc, ref, got, pos_tol, grad_tol)
+
+
+def test_cloth32_distance_fp64_full_rollout():
+    """The 32x32 FP64 configuration (60 frames, 20 iterations), every output."""
+    sc = scenes.config_c1(n_frames=60)
+    tg = scenes.config_c1(n_frames=60, target=True)
+    osc = O.OracleScene(sc, n_threads=4)
+    xt, _, _ = O.forward(O.OracleScene(tg, n_threads=4), 60)
+    mask = np.zeros(60, bool)
+    mask[-1] = True
+    xf, _, _ = O.forward(osc, 60)
+    L, dL = O.goal_l2(xf, xt, mask)
+    g = O.adjoint(osc, 60, dL)
+    ref = {"x_frames": xf, "targets": xt, "mask": mask, "loss": L, "grads": g,
+           "v_final": O.forward(osc, 60)[2]}
+    got = gpu_case(_sim(sc, "f64"), 60, ref)
+    errs = compare(sc, ref, got, 1e-10, 1e-8, groups=("x0", "v0", "dist_alpha"))
+    assert errs["loss"] < 1e-9
+
+
+def test_ragged_sets_several_tiles():
+    """A 40x37 cloth: every set spans several 256-wide tiles with a ragged tail."""
+    sc = scenes.small_cloth(n=6, frames=2, substeps=1, iterations=3)
+    big = scenes.cloth_grid(40, 37, 0.02, origin=(-0.4, 0.0, -0.36), pinned=(0, 36), contact=True)
+    rng = np.random.default_rng(2)
+    big.dist_alpha = 1e-6 * rng.uniform(0.5, 2, big.n_dist)
+    big.bend_alpha = 1e-3 * rng.uniform(0.5, 2, big.n_bend)
+    big.tet_E = np.zeros(0)
+    big.sphere = (0.0, -0.25, 0.0, 0.3)
+    big.contact_compliance = 1e-7
+    big.dt, big.substeps, big.iterations, big.n_frames = 1 / 60, 2, 4, 2
+    assert all(len(s) % 256 != 0 for s in big.set_items)
+    assert max(len(s) for s in big.set_items) > 512
+    ref = reference_case(big, 2, n_threads=8)
+    got = gpu_case(_sim(big, "f64"), 2, ref)
+    compare(big, ref, got, 1e-10, 1e-8)
+    del sc
+
+
+@pytest.mark.parametrize("K,S", [(0, 2), (1, 1), (2, 3)])
+def test_iteration_and_substep_edge_counts(K, S):
+    sc = scenes.small_cloth(n=5, frames=2, substeps=S, iterations=K)
+    ref = reference_case(sc, 2)
+    got = gpu_case(_sim(sc, "f64"), 2, ref)
+    compare(sc, ref, got, 1e-10, 1e-8)
+
+
+def test_degenerate_constraints():
+    """Pinned-pinned edge with compliance (updates lambda only), a zero
+    compliance edge, and an empty set in the schedule."""
+    sc = scenes.small_cloth(n=5, frames=2, substeps=2, iterations=3, pinned=(0, 1, 2, 3, 4), sphere=False)
+    sc.dist_alpha[0] = 0.0
+    sc.set_type.append(scenes.DIST)
+    sc.set_items.append(np.zeros(0, np.int32))
+    ref = reference_case(sc, 2)
+    got = gpu_case(_sim(sc, "f64"), 2, ref)
+    compare(sc, ref, got, 1e-10, 1e-8)
+
+
+def test_bitwise_determinism_and_tape_modes():
+    import torch
+    sc = scenes.small_cloth(n=12, frames=3, substeps=3, iterations=4)
+    ref = reference_case(sc, 3, n_threads=8)
+    outs = []
+    for mode in (1, 1, 2):
+        got = gpu_case(_sim(sc, "f32", tape_mode=mode), 3, ref)
+        outs.append(got)
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            assert np.array_equal(o["grads"][k], v), k
+    del torch
+
+
+def test_goal_matches_reference():
+    sc = scenes.small_cloth(n=6, frames=3, substeps=1, iterations=2)
+    ref = reference_case(sc, 3, mask=np.array([1, 0, 1], bool))
+    got = gpu_case(_sim(sc, "f64"), 3, ref)
+    assert abs(got["loss"] - ref["loss"]) <= 1e-12 * ref["loss"]
+
+
+def test_nonfinite_parameter_is_rejected():
+    import torch
+    from paper_2301_01396_amd.lib import XPBDError, XPBD_ERR_NONFINITE
+    sc = scenes.small_cloth(n=4, frames=1)
+    sim = _sim(sc, "f32")
+    a = sim.tensor(sc.dist_alpha)
+    a[3] = float("nan")
+    with pytest.raises(XPBDError) as e:
+        sim.forward(1, dist_alpha=a)
+    assert e.value.status == XPBD_ERR_NONFINITE
+    del torch
