@@ -1,0 +1,289 @@
+"""Benchmark: forward + exact-adjoint XPBD constraint projections per second.
+
+One step = one differentiable rollout of the workload (every frame, substep,
+iteration and independent set) followed by its adjoint, through the
+torch.autograd binding, with inputs resident on the GPU.  Counted
+projections are forward evaluations plus reverse evaluations (the adjoint's
+recomputation of each frame is overhead and not counted); a tet counts its
+deviatoric and hydrostatic projections, a contact constraint counts once
+per evaluation.
+
+Default workload: cloth 256x256 with distance, bending and sphere contact,
+FP32, dt 1/60, 4 substeps, 30 iterations, 30 frames, gradients with respect
+to both compliance fields and v0.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic bytes per projection of each kernel family in FP32 (index =
+# 2 * type forward, 2 * type + 1 reverse), from the record and vertex traffic
+# each one must move: see the kernel table of the design notes.
+ALG_BYTES = {             # family: (index bytes, words of the state dtype)
+    0: (8, 20), 1: (8, 26),     # distance fwd: idx 8 + L, at, lambda r/w + 2 vertices r/w
+    2: (16, 36), 3: (16, 48),   # bending
+    4: (8, 24), 5: (8, 31),     # tet, per projection (one tet item moves twice this)
+    6: (4, 10), 7: (4, 22),     # contact
+}
+
+
+# record words written per projection by a forward that keeps the adjoint's
+# record (vertex differences + multiplier): dist 4, bend 10, tet 6 (12 per
+# item), contact 4
+TAPE_WORDS = {0: 4, 2: 10, 4: 6, 6: 4}
+
+
+def alg_bytes(fam: int, tsz: int, recording: bool = False) -> float:
+    ib, words = ALG_BYTES[fam]
+    if recording and fam in TAPE_WORDS:
+        words += TAPE_WORDS[fam]
+    return ib + words * tsz
+
+
+def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
+    """Average algorithmic bytes per projection over the workload's mix (the
+    persistent frame kernel runs every set type)."""
+    n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
+         6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
+    tot = sum(n.values())
+    return sum(cnt * alg_bytes(f + (1 if reverse else 0), tsz, recording and not reverse)
+               for f, cnt in n.items()) / max(tot, 1)
+
+
+FAMILY = {0: "dist_fwd", 1: "dist_rev", 2: "bend_fwd", 3: "bend_rev", 4: "tet_fwd", 5: "tet_rev",
+          6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev"}
+KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: "k_tet", 5: "k_tet_rev",
+                 6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)"}
+HBM_PEAK_GBS = 8000.0
+
+
+def csrc_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2301_01396_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str):
+    from paper_2301_01396_amd import scenes
+    if name == "c1":
+        return scenes.config_c1(), scenes.config_c1(target=True)
+    if name == "c2":
+        return scenes.config_c2(), scenes.config_c2(target=True)
+    if name == "c3":
+        return scenes.config_c3(), scenes.config_c3(target=True)
+    if name == "c4":
+        return scenes.config_c4(), None
+    raise SystemExit(f"unknown workload {name}")
+
+
+def workload_config(name, sc, F):
+    return {"workload": {"c1": "cloth32_distance_fp64", "c2": "cloth256_dist_bend_sphere",
+                         "c3": "tetbox64_neohookean", "c4": "cloth2048x4096_dist_bend_force"}[name],
+            "verts": sc.n_verts, "dist": sc.n_dist, "bend": sc.n_bend, "tets": sc.n_tet,
+            "contacts": int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0,
+            "frames": F, "substeps": sc.substeps, "iterations": sc.iterations, "dt": sc.dt,
+            "sets_per_iteration": len(sc.set_type)}
+
+
+def cpu_baseline(name, sc, budget_s: float = 20.0):
+    """The FP64 reference on the host cores, on a bounded prefix of the
+    workload (one frame, or fewer substeps), forward + adjoint."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    osc = O.OracleScene(sc, n_threads=threads)
+    kw = {}
+    if sc.f_ext is not None:
+        kw["f_ext"] = sc.f_ext[:1]
+    t0 = time.perf_counter()
+    xf, _, _ = O.forward(osc, 1, **kw)
+    t1 = time.perf_counter()
+    dL = xf - xf.mean(axis=1, keepdims=True)
+    O.adjoint(osc, 1, dL, **kw)
+    t2 = time.perf_counter()
+    proj = sc.projections_per_rollout(1)
+    value = 2 * proj / (t2 - t0)
+    return {"value": value, "unit": "projections/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 frame of the workload ({proj} forward + {proj} reverse projections, FP64): "
+                      f"forward {t1 - t0:.2f} s, adjoint incl. recompute {t2 - t1:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--frames", type=int, default=0, help="override frame count (0 = the workload's)")
+    ap.add_argument("--profile-stride", type=int, default=4,
+                    help="bracket every n-th projection launch with HIP events (0 = off)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default="auto", choices=["auto", "plain", "persistent"])
+    ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0 = auto)")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="also time this many steps with one launch per set (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_01396_amd import autograd as AG
+    from paper_2301_01396_amd.lib import Simulator
+
+    dev = torch.device("cuda:0")
+    sc, tg = make_workload(args.workload)
+    F = args.frames or sc.n_frames
+    dtype = torch.float64 if args.workload == "c1" else torch.float32
+    lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
+    sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
+
+    # ---------------- targets (outside the timed region)
+    mask = np.zeros(F, np.uint8)
+    if args.workload == "c4":
+        mask[min(9, F - 1)] = 1
+        mask[F - 1] = 1
+        from paper_2301_01396_amd import scenes
+        f_key = sim.tensor(scenes.force_field(5, 4096, 2048, F))
+        targets, _, _ = sim.forward(F, f_ext=f_key)
+        del f_key
+        f_ctrl = sim.tensor(sc.f_ext[:F])
+    else:
+        mask[F - 1] = 1
+        tsim = Simulator(tg, dtype=dtype, device=dev)
+        targets, _, _ = tsim.forward(F)
+        tsim.close()
+        f_ctrl = None
+    torch.cuda.synchronize()
+
+    x0 = sim.tensor(sc.x0)
+    v0 = sim.tensor(sc.v0).requires_grad_(args.workload in ("c2",))
+    da = sim.tensor(sc.dist_alpha).requires_grad_(args.workload in ("c1", "c2")) if sc.n_dist else None
+    ba = sim.tensor(sc.bend_alpha).requires_grad_(args.workload == "c2") if sc.n_bend else None
+    te = sim.tensor(sc.tet_E).requires_grad_(True) if sc.n_tet else None
+    if f_ctrl is not None:
+        f_ctrl.requires_grad_(True)
+    sphere = torch.tensor(sc.sphere, dtype=torch.float64) if sc.contact else None
+    leaves = [t for t in (v0, da, ba, te, f_ctrl) if t is not None and t.requires_grad]
+
+    def step(s=sim):
+        for t in leaves:
+            t.grad = None
+        xf = AG.rollout(s, F, x0, v0, da, ba, te, f_ctrl, sphere)
+        loss = AG.goal_l2(s, xf, targets, mask)
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+        log("warmup step done")
+    torch.cuda.synchronize()
+    sim.profile_read()
+    # the persistent path launches two kernels per frame: time every one
+    sim.profile_enable(1 if sim.info()["persistent"] and args.profile_stride else args.profile_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.profile_enable(0)
+    launches, ms, items = sim.profile_read()
+    elapsed = t1 - t0
+    proj_step = 2 * sc.projections_per_rollout(F)
+    value = proj_step * args.steps / elapsed
+    grads_finite = all(bool(torch.isfinite(t.grad).all()) for t in leaves)
+    info = sim.info()
+    log(f"timed {args.steps} steps: {elapsed / args.steps * 1e3:.1f} ms/step, info {info}")
+    recording = info["tape_mode"] == 3
+
+    plain = None
+    if args.plain_steps > 0 and info["persistent"]:
+        psim = Simulator(sc, dtype=dtype, device=dev, launch_mode=1)
+        step(psim)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(psim)
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        psim.close()
+        plain = {"value": proj_step * args.plain_steps / (p1 - p0),
+                 "ms_per_step": (p1 - p0) / args.plain_steps * 1e3, "steps": args.plain_steps,
+                 "launch": "one kernel launch per independent set"}
+        log(f"plain launch: {plain['ms_per_step']:.1f} ms/step")
+
+    roof = None
+    kernels = {}
+    tsz = 8 if dtype == torch.float64 else 4
+    def fam_bytes(fam):
+        if fam == 8:
+            return mix_bytes(sc, False, tsz, recording)
+        if fam == 9:
+            return mix_bytes(sc, True, tsz, recording)
+        return alg_bytes(fam, tsz, recording)
+
+    for fam in range(10):
+        if launches[fam]:
+            avg_ms = ms[fam] / launches[fam]
+            per_launch_items = items[fam] / launches[fam]
+            gbs = fam_bytes(fam) * per_launch_items / (avg_ms * 1e-3) / 1e9
+            kernels[FAMILY[fam]] = {"launches_sampled": launches[fam], "avg_us": round(avg_ms * 1e3, 3),
+                                    "items_per_launch": round(per_launch_items, 1),
+                                    "alg_GBps": round(gbs, 1),
+                                    "share_of_sampled_ms": None}
+    tot = sum(ms)
+    for fam in range(10):
+        if launches[fam]:
+            kernels[FAMILY[fam]]["share_of_sampled_ms"] = round(ms[fam] / tot, 3)
+    if tot > 0:
+        dom = max(range(10), key=lambda f: ms[f])
+        k = kernels[FAMILY[dom]]
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+        if os.path.exists(tf):
+            rec = json.load(open(tf)).get(f"{args.workload}:{KERNEL_SYMBOL[dom]}")
+            if rec and rec.get("csrc_sha") == csrc_hash():
+                traffic = rec["bytes_per_dispatch_scaled"] * k["items_per_launch"] / rec["items_per_dispatch"]
+        roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": k["alg_GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(k["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_projection": round(fam_bytes(dom), 1),
+                "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, sc)
+
+    out = {
+        "metric": "constraint projections/s fwd+adjoint",
+        "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if dtype == torch.float64 else "f32",
+        "data": "synthetic (seeded grid cloth / tet box, parameters and targets generated)",
+        "config": workload_config(args.workload, sc, F),
+        "projections_per_step": proj_step, "loss": float(loss.detach().cpu()), "grads_finite": grads_finite,
+        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "plain_launch": plain,
+        "launch": "persistent frame kernel" if info["persistent"] else "one kernel launch per set",
+        "persistent_blocks": info["persistent_blocks"], "tape_mode": info["tape_mode"],
+        "profile_stride": args.profile_stride, "csrc_sha": csrc_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

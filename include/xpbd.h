@@ -114,7 +114,20 @@ typedef struct {
   xpbd_dtype dtype;          /* arithmetic and storage type of the state */
   size_t hbm_budget_bytes;   /* 0 = no limit; else XPBD_ERR_OOM past it */
   int32_t tet_gamma_one;     /* 1: gamma = 1 (the formula as printed); 0: 1 + mu/lambda */
-  int32_t tape_mode;         /* 0 auto, 1 record a whole frame, 2 one substep at a time */
+  int32_t tape_mode;         /* record of projection inputs for the adjoint:
+                                0 auto: the whole rollout during a forward flagged
+                                  XPBD_FWD_FOR_ADJOINT if it fits, else per frame,
+                                  else per substep;
+                                1 recompute each frame from its checkpoint, record
+                                  the whole frame;
+                                2 recompute one substep at a time (least memory);
+                                3 record the whole rollout during the forward (needs
+                                  XPBD_FWD_FOR_ADJOINT; XPBD_ERR_OOM if it does not fit) */
+  int32_t launch_mode;       /* 0 auto, 1 one kernel launch per independent set,
+                                2 persistent: one cooperative launch runs a whole frame's
+                                  sets with a grid-wide barrier between sets */
+  int32_t persistent_blocks; /* workgroups of the persistent launch, 0 = sized to the
+                                largest set (capped at what the device co-schedules) */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral
@@ -143,10 +156,14 @@ typedef struct {
  * vertices is ignored).  Writes the end-of-frame positions to x_frames
  * (device [F][V][3], may be NULL) and the final state to x_final, v_final
  * (device [V][3], may be NULL).  Keeps per-frame checkpoints for
- * xpbd_adjoint.  Errors: XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP. */
+ * xpbd_adjoint; with flags & XPBD_FWD_FOR_ADJOINT it may also keep the
+ * record of every projection's inputs (tape_mode 0 or 3) so that the
+ * adjoint needs no recomputation.  Errors: XPBD_ERR_INVALID, XPBD_ERR_OOM,
+ * XPBD_ERR_NONFINITE, XPBD_ERR_HIP. */
+#define XPBD_FWD_FOR_ADJOINT 1
 xpbd_status xpbd_forward(xpbd_ctx ctx, const void* x0, const void* v0, const xpbd_params* p,
                          int32_t n_frames, void* x_frames, void* x_final, void* v_final,
-                         void* stream);
+                         int32_t flags, void* stream);
 
 /* Gradient outputs (device).  Any pointer may be NULL.  Parameter gradients
  * are accumulated and returned in FP64; state-shaped ones in the ctx dtype.
@@ -185,17 +202,22 @@ typedef struct {
   int64_t projections_per_iteration;   /* tets count D and H; contacts counted as evaluated */
   int64_t device_bytes;                /* device memory held by the context now */
   int64_t tape_bytes_per_iteration;    /* record of projection inputs, one iteration */
-  int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep) */
+  int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep, 3 forward record) */
+  int32_t persistent;                  /* 1 if frames run as persistent launches */
+  int32_t persistent_blocks;           /* their workgroup count (0 before the first) */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 
-/* Kernel timing for measurement: when enabled, every launch of the
- * projection and reverse kernels is bracketed by HIP events on the call's
- * stream; xpbd_profile_read synchronises them and returns, per kernel family
- * (index = 2 * type for forward projections, 2 * type + 1 for reverse),
- * the number of launches, total milliseconds and total items processed. */
+/* Kernel timing for measurement: with on = n > 0, every n-th launch of the
+ * projection and reverse kernels (plain mode) or of the per-frame
+ * persistent kernels is bracketed by HIP events on the call's stream (0 =
+ * off).  xpbd_profile_read synchronises them and returns, per kernel family
+ * (index 2 * type: forward projections of that type, 2 * type + 1: their
+ * reverse; 8: persistent forward frame, 9: persistent reverse frame), the
+ * number of timed launches, their total milliseconds and the projections
+ * they processed, then resets the counts. */
 xpbd_status xpbd_profile_enable(xpbd_ctx ctx, int32_t on);
-xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[8], double ms[8], int64_t items[8]);
+xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[10], double ms[10], int64_t items[10]);
 
 const char* xpbd_last_error(xpbd_ctx ctx);
 const char* xpbd_status_string(xpbd_status s);

@@ -114,8 +114,18 @@ struct xpbd_ctx_s {
   void* contact_lamb = nullptr; void* contact_sacc = nullptr;
   void* tape = nullptr; size_t tape_cap = 0;
 
+  // persistent program launches
+  bool persistent = false;
+  int prog_blocks_opt = 0;
+  int prog_grid = 0;
+  Phase* fw_prog = nullptr; Phase* rv_prog = nullptr;
+  int n_fw_prog = 0, n_rv_prog = 0;
+  unsigned* bar = nullptr;
+  int* abort_flag = nullptr;
+
   // forward bookkeeping for the adjoint
   bool have_forward = false;
+  bool fwd_recorded = false;
   int fwd_frames = 0;
   xpbd_params fwd_params{};
 
@@ -125,9 +135,9 @@ struct xpbd_ctx_s {
   struct Ev { hipEvent_t a, b; int fam; int64_t items; };
   std::vector<Ev> ev_pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-  int64_t prof_launch[8] = {0};
-  double prof_ms[8] = {0};
-  int64_t prof_items[8] = {0};
+  int64_t prof_launch[10] = {0};
+  double prof_ms[10] = {0};
+  int64_t prof_items[10] = {0};
 
   ~xpbd_ctx_s() {
     for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
@@ -245,137 +255,202 @@ template <class T> struct Ops {
     if (e != hipSuccess) fail(XPBD_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   }
 
-  static Sphere<T> sphere(xpbd_ctx c, const double* s) {
-    return Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
+  static Dev<T> dev(xpbd_ctx c, const double* s) {
+    Dev<T> D{};
+    D.X = (V4*)c->X; D.Vv = (V4*)c->Vv; D.Xp = (V4*)c->Xp; D.XB = (V4*)c->XB; D.VB = (V4*)c->VB; D.V = c->V;
+    D.d_idx = c->dist_idx; D.d_rest = (const T*)c->dist_rest; D.d_at = (const T*)c->dist_at;
+    D.d_lam = (T*)c->dist_lam; D.d_lamb = (T*)c->dist_lamb; D.d_ab = (T*)c->dist_ab; D.d_acc = c->dist_acc;
+    D.b_idx = c->bend_idx; D.b_th0 = (const T*)c->bend_theta0; D.b_at = (const T*)c->bend_at;
+    D.b_lam = (T*)c->bend_lam; D.b_lamb = (T*)c->bend_lamb; D.b_ab = (T*)c->bend_ab; D.b_acc = c->bend_acc;
+    D.tr = TetRec<T>{c->tet_idx, (const T*)c->tet_B, (const T*)c->tet_atD, (const T*)c->tet_atH,
+                     (const T*)c->tet_gamma, c->n_tet};
+    D.t_lamD = (T*)c->tet_lamD; D.t_lamH = (T*)c->tet_lamH; D.t_lambD = (T*)c->tet_lambD;
+    D.t_lambH = (T*)c->tet_lambH; D.t_eb = (T*)c->tet_eb; D.t_acc = c->tet_acc;
+    D.c_vid = c->contact_vid; D.c_lam = (T*)c->contact_lam; D.c_lamb = (T*)c->contact_lamb;
+    D.c_sacc = (V4*)c->contact_sacc;
+    D.sph = Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
+    D.h = (T)c->h; D.inv_h = (T)(1.0 / c->h);
+    D.gx = (T)c->g[0]; D.gy = (T)c->g[1]; D.gz = (T)c->g[2];
+    return D;
   }
 
-  // one forward projection launch of set si
-  static void project(xpbd_ctx c, const SetInfo& si, bool first, V4* tape, const double* sph, hipStream_t st) {
+  // ------------------------------------------------------------ plain launches (one per set)
+  static void project(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, V4* tape, hipStream_t st) {
     if (si.count == 0) return;
     unsigned nb = nblocks(si.count);
-    V4* X = (V4*)c->X;
     xpbd_ctx_s::Ev ev;
     bool on;
     prof_begin(c, st, 2 * si.type, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
-#define XPBD_LAUNCH(KERN, ...)                                                          \
-  do {                                                                                  \
-    if (first) {                                                                        \
-      if (tape) KERN<T, true, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                \
-      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                    \
-    } else {                                                                            \
-      if (tape) KERN<T, false, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);               \
-      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                   \
-    }                                                                                   \
+#define XPBD_LAUNCH(KERN, TP)                                                                     \
+  do {                                                                                            \
+    if (first) {                                                                                  \
+      if (tape) KERN<T, true, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);     \
+      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);         \
+    } else {                                                                                      \
+      if (tape) KERN<T, false, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);    \
+      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);        \
+    }                                                                                             \
   } while (0)
     switch (si.type) {
-      case XPBD_DIST:
-        XPBD_LAUNCH(k_dist, c->dist_idx, (const T*)c->dist_rest, (const T*)c->dist_at, (T*)c->dist_lam, X,
-                    si.begin, si.count, tape);
-        break;
-      case XPBD_BEND:
-        XPBD_LAUNCH(k_bend, c->bend_idx, (const T*)c->bend_theta0, (const T*)c->bend_at, (T*)c->bend_lam, X,
-                    si.begin, si.count, tape);
-        break;
-      case XPBD_TET: {
-        TetRec<T> R{c->tet_idx, (const T*)c->tet_B, (const T*)c->tet_atD, (const T*)c->tet_atH,
-                    (const T*)c->tet_gamma, c->n_tet};
-        XPBD_LAUNCH(k_tet, R, (T*)c->tet_lamD, (T*)c->tet_lamH, X, si.begin, si.count, tape);
-        break;
-      }
-      default:
-        XPBD_LAUNCH(k_contact, c->contact_vid, (T*)c->contact_lam, X, si.begin, si.count, sphere(c, sph), tape);
-        break;
+      case XPBD_DIST: XPBD_LAUNCH(k_dist, V4); break;
+      case XPBD_BEND: XPBD_LAUNCH(k_bend, V4); break;
+      case XPBD_TET: XPBD_LAUNCH(k_tet, V4); break;
+      default: XPBD_LAUNCH(k_contact, V4); break;
     }
-#undef XPBD_LAUNCH
     check_launch();
     prof_end(c, st, ev, on);
   }
 
-  static void reverse(xpbd_ctx c, const SetInfo& si, bool first, bool last, const V4* tape, const double* sph,
+  static void reverse(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, bool last, const V4* tape,
                       hipStream_t st) {
     if (si.count == 0) return;
     unsigned nb = nblocks(si.count);
-    V4* XB = (V4*)c->XB;
     xpbd_ctx_s::Ev ev;
     bool on;
     prof_begin(c, st, 2 * si.type + 1, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
-#define XPBD_LAUNCH(KERN, ...)                                                          \
-  do {                                                                                  \
-    if (first) {                                                                        \
-      if (last) KERN<T, true, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                \
-      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                    \
-    } else {                                                                            \
-      if (last) KERN<T, false, true><<<nb, kBlock, 0, st>>>(__VA_ARGS__);               \
-      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(__VA_ARGS__);                   \
-    }                                                                                   \
+    const bool tape_ = last;   // second template flag of the reverse kernels is LAST
+    (void)tape_;
+#define XPBD_RLAUNCH(KERN)                                                                        \
+  do {                                                                                            \
+    if (first) {                                                                                  \
+      if (last) KERN<T, true, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);          \
+      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);              \
+    } else {                                                                                      \
+      if (last) KERN<T, false, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);         \
+      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);             \
+    }                                                                                             \
   } while (0)
     switch (si.type) {
-      case XPBD_DIST:
-        XPBD_LAUNCH(k_dist_rev, c->dist_idx, (const T*)c->dist_rest, (const T*)c->dist_at, XB, (T*)c->dist_lamb,
-                    (T*)c->dist_ab, c->dist_acc, si.begin, si.count, tape);
-        break;
-      case XPBD_BEND:
-        XPBD_LAUNCH(k_bend_rev, c->bend_idx, (const T*)c->bend_theta0, (const T*)c->bend_at, XB,
-                    (T*)c->bend_lamb, (T*)c->bend_ab, c->bend_acc, si.begin, si.count, tape);
-        break;
-      case XPBD_TET: {
-        TetRec<T> R{c->tet_idx, (const T*)c->tet_B, (const T*)c->tet_atD, (const T*)c->tet_atH,
-                    (const T*)c->tet_gamma, c->n_tet};
-        XPBD_LAUNCH(k_tet_rev, R, XB, (T*)c->tet_lambD, (T*)c->tet_lambH, (T*)c->tet_eb, c->tet_acc, si.begin,
-                    si.count, tape);
-        break;
-      }
-      default:
-        XPBD_LAUNCH(k_contact_rev, c->contact_vid, XB, (T*)c->contact_lamb, (V4*)c->contact_sacc, si.begin,
-                    si.count, sphere(c, sph), tape);
-        break;
+      case XPBD_DIST: XPBD_RLAUNCH(k_dist_rev); break;
+      case XPBD_BEND: XPBD_RLAUNCH(k_bend_rev); break;
+      case XPBD_TET: XPBD_RLAUNCH(k_tet_rev); break;
+      default: XPBD_RLAUNCH(k_contact_rev); break;
     }
 #undef XPBD_LAUNCH
+#undef XPBD_RLAUNCH
     check_launch();
     prof_end(c, st, ev, on);
   }
 
-  // tape pointer of set k, iteration it, substep slot s (within the tape buffer)
+  // record pointer of set si, iteration it, substep slot (within the record buffer)
   static V4* tape_at(xpbd_ctx c, int slot, int it, const SetInfo& si) {
     char* base = (char*)c->tape + ((size_t)slot * c->K + it) * c->iter_tape_bytes + si.tape_off;
     return (V4*)base;
   }
 
-  // one substep of Eq. xpbdUpdateRule; tape slot < 0 means no record
-  static void substep(xpbd_ctx c, const T* f, const double* sph, int slot, hipStream_t st) {
-    const int V = c->V;
-    T h = (T)c->h;
-    k_predict<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->X, (V4*)c->Vv, (V4*)c->Xp, f, h, (T)c->g[0], (T)c->g[1],
-                                                (T)c->g[2], V);
+  // one substep of Eq. xpbdUpdateRule; record slot < 0 means no record
+  static void substep(xpbd_ctx c, const Dev<T>& D, const T* f, int slot, hipStream_t st) {
+    k_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, f);
     check_launch();
     for (int it = 0; it < c->K; ++it)
-      for (const SetInfo& si : c->sets)
-        project(c, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, sph, st);
-    k_velocity<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (V4*)c->Vv, (const V4*)c->Xp,
-                                                 (T)(1.0 / c->h), V);
+      for (const SetInfo& si : c->sets) project(c, D, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
+    k_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
   }
 
-  static void reverse_substep(xpbd_ctx c, T* fbar, const double* sph, double* dsph, int slot, hipStream_t st) {
-    const int V = c->V;
-    T h = (T)c->h, ih = (T)(1.0 / c->h);
-    k_rev_velocity<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const V4*)c->VB, ih, V);
+  static void reverse_substep(xpbd_ctx c, const Dev<T>& D, T* fbar, double* dsph, int slot, hipStream_t st) {
+    k_rev_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
     for (int it = c->K - 1; it >= 0; --it)
       for (int k = (int)c->sets.size() - 1; k >= 0; --k) {
         const SetInfo& si = c->sets[k];
-        reverse(c, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), sph, st);
+        reverse(c, D, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), st);
       }
     if (c->K > 0 && dsph)
       for (const SetInfo& si : c->sets)
         if (si.type == XPBD_CONTACT && si.count > 0) {
-          k_sphere_reduce<T><<<1, 1024, 0, st>>>((const V4*)c->contact_sacc, si.begin, si.count, dsph);
+          k_sphere_reduce<T><<<1, kBlock, 0, st>>>((const V4*)c->contact_sacc, si.begin, si.count, dsph);
           check_launch();
         }
-    k_rev_predict<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, fbar, h, ih, V);
+    k_rev_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, fbar);
     check_launch();
   }
 
+  // ------------------------------------------------------------ persistent program launches
+  // Forward program of one frame: S x (predict, K x sets, velocity), record
+  // offsets relative to the frame's record base; reverse program mirrors it.
+  static void build_programs(xpbd_ctx c) {
+    std::vector<Phase> fw, rv;
+    const int S = c->S, K = c->K;
+    for (int s = 0; s < S; ++s) {
+      fw.push_back({OP_PREDICT, 0, 0, c->V, -1});
+      for (int it = 0; it < K; ++it)
+        for (const SetInfo& si : c->sets) {
+          if (!si.count) continue;
+          long long off = (long long)(((size_t)s * K + it) * c->iter_tape_bytes + si.tape_off);
+          fw.push_back({OP_SET + si.type, (it == 0 ? PF_FIRST : 0) | PF_SECOND, si.begin, si.count, off});
+        }
+      fw.push_back({OP_VELOCITY, 0, 0, c->V, -1});
+    }
+    for (int s = S - 1; s >= 0; --s) {
+      rv.push_back({OP_REV_VELOCITY, 0, 0, c->V, -1});
+      for (int it = K - 1; it >= 0; --it)
+        for (int k = (int)c->sets.size() - 1; k >= 0; --k) {
+          const SetInfo& si = c->sets[k];
+          if (!si.count) continue;
+          long long off = (long long)(((size_t)s * K + it) * c->iter_tape_bytes + si.tape_off);
+          rv.push_back({OP_SET_REV + si.type, (it == K - 1 ? PF_FIRST : 0) | (it == 0 ? PF_SECOND : 0), si.begin,
+                        si.count, off});
+        }
+      if (K > 0)
+        for (const SetInfo& si : c->sets)
+          if (si.type == XPBD_CONTACT && si.count) rv.push_back({OP_SPHERE, 0, si.begin, si.count, -1});
+      rv.push_back({OP_REV_PREDICT, 0, 0, c->V, -1});
+    }
+    c->n_fw_prog = (int)fw.size();
+    c->n_rv_prog = (int)rv.size();
+    c->fw_prog = (Phase*)c->alloc(fw.size() * sizeof(Phase));
+    c->rv_prog = (Phase*)c->alloc(rv.size() * sizeof(Phase));
+    c->upload(c->fw_prog, fw);
+    c->upload(c->rv_prog, rv);
+  }
+
+  static int program_grid(xpbd_ctx c) {
+    if (c->prog_grid) return c->prog_grid;
+    int dev = 0, ncu = 0, per_cu = 0, coop = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) fail(XPBD_ERR_HIP, "device does not support cooperative launch");
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_program<T>, kBlock, 0));
+    int cap = ncu * std::max(per_cu, 1);
+    int want = c->prog_blocks_opt;
+    if (want <= 0) {
+      int mx = c->V;
+      for (const SetInfo& si : c->sets) mx = std::max(mx, si.count);
+      want = (int)nblocks(mx);
+    }
+    c->prog_grid = std::max(1, std::min(std::min(want, cap), 4096));
+    return c->prog_grid;
+  }
+
+  static void run_program(xpbd_ctx c, const Dev<T>& D, bool reverse_prog, char* tape_base, const T* f, T* fbar,
+                          double* dsph, bool record, hipStream_t st) {
+    if (!c->fw_prog) build_programs(c);
+    int G = program_grid(c);
+    RunArgs<T> R{};
+    R.tape = tape_base;
+    R.f = f;
+    R.fbar = fbar;
+    R.sph_out = dsph;
+    R.record = record ? 1 : 0;
+    R.bar = c->bar;
+    R.abort = c->abort_flag;
+    R.spin_limit = 1u << 22;
+    const Phase* prog = reverse_prog ? c->rv_prog : c->fw_prog;
+    int n = reverse_prog ? c->n_rv_prog : c->n_fw_prog;
+    if (n == 0) return;
+    HIPCHK(hipMemsetAsync(c->bar, 0, ((size_t)G * kFlagStride + 1) * sizeof(unsigned), st));
+    Dev<T> Dl = D;
+    void* args[] = {(void*)&Dl, (void*)&prog, (void*)&n, (void*)&R};
+    xpbd_ctx_s::Ev ev;
+    bool on;
+    prof_begin(c, st, reverse_prog ? 9 : 8, (int64_t)c->S * c->K * c->proj_per_iter, &ev, &on);
+    HIPCHK(hipLaunchCooperativeKernel((const void*)k_program<T>, dim3(G), dim3(kBlock), args, 0, st));
+    prof_end(c, st, ev, on);
+  }
+
+  // ------------------------------------------------------------ frame loops
   template <class U> static void fill(U* p, U v, size_t n, hipStream_t st) {
     if (!n || !p) return;
     k_fill<U><<<nblocks(n), kBlock, 0, st>>>(p, v, n);
@@ -396,16 +471,21 @@ template <class T> struct Ops {
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
     check_launch();
-    int flag = 0;
-    HIPCHK(hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    int flags[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&flags[0], c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&flags[1], c->abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (flag) fail(XPBD_ERR_NONFINITE, "a compliance or Young's modulus is negative, zero (E) or not finite");
+    if (flags[1]) {
+      HIPCHK(hipMemset(c->abort_flag, 0, sizeof(int)));
+      fail(XPBD_ERR_HIP, "an earlier persistent sweep gave up waiting at a grid barrier; its results are invalid");
+    }
+    if (flags[0]) fail(XPBD_ERR_NONFINITE, "a compliance or Young's modulus is negative, zero (E) or not finite");
     for (int a = 0; a < 4; ++a)
       if (!std::isfinite(p->sphere[a])) fail(XPBD_ERR_NONFINITE, "sphere parameter %d is not finite", a);
   }
 
   static void forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_params* p, int F, void* xf,
-                      void* x_final, void* v_final, hipStream_t st) {
+                      void* x_final, void* v_final, bool record, hipStream_t st) {
     const int V = c->V;
     const size_t vb = (size_t)V * sizeof(V4);
     if (c->ck_frames < F) {
@@ -417,13 +497,20 @@ template <class T> struct Ops {
       c->ck_frames = F;
     }
     gather_params(c, p, st);
+    Dev<T> D = dev(c, p->sphere);
     k_pack<T><<<nblocks(V), kBlock, 0, st>>>((const T*)x0, (const T*)v0, (const T*)c->w, (V4*)c->X, (V4*)c->Vv, V);
     check_launch();
+    const size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
     for (int f = 0; f < F; ++f) {
       HIPCHK(hipMemcpyAsync((char*)c->ckX + f * vb, c->X, vb, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync((char*)c->ckV + f * vb, c->Vv, vb, hipMemcpyDeviceToDevice, st));
       const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
-      for (int s = 0; s < c->S; ++s) substep(c, ff, p->sphere, -1, st);
+      if (c->persistent) {
+        run_program(c, D, false, record ? (char*)c->tape + (size_t)f * frame_tape : nullptr, ff, nullptr, nullptr,
+                    record, st);
+      } else {
+        for (int s = 0; s < c->S; ++s) substep(c, D, ff, record ? f * c->S + s : -1, st);
+      }
       if (xf) {
         k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (T*)xf + (size_t)f * 3 * V, V);
         check_launch();
@@ -451,8 +538,10 @@ template <class T> struct Ops {
     if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
     // parameters used by the recomputation (same as the forward's)
     gather_params(c, p, st);
+    Dev<T> D = dev(c, p->sphere);
     k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
     check_launch();
+    const size_t frame_tape = (size_t)S * c->K * c->iter_tape_bytes;
     for (int f = F - 1; f >= 0; --f) {
       if (dLdx && (!mask || mask[f])) {
         k_adj_inject<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);
@@ -460,16 +549,25 @@ template <class T> struct Ops {
       }
       const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
       T* fb = out->f_ext ? (T*)out->f_ext + (size_t)f * 3 * V : nullptr;
-      if (mode == 1) {
-        restore(c, f, st);
-        for (int s = 0; s < S; ++s) substep(c, ff, p->sphere, s, st);
-        for (int s = S - 1; s >= 0; --s) reverse_substep(c, fb, p->sphere, out->sphere, s, st);
+      if (mode == 3 || mode == 1) {
+        char* base = mode == 3 ? (char*)c->tape + (size_t)f * frame_tape : (char*)c->tape;
+        if (mode == 1) {
+          restore(c, f, st);
+          if (c->persistent) run_program(c, D, false, base, ff, nullptr, nullptr, true, st);
+          else for (int s = 0; s < S; ++s) substep(c, D, ff, s, st);
+        }
+        if (c->persistent) {
+          run_program(c, D, true, base, nullptr, fb, out->sphere, false, st);
+        } else {
+          int slot0 = mode == 3 ? f * S : 0;
+          for (int s = S - 1; s >= 0; --s) reverse_substep(c, D, fb, out->sphere, slot0 + s, st);
+        }
       } else {
         for (int s = S - 1; s >= 0; --s) {
           restore(c, f, st);
-          for (int q = 0; q < s; ++q) substep(c, ff, p->sphere, -1, st);
-          substep(c, ff, p->sphere, 0, st);
-          reverse_substep(c, fb, p->sphere, out->sphere, 0, st);
+          for (int q = 0; q < s; ++q) substep(c, D, ff, -1, st);
+          substep(c, D, ff, 0, st);
+          reverse_substep(c, D, fb, out->sphere, 0, st);
         }
       }
     }
@@ -494,7 +592,8 @@ template <class T> struct Ops {
     const size_t n = (size_t)3 * c->V;
     const size_t nb = nblocks(n);
     if (c->parts_n < nb * F) {
-      c->release(*(void**)&c->parts);
+      void* pp = c->parts;
+      c->release(pp);
       c->parts = (double*)c->alloc(nb * F * sizeof(double));
       c->parts_n = nb * F;
     }
@@ -520,7 +619,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   if (cd->n_dist < 0 || cd->n_bend < 0 || cd->n_tet < 0) fail(XPBD_ERR_INVALID, "negative counts");
   if ((cd->n_dist && !cd->dist_v) || (cd->n_bend && !cd->bend_v) || (cd->n_tet && (!cd->tet_v || !cd->tet_nu)))
     fail(XPBD_ERR_INVALID, "missing constraint arrays");
-  if (o->tape_mode < 0 || o->tape_mode > 2) fail(XPBD_ERR_INVALID, "bad tape_mode");
+  if (o->tape_mode < 0 || o->tape_mode > 3) fail(XPBD_ERR_INVALID, "bad tape_mode");
+  if (o->launch_mode < 0 || o->launch_mode > 2 || o->persistent_blocks < 0)
+    fail(XPBD_ERR_INVALID, "bad launch_mode / persistent_blocks");
   c->dtype = o->dtype;
   c->tsz = o->dtype == XPBD_F32 ? 4 : 8;
   c->V = m->n_verts;
@@ -664,6 +765,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   c->Vv = c->alloc(V * V4b);
   c->Xp = c->alloc(V * V4b);
   c->flag = (int*)c->alloc(sizeof(int));
+  c->bar = (unsigned*)c->alloc(((size_t)4096 * kFlagStride + 1) * sizeof(unsigned));
+  c->abort_flag = (int*)c->alloc(sizeof(int));
+  HIPCHK(hipMemset(c->abort_flag, 0, sizeof(int)));
   std::vector<double> wv(m->inv_mass, m->inv_mass + V);
   auto up_T = [&](void* dst, const std::vector<double>& v) {
     if (c->dtype == XPBD_F32) c->upload(dst, cast_vec<float>(v));
@@ -718,6 +822,27 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   }
 }
 
+// plain launches or the persistent program kernel
+void choose_launch(xpbd_ctx c, const xpbd_options* o) {
+  c->prog_blocks_opt = o->persistent_blocks;
+  if (o->launch_mode == 1) { c->persistent = false; return; }
+  int dev = 0, coop = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (o->launch_mode == 2) {
+    if (!coop) fail(XPBD_ERR_INVALID, "launch_mode 2 needs cooperative launch support");
+    c->persistent = true;
+    return;
+  }
+  // auto: one launch per set.  Measured on MI355X (cloth 256x256, sets of
+  // 12k-65k constraints): a launch costs about 4.3 us, while a grid-wide
+  // barrier across the 8 XCDs costs 7-16 us (each block's agent-scope fences
+  // write back and invalidate its XCD's L2), so the persistent kernel is
+  // only used when asked for.
+  c->persistent = false;
+  (void)coop;
+}
+
 // allocate the adjoint working set for a tape of `slots` substeps
 void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
   const size_t T_ = c->tsz, V4b = 4 * T_;
@@ -752,6 +877,21 @@ void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
     c->tape = c->alloc(need);
     c->tape_cap = need;
   }
+}
+
+// can `bytes` more of record be held (beyond what the record buffer holds now)?
+bool fits_on_device(xpbd_ctx c, size_t bytes) {
+  size_t have = c->tape_cap;
+  if (bytes <= have) return true;
+  size_t extra = bytes - have;
+  // adjoint working set not yet allocated counts too (rough upper bound)
+  size_t work = c->XB ? 0 : (size_t)c->V * 8 * c->tsz + (size_t)(c->n_dist + c->n_bend + 2 * c->n_tet) * 24 +
+                                (size_t)c->n_contact * 6 * c->tsz;
+  if (c->budget) return c->dev_bytes + extra + work <= c->budget;
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  const size_t margin = (size_t)4 << 30;
+  return extra + work + margin <= fr;
 }
 
 template <class F> xpbd_status guarded(xpbd_ctx c, F&& fn) {
@@ -789,7 +929,10 @@ xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* 
   } catch (...) {
     return XPBD_ERR_OOM;
   }
-  xpbd_status st = guarded(c, [&] { build(c, mesh, cons, schedule, opt); });
+  xpbd_status st = guarded(c, [&] {
+    build(c, mesh, cons, schedule, opt);
+    choose_launch(c, opt);
+  });
   if (st != XPBD_OK) {
     g_create_err = c->err;
     delete c;
@@ -806,16 +949,30 @@ xpbd_status xpbd_destroy(xpbd_ctx ctx) {
 }
 
 xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_params* p, int32_t n_frames,
-                         void* x_frames, void* x_final, void* v_final, void* stream) {
+                         void* x_frames, void* x_final, void* v_final, int32_t flags, void* stream) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
     if (!p || !x0 || !v0 || n_frames < 1) fail(XPBD_ERR_INVALID, "forward: null argument or n_frames < 1");
     if (c->n_tet && !p->tet_E) fail(XPBD_ERR_INVALID, "forward: tet_E required");
+    if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
     c->have_forward = false;
+    c->fwd_recorded = false;
+    bool record = false;
+    if ((flags & XPBD_FWD_FOR_ADJOINT) && (c->tape_mode_opt == 0 || c->tape_mode_opt == 3)) {
+      size_t need = (size_t)n_frames * c->S * c->K * c->iter_tape_bytes;
+      bool fits = fits_on_device(c, need);
+      if (c->tape_mode_opt == 3 && !fits)
+        fail(XPBD_ERR_OOM, "forward: the record of the whole rollout (%zu bytes) does not fit", need);
+      record = fits;
+      if (record) ensure_adjoint_buffers(c, n_frames * c->S);
+    } else if (c->tape_mode_opt == 3) {
+      fail(XPBD_ERR_INVALID, "forward: tape_mode 3 needs XPBD_FWD_FOR_ADJOINT");
+    }
     hipStream_t st = (hipStream_t)stream;
-    if (c->dtype == XPBD_F32) Ops<float>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, st);
-    else Ops<double>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, st);
+    if (c->dtype == XPBD_F32) Ops<float>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, record, st);
+    else Ops<double>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, record, st);
     c->have_forward = true;
+    c->fwd_recorded = record;
     c->fwd_frames = n_frames;
     c->fwd_params = *p;
   });
@@ -832,21 +989,16 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
         q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0)
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
     int mode = c->tape_mode_opt;
-    if (mode == 0) {
-      // whole-frame record if it fits the budget (or, with no budget, free memory)
+    if (c->fwd_recorded) {
+      mode = 3;
+    } else if (mode == 0 || mode == 3) {
+      // whole-frame record if it fits, else one substep at a time
       size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
-      size_t have = c->tape_cap;
-      size_t limit;
-      if (c->budget) limit = c->budget > c->dev_bytes ? c->budget - c->dev_bytes + have : 0;
-      else {
-        size_t fr = 0, tot = 0;
-        HIPCHK(hipMemGetInfo(&fr, &tot));
-        limit = fr + have > ((size_t)4 << 30) ? fr + have - ((size_t)4 << 30) : 0;
-      }
-      mode = frame_tape <= limit ? 1 : 2;
+      mode = fits_on_device(c, frame_tape) ? 1 : 2;
     }
-    ensure_adjoint_buffers(c, mode == 1 ? c->S : 1);
+    ensure_adjoint_buffers(c, mode == 3 ? c->fwd_frames * c->S : mode == 1 ? c->S : 1);
     c->tape_mode_used = mode;
+    if (mode == 3) c->fwd_recorded = false;   // the record is consumed by this adjoint
     hipStream_t st = (hipStream_t)stream;
     if (c->dtype == XPBD_F32) Ops<float>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
     else Ops<double>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
@@ -876,6 +1028,8 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->device_bytes = (int64_t)c->dev_bytes;
   info->tape_bytes_per_iteration = (int64_t)c->iter_tape_bytes;
   info->tape_mode = c->tape_mode_used;
+  info->persistent = c->persistent ? 1 : 0;
+  info->persistent_blocks = c->persistent ? c->prog_grid : 0;
   return XPBD_OK;
 }
 
@@ -886,7 +1040,7 @@ xpbd_status xpbd_profile_enable(xpbd_ctx c, int32_t on) {
   return XPBD_OK;
 }
 
-xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[8], double ms[8], int64_t items[8]) {
+xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[10], double ms[10], int64_t items[10]) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
     for (auto& e : c->ev_pending) {
@@ -899,7 +1053,7 @@ xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[8], double ms[8], int
       c->ev_free.push_back({e.a, e.b});
     }
     c->ev_pending.clear();
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 10; ++i) {
       if (launches) launches[i] = c->prof_launch[i];
       if (ms) ms[i] = c->prof_ms[i];
       if (items) items[i] = c->prof_items[i];

@@ -6,94 +6,27 @@
 // the vertex adjoints as {xbar, ybar, zbar, w}.  Constraint records are
 // structure-of-arrays in schedule order, so every record load is coalesced.
 //
-// Forward kernels can record, per projection, exactly the inputs its
-// adjoint needs (the vertex differences and the multiplier before the
-// update); reverse kernels recompute C, grad C, D and dlambda from that
-// record bit for bit and apply the chain rule to
+// Forward items can record, per projection, exactly the inputs its adjoint
+// needs (the vertex differences and the multiplier before the update);
+// reverse items recompute C, grad C, D and dlambda from that record bit for
+// bit and apply the chain rule to
 //     dlambda = (-C - at lambda) / D,  lambda += dlambda,
 //     x_k += w_k dlambda grad_k C
 // (Eq. xpbd and the position update of Sec. 3.1), with the partials of
 // Sec. 4.3: the adjoint of grad C (through the position update and through
 // D = sum_k w_k |grad_k C|^2 + at), the Hessian-vector product it feeds,
 // and the compliance adjoint -dlbar (lambda + dlambda) / D.
+//
+// Each per-item body is a device function used twice: by a plain kernel
+// (one launch per independent set) and by the persistent program kernel,
+// which walks a list of phases (sets, per-vertex steps) inside one
+// cooperative launch with a grid-wide barrier between phases.
 #pragma once
 #include "xpbd_device.hpp"
 
 namespace xpbd {
 
 constexpr int kBlock = 256;
-
-__device__ __forceinline__ int thread_item(int count) {
-  int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  return t < count ? t : -1;
-}
-
-// ===================================================================== forward
-
-template <class T, bool FIRST, bool TAPE>
-__global__ __launch_bounds__(kBlock) void k_dist(const int2* __restrict__ idx, const T* __restrict__ rest,
-                                                 const T* __restrict__ at, T* __restrict__ lam,
-                                                 Vec4<T>* __restrict__ X, int begin, int count,
-                                                 Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
-  int j = begin + t;
-  int2 e = idx[j];
-  Vec4<T> a = X[e.x], b = X[e.y];
-  V3<T> r = xyz(a) - xyz(b);
-  T lb = FIRST ? T(0) : lam[j];
-  if (TAPE) tape[t] = Vec4<T>{r.x, r.y, r.z, lb};
-  DistEval<T> ev = dist_eval(r, rest[j]);
-  T a_t = at[j];
-  T D = a.w + b.w + a_t;
-  if (!ev.ok || !(D > T(0))) {
-    if (FIRST) lam[j] = T(0);
-    return;
-  }
-  T dl = (-ev.C - a_t * lb) / D;
-  lam[j] = lb + dl;
-  T sa = a.w * dl, sb = b.w * dl;
-  a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
-  b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
-  X[e.x] = a;
-  X[e.y] = b;
-}
-
-template <class T, bool FIRST, bool TAPE>
-__global__ __launch_bounds__(kBlock) void k_bend(const int4* __restrict__ idx, const T* __restrict__ theta0,
-                                                 const T* __restrict__ at, T* __restrict__ lam,
-                                                 Vec4<T>* __restrict__ X, int begin, int count,
-                                                 Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
-  int j = begin + t;
-  int4 q = idx[j];
-  Vec4<T> p[4] = {X[q.x], X[q.y], X[q.z], X[q.w]};
-  V3<T> e = xyz(p[1]) - xyz(p[0]), a = xyz(p[2]) - xyz(p[0]), b = xyz(p[3]) - xyz(p[0]);
-  T lb = FIRST ? T(0) : lam[j];
-  if (TAPE) {
-    tape[t] = Vec4<T>{e.x, e.y, e.z, lb};
-    tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
-    reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
-  }
-  BendEval<T> ev = bend_eval(e, a, b, theta0[j]);
-  T a_t = at[j];
-  T D = a_t;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) D += p[k].w * dot(ev.g[k], ev.g[k]);
-  if (!ev.ok || !(D > T(0))) {
-    if (FIRST) lam[j] = T(0);
-    return;
-  }
-  T dl = (-ev.C - a_t * lb) / D;
-  lam[j] = lb + dl;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    T s = p[k].w * dl;
-    p[k].x += s * ev.g[k].x; p[k].y += s * ev.g[k].y; p[k].z += s * ev.g[k].z;
-  }
-  X[q.x] = p[0]; X[q.y] = p[1]; X[q.z] = p[2]; X[q.w] = p[3];
-}
 
 template <class T> struct TetRec {
   const int4* idx;
@@ -103,6 +36,81 @@ template <class T> struct TetRec {
   const T* gamma;    // [n_tet]
   int n;             // n_tet (stride of B)
 };
+
+template <class T> struct Sphere { T cx, cy, cz, R, tau, at; };
+
+// Every device array and scalar the sweeps use (passed by value).
+template <class T> struct Dev {
+  Vec4<T>* X;    // positions + inverse mass
+  Vec4<T>* Vv;   // velocities
+  Vec4<T>* Xp;   // positions at the start of the substep
+  Vec4<T>* XB;   // position adjoints + inverse mass
+  Vec4<T>* VB;   // velocity adjoints
+  int V;
+  const int2* d_idx; const T* d_rest; const T* d_at; T* d_lam; T* d_lamb; T* d_ab; double* d_acc;
+  const int4* b_idx; const T* b_th0; const T* b_at; T* b_lam; T* b_lamb; T* b_ab; double* b_acc;
+  TetRec<T> tr; T* t_lamD; T* t_lamH; T* t_lambD; T* t_lambH; T* t_eb; double* t_acc;
+  const int* c_vid; T* c_lam; T* c_lamb; Vec4<T>* c_sacc;
+  Sphere<T> sph;
+  T h, inv_h, gx, gy, gz;
+};
+
+// ===================================================================== forward items
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void dist_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int2 e = D.d_idx[j];
+  Vec4<T> a = D.X[e.x], b = D.X[e.y];
+  V3<T> r = xyz(a) - xyz(b);
+  T lb = FIRST ? T(0) : D.d_lam[j];
+  if (TAPE) tape[t] = Vec4<T>{r.x, r.y, r.z, lb};
+  DistEval<T> ev = dist_eval(r, D.d_rest[j]);
+  T a_t = D.d_at[j];
+  T Dn = a.w + b.w + a_t;
+  if (!ev.ok || !(Dn > T(0))) {
+    if (FIRST) D.d_lam[j] = T(0);
+    return;
+  }
+  T dl = (-ev.C - a_t * lb) / Dn;
+  D.d_lam[j] = lb + dl;
+  T sa = a.w * dl, sb = b.w * dl;
+  a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
+  b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
+  D.X[e.x] = a;
+  D.X[e.y] = b;
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void bend_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int4 q = D.b_idx[j];
+  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
+  V3<T> e = xyz(p[1]) - xyz(p[0]), a = xyz(p[2]) - xyz(p[0]), b = xyz(p[3]) - xyz(p[0]);
+  T lb = FIRST ? T(0) : D.b_lam[j];
+  if (TAPE) {
+    tape[t] = Vec4<T>{e.x, e.y, e.z, lb};
+    tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
+    reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
+  }
+  BendEval<T> ev = bend_eval(e, a, b, D.b_th0[j]);
+  T a_t = D.b_at[j];
+  T Dn = a_t;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Dn += p[k].w * dot(ev.g[k], ev.g[k]);
+  if (!ev.ok || !(Dn > T(0))) {
+    if (FIRST) D.b_lam[j] = T(0);
+    return;
+  }
+  T dl = (-ev.C - a_t * lb) / Dn;
+  D.b_lam[j] = lb + dl;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    T s = p[k].w * dl;
+    p[k].x += s * ev.g[k].x; p[k].y += s * ev.g[k].y; p[k].z += s * ev.g[k].z;
+  }
+  D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3];
+}
 
 template <class T> __device__ __forceinline__ M3<T> load_B(const T* B, int n, int j) {
   M3<T> m;
@@ -115,7 +123,7 @@ template <class T> __device__ __forceinline__ M3<T> load_B(const T* B, int n, in
 
 // One tet item = deviatoric projection then hydrostatic projection.  The
 // hydrostatic constraint is evaluated on the edge matrix updated in place by
-// the deviatoric correction (d_k += delta_{k} - delta_0).
+// the deviatoric correction (d_k += delta_k - delta_0).
 template <class T> struct TetStep {
   TetEval<T> evD, evH;
   bool appD, appH;
@@ -147,17 +155,14 @@ __device__ __forceinline__ void tet_step(const V3<T> d0[3], const T w[4], const 
 }
 
 template <class T, bool FIRST, bool TAPE>
-__global__ __launch_bounds__(kBlock) void k_tet(TetRec<T> R, T* __restrict__ lamD, T* __restrict__ lamH,
-                                                Vec4<T>* __restrict__ X, int begin, int count,
-                                                Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void tet_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
   int j = begin + t;
+  const TetRec<T>& R = D.tr;
   int4 q = R.idx[j];
-  Vec4<T> p[4] = {X[q.x], X[q.y], X[q.z], X[q.w]};
+  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
   V3<T> d[3] = {xyz(p[1]) - xyz(p[0]), xyz(p[2]) - xyz(p[0]), xyz(p[3]) - xyz(p[0])};
-  T lD = FIRST ? T(0) : lamD[j];
-  T lH = FIRST ? T(0) : lamH[j];
+  T lD = FIRST ? T(0) : D.t_lamD[j];
+  T lH = FIRST ? T(0) : D.t_lamH[j];
   if (TAPE) {
     tape[t] = Vec4<T>{d[0].x, d[0].y, d[0].z, d[1].x};
     tape[count + t] = Vec4<T>{d[1].y, d[1].z, d[2].x, d[2].y};
@@ -167,47 +172,42 @@ __global__ __launch_bounds__(kBlock) void k_tet(TetRec<T> R, T* __restrict__ lam
   T w[4] = {p[0].w, p[1].w, p[2].w, p[3].w};
   TetStep<T> s;
   tet_step(d, w, B, R.atD[j], R.atH[j], R.gamma[j], lD, lH, s);
-  lamD[j] = lD + s.dlD;
-  lamH[j] = lH + s.dlH;
+  D.t_lamD[j] = lD + s.dlD;
+  D.t_lamH[j] = lH + s.dlH;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     p[k].x = (p[k].x + s.dD[k].x) + s.dH[k].x;
     p[k].y = (p[k].y + s.dD[k].y) + s.dH[k].y;
     p[k].z = (p[k].z + s.dD[k].z) + s.dH[k].z;
   }
-  X[q.x] = p[0]; X[q.y] = p[1]; X[q.z] = p[2]; X[q.w] = p[3];
+  D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3];
 }
-
-template <class T> struct Sphere { T cx, cy, cz, R, tau, at; };
 
 template <class T, bool FIRST, bool TAPE>
-__global__ __launch_bounds__(kBlock) void k_contact(const int* __restrict__ vid, T* __restrict__ lam,
-                                                    Vec4<T>* __restrict__ X, int begin, int count, Sphere<T> S,
-                                                    Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void contact_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
   int j = begin + t;
-  int v = vid[j];
-  Vec4<T> p = X[v];
-  T lb = FIRST ? T(0) : lam[j];
+  int v = D.c_vid[j];
+  const Sphere<T>& S = D.sph;
+  Vec4<T> p = D.X[v];
+  T lb = FIRST ? T(0) : D.c_lam[j];
   if (TAPE) tape[t] = Vec4<T>{p.x, p.y, p.z, lb};
   ContactEval<T> ev = contact_eval(V3<T>{p.x - S.cx, p.y - S.cy, p.z - S.cz}, S.R, S.tau);
-  T D = p.w + S.at;
-  if (!ev.ok || !(ev.C < T(0)) || !(D > T(0))) {
-    if (FIRST) lam[j] = T(0);
+  T Dn = p.w + S.at;
+  if (!ev.ok || !(ev.C < T(0)) || !(Dn > T(0))) {
+    if (FIRST) D.c_lam[j] = T(0);
     return;
   }
-  T dl = (-ev.C - S.at * lb) / D;
-  lam[j] = lb + dl;
+  T dl = (-ev.C - S.at * lb) / Dn;
+  D.c_lam[j] = lb + dl;
   T s = p.w * dl;
   p.x += s * ev.n.x; p.y += s * ev.n.y; p.z += s * ev.n.z;
-  X[v] = p;
+  D.X[v] = p;
 }
 
-// ===================================================================== reverse
-// Adjoint of one projection given the adjoints of its outputs.  Inputs:
-// gradient g_k, weights w_k, D, dlambda, lambda_before, at; x̄_k (in/out).
-// Returns dlbar; writes gbar_k (adjoint of grad_k C).
+// ===================================================================== reverse items
+// Adjoint of one projection given the adjoints of its outputs: gradient g_k,
+// weights w_k, denominator D, dlambda, lambda_bar, position adjoints xb_k.
+// Returns dlambda_bar; writes gbar_k (adjoint of grad_k C).
 template <class T, int N>
 __device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T D, T dl, T lbar, const V3<T> xb[N],
                                           V3<T> gb[N]) {
@@ -222,25 +222,20 @@ __device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T D, T
 }
 
 template <class T, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_dist_rev(const int2* __restrict__ idx, const T* __restrict__ rest,
-                                                     const T* __restrict__ at, Vec4<T>* __restrict__ XB,
-                                                     T* __restrict__ lamb, T* __restrict__ abar,
-                                                     double* __restrict__ acc, int begin, int count,
-                                                     const Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void dist_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                              const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
-  int2 e = idx[j];
+  int2 e = D.d_idx[j];
   Vec4<T> tp = tape[t];
-  T lbar = FIRST ? T(0) : lamb[j];
-  T ab = FIRST ? T(0) : abar[j];
-  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, rest[j]);
-  Vec4<T> A = XB[e.x], Bv = XB[e.y];
-  T a_t = at[j];
-  T D = A.w + Bv.w + a_t;
-  if (ev.ok && D > T(0)) {
+  T lbar = FIRST ? T(0) : D.d_lamb[j];
+  T ab = FIRST ? T(0) : D.d_ab[j];
+  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, D.d_rest[j]);
+  Vec4<T> A = D.XB[e.x], Bv = D.XB[e.y];
+  T a_t = D.d_at[j];
+  T Dn = A.w + Bv.w + a_t;
+  if (ev.ok && Dn > T(0)) {
     T lb = tp.w;
-    T dl = (-ev.C - a_t * lb) / D;
+    T dl = (-ev.C - a_t * lb) / Dn;
     V3<T> xa = xyz(A), xb = xyz(Bv);
     T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
     // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
@@ -249,93 +244,85 @@ __global__ __launch_bounds__(kBlock) void k_dist_rev(const int2* __restrict__ id
     T un = dot(ev.n, u);
     T s = dl / ev.len;
     V3<T> hv = {s * (u.x - un * ev.n.x), s * (u.y - un * ev.n.y), s * (u.z - un * ev.n.z)};
-    T Cb = -dlb / D;
-    lbar = lbar - dlb * a_t / D;
-    ab = ab - dlb * (lb + dl) / D;
+    T Cb = -dlb / Dn;
+    lbar = lbar - dlb * a_t / Dn;
+    ab = ab - dlb * (lb + dl) / Dn;
     A.x += Cb * ev.n.x + hv.x; A.y += Cb * ev.n.y + hv.y; A.z += Cb * ev.n.z + hv.z;
     Bv.x -= Cb * ev.n.x + hv.x; Bv.y -= Cb * ev.n.y + hv.y; Bv.z -= Cb * ev.n.z + hv.z;
-    XB[e.x] = A;
-    XB[e.y] = Bv;
+    D.XB[e.x] = A;
+    D.XB[e.y] = Bv;
   }
   if (LAST) {
-    acc[j] += (double)ab;
+    D.d_acc[j] += (double)ab;
   } else {
-    lamb[j] = lbar;
-    abar[j] = ab;
+    D.d_lamb[j] = lbar;
+    D.d_ab[j] = ab;
   }
 }
 
 template <class T, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_bend_rev(const int4* __restrict__ idx, const T* __restrict__ theta0,
-                                                     const T* __restrict__ at, Vec4<T>* __restrict__ XB,
-                                                     T* __restrict__ lamb, T* __restrict__ abar,
-                                                     double* __restrict__ acc, int begin, int count,
-                                                     const Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void bend_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                              const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
-  int4 q = idx[j];
+  int4 q = D.b_idx[j];
   Vec4<T> tA = tape[t], tB = tape[count + t];
   Vec2<T> tC = reinterpret_cast<const Vec2<T>*>(tape + 2 * count)[t];
   V3<T> e = {tA.x, tA.y, tA.z}, a = {tB.x, tB.y, tB.z}, b = {tB.w, tC.x, tC.y};
   T lb = tA.w;
-  T lbar = FIRST ? T(0) : lamb[j];
-  T ab = FIRST ? T(0) : abar[j];
-  BendEval<T> ev = bend_eval(e, a, b, theta0[j]);
-  Vec4<T> P[4] = {XB[q.x], XB[q.y], XB[q.z], XB[q.w]};
+  T lbar = FIRST ? T(0) : D.b_lamb[j];
+  T ab = FIRST ? T(0) : D.b_ab[j];
+  BendEval<T> ev = bend_eval(e, a, b, D.b_th0[j]);
+  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
   T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
-  T a_t = at[j];
-  T D = a_t;
+  T a_t = D.b_at[j];
+  T Dn = a_t;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) D += w[k] * dot(ev.g[k], ev.g[k]);
-  if (ev.ok && D > T(0)) {
-    T dl = (-ev.C - a_t * lb) / D;
+  for (int k = 0; k < 4; ++k) Dn += w[k] * dot(ev.g[k], ev.g[k]);
+  if (ev.ok && Dn > T(0)) {
+    T dl = (-ev.C - a_t * lb) / Dn;
     V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
     V3<T> gb[4], hv[4];
-    T dlb = proj_adjoint<T, 4>(ev.g, w, D, dl, lbar, xb, gb);
+    T dlb = proj_adjoint<T, 4>(ev.g, w, Dn, dl, lbar, xb, gb);
     bend_hvp(e, a, b, gb, hv);
-    T Cb = -dlb / D;
-    lbar = lbar - dlb * a_t / D;
-    ab = ab - dlb * (lb + dl) / D;
+    T Cb = -dlb / Dn;
+    lbar = lbar - dlb * a_t / Dn;
+    ab = ab - dlb * (lb + dl) / Dn;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       P[k].x += Cb * ev.g[k].x + hv[k].x;
       P[k].y += Cb * ev.g[k].y + hv[k].y;
       P[k].z += Cb * ev.g[k].z + hv[k].z;
     }
-    XB[q.x] = P[0]; XB[q.y] = P[1]; XB[q.z] = P[2]; XB[q.w] = P[3];
+    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
   }
   if (LAST) {
-    acc[j] += (double)ab;
+    D.b_acc[j] += (double)ab;
   } else {
-    lamb[j] = lbar;
-    abar[j] = ab;
+    D.b_lamb[j] = lbar;
+    D.b_ab[j] = ab;
   }
 }
 
 // tet: ebar accumulates sum over projections of (atbar_D at_D + atbar_H at_H),
 // i.e. alphabar_D alpha_D + alphabar_H alpha_H, whence dL/dE = -ebar / E.
 template <class T, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_tet_rev(TetRec<T> R, Vec4<T>* __restrict__ XB, T* __restrict__ lambD,
-                                                    T* __restrict__ lambH, T* __restrict__ ebar,
-                                                    double* __restrict__ acc, int begin, int count,
-                                                    const Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                             const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
+  const TetRec<T>& R = D.tr;
   int4 q = R.idx[j];
   Vec4<T> t0 = tape[t], t1 = tape[count + t], t2 = tape[2 * count + t];
   V3<T> d[3] = {{t0.x, t0.y, t0.z}, {t0.w, t1.x, t1.y}, {t1.z, t1.w, t2.x}};
   T lD = t2.y, lH = t2.z;
-  Vec4<T> P[4] = {XB[q.x], XB[q.y], XB[q.z], XB[q.w]};
+  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
   T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
   M3<T> B = load_B(R.B, R.n, j);
   T atD = R.atD[j], atH = R.atH[j];
   TetStep<T> s;
   tet_step(d, w, B, atD, atH, R.gamma[j], lD, lH, s);
-  T lbD = FIRST ? T(0) : lambD[j];
-  T lbH = FIRST ? T(0) : lambH[j];
-  T eb = FIRST ? T(0) : ebar[j];
+  T lbD = FIRST ? T(0) : D.t_lambD[j];
+  T lbH = FIRST ? T(0) : D.t_lambH[j];
+  T eb = FIRST ? T(0) : D.t_eb[j];
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
   if (s.appH) {
@@ -359,56 +346,135 @@ __global__ __launch_bounds__(kBlock) void k_tet_rev(TetRec<T> R, Vec4<T>* __rest
   if (s.appD || s.appH) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) { P[k].x = xb[k].x; P[k].y = xb[k].y; P[k].z = xb[k].z; }
-    XB[q.x] = P[0]; XB[q.y] = P[1]; XB[q.z] = P[2]; XB[q.w] = P[3];
+    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
   }
   if (LAST) {
-    acc[j] += (double)eb;
+    D.t_acc[j] += (double)eb;
   } else {
-    lambD[j] = lbD;
-    lambH[j] = lbH;
-    ebar[j] = eb;
+    D.t_lambD[j] = lbD;
+    D.t_lambH[j] = lbH;
+    D.t_eb[j] = eb;
   }
 }
 
 // contact: also accumulates the sphere adjoint (cbar, Rbar) per contact
 template <class T, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_contact_rev(const int* __restrict__ vid, Vec4<T>* __restrict__ XB,
-                                                        T* __restrict__ lamb, Vec4<T>* __restrict__ sacc,
-                                                        int begin, int count, Sphere<T> S,
-                                                        const Vec4<T>* __restrict__ tape) {
-  int t = thread_item(count);
-  if (t < 0) return;
+__device__ __forceinline__ void contact_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                                 const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
-  int v = vid[j];
+  int v = D.c_vid[j];
+  const Sphere<T>& S = D.sph;
   Vec4<T> tp = tape[t];
-  T lbar = FIRST ? T(0) : lamb[j];
-  Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : sacc[j];
+  T lbar = FIRST ? T(0) : D.c_lamb[j];
+  Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : D.c_sacc[j];
   ContactEval<T> ev = contact_eval(V3<T>{tp.x - S.cx, tp.y - S.cy, tp.z - S.cz}, S.R, S.tau);
-  Vec4<T> P = XB[v];
-  T D = P.w + S.at;
-  if (ev.ok && ev.C < T(0) && D > T(0)) {
+  Vec4<T> P = D.XB[v];
+  T Dn = P.w + S.at;
+  if (ev.ok && ev.C < T(0) && Dn > T(0)) {
     T lb = tp.w;
-    T dl = (-ev.C - S.at * lb) / D;
+    T dl = (-ev.C - S.at * lb) / Dn;
     V3<T> xb = xyz(P);
     T dlb = lbar + P.w * dot(ev.n, xb);
-    T c = T(2) * dlb * dl / D;
+    T c = T(2) * dlb * dl / Dn;
     V3<T> gb = {P.w * (dl * xb.x - c * ev.n.x), P.w * (dl * xb.y - c * ev.n.y), P.w * (dl * xb.z - c * ev.n.z)};
     T gn = dot(ev.n, gb);
     T inv = T(1) / ev.d;
     V3<T> hv = {inv * (gb.x - gn * ev.n.x), inv * (gb.y - gn * ev.n.y), inv * (gb.z - gn * ev.n.z)};
-    T Cb = -dlb / D;
-    lbar = lbar - dlb * S.at / D;
+    T Cb = -dlb / Dn;
+    lbar = lbar - dlb * S.at / Dn;
     P.x += Cb * ev.n.x + hv.x; P.y += Cb * ev.n.y + hv.y; P.z += Cb * ev.n.z + hv.z;
-    XB[v] = P;
+    D.XB[v] = P;
     // C = |x - c| - R - tau: dC/dc = -n, dC/dR = -1, d(grad_x C)/dc = -P/|x-c|
     sa.x -= Cb * ev.n.x + hv.x; sa.y -= Cb * ev.n.y + hv.y; sa.z -= Cb * ev.n.z + hv.z;
     sa.w -= Cb;
   }
-  if (!LAST) lamb[j] = lbar;
-  sacc[j] = sa;
+  if (!LAST) D.c_lamb[j] = lbar;
+  D.c_sacc[j] = sa;
 }
 
-// ===================================================================== per-vertex kernels
+// ===================================================================== per-vertex items
+
+// substep start: x_prev = x; v += h (g + w f) for free vertices; x += h v
+template <class T> __device__ __forceinline__ void predict_item(const Dev<T>& D, int k, const T* __restrict__ f) {
+  Vec4<T> x = D.X[k], v = D.Vv[k];
+  D.Xp[k] = x;
+  if (x.w > T(0)) {
+    T fx = T(0), fy = T(0), fz = T(0);
+    if (f) { fx = f[3 * k]; fy = f[3 * k + 1]; fz = f[3 * k + 2]; }
+    v.x += D.h * (D.gx + x.w * fx);
+    v.y += D.h * (D.gy + x.w * fy);
+    v.z += D.h * (D.gz + x.w * fz);
+    D.Vv[k] = v;
+  }
+  x.x += D.h * v.x; x.y += D.h * v.y; x.z += D.h * v.z;
+  D.X[k] = x;
+}
+// substep end: v = (x - x_prev) / h
+template <class T> __device__ __forceinline__ void velocity_item(const Dev<T>& D, int k) {
+  Vec4<T> x = D.X[k], xp = D.Xp[k];
+  D.Vv[k] = Vec4<T>{(x.x - xp.x) * D.inv_h, (x.y - xp.y) * D.inv_h, (x.z - xp.z) * D.inv_h, T(0)};
+}
+// reverse of v = (x - x_prev)/h, first half: xbar += vbar / h
+template <class T> __device__ __forceinline__ void rev_velocity_item(const Dev<T>& D, int k) {
+  Vec4<T> p = D.XB[k], v = D.VB[k];
+  p.x += v.x * D.inv_h; p.y += v.y * D.inv_h; p.z += v.z * D.inv_h;
+  D.XB[k] = p;
+}
+// reverse of the prediction plus the x_prev half of the velocity update:
+//   vbar_mid = h xbar (free), fbar += h w vbar_mid, xbar = xbar - vbar_old / h,
+//   vbar = vbar_mid
+template <class T> __device__ __forceinline__ void rev_predict_item(const Dev<T>& D, int k, T* __restrict__ fbar) {
+  Vec4<T> p = D.XB[k], v = D.VB[k];
+  Vec4<T> vm = {T(0), T(0), T(0), T(0)};
+  if (p.w > T(0)) { vm.x = D.h * p.x; vm.y = D.h * p.y; vm.z = D.h * p.z; }
+  if (fbar) {
+    T s = D.h * p.w;
+    fbar[3 * k] += s * vm.x; fbar[3 * k + 1] += s * vm.y; fbar[3 * k + 2] += s * vm.z;
+  }
+  p.x -= v.x * D.inv_h; p.y -= v.y * D.inv_h; p.z -= v.z * D.inv_h;
+  D.XB[k] = p;
+  D.VB[k] = vm;
+}
+
+// ===================================================================== plain kernels (one launch per set)
+
+__device__ __forceinline__ int thread_item(int count) {
+  int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  return t < count ? t : -1;
+}
+
+#define XPBD_SET_KERNEL(NAME, ITEM, TAPE_T)                                                              \
+  template <class T, bool F1, bool F2>                                                                   \
+  __global__ __launch_bounds__(kBlock) void NAME(Dev<T> D, int begin, int count, TAPE_T* tape) {         \
+    int t = thread_item(count);                                                                          \
+    if (t >= 0) ITEM<T, F1, F2>(D, begin, count, t, tape);                                               \
+  }
+XPBD_SET_KERNEL(k_dist, dist_item, Vec4<T>)
+XPBD_SET_KERNEL(k_bend, bend_item, Vec4<T>)
+XPBD_SET_KERNEL(k_tet, tet_item, Vec4<T>)
+XPBD_SET_KERNEL(k_contact, contact_item, Vec4<T>)
+XPBD_SET_KERNEL(k_dist_rev, dist_rev_item, const Vec4<T>)
+XPBD_SET_KERNEL(k_bend_rev, bend_rev_item, const Vec4<T>)
+XPBD_SET_KERNEL(k_tet_rev, tet_rev_item, const Vec4<T>)
+XPBD_SET_KERNEL(k_contact_rev, contact_rev_item, const Vec4<T>)
+#undef XPBD_SET_KERNEL
+
+template <class T> __global__ __launch_bounds__(kBlock) void k_predict(Dev<T> D, const T* f) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < D.V) predict_item(D, k, f);
+}
+template <class T> __global__ __launch_bounds__(kBlock) void k_velocity(Dev<T> D) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < D.V) velocity_item(D, k);
+}
+template <class T> __global__ __launch_bounds__(kBlock) void k_rev_velocity(Dev<T> D) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < D.V) rev_velocity_item(D, k);
+}
+template <class T> __global__ __launch_bounds__(kBlock) void k_rev_predict(Dev<T> D, T* fbar) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < D.V) rev_predict_item(D, k, fbar);
+}
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_pack(const T* __restrict__ x0, const T* __restrict__ v0,
@@ -430,37 +496,6 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const Vec4<T>* __restrict__ X
   out[3 * k] = p.x; out[3 * k + 1] = p.y; out[3 * k + 2] = p.z;
 }
 
-// substep start: x_prev = x; v += h (g + w f) for free vertices; x += h v
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_predict(Vec4<T>* __restrict__ X, Vec4<T>* __restrict__ Vv,
-                                                    Vec4<T>* __restrict__ Xp, const T* __restrict__ f, T h,
-                                                    T gx, T gy, T gz, int n) {
-  int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  Vec4<T> x = X[k], v = Vv[k];
-  Xp[k] = x;
-  if (x.w > T(0)) {
-    T fx = T(0), fy = T(0), fz = T(0);
-    if (f) { fx = f[3 * k]; fy = f[3 * k + 1]; fz = f[3 * k + 2]; }
-    v.x += h * (gx + x.w * fx);
-    v.y += h * (gy + x.w * fy);
-    v.z += h * (gz + x.w * fz);
-    Vv[k] = v;
-  }
-  x.x += h * v.x; x.y += h * v.y; x.z += h * v.z;
-  X[k] = x;
-}
-
-// substep end: v = (x - x_prev) / h
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_velocity(const Vec4<T>* __restrict__ X, Vec4<T>* __restrict__ Vv,
-                                                     const Vec4<T>* __restrict__ Xp, T inv_h, int n) {
-  int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  Vec4<T> x = X[k], xp = Xp[k];
-  Vv[k] = Vec4<T>{(x.x - xp.x) * inv_h, (x.y - xp.y) * inv_h, (x.z - xp.z) * inv_h, T(0)};
-}
-
 // adjoint state init: xbar = 0 (keeping w), vbar = dL/dv_final or 0
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_adj_init(Vec4<T>* __restrict__ XB, Vec4<T>* __restrict__ VB,
@@ -480,37 +515,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_inject(Vec4<T>* __restrict__ XB,
   Vec4<T> p = XB[k];
   p.x += g[3 * k]; p.y += g[3 * k + 1]; p.z += g[3 * k + 2];
   XB[k] = p;
-}
-
-// reverse of v = (x - x_prev)/h, first half: xbar += vbar / h
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_rev_velocity(Vec4<T>* __restrict__ XB, const Vec4<T>* __restrict__ VB,
-                                                         T inv_h, int n) {
-  int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  Vec4<T> p = XB[k], v = VB[k];
-  p.x += v.x * inv_h; p.y += v.y * inv_h; p.z += v.z * inv_h;
-  XB[k] = p;
-}
-
-// reverse of the prediction plus the x_prev half of the velocity update:
-//   vbar_mid = h xbar (free), fbar += h w vbar_mid, xbar = xbar - vbar_old / h,
-//   vbar = vbar_mid
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_rev_predict(Vec4<T>* __restrict__ XB, Vec4<T>* __restrict__ VB,
-                                                        T* __restrict__ fbar, T h, T inv_h, int n) {
-  int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  Vec4<T> p = XB[k], v = VB[k];
-  Vec4<T> vm = {T(0), T(0), T(0), T(0)};
-  if (p.w > T(0)) { vm.x = h * p.x; vm.y = h * p.y; vm.z = h * p.z; }
-  if (fbar) {
-    T s = h * p.w;
-    fbar[3 * k] += s * vm.x; fbar[3 * k + 1] += s * vm.y; fbar[3 * k + 2] += s * vm.z;
-  }
-  p.x -= v.x * inv_h; p.y -= v.y * inv_h; p.z -= v.z * inv_h;
-  XB[k] = p;
-  VB[k] = vm;
 }
 
 template <class T>
@@ -570,25 +574,31 @@ __global__ __launch_bounds__(kBlock) void k_scatter_E_grad(const double* __restr
   out[u] = -acc[i] / (double)E[u];
 }
 
-// deterministic single-block reduction of the per-contact sphere adjoints
-// into the FP64 sphere gradient
-template <class T>
-__global__ __launch_bounds__(1024) void k_sphere_reduce(const Vec4<T>* __restrict__ sacc, int begin, int count,
-                                                        double* __restrict__ out) {
-  __shared__ double sh[4][1024];
+// Deterministic block reduction of the per-contact sphere adjoints into the
+// FP64 sphere gradient (fixed order: strided partial sums, then a tree).
+template <class T, int NT>
+__device__ __forceinline__ void sphere_reduce_block(const Vec4<T>* __restrict__ sacc, int begin, int count,
+                                                    double* __restrict__ out, double (*sh)[NT]) {
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int i = threadIdx.x; i < count; i += 1024) {
+  for (int i = threadIdx.x; i < count; i += NT) {
     Vec4<T> v = sacc[begin + i];
     s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
   }
   sh[0][threadIdx.x] = s0; sh[1][threadIdx.x] = s1; sh[2][threadIdx.x] = s2; sh[3][threadIdx.x] = s3;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
       for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x < 4 && out) out[threadIdx.x] += sh[threadIdx.x][0];
+  __syncthreads();
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sphere_reduce(const Vec4<T>* __restrict__ sacc, int begin, int count,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[4][kBlock];
+  sphere_reduce_block<T, kBlock>(sacc, begin, count, out, sh);
 }
 
 // FP64 goal: per-block partial sums of 1/2 |x - x*|^2 on masked frames, and
@@ -625,5 +635,137 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const double* __restrict__ p
   }
   if (threadIdx.x == 0) *out = accumulate ? *out + sh[0] : sh[0];
 }
+
+// ===================================================================== persistent program kernel
+
+enum PhaseOp : int {
+  OP_PREDICT = 0, OP_VELOCITY = 1, OP_REV_VELOCITY = 2, OP_REV_PREDICT = 3, OP_SPHERE = 4,
+  OP_SET = 8,        // + type (0 dist, 1 bend, 2 tet, 3 contact): forward projection of a set
+  OP_SET_REV = 16,   // + type: reverse of a set
+};
+enum PhaseFlag : int { PF_FIRST = 1, PF_SECOND = 2 };   // SECOND = record (forward) or LAST (reverse)
+
+struct Phase {
+  int op, flags, begin, count;
+  long long tape_off;   // byte offset of the set's record from the launch's record base, -1: none
+};
+
+// Per-launch arguments of one program run.
+template <class T> struct RunArgs {
+  char* tape;           // record base of this launch
+  const T* f;           // external force of the frame, or null
+  T* fbar;              // external-force adjoint of the frame, or null
+  double* sph_out;      // FP64 sphere gradient, or null
+  int record;           // forward: write the record where the phase has one
+  unsigned* bar;        // barrier flags: kFlagStride words per block + release word (zero at launch)
+  int* abort;           // set when a barrier wait runs out (bounded wait)
+  unsigned spin_limit;  // polls before a barrier wait gives up
+};
+
+// Grid-wide barrier for a cooperative launch without read-modify-write
+// contention: block b publishes the barrier's epoch in its own flag (one
+// 128-byte line per block); block 0 waits for every flag (its threads poll
+// disjoint flags in parallel), then publishes the epoch in the release word
+// that the other blocks poll.  The agent-scope fences make each block's
+// writes visible to the other XCDs before it arrives and drop stale cache
+// lines after release.  Waits are bounded: past spin_limit polls a block
+// records an abort and every block leaves at its next barrier.
+constexpr int kFlagStride = 32;   // unsigned words between block flags (128 B)
+
+__device__ __forceinline__ bool spin_until(const unsigned* p, unsigned epoch, int* abort, unsigned spin_limit) {
+  unsigned polls = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    if (++polls > spin_limit) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if ((polls & 63) == 0 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned* flags, unsigned epoch, int* abort, unsigned spin_limit) {
+  __shared__ int s_ok;
+  unsigned* release = flags + (size_t)gridDim.x * kFlagStride;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_ok = 1;
+    __threadfence();
+    __hip_atomic_store(flags + (size_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    bool ok = true;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+      if (!spin_until(flags + (size_t)b * kFlagStride, epoch, abort, spin_limit)) { ok = false; break; }
+    if (!ok) s_ok = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_ok) {
+      __threadfence();
+      __hip_atomic_store(release, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    if (!spin_until(release, epoch, abort, spin_limit)) s_ok = 0;
+  }
+  if (threadIdx.x == 0) __threadfence();
+  __syncthreads();
+  return s_ok != 0;
+}
+
+#define XPBD_GRID_LOOP(ITEM, TP)                                                                          \
+  {                                                                                                       \
+    const int stride = gridDim.x * kBlock;                                                                \
+    const int base = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;                              \
+    TP* tp = (TP*)(P.tape_off >= 0 ? R.tape + P.tape_off : nullptr);                                      \
+    bool f1 = P.flags & PF_FIRST, f2 = P.flags & PF_SECOND;                                               \
+    if (f1 && f2) { for (int t = base; t < P.count; t += stride) ITEM<T, true, true>(D, P.begin, P.count, t, tp); }   \
+    else if (f1) { for (int t = base; t < P.count; t += stride) ITEM<T, true, false>(D, P.begin, P.count, t, tp); }   \
+    else if (f2) { for (int t = base; t < P.count; t += stride) ITEM<T, false, true>(D, P.begin, P.count, t, tp); }   \
+    else { for (int t = base; t < P.count; t += stride) ITEM<T, false, false>(D, P.begin, P.count, t, tp); }         \
+  }
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_program(Dev<T> D, const Phase* __restrict__ prog, int n_phases,
+                                                    RunArgs<T> R) {
+  __shared__ double sh[4][kBlock];
+  unsigned epoch = 0;
+  for (int p = 0; p < n_phases; ++p) {
+    Phase P = prog[p];
+    if (!R.record && P.op < OP_SET_REV && P.op >= OP_SET) P.flags &= ~PF_SECOND;
+    if (P.op >= OP_SET && P.op < OP_SET_REV && !(P.flags & PF_SECOND)) P.tape_off = -1;
+    switch (P.op) {
+      case OP_PREDICT:
+        for (int k = blockIdx.x * kBlock + threadIdx.x; k < D.V; k += gridDim.x * kBlock) predict_item(D, k, R.f);
+        break;
+      case OP_VELOCITY:
+        for (int k = blockIdx.x * kBlock + threadIdx.x; k < D.V; k += gridDim.x * kBlock) velocity_item(D, k);
+        break;
+      case OP_REV_VELOCITY:
+        for (int k = blockIdx.x * kBlock + threadIdx.x; k < D.V; k += gridDim.x * kBlock) rev_velocity_item(D, k);
+        break;
+      case OP_REV_PREDICT:
+        for (int k = blockIdx.x * kBlock + threadIdx.x; k < D.V; k += gridDim.x * kBlock)
+          rev_predict_item(D, k, R.fbar);
+        break;
+      case OP_SPHERE:
+        if (blockIdx.x == 0 && R.sph_out) sphere_reduce_block<T, kBlock>(D.c_sacc, P.begin, P.count, R.sph_out, sh);
+        break;
+      case OP_SET + 0: XPBD_GRID_LOOP(dist_item, Vec4<T>) break;
+      case OP_SET + 1: XPBD_GRID_LOOP(bend_item, Vec4<T>) break;
+      case OP_SET + 2: XPBD_GRID_LOOP(tet_item, Vec4<T>) break;
+      case OP_SET + 3: XPBD_GRID_LOOP(contact_item, Vec4<T>) break;
+      case OP_SET_REV + 0: XPBD_GRID_LOOP(dist_rev_item, const Vec4<T>) break;
+      case OP_SET_REV + 1: XPBD_GRID_LOOP(bend_rev_item, const Vec4<T>) break;
+      case OP_SET_REV + 2: XPBD_GRID_LOOP(tet_rev_item, const Vec4<T>) break;
+      case OP_SET_REV + 3: XPBD_GRID_LOOP(contact_rev_item, const Vec4<T>) break;
+      default: break;
+    }
+    if (p + 1 == n_phases) break;   // kernel end orders the last phase
+    ++epoch;
+    if (!grid_barrier(R.bar, epoch, R.abort, R.spin_limit)) return;
+  }
+}
+#undef XPBD_GRID_LOOP
 
 }  // namespace xpbd

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libxpbd.so")
 
 XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE = range(6)
 F32, F64 = 0, 1
+FWD_FOR_ADJOINT = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
            "xpbd_status_string")
@@ -46,7 +47,8 @@ class ScheduleDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("iterations", C.c_int32),
                 ("gravity", C.c_double * 3), ("dtype", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
-                ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32)]
+                ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32), ("launch_mode", C.c_int32),
+                ("persistent_blocks", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -63,7 +65,7 @@ class Info(C.Structure):
     _fields_ = [("n_verts", C.c_int32), ("n_dist", C.c_int32), ("n_bend", C.c_int32), ("n_tet", C.c_int32),
                 ("n_contact", C.c_int32), ("n_sets", C.c_int32), ("projections_per_iteration", C.c_int64),
                 ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
-                ("tape_mode", C.c_int32)]
+                ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32)]
 
 
 class XPBDError(RuntimeError):
@@ -88,7 +90,7 @@ def load() -> C.CDLL:
         lib.xpbd_destroy.restype = C.c_int
         lib.xpbd_destroy.argtypes = [_vp]
         lib.xpbd_forward.restype = C.c_int
-        lib.xpbd_forward.argtypes = [_vp, _vp, _vp, C.POINTER(Params), C.c_int32, _vp, _vp, _vp, _vp]
+        lib.xpbd_forward.argtypes = [_vp, _vp, _vp, C.POINTER(Params), C.c_int32, _vp, _vp, _vp, C.c_int32, _vp]
         lib.xpbd_adjoint.restype = C.c_int
         lib.xpbd_adjoint.argtypes = [_vp, C.POINTER(Params), _vp, C.POINTER(C.c_uint8), _vp,
                                      C.POINTER(Grads), _vp]
@@ -121,7 +123,8 @@ class Simulator:
 
     def __init__(self, scene, dtype: torch.dtype = torch.float32, device="cuda:0",
                  hbm_budget_bytes: int = 0, tape_mode: int = 0, tet_gamma_one: bool = False,
-                 iterations: Optional[int] = None, substeps: Optional[int] = None):
+                 iterations: Optional[int] = None, substeps: Optional[int] = None, launch_mode: int = 0,
+                 persistent_blocks: int = 0):
         self.lib = load()
         self.scene = scene
         self.dtype = dtype
@@ -149,6 +152,8 @@ class Simulator:
         o.hbm_budget_bytes = hbm_budget_bytes
         o.tet_gamma_one = 1 if tet_gamma_one else 0
         o.tape_mode = tape_mode
+        o.launch_mode = launch_mode
+        o.persistent_blocks = persistent_blocks
         with torch.cuda.device(self.device):
             rc = self.lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(self._ctx))
         if rc != XPBD_OK:
@@ -199,8 +204,11 @@ class Simulator:
 
     # ------------------------------------------------------------------ API
     def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
-                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None):
-        """Roll out; returns (x_frames or None, x_final, v_final) on the device."""
+                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False):
+        """Roll out; returns (x_frames or None, x_final, v_final) on the device.
+
+        ``for_adjoint``: an adjoint will follow; the library may keep the record
+        of every projection now so the adjoint needs no recomputation."""
         sc = self.scene
         V = sc.n_verts
         x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
@@ -218,7 +226,7 @@ class Simulator:
         xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)
         ve = torch.empty((V, 3), dtype=self.dtype, device=self.device)
         rc = self.lib.xpbd_forward(self._ctx, _ptr(x0), _ptr(v0), C.byref(p), n_frames, _ptr(xf), _ptr(xe),
-                                   _ptr(ve), _stream_ptr(self.device))
+                                   _ptr(ve), FWD_FOR_ADJOINT if for_adjoint else 0, _stream_ptr(self.device))
         self._check(rc)
         self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames)
         return xf, xe, ve
@@ -284,9 +292,10 @@ class Simulator:
         self._check(self.lib.xpbd_profile_enable(self._ctx, stride))
 
     def profile_read(self):
-        """Per kernel family (2*type fwd, 2*type+1 reverse): launches, ms, items."""
-        la = (C.c_int64 * 8)()
-        ms = (C.c_double * 8)()
-        it = (C.c_int64 * 8)()
+        """Per kernel family (2*type fwd, 2*type+1 reverse, 8/9 persistent
+        forward/reverse frames): timed launches, ms, projections."""
+        la = (C.c_int64 * 10)()
+        ms = (C.c_double * 10)()
+        it = (C.c_int64 * 10)()
         self._check(self.lib.xpbd_profile_read(self._ctx, la, ms, it))
         return list(la), list(ms), list(it)

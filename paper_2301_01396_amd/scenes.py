@@ -325,14 +325,27 @@ def force_field(seed: int, nr: int, nc: int, n_frames: int, amplitude: float = 2
     u = (np.arange(nc) / max(nc - 1, 1))[None, :]
     v = (np.arange(nr) / max(nr - 1, 1))[:, None]
     out = np.zeros((n_frames, nr * nc, 3), dtype=np.float64)
+    # sin(S + T) = sin S cos T + cos S sin T with S the spatial phase and
+    # T = 2 pi r (f + 1) / frames_period the temporal one
+    sS = np.empty((3, 4, nr * nc))
+    cS = np.empty((3, 4, nr * nc))
+    for c in range(3):
+        for m in range(4):
+            S = (2 * np.pi * (p[c, m] * u + q[c, m] * v) + phi[c, m]).ravel()
+            np.sin(S, out=sS[c, m])
+            np.cos(S, out=cS[c, m])
+    acc = np.empty(nr * nc)
+    tmp = np.empty(nr * nc)
     for f in range(n_frames):
         for c in range(3):
-            acc = np.zeros((nr, nc))
+            acc.fill(0.0)
             for m in range(4):
-                acc += a[c, m] * np.sin(2 * np.pi * (p[c, m] * u + q[c, m] * v
-                                                     + r[c, m] * (f + 1) / frames_period)
-                                        + phi[c, m])
-            out[f, :, c] = amplitude * acc.ravel()
+                T = 2 * np.pi * r[c, m] * (f + 1) / frames_period
+                np.multiply(sS[c, m], amplitude * a[c, m] * np.cos(T), out=tmp)
+                acc += tmp
+                np.multiply(cS[c, m], amplitude * a[c, m] * np.sin(T), out=tmp)
+                acc += tmp
+            out[f, :, c] = acc
     return out
 
 

@@ -35,11 +35,11 @@ def reference_case(sc, F, mask=None, seed=0, noise=0.01, f_ext=None, emulate_f32
             "dL": dL, "grads": g}
 
 
-def gpu_case(sim, F, ref, f_ext=None):
+def gpu_case(sim, F, ref, f_ext=None, for_adjoint=True):
     """Same rollout, goal and adjoint through the C ABI."""
     import torch
     fe = None if f_ext is None else sim.tensor(f_ext)
-    xf, xe, ve = sim.forward(F, f_ext=fe)
+    xf, xe, ve = sim.forward(F, f_ext=fe, for_adjoint=for_adjoint)
     loss, dL = sim.goal_l2(xf, sim.tensor(ref["targets"]), ref["mask"])
     g = sim.adjoint(dL, ref["mask"])
     torch.cuda.synchronize()

@@ -102,14 +102,14 @@ def test_rejects_contact_on_pinned_vertex_and_bad_options():
     assert _create(sc, substeps=0)[0] == L.XPBD_ERR_INVALID
     assert _create(sc, dt=-1.0)[0] == L.XPBD_ERR_INVALID
     assert _create(sc, dtype=7)[0] == L.XPBD_ERR_INVALID
-    assert _create(sc, tape_mode=3)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, tape_mode=4)[0] == L.XPBD_ERR_INVALID
 
 
 def test_null_context_calls_fail_cleanly():
     lib = L.load()
     assert lib.xpbd_destroy(None) == L.XPBD_ERR_INVALID
     p = L.Params()
-    assert lib.xpbd_forward(None, None, None, C.byref(p), 1, None, None, None, None) == L.XPBD_ERR_INVALID
+    assert lib.xpbd_forward(None, None, None, C.byref(p), 1, None, None, None, 0, None) == L.XPBD_ERR_INVALID
 
 
 @pytest.mark.parametrize("maker", [lambda: scenes.small_cloth(n=6), lambda: scenes.small_tets(n=2),

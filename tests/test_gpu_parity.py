@@ -102,14 +102,39 @@ def test_bitwise_determinism_and_tape_modes():
     sc = scenes.small_cloth(n=12, frames=3, substeps=3, iterations=4)
     ref = reference_case(sc, 3, n_threads=8)
     outs = []
-    for mode in (1, 1, 2):
-        got = gpu_case(_sim(sc, "f32", tape_mode=mode), 3, ref)
+    infos = []
+    for mode in (1, 1, 2, 3, 0):
+        sim = _sim(sc, "f32", tape_mode=mode)
+        got = gpu_case(sim, 3, ref)
         outs.append(got)
+        infos.append(sim.info()["tape_mode"])
+    assert infos == [1, 1, 2, 3, 3]
     for o in outs[1:]:
         assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
         for k, v in outs[0]["grads"].items():
             assert np.array_equal(o["grads"][k], v), k
     del torch
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_plain_and_persistent_launches_agree_bitwise(dtype):
+    """One launch per set and the persistent frame kernel (several
+    workgroups, grid barriers between sets) compute the same numbers."""
+    sc = scenes.small_cloth(n=40, frames=2, substeps=2, iterations=3)
+    ref = reference_case(sc, 2, n_threads=8)
+    outs, modes = [], []
+    for lm, blocks in ((1, 0), (2, 0), (2, 3), (2, 16)):
+        sim = _sim(sc, dtype, launch_mode=lm, persistent_blocks=blocks)
+        outs.append(gpu_case(sim, 2, ref))
+        info = sim.info()
+        modes.append((info["persistent"], info["persistent_blocks"]))
+    assert modes[0] == (0, 0) and modes[1][0] == 1 and modes[2] == (1, 3) and modes[3] == (1, 16)
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            assert np.array_equal(o["grads"][k], v), k
+    tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
+    compare(sc, ref, outs[1], *tol)
 
 
 def test_goal_matches_reference():
