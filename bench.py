@@ -61,9 +61,10 @@ def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
 
 
 FAMILY = {0: "dist_fwd", 1: "dist_rev", 2: "bend_fwd", 3: "bend_rev", 4: "tet_fwd", 5: "tet_rev",
-          6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev"}
+          6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev", 10: "group_fwd", 11: "group_rev"}
 KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: "k_tet", 5: "k_tet_rev",
-                 6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)"}
+                 6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)",
+                 10: "k_group_fwd", 11: "k_group_rev"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -76,16 +77,17 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str):
+def make_workload(name: str, tile: int = -1):
     from paper_2301_01396_amd import scenes
+    kw = {} if tile < 0 else {"tile": tile}
     if name == "c1":
         return scenes.config_c1(), scenes.config_c1(target=True)
     if name == "c2":
-        return scenes.config_c2(), scenes.config_c2(target=True)
+        return scenes.config_c2(**kw), scenes.config_c2(target=True, **kw)
     if name == "c3":
-        return scenes.config_c3(), scenes.config_c3(target=True)
+        return scenes.config_c3(**kw), scenes.config_c3(target=True, **kw)
     if name == "c4":
-        return scenes.config_c4(), None
+        return scenes.config_c4(**kw), None
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -95,16 +97,24 @@ def workload_config(name, sc, F):
             "verts": sc.n_verts, "dist": sc.n_dist, "bend": sc.n_bend, "tets": sc.n_tet,
             "contacts": int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0,
             "frames": F, "substeps": sc.substeps, "iterations": sc.iterations, "dt": sc.dt,
-            "sets_per_iteration": len(sc.set_type)}
+            "sets_per_iteration": len(sc.set_type), "lds_groups": len(sc.groups)}
 
 
-def cpu_baseline(name, sc, budget_s: float = 20.0):
+def cpu_baseline(name, sc, max_projections: int = 60_000_000):
     """The FP64 reference on the host cores, on a bounded prefix of the
-    workload (one frame, or fewer substeps), forward + adjoint."""
+    workload: one frame, with fewer substeps / iterations when one frame
+    holds more than ``max_projections`` forward projections; forward and
+    adjoint are both timed."""
+    import copy
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
-    osc = O.OracleScene(sc, n_threads=threads)
+    sample = copy.copy(sc)
+    per_it = sc.projections_per_iteration()
+    if per_it * sc.iterations * sc.substeps > max_projections:
+        sample.substeps = 1
+        sample.iterations = max(1, min(sc.iterations, max_projections // max(per_it, 1)))
+    osc = O.OracleScene(sample, n_threads=threads)
     kw = {}
     if sc.f_ext is not None:
         kw["f_ext"] = sc.f_ext[:1]
@@ -114,10 +124,11 @@ def cpu_baseline(name, sc, budget_s: float = 20.0):
     dL = xf - xf.mean(axis=1, keepdims=True)
     O.adjoint(osc, 1, dL, **kw)
     t2 = time.perf_counter()
-    proj = sc.projections_per_rollout(1)
+    proj = sample.projections_per_rollout(1)
     value = 2 * proj / (t2 - t0)
     return {"value": value, "unit": "projections/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 frame of the workload ({proj} forward + {proj} reverse projections, FP64): "
+            "sample": f"1 frame of the workload with {sample.substeps} substep(s) x {sample.iterations} "
+                      f"iterations ({proj} forward + {proj} reverse projections, FP64): "
                       f"forward {t1 - t0:.2f} s, adjoint incl. recompute {t2 - t1:.2f} s"}
 
 
@@ -128,11 +139,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--frames", type=int, default=0, help="override frame count (0 = the workload's)")
-    ap.add_argument("--profile-stride", type=int, default=4,
+    ap.add_argument("--profile-stride", type=int, default=7,
                     help="bracket every n-th projection launch with HIP events (0 = off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto", choices=["auto", "plain", "persistent"])
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0 = auto)")
+    ap.add_argument("--tile", type=int, default=-1, help="schedule tile width (-1 = the workload's, 0 = untiled)")
+    ap.add_argument("--no-groups", action="store_true", help="run every set as its own launch")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
@@ -145,11 +158,12 @@ def main():
     from paper_2301_01396_amd.lib import Simulator
 
     dev = torch.device("cuda:0")
-    sc, tg = make_workload(args.workload)
+    sc, tg = make_workload(args.workload, args.tile)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
-    sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks)
+    sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
+                    use_groups=not args.no_groups)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
 
@@ -194,8 +208,12 @@ def main():
         log("warmup step done")
     torch.cuda.synchronize()
     sim.profile_read()
-    # the persistent path launches two kernels per frame: time every one
-    sim.profile_enable(1 if sim.info()["persistent"] and args.profile_stride else args.profile_stride)
+    # the persistent path launches two kernels per frame: time every one;
+    # otherwise a stride coprime with the launches of one iteration
+    stride = args.profile_stride
+    if stride and sim.info()["persistent"]:
+        stride = 1
+    sim.profile_enable(stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -213,8 +231,8 @@ def main():
     recording = info["tape_mode"] == 3
 
     plain = None
-    if args.plain_steps > 0 and info["persistent"]:
-        psim = Simulator(sc, dtype=dtype, device=dev, launch_mode=1)
+    if args.plain_steps > 0 and (info["persistent"] or info["n_groups_lds"]):
+        psim = Simulator(sc, dtype=dtype, device=dev, launch_mode=1, use_groups=False)
         step(psim)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
@@ -232,13 +250,13 @@ def main():
     kernels = {}
     tsz = 8 if dtype == torch.float64 else 4
     def fam_bytes(fam):
-        if fam == 8:
+        if fam in (8, 10):
             return mix_bytes(sc, False, tsz, recording)
-        if fam == 9:
+        if fam in (9, 11):
             return mix_bytes(sc, True, tsz, recording)
         return alg_bytes(fam, tsz, recording)
 
-    for fam in range(10):
+    for fam in range(12):
         if launches[fam]:
             avg_ms = ms[fam] / launches[fam]
             per_launch_items = items[fam] / launches[fam]
@@ -248,11 +266,11 @@ def main():
                                     "alg_GBps": round(gbs, 1),
                                     "share_of_sampled_ms": None}
     tot = sum(ms)
-    for fam in range(10):
+    for fam in range(12):
         if launches[fam]:
             kernels[FAMILY[fam]]["share_of_sampled_ms"] = round(ms[fam] / tot, 3)
     if tot > 0:
-        dom = max(range(10), key=lambda f: ms[f])
+        dom = max(range(12), key=lambda f: ms[f])
         k = kernels[FAMILY[dom]]
         traffic = None
         tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -278,7 +296,9 @@ def main():
         "config": workload_config(args.workload, sc, F),
         "projections_per_step": proj_step, "loss": float(loss.detach().cpu()), "grads_finite": grads_finite,
         "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "plain_launch": plain,
-        "launch": "persistent frame kernel" if info["persistent"] else "one kernel launch per set",
+        "launch": ("persistent frame kernel" if info["persistent"] else
+                   f"LDS group launches ({info['n_groups_lds']} groups), one launch per other set"
+                   if info["n_groups_lds"] else "one kernel launch per set"),
         "persistent_blocks": info["persistent_blocks"], "tape_mode": info["tape_mode"],
         "profile_stride": args.profile_stride, "csrc_sha": csrc_hash(),
     }

@@ -99,11 +99,22 @@ typedef struct {
  * bending and tet constraint must appear exactly once in the schedule, and a
  * contact vertex at most once and only if its inverse mass is > 0.
  * Otherwise xpbd_create returns XPBD_ERR_INVALID. */
+/* Optional LDS groups (a performance hint that never changes results):
+ * group g covers the consecutive sets [group_sets[2g], group_sets[2g+1])
+ * and gives a patch id (>= 0) for every vertex in group_patch[g * V + v].
+ * Every constraint of the group's sets must have all its vertices in one
+ * patch (else XPBD_ERR_INVALID); the library may then run the whole group
+ * as one launch, one workgroup per patch with the patch's vertices and
+ * records in LDS, which computes exactly what the sets compute one by one.
+ * Groups must not overlap and hold at most 64 sets. */
 typedef struct {
   int32_t n_sets;
   const int32_t* set_type;     /* host [n_sets] xpbd_ctype */
   const int64_t* set_offsets;  /* host [n_sets + 1] */
   const int32_t* set_items;    /* host [set_offsets[n_sets]] */
+  int32_t n_groups;            /* 0 = none */
+  const int32_t* group_sets;   /* host [n_groups][2] */
+  const int32_t* group_patch;  /* host [n_groups][V] */
 } xpbd_schedule_desc;
 
 typedef struct {
@@ -205,6 +216,9 @@ typedef struct {
   int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep, 3 forward record) */
   int32_t persistent;                  /* 1 if frames run as persistent launches */
   int32_t persistent_blocks;           /* their workgroup count (0 before the first) */
+  int32_t n_groups;                    /* LDS groups given */
+  int32_t n_groups_lds;                /* of which run as one LDS launch each */
+  int32_t max_group_lds_bytes;         /* largest LDS footprint of those launches */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 
@@ -213,11 +227,12 @@ xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
  * persistent kernels is bracketed by HIP events on the call's stream (0 =
  * off).  xpbd_profile_read synchronises them and returns, per kernel family
  * (index 2 * type: forward projections of that type, 2 * type + 1: their
- * reverse; 8: persistent forward frame, 9: persistent reverse frame), the
- * number of timed launches, their total milliseconds and the projections
- * they processed, then resets the counts. */
+ * reverse; 8: persistent forward frame, 9: persistent reverse frame,
+ * 10: LDS group forward, 11: LDS group reverse), the number of timed
+ * launches, their total milliseconds and the projections they processed,
+ * then resets the counts. */
 xpbd_status xpbd_profile_enable(xpbd_ctx ctx, int32_t on);
-xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[10], double ms[10], int64_t items[10]);
+xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[12], double ms[12], int64_t items[12]);
 
 const char* xpbd_last_error(xpbd_ctx ctx);
 const char* xpbd_status_string(xpbd_status s);

@@ -12,9 +12,11 @@ SOURCES = [os.path.join(CSRC, "xpbd.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("xpbd_device.hpp", "xpbd_kernels.hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "xpbd.h")]
 
-# -O3 without fast-math: IEEE division and square root.  Packed-FP32 ops are
+# -O3 without fast-math: IEEE division and square root; multiply-adds are
+# fused per source expression only (-ffp-contract=on), so every kernel that
+# shares a projection routine rounds it the same way.  Packed-FP32 ops are
 # disabled (-packed-fp32-ops) for the device code.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 

@@ -95,6 +95,7 @@ struct xpbd_ctx_s {
   int4* tet_idx = nullptr; void* tet_B = nullptr; int* tet_perm = nullptr; double* tet_nu = nullptr;
   double* tet_vol = nullptr;
   int* contact_vid = nullptr;
+  int* contact_order = nullptr;   // per contact set: set-local items by ascending vertex
   void* w = nullptr;              // [V] inverse mass (T)
   // per forward
   void* dist_at = nullptr; void* bend_at = nullptr;
@@ -113,6 +114,26 @@ struct xpbd_ctx_s {
   void* tet_lambD = nullptr; void* tet_lambH = nullptr; void* tet_eb = nullptr; double* tet_acc = nullptr;
   void* contact_lamb = nullptr; void* contact_sacc = nullptr;
   void* tape = nullptr; size_t tape_cap = 0;
+
+  // LDS groups
+  struct Group {
+    int a, b;                 // sets [a, b)
+    bool lds = false;         // run as one launch per iteration
+    int P = 0;
+    size_t smem_fwd = 0, smem_rev = 0;
+    int64_t items = 0;        // projections per iteration inside the group
+    int* pv_start = nullptr; int* pv = nullptr; int* cnt = nullptr; int* set_type = nullptr;
+    long long* fimg = nullptr; long long* rimg = nullptr; long long* tpos = nullptr; int* rec_first = nullptr;
+    long long tape_off = 0;   // inside one iteration's record
+    size_t tape_bytes = 0;
+  };
+  std::vector<Group> groups;
+  std::vector<int> group_at_start, group_at_end;   // per set: group starting / ending there, -1 none
+  char* fimg = nullptr; char* rimg = nullptr;            // group record images
+  long long* fpos[3] = {nullptr, nullptr, nullptr};     // per dist / bend / tet: record offset in fimg, -1 none
+  long long* rpos[3] = {nullptr, nullptr, nullptr};
+  size_t lds_limit = 65536;
+  int max_group_lds = 0;
 
   // persistent program launches
   bool persistent = false;
@@ -135,9 +156,9 @@ struct xpbd_ctx_s {
   struct Ev { hipEvent_t a, b; int fam; int64_t items; };
   std::vector<Ev> ev_pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-  int64_t prof_launch[10] = {0};
-  double prof_ms[10] = {0};
-  int64_t prof_items[10] = {0};
+  int64_t prof_launch[12] = {0};
+  double prof_ms[12] = {0};
+  int64_t prof_items[12] = {0};
 
   ~xpbd_ctx_s() {
     for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
@@ -268,6 +289,7 @@ template <class T> struct Ops {
     D.t_lambH = (T*)c->tet_lambH; D.t_eb = (T*)c->tet_eb; D.t_acc = c->tet_acc;
     D.c_vid = c->contact_vid; D.c_lam = (T*)c->contact_lam; D.c_lamb = (T*)c->contact_lamb;
     D.c_sacc = (V4*)c->contact_sacc;
+    D.c_order = c->contact_order;
     D.sph = Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
     D.h = (T)c->h; D.inv_h = (T)(1.0 / c->h);
     D.gx = (T)c->g[0]; D.gy = (T)c->g[1]; D.gz = (T)c->g[2];
@@ -338,12 +360,93 @@ template <class T> struct Ops {
     return (V4*)base;
   }
 
+  static GroupDev group_dev(const xpbd_ctx_s::Group& g) {
+    GroupDev G;
+    G.pv_start = g.pv_start; G.pv = g.pv; G.cnt = g.cnt; G.set_type = g.set_type;
+    G.fimg = g.fimg; G.rimg = g.rimg; G.tpos = g.tpos; G.rec_first = g.rec_first;
+    G.nset = g.b - g.a;
+    G.P = g.P;
+    G.tape_off = g.tape_off;
+    return G;
+  }
+
+  static void group_fwd(xpbd_ctx c, const Dev<T>& D, const xpbd_ctx_s::Group& g, bool first, char* tape_iter,
+                        hipStream_t st) {
+    GroupDev G = group_dev(g);
+    xpbd_ctx_s::Ev ev;
+    bool on;
+    prof_begin(c, st, 10, g.items, &ev, &on);
+    dim3 grid(g.P);
+    if (first) {
+      if (tape_iter) k_group_fwd<T, true, true><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+      else k_group_fwd<T, true, false><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+    } else {
+      if (tape_iter) k_group_fwd<T, false, true><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+      else k_group_fwd<T, false, false><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+    }
+    check_launch();
+    prof_end(c, st, ev, on);
+  }
+
+  static void group_rev(xpbd_ctx c, const Dev<T>& D, const xpbd_ctx_s::Group& g, bool first, bool last,
+                        const char* tape_iter, hipStream_t st) {
+    GroupDev G = group_dev(g);
+    xpbd_ctx_s::Ev ev;
+    bool on;
+    prof_begin(c, st, 11, g.items, &ev, &on);
+    dim3 grid(g.P);
+    if (first) {
+      if (last) k_group_rev<T, true, true><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+      else k_group_rev<T, true, false><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+    } else {
+      if (last) k_group_rev<T, false, true><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+      else k_group_rev<T, false, false><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+    }
+    check_launch();
+    prof_end(c, st, ev, on);
+  }
+
+  static void group_fill(xpbd_ctx c, hipStream_t st) {
+    if (!c->fimg) return;
+    if (c->n_dist && c->fpos[0])
+      k_group_fill<T><<<nblocks(c->n_dist), kBlock, 0, st>>>(0, c->n_dist, c->fpos[0], c->rpos[0], c->fimg, c->rimg,
+                                                             (const T*)c->dist_at, nullptr, nullptr);
+    if (c->n_bend && c->fpos[1])
+      k_group_fill<T><<<nblocks(c->n_bend), kBlock, 0, st>>>(1, c->n_bend, c->fpos[1], c->rpos[1], c->fimg, c->rimg,
+                                                             (const T*)c->bend_at, nullptr, nullptr);
+    if (c->n_tet && c->fpos[2])
+      k_group_fill<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(2, c->n_tet, c->fpos[2], c->rpos[2], c->fimg, c->rimg,
+                                                            (const T*)c->tet_atD, (const T*)c->tet_atH,
+                                                            (const T*)c->tet_gamma);
+    check_launch();
+  }
+
+  static void allow_lds(size_t bytes) {
+    if (bytes <= 65536) return;
+    const void* ks[] = {(const void*)k_group_fwd<T, true, true>, (const void*)k_group_fwd<T, true, false>,
+                        (const void*)k_group_fwd<T, false, true>, (const void*)k_group_fwd<T, false, false>,
+                        (const void*)k_group_rev<T, true, true>, (const void*)k_group_rev<T, true, false>,
+                        (const void*)k_group_rev<T, false, true>, (const void*)k_group_rev<T, false, false>};
+    for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  }
+
   // one substep of Eq. xpbdUpdateRule; record slot < 0 means no record
   static void substep(xpbd_ctx c, const Dev<T>& D, const T* f, int slot, hipStream_t st) {
     k_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, f);
     check_launch();
+    const int ns = (int)c->sets.size();
     for (int it = 0; it < c->K; ++it)
-      for (const SetInfo& si : c->sets) project(c, D, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
+      for (int k = 0; k < ns; ++k) {
+        int g = c->group_at_start.empty() ? -1 : c->group_at_start[k];
+        if (g >= 0 && c->groups[g].lds) {
+          char* ti = slot >= 0 ? (char*)c->tape + ((size_t)slot * c->K + it) * c->iter_tape_bytes : nullptr;
+          group_fwd(c, D, c->groups[g], it == 0, ti, st);
+          k = c->groups[g].b - 1;
+          continue;
+        }
+        const SetInfo& si = c->sets[k];
+        project(c, D, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
+      }
     k_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
   }
@@ -353,13 +456,21 @@ template <class T> struct Ops {
     check_launch();
     for (int it = c->K - 1; it >= 0; --it)
       for (int k = (int)c->sets.size() - 1; k >= 0; --k) {
+        int g = c->group_at_end.empty() ? -1 : c->group_at_end[k];
+        if (g >= 0 && c->groups[g].lds) {
+          const char* ti = (const char*)c->tape + ((size_t)slot * c->K + it) * c->iter_tape_bytes;
+          group_rev(c, D, c->groups[g], it == c->K - 1, it == 0, ti, st);
+          k = c->groups[g].a;
+          continue;
+        }
         const SetInfo& si = c->sets[k];
         reverse(c, D, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), st);
       }
     if (c->K > 0 && dsph)
       for (const SetInfo& si : c->sets)
         if (si.type == XPBD_CONTACT && si.count > 0) {
-          k_sphere_reduce<T><<<1, kBlock, 0, st>>>((const V4*)c->contact_sacc, si.begin, si.count, dsph);
+          k_sphere_reduce<T><<<1, kBlock, 0, st>>>((const V4*)c->contact_sacc, c->contact_order, si.begin, si.count,
+                                                   dsph);
           check_launch();
         }
     k_rev_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, fbar);
@@ -471,6 +582,7 @@ template <class T> struct Ops {
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
     check_launch();
+    group_fill(c, st);
     int flags[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(&flags[0], c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&flags[1], c->abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -610,6 +722,11 @@ template <class T> struct Ops {
 
 // ===================================================================== create
 
+template <class T>
+void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
+                  const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
+                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c);
+
 void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, const xpbd_schedule_desc* sd,
            const xpbd_options* o) {
   if (!m || !cd || !sd || !o) fail(XPBD_ERR_INVALID, "null descriptor");
@@ -664,14 +781,31 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   perm_b.reserve(c->n_bend);
   perm_t.reserve(c->n_tet);
   if (sd->n_sets > 0 && sd->set_offsets[0] != 0) fail(XPBD_ERR_INVALID, "set_offsets[0] must be 0");
+  // LDS groups: which group each set belongs to
+  std::vector<int> set_group(std::max(sd->n_sets, 0), -1);
+  if (sd->n_groups < 0 || (sd->n_groups > 0 && (!sd->group_sets || !sd->group_patch)))
+    fail(XPBD_ERR_INVALID, "bad group arrays");
+  for (int g = 0; g < sd->n_groups; ++g) {
+    int a = sd->group_sets[2 * g], b = sd->group_sets[2 * g + 1];
+    if (a < 0 || b > sd->n_sets || b <= a || b - a > kMaxGroupSets)
+      fail(XPBD_ERR_INVALID, "group %d: bad set range [%d, %d)", g, a, b);
+    for (int q = a; q < b; ++q) {
+      if (set_group[q] >= 0) fail(XPBD_ERR_INVALID, "groups %d and %d overlap", set_group[q], g);
+      set_group[q] = g;
+    }
+    for (int v = 0; v < V; ++v)
+      if (sd->group_patch[(size_t)g * V + v] < 0) fail(XPBD_ERR_INVALID, "group %d: negative patch id", g);
+  }
   for (int s = 0; s < sd->n_sets; ++s) {
     int ty = sd->set_type[s];
     int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
     if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
     if (ty < 0 || ty > 3) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
     if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
-    // order items inside the set by their smallest vertex (locality)
-    std::vector<std::pair<int, int>> items;
+    // order items inside the set by patch (grouped sets), then by their
+    // smallest vertex (locality)
+    const int32_t* gpatch = set_group[s] >= 0 ? sd->group_patch + (size_t)set_group[s] * V : nullptr;
+    std::vector<std::pair<int64_t, int>> items;
     items.reserve(e - b);
     for (int64_t q = b; q < e; ++q) {
       int it = sd->set_items[q];
@@ -685,18 +819,24 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
       else if (ty == XPBD_BEND) vv = cd->bend_v + 4 * (int64_t)it;
       else if (ty == XPBD_TET) vv = cd->tet_v + 4 * (int64_t)it;
       int key = INT32_MAX;
+      int64_t patch = 0;
       for (int k = 0; k < nv; ++k) {
         int v = vv ? vv[k] : it;
         if (stamp[v] == s) fail(XPBD_ERR_INVALID, "set %d is not independent: vertex %d appears twice", s, v);
         stamp[v] = s;
         key = std::min(key, v);
+        if (gpatch) {
+          if (k == 0) patch = gpatch[v];
+          else if (gpatch[v] != patch)
+            fail(XPBD_ERR_INVALID, "set %d (group %d): a constraint spans two patches", s, set_group[s]);
+        }
       }
       int* seen = ty == XPBD_DIST ? &seen_d[it] : ty == XPBD_BEND ? &seen_b[it] : ty == XPBD_TET ? &seen_t[it] : &seen_c[it];
       if (*seen) fail(XPBD_ERR_INVALID, "constraint %d of type %d appears twice in the schedule", it, ty);
       *seen = 1;
       if (ty == XPBD_CONTACT && !(m->inv_mass[it] > 0))
         fail(XPBD_ERR_INVALID, "contact on pinned vertex %d", it);
-      items.push_back({key, it});
+      items.push_back({(patch << 32) | (int64_t)key, it});
     }
     std::stable_sort(items.begin(), items.end());
     SetInfo si{};
@@ -819,6 +959,252 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     c->contact_vid = (int*)c->alloc(n * sizeof(int));
     c->contact_lam = c->alloc(n * T_);
     c->upload(c->contact_vid, vid_c);
+    std::vector<int> order(n);
+    for (const SetInfo& si : c->sets) {
+      if (si.type != XPBD_CONTACT) continue;
+      std::vector<int> loc(si.count);
+      for (int i = 0; i < si.count; ++i) loc[i] = i;
+      std::sort(loc.begin(), loc.end(), [&](int x, int y) { return vid_c[si.begin + x] < vid_c[si.begin + y]; });
+      for (int i = 0; i < si.count; ++i) order[si.begin + i] = loc[i];
+    }
+    c->contact_order = (int*)c->alloc(n * sizeof(int));
+    c->upload(c->contact_order, order);
+  }
+
+  // ---- LDS groups
+  c->group_at_start.assign(c->sets.size(), -1);
+  c->group_at_end.assign(c->sets.size(), -1);
+  if (sd->n_groups > 0 && o->launch_mode != 2) {
+    if (c->dtype == XPBD_F32) build_groups<float>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c);
+    else build_groups<double>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c);
+  } else {
+    for (int g = 0; g < sd->n_groups; ++g) {
+      xpbd_ctx_s::Group G;
+      G.a = sd->group_sets[2 * g];
+      G.b = sd->group_sets[2 * g + 1];
+      c->groups.push_back(G);
+    }
+  }
+  // per-iteration record layout: sets outside LDS groups, then one chunk per LDS group
+  size_t toff = 0;
+  for (size_t k = 0; k < c->sets.size(); ++k) {
+    SetInfo& si = c->sets[k];
+    int g = -1;
+    for (size_t q = 0; q < c->groups.size(); ++q)
+      if (c->groups[q].lds && (int)k >= c->groups[q].a && (int)k < c->groups[q].b) g = (int)q;
+    if (g >= 0) continue;
+    si.tape_off = toff;
+    toff += align256(tape_item_bytes(si.type, c->tsz) * (size_t)si.count);
+  }
+  for (auto& G : c->groups)
+    if (G.lds) {
+      G.tape_off = (long long)toff;
+      toff += align256(G.tape_bytes);
+    }
+  c->iter_tape_bytes = toff;
+}
+
+// Build the LDS launch data of every schedule group: patch vertex lists,
+// per-patch item counts, and the forward / reverse record images in their
+// LDS layout (static fields here; compliances are filled per call).
+template <class T>
+void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
+                  const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
+                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c) {
+  const int V = c->V;
+  {
+    int dev = 0, lim = 0, optin = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      optin = 0;
+    }
+    c->lds_limit = (size_t)std::max(lim, optin);
+  }
+  auto verts_of = [&](int type, int j, int out[4]) -> int {
+    switch (type) {
+      case XPBD_DIST: out[0] = didx[j].x; out[1] = didx[j].y; return 2;
+      case XPBD_BEND: out[0] = bidx[j].x; out[1] = bidx[j].y; out[2] = bidx[j].z; out[3] = bidx[j].w; return 4;
+      case XPBD_TET: out[0] = tidx[j].x; out[1] = tidx[j].y; out[2] = tidx[j].z; out[3] = tidx[j].w; return 4;
+      default: out[0] = vid_c[j]; return 1;
+    }
+  };
+  const int ntype[3] = {c->n_dist, c->n_bend, c->n_tet};
+  std::vector<long long> fpos[3], rpos[3];
+  for (int t = 0; t < 3; ++t) { fpos[t].assign(ntype[t], -1); rpos[t].assign(ntype[t], -1); }
+  std::vector<unsigned char> fimg, rimg;
+  std::vector<int> lidx(V, -1);
+  std::vector<char> ref(V, 0);
+  for (int g = 0; g < sd->n_groups; ++g) {
+    xpbd_ctx_s::Group G;
+    G.a = sd->group_sets[2 * g];
+    G.b = sd->group_sets[2 * g + 1];
+    const int ns = G.b - G.a;
+    const int32_t* gp = sd->group_patch + (size_t)g * V;
+    std::fill(ref.begin(), ref.end(), 0);
+    for (int q = G.a; q < G.b; ++q) {
+      const SetInfo& si = c->sets[q];
+      for (int i = 0; i < si.count; ++i) {
+        int vv[4];
+        int nv = verts_of(si.type, si.begin + i, vv);
+        for (int k = 0; k < nv; ++k) ref[vv[k]] = 1;
+      }
+      G.items += si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count;
+    }
+    std::vector<int> raw;
+    for (int v = 0; v < V; ++v) if (ref[v]) raw.push_back(gp[v]);
+    std::sort(raw.begin(), raw.end());
+    raw.erase(std::unique(raw.begin(), raw.end()), raw.end());
+    const int P = (int)raw.size();
+    G.P = P;
+    auto cpatch = [&](int v) { return (int)(std::lower_bound(raw.begin(), raw.end(), gp[v]) - raw.begin()); };
+    std::vector<int> pv_start(P + 1, 0), pv;
+    for (int v = 0; v < V; ++v) if (ref[v]) pv_start[cpatch(v) + 1]++;
+    for (int p = 0; p < P; ++p) pv_start[p + 1] += pv_start[p];
+    pv.resize(pv_start[P]);
+    {
+      std::vector<int> fillp(pv_start.begin(), pv_start.end() - 1);
+      for (int v = 0; v < V; ++v)
+        if (ref[v]) {
+          int cp = cpatch(v);
+          lidx[v] = fillp[cp] - pv_start[cp];
+          pv[fillp[cp]++] = v;
+        }
+    }
+    int nv_max = 0;
+    for (int p = 0; p < P; ++p) nv_max = std::max(nv_max, pv_start[p + 1] - pv_start[p]);
+    // items of each set per patch (items are sorted by patch inside a set)
+    std::vector<int> cnt((size_t)P * ns, 0), first((size_t)P * ns, 0), stype(ns);
+    for (int q = 0; q < ns; ++q) {
+      const SetInfo& si = c->sets[G.a + q];
+      stype[q] = si.type;
+      for (int i = 0; i < si.count; ++i) {
+        int vv[4];
+        verts_of(si.type, si.begin + i, vv);
+        cnt[(size_t)cpatch(vv[0]) * ns + q]++;
+      }
+      int acc = si.begin;
+      for (int p = 0; p < P; ++p) {
+        first[(size_t)p * ns + q] = acc;
+        acc += cnt[(size_t)p * ns + q];
+      }
+    }
+    // sizes per patch
+    std::vector<long long> foff(P), roff(P), tpos(P);
+    size_t mf = 0, mr = 0, fsum = 0, rsum = 0, tsum = 0;
+    for (int p = 0; p < P; ++p) {
+      size_t vb = al32((size_t)(pv_start[p + 1] - pv_start[p]) * sizeof(Vec4<T>));
+      size_t rf = 0, rr = 0, tb = 0;
+      for (int q = 0; q < ns; ++q) {
+        size_t n = cnt[(size_t)p * ns + q];
+        rf += al32(n * fwd_rec_bytes<T>(stype[q]));
+        rr += al32(n * rev_rec_bytes<T>(stype[q]));
+        tb += al32(n * tape_words(stype[q]) * sizeof(T));
+      }
+      foff[p] = (long long)(fimg.size() + fsum);
+      roff[p] = (long long)(rimg.size() + rsum);
+      tpos[p] = (long long)tsum;
+      fsum += rf; rsum += rr; tsum += tb;
+      mf = std::max(mf, vb + rf);
+      mr = std::max(mr, vb + rr + tb);
+    }
+    G.smem_fwd = mf;
+    G.smem_rev = mr;
+    G.tape_bytes = tsum;
+    G.lds = P > 0 && nv_max <= 65535 && std::max(mf, mr) <= c->lds_limit;
+    if (G.lds) {
+      // record images in LDS layout
+      size_t fbase = fimg.size(), rbase = rimg.size();
+      fimg.resize(fbase + fsum, 0);
+      rimg.resize(rbase + rsum, 0);
+      for (int p = 0; p < P; ++p) {
+        size_t fo = (size_t)foff[p], ro = (size_t)roff[p];
+        for (int q = 0; q < ns; ++q) {
+          const int n = cnt[(size_t)p * ns + q], ty = stype[q];
+          for (int i = 0; i < n; ++i) {
+            int j = first[(size_t)p * ns + q] + i;
+            int vv[4] = {0, 0, 0, 0};
+            int nv = verts_of(ty, j, vv);
+            unsigned l[4] = {0, 0, 0, 0};
+            for (int k = 0; k < nv; ++k) l[k] = (unsigned)lidx[vv[k]];
+            unsigned l01 = l[0] | (l[1] << 16), l23 = l[2] | (l[3] << 16);
+            unsigned char* fp = &fimg[fo + i * fwd_rec_bytes<T>(ty)];
+            unsigned char* rp = &rimg[ro + i * rev_rec_bytes<T>(ty)];
+            switch (ty) {
+              case XPBD_DIST: {
+                SDist<T> f{(T)drest[j], T(0), T(0), l01};
+                RDist<T> r{(T)drest[j], T(0), T(0), T(0), l01};
+                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                break;
+              }
+              case XPBD_BEND: {
+                SBend<T> f{(T)btheta[j], T(0), T(0), l01, l23};
+                RBend<T> r{(T)btheta[j], T(0), T(0), T(0), l01, l23};
+                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                break;
+              }
+              case XPBD_TET: {
+                STet<T> f{};
+                RTet<T> r{};
+                for (int k = 0; k < 9; ++k) f.B[k] = r.B[k] = (T)tB[(size_t)k * c->n_tet + j];
+                f.l01 = r.l01 = l01;
+                f.l23 = r.l23 = l23;
+                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                break;
+              }
+              default: {
+                SCon<T> f{T(0), l[0]};
+                RCon<T> r{};
+                r.l = l[0];
+                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                break;
+              }
+            }
+            if (ty != XPBD_CONTACT) {
+              fpos[ty][j] = (long long)(fo + i * fwd_rec_bytes<T>(ty));
+              rpos[ty][j] = (long long)(ro + i * rev_rec_bytes<T>(ty));
+            }
+          }
+          fo += al32((size_t)n * fwd_rec_bytes<T>(ty));
+          ro += al32((size_t)n * rev_rec_bytes<T>(ty));
+        }
+      }
+      c->max_group_lds = std::max(c->max_group_lds, (int)std::max(mf, mr));
+      G.pv_start = (int*)c->alloc(pv_start.size() * sizeof(int));
+      G.pv = (int*)c->alloc(pv.size() * sizeof(int));
+      G.cnt = (int*)c->alloc(cnt.size() * sizeof(int));
+      G.rec_first = (int*)c->alloc(first.size() * sizeof(int));
+      G.set_type = (int*)c->alloc(ns * sizeof(int));
+      G.fimg = (long long*)c->alloc(P * sizeof(long long));
+      G.rimg = (long long*)c->alloc(P * sizeof(long long));
+      G.tpos = (long long*)c->alloc(P * sizeof(long long));
+      c->upload(G.pv_start, pv_start);
+      c->upload(G.pv, pv);
+      c->upload(G.cnt, cnt);
+      c->upload(G.rec_first, first);
+      c->upload(G.set_type, stype);
+      c->upload(G.fimg, foff);
+      c->upload(G.rimg, roff);
+      c->upload(G.tpos, tpos);
+      c->group_at_start[G.a] = g;
+      c->group_at_end[G.b - 1] = g;
+    }
+    c->groups.push_back(G);
+  }
+  if (!fimg.empty()) {
+    c->fimg = (char*)c->alloc(fimg.size());
+    c->rimg = (char*)c->alloc(rimg.size());
+    c->upload(c->fimg, fimg);
+    c->upload(c->rimg, rimg);
+    for (int t = 0; t < 3; ++t)
+      if (ntype[t]) {
+        c->fpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
+        c->rpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
+        c->upload(c->fpos[t], fpos[t]);
+        c->upload(c->rpos[t], rpos[t]);
+      }
+    Ops<T>::allow_lds((size_t)c->max_group_lds);
   }
 }
 
@@ -1030,6 +1416,11 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->tape_mode = c->tape_mode_used;
   info->persistent = c->persistent ? 1 : 0;
   info->persistent_blocks = c->persistent ? c->prog_grid : 0;
+  info->n_groups = (int32_t)c->groups.size();
+  int nl = 0;
+  for (auto& g : c->groups) nl += g.lds ? 1 : 0;
+  info->n_groups_lds = nl;
+  info->max_group_lds_bytes = c->max_group_lds;
   return XPBD_OK;
 }
 
@@ -1040,7 +1431,7 @@ xpbd_status xpbd_profile_enable(xpbd_ctx c, int32_t on) {
   return XPBD_OK;
 }
 
-xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[10], double ms[10], int64_t items[10]) {
+xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[12], double ms[12], int64_t items[12]) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
     for (auto& e : c->ev_pending) {
@@ -1053,7 +1444,7 @@ xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[10], double ms[10], i
       c->ev_free.push_back({e.a, e.b});
     }
     c->ev_pending.clear();
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 12; ++i) {
       if (launches) launches[i] = c->prof_launch[i];
       if (ms) ms[i] = c->prof_ms[i];
       if (items) items[i] = c->prof_items[i];

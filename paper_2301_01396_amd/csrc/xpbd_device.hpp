@@ -70,13 +70,18 @@ template <class T> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L
 // theta = atan2(((n1 x n2) . e)/|e|, n1 . n2).
 // grad x2 = -|e| n1/|n1|^2, grad x3 = -|e| n2/|n2|^2,
 // grad x1 = (a.e/|e|) n1/|n1|^2 + (b.e/|e|) n2/|n2|^2, grad x0 = -(sum).
+template <class S> __device__ __forceinline__ S one_over(S x) { return S(1) / x; }
+template <class T> __device__ __forceinline__ Dual<T> one_over(Dual<T> x) {
+  T r = T(1) / x.v;
+  return {r, -x.d * r * r};
+}
 template <class S> __device__ __forceinline__ void bend_gradient(V3<S> e, V3<S> a, V3<S> b, V3<S> g[4]) {
   V3<S> n1 = cross(e, a), n2 = cross(b, e);
   S le = dsqrt(dot(e, e));
-  S i1 = S(dot(n1, n1)), i2 = S(dot(n2, n2));
-  V3<S> s1 = {n1.x / i1, n1.y / i1, n1.z / i1};
-  V3<S> s2 = {n2.x / i2, n2.y / i2, n2.z / i2};
-  S c1 = dot(a, e) / le, c2 = dot(b, e) / le;
+  S r1 = one_over(S(dot(n1, n1))), r2 = one_over(S(dot(n2, n2))), rl = one_over(le);
+  V3<S> s1 = {n1.x * r1, n1.y * r1, n1.z * r1};
+  V3<S> s2 = {n2.x * r2, n2.y * r2, n2.z * r2};
+  S c1 = dot(a, e) * rl, c2 = dot(b, e) * rl;
   g[2] = {-(le * s1.x), -(le * s1.y), -(le * s1.z)};
   g[3] = {-(le * s2.x), -(le * s2.y), -(le * s2.z)};
   g[1] = {c1 * s1.x + c2 * s2.x, c1 * s1.y + c2 * s2.y, c1 * s1.z + c2 * s2.z};

@@ -50,66 +50,56 @@ template <class T> struct Dev {
   const int2* d_idx; const T* d_rest; const T* d_at; T* d_lam; T* d_lamb; T* d_ab; double* d_acc;
   const int4* b_idx; const T* b_th0; const T* b_at; T* b_lam; T* b_lamb; T* b_ab; double* b_acc;
   TetRec<T> tr; T* t_lamD; T* t_lamH; T* t_lambD; T* t_lambH; T* t_eb; double* t_acc;
-  const int* c_vid; T* c_lam; T* c_lamb; Vec4<T>* c_sacc;
+  const int* c_vid; T* c_lam; T* c_lamb; Vec4<T>* c_sacc; const int* c_order;
   Sphere<T> sph;
   T h, inv_h, gx, gy, gz;
 };
 
-// ===================================================================== forward items
+// ===================================================================== projection cores
+// Each core works on register copies of one constraint's vertices and
+// record, so the same arithmetic serves vertex state in global memory and
+// vertex tiles in LDS.  Forward cores return lambda after the projection
+// (lambda before when it is skipped) and optionally emit the adjoint's
+// record; reverse cores update the vertex adjoints, lambda_bar and the
+// compliance adjoint in place.
 
-template <class T, bool FIRST, bool TAPE>
-__device__ __forceinline__ void dist_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int2 e = D.d_idx[j];
-  Vec4<T> a = D.X[e.x], b = D.X[e.y];
+template <class T, bool TAPE>
+__device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T lb, Vec4<T>* tape) {
   V3<T> r = xyz(a) - xyz(b);
-  T lb = FIRST ? T(0) : D.d_lam[j];
-  if (TAPE) tape[t] = Vec4<T>{r.x, r.y, r.z, lb};
-  DistEval<T> ev = dist_eval(r, D.d_rest[j]);
-  T a_t = D.d_at[j];
+  if (TAPE) *tape = Vec4<T>{r.x, r.y, r.z, lb};
+  DistEval<T> ev = dist_eval(r, rest);
   T Dn = a.w + b.w + a_t;
-  if (!ev.ok || !(Dn > T(0))) {
-    if (FIRST) D.d_lam[j] = T(0);
-    return;
-  }
+  if (!ev.ok || !(Dn > T(0))) return lb;
   T dl = (-ev.C - a_t * lb) / Dn;
-  D.d_lam[j] = lb + dl;
   T sa = a.w * dl, sb = b.w * dl;
   a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
   b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
-  D.X[e.x] = a;
-  D.X[e.y] = b;
+  return lb + dl;
 }
 
-template <class T, bool FIRST, bool TAPE>
-__device__ __forceinline__ void bend_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int4 q = D.b_idx[j];
-  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
+// bending record of set item t: Vec4 (e, lambda) at tape[t], Vec4 (a, b.x) at
+// tape[count + t], Vec2 (b.y, b.z) at element t of the Vec2 array that
+// starts at tape + 2 * count
+template <class T, bool TAPE>
+__device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<T>* tape, int t, int count) {
   V3<T> e = xyz(p[1]) - xyz(p[0]), a = xyz(p[2]) - xyz(p[0]), b = xyz(p[3]) - xyz(p[0]);
-  T lb = FIRST ? T(0) : D.b_lam[j];
   if (TAPE) {
     tape[t] = Vec4<T>{e.x, e.y, e.z, lb};
     tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
     reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
   }
-  BendEval<T> ev = bend_eval(e, a, b, D.b_th0[j]);
-  T a_t = D.b_at[j];
+  BendEval<T> ev = bend_eval(e, a, b, theta0);
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += p[k].w * dot(ev.g[k], ev.g[k]);
-  if (!ev.ok || !(Dn > T(0))) {
-    if (FIRST) D.b_lam[j] = T(0);
-    return;
-  }
+  if (!ev.ok || !(Dn > T(0))) return lb;
   T dl = (-ev.C - a_t * lb) / Dn;
-  D.b_lam[j] = lb + dl;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     T s = p[k].w * dl;
     p[k].x += s * ev.g[k].x; p[k].y += s * ev.g[k].y; p[k].z += s * ev.g[k].z;
   }
-  D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3];
+  return lb + dl;
 }
 
 template <class T> __device__ __forceinline__ M3<T> load_B(const T* B, int n, int j) {
@@ -154,57 +144,40 @@ __device__ __forceinline__ void tet_step(const V3<T> d0[3], const T w[4], const 
   for (int k = 0; k < 4; ++k) s.dH[k] = s.appH ? (w[k] * s.dlH) * s.evH.g[k] : V3<T>{T(0), T(0), T(0)};
 }
 
-template <class T, bool FIRST, bool TAPE>
-__device__ __forceinline__ void tet_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  const TetRec<T>& R = D.tr;
-  int4 q = R.idx[j];
-  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
+template <class T, bool TAPE>
+__device__ __forceinline__ void tet_fwd(Vec4<T> p[4], const M3<T>& B, T atD, T atH, T gamma, T& lD, T& lH,
+                                        Vec4<T>* tape, int count) {
   V3<T> d[3] = {xyz(p[1]) - xyz(p[0]), xyz(p[2]) - xyz(p[0]), xyz(p[3]) - xyz(p[0])};
-  T lD = FIRST ? T(0) : D.t_lamD[j];
-  T lH = FIRST ? T(0) : D.t_lamH[j];
   if (TAPE) {
-    tape[t] = Vec4<T>{d[0].x, d[0].y, d[0].z, d[1].x};
-    tape[count + t] = Vec4<T>{d[1].y, d[1].z, d[2].x, d[2].y};
-    tape[2 * count + t] = Vec4<T>{d[2].z, lD, lH, T(0)};
+    tape[0] = Vec4<T>{d[0].x, d[0].y, d[0].z, d[1].x};
+    tape[count] = Vec4<T>{d[1].y, d[1].z, d[2].x, d[2].y};
+    tape[2 * count] = Vec4<T>{d[2].z, lD, lH, T(0)};
   }
-  M3<T> B = load_B(R.B, R.n, j);
   T w[4] = {p[0].w, p[1].w, p[2].w, p[3].w};
   TetStep<T> s;
-  tet_step(d, w, B, R.atD[j], R.atH[j], R.gamma[j], lD, lH, s);
-  D.t_lamD[j] = lD + s.dlD;
-  D.t_lamH[j] = lH + s.dlH;
+  tet_step(d, w, B, atD, atH, gamma, lD, lH, s);
+  lD = lD + s.dlD;
+  lH = lH + s.dlH;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     p[k].x = (p[k].x + s.dD[k].x) + s.dH[k].x;
     p[k].y = (p[k].y + s.dD[k].y) + s.dH[k].y;
     p[k].z = (p[k].z + s.dD[k].z) + s.dH[k].z;
   }
-  D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3];
 }
 
-template <class T, bool FIRST, bool TAPE>
-__device__ __forceinline__ void contact_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int v = D.c_vid[j];
-  const Sphere<T>& S = D.sph;
-  Vec4<T> p = D.X[v];
-  T lb = FIRST ? T(0) : D.c_lam[j];
-  if (TAPE) tape[t] = Vec4<T>{p.x, p.y, p.z, lb};
+template <class T, bool TAPE>
+__device__ __forceinline__ T contact_fwd(Vec4<T>& p, const Sphere<T>& S, T lb, Vec4<T>* tape) {
+  if (TAPE) *tape = Vec4<T>{p.x, p.y, p.z, lb};
   ContactEval<T> ev = contact_eval(V3<T>{p.x - S.cx, p.y - S.cy, p.z - S.cz}, S.R, S.tau);
   T Dn = p.w + S.at;
-  if (!ev.ok || !(ev.C < T(0)) || !(Dn > T(0))) {
-    if (FIRST) D.c_lam[j] = T(0);
-    return;
-  }
+  if (!ev.ok || !(ev.C < T(0)) || !(Dn > T(0))) return lb;
   T dl = (-ev.C - S.at * lb) / Dn;
-  D.c_lam[j] = lb + dl;
   T s = p.w * dl;
   p.x += s * ev.n.x; p.y += s * ev.n.y; p.z += s * ev.n.z;
-  D.X[v] = p;
+  return lb + dl;
 }
 
-// ===================================================================== reverse items
 // Adjoint of one projection given the adjoints of its outputs: gradient g_k,
 // weights w_k, denominator D, dlambda, lambda_bar, position adjoints xb_k.
 // Returns dlambda_bar; writes gbar_k (adjoint of grad_k C).
@@ -221,108 +194,71 @@ __device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T D, T
   return dlb;
 }
 
-template <class T, bool FIRST, bool LAST>
-__device__ __forceinline__ void dist_rev_item(const Dev<T>& D, int begin, int count, int t,
-                                              const Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int2 e = D.d_idx[j];
-  Vec4<T> tp = tape[t];
-  T lbar = FIRST ? T(0) : D.d_lamb[j];
-  T ab = FIRST ? T(0) : D.d_ab[j];
-  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, D.d_rest[j]);
-  Vec4<T> A = D.XB[e.x], Bv = D.XB[e.y];
-  T a_t = D.d_at[j];
+// A and Bv hold (xbar, w) of the two vertices; returns true if they changed.
+template <class T>
+__device__ __forceinline__ bool dist_rev(Vec4<T>& A, Vec4<T>& Bv, Vec4<T> tp, T rest, T a_t, T& lbar, T& ab) {
+  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, rest);
   T Dn = A.w + Bv.w + a_t;
-  if (ev.ok && Dn > T(0)) {
-    T lb = tp.w;
-    T dl = (-ev.C - a_t * lb) / Dn;
-    V3<T> xa = xyz(A), xb = xyz(Bv);
-    T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
-    // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
-    // along n and vanishes under P, leaving dl * P (w_i xa - w_j xb) / |r|.
-    V3<T> u = A.w * xa - Bv.w * xb;
-    T un = dot(ev.n, u);
-    T s = dl / ev.len;
-    V3<T> hv = {s * (u.x - un * ev.n.x), s * (u.y - un * ev.n.y), s * (u.z - un * ev.n.z)};
-    T Cb = -dlb / Dn;
-    lbar = lbar - dlb * a_t / Dn;
-    ab = ab - dlb * (lb + dl) / Dn;
-    A.x += Cb * ev.n.x + hv.x; A.y += Cb * ev.n.y + hv.y; A.z += Cb * ev.n.z + hv.z;
-    Bv.x -= Cb * ev.n.x + hv.x; Bv.y -= Cb * ev.n.y + hv.y; Bv.z -= Cb * ev.n.z + hv.z;
-    D.XB[e.x] = A;
-    D.XB[e.y] = Bv;
-  }
-  if (LAST) {
-    D.d_acc[j] += (double)ab;
-  } else {
-    D.d_lamb[j] = lbar;
-    D.d_ab[j] = ab;
-  }
+  if (!(ev.ok && Dn > T(0))) return false;
+  T lb = tp.w;
+  T dl = (-ev.C - a_t * lb) / Dn;
+  V3<T> xa = xyz(A), xb = xyz(Bv);
+  T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
+  // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
+  // along n and vanishes under P, leaving dl * P (w_i xa - w_j xb) / |r|.
+  V3<T> u = A.w * xa - Bv.w * xb;
+  T un = dot(ev.n, u);
+  T s = dl / ev.len;
+  V3<T> hv = {s * (u.x - un * ev.n.x), s * (u.y - un * ev.n.y), s * (u.z - un * ev.n.z)};
+  T Cb = -dlb / Dn;
+  lbar = lbar - dlb * a_t / Dn;
+  ab = ab - dlb * (lb + dl) / Dn;
+  A.x += Cb * ev.n.x + hv.x; A.y += Cb * ev.n.y + hv.y; A.z += Cb * ev.n.z + hv.z;
+  Bv.x -= Cb * ev.n.x + hv.x; Bv.y -= Cb * ev.n.y + hv.y; Bv.z -= Cb * ev.n.z + hv.z;
+  return true;
 }
 
-template <class T, bool FIRST, bool LAST>
-__device__ __forceinline__ void bend_rev_item(const Dev<T>& D, int begin, int count, int t,
-                                              const Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int4 q = D.b_idx[j];
+template <class T>
+__device__ __forceinline__ bool bend_rev(Vec4<T> P[4], const Vec4<T>* tape, int t, int count, T theta0, T a_t,
+                                         T& lbar, T& ab) {
   Vec4<T> tA = tape[t], tB = tape[count + t];
   Vec2<T> tC = reinterpret_cast<const Vec2<T>*>(tape + 2 * count)[t];
   V3<T> e = {tA.x, tA.y, tA.z}, a = {tB.x, tB.y, tB.z}, b = {tB.w, tC.x, tC.y};
   T lb = tA.w;
-  T lbar = FIRST ? T(0) : D.b_lamb[j];
-  T ab = FIRST ? T(0) : D.b_ab[j];
-  BendEval<T> ev = bend_eval(e, a, b, D.b_th0[j]);
-  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
+  BendEval<T> ev = bend_eval(e, a, b, theta0);
   T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
-  T a_t = D.b_at[j];
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += w[k] * dot(ev.g[k], ev.g[k]);
-  if (ev.ok && Dn > T(0)) {
-    T dl = (-ev.C - a_t * lb) / Dn;
-    V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
-    V3<T> gb[4], hv[4];
-    T dlb = proj_adjoint<T, 4>(ev.g, w, Dn, dl, lbar, xb, gb);
-    bend_hvp(e, a, b, gb, hv);
-    T Cb = -dlb / Dn;
-    lbar = lbar - dlb * a_t / Dn;
-    ab = ab - dlb * (lb + dl) / Dn;
+  if (!(ev.ok && Dn > T(0))) return false;
+  T dl = (-ev.C - a_t * lb) / Dn;
+  V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
+  V3<T> gb[4], hv[4];
+  T dlb = proj_adjoint<T, 4>(ev.g, w, Dn, dl, lbar, xb, gb);
+  bend_hvp(e, a, b, gb, hv);
+  T Cb = -dlb / Dn;
+  lbar = lbar - dlb * a_t / Dn;
+  ab = ab - dlb * (lb + dl) / Dn;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      P[k].x += Cb * ev.g[k].x + hv[k].x;
-      P[k].y += Cb * ev.g[k].y + hv[k].y;
-      P[k].z += Cb * ev.g[k].z + hv[k].z;
-    }
-    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
+  for (int k = 0; k < 4; ++k) {
+    P[k].x += Cb * ev.g[k].x + hv[k].x;
+    P[k].y += Cb * ev.g[k].y + hv[k].y;
+    P[k].z += Cb * ev.g[k].z + hv[k].z;
   }
-  if (LAST) {
-    D.b_acc[j] += (double)ab;
-  } else {
-    D.b_lamb[j] = lbar;
-    D.b_ab[j] = ab;
-  }
+  return true;
 }
 
 // tet: ebar accumulates sum over projections of (atbar_D at_D + atbar_H at_H),
 // i.e. alphabar_D alpha_D + alphabar_H alpha_H, whence dL/dE = -ebar / E.
-template <class T, bool FIRST, bool LAST>
-__device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int count, int t,
-                                             const Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  const TetRec<T>& R = D.tr;
-  int4 q = R.idx[j];
-  Vec4<T> t0 = tape[t], t1 = tape[count + t], t2 = tape[2 * count + t];
+template <class T>
+__device__ __forceinline__ bool tet_rev(Vec4<T> P[4], const Vec4<T>* tape, int count, const M3<T>& B, T atD, T atH,
+                                        T gamma, T& lbD, T& lbH, T& eb) {
+  Vec4<T> t0 = tape[0], t1 = tape[count], t2 = tape[2 * count];
   V3<T> d[3] = {{t0.x, t0.y, t0.z}, {t0.w, t1.x, t1.y}, {t1.z, t1.w, t2.x}};
   T lD = t2.y, lH = t2.z;
-  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
   T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
-  M3<T> B = load_B(R.B, R.n, j);
-  T atD = R.atD[j], atH = R.atH[j];
   TetStep<T> s;
-  tet_step(d, w, B, atD, atH, R.gamma[j], lD, lH, s);
-  T lbD = FIRST ? T(0) : D.t_lambD[j];
-  T lbH = FIRST ? T(0) : D.t_lambH[j];
-  T eb = FIRST ? T(0) : D.t_eb[j];
+  tet_step(d, w, B, atD, atH, gamma, lD, lH, s);
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
   if (s.appH) {
@@ -343,51 +279,139 @@ __device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int cou
 #pragma unroll
     for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evD.g[k] + hv[k]);
   }
-  if (s.appD || s.appH) {
+  if (!(s.appD || s.appH)) return false;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { P[k].x = xb[k].x; P[k].y = xb[k].y; P[k].z = xb[k].z; }
-    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
-  }
-  if (LAST) {
-    D.t_acc[j] += (double)eb;
-  } else {
-    D.t_lambD[j] = lbD;
-    D.t_lambH[j] = lbH;
-    D.t_eb[j] = eb;
-  }
+  for (int k = 0; k < 4; ++k) { P[k].x = xb[k].x; P[k].y = xb[k].y; P[k].z = xb[k].z; }
+  return true;
 }
 
-// contact: also accumulates the sphere adjoint (cbar, Rbar) per contact
+// contact: also accumulates the sphere adjoint (cbar, Rbar) in sa
+template <class T>
+__device__ __forceinline__ bool contact_rev(Vec4<T>& P, Vec4<T> tp, const Sphere<T>& S, T& lbar, Vec4<T>& sa) {
+  ContactEval<T> ev = contact_eval(V3<T>{tp.x - S.cx, tp.y - S.cy, tp.z - S.cz}, S.R, S.tau);
+  T Dn = P.w + S.at;
+  if (!(ev.ok && ev.C < T(0) && Dn > T(0))) return false;
+  T lb = tp.w;
+  T dl = (-ev.C - S.at * lb) / Dn;
+  V3<T> xb = xyz(P);
+  T dlb = lbar + P.w * dot(ev.n, xb);
+  T c = T(2) * dlb * dl / Dn;
+  V3<T> gb = {P.w * (dl * xb.x - c * ev.n.x), P.w * (dl * xb.y - c * ev.n.y), P.w * (dl * xb.z - c * ev.n.z)};
+  T gn = dot(ev.n, gb);
+  T inv = T(1) / ev.d;
+  V3<T> hv = {inv * (gb.x - gn * ev.n.x), inv * (gb.y - gn * ev.n.y), inv * (gb.z - gn * ev.n.z)};
+  T Cb = -dlb / Dn;
+  lbar = lbar - dlb * S.at / Dn;
+  P.x += Cb * ev.n.x + hv.x; P.y += Cb * ev.n.y + hv.y; P.z += Cb * ev.n.z + hv.z;
+  // C = |x - c| - R - tau: dC/dc = -n, dC/dR = -1, d(grad_x C)/dc = -P/|x-c|
+  sa.x -= Cb * ev.n.x + hv.x; sa.y -= Cb * ev.n.y + hv.y; sa.z -= Cb * ev.n.z + hv.z;
+  sa.w -= Cb;
+  return true;
+}
+
+// ===================================================================== items on global vertex state
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void dist_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int2 e = D.d_idx[j];
+  Vec4<T> a = D.X[e.x], b = D.X[e.y];
+  T lb = FIRST ? T(0) : D.d_lam[j];
+  T ln = dist_fwd<T, TAPE>(a, b, D.d_rest[j], D.d_at[j], lb, tape + t);
+  D.d_lam[j] = ln;
+  if (ln != lb) { D.X[e.x] = a; D.X[e.y] = b; }
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void bend_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int4 q = D.b_idx[j];
+  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
+  T lb = FIRST ? T(0) : D.b_lam[j];
+  T ln = bend_fwd<T, TAPE>(p, D.b_th0[j], D.b_at[j], lb, tape, t, count);
+  D.b_lam[j] = ln;
+  if (ln != lb) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3]; }
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void tet_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  const TetRec<T>& R = D.tr;
+  int4 q = R.idx[j];
+  Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
+  T lD = FIRST ? T(0) : D.t_lamD[j];
+  T lH = FIRST ? T(0) : D.t_lamH[j];
+  tet_fwd<T, TAPE>(p, load_B(R.B, R.n, j), R.atD[j], R.atH[j], R.gamma[j], lD, lH, tape + t, count);
+  D.t_lamD[j] = lD;
+  D.t_lamH[j] = lH;
+  D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3];
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void contact_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int v = D.c_vid[j];
+  Vec4<T> p = D.X[v];
+  T lb = FIRST ? T(0) : D.c_lam[j];
+  T ln = contact_fwd<T, TAPE>(p, D.sph, lb, tape + t);
+  D.c_lam[j] = ln;
+  if (ln != lb) D.X[v] = p;
+}
+
+template <class T, bool FIRST, bool LAST>
+__device__ __forceinline__ void dist_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                              const Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int2 e = D.d_idx[j];
+  T lbar = FIRST ? T(0) : D.d_lamb[j];
+  T ab = FIRST ? T(0) : D.d_ab[j];
+  Vec4<T> A = D.XB[e.x], Bv = D.XB[e.y];
+  if (dist_rev(A, Bv, tape[t], D.d_rest[j], D.d_at[j], lbar, ab)) { D.XB[e.x] = A; D.XB[e.y] = Bv; }
+  if (LAST) D.d_acc[j] += (double)ab;
+  else { D.d_lamb[j] = lbar; D.d_ab[j] = ab; }
+}
+
+template <class T, bool FIRST, bool LAST>
+__device__ __forceinline__ void bend_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                              const Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int4 q = D.b_idx[j];
+  T lbar = FIRST ? T(0) : D.b_lamb[j];
+  T ab = FIRST ? T(0) : D.b_ab[j];
+  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
+  if (bend_rev(P, tape, t, count, D.b_th0[j], D.b_at[j], lbar, ab)) {
+    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
+  }
+  if (LAST) D.b_acc[j] += (double)ab;
+  else { D.b_lamb[j] = lbar; D.b_ab[j] = ab; }
+}
+
+template <class T, bool FIRST, bool LAST>
+__device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                             const Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  const TetRec<T>& R = D.tr;
+  int4 q = R.idx[j];
+  T lbD = FIRST ? T(0) : D.t_lambD[j];
+  T lbH = FIRST ? T(0) : D.t_lambH[j];
+  T eb = FIRST ? T(0) : D.t_eb[j];
+  Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
+  if (tet_rev(P, tape + t, count, load_B(R.B, R.n, j), R.atD[j], R.atH[j], R.gamma[j], lbD, lbH, eb)) {
+    D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
+  }
+  if (LAST) D.t_acc[j] += (double)eb;
+  else { D.t_lambD[j] = lbD; D.t_lambH[j] = lbH; D.t_eb[j] = eb; }
+}
+
 template <class T, bool FIRST, bool LAST>
 __device__ __forceinline__ void contact_rev_item(const Dev<T>& D, int begin, int count, int t,
                                                  const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
   int v = D.c_vid[j];
-  const Sphere<T>& S = D.sph;
-  Vec4<T> tp = tape[t];
   T lbar = FIRST ? T(0) : D.c_lamb[j];
   Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : D.c_sacc[j];
-  ContactEval<T> ev = contact_eval(V3<T>{tp.x - S.cx, tp.y - S.cy, tp.z - S.cz}, S.R, S.tau);
   Vec4<T> P = D.XB[v];
-  T Dn = P.w + S.at;
-  if (ev.ok && ev.C < T(0) && Dn > T(0)) {
-    T lb = tp.w;
-    T dl = (-ev.C - S.at * lb) / Dn;
-    V3<T> xb = xyz(P);
-    T dlb = lbar + P.w * dot(ev.n, xb);
-    T c = T(2) * dlb * dl / Dn;
-    V3<T> gb = {P.w * (dl * xb.x - c * ev.n.x), P.w * (dl * xb.y - c * ev.n.y), P.w * (dl * xb.z - c * ev.n.z)};
-    T gn = dot(ev.n, gb);
-    T inv = T(1) / ev.d;
-    V3<T> hv = {inv * (gb.x - gn * ev.n.x), inv * (gb.y - gn * ev.n.y), inv * (gb.z - gn * ev.n.z)};
-    T Cb = -dlb / Dn;
-    lbar = lbar - dlb * S.at / Dn;
-    P.x += Cb * ev.n.x + hv.x; P.y += Cb * ev.n.y + hv.y; P.z += Cb * ev.n.z + hv.z;
-    D.XB[v] = P;
-    // C = |x - c| - R - tau: dC/dc = -n, dC/dR = -1, d(grad_x C)/dc = -P/|x-c|
-    sa.x -= Cb * ev.n.x + hv.x; sa.y -= Cb * ev.n.y + hv.y; sa.z -= Cb * ev.n.z + hv.z;
-    sa.w -= Cb;
-  }
+  if (contact_rev(P, tape[t], D.sph, lbar, sa)) D.XB[v] = P;
   if (!LAST) D.c_lamb[j] = lbar;
   D.c_sacc[j] = sa;
 }
@@ -576,12 +600,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_E_grad(const double* __restr
 
 // Deterministic block reduction of the per-contact sphere adjoints into the
 // FP64 sphere gradient (fixed order: strided partial sums, then a tree).
+// `order` lists the set's items by ascending vertex, so the sum does not
+// depend on how the items are laid out.
 template <class T, int NT>
-__device__ __forceinline__ void sphere_reduce_block(const Vec4<T>* __restrict__ sacc, int begin, int count,
-                                                    double* __restrict__ out, double (*sh)[NT]) {
+__device__ __forceinline__ void sphere_reduce_block(const Vec4<T>* __restrict__ sacc, const int* __restrict__ order,
+                                                    int begin, int count, double* __restrict__ out, double (*sh)[NT]) {
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (int i = threadIdx.x; i < count; i += NT) {
-    Vec4<T> v = sacc[begin + i];
+    Vec4<T> v = sacc[begin + order[begin + i]];
     s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
   }
   sh[0][threadIdx.x] = s0; sh[1][threadIdx.x] = s1; sh[2][threadIdx.x] = s2; sh[3][threadIdx.x] = s3;
@@ -595,10 +621,10 @@ __device__ __forceinline__ void sphere_reduce_block(const Vec4<T>* __restrict__ 
   __syncthreads();
 }
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_sphere_reduce(const Vec4<T>* __restrict__ sacc, int begin, int count,
-                                                          double* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_sphere_reduce(const Vec4<T>* __restrict__ sacc, const int* __restrict__ order,
+                                                          int begin, int count, double* __restrict__ out) {
   __shared__ double sh[4][kBlock];
-  sphere_reduce_block<T, kBlock>(sacc, begin, count, out, sh);
+  sphere_reduce_block<T, kBlock>(sacc, order, begin, count, out, sh);
 }
 
 // FP64 goal: per-block partial sums of 1/2 |x - x*|^2 on masked frames, and
@@ -634,6 +660,279 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const double* __restrict__ p
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = accumulate ? *out + sh[0] : sh[0];
+}
+
+// ===================================================================== LDS group kernels
+// A group is a run of consecutive independent sets together with a vertex
+// partition under which every constraint of those sets has all its vertices
+// in one patch.  One workgroup per patch stages the patch's vertices and the
+// records of its constraints in LDS, runs the group's sets in schedule order
+// with a workgroup barrier between sets, and writes back.  Patches share no
+// vertex inside the group, so the result equals running the sets one launch
+// at a time, bit for bit.
+//
+// The records of a group live in global memory as patch-major images laid
+// out exactly like the LDS copy (set after set, each padded to 32 bytes), so
+// staging is one contiguous 16-byte copy per patch.  The forward writes the
+// adjoint's record of projection inputs in the same patch-major layout,
+// which the reverse stages the same way.
+
+constexpr int kMaxGroupSets = 64;
+
+template <class T> struct SDist { T rest, at, lam; unsigned l; };
+template <class T> struct SBend { T th0, at, lam; unsigned l01, l23; };
+template <class T> struct STet { T B[9]; T atD, atH, gam, lD, lH; unsigned l01, l23; };
+template <class T> struct SCon { T lam; unsigned l; };
+template <class T> struct RDist { T rest, at, lamb, ab; unsigned l; };
+template <class T> struct RBend { T th0, at, lamb, ab; unsigned l01, l23; };
+template <class T> struct RTet { T B[9]; T atD, atH, gam, lbD, lbH, eb; unsigned l01, l23; };
+template <class T> struct RCon { Vec4<T> sa; T lamb; unsigned l; };
+
+__host__ __device__ __forceinline__ size_t al32(size_t b) { return (b + 31) & ~(size_t)31; }
+__device__ __forceinline__ int lo16(unsigned v) { return (int)(v & 0xffffu); }
+__device__ __forceinline__ int hi16(unsigned v) { return (int)(v >> 16); }
+
+template <class T> __host__ __device__ inline size_t fwd_rec_bytes(int type) {
+  return type == 0 ? sizeof(SDist<T>) : type == 1 ? sizeof(SBend<T>) : type == 2 ? sizeof(STet<T>) : sizeof(SCon<T>);
+}
+template <class T> __host__ __device__ inline size_t rev_rec_bytes(int type) {
+  return type == 0 ? sizeof(RDist<T>) : type == 1 ? sizeof(RBend<T>) : type == 2 ? sizeof(RTet<T>) : sizeof(RCon<T>);
+}
+__host__ __device__ inline size_t tape_words(int type) { return type == 1 ? 10 : type == 2 ? 12 : 4; }
+
+struct GroupDev {
+  const int* pv_start;      // [P + 1] patch vertex ranges
+  const int* pv;            // global vertex of each patch slot
+  const int* cnt;           // [P][nset] items of each set in each patch
+  const int* set_type;      // [nset]
+  const long long* fimg;    // [P] byte offset of each patch's forward record image
+  const long long* rimg;    // [P] ... reverse record image
+  const long long* tpos;    // [P] byte offset of each patch's record of inputs in the group's chunk
+  const int* rec_first;     // [P][nset] internal index of the patch's first item in each set
+  int nset, P;
+  long long tape_off;       // byte offset of the group's chunk inside one iteration's record
+};
+
+// Workgroup barrier that orders LDS only: the group kernels share nothing
+// through global memory between sets, so outstanding global stores (the
+// record of projection inputs) keep draining across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += kBlock) d[i] = s[i];
+}
+
+template <class T, bool FIRST, bool TAPE>
+__global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char* __restrict__ fimg,
+                                                      char* __restrict__ tape_iter) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
+  const int* cnt = G.cnt + (size_t)p * G.nset;
+  Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
+  unsigned char* rec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  size_t rbytes = 0;
+  for (int q = 0; q < G.nset; ++q) rbytes += al32((size_t)cnt[q] * fwd_rec_bytes<T>(G.set_type[q]));
+  char* gimg = fimg + G.fimg[p];
+  for (int i = tid; i < nv; i += kBlock) sX[i] = D.X[G.pv[v0 + i]];
+  copy16(rec, gimg, rbytes);
+  lds_barrier();
+  char* gt = TAPE ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
+  unsigned char* r = rec;
+  for (int q = 0; q < G.nset; ++q) {
+    const int n = cnt[q], ty = G.set_type[q];
+    Vec4<T>* tape = reinterpret_cast<Vec4<T>*>(gt);
+    switch (ty) {
+      case 0:
+        for (int i = tid; i < n; i += kBlock) {
+          SDist<T>& s = reinterpret_cast<SDist<T>*>(r)[i];
+          int la = lo16(s.l), lb = hi16(s.l);
+          Vec4<T> a = sX[la], bb = sX[lb];
+          T l0 = FIRST ? T(0) : s.lam;
+          T ln = dist_fwd<T, TAPE>(a, bb, s.rest, s.at, l0, tape + i);
+          if (ln != l0) { sX[la] = a; sX[lb] = bb; }
+          s.lam = ln;
+        }
+        break;
+      case 1:
+        for (int i = tid; i < n; i += kBlock) {
+          SBend<T>& s = reinterpret_cast<SBend<T>*>(r)[i];
+          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+          Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+          T l0 = FIRST ? T(0) : s.lam;
+          T ln = bend_fwd<T, TAPE>(pp, s.th0, s.at, l0, tape, i, n);
+          if (ln != l0) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3]; }
+          s.lam = ln;
+        }
+        break;
+      case 2:
+        for (int i = tid; i < n; i += kBlock) {
+          STet<T>& s = reinterpret_cast<STet<T>*>(r)[i];
+          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+          Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+          M3<T> B;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
+          T lD = FIRST ? T(0) : s.lD, lH = FIRST ? T(0) : s.lH;
+          tet_fwd<T, TAPE>(pp, B, s.atD, s.atH, s.gam, lD, lH, tape + i, n);
+          s.lD = lD; s.lH = lH;
+          sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3];
+        }
+        break;
+      default:
+        for (int i = tid; i < n; i += kBlock) {
+          SCon<T>& s = reinterpret_cast<SCon<T>*>(r)[i];
+          int l = (int)s.l;
+          Vec4<T> pp = sX[l];
+          T l0 = FIRST ? T(0) : s.lam;
+          T ln = contact_fwd<T, TAPE>(pp, D.sph, l0, tape + i);
+          if (ln != l0) sX[l] = pp;
+          s.lam = ln;
+        }
+        break;
+    }
+    r += al32((size_t)n * fwd_rec_bytes<T>(ty));
+    if (TAPE) gt += al32((size_t)n * tape_words(ty) * sizeof(T));
+    lds_barrier();
+  }
+  for (int i = tid; i < nv; i += kBlock) D.X[G.pv[v0 + i]] = sX[i];
+  copy16(gimg, rec, rbytes);
+}
+
+template <class T, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char* __restrict__ rimg,
+                                                      const char* __restrict__ tape_iter) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
+  const int* cnt = G.cnt + (size_t)p * G.nset;
+  Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
+  unsigned char* rec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  size_t rbytes = 0, tbytes = 0;
+  for (int q = 0; q < G.nset; ++q) {
+    rbytes += al32((size_t)cnt[q] * rev_rec_bytes<T>(G.set_type[q]));
+    tbytes += al32((size_t)cnt[q] * tape_words(G.set_type[q]) * sizeof(T));
+  }
+  unsigned char* tap = rec + rbytes;
+  char* gimg = rimg + G.rimg[p];
+  for (int i = tid; i < nv; i += kBlock) sX[i] = D.XB[G.pv[v0 + i]];
+  copy16(rec, gimg, rbytes);
+  copy16(tap, tape_iter + G.tape_off + G.tpos[p], tbytes);
+  lds_barrier();
+  // walk the sets backwards: start past the last region
+  unsigned char* r = rec + rbytes;
+  unsigned char* t = tap + tbytes;
+  for (int q = G.nset - 1; q >= 0; --q) {
+    const int n = cnt[q], ty = G.set_type[q];
+    r -= al32((size_t)n * rev_rec_bytes<T>(ty));
+    t -= al32((size_t)n * tape_words(ty) * sizeof(T));
+    const Vec4<T>* st = reinterpret_cast<const Vec4<T>*>(t);
+    switch (ty) {
+      case 0:
+        for (int i = tid; i < n; i += kBlock) {
+          RDist<T>& s = reinterpret_cast<RDist<T>*>(r)[i];
+          int la = lo16(s.l), lb = hi16(s.l);
+          Vec4<T> A = sX[la], Bv = sX[lb];
+          T lbar = FIRST ? T(0) : s.lamb, ab = FIRST ? T(0) : s.ab;
+          if (dist_rev(A, Bv, st[i], s.rest, s.at, lbar, ab)) { sX[la] = A; sX[lb] = Bv; }
+          s.lamb = lbar; s.ab = ab;
+        }
+        break;
+      case 1:
+        for (int i = tid; i < n; i += kBlock) {
+          RBend<T>& s = reinterpret_cast<RBend<T>*>(r)[i];
+          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+          Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+          T lbar = FIRST ? T(0) : s.lamb, ab = FIRST ? T(0) : s.ab;
+          if (bend_rev(P, st, i, n, s.th0, s.at, lbar, ab)) {
+            sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
+          }
+          s.lamb = lbar; s.ab = ab;
+        }
+        break;
+      case 2:
+        for (int i = tid; i < n; i += kBlock) {
+          RTet<T>& s = reinterpret_cast<RTet<T>*>(r)[i];
+          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+          Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+          M3<T> B;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
+          T lbD = FIRST ? T(0) : s.lbD, lbH = FIRST ? T(0) : s.lbH, eb = FIRST ? T(0) : s.eb;
+          if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, eb)) {
+            sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
+          }
+          s.lbD = lbD; s.lbH = lbH; s.eb = eb;
+        }
+        break;
+      default:
+        for (int i = tid; i < n; i += kBlock) {
+          RCon<T>& s = reinterpret_cast<RCon<T>*>(r)[i];
+          int l = (int)s.l;
+          Vec4<T> P = sX[l];
+          T lbar = FIRST ? T(0) : s.lamb;
+          Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : s.sa;
+          if (contact_rev(P, st[i], D.sph, lbar, sa)) sX[l] = P;
+          s.lamb = lbar; s.sa = sa;
+        }
+        break;
+    }
+    lds_barrier();
+  }
+  for (int i = tid; i < nv; i += kBlock) D.XB[G.pv[v0 + i]] = sX[i];
+  if (!LAST) {
+    copy16(gimg, rec, rbytes);
+    return;
+  }
+  // last reverse iteration of the substep: FP64 parameter adjoints and the
+  // per-contact sphere adjoints leave the image
+  const int* first = G.rec_first + (size_t)p * G.nset;
+  r = rec;
+  for (int q = 0; q < G.nset; ++q) {
+    const int n = cnt[q], ty = G.set_type[q], jb = first[q];
+    switch (ty) {
+      case 0: for (int i = tid; i < n; i += kBlock) D.d_acc[jb + i] += (double)reinterpret_cast<RDist<T>*>(r)[i].ab; break;
+      case 1: for (int i = tid; i < n; i += kBlock) D.b_acc[jb + i] += (double)reinterpret_cast<RBend<T>*>(r)[i].ab; break;
+      case 2: for (int i = tid; i < n; i += kBlock) D.t_acc[jb + i] += (double)reinterpret_cast<RTet<T>*>(r)[i].eb; break;
+      default: for (int i = tid; i < n; i += kBlock) D.c_sacc[jb + i] = reinterpret_cast<RCon<T>*>(r)[i].sa; break;
+    }
+    r += al32((size_t)n * rev_rec_bytes<T>(ty));
+  }
+}
+
+// copy the per-call compliances (alpha / h^2 and the tet constants) into the
+// group record images: pos[j] is the byte offset of constraint j's record,
+// -1 outside LDS groups
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const long long* __restrict__ fpos,
+                                                       const long long* __restrict__ rpos, char* __restrict__ fimg,
+                                                       char* __restrict__ rimg, const T* __restrict__ at,
+                                                       const T* __restrict__ atH, const T* __restrict__ gam) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n || fpos[j] < 0) return;
+  switch (type) {
+    case 0:
+      reinterpret_cast<SDist<T>*>(fimg + fpos[j])->at = at[j];
+      reinterpret_cast<RDist<T>*>(rimg + rpos[j])->at = at[j];
+      break;
+    case 1:
+      reinterpret_cast<SBend<T>*>(fimg + fpos[j])->at = at[j];
+      reinterpret_cast<RBend<T>*>(rimg + rpos[j])->at = at[j];
+      break;
+    default: {
+      STet<T>* f = reinterpret_cast<STet<T>*>(fimg + fpos[j]);
+      RTet<T>* r = reinterpret_cast<RTet<T>*>(rimg + rpos[j]);
+      f->atD = at[j]; f->atH = atH[j]; f->gam = gam[j];
+      r->atD = at[j]; r->atH = atH[j]; r->gam = gam[j];
+      break;
+    }
+  }
 }
 
 // ===================================================================== persistent program kernel
@@ -749,7 +1048,8 @@ __global__ __launch_bounds__(kBlock) void k_program(Dev<T> D, const Phase* __res
           rev_predict_item(D, k, R.fbar);
         break;
       case OP_SPHERE:
-        if (blockIdx.x == 0 && R.sph_out) sphere_reduce_block<T, kBlock>(D.c_sacc, P.begin, P.count, R.sph_out, sh);
+        if (blockIdx.x == 0 && R.sph_out)
+          sphere_reduce_block<T, kBlock>(D.c_sacc, D.c_order, P.begin, P.count, R.sph_out, sh);
         break;
       case OP_SET + 0: XPBD_GRID_LOOP(dist_item, Vec4<T>) break;
       case OP_SET + 1: XPBD_GRID_LOOP(bend_item, Vec4<T>) break;

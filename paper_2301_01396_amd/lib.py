@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libxpbd.so")
 XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE = range(6)
 F32, F64 = 0, 1
 FWD_FOR_ADJOINT = 1
+N_FAMILIES = 12   # kernel families reported by xpbd_profile_read
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
            "xpbd_status_string")
@@ -41,7 +42,8 @@ class ConstraintDesc(C.Structure):
 
 
 class ScheduleDesc(C.Structure):
-    _fields_ = [("n_sets", C.c_int32), ("set_type", _ip), ("set_offsets", _lp), ("set_items", _ip)]
+    _fields_ = [("n_sets", C.c_int32), ("set_type", _ip), ("set_offsets", _lp), ("set_items", _ip),
+                ("n_groups", C.c_int32), ("group_sets", _ip), ("group_patch", _ip)]
 
 
 class Options(C.Structure):
@@ -65,7 +67,8 @@ class Info(C.Structure):
     _fields_ = [("n_verts", C.c_int32), ("n_dist", C.c_int32), ("n_bend", C.c_int32), ("n_tet", C.c_int32),
                 ("n_contact", C.c_int32), ("n_sets", C.c_int32), ("projections_per_iteration", C.c_int64),
                 ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
-                ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32)]
+                ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32),
+                ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32)]
 
 
 class XPBDError(RuntimeError):
@@ -110,6 +113,16 @@ def load() -> C.CDLL:
     return _lib
 
 
+def schedule_groups(scene, use_groups: bool = True):
+    """Flatten a scene's LDS groups to (int32 [G*2], int32 [G*V])."""
+    groups = getattr(scene, "groups", None) or []
+    if not use_groups or not groups:
+        return np.zeros(2, np.int32)[:0], np.zeros(1, np.int32)[:0]
+    gs = np.asarray([[a, b] for a, b, _ in groups], np.int32).reshape(-1)
+    gp = np.ascontiguousarray(np.stack([np.asarray(pm, np.int32) for _, _, pm in groups]).reshape(-1))
+    return gs, gp
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -124,7 +137,7 @@ class Simulator:
     def __init__(self, scene, dtype: torch.dtype = torch.float32, device="cuda:0",
                  hbm_budget_bytes: int = 0, tape_mode: int = 0, tet_gamma_one: bool = False,
                  iterations: Optional[int] = None, substeps: Optional[int] = None, launch_mode: int = 0,
-                 persistent_blocks: int = 0):
+                 persistent_blocks: int = 0, use_groups: bool = True):
         self.lib = load()
         self.scene = scene
         self.dtype = dtype
@@ -141,7 +154,9 @@ class Simulator:
         cd = ConstraintDesc(scene.n_dist, dist_v.ctypes.data_as(_ip), scene.n_bend, bend_v.ctypes.data_as(_ip),
                             scene.n_tet, tet_v.ctypes.data_as(_ip), tet_nu.ctypes.data_as(_dp),
                             1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance)
-        sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip))
+        gs, gp = schedule_groups(scene, use_groups)
+        sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip),
+                          len(gs) // 2, gs.ctypes.data_as(_ip), gp.ctypes.data_as(_ip))
         o = Options()
         o.dt = scene.dt
         o.substeps = scene.substeps if substeps is None else substeps
@@ -294,8 +309,8 @@ class Simulator:
     def profile_read(self):
         """Per kernel family (2*type fwd, 2*type+1 reverse, 8/9 persistent
         forward/reverse frames): timed launches, ms, projections."""
-        la = (C.c_int64 * 10)()
-        ms = (C.c_double * 10)()
-        it = (C.c_int64 * 10)()
+        la = (C.c_int64 * N_FAMILIES)()
+        ms = (C.c_double * N_FAMILIES)()
+        it = (C.c_int64 * N_FAMILIES)()
         self._check(self.lib.xpbd_profile_read(self._ctx, la, ms, it))
         return list(la), list(ms), list(it)

@@ -69,6 +69,8 @@ class Scene:
     x0: Optional[np.ndarray] = None           # (V, 3)
     v0: Optional[np.ndarray] = None           # (V, 3)
     name: str = ""
+    # optional LDS groups: (first set, one past last set, patch id per vertex)
+    groups: List[Tuple[int, int, np.ndarray]] = field(default_factory=list)
 
     @property
     def n_verts(self) -> int:
@@ -110,12 +112,15 @@ class Scene:
 
 # ---------------------------------------------------------------- colouring
 
-def greedy_color(cverts: np.ndarray, batches: List[np.ndarray], n_verts: int) -> np.ndarray:
+def greedy_color(cverts: np.ndarray, batches: List[np.ndarray], n_verts: int,
+                 subset: bool = False) -> np.ndarray:
     """Greedy first-fit colouring, visiting ``batches`` in order.
 
     Each batch must be vertex-disjoint (independent by construction), so its
     members are coloured simultaneously; the result equals sequential
-    first-fit in (batch, member) order.  At most 64 colours.
+    first-fit in (batch, member) order.  At most 64 colours.  With
+    ``subset`` the batches may cover only some constraints; the others get
+    colour -1.
     """
     cverts = np.asarray(cverts)
     vmask = np.zeros(n_verts, dtype=np.uint64)
@@ -133,7 +138,7 @@ def greedy_color(cverts: np.ndarray, batches: List[np.ndarray], n_verts: int) ->
         bits = np.left_shift(np.uint64(1), c.astype(np.uint64))
         for col in range(cv.shape[1]):
             vmask[cv[:, col]] |= bits
-    if np.any(color < 0):
+    if not subset and np.any(color < 0):
         raise ValueError("a constraint was not in any batch")
     return color
 
@@ -302,6 +307,92 @@ def tet_box(n: int, size: float = 1.0, density: float = 1000.0,
     return sc
 
 
+# ---------------------------------------------------------------- tiled schedules
+
+def tiled_schedule(sc: Scene, coords: np.ndarray, tile: int, typed_batches, contact_last: bool = True):
+    """Replace ``sc``'s schedule by a tiled one and record its LDS groups.
+
+    ``coords`` are integer lattice coordinates of the vertices (V, d);
+    tilings are the 2^d shifts of a ``tile``-wide lattice by 0 or tile/2 per
+    axis.  Each constraint goes to the first tiling in which all its
+    vertices fall in one tile; every tiling contributes its constraints as
+    greedily coloured sets (distance, then bending, then tets), forming one
+    group with that tiling's tile id per vertex.  The contact set closes
+    the last group.  Constraints left over (none for tiles wider than twice
+    a constraint's extent) follow as ungrouped sets.
+    """
+    d = coords.shape[1]
+    V = sc.n_verts
+    shifts = [tuple((m >> a) & 1 for a in range(d)) for m in range(2 ** d)]
+    ext = coords.max(axis=0) + tile + 2
+    maps = []
+    for sh in shifts:
+        cell = (coords + np.array(sh) * (tile // 2)) // tile
+        pid = np.zeros(V, np.int64)
+        for a in range(d):
+            pid = pid * int(ext[a] // tile + 2) + cell[:, a]
+        maps.append(pid.astype(np.int32))
+    sets_t, sets_i, groups = [], [], []
+    assign = {}
+    for ty, cv, batches in typed_batches:
+        a = np.full(len(cv), -1, np.int32)
+        for t, pm in enumerate(maps):
+            if len(cv) == 0:
+                break
+            pc = pm[cv]
+            inside = np.all(pc == pc[:, :1], axis=1) & (a < 0)
+            a[inside] = t
+        assign[ty] = a
+    for t, pm in enumerate(maps):
+        first = len(sets_t)
+        for ty, cv, batches in typed_batches:
+            sel = assign[ty] == t
+            if not np.any(sel):
+                continue
+            col = greedy_color(cv, [b[sel[b]] for b in batches], V, subset=True)
+            for st in sets_from_colors(cv, col):
+                sets_t.append(ty)
+                sets_i.append(st)
+        if contact_last and sc.contact and t == len(maps) - 1:
+            sets_t.append(CONTACT)
+            sets_i.append(np.nonzero(sc.inv_mass > 0)[0].astype(np.int32))
+        if len(sets_t) > first:
+            groups.append((first, len(sets_t), pm))
+    for ty, cv, batches in typed_batches:
+        sel = assign[ty] < 0
+        if np.any(sel):
+            col = greedy_color(cv, [b[sel[b]] for b in batches], V, subset=True)
+            for st in sets_from_colors(cv, col):
+                sets_t.append(ty)
+                sets_i.append(st)
+    sc.set_type, sc.set_items, sc.groups = sets_t, sets_i, groups
+    return sc
+
+
+def tile_cloth(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
+    """Tiled schedule for an nr x nc grid cloth (4 tilings of tile x tile)."""
+    dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
+    assert np.array_equal(dist_v, sc.dist_v)
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel()], 1)
+    typed = [(DIST, sc.dist_v, dist_batches)]
+    if sc.n_bend:
+        typed.append((BEND, sc.bend_v, bend_batches))
+    return tiled_schedule(sc, coords, tile, typed)
+
+
+def tile_box(sc: Scene, n: int, tile: int = 4) -> Scene:
+    """Tiled schedule for an n^3-cube tet box (8 tilings of tile^3 cubes)."""
+    n1 = n + 1
+    ii, jj, kk = np.meshgrid(np.arange(n1), np.arange(n1), np.arange(n1), indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)
+    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    cls = ((ci % 2) * 4 + (cj % 2) * 2 + (ck % 2)).ravel()
+    tid = np.arange(sc.n_tet).reshape(-1, 5)
+    batches = [tid[np.nonzero(cls == c)[0], t] for c in range(8) for t in range(5)]
+    return tiled_schedule(sc, coords, tile, [(TET, sc.tet_v, batches)])
+
+
 # ---------------------------------------------------------------- parameter fields
 
 def lognormal(rng, mu, sigma, n):
@@ -378,10 +469,13 @@ def config_c1(n_frames: int = 60, target: bool = False) -> Scene:
     return sc
 
 
-def config_c2(n_frames: int = 30, target: bool = False, n: int = 256) -> Scene:
+def config_c2(n_frames: int = 30, target: bool = False, n: int = 256, tile: int = 16) -> Scene:
     """256x256 cloth centred at the origin with distance + bending + sphere
-    contact (c = (0, -0.35, 0), R = 0.3), dt 1/60, 4 substeps, 30 iterations."""
+    contact (c = (0, -0.35, 0), R = 0.3), dt 1/60, 4 substeps, 30 iterations.
+    tile > 0: tiled schedule (4 shifted tilings of tile x tile vertices)."""
     sc = cloth_grid(n, n, 1.0 / (n - 1), origin=(-0.5, 0.0, -0.5), contact=True)
+    if tile:
+        tile_cloth(sc, n, n, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(2 if target else 1, sc.n_dist, sc.n_bend)
     sc.tet_E = np.zeros(0)
     sc.sphere = (0.0, -0.35, 0.0, 0.3)
@@ -391,10 +485,13 @@ def config_c2(n_frames: int = 30, target: bool = False, n: int = 256) -> Scene:
     return sc
 
 
-def config_c3(n_frames: int = 20, target: bool = False, n: int = 64) -> Scene:
+def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int = 4) -> Scene:
     """64^3-cube tet box (5 tets per cube), bottom pinned, Neo-Hookean,
-    dt 1/60, 2 substeps, 20 iterations."""
+    dt 1/60, 2 substeps, 20 iterations.  tile > 0: tiled schedule (8 shifted
+    tilings of tile^3 cubes)."""
     sc = tet_box(n)
+    if tile:
+        tile_box(sc, n, tile)
     E, nu = tet_material(1, sc.n_tet)
     if target:
         E = tet_material(2, sc.n_tet, nu=nu)[0]
@@ -405,11 +502,13 @@ def config_c3(n_frames: int = 20, target: bool = False, n: int = 64) -> Scene:
     return sc
 
 
-def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4) -> Scene:
+def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 16) -> Scene:
     """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
     distance + bending, per-frame per-vertex force controls, dt 1/60,
-    2 substeps, 20 iterations."""
+    2 substeps, 20 iterations.  tile > 0: tiled schedule."""
     sc = cloth_grid(nr, nc, 1.0 / (nc - 1), pinned=(0, nc - 1))
+    if tile:
+        tile_cloth(sc, nr, nc, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)
     sc.tet_E = np.zeros(0)
     sc.f_ext = force_field(force_seed, nr, nc, n_frames)

@@ -46,7 +46,9 @@ def _create(sc, **opt):
     cd = L.ConstraintDesc(sc.n_dist, dv.ctypes.data_as(L._ip), sc.n_bend, bv.ctypes.data_as(L._ip), sc.n_tet,
                           tv.ctypes.data_as(L._ip), nu.ctypes.data_as(L._dp), 1 if sc.contact else 0,
                           sc.contact_thickness, sc.contact_compliance)
-    sd = L.ScheduleDesc(len(st), st.ctypes.data_as(L._ip), off.ctypes.data_as(L._lp), items.ctypes.data_as(L._ip))
+    gs, gp = L.schedule_groups(sc)
+    sd = L.ScheduleDesc(len(st), st.ctypes.data_as(L._ip), off.ctypes.data_as(L._lp), items.ctypes.data_as(L._ip),
+                        len(gs) // 2, gs.ctypes.data_as(L._ip), gp.ctypes.data_as(L._ip))
     o = L.Options()
     o.dt = opt.get("dt", sc.dt)
     o.substeps = opt.get("substeps", sc.substeps)
@@ -129,3 +131,53 @@ def test_generated_schedules_are_valid_colorings(maker):
         assert len(np.unique(verts)) == len(verts)
     for k, v in seen.items():
         assert np.all(v == 1)
+
+
+def test_rejects_groups_whose_constraints_span_patches():
+    sc = scenes.small_cloth(n=20)
+    scenes.tile_cloth(sc, 20, 20, tile=8)
+    a, b, pm = sc.groups[0]
+    bad = pm.copy()
+    bad[sc.dist_v[sc.set_items[a][0], 0]] += 1       # split the first constraint's vertices
+    sc.groups[0] = (a, b, bad)
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "spans two patches" in msg
+    sc = scenes.small_cloth(n=20)
+    scenes.tile_cloth(sc, 20, 20, tile=8)
+    sc.groups.append((0, 2, sc.groups[0][2]))          # overlaps group 0
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "overlap" in msg
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.tile_cloth(scenes.small_cloth(n=40), 40, 40, 16),
+                                   lambda: scenes.tile_box(scenes.small_tets(n=8), 8, 4)])
+def test_tiled_schedules_are_valid_and_grouped(maker):
+    sc = maker()
+    st, off, items = sc.schedule_arrays()
+    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v}
+    seen = {k: np.zeros(len(v), int) for k, v in cv.items()}
+    for s in range(len(st)):
+        it = items[off[s]:off[s + 1]]
+        verts = it[:, None] if st[s] == scenes.CONTACT else cv[st[s]][it]
+        if st[s] != scenes.CONTACT:
+            seen[st[s]][it] += 1
+        assert len(np.unique(verts)) == verts.size
+    for v in seen.values():
+        assert np.all(v == 1)
+    covered = set()
+    for a, b, pm in sc.groups:
+        for s in range(a, b):
+            covered.add(s)
+            it = items[off[s]:off[s + 1]]
+            verts = it[:, None] if st[s] == scenes.CONTACT else cv[st[s]][it]
+            pc = pm[verts]
+            assert np.all(pc == pc[:, :1])
+    assert covered == set(range(len(st)))
+
+
+def test_profile_family_count_matches_header():
+    txt = open(os.path.join(ROOT, "include", "xpbd.h")).read()
+    m = re.search(r"xpbd_profile_read\(xpbd_ctx ctx, int64_t launches\[(\d+)\], double ms\[(\d+)\], "
+                  r"int64_t items\[(\d+)\]\)", txt)
+    assert m and len(set(m.groups())) == 1
+    assert int(m.group(1)) == L.N_FAMILIES

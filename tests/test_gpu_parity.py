@@ -137,6 +137,45 @@ def test_plain_and_persistent_launches_agree_bitwise(dtype):
     compare(sc, ref, outs[1], *tol)
 
 
+def _tiled_cloth(n=40, tile=16, frames=2, S=2, K=3):
+    sc = scenes.small_cloth(n=n, frames=frames, substeps=S, iterations=K)
+    return scenes.tile_cloth(sc, n, n, tile)
+
+
+def _tiled_tets(n=6, tile=4, frames=2):
+    sc = scenes.small_tets(n=n, frames=frames, substeps=2, iterations=3)
+    return scenes.tile_box(sc, n, tile)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("kind", ["cloth", "tets"])
+def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
+    """LDS group launches compute exactly what one launch per set computes
+    on the same (tiled) schedule; both match the FP64 reference."""
+    sc = _tiled_cloth() if kind == "cloth" else _tiled_tets()
+    ref = reference_case(sc, 2, n_threads=8, noise=0.01 if kind == "cloth" else 1e-3)
+    a_sim = _sim(sc, dtype)
+    b_sim = _sim(sc, dtype, use_groups=False)
+    ia, ib = a_sim.info(), b_sim.info()
+    assert ia["n_groups_lds"] == ia["n_groups"] == len(sc.groups) and ib["n_groups"] == 0
+    a = gpu_case(a_sim, 2, ref)
+    b = gpu_case(b_sim, 2, ref)
+    assert np.array_equal(a["x_frames"], b["x_frames"])
+    for k, v in b["grads"].items():
+        assert np.array_equal(a["grads"][k], v), k
+    tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
+    compare(sc, ref, a, *tol)
+
+
+def test_oversized_groups_fall_back_to_per_set_launches():
+    sc = _tiled_cloth(n=130, tile=128, frames=1, S=1, K=2)
+    sim = _sim(sc, "f64")
+    info = sim.info()
+    assert info["n_groups"] > 0 and info["n_groups_lds"] < info["n_groups"]
+    ref = reference_case(sc, 1, n_threads=8)
+    compare(sc, ref, gpu_case(sim, 1, ref), 1e-10, 1e-8)
+
+
 def test_goal_matches_reference():
     sc = scenes.small_cloth(n=6, frames=3, substeps=1, iterations=2)
     ref = reference_case(sc, 3, mask=np.array([1, 0, 1], bool))
