@@ -485,7 +485,7 @@ def config_c2(n_frames: int = 30, target: bool = False, n: int = 256, tile: int 
     return sc
 
 
-def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int = 4) -> Scene:
+def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int = 0) -> Scene:
     """64^3-cube tet box (5 tets per cube), bottom pinned, Neo-Hookean,
     dt 1/60, 2 substeps, 20 iterations.  tile > 0: tiled schedule (8 shifted
     tilings of tile^3 cubes)."""
@@ -502,7 +502,7 @@ def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int =
     return sc
 
 
-def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 16) -> Scene:
+def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 0) -> Scene:
     """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
     distance + bending, per-frame per-vertex force controls, dt 1/60,
     2 substeps, 20 iterations.  tile > 0: tiled schedule."""

@@ -1,0 +1,231 @@
+"""Continuous-batching request loop for rollout and gradient requests.
+
+Requests (a mesh with its parameters, a frame count and optionally a goal
+whose gradient is wanted) arrive at any time.  The server admits a request
+when a slot is free and its device-memory estimate fits the HBM budget next
+to the requests already resident; admitted requests run concurrently, each
+on its own HIP stream, so their kernels overlap on the device.  A request
+that arrives while others run is admitted as soon as a slot and memory free
+up.  Every request's state stays on the device until its result is copied
+out.  Latency is measured from arrival to result.
+
+All simulation work runs in the library's kernels; this module only
+schedules calls.  Each request gets its own context, so its result does not
+depend on what else is running (bitwise).
+"""
+from __future__ import annotations
+
+import heapq
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Dict, List, Optional
+
+import numpy as np
+import torch
+
+from .lib import Simulator
+
+
+@dataclass
+class Request:
+    rid: int
+    scene: Any                      # scenes.Scene
+    n_frames: int
+    adjoint: bool = False
+    targets: Optional[np.ndarray] = None   # (F, V, 3) goal targets; goal on the last frame
+    arrival: float = 0.0            # seconds after the start of the run
+    # filled by the server
+    admitted: float = -1.0
+    done: float = -1.0
+    slot: int = -1
+    result: Dict[str, np.ndarray] = field(default_factory=dict)
+    projections: int = 0
+    device_bytes: int = 0
+
+
+def estimate_bytes(sc, n_frames: int, adjoint: bool, dtype_bytes: int = 4) -> int:
+    """Upper estimate of a request's device memory (records, state,
+    checkpoints, adjoint working set and one frame of the adjoint's record)."""
+    V, nd, nb, nt = sc.n_verts, sc.n_dist, sc.n_bend, sc.n_tet
+    t = dtype_bytes
+    rec = nd * (8 + 6 * t) + nb * (16 + 6 * t) + nt * (16 + 17 * t) + V * (8 + 5 * t)
+    state = V * 16 * t
+    ck = 2 * n_frames * V * 4 * t
+    out = n_frames * V * 3 * t * 2
+    adj = 0
+    if adjoint:
+        adj = V * 8 * t + (nd + nb + nt) * (2 * t + 8)
+        adj += sc.substeps * sc.iterations * (nd * 4 * t + nb * 10 * t + nt * 12 * t + V * 4 * t)
+    return int(1.15 * (rec + state + ck + out + adj)) + (8 << 20)
+
+
+class Server:
+    """Runs requests with ``slots`` concurrent streams within ``hbm_budget``."""
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 64 << 30, device="cuda:0",
+                 dtype: torch.dtype = torch.float32, record_whole_rollout: bool = True):
+        self.slots = slots
+        self.budget = hbm_budget
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.record = record_whole_rollout
+        self._lock = threading.Condition()
+        self._pending: List = []          # heap of (arrival, rid, request)
+        self._in_use = 0
+        self._free_slots = list(range(slots))
+        self._finished: List[Request] = []
+        self._closed = False
+        self._t0 = 0.0
+        self._queue_depth: List[int] = []
+        self._errors: List[str] = []
+
+    # ---------------------------------------------------------------- execution
+    def _run_one(self, req: Request, stream: torch.cuda.Stream):
+        sc = req.scene
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            sim = Simulator(sc, dtype=self.dtype, device=self.device,
+                            tape_mode=0 if self.record else 1)
+            try:
+                xf, xe, ve = sim.forward(req.n_frames, for_adjoint=req.adjoint)
+                res = {}
+                if req.adjoint:
+                    mask = np.zeros(req.n_frames, np.uint8)
+                    mask[-1] = 1
+                    tg = sim.tensor(req.targets)
+                    loss, dL = sim.goal_l2(xf, tg, mask)
+                    g = sim.adjoint(dL, mask)
+                    res["loss"] = loss
+                    res.update({k: v for k, v in g.items()})
+                res["x_final"] = xe
+                stream.synchronize()
+                req.result = {k: (v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else v)
+                              for k, v in res.items()}
+                req.projections = sc.projections_per_rollout(req.n_frames) * (2 if req.adjoint else 1)
+            finally:
+                sim.close()
+
+    def _make_stream(self):
+        return torch.cuda.Stream(device=self.device)      # default priority
+
+    def _worker(self, slot: int):
+        stream = self._make_stream()
+        while True:
+            with self._lock:
+                while True:
+                    if self._closed and not self._pending:
+                        return
+                    now = time.perf_counter() - self._t0
+                    admissible = None
+                    if self._pending and self._pending[0][0] <= now:
+                        arr, rid, req = self._pending[0]
+                        if self._in_use + req.device_bytes <= self.budget or self._in_use == 0:
+                            admissible = heapq.heappop(self._pending)[2]
+                    if admissible is not None:
+                        req = admissible
+                        self._in_use += req.device_bytes
+                        self._queue_depth.append(sum(1 for a, _, _ in self._pending if a <= now))
+                        break
+                    timeout = None
+                    if self._pending and self._pending[0][0] > now:
+                        timeout = self._pending[0][0] - now
+                    self._lock.wait(timeout if timeout is not None else 0.05)
+            req.admitted = time.perf_counter() - self._t0
+            req.slot = slot
+            try:
+                self._run_one(req, stream)
+            except Exception as e:        # report, keep serving the others
+                self._errors.append(f"request {req.rid}: {e}")
+            req.done = time.perf_counter() - self._t0
+            with self._lock:
+                self._in_use -= req.device_bytes
+                self._finished.append(req)
+                self._lock.notify_all()
+
+    def run(self, requests: List[Request]) -> Dict[str, Any]:
+        """Serve ``requests`` (arrival times relative to now); returns a report."""
+        for r in requests:
+            r.device_bytes = estimate_bytes(r.scene, r.n_frames, r.adjoint,
+                                            8 if self.dtype == torch.float64 else 4)
+        self._pending = [(r.arrival, r.rid, r) for r in requests]
+        heapq.heapify(self._pending)
+        self._finished = []
+        self._closed = True
+        self._queue_depth = []
+        if torch.cuda.is_available():
+            torch.cuda.synchronize(self.device)
+        self._t0 = time.perf_counter()
+        threads = [threading.Thread(target=self._worker, args=(s,), daemon=True) for s in range(self.slots)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        wall = time.perf_counter() - self._t0
+        if self._errors:
+            raise RuntimeError("; ".join(self._errors))
+        return report(self._finished, wall, self._queue_depth)
+
+
+def report(done: List[Request], wall: float, depth: List[int]) -> Dict[str, Any]:
+    lat = np.array([r.done - r.arrival for r in done])
+    proj = sum(r.projections for r in done)
+    return {"requests": len(done), "wall_s": wall,
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_latency_s": float(lat.mean()) if len(lat) else None,
+            "throughput_rps": len(done) / wall if wall > 0 else None,
+            "projections_per_s": proj / wall if wall > 0 else None,
+            "max_queue_depth": int(max(depth)) if depth else 0,
+            "max_concurrent": max_concurrency(done)}
+
+
+def max_concurrency(done: List[Request]) -> int:
+    ev = []
+    for r in done:
+        ev.append((r.admitted, 1))
+        ev.append((r.done, -1))
+    ev.sort()
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def make_mix(n: int, qps: float, seed: int = 6, frames=(30, 120), size_mu=np.log(16000), size_sigma=1.0,
+             vmin=1000, vmax=250_000, substeps: int = 2, iterations: int = 20, frames_scale: float = 1.0):
+    """Serving mix: Poisson arrivals at ``qps``; half grid cloths, half tet
+    boxes; ln V ~ N(size_mu, size_sigma) clipped to [vmin, vmax]; frames
+    ~ U{frames}; half the requests want the gradient.  Draw order: arrival
+    gaps, kind, size, frames, adjoint flag, then per-request parameter
+    seeds."""
+    from . import scenes
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, n)
+    kind = rng.integers(0, 2, n)
+    sizes = np.clip(np.exp(rng.normal(size_mu, size_sigma, n)), vmin, vmax)
+    fr = rng.integers(frames[0], frames[1] + 1, n)
+    adj = rng.integers(0, 2, n)
+    pseed = rng.integers(0, 2 ** 31, n)
+    reqs = []
+    t = 0.0
+    for i in range(n):
+        t += gaps[i]
+        if kind[i] == 0:
+            m = max(4, int(round(np.sqrt(sizes[i]))))
+            sc = scenes.cloth_grid(m, m, 1.0 / (m - 1), origin=(-0.5, 0.0, -0.5), pinned=(0, m - 1))
+            sc.dist_alpha, sc.bend_alpha = scenes.cloth_alpha(int(pseed[i]), sc.n_dist, sc.n_bend)
+            sc.tet_E = np.zeros(0)
+        else:
+            m = max(1, int(round(sizes[i] ** (1.0 / 3.0))) - 1)
+            sc = scenes.tet_box(m)
+            sc.tet_E, sc.tet_nu = scenes.tet_material(int(pseed[i]), sc.n_tet)
+            sc.dist_alpha, sc.bend_alpha = np.zeros(0), np.zeros(0)
+        sc.dt, sc.substeps, sc.iterations = 1.0 / 60.0, substeps, iterations
+        F = max(1, int(fr[i] * frames_scale))
+        sc.n_frames = F
+        tg = None
+        if adj[i]:
+            tg = np.repeat((sc.rest + np.array([0.0, -0.05, 0.0]))[None], F, axis=0)
+        reqs.append(Request(rid=i, scene=sc, n_frames=F, adjoint=bool(adj[i]), targets=tg, arrival=t))
+    return reqs
