@@ -50,6 +50,30 @@ def alg_bytes(fam: int, tsz: int, recording: bool = False) -> float:
     return ib + words * tsz
 
 
+# LDS group kernels: words of the record image read and written per
+# projection (forward: rest/theta0, at, lambda + packed slots; reverse adds
+# lambda_bar and the compliance adjoint), plus the record of inputs
+GROUP_REC_WORDS = {0: (4, 5), 2: (5, 6), 4: (8, 8.5), 6: (2, 8)}
+
+
+def group_bytes(sc, reverse: bool, tsz: int, recording: bool, n_groups: int) -> float:
+    """Average algorithmic bytes per projection of an LDS group launch:
+    record image read + write, record of inputs (written by the forward
+    when recording, read by the reverse), and each group's vertex tiles read
+    and written once per launch."""
+    n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
+         6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
+    tot = max(sum(n.values()), 1)
+    b = 0.0
+    for f, cnt in n.items():
+        words = 2 * GROUP_REC_WORDS[f][1 if reverse else 0]
+        if reverse or recording:
+            words += TAPE_WORDS[f]
+        b += cnt * words * tsz
+    b += n_groups * sc.n_verts * 2 * 4 * tsz
+    return b / tot
+
+
 def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
     """Average algorithmic bytes per projection over the workload's mix (the
     persistent frame kernel runs every set type)."""
@@ -77,7 +101,7 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str, tile: int = -1):
+def make_workload(name: str, tile: int = -1, frames: int = 0):
     from paper_2301_01396_amd import scenes
     kw = {} if tile < 0 else {"tile": tile}
     if name == "c1":
@@ -87,6 +111,8 @@ def make_workload(name: str, tile: int = -1):
     if name == "c3":
         return scenes.config_c3(**kw), scenes.config_c3(target=True, **kw)
     if name == "c4":
+        if frames:
+            kw["n_frames"] = frames
         return scenes.config_c4(**kw), None
     raise SystemExit(f"unknown workload {name}")
 
@@ -139,20 +165,25 @@ def serve_bench(args):
     import torch
     from paper_2301_01396_amd import serve
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    mix = lambda qps: serve.make_mix(args.requests, qps=qps, seed=6)
-    reqs = mix(1.0)
+    reqs = serve.make_mix(args.requests, qps=1.0, seed=6)
+    base = [r.arrival for r in reqs]     # Poisson arrivals at 1 request/s; rescaled per rate
+
+    def at_rate(qps):
+        for r, a in zip(reqs, base):
+            r.arrival = a / qps
+            r.admitted = r.done = -1.0
+            r.result = {}
+        return reqs
+
     log(f"serving mix: {len(reqs)} requests, {sum(r.scene.n_verts for r in reqs)} vertices in total")
     warm = serve.make_mix(2, qps=100.0, seed=7, vmax=4000, frames_scale=0.1)
-    serve.Server(slots=2).run(warm)
-    for r in reqs:
-        r.arrival = 0.0
-    seq = serve.Server(slots=1).run(reqs)
+    serve.Server(slots=2, record_whole_rollout=False).run(warm)
+    seq = serve.Server(slots=1, record_whole_rollout=False).run(at_rate(1e9))
     cap = seq["throughput_rps"]
     log(f"sequential: {seq}")
     rows = []
     for frac in (0.5, 1.0, 1.5, 3.0):
-        rs = mix(frac * cap)
-        rep = serve.Server(slots=args.slots).run(rs)
+        rep = serve.Server(slots=args.slots, record_whole_rollout=False).run(at_rate(frac * cap))
         rep["qps"] = frac * cap
         rep["qps_over_sequential_capacity"] = frac
         rows.append(rep)
@@ -177,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=24, help="serving mix size (c5)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run a plain device copy kernel over this many bytes (counter calibration)")
     ap.add_argument("--slots", type=int, default=8, help="concurrent requests (c5)")
     ap.add_argument("--frames", type=int, default=0, help="override frame count (0 = the workload's)")
     ap.add_argument("--profile-stride", type=int, default=7,
@@ -197,11 +230,22 @@ def main():
     from paper_2301_01396_amd import autograd as AG
     from paper_2301_01396_amd.lib import Simulator
 
+    if args.calibrate_copy:
+        # reads and writes exactly calibrate_copy bytes per launch
+        n = args.calibrate_copy // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                          "launches": 5}), flush=True)
+        return
     if args.workload == "c5":
         return serve_bench(args)
 
     dev = torch.device("cuda:0")
-    sc, tg = make_workload(args.workload, args.tile)
+    sc, tg = make_workload(args.workload, args.tile, args.frames)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
@@ -293,10 +337,12 @@ def main():
     kernels = {}
     tsz = 8 if dtype == torch.float64 else 4
     def fam_bytes(fam):
-        if fam in (8, 10):
+        if fam == 8:
             return mix_bytes(sc, False, tsz, recording)
-        if fam in (9, 11):
+        if fam == 9:
             return mix_bytes(sc, True, tsz, recording)
+        if fam in (10, 11):
+            return group_bytes(sc, fam == 11, tsz, recording, max(info["n_groups_lds"], 1))
         return alg_bytes(fam, tsz, recording)
 
     for fam in range(12):
@@ -315,14 +361,17 @@ def main():
     if tot > 0:
         dom = max(range(12), key=lambda f: ms[f])
         k = kernels[FAMILY[dom]]
-        traffic = None
+        traffic = traffic_gbs = None
         tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
         if os.path.exists(tf):
             rec = json.load(open(tf)).get(f"{args.workload}:{KERNEL_SYMBOL[dom]}")
             if rec and rec.get("csrc_sha") == csrc_hash():
                 traffic = rec["bytes_per_dispatch_scaled"] * k["items_per_launch"] / rec["items_per_dispatch"]
+                traffic_gbs = round(traffic / (k["avg_us"] * 1e-6) / 1e9, 1)
         roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": k["alg_GBps"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(k["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_GBps": traffic_gbs,
                 "bytes_per_projection": round(fam_bytes(dom), 1),
                 "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"]}
 

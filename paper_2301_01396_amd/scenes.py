@@ -512,6 +512,7 @@ def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: in
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)
     sc.tet_E = np.zeros(0)
     sc.f_ext = force_field(force_seed, nr, nc, n_frames)
+    sc.n_frames = n_frames
     sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 2, 20, n_frames
     sc.name = f"cloth{nc}x{nr}_dist_bend_force"
     return sc
