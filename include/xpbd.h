@@ -234,6 +234,85 @@ xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 xpbd_status xpbd_profile_enable(xpbd_ctx ctx, int32_t on);
 xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[12], double ms[12], int64_t items[12]);
 
+/* ---------------------------------------------------------------- packs
+ * A pack runs jobs on many contexts (meshes of any size and constraint mix)
+ * together: each round advances every job in it by one frame of its forward
+ * rollout or of its adjoint, and every launch of the round serves the same
+ * step (substep, iteration, position in the schedule) of all of them, so
+ * one launch covers many meshes.  Jobs join at the next round after
+ * xpbd_pack_add and leave when done; each job's results are bitwise those of
+ * running its context alone with xpbd_forward, xpbd_goal_l2 and
+ * xpbd_adjoint (the pack always uses one launch per set, which computes what
+ * every launch_mode computes).  With XPBD_PACK_GRAPHS a round's launches are
+ * captured once in a HIP graph while the pack's jobs and phases stay the
+ * same, and replayed for every further round.
+ *
+ * A job is a forward rollout of `n_frames` frames from (x0, v0) with
+ * `params` (as xpbd_forward), writing x_frames / x_final / v_final (any may
+ * be NULL; x_frames is required with an adjoint).  If `targets` is not NULL
+ * the job then computes the goal of xpbd_goal_l2 (frames with frame_mask[f]
+ * != 0; NULL = all) into *loss (device double, may be NULL) and its exact
+ * adjoint into `grads` (as xpbd_adjoint, with dLdv_final as its dLdv_final).
+ * The adjoint replays the forward's record of every projection if it fits
+ * the context's budget (tape_mode 0 or 3), else recomputes each frame from
+ * its checkpoint (tape_mode 0 or 1); tape_mode 2 is not available in packs.
+ *
+ * Every context in a pack must have the pack's dtype and the same substeps
+ * and iterations as the pack's first job; a context serves one job at a
+ * time.  Device pointers of a job must stay valid until the job is reported
+ * done and the stream has reached that point.  Calls on one pack are ordered
+ * on the stream passed to them; use one stream per pack.  The context's
+ * earlier forward record is invalidated by a job (xpbd_adjoint afterwards
+ * returns XPBD_ERR_STATE). */
+typedef struct xpbd_pack_s* xpbd_pack;
+
+typedef struct {
+  const void* x0;             /* device [V][3] */
+  const void* v0;             /* device [V][3] */
+  xpbd_params params;
+  int32_t n_frames;           /* F >= 1 */
+  void* x_frames;             /* device [F][V][3] or NULL */
+  void* x_final;              /* device [V][3] or NULL */
+  void* v_final;              /* device [V][3] or NULL */
+  const void* targets;        /* device [F][V][3] goal targets, NULL = no adjoint */
+  const uint8_t* frame_mask;  /* host [F] (copied), NULL = every frame */
+  const void* dLdv_final;     /* device [V][3] or NULL */
+  double* loss;               /* device double or NULL */
+  xpbd_grads grads;
+} xpbd_job;
+
+typedef struct {
+  int32_t active_jobs;        /* jobs in the pack now */
+  int64_t rounds;             /* rounds run so far */
+  int64_t launches;           /* kernel launches issued directly */
+  int64_t graph_launches;     /* rounds replayed from a captured graph */
+  int64_t graph_captures;     /* graphs captured (once per change of jobs or phases) */
+  int32_t last_round_launches;/* launches in the current round plan */
+} xpbd_pack_stats;
+
+#define XPBD_PACK_GRAPHS 1
+/* Errors: XPBD_ERR_INVALID (bad dtype or flags), XPBD_ERR_OOM. */
+xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, xpbd_pack* out);
+/* Synchronises the pack's last stream, then frees the pack (not its contexts). */
+xpbd_status xpbd_pack_destroy(xpbd_pack pack);
+/* Validate a job, gather its parameters (synchronises `stream` to check
+ * them), allocate its context's checkpoints and record, load (x0, v0), and
+ * queue it for the next round.  *job_id (> 0) identifies it in
+ * xpbd_pack_run.  Errors: XPBD_ERR_INVALID (mismatched dtype / substeps /
+ * iterations, context already in a job, bad job), XPBD_ERR_NONFINITE,
+ * XPBD_ERR_OOM (record does not fit), XPBD_ERR_HIP. */
+xpbd_status xpbd_pack_add(xpbd_pack pack, xpbd_ctx ctx, const xpbd_job* job, void* stream, int64_t* job_id);
+/* Run up to max_rounds rounds on `stream`, returning after the first round
+ * in which any job finished.  The ids of finished jobs (at most `cap`; the
+ * rest are reported by the next call) are written to done_ids and their
+ * count to *n_done; their outputs are complete once the stream reaches the
+ * end of this call.  Errors: XPBD_ERR_HIP (a kernel or graph failure; the
+ * pack's jobs are then invalid), XPBD_ERR_INVALID. */
+xpbd_status xpbd_pack_run(xpbd_pack pack, int32_t max_rounds, void* stream, int64_t* done_ids, int32_t cap,
+                          int32_t* n_done);
+xpbd_status xpbd_pack_get_stats(xpbd_pack pack, xpbd_pack_stats* stats);
+const char* xpbd_pack_last_error(xpbd_pack pack);
+
 const char* xpbd_last_error(xpbd_ctx ctx);
 const char* xpbd_status_string(xpbd_status s);
 

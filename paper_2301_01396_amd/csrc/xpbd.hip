@@ -16,6 +16,7 @@
 
 #include "../../include/xpbd.h"
 #include "xpbd_kernels.hpp"
+#include "xpbd_pack_kernels.hpp"
 
 using namespace xpbd;
 
@@ -144,6 +145,11 @@ struct xpbd_ctx_s {
   unsigned* bar = nullptr;
   int* abort_flag = nullptr;
 
+  // packs: the context serves at most one job at a time
+  bool in_pack = false;
+  uint8_t* pack_mask = nullptr;   // device [F] goal frames of the current job
+  int pack_mask_cap = 0;
+
   // forward bookkeeping for the adjoint
   bool have_forward = false;
   bool fwd_recorded = false;
@@ -267,6 +273,18 @@ void prof_end(xpbd_ctx c, hipStream_t st, xpbd_ctx_s::Ev& e, bool on) {
 }
 
 // ===================================================================== launches
+
+// per-frame checkpoints of (x, v) for F frames
+void ensure_checkpoints(xpbd_ctx c, int F) {
+  if (c->ck_frames >= F) return;
+  const size_t vb = (size_t)c->V * 4 * c->tsz;
+  c->release(c->ckX);
+  c->release(c->ckV);
+  c->ck_frames = 0;
+  c->ckX = c->alloc((size_t)F * vb);
+  c->ckV = c->alloc((size_t)F * vb);
+  c->ck_frames = F;
+}
 
 template <class T> struct Ops {
   using V4 = Vec4<T>;
@@ -600,14 +618,7 @@ template <class T> struct Ops {
                       void* x_final, void* v_final, bool record, hipStream_t st) {
     const int V = c->V;
     const size_t vb = (size_t)V * sizeof(V4);
-    if (c->ck_frames < F) {
-      c->release(c->ckX);
-      c->release(c->ckV);
-      c->ck_frames = 0;
-      c->ckX = c->alloc((size_t)F * vb);
-      c->ckV = c->alloc((size_t)F * vb);
-      c->ck_frames = F;
-    }
+    ensure_checkpoints(c, F);
     gather_params(c, p, st);
     Dev<T> D = dev(c, p->sphere);
     k_pack<T><<<nblocks(V), kBlock, 0, st>>>((const T*)x0, (const T*)v0, (const T*)c->w, (V4*)c->X, (V4*)c->Vv, V);
@@ -642,17 +653,10 @@ template <class T> struct Ops {
   static void adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx, const uint8_t* mask, const void* dLdv,
                       const xpbd_grads* out, int mode, hipStream_t st) {
     const int V = c->V, F = c->fwd_frames, S = c->S;
-    // gradients wrt the per-constraint parameters accumulate in FP64
-    fill<double>(c->dist_acc, 0.0, c->n_dist, st);
-    fill<double>(c->bend_acc, 0.0, c->n_bend, st);
-    fill<double>(c->tet_acc, 0.0, c->n_tet, st);
-    if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
-    if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
     // parameters used by the recomputation (same as the forward's)
     gather_params(c, p, st);
+    begin_adjoint(c, F, dLdv, out, st);
     Dev<T> D = dev(c, p->sphere);
-    k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
-    check_launch();
     const size_t frame_tape = (size_t)S * c->K * c->iter_tape_bytes;
     for (int f = F - 1; f >= 0; --f) {
       if (dLdx && (!mask || mask[f])) {
@@ -683,6 +687,27 @@ template <class T> struct Ops {
         }
       }
     }
+    finish_adjoint(c, p, out, st);
+  }
+
+  // adjoint state and gradient outputs before the first reversed frame:
+  // FP64 accumulators of the per-constraint parameter gradients, sphere and
+  // force gradients zeroed, xbar = 0, vbar = dL/dv_final
+  static void begin_adjoint(xpbd_ctx c, int F, const void* dLdv, const xpbd_grads* out, hipStream_t st) {
+    const int V = c->V;
+    fill<double>(c->dist_acc, 0.0, c->n_dist, st);
+    fill<double>(c->bend_acc, 0.0, c->n_bend, st);
+    fill<double>(c->tet_acc, 0.0, c->n_tet, st);
+    if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
+    if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
+    k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
+    check_launch();
+  }
+
+  // after the last reversed frame: dL/dx0, dL/dv0, and the parameter
+  // gradients in the caller's constraint order
+  static void finish_adjoint(xpbd_ctx c, const xpbd_params* p, const xpbd_grads* out, hipStream_t st) {
+    const int V = c->V;
     if (out->x0) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->XB, (T*)out->x0, V);
     if (out->v0) k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->VB, (T*)out->v0, V);
     check_launch();
@@ -699,16 +724,21 @@ template <class T> struct Ops {
     check_launch();
   }
 
-  static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, int F, double* loss,
-                   void* dLdx, hipStream_t st) {
-    const size_t n = (size_t)3 * c->V;
-    const size_t nb = nblocks(n);
+  static void ensure_parts(xpbd_ctx c, int F) {
+    const size_t nb = nblocks((size_t)3 * c->V);
     if (c->parts_n < nb * F) {
       void* pp = c->parts;
       c->release(pp);
       c->parts = (double*)c->alloc(nb * F * sizeof(double));
       c->parts_n = nb * F;
     }
+  }
+
+  static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, int F, double* loss,
+                   void* dLdx, hipStream_t st) {
+    const size_t n = (size_t)3 * c->V;
+    const size_t nb = nblocks(n);
+    ensure_parts(c, F);
     for (int f = 0; f < F; ++f) {
       int on = mask ? (mask[f] != 0) : 1;
       k_goal<T><<<nb, kBlock, 0, st>>>((const T*)xf + f * n, (const T*)tg + f * n,
@@ -1330,6 +1360,10 @@ xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* 
 
 xpbd_status xpbd_destroy(xpbd_ctx ctx) {
   if (!ctx) return XPBD_ERR_INVALID;
+  if (ctx->in_pack) {
+    ctx->err = "destroy: the context is serving a job of a pack";
+    return XPBD_ERR_STATE;
+  }
   delete ctx;
   return XPBD_OK;
 }
@@ -1338,6 +1372,7 @@ xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_
                          void* x_frames, void* x_final, void* v_final, int32_t flags, void* stream) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
+    if (c->in_pack) fail(XPBD_ERR_STATE, "forward: the context is serving a job of a pack");
     if (!p || !x0 || !v0 || n_frames < 1) fail(XPBD_ERR_INVALID, "forward: null argument or n_frames < 1");
     if (c->n_tet && !p->tet_E) fail(XPBD_ERR_INVALID, "forward: tet_E required");
     if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
@@ -1368,6 +1403,7 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
                          const void* dLdv_final, const xpbd_grads* out, void* stream) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
+    if (c->in_pack) fail(XPBD_ERR_STATE, "adjoint: the context is serving a job of a pack");
     if (!p || !out) fail(XPBD_ERR_INVALID, "adjoint: null argument");
     if (!c->have_forward) fail(XPBD_ERR_STATE, "adjoint: no preceding forward on this context");
     const xpbd_params& q = c->fwd_params;
@@ -1470,3 +1506,5 @@ const char* xpbd_status_string(xpbd_status s) {
 }
 
 }  // extern "C"
+
+#include "xpbd_pack_host.hpp"

@@ -21,9 +21,11 @@ XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_
 F32, F64 = 0, 1
 FWD_FOR_ADJOINT = 1
 N_FAMILIES = 12   # kernel families reported by xpbd_profile_read
+PACK_GRAPHS = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
-           "xpbd_status_string")
+           "xpbd_status_string", "xpbd_pack_create", "xpbd_pack_destroy", "xpbd_pack_add", "xpbd_pack_run",
+           "xpbd_pack_get_stats", "xpbd_pack_last_error")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -71,6 +73,17 @@ class Info(C.Structure):
                 ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32)]
 
 
+class Job(C.Structure):
+    _fields_ = [("x0", _vp), ("v0", _vp), ("params", Params), ("n_frames", C.c_int32), ("x_frames", _vp),
+                ("x_final", _vp), ("v_final", _vp), ("targets", _vp), ("frame_mask", C.POINTER(C.c_uint8)),
+                ("dLdv_final", _vp), ("loss", _vp), ("grads", Grads)]
+
+
+class PackStats(C.Structure):
+    _fields_ = [("active_jobs", C.c_int32), ("rounds", C.c_int64), ("launches", C.c_int64),
+                ("graph_launches", C.c_int64), ("graph_captures", C.c_int64), ("last_round_launches", C.c_int32)]
+
+
 class XPBDError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"xpbd status {status}: {msg}")
@@ -109,6 +122,18 @@ def load() -> C.CDLL:
         lib.xpbd_last_error.argtypes = [_vp]
         lib.xpbd_status_string.restype = C.c_char_p
         lib.xpbd_status_string.argtypes = [C.c_int]
+        lib.xpbd_pack_create.restype = C.c_int
+        lib.xpbd_pack_create.argtypes = [C.c_int, C.c_int32, C.POINTER(_vp)]
+        lib.xpbd_pack_destroy.restype = C.c_int
+        lib.xpbd_pack_destroy.argtypes = [_vp]
+        lib.xpbd_pack_add.restype = C.c_int
+        lib.xpbd_pack_add.argtypes = [_vp, _vp, C.POINTER(Job), _vp, _lp]
+        lib.xpbd_pack_run.restype = C.c_int
+        lib.xpbd_pack_run.argtypes = [_vp, C.c_int32, _vp, _lp, C.c_int32, _ip]
+        lib.xpbd_pack_get_stats.restype = C.c_int
+        lib.xpbd_pack_get_stats.argtypes = [_vp, C.POINTER(PackStats)]
+        lib.xpbd_pack_last_error.restype = C.c_char_p
+        lib.xpbd_pack_last_error.argtypes = [_vp]
         _lib = lib
     return _lib
 
@@ -218,12 +243,7 @@ class Simulator:
         return t
 
     # ------------------------------------------------------------------ API
-    def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
-                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False):
-        """Roll out; returns (x_frames or None, x_final, v_final) on the device.
-
-        ``for_adjoint``: an adjoint will follow; the library may keep the record
-        of every projection now so the adjoint needs no recomputation."""
+    def _inputs(self, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere):
         sc = self.scene
         V = sc.n_verts
         x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
@@ -233,24 +253,9 @@ class Simulator:
         te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet,)) if sc.n_tet else None
         fe = f_ext if f_ext is not None else sc.f_ext
         fe = self._arg(fe, (n_frames, V, 3)) if fe is not None else None
-        p = self._params(da, ba, te, fe, sphere)
-        xf = None
-        if frames:
-            xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
-                                                                           device=self.device)
-        xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)
-        ve = torch.empty((V, 3), dtype=self.dtype, device=self.device)
-        rc = self.lib.xpbd_forward(self._ctx, _ptr(x0), _ptr(v0), C.byref(p), n_frames, _ptr(xf), _ptr(xe),
-                                   _ptr(ve), FWD_FOR_ADJOINT if for_adjoint else 0, _stream_ptr(self.device))
-        self._check(rc)
-        self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames)
-        return xf, xe, ve
+        return x0, v0, da, ba, te, fe, self._params(da, ba, te, fe, sphere)
 
-    def adjoint(self, dLdx_frames=None, frame_mask=None, dLdv_final=None, want=None) -> Dict[str, torch.Tensor]:
-        """Exact adjoint of the last forward; returns a dict of gradients."""
-        if self._fwd_keep is None:
-            raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
-        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+    def _grad_buffers(self, F, want):
         sc = self.scene
         V = sc.n_verts
         want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere"))
@@ -272,6 +277,37 @@ class Simulator:
             g["sphere"] = torch.empty(4, dtype=f64, device=dev)
         gr = Grads(*(_ptr(g.get(k)) for k in ("dist_alpha", "bend_alpha", "tet_E", "f_ext", "x0", "v0",
                                               "sphere")))
+        return g, gr
+
+    def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
+                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False):
+        """Roll out; returns (x_frames or None, x_final, v_final) on the device.
+
+        ``for_adjoint``: an adjoint will follow; the library may keep the record
+        of every projection now so the adjoint needs no recomputation."""
+        sc = self.scene
+        V = sc.n_verts
+        x0, v0, da, ba, te, fe, p = self._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
+        xf = None
+        if frames:
+            xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
+                                                                           device=self.device)
+        xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        ve = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        rc = self.lib.xpbd_forward(self._ctx, _ptr(x0), _ptr(v0), C.byref(p), n_frames, _ptr(xf), _ptr(xe),
+                                   _ptr(ve), FWD_FOR_ADJOINT if for_adjoint else 0, _stream_ptr(self.device))
+        self._check(rc)
+        self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames)
+        return xf, xe, ve
+
+    def adjoint(self, dLdx_frames=None, frame_mask=None, dLdv_final=None, want=None) -> Dict[str, torch.Tensor]:
+        """Exact adjoint of the last forward; returns a dict of gradients."""
+        if self._fwd_keep is None:
+            raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
+        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+        sc = self.scene
+        V = sc.n_verts
+        g, gr = self._grad_buffers(F, want)
         dl = self._arg(dLdx_frames, (F, V, 3)) if dLdx_frames is not None else None
         dv = self._arg(dLdv_final, (V, 3)) if dLdv_final is not None else None
         mask_arr = None
@@ -314,3 +350,108 @@ class Simulator:
         it = (C.c_int64 * N_FAMILIES)()
         self._check(self.lib.xpbd_profile_read(self._ctx, la, ms, it))
         return list(la), list(ms), list(it)
+
+
+class PackJob:
+    """One job of a Pack: its simulator, its output tensors on the device
+    (``x_frames``, ``x_final``, ``v_final``, ``loss``, ``grads``) and the
+    inputs the device still reads (kept alive until the job is done)."""
+
+    def __init__(self, sim, n_frames, keep, outputs):
+        self.sim = sim
+        self.n_frames = n_frames
+        self._keep = keep
+        self.x_frames, self.x_final, self.v_final, self.loss, self.grads = outputs
+        self.id = 0
+        self.tag = None
+
+
+class Pack:
+    """Jobs on many simulators advanced together, one frame per round, each
+    launch serving the same step of every job (xpbd_pack_* in xpbd.h)."""
+
+    def __init__(self, dtype: torch.dtype = torch.float32, device="cuda:0", graphs: bool = False):
+        self.lib = load()
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self._pk = _vp()
+        rc = self.lib.xpbd_pack_create(F64 if dtype == torch.float64 else F32, PACK_GRAPHS if graphs else 0,
+                                       C.byref(self._pk))
+        if rc != XPBD_OK:
+            raise XPBDError(rc, "pack create failed")
+        self.jobs: Dict[int, PackJob] = {}
+
+    def _check(self, rc):
+        if rc != XPBD_OK:
+            raise XPBDError(rc, self.lib.xpbd_pack_last_error(self._pk).decode())
+
+    def add(self, sim: Simulator, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
+            f_ext=None, sphere=None, targets=None, frame_mask=None, dLdv_final=None, want=None,
+            frames: bool = True, tag=None) -> PackJob:
+        """Queue a rollout of ``n_frames`` frames and, with ``targets`` ([F, V, 3]),
+        the goal and its adjoint.  Returns the job; its tensors are complete
+        once ``run`` has reported it done and the stream has reached that point."""
+        if sim.dtype != self.dtype or sim.device != self.device:
+            raise ValueError("simulator dtype / device differ from the pack's")
+        V = sim.scene.n_verts
+        x0, v0, da, ba, te, fe, p = sim._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
+        adj = targets is not None
+        xf = torch.empty((n_frames, V, 3), dtype=self.dtype, device=self.device) if (frames or adj) else None
+        xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        ve = torch.empty((V, 3), dtype=self.dtype, device=self.device)
+        tg = sim._arg(targets, (n_frames, V, 3)) if adj else None
+        dv = sim._arg(dLdv_final, (V, 3)) if dLdv_final is not None else None
+        loss = torch.zeros((), dtype=torch.float64, device=self.device) if adj else None
+        g, gr = sim._grad_buffers(n_frames, want) if adj else ({}, Grads())
+        mask_arr = None
+        j = Job()
+        j.x0, j.v0, j.params, j.n_frames = _ptr(x0), _ptr(v0), p, n_frames
+        j.x_frames, j.x_final, j.v_final = _ptr(xf), _ptr(xe), _ptr(ve)
+        j.targets, j.dLdv_final, j.loss, j.grads = _ptr(tg), _ptr(dv), _ptr(loss), gr
+        if frame_mask is not None:
+            mask_arr = np.ascontiguousarray(np.asarray(frame_mask, dtype=np.uint8))
+            if mask_arr.shape != (n_frames,):
+                raise ValueError("frame_mask must have one entry per frame")
+            j.frame_mask = mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
+        jid = C.c_int64(0)
+        self._check(self.lib.xpbd_pack_add(self._pk, sim._ctx, C.byref(j), _stream_ptr(self.device), C.byref(jid)))
+        job = PackJob(sim, n_frames, (x0, v0, da, ba, te, fe, tg, dv, j), (xf, xe, ve, loss, g))
+        job.id = jid.value
+        job.tag = tag
+        self.jobs[job.id] = job
+        return job
+
+    def run(self, max_rounds: int = 1 << 30):
+        """Run rounds until one finishes a job (or max_rounds); returns the
+        finished jobs (stream-ordered: synchronise before reading them)."""
+        cap = max(1, len(self.jobs))
+        ids = (C.c_int64 * cap)()
+        n = C.c_int32(0)
+        self._check(self.lib.xpbd_pack_run(self._pk, max_rounds, _stream_ptr(self.device), ids, cap, C.byref(n)))
+        return [self.jobs.pop(ids[i]) for i in range(n.value)]
+
+    def run_all(self):
+        """Run until every queued job is done; returns them in completion order."""
+        out = []
+        while self.jobs:
+            got = self.run()
+            if not got and self.stats()["active_jobs"] == 0:
+                break
+            out.extend(got)
+        return out
+
+    def stats(self) -> Dict[str, int]:
+        s = PackStats()
+        self._check(self.lib.xpbd_pack_get_stats(self._pk, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in PackStats._fields_}
+
+    def close(self):
+        if self._pk:
+            self.lib.xpbd_pack_destroy(self._pk)
+            self._pk = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

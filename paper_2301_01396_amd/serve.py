@@ -11,7 +11,10 @@ out.  Latency is measured from arrival to result.
 
 All simulation work runs in the library's kernels; this module only
 schedules calls.  Each request gets its own context, so its result does not
-depend on what else is running (bitwise).
+depend on what else is running (bitwise).  Two executors: ``Server`` runs
+each admitted request on its own stream (kernels of different requests
+overlap on the device), ``PackedServer`` runs every admitted request in one
+pack, so each launch serves the same step of all of them.
 """
 from __future__ import annotations
 
@@ -164,6 +167,109 @@ class Server:
         if self._errors:
             raise RuntimeError("; ".join(self._errors))
         return report(self._finished, wall, self._queue_depth)
+
+
+class PackedServer:
+    """Continuous batching through one pack: a scheduler thread admits
+    arrived requests by HBM budget and slot count into the pack, where they
+    join the next round and share every launch with the requests already
+    running; finished requests leave, and their results are copied out on
+    the same stream while later rounds run.  ``graphs`` replays a round from a
+    captured HIP graph while the pack's membership stays the same."""
+
+    def __init__(self, slots: int = 16, hbm_budget: int = 64 << 30, device="cuda:0",
+                 dtype: torch.dtype = torch.float32, graphs: bool = False, rounds_per_call: int = 4):
+        self.slots = slots
+        self.budget = hbm_budget
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.graphs = graphs
+        self.rounds = rounds_per_call
+        self.pack_stats: Dict[str, int] = {}
+
+    def _admit(self, pack, req: Request):
+        sc = req.scene
+        sim = Simulator(sc, dtype=self.dtype, device=self.device, tape_mode=1)
+        mask = None
+        if req.adjoint:
+            mask = np.zeros(req.n_frames, np.uint8)
+            mask[-1] = 1
+        job = pack.add(sim, req.n_frames, targets=req.targets if req.adjoint else None, frame_mask=mask,
+                       want=("x0", "v0", "dist_alpha", "bend_alpha", "tet_E"), frames=False, tag=req)
+        req.projections = sc.projections_per_rollout(req.n_frames) * (2 if req.adjoint else 1)
+        return job
+
+    def _collect(self, job, stream):
+        """Start the device-to-host copies of a finished job's results."""
+        res = {"x_final": job.x_final}
+        if job.loss is not None:
+            res["loss"] = job.loss
+            res.update(job.grads)
+        host = {}
+        for k, v in res.items():
+            h = torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
+            h.copy_(v, non_blocking=True)
+            host[k] = h
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        return ev, host
+
+    def run(self, requests: List[Request]) -> Dict[str, Any]:
+        from .lib import Pack
+        for r in requests:
+            r.device_bytes = estimate_bytes(r.scene, r.n_frames, r.adjoint, 8 if self.dtype == torch.float64 else 4)
+        pending = [(r.arrival, r.rid, r) for r in requests]
+        heapq.heapify(pending)
+        finished: List[Request] = []
+        depth: List[int] = []
+        in_use = 0
+        running: Dict[int, Any] = {}
+        copying = []
+        stream = torch.cuda.Stream(device=self.device)     # default priority
+        pack = Pack(dtype=self.dtype, device=self.device, graphs=self.graphs)
+        torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            while pending or running or copying:
+                now = time.perf_counter() - t0
+                while pending and pending[0][0] <= now and len(running) < self.slots:
+                    req = pending[0][2]
+                    if running and in_use + req.device_bytes > self.budget:
+                        break
+                    heapq.heappop(pending)
+                    depth.append(sum(1 for a, _, _ in pending if a <= now))
+                    req.admitted = time.perf_counter() - t0
+                    req.slot = len(running)
+                    job = self._admit(pack, req)
+                    running[job.id] = job
+                    in_use += req.device_bytes
+                if running:
+                    for job in pack.run(self.rounds):
+                        running.pop(job.id)
+                        copying.append((job,) + self._collect(job, stream))
+                still = []
+                for job, ev, host in copying:
+                    if ev.query():
+                        req = job.tag
+                        req.done = time.perf_counter() - t0
+                        req.result = {k: v.numpy() for k, v in host.items()}
+                        job.sim.close()
+                        in_use -= req.device_bytes
+                        finished.append(req)
+                    else:
+                        still.append((job, ev, host))
+                copying = still
+                if not running and copying:
+                    copying[0][1].synchronize()
+                elif not running and pending:
+                    time.sleep(max(0.0, min(0.01, pending[0][0] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        self.finished = finished
+        self.pack_stats = pack.stats()
+        pack.close()
+        rep = report(finished, wall, depth)
+        rep["pack"] = self.pack_stats
+        return rep
 
 
 def report(done: List[Request], wall: float, depth: List[int]) -> Dict[str, Any]:

@@ -81,3 +81,27 @@ def test_results_are_the_same_alone_and_in_the_mix():
         got = s1._finished[0].result
         for k, v in got.items():
             assert np.array_equal(np.asarray(v), np.asarray(by_id[r.rid].result[k])), (r.rid, k)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graphs", [False, True])
+def test_packed_server_matches_requests_run_alone(graphs):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mix = serve.make_mix(8, qps=50.0, seed=6, vmax=6000, frames_scale=0.1)
+    srv = serve.PackedServer(slots=6, hbm_budget=32 << 30, graphs=graphs, rounds_per_call=2)
+    rep = srv.run(mix)
+    assert rep["requests"] == 8 and rep["max_concurrent"] >= 2
+    assert rep["pack"]["rounds"] > 0
+    by_id = {r.rid: r for r in srv.finished}
+    for r in mix[:4]:
+        alone = serve.make_mix(8, qps=50.0, seed=6, vmax=6000, frames_scale=0.1)[r.rid]
+        alone.arrival = 0.0
+        s1 = serve.Server(slots=1, hbm_budget=32 << 30)
+        s1.run([alone])
+        got = s1._finished[0].result
+        packed = by_id[r.rid].result
+        assert "x_final" in packed and (("loss" in packed) == alone.adjoint)
+        for k, v in packed.items():
+            assert np.array_equal(np.asarray(v), np.asarray(got[k])), (r.rid, k)
