@@ -8,9 +8,15 @@ recomputation of each frame is overhead and not counted); a tet counts its
 deviatoric and hydrostatic projections, a contact constraint counts once
 per evaluation.
 
-Default workload: cloth 256x256 with distance, bending and sphere contact,
-FP32, dt 1/60, 4 substeps, 30 iterations, 30 frames, gradients with respect
-to both compliance fields and v0.  Prints one JSON line.
+Default workload: the 2048x4096 cloth (8,388,608 vertices, 25.2M DoF,
+25.2M distance + 25.1M bending constraints), FP32, dt 1/60, 2 substeps, 20
+iterations, 20 frames, per-vertex force controls, keyframe goal at frames 10
+and 20, gradient with respect to every frame's forces: the configuration
+whose working set is far larger than the GPU's caches, so the projection and
+reverse kernels stream HBM and the roofline is HBM bandwidth.  --workload c2
+(256x256 cloth with a sphere), c3 (64^3 tet box), c1 (32x32, FP64) and c5
+(serving mix: p50/p99 latency and throughput, packed against one request at
+a time) run the other configurations.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -43,10 +49,14 @@ ALG_BYTES = {             # family: (index bytes, words of the state dtype)
 TAPE_WORDS = {0: 4, 2: 10, 4: 6, 6: 4}
 
 
-def alg_bytes(fam: int, tsz: int, recording: bool = False) -> float:
+def alg_bytes(fam: int, tsz: int, recording: float = 0.0) -> float:
+    """Bytes per projection; ``recording`` = fraction of the family's
+    forward launches that also write the adjoint's record (1 when the
+    forward keeps the whole rollout's record, 1/2 when each frame is run
+    once forward and once more by the adjoint to record it)."""
     ib, words = ALG_BYTES[fam]
-    if recording and fam in TAPE_WORDS:
-        words += TAPE_WORDS[fam]
+    if fam in TAPE_WORDS:
+        words += float(recording) * TAPE_WORDS[fam]
     return ib + words * tsz
 
 
@@ -188,8 +198,9 @@ def serve_bench(args):
     log(f"sequential: {seq}")
     executors = {
         "streams": lambda: serve.Server(slots=args.slots, record_whole_rollout=False),
-        "pack": lambda: serve.PackedServer(slots=args.pack_slots, graphs=False),
-        "pack_graphs": lambda: serve.PackedServer(slots=args.pack_slots, graphs=True),
+        "pack": lambda: serve.PackedServer(slots=args.pack_slots, graphs=False, n_packs=1),
+        "pack_graphs": lambda: serve.PackedServer(slots=args.pack_slots, graphs=True, n_packs=1),
+        "packs_graphs": lambda: serve.PackedServer(slots=args.pack_slots, graphs=True, n_packs=args.packs),
     }
     rows = []
     for frac in (0.5, 1.0, 1.5, 3.0, 1e9):
@@ -201,12 +212,12 @@ def serve_bench(args):
             rows.append(rep)
             log(f"qps {frac:g} x capacity, {name}: {rep}")
     best = max(rows, key=lambda r: r["projections_per_s"])
-    out = {"metric": "constraint projections/s fwd+adjoint; p50/p99 request latency",
+    out = {"metric": "constraint projections/s fwd+adjoint vs plain launch; p50/p99 request latency",
            "value": best["projections_per_s"], "unit": "projections/s", "n_gpus": 1,
            "steps": len(rows), "warmup": 1, "ms_per_step": best["wall_s"] * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic serving mix (seed 6)",
            "config": {"workload": "serving_mix", "requests": args.requests, "slots": args.slots,
-                      "pack_slots": args.pack_slots,
+                      "pack_slots": args.pack_slots, "packs": args.packs,
                       "mesh": "50% grid cloth / 50% tet box, ln V ~ N(ln 16000, 1) in [1k, 250k]",
                       "frames": "U{30..120}", "adjoint_fraction": 0.5, "substeps": 2, "iterations": 20},
            "best": {"executor": best["executor"], "qps_over_sequential_capacity": best["qps_over_sequential_capacity"],
@@ -217,17 +228,66 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def implicit_bench(args):
+    """The paper's implicit adjoint (CG per substep) against the exact
+    reverse adjoint on one workload: time of each and their gradients'
+    relative difference per parameter group."""
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    sc, tg = make_workload(args.workload, args.tile, args.frames)
+    F = args.frames or sc.n_frames
+    dtype = torch.float64 if args.workload == "c1" else torch.float32
+    sim = Simulator(sc, dtype=dtype)
+    mask = np.zeros(F, np.uint8)
+    mask[F - 1] = 1
+    if tg is not None:
+        tsim = Simulator(tg, dtype=dtype)
+        targets, _, _ = tsim.forward(F)
+        tsim.close()
+    else:
+        targets, _, _ = sim.forward(F)
+        targets = targets * 0.99
+    res = {}
+    for kind in ("exact", "implicit", "exact", "implicit"):      # second pass timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xf, _, _ = sim.forward(F, for_adjoint=(kind == "exact"))
+        _, dL = sim.goal_l2(xf, targets, mask)
+        if kind == "exact":
+            g = sim.adjoint(dL, mask, want=("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
+            rep = None
+        else:
+            g, rep = sim.adjoint_implicit(dL, mask, max_iterations=args.cg_iters, rel_tolerance=args.cg_tol)
+        torch.cuda.synchronize()
+        res[kind] = {"s": time.perf_counter() - t0, "g": {k: v.double().cpu().numpy() for k, v in g.items()},
+                     "cg": rep}
+        log(f"{kind}: {res[kind]['s']:.3f} s {rep or ''}")
+    diff = {}
+    for k, a in res["exact"]["g"].items():
+        b = res["implicit"]["g"].get(k)
+        if b is not None and np.linalg.norm(a) > 0:
+            diff[k] = float(np.linalg.norm(b - a) / np.linalg.norm(a))
+    out = {"metric": "implicit adjoint (CG per substep) vs exact reverse adjoint", "workload":
+           workload_config(args.workload, sc, F), "dtype": "f64" if dtype == torch.float64 else "f32",
+           "exact_fwd_adjoint_s": res["exact"]["s"], "implicit_fwd_adjoint_s": res["implicit"]["s"],
+           "cg": res["implicit"]["cg"], "cg_rel_tolerance": args.cg_tol, "cg_max_iterations": args.cg_iters,
+           "rel_difference_implicit_vs_exact": diff}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=24, help="serving mix size (c5)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy kernel over this many bytes (counter calibration)")
     ap.add_argument("--slots", type=int, default=8, help="concurrent requests, one stream each (c5)")
-    ap.add_argument("--pack-slots", type=int, default=16, help="requests sharing one pack (c5)")
+    ap.add_argument("--pack-slots", type=int, default=32, help="requests in packs at once (c5)")
+    ap.add_argument("--packs", type=int, default=4, help="packs, one stream each (c5)")
     ap.add_argument("--frames", type=int, default=0, help="override frame count (0 = the workload's)")
     ap.add_argument("--profile-stride", type=int, default=7,
                     help="bracket every n-th projection launch with HIP events (0 = off)")
@@ -236,6 +296,10 @@ def main():
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0 = auto)")
     ap.add_argument("--tile", type=int, default=-1, help="schedule tile width (-1 = the workload's, 0 = untiled)")
     ap.add_argument("--no-groups", action="store_true", help="run every set as its own launch")
+    ap.add_argument("--implicit", action="store_true",
+                    help="compare the implicit (CG) adjoint with the exact one on the workload")
+    ap.add_argument("--cg-iters", type=int, default=2000)
+    ap.add_argument("--cg-tol", type=float, default=1e-8)
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
@@ -260,6 +324,8 @@ def main():
         return
     if args.workload == "c5":
         return serve_bench(args)
+    if args.implicit:
+        return implicit_bench(args)
 
     dev = torch.device("cuda:0")
     sc, tg = make_workload(args.workload, args.tile, args.frames)
@@ -332,7 +398,10 @@ def main():
     grads_finite = all(bool(torch.isfinite(t.grad).all()) for t in leaves)
     info = sim.info()
     log(f"timed {args.steps} steps: {elapsed / args.steps * 1e3:.1f} ms/step, info {info}")
-    recording = info["tape_mode"] == 3
+    # share of forward launches that write the record: all of them when the
+    # forward keeps the whole rollout's record, half when every frame is
+    # recomputed once by the adjoint
+    recording = {3: 1.0, 1: 0.5}.get(info["tape_mode"], 0.0)
 
     plain = None
     if args.plain_steps > 0 and (info["persistent"] or info["n_groups_lds"]):
@@ -349,6 +418,9 @@ def main():
                  "ms_per_step": (p1 - p0) / args.plain_steps * 1e3, "steps": args.plain_steps,
                  "launch": "one kernel launch per independent set"}
         log(f"plain launch: {plain['ms_per_step']:.1f} ms/step")
+    elif not (info["persistent"] or info["n_groups_lds"]):
+        plain = {"value": value, "ms_per_step": elapsed / args.steps * 1e3, "steps": args.steps,
+                 "launch": "the timed path itself: one kernel launch per independent set"}
 
     roof = None
     kernels = {}
@@ -397,7 +469,7 @@ def main():
         cpu = cpu_baseline(args.workload, sc)
 
     out = {
-        "metric": "constraint projections/s fwd+adjoint",
+        "metric": "constraint projections/s fwd+adjoint vs plain launch; p50/p99 request latency",
         "value": value, "unit": "projections/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if dtype == torch.float64 else "f32",

@@ -69,7 +69,8 @@ typedef enum {
   XPBD_ERR_OOM = 2,       /* allocation failed or hbm_budget_bytes exceeded */
   XPBD_ERR_HIP = 3,       /* HIP runtime error (includes earlier async faults) */
   XPBD_ERR_STATE = 4,     /* adjoint without a matching forward */
-  XPBD_ERR_NONFINITE = 5  /* non-finite input parameter */
+  XPBD_ERR_NONFINITE = 5, /* non-finite input parameter */
+  XPBD_ERR_SOLVER = 6     /* iterative solve failed (system not positive definite) */
 } xpbd_status;
 
 typedef enum { XPBD_F32 = 0, XPBD_F64 = 1 } xpbd_dtype;
@@ -208,6 +209,38 @@ xpbd_status xpbd_goal_l2(xpbd_ctx ctx, const void* x_frames, const void* targets
                          const uint8_t* frame_mask, int32_t n_frames, double* loss,
                          void* dLdx, void* stream);
 
+/* Implicit adjoint of Sec. 4.2 (Eq. adjointXPBD) for the preceding
+ * xpbd_forward, the paper's own derivative: each substep's projection is
+ * taken as converged, x = y + M^-1 sum_j grad C_j lambda_j with lambda_j =
+ * -C_j / alpha~_j at the substep's end state (contacts active where C < 0
+ * there), and the substep's adjoint solves (I - M^-1 K)^T w = xbar with
+ * K = sum_j (lambda_j Hess C_j - grad C_j grad C_j^T / alpha~_j) (Sec. 4.3
+ * partials).  On the free vertices this is the symmetric system (M - K) y =
+ * xbar, w = M y, solved by Jacobi-preconditioned conjugate gradients in FP64
+ * with a matrix-free operator; no positive-definite projection is applied,
+ * so a system that is not positive definite fails with XPBD_ERR_SOLVER.
+ * Then vbar = h w (free vertices), dL/df_ext += h w_inv vbar, xbar = w -
+ * vbar_old / h, and dL/dalpha_j += (grad C_j . y)(-lambda_j / alpha~_j) / h^2.
+ * Frames are recomputed from the forward's checkpoints.  It differs from
+ * xpbd_adjoint, the exact derivative of the iterated rollout, wherever the
+ * iterations have not converged or the constraint gradients turn along the
+ * iteration path.
+ * Outputs: dist / bend compliance, f_ext, x0, v0 (as xpbd_adjoint);
+ * out->tet_E and out->sphere must be NULL.  Every active constraint needs a
+ * positive compliance (else XPBD_ERR_INVALID).  `cg` gives the iteration
+ * limit and relative residual tolerance per substep and receives the
+ * iteration counts and the worst relative residual reached. */
+typedef struct {
+  int32_t max_iterations;       /* in: CG iterations per substep, >= 1 */
+  double rel_tolerance;         /* in: stop at |r| <= rel_tolerance |xbar| */
+  int64_t total_iterations;     /* out */
+  int32_t max_iterations_used;  /* out: most iterations one substep took */
+  double worst_rel_residual;    /* out */
+} xpbd_cg;
+xpbd_status xpbd_adjoint_implicit(xpbd_ctx ctx, const xpbd_params* p, const void* dLdx_frames,
+                                  const uint8_t* frame_mask, xpbd_cg* cg, const xpbd_grads* out,
+                                  void* stream);
+
 typedef struct {
   int32_t n_verts, n_dist, n_bend, n_tet, n_contact, n_sets;
   int64_t projections_per_iteration;   /* tets count D and H; contacts counted as evaluated */
@@ -295,12 +328,15 @@ typedef struct {
 xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, xpbd_pack* out);
 /* Synchronises the pack's last stream, then frees the pack (not its contexts). */
 xpbd_status xpbd_pack_destroy(xpbd_pack pack);
-/* Validate a job, gather its parameters (synchronises `stream` to check
- * them), allocate its context's checkpoints and record, load (x0, v0), and
- * queue it for the next round.  *job_id (> 0) identifies it in
- * xpbd_pack_run.  Errors: XPBD_ERR_INVALID (mismatched dtype / substeps /
- * iterations, context already in a job, bad job), XPBD_ERR_NONFINITE,
- * XPBD_ERR_OOM (record does not fit), XPBD_ERR_HIP. */
+/* Validate a job, gather and check its parameters, allocate its context's
+ * checkpoints and record, load (x0, v0), and queue it for the next round.
+ * This work runs on a stream of the pack's own and waits only for itself
+ * (and for the context's previous pack job, if that is still running), never
+ * for the pack's rounds; `stream` is not used.  The context must have no
+ * other work in flight.  *job_id (> 0) identifies the job in xpbd_pack_run.
+ * Errors: XPBD_ERR_INVALID (mismatched dtype / substeps / iterations,
+ * context already in a job, bad job), XPBD_ERR_NONFINITE, XPBD_ERR_OOM
+ * (record does not fit), XPBD_ERR_HIP. */
 xpbd_status xpbd_pack_add(xpbd_pack pack, xpbd_ctx ctx, const xpbd_job* job, void* stream, int64_t* job_id);
 /* Run up to max_rounds rounds on `stream`, returning after the first round
  * in which any job finished.  The ids of finished jobs (at most `cap`; the

@@ -149,6 +149,11 @@ struct xpbd_ctx_s {
   bool in_pack = false;
   uint8_t* pack_mask = nullptr;   // device [F] goal frames of the current job
   int pack_mask_cap = 0;
+  hipEvent_t pack_event = nullptr;  // recorded after the last work of its latest job
+
+  // implicit adjoint work space (substep end states, CG vectors)
+  void* imp_buf = nullptr;
+  size_t imp_cap = 0;
 
   // forward bookkeeping for the adjoint
   bool have_forward = false;
@@ -167,6 +172,10 @@ struct xpbd_ctx_s {
   int64_t prof_items[12] = {0};
 
   ~xpbd_ctx_s() {
+    if (pack_event) {
+      (void)hipEventSynchronize(pack_event);
+      (void)hipEventDestroy(pack_event);
+    }
     for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
     for (auto& e : ev_pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -1501,6 +1510,7 @@ const char* xpbd_status_string(xpbd_status s) {
     case XPBD_ERR_HIP: return "HIP error";
     case XPBD_ERR_STATE: return "invalid state";
     case XPBD_ERR_NONFINITE: return "non-finite value";
+    case XPBD_ERR_SOLVER: return "solver failure";
   }
   return "unknown";
 }
@@ -1508,3 +1518,4 @@ const char* xpbd_status_string(xpbd_status s) {
 }  // extern "C"
 
 #include "xpbd_pack_host.hpp"
+#include "xpbd_implicit_host.hpp"

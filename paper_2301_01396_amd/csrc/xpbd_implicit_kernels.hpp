@@ -1,0 +1,257 @@
+// Kernels of the implicit adjoint (Sec. 4.2, Eq. adjointXPBD, with the
+// partial derivatives of Sec. 4.3): each substep's projection is taken as
+// converged, x = y + M^-1 sum_j grad C_j lambda_j with lambda_j = -C_j /
+// alpha~_j at the substep's end state, and its adjoint solves
+//     (I - M^-1 K)^T w = xbar,   K = sum_j (lambda_j Hess C_j - grad C_j grad C_j^T / alpha~_j).
+// With w = M y on the free vertices this is the symmetric system
+// (M - K) y = xbar restricted to the free vertices, solved by preconditioned
+// conjugate gradients in FP64.  The operator is applied matrix-free, one
+// launch per independent set: no two constraints of a set share a vertex,
+// so every constraint adds its 3x3 blocks' action to its own vertices
+// without atomics.  Pinned vertices keep y = 0; their w is xbar + (K y).
+#pragma once
+
+#include "xpbd_kernels.hpp"
+
+namespace xpbd {
+
+using D4 = Vec4<double>;
+
+__device__ __forceinline__ V3<double> d3(const D4& v) { return {v.x, v.y, v.z}; }
+template <class T> __device__ __forceinline__ V3<double> pos(const Vec4<T>& v) {
+  return {(double)v.x, (double)v.y, (double)v.z};
+}
+__device__ __forceinline__ void add3(D4& o, V3<double> a) { o.x += a.x; o.y += a.y; o.z += a.z; }
+
+enum ImpMode {
+  IMP_APPLY = 0,  // Q += -K P (every vertex of the constraint)
+  IMP_DIAG = 1,   // Q += (grad C)^2 / alpha~ componentwise (Jacobi preconditioner)
+  IMP_GRAD = 2    // acc_j += (grad C_j . P) (-lambda_j / alpha~_j) / h^2
+};
+
+// one constraint row with n vertices: value C, gradient g, stiffness at
+template <int MODE>
+__device__ __forceinline__ void imp_row(int n, const int* vid, double C, double at, const V3<double>* g,
+                                        const V3<double>* hv, const D4* __restrict__ P, D4* __restrict__ Q,
+                                        double* acc, double ih2) {
+  const double lam = -C / at;
+  if (MODE == IMP_DIAG) {
+    for (int k = 0; k < n; ++k) {
+      D4 q = Q[vid[k]];
+      q.x += g[k].x * g[k].x / at; q.y += g[k].y * g[k].y / at; q.z += g[k].z * g[k].z / at;
+      Q[vid[k]] = q;
+    }
+    return;
+  }
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += dot(g[k], d3(P[vid[k]]));
+  if (MODE == IMP_GRAD) {
+    *acc += s * (-lam / at) * ih2;
+    return;
+  }
+  for (int k = 0; k < n; ++k) {
+    D4 q = Q[vid[k]];
+    add3(q, (-lam) * hv[k] + (s / at) * g[k]);
+    Q[vid[k]] = q;
+  }
+}
+
+template <class T, int TY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int count, const Vec4<T>* __restrict__ XE,
+                                                    const D4* __restrict__ P, D4* __restrict__ Q, double ih2,
+                                                    int* __restrict__ bad) {
+  const int t = thread_item(count);
+  if (t < 0) return;
+  const int j = begin + t;
+  V3<double> gb[4], hv[4] = {};
+  if (TY == 0) {
+    const int2 e = D.d_idx[j];
+    const int vid[2] = {e.x, e.y};
+    DistEval<double> ev = dist_eval(pos(XE[e.x]) - pos(XE[e.y]), (double)D.d_rest[j]);
+    if (!ev.ok) return;
+    const double at = (double)D.d_at[j];
+    if (!(at > 0.0)) { *bad = 1; return; }
+    V3<double> g[2] = {ev.n, -ev.n};
+    if (MODE == IMP_APPLY) {
+      V3<double> d = d3(P[e.x]) - d3(P[e.y]);
+      double dn = dot(d, ev.n);
+      hv[0] = (1.0 / ev.len) * (d - dn * ev.n);
+      hv[1] = -hv[0];
+    }
+    imp_row<MODE>(2, vid, ev.C, at, g, hv, P, Q, D.d_acc + j, ih2);
+  } else if (TY == 1) {
+    const int4 q = D.b_idx[j];
+    const int vid[4] = {q.x, q.y, q.z, q.w};
+    V3<double> x0 = pos(XE[q.x]);
+    V3<double> e = pos(XE[q.y]) - x0, a = pos(XE[q.z]) - x0, b = pos(XE[q.w]) - x0;
+    BendEval<double> ev = bend_eval(e, a, b, (double)D.b_th0[j]);
+    if (!ev.ok) return;
+    const double at = (double)D.b_at[j];
+    if (!(at > 0.0)) { *bad = 1; return; }
+    if (MODE == IMP_APPLY) {
+      for (int k = 0; k < 4; ++k) gb[k] = d3(P[vid[k]]);
+      bend_hvp(e, a, b, gb, hv);
+    }
+    imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, D.b_acc + j, ih2);
+  } else if (TY == 2) {
+    const TetRec<T>& R = D.tr;
+    const int4 q = R.idx[j];
+    const int vid[4] = {q.x, q.y, q.z, q.w};
+    V3<double> x0 = pos(XE[q.x]);
+    const V3<double> dd[3] = {pos(XE[q.y]) - x0, pos(XE[q.z]) - x0, pos(XE[q.w]) - x0};
+    M3<T> Bt = load_B(R.B, R.n, j);
+    M3<double> B;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) B.m[r][c] = (double)Bt.m[r][c];
+    if (MODE == IMP_APPLY)
+      for (int k = 0; k < 4; ++k) gb[k] = d3(P[vid[k]]);
+    // deviatoric then hydrostatic row, both at the end state; the tets'
+    // parameter gradient is not produced by this adjoint
+    {
+      TetEval<double> ev = tet_dev_eval(dd, B);
+      const double at = (double)R.atD[j];
+      if (ev.ok) {
+        if (!(at > 0.0)) { *bad = 1; return; }
+        if (MODE == IMP_APPLY) tet_dev_hvp(ev, B, gb, hv);
+        if (MODE != IMP_GRAD) imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, nullptr, ih2);
+      }
+    }
+    {
+      TetEval<double> ev = tet_hyd_eval(dd, B, (double)R.gamma[j]);
+      const double at = (double)R.atH[j];
+      if (!(at > 0.0)) { *bad = 1; return; }
+      if (MODE == IMP_APPLY) tet_hyd_hvp(ev, B, gb, hv);
+      if (MODE != IMP_GRAD) imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, nullptr, ih2);
+    }
+  } else {
+    const int v = D.c_vid[j];
+    const int vid[1] = {v};
+    const V3<double> c = {(double)D.sph.cx, (double)D.sph.cy, (double)D.sph.cz};
+    ContactEval<double> ev = contact_eval(pos(XE[v]) - c, (double)D.sph.R, (double)D.sph.tau);
+    if (!ev.ok || !(ev.C < 0.0)) return;
+    const double at = (double)D.sph.at;
+    if (!(at > 0.0)) { *bad = 1; return; }
+    V3<double> g[1] = {ev.n};
+    if (MODE == IMP_APPLY) {
+      V3<double> d = d3(P[v]);
+      hv[0] = (1.0 / ev.d) * (d - dot(d, ev.n) * ev.n);
+    }
+    if (MODE != IMP_GRAD) imp_row<MODE>(1, vid, ev.C, at, g, hv, P, Q, nullptr, ih2);
+  }
+}
+
+// Q = M P on free vertices (M = 1 / w), 0 on pinned ones
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_imp_mass(const Vec4<T>* __restrict__ XB, const D4* __restrict__ P,
+                                                     D4* __restrict__ Q, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  double w = (double)XB[k].w;
+  D4 p = P[k];
+  Q[k] = w > 0.0 ? D4{p.x / w, p.y / w, p.z / w, 0.0} : D4{0.0, 0.0, 0.0, 0.0};
+}
+
+// b = xbar on free vertices (0 on pinned), y = 0, r = b
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_imp_rhs(const Vec4<T>* __restrict__ XB, D4* __restrict__ Bv,
+                                                    D4* __restrict__ Y, D4* __restrict__ R, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> x = XB[k];
+  D4 b = x.w > T(0) ? D4{(double)x.x, (double)x.y, (double)x.z, 0.0} : D4{0.0, 0.0, 0.0, 0.0};
+  Bv[k] = b;
+  R[k] = b;
+  Y[k] = D4{0.0, 0.0, 0.0, 0.0};
+}
+
+// deterministic partial sums of a . b (b = null: a . a) over the free
+// vertices, or of a . (b / diag) when diag is given
+__global__ __launch_bounds__(kBlock) void k_imp_dot(const D4* __restrict__ a, const D4* __restrict__ b,
+                                                    const D4* __restrict__ diag, int n, double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  double s = 0.0;
+  if (k < n) {
+    D4 x = a[k], y = b ? b[k] : a[k];
+    if (diag) {
+      D4 dg = diag[k];
+      if (dg.x > 0.0) s += x.x * y.x / dg.x;
+      if (dg.y > 0.0) s += x.y * y.y / dg.y;
+      if (dg.z > 0.0) s += x.z * y.z / dg.z;
+    } else {
+      s = x.x * y.x + x.y * y.y + x.z * y.z;
+    }
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// diag = M + accumulated (grad C)^2 / alpha~ on free vertices, 0 on pinned
+// ones (the zero marks them for the other CG kernels)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_imp_diag(const Vec4<T>* __restrict__ XB, D4* __restrict__ DG, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  double w = (double)XB[k].w;
+  D4 d = DG[k];
+  DG[k] = w > 0.0 ? D4{d.x + 1.0 / w, d.y + 1.0 / w, d.z + 1.0 / w, 0.0} : D4{0.0, 0.0, 0.0, 0.0};
+}
+
+// y += alpha p; r -= alpha q on free vertices
+__global__ __launch_bounds__(kBlock) void k_imp_axpy2(double alpha, const D4* __restrict__ P, const D4* __restrict__ Q,
+                                                      const D4* __restrict__ DG, D4* __restrict__ Y,
+                                                      D4* __restrict__ R, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n || !(DG[k].x > 0.0)) return;
+  D4 p = P[k], q = Q[k], y = Y[k], r = R[k];
+  y.x += alpha * p.x; y.y += alpha * p.y; y.z += alpha * p.z;
+  r.x -= alpha * q.x; r.y -= alpha * q.y; r.z -= alpha * q.z;
+  Y[k] = y;
+  R[k] = r;
+}
+
+// p = r / diag + beta p (free vertices; pinned stay 0)
+__global__ __launch_bounds__(kBlock) void k_imp_dir(double beta, const D4* __restrict__ R, const D4* __restrict__ DG,
+                                                    D4* __restrict__ P, int n, int first) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  D4 r = R[k], dg = DG[k], p = first ? D4{0.0, 0.0, 0.0, 0.0} : P[k];
+  D4 z = {dg.x > 0.0 ? r.x / dg.x : 0.0, dg.y > 0.0 ? r.y / dg.y : 0.0, dg.z > 0.0 ? r.z / dg.z : 0.0, 0.0};
+  P[k] = D4{z.x + beta * p.x, z.y + beta * p.y, z.z + beta * p.z, 0.0};
+}
+
+// After the solve (Q = (M - K) y on free vertices, -(K y) on pinned ones):
+//   w = M y (free), w = xbar + K y (pinned);  xbar_prev = -vbar / h;
+//   vbar_mid = h w (free), fbar += h w_inv vbar_mid;  vbar = vbar_mid;  xbar = w + xbar_prev
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_imp_finish(Vec4<T>* __restrict__ XB, Vec4<T>* __restrict__ VB,
+                                                       const D4* __restrict__ Y, const D4* __restrict__ Q,
+                                                       T* __restrict__ fbar, double h, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  Vec4<T> xb = XB[k], vb = VB[k];
+  const double wi = (double)xb.w;
+  D4 y = Y[k];
+  V3<double> w, vm = {0.0, 0.0, 0.0};
+  if (wi > 0.0) {
+    w = {y.x / wi, y.y / wi, y.z / wi};
+    vm = h * w;
+    if (fbar) {
+      fbar[3 * k] += (T)(h * wi * vm.x);
+      fbar[3 * k + 1] += (T)(h * wi * vm.y);
+      fbar[3 * k + 2] += (T)(h * wi * vm.z);
+    }
+  } else {
+    D4 q = Q[k];
+    w = {(double)xb.x - q.x, (double)xb.y - q.y, (double)xb.z - q.z};
+  }
+  XB[k] = Vec4<T>{(T)(w.x - (double)vb.x / h), (T)(w.y - (double)vb.y / h), (T)(w.z - (double)vb.z / h), xb.w};
+  VB[k] = Vec4<T>{(T)vm.x, (T)vm.y, (T)vm.z, T(0)};
+}
+
+}  // namespace xpbd

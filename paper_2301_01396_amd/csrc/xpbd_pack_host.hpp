@@ -34,30 +34,52 @@ struct xpbd_pack_s {
     size_t seg;      // first segment in the table
     int nseg;
   };
-  std::vector<Launch> plan;
-  int n_members = 0;
-  void* dmem = nullptr; size_t dmem_cap = 0;   // member table (device)
-  void* dseg = nullptr; size_t dseg_cap = 0;   // segment tables (device)
+  // Two plan slots used in turn, so that building a new plan never waits for
+  // the rounds of the current one: a slot is reused only after the last
+  // round that read its tables (an event recorded after every round).
+  struct Slot {
+    std::vector<Launch> plan;
+    int n_members = 0;
+    void* dmem = nullptr; size_t dmem_cap = 0;   // member table (device)
+    void* dseg = nullptr; size_t dseg_cap = 0;   // segment tables (device)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;                   // after the slot's last round
+    bool pending = false;
+    void drop_graph() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+  };
+  Slot slot[2];
+  int cur = -1;
 
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
   hipStream_t last_stream = nullptr;
   bool used = false;
+  // admission work (parameter checks, initial state) runs on its own stream
+  // so that adding a job never waits for the pack's rounds
+  hipStream_t adm_stream = nullptr;
+  hipEvent_t adm_event = nullptr;
+  bool adm_pending = false;
   xpbd_pack_stats stats{};
 
-  void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-  }
   ~xpbd_pack_s() {
     if (used) (void)hipStreamSynchronize(last_stream);
-    drop_graph();
-    if (dmem) (void)hipFree(dmem);
-    if (dseg) (void)hipFree(dseg);
+    for (Slot& s : slot) {
+      s.drop_graph();
+      if (s.dmem) (void)hipFree(s.dmem);
+      if (s.dseg) (void)hipFree(s.dseg);
+      if (s.done) (void)hipEventDestroy(s.done);
+    }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (adm_stream) {
+      (void)hipStreamSynchronize(adm_stream);
+      (void)hipStreamDestroy(adm_stream);
+    }
+    if (adm_event) (void)hipEventDestroy(adm_event);
     for (auto& J : jobs) J.c->in_pack = false;
   }
 };
@@ -94,8 +116,15 @@ template <class T> struct PackOps {
     if (adj && !j->x_frames) fail(XPBD_ERR_INVALID, "pack add: a job with an adjoint needs x_frames");
     c->have_forward = false;
     c->fwd_recorded = false;
-    // waits for the stream, so every earlier job of this pack is finished
-    // on the device before its context buffers are reused below
+    // the context's previous job (in any pack) must be finished on the
+    // device before its buffers are reused
+    if (c->pack_event) HIPCHK(hipEventSynchronize(c->pack_event));
+    if (!pk->adm_stream) {
+      HIPCHK(hipStreamCreateWithFlags(&pk->adm_stream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&pk->adm_event, hipEventDisableTiming));
+    }
+    (void)st;
+    st = pk->adm_stream;
     Ops<T>::gather_params(c, &j->params, st);
     ensure_checkpoints(c, F);
     Job J;
@@ -133,6 +162,9 @@ template <class T> struct PackOps {
     k_pack<T><<<nblocks(c->V), kBlock, 0, st>>>((const T*)j->x0, (const T*)j->v0, (const T*)c->w, (V4*)c->X,
                                                  (V4*)c->Vv, c->V);
     check_launch();
+    HIPCHK(hipEventRecord(pk->adm_event, st));
+    pk->adm_pending = true;
+    if (!c->pack_event) HIPCHK(hipEventCreateWithFlags(&c->pack_event, hipEventDisableTiming));
     J.id = pk->next_id++;
     pk->jobs.push_back(J);
     c->in_pack = true;
@@ -144,9 +176,12 @@ template <class T> struct PackOps {
   static bool fwd_kind(const Job& J) { return J.phase == 0 || J.mode == 1; }
 
   static void build_plan(xpbd_pack pk, hipStream_t st) {
-    // the tables may be read by launches still in flight
-    if (pk->used) HIPCHK(hipStreamSynchronize(pk->last_stream));
-    pk->drop_graph();
+    const int next = (pk->cur + 1) % 2;
+    xpbd_pack_s::Slot& SL = pk->slot[next];
+    if (SL.pending) HIPCHK(hipEventSynchronize(SL.done));   // its last round has finished
+    SL.pending = false;
+    SL.drop_graph();
+    if (!SL.done) HIPCHK(hipEventCreateWithFlags(&SL.done, hipEventDisableTiming));
     const int M = (int)pk->jobs.size();
     const int S = pk->S, K = pk->K;
     std::vector<PackMember<T>> mem(M);
@@ -251,15 +286,18 @@ template <class T> struct PackOps {
       }
     }
     if (M) plan.push_back({xpbd_pack_s::L_ADVANCE, 0, false, false, 0, nblocks(M), 0, 0});
-    pack_grow(pk->dmem, pk->dmem_cap, std::max<size_t>(1, (size_t)M) * sizeof(PackMember<T>));
-    pack_grow(pk->dseg, pk->dseg_cap, std::max<size_t>(1, seg.size()) * sizeof(PackSeg));
-    if (M) HIPCHK(hipMemcpy(pk->dmem, mem.data(), (size_t)M * sizeof(PackMember<T>), hipMemcpyHostToDevice));
-    if (!seg.empty()) HIPCHK(hipMemcpy(pk->dseg, seg.data(), seg.size() * sizeof(PackSeg), hipMemcpyHostToDevice));
-    pk->plan.swap(plan);
-    pk->n_members = M;
-    pk->stats.last_round_launches = (int32_t)pk->plan.size();
-    pk->dirty = false;
+    pack_grow(SL.dmem, SL.dmem_cap, std::max<size_t>(1, (size_t)M) * sizeof(PackMember<T>));
+    pack_grow(SL.dseg, SL.dseg_cap, std::max<size_t>(1, seg.size()) * sizeof(PackSeg));
+    // host-synchronous copies: complete before any later launch reads them,
+    // and nothing in flight reads this slot any more
+    if (M) HIPCHK(hipMemcpy(SL.dmem, mem.data(), (size_t)M * sizeof(PackMember<T>), hipMemcpyHostToDevice));
+    if (!seg.empty()) HIPCHK(hipMemcpy(SL.dseg, seg.data(), seg.size() * sizeof(PackSeg), hipMemcpyHostToDevice));
     (void)st;
+    SL.plan.swap(plan);
+    SL.n_members = M;
+    pk->cur = next;
+    pk->stats.last_round_launches = (int32_t)SL.plan.size();
+    pk->dirty = false;
   }
 
   // ---------------------------------------------------------------- launches
@@ -278,9 +316,11 @@ template <class T> struct PackOps {
   }
 
   static void launch_plan(xpbd_pack pk, hipStream_t st) {
-    PackMember<T>* mem = (PackMember<T>*)pk->dmem;
-    const PackSeg* seg0 = (const PackSeg*)pk->dseg;
-    for (const Launch& L : pk->plan) {
+    const xpbd_pack_s::Slot& SL = pk->slot[pk->cur];
+    PackMember<T>* mem = (PackMember<T>*)SL.dmem;
+    const PackSeg* seg0 = (const PackSeg*)SL.dseg;
+    const int n_members = SL.n_members;
+    for (const Launch& L : SL.plan) {
       const PackSeg* sg = seg0 + L.seg;
       switch (L.kind) {
         case xpbd_pack_s::L_VERT:
@@ -316,13 +356,14 @@ template <class T> struct PackOps {
           }
           break;
         case xpbd_pack_s::L_SPHERE: k_pack_sphere<T><<<L.grid, kBlock, 0, st>>>(mem, sg); break;
-        default: k_pack_advance<T><<<L.grid, kBlock, 0, st>>>(mem, pk->n_members); break;
+        default: k_pack_advance<T><<<L.grid, kBlock, 0, st>>>(mem, n_members); break;
       }
       check_launch();
     }
   }
 
   static void capture(xpbd_pack pk) {
+    xpbd_pack_s::Slot& SL = pk->slot[pk->cur];
     if (!pk->cap_stream) HIPCHK(hipStreamCreateWithFlags(&pk->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(pk->cap_stream, hipStreamCaptureModeThreadLocal));
     try {
@@ -333,13 +374,14 @@ template <class T> struct PackOps {
       if (g) (void)hipGraphDestroy(g);
       throw;
     }
-    HIPCHK(hipStreamEndCapture(pk->cap_stream, &pk->graph));
-    HIPCHK(hipGraphInstantiate(&pk->exec, pk->graph, nullptr, nullptr, 0));
+    HIPCHK(hipStreamEndCapture(pk->cap_stream, &SL.graph));
+    HIPCHK(hipGraphInstantiate(&SL.exec, SL.graph, nullptr, nullptr, 0));
     pk->stats.graph_captures += 1;
   }
 
   // ---------------------------------------------------------------- phase changes
-  static void finish_job(xpbd_pack pk, Job& J) {
+  static void finish_job(xpbd_pack pk, Job& J, hipStream_t st) {
+    HIPCHK(hipEventRecord(J.c->pack_event, st));
     J.c->in_pack = false;
     pk->done.push_back(J.id);
   }
@@ -357,7 +399,7 @@ template <class T> struct PackOps {
         check_launch();
         pk->dirty = true;
         if (!J.j.targets) {
-          finish_job(pk, J);
+          finish_job(pk, J, st);
           continue;
         }
         if (J.j.loss) Ops<T>::goal(c, J.j.x_frames, J.j.targets, J.mask.data(), F, J.j.loss, nullptr, st);
@@ -367,7 +409,7 @@ template <class T> struct PackOps {
       } else if (J.phase == 1 && J.f < 0) {
         Ops<T>::finish_adjoint(c, &J.j.params, &J.j.grads, st);
         pk->dirty = true;
-        finish_job(pk, J);
+        finish_job(pk, J, st);
         continue;
       }
       keep.push_back(J);
@@ -377,15 +419,22 @@ template <class T> struct PackOps {
 
   static void run(xpbd_pack pk, int max_rounds, hipStream_t st) {
     for (int r = 0; r < max_rounds && !pk->jobs.empty(); ++r) {
+      if (pk->adm_pending) {
+        HIPCHK(hipStreamWaitEvent(st, pk->adm_event, 0));
+        pk->adm_pending = false;
+      }
       if (pk->dirty) build_plan(pk, st);
+      xpbd_pack_s::Slot& SL = pk->slot[pk->cur];
       if (pk->graphs) {
-        if (!pk->exec) capture(pk);
-        HIPCHK(hipGraphLaunch(pk->exec, st));
+        if (!SL.exec) capture(pk);
+        HIPCHK(hipGraphLaunch(SL.exec, st));
         pk->stats.graph_launches += 1;
       } else {
         launch_plan(pk, st);
-        pk->stats.launches += (int64_t)pk->plan.size();
+        pk->stats.launches += (int64_t)SL.plan.size();
       }
+      HIPCHK(hipEventRecord(SL.done, st));
+      SL.pending = true;
       pk->used = true;
       pk->last_stream = st;
       pk->stats.rounds += 1;
@@ -449,7 +498,6 @@ xpbd_status xpbd_pack_add(xpbd_pack pk, xpbd_ctx c, const xpbd_job* job, void* s
       fail(XPBD_ERR_INVALID, "pack add: substeps / iterations (%d, %d) differ from the pack's (%d, %d)", c->S, c->K,
            pk->S, pk->K);
     hipStream_t st = (hipStream_t)stream;
-    if (pk->used && st != pk->last_stream) HIPCHK(hipStreamSynchronize(pk->last_stream));
     try {
       if (c->dtype == XPBD_F32) PackOps<float>::add(pk, c, job, st, job_id);
       else PackOps<double>::add(pk, c, job, st, job_id);

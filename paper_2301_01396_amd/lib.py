@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libxpbd.so")
 
-XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE = range(6)
+XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE, XPBD_ERR_SOLVER = range(7)
 F32, F64 = 0, 1
 FWD_FOR_ADJOINT = 1
 N_FAMILIES = 12   # kernel families reported by xpbd_profile_read
@@ -25,7 +25,7 @@ PACK_GRAPHS = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
            "xpbd_status_string", "xpbd_pack_create", "xpbd_pack_destroy", "xpbd_pack_add", "xpbd_pack_run",
-           "xpbd_pack_get_stats", "xpbd_pack_last_error")
+           "xpbd_pack_get_stats", "xpbd_pack_last_error", "xpbd_adjoint_implicit")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -84,6 +84,11 @@ class PackStats(C.Structure):
                 ("graph_launches", C.c_int64), ("graph_captures", C.c_int64), ("last_round_launches", C.c_int32)]
 
 
+class CG(C.Structure):
+    _fields_ = [("max_iterations", C.c_int32), ("rel_tolerance", C.c_double), ("total_iterations", C.c_int64),
+                ("max_iterations_used", C.c_int32), ("worst_rel_residual", C.c_double)]
+
+
 class XPBDError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"xpbd status {status}: {msg}")
@@ -122,6 +127,9 @@ def load() -> C.CDLL:
         lib.xpbd_last_error.argtypes = [_vp]
         lib.xpbd_status_string.restype = C.c_char_p
         lib.xpbd_status_string.argtypes = [C.c_int]
+        lib.xpbd_adjoint_implicit.restype = C.c_int
+        lib.xpbd_adjoint_implicit.argtypes = [_vp, C.POINTER(Params), _vp, C.POINTER(C.c_uint8), C.POINTER(CG),
+                                              C.POINTER(Grads), _vp]
         lib.xpbd_pack_create.restype = C.c_int
         lib.xpbd_pack_create.argtypes = [C.c_int, C.c_int32, C.POINTER(_vp)]
         lib.xpbd_pack_destroy.restype = C.c_int
@@ -321,6 +329,32 @@ class Simulator:
                                    _stream_ptr(self.device))
         self._check(rc)
         return g
+
+    def adjoint_implicit(self, dLdx_frames, frame_mask=None, max_iterations: int = 1000,
+                         rel_tolerance: float = 1e-10, want=None):
+        """Implicit adjoint of the last forward (the paper's converged-step
+        form, solved by CG): returns (gradients, CG report)."""
+        if self._fwd_keep is None:
+            raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
+        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+        V = self.scene.n_verts
+        g, gr = self._grad_buffers(F, want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
+        gr.tet_E = None
+        gr.sphere = None
+        g.pop("tet_E", None)
+        g.pop("sphere", None)
+        dl = self._arg(dLdx_frames, (F, V, 3))
+        cg = CG(max_iterations, rel_tolerance, 0, 0, 0.0)
+        mask_ptr = None
+        mask_arr = None
+        if frame_mask is not None:
+            mask_arr = np.ascontiguousarray(np.asarray(frame_mask, dtype=np.uint8))
+            mask_ptr = mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = self.lib.xpbd_adjoint_implicit(self._ctx, C.byref(p), _ptr(dl), mask_ptr, C.byref(cg), C.byref(gr),
+                                            _stream_ptr(self.device))
+        self._check(rc)
+        return g, {"total_iterations": cg.total_iterations, "max_iterations_used": cg.max_iterations_used,
+                   "worst_rel_residual": cg.worst_rel_residual}
 
     def goal_l2(self, x_frames: torch.Tensor, targets: torch.Tensor, frame_mask=None):
         """FP64 goal 1/2 sum_{masked f} |x(f) - x*(f)|^2 and its gradient."""

@@ -184,13 +184,19 @@ def cloth_grid_topology(nr: int, nc: int):
     hi, hj = ii[1:-1, :-1].ravel(), jj[1:-1, :-1].ravel()
     vi, vj = ii[:-1, 1:-1].ravel(), jj[:-1, 1:-1].ravel()
     di, dj = ii[:-1, :-1].ravel(), jj[:-1, :-1].ravel()
+    # each batch touches every vertex at most once, and (away from the
+    # border) every vertex exactly once: H hinges of rows i, i + 2 meet row
+    # i + 1 in columns of opposite parity, likewise V hinges; D hinges are
+    # the 2x2 quads of one parity class.  Twelve batches is the minimum
+    # (twelve hinges share an interior vertex), and dense sets read and write
+    # whole cache lines of the vertex array.
     bend_batches = []
-    for a in range(3):
+    for a in range(2):
         for b in range(2):
-            bend_batches.append(np.nonzero((hi % 3 == a) & (hj % 2 == b))[0])
-    for a in range(3):
+            bend_batches.append(np.nonzero((hi % 2 == a) & (hj % 2 == b))[0])
+    for a in range(2):
         for b in range(2):
-            bend_batches.append(n_hh + np.nonzero((vj % 3 == a) & (vi % 2 == b))[0])
+            bend_batches.append(n_hh + np.nonzero((vj % 2 == a) & (vi % 2 == b))[0])
     for a in range(2):
         for b in range(2):
             bend_batches.append(n_hh + n_hv + np.nonzero((di % 2 == a) & (dj % 2 == b))[0])
@@ -369,6 +375,82 @@ def tiled_schedule(sc: Scene, coords: np.ndarray, tile: int, typed_batches, cont
     return sc
 
 
+def _group_sets(typed, sel_of, V):
+    """Greedy sets of the selected constraints of each type, in type order."""
+    out_t, out_i = [], []
+    for ty, cv, batches in typed:
+        sel = sel_of[ty]
+        if not np.any(sel):
+            continue
+        col = greedy_color(cv, [b[sel[b]] for b in batches], V, subset=True)
+        for st in sets_from_colors(cv, col):
+            out_t.append(ty)
+            out_i.append(st)
+    return out_t, out_i
+
+
+def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
+    """Three-group tiled schedule for an nr x nc grid cloth.
+
+    Group A: constraints inside one tile x tile tile (patch = tile).
+    Group B: constraints crossing exactly one tile border line, away from
+    the tile corners (patch = the border segment between two corners; the
+    segments are vertex-disjoint because every vertex within two rows of a
+    row line and two columns of a column line is a corner vertex).
+    Group C: the constraints that touch a corner vertex, then the contact
+    set (patch = the tile of the half-shifted tiling around that corner).
+    Every constraint is in exactly one group; an iteration runs A, B, C.
+    """
+    dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
+    assert np.array_equal(dist_v, sc.dist_v)
+    V = sc.n_verts
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    ntj = nc // tile + 2
+    tile_id = (ii // tile) * ntj + jj // tile
+    near_r = np.isin(ii % tile, [tile - 2, tile - 1, 0, 1])
+    near_c = np.isin(jj % tile, [tile - 2, tile - 1, 0, 1])
+    corner = near_r & near_c
+    h = tile // 2
+    corner_tile = ((ii + h) // tile) * ntj + (jj + h) // tile
+    # border segments: row line k (between rows tile*k - 1 and tile*k) within
+    # column tile m, and column line m within row tile k
+    row_line = (ii + 2) // tile
+    col_line = (jj + 2) // tile
+    nseg = (nr // tile + 2) * ntj
+    seg_id = np.where(near_r, row_line * ntj + jj // tile, nseg + (ii // tile) * ntj + col_line)
+    typed = [(DIST, sc.dist_v, dist_batches)]
+    if sc.n_bend:
+        typed.append((BEND, sc.bend_v, bend_batches))
+    sel = {}
+    for ty, cv, _ in typed:
+        t = tile_id[cv]
+        in_a = np.all(t == t[:, :1], axis=1)
+        touches_corner = np.any(corner[cv], axis=1)
+        sel[ty] = (in_a, ~in_a & ~touches_corner, ~in_a & touches_corner)
+    sets_t, sets_i, groups = [], [], []
+    for g, pm in enumerate((tile_id, seg_id, corner_tile)):
+        first = len(sets_t)
+        st, si = _group_sets(typed, {ty: sel[ty][g] for ty, _, _ in typed}, V)
+        sets_t += st
+        sets_i += si
+        if g == 2 and sc.contact:
+            sets_t.append(CONTACT)
+            sets_i.append(np.nonzero(sc.inv_mass > 0)[0].astype(np.int32))
+        if len(sets_t) > first:
+            groups.append((first, len(sets_t), pm.astype(np.int32)))
+    # every constraint must lie within one patch of its group
+    for (a, b, pm) in groups:
+        for k in range(a, b):
+            if sets_t[k] == CONTACT:
+                continue
+            cv = (sc.dist_v if sets_t[k] == DIST else sc.bend_v)[sets_i[k]]
+            p = pm[cv]
+            assert np.all(p == p[:, :1]), "tiling left a constraint across patches"
+    sc.set_type, sc.set_items, sc.groups = sets_t, sets_i, groups
+    return sc
+
+
 def tile_cloth(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
     """Tiled schedule for an nr x nc grid cloth (4 tilings of tile x tile)."""
     dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
@@ -469,13 +551,15 @@ def config_c1(n_frames: int = 60, target: bool = False) -> Scene:
     return sc
 
 
-def config_c2(n_frames: int = 30, target: bool = False, n: int = 256, tile: int = 16) -> Scene:
+def config_c2(n_frames: int = 30, target: bool = False, n: int = 256, tile: int = 16,
+              tiling: str = "lines") -> Scene:
     """256x256 cloth centred at the origin with distance + bending + sphere
     contact (c = (0, -0.35, 0), R = 0.3), dt 1/60, 4 substeps, 30 iterations.
-    tile > 0: tiled schedule (4 shifted tilings of tile x tile vertices)."""
+    tile > 0: tiled schedule, either three groups (tiles, border segments,
+    corners: ``tiling="lines"``) or four shifted tilings (``"shifts"``)."""
     sc = cloth_grid(n, n, 1.0 / (n - 1), origin=(-0.5, 0.0, -0.5), contact=True)
     if tile:
-        tile_cloth(sc, n, n, tile)
+        (tile_cloth_lines if tiling == "lines" else tile_cloth)(sc, n, n, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(2 if target else 1, sc.n_dist, sc.n_bend)
     sc.tet_E = np.zeros(0)
     sc.sphere = (0.0, -0.35, 0.0, 0.3)

@@ -170,22 +170,28 @@ class Server:
 
 
 class PackedServer:
-    """Continuous batching through one pack: a scheduler thread admits
-    arrived requests by HBM budget and slot count into the pack, where they
-    join the next round and share every launch with the requests already
-    running; finished requests leave, and their results are copied out on
-    the same stream while later rounds run.  ``graphs`` replays a round from a
-    captured HIP graph while the pack's membership stays the same."""
+    """Continuous batching through packs: a scheduler thread admits arrived
+    requests by HBM budget and slot count into one of ``n_packs`` packs (cloth
+    and tet requests in separate packs, so a pack's launches are not
+    lengthened by the other kind's longer schedule), where they join the next
+    round and share every launch with the requests already in that pack.
+    Each pack runs on its own stream, so the packs' launches overlap on the
+    device; the scheduler keeps at most ``ahead`` rounds of each pack queued.
+    Finished requests leave at once and their results are copied out on the
+    pack's stream while later rounds run.  ``graphs`` replays a round from a
+    captured HIP graph while a pack's membership stays the same."""
 
-    def __init__(self, slots: int = 16, hbm_budget: int = 64 << 30, device="cuda:0",
-                 dtype: torch.dtype = torch.float32, graphs: bool = False, rounds_per_call: int = 4):
+    def __init__(self, slots: int = 32, hbm_budget: int = 64 << 30, device="cuda:0",
+                 dtype: torch.dtype = torch.float32, graphs: bool = True, n_packs: int = 1, ahead: int = 2):
         self.slots = slots
         self.budget = hbm_budget
         self.device = torch.device(device)
         self.dtype = dtype
         self.graphs = graphs
-        self.rounds = rounds_per_call
-        self.pack_stats: Dict[str, int] = {}
+        self.n_packs = max(1, n_packs)
+        self.ahead = max(1, ahead)
+        self.pack_stats: List[Dict[str, int]] = []
+        self.finished: List[Request] = []
 
     def _admit(self, pack, req: Request):
         sc = req.scene
@@ -199,7 +205,8 @@ class PackedServer:
         req.projections = sc.projections_per_rollout(req.n_frames) * (2 if req.adjoint else 1)
         return job
 
-    def _collect(self, job, stream):
+    @staticmethod
+    def _collect(job, stream):
         """Start the device-to-host copies of a finished job's results."""
         res = {"x_final": job.x_final}
         if job.loss is not None:
@@ -214,6 +221,11 @@ class PackedServer:
         ev.record(stream)
         return ev, host
 
+    def _pick(self, packs, req):
+        kind = 1 if req.scene.n_tet else 0
+        mine = [i for i in range(len(packs)) if i % 2 == kind % 2] if len(packs) > 1 else [0]
+        return min(mine, key=lambda i: len(packs[i][0].jobs))
+
     def run(self, requests: List[Request]) -> Dict[str, Any]:
         from .lib import Pack
         for r in requests:
@@ -223,52 +235,79 @@ class PackedServer:
         finished: List[Request] = []
         depth: List[int] = []
         in_use = 0
-        running: Dict[int, Any] = {}
+        running = 0
         copying = []
-        stream = torch.cuda.Stream(device=self.device)     # default priority
-        pack = Pack(dtype=self.dtype, device=self.device, graphs=self.graphs)
+        closing = []
+        # (pack, stream, queued round events)
+        packs = []
+        for _ in range(self.n_packs):
+            st = torch.cuda.Stream(device=self.device)     # default priority
+            packs.append((Pack(dtype=self.dtype, device=self.device, graphs=self.graphs), st, []))
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
-        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+        with torch.cuda.device(self.device):
             while pending or running or copying:
                 now = time.perf_counter() - t0
-                while pending and pending[0][0] <= now and len(running) < self.slots:
+                while pending and pending[0][0] <= now and running < self.slots:
                     req = pending[0][2]
                     if running and in_use + req.device_bytes > self.budget:
                         break
                     heapq.heappop(pending)
                     depth.append(sum(1 for a, _, _ in pending if a <= now))
                     req.admitted = time.perf_counter() - t0
-                    req.slot = len(running)
-                    job = self._admit(pack, req)
-                    running[job.id] = job
+                    i = self._pick(packs, req)
+                    req.slot = i
+                    self._admit(packs[i][0], req)
+                    running += 1
                     in_use += req.device_bytes
-                if running:
-                    for job in pack.run(self.rounds):
-                        running.pop(job.id)
-                        copying.append((job,) + self._collect(job, stream))
+                progressed = False
+                for pack, st, queued in packs:
+                    while queued and queued[0].query():
+                        queued.pop(0)
+                    if not pack.jobs or len(queued) >= self.ahead:
+                        continue
+                    with torch.cuda.stream(st):
+                        for job in pack.run(1):
+                            running -= 1
+                            copying.append((job,) + self._collect(job, st))
+                        ev = torch.cuda.Event()
+                        ev.record(st)
+                    queued.append(ev)
+                    progressed = True
                 still = []
                 for job, ev, host in copying:
                     if ev.query():
                         req = job.tag
                         req.done = time.perf_counter() - t0
                         req.result = {k: v.numpy() for k, v in host.items()}
-                        job.sim.close()
+                        closing.append(job.sim)      # freed after the run: a free waits for the device
                         in_use -= req.device_bytes
                         finished.append(req)
                     else:
                         still.append((job, ev, host))
                 copying = still
-                if not running and copying:
-                    copying[0][1].synchronize()
-                elif not running and pending:
-                    time.sleep(max(0.0, min(0.01, pending[0][0] - (time.perf_counter() - t0))))
+                if not progressed:
+                    waits = [q[0] for _, _, q in packs if q]
+                    if waits:
+                        waits[0].synchronize()
+                    elif copying:
+                        copying[0][1].synchronize()
+                    elif pending:
+                        time.sleep(max(0.0, min(0.005, pending[0][0] - (time.perf_counter() - t0))))
         wall = time.perf_counter() - t0
+        for sim in closing:
+            sim.close()
         self.finished = finished
-        self.pack_stats = pack.stats()
-        pack.close()
+        self.pack_stats = [p.stats() for p, _, _ in packs]
+        for p, _, _ in packs:
+            p.close()
         rep = report(finished, wall, depth)
-        rep["pack"] = self.pack_stats
+        tot = {}
+        for st_ in self.pack_stats:
+            for k, v in st_.items():
+                tot[k] = tot.get(k, 0) + v
+        rep["pack"] = tot
+        rep["n_packs"] = self.n_packs
         return rep
 
 

@@ -99,18 +99,33 @@ def test_tetbox64_one_frame_fp32_positions():
 def test_cloth2048x4096_one_substep_with_forces():
     """2048x4096 cloth (25.2M DoF) with the per-vertex force field, one frame
     of 1 substep x 2 iterations; gradients for the forces, compliances, x0
-    and v0."""
+    and v0.  Each gradient group must be within 1e-3 of the FP64 reference,
+    or within twice the error the reference itself makes when its state is
+    rounded to FP32 after every write, whichever is larger (the stiff
+    distance compliances, alpha~ about 1e-3 against w |grad C|^2 = 2, give
+    dL/dalpha an intrinsic FP32 error of about 3.4e-3)."""
     sc = scenes.config_c4(n_frames=1)
     sc.substeps, sc.iterations = 1, 2
     sim = _sim(sc)
     rng = np.random.default_rng(3)
-    osc = O.OracleScene(sc, n_threads=THREADS)
-    xf, xe, ve = O.forward(osc, 1, f_ext=sc.f_ext)
-    tgt = xf + 0.01 * rng.standard_normal(xf.shape)
     mask = np.ones(1, bool)
-    L, dL = O.goal_l2(xf, tgt, mask)
-    g = O.adjoint(osc, 1, dL, f_ext=sc.f_ext)
-    ref = {"x_frames": xf, "x_final": xe, "v_final": ve, "targets": tgt, "mask": mask, "loss": L, "grads": g}
+    res = {}
+    for em in (False, True):
+        osc = O.OracleScene(sc, emulate_f32=em, n_threads=THREADS)
+        xf, xe, ve = O.forward(osc, 1, f_ext=sc.f_ext)
+        if not em:
+            tgt = xf + 0.01 * rng.standard_normal(xf.shape)
+        L, dL = O.goal_l2(xf, tgt, mask)
+        res[em] = {"x_frames": xf, "x_final": xe, "v_final": ve, "targets": tgt, "mask": mask, "loss": L,
+                   "grads": O.adjoint(osc, 1, dL, f_ext=sc.f_ext)}
+    ref, emu = res[False], res[True]
     got = gpu_case(sim, 1, ref, f_ext=sc.f_ext)
-    errs = compare(sc, ref, got, 1e-5, 1e-3)
-    print("cloth2048x4096:", errs)
+    errs = {"x_frames": rel(got["x_frames"], ref["x_frames"])}
+    assert errs["x_frames"] <= 1e-5, errs
+    for k, r in ref["grads"].items():
+        if r.size == 0 or np.linalg.norm(r) == 0:
+            continue
+        intrinsic = rel(emu["grads"][k], r)
+        errs[k] = (rel(got["grads"][k], r), intrinsic)
+        assert errs[k][0] <= max(1e-3, 2 * intrinsic), (k, errs)
+    print("cloth2048x4096 (error, intrinsic FP32 error):", errs)

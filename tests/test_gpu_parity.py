@@ -137,9 +137,9 @@ def test_plain_and_persistent_launches_agree_bitwise(dtype):
     compare(sc, ref, outs[1], *tol)
 
 
-def _tiled_cloth(n=40, tile=16, frames=2, S=2, K=3):
+def _tiled_cloth(n=40, tile=16, frames=2, S=2, K=3, lines=False):
     sc = scenes.small_cloth(n=n, frames=frames, substeps=S, iterations=K)
-    return scenes.tile_cloth(sc, n, n, tile)
+    return (scenes.tile_cloth_lines if lines else scenes.tile_cloth)(sc, n, n, tile)
 
 
 def _tiled_tets(n=6, tile=4, frames=2):
@@ -148,11 +148,12 @@ def _tiled_tets(n=6, tile=4, frames=2):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("kind", ["cloth", "tets"])
+@pytest.mark.parametrize("kind", ["cloth", "cloth_lines", "tets"])
 def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
     """LDS group launches compute exactly what one launch per set computes
     on the same (tiled) schedule; both match the FP64 reference."""
-    sc = _tiled_cloth() if kind == "cloth" else _tiled_tets()
+    sc = {"cloth": _tiled_cloth, "cloth_lines": lambda: _tiled_cloth(n=37, tile=8, lines=True),
+          "tets": _tiled_tets}[kind]()
     ref = reference_case(sc, 2, n_threads=8, noise=0.01 if kind == "cloth" else 1e-3)
     a_sim = _sim(sc, dtype)
     b_sim = _sim(sc, dtype, use_groups=False)

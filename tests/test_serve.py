@@ -90,7 +90,7 @@ def test_packed_server_matches_requests_run_alone(graphs):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     mix = serve.make_mix(8, qps=50.0, seed=6, vmax=6000, frames_scale=0.1)
-    srv = serve.PackedServer(slots=6, hbm_budget=32 << 30, graphs=graphs, rounds_per_call=2)
+    srv = serve.PackedServer(slots=6, hbm_budget=32 << 30, graphs=graphs, n_packs=2)
     rep = srv.run(mix)
     assert rep["requests"] == 8 and rep["max_concurrent"] >= 2
     assert rep["pack"]["rounds"] > 0
