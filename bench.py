@@ -155,20 +155,23 @@ def cpu_baseline(name, sc, max_projections: int = 60_000_000):
     if per_it * sc.iterations * sc.substeps > max_projections:
         sample.substeps = 1
         sample.iterations = max(1, min(sc.iterations, max_projections // max(per_it, 1)))
+    frames = 1
+    if sample.substeps == sc.substeps and sample.iterations == sc.iterations:
+        frames = int(max(1, min(sc.n_frames, max_projections // max(sc.projections_per_rollout(1), 1))))
     osc = O.OracleScene(sample, n_threads=threads)
     kw = {}
     if sc.f_ext is not None:
-        kw["f_ext"] = sc.f_ext[:1]
+        kw["f_ext"] = sc.f_ext[:frames]
     t0 = time.perf_counter()
-    xf, _, _ = O.forward(osc, 1, **kw)
+    xf, _, _ = O.forward(osc, frames, **kw)
     t1 = time.perf_counter()
     dL = xf - xf.mean(axis=1, keepdims=True)
-    O.adjoint(osc, 1, dL, **kw)
+    O.adjoint(osc, frames, dL, **kw)
     t2 = time.perf_counter()
-    proj = sample.projections_per_rollout(1)
+    proj = sample.projections_per_rollout(frames)
     value = 2 * proj / (t2 - t0)
     return {"value": value, "unit": "projections/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 frame of the workload with {sample.substeps} substep(s) x {sample.iterations} "
+            "sample": f"{frames} frame(s) of the workload with {sample.substeps} substep(s) x {sample.iterations} "
                       f"iterations ({proj} forward + {proj} reverse projections, FP64): "
                       f"forward {t1 - t0:.2f} s, adjoint incl. recompute {t2 - t1:.2f} s"}
 

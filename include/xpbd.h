@@ -140,6 +140,8 @@ typedef struct {
                                   sets with a grid-wide barrier between sets */
   int32_t persistent_blocks; /* workgroups of the persistent launch, 0 = sized to the
                                 largest set (capped at what the device co-schedules) */
+  int32_t block_size;        /* workgroup size of the one-launch-per-set kernels: a power
+                                of two in [64, 1024], 0 = 256; results do not depend on it */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral
@@ -217,8 +219,11 @@ xpbd_status xpbd_goal_l2(xpbd_ctx ctx, const void* x_frames, const void* targets
  * K = sum_j (lambda_j Hess C_j - grad C_j grad C_j^T / alpha~_j) (Sec. 4.3
  * partials).  On the free vertices this is the symmetric system (M - K) y =
  * xbar, w = M y, solved by Jacobi-preconditioned conjugate gradients in FP64
- * with a matrix-free operator; no positive-definite projection is applied,
- * so a system that is not positive definite fails with XPBD_ERR_SOLVER.
+ * with a matrix-free operator.  With cg->pd_projection each constraint's
+ * block -lambda_j Hess C_j is first replaced by its positive semidefinite
+ * part (eigenvalues below zero dropped; Sec. 4.3.3), which makes the system
+ * positive definite; without it, a system that is not positive definite
+ * fails with XPBD_ERR_SOLVER.
  * Then vbar = h w (free vertices), dL/df_ext += h w_inv vbar, xbar = w -
  * vbar_old / h, and dL/dalpha_j += (grad C_j . y)(-lambda_j / alpha~_j) / h^2.
  * Frames are recomputed from the forward's checkpoints.  It differs from
@@ -233,6 +238,8 @@ xpbd_status xpbd_goal_l2(xpbd_ctx ctx, const void* x_frames, const void* targets
 typedef struct {
   int32_t max_iterations;       /* in: CG iterations per substep, >= 1 */
   double rel_tolerance;         /* in: stop at |r| <= rel_tolerance |xbar| */
+  int32_t pd_projection;        /* in: 1 = project each constraint's block -lambda Hess C
+                                   to positive semidefinite first (Sec. 4.3.3) */
   int64_t total_iterations;     /* out */
   int32_t max_iterations_used;  /* out: most iterations one substep took */
   double worst_rel_residual;    /* out */

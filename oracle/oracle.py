@@ -70,6 +70,7 @@ def _load():
         lib.orc_forward.restype = C.c_int
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint_implicit.restype = C.c_int
+        lib.orc_psd_project.restype = C.c_int
         lib.orc_constraint.restype = C.c_int
         lib.orc_rest_data.restype = C.c_int
         lib.orc_max_threads.restype = C.c_int
@@ -190,8 +191,19 @@ def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=
     return g
 
 
-def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, **params):
-    """Converged-limit adjoint of Eq. adjointXPBD (tiny meshes)."""
+def psd_project(a):
+    """Projection of a symmetric matrix onto the PSD cone (Jacobi eigen)."""
+    a = np.array(a, np.float64, order="C")
+    n = a.shape[0]
+    rc = _load().orc_psd_project(C.c_int(n), _d(a))
+    if rc:
+        raise RuntimeError(f"orc_psd_project failed ({rc})")
+    return a
+
+
+def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, pd: bool = False, **params):
+    """Converged-limit adjoint of Eq. adjointXPBD (tiny meshes); ``pd``
+    projects each constraint's Hessian block to PSD first (Sec. 4.3.3)."""
     sc = osc.sc
     V = sc.n_verts
     x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)
@@ -203,7 +215,8 @@ def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, **
          "f_ext": np.zeros((n_frames, V, 3))}
     rc = _load().orc_adjoint_implicit(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0),
                                       _d(dLdx), _d(g["x0"]), _d(g["v0"]),
-                                      _d(g["dist_alpha"]), _d(g["bend_alpha"]), _d(g["f_ext"]))
+                                      _d(g["dist_alpha"]), _d(g["bend_alpha"]), _d(g["f_ext"]),
+                                      C.c_int(1 if pd else 0))
     if rc:
         raise RuntimeError(f"orc_adjoint_implicit failed ({rc})")
     return g

@@ -704,9 +704,65 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
 // lambda_j = -C_j / alpha~_j at the end-of-substep state (contacts active
 // where C < 0 there).  Same outputs as orc_adjoint for the compliances of
 // distance and bending rows, x0, v0 and f.
+// Projection of a symmetric n x n matrix (row-major, in place) onto the
+// positive semidefinite cone: eigen-decomposition by cyclic Jacobi rotations,
+// negative eigenvalues set to zero, matrix rebuilt (Sec. 4.3.3 projects the
+// derivative blocks this way before the CG solve).
+int orc_psd_project(int n, double* a) {
+  if (n < 1 || n > NG) return 1;
+  std::vector<double> A(a, a + (size_t)n * n), Vm((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Vm[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int pp = 0; pp < n - 1; ++pp)
+      for (int q = pp + 1; q < n; ++q) {
+        double apq = A[(size_t)pp * n + q];
+        if (apq == 0.0) continue;
+        // rotation angle that zeroes A[p][q]: tan(2 phi) = 2 apq / (aqq - app)
+        double theta = (A[(size_t)q * n + q] - A[(size_t)pp * n + pp]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {   // A <- A J (columns p, q)
+          double akp = A[(size_t)k * n + pp], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + pp] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // A <- J^T A (rows p, q)
+          double apk = A[(size_t)pp * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)pp * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {   // V <- V J
+          double vkp = Vm[(size_t)k * n + pp], vkq = Vm[(size_t)k * n + q];
+          Vm[(size_t)k * n + pp] = cs * vkp - sn * vkq;
+          Vm[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double lk = A[(size_t)k * n + k];
+        if (lk > 0.0) acc += Vm[(size_t)i * n + k] * lk * Vm[(size_t)j * n + k];
+      }
+      a[(size_t)i * n + j] = acc;
+    }
+  return 0;
+}
+
+// pd != 0: each constraint's Hessian block -lambda_j Hess C_j is projected to
+// positive semidefinite before assembly (the rank-one block grad C grad C^T /
+// alpha~ is already), so the system is symmetric positive definite.
 int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                          const double* dLdx, double* g_x0, double* g_v0, double* g_dist_alpha,
-                         double* g_bend_alpha, double* g_f) {
+                         double* g_bend_alpha, double* g_f, int pd) {
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);
@@ -759,19 +815,31 @@ int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const d
       for (const Act& a : act) {
         const Row& r = a.r;
         double lamj = -a.e.C / a.at;
-        // Hessian columns via HVPs with unit directions
+        const int nl = 3 * r.nv;
+        // local block N = -lambda Hess C, columns via HVPs with unit directions
+        double N[NG * NG];
         for (int k2 = 0; k2 < r.nv; ++k2)
           for (int b2 = 0; b2 < 3; ++b2) {
             double dir[NG] = {0};
             dir[3 * k2 + b2] = 1.0;
             double hv[NG];
             eval_hvp(&c.m, p, r, xe.data(), dir, hv);
-            // modify: reuse full-index eval by mapping the row's local slots
+            for (int i = 0; i < nl; ++i) N[i * nl + 3 * k2 + b2] = -lamj * hv[i];
+          }
+        if (pd) {
+          // symmetrise exactly, then project
+          for (int i = 0; i < nl; ++i)
+            for (int j = i + 1; j < nl; ++j) N[i * nl + j] = N[j * nl + i] = 0.5 * (N[i * nl + j] + N[j * nl + i]);
+          if (orc_psd_project(nl, N)) return 5;
+        }
+        for (int k2 = 0; k2 < r.nv; ++k2)
+          for (int b2 = 0; b2 < 3; ++b2) {
             size_t col = 3 * (size_t)r.v[k2] + b2;
             for (int k1 = 0; k1 < r.nv; ++k1)
               for (int b1 = 0; b1 < 3; ++b1) {
                 size_t row = 3 * (size_t)r.v[k1] + b1;
-                double Kv = lamj * hv[3 * k1 + b1] - a.e.g[3 * k1 + b1] * a.e.g[3 * k2 + b2] / a.at;
+                // K = lambda Hess C - grad C grad C^T / alpha~ = -(N + g g^T / alpha~)
+                double Kv = -N[(3 * k1 + b1) * nl + 3 * k2 + b2] - a.e.g[3 * k1 + b1] * a.e.g[3 * k2 + b2] / a.at;
                 double w = s->inv_mass[r.v[k1]];
                 // (I - M^-1 K): entry (row, col) ; we store the transpose
                 A[col * n3 + row] -= w * Kv;

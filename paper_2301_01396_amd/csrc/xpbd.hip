@@ -80,6 +80,7 @@ struct xpbd_ctx_s {
   size_t budget;
   int gamma_one;
   int tape_mode_opt;
+  int block = kBlock;   // workgroup size of the per-set kernels
   int tape_mode_used = 0;
   double tau = 0, alpha_c = 0;
   std::vector<SetInfo> sets;
@@ -326,18 +327,19 @@ template <class T> struct Ops {
   // ------------------------------------------------------------ plain launches (one per set)
   static void project(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, V4* tape, hipStream_t st) {
     if (si.count == 0) return;
-    unsigned nb = nblocks(si.count);
+    const int bs = c->block;
+    unsigned nb = nblocks(si.count, bs);
     xpbd_ctx_s::Ev ev;
     bool on;
     prof_begin(c, st, 2 * si.type, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
 #define XPBD_LAUNCH(KERN, TP)                                                                     \
   do {                                                                                            \
     if (first) {                                                                                  \
-      if (tape) KERN<T, true, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);     \
-      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);         \
+      if (tape) KERN<T, true, true><<<nb, bs, 0, st>>>(D, si.begin, si.count, (TP*)tape);         \
+      else KERN<T, true, false><<<nb, bs, 0, st>>>(D, si.begin, si.count, (TP*)tape);             \
     } else {                                                                                      \
-      if (tape) KERN<T, false, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);    \
-      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, (TP*)tape);        \
+      if (tape) KERN<T, false, true><<<nb, bs, 0, st>>>(D, si.begin, si.count, (TP*)tape);        \
+      else KERN<T, false, false><<<nb, bs, 0, st>>>(D, si.begin, si.count, (TP*)tape);            \
     }                                                                                             \
   } while (0)
     switch (si.type) {
@@ -353,7 +355,8 @@ template <class T> struct Ops {
   static void reverse(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, bool last, const V4* tape,
                       hipStream_t st) {
     if (si.count == 0) return;
-    unsigned nb = nblocks(si.count);
+    const int bs = c->block;
+    unsigned nb = nblocks(si.count, bs);
     xpbd_ctx_s::Ev ev;
     bool on;
     prof_begin(c, st, 2 * si.type + 1, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
@@ -362,11 +365,11 @@ template <class T> struct Ops {
 #define XPBD_RLAUNCH(KERN)                                                                        \
   do {                                                                                            \
     if (first) {                                                                                  \
-      if (last) KERN<T, true, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);          \
-      else KERN<T, true, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);              \
+      if (last) KERN<T, true, true><<<nb, bs, 0, st>>>(D, si.begin, si.count, tape);              \
+      else KERN<T, true, false><<<nb, bs, 0, st>>>(D, si.begin, si.count, tape);                  \
     } else {                                                                                      \
-      if (last) KERN<T, false, true><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);         \
-      else KERN<T, false, false><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, tape);             \
+      if (last) KERN<T, false, true><<<nb, bs, 0, st>>>(D, si.begin, si.count, tape);             \
+      else KERN<T, false, false><<<nb, bs, 0, st>>>(D, si.begin, si.count, tape);                 \
     }                                                                                             \
   } while (0)
     switch (si.type) {
@@ -778,6 +781,10 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   if (o->tape_mode < 0 || o->tape_mode > 3) fail(XPBD_ERR_INVALID, "bad tape_mode");
   if (o->launch_mode < 0 || o->launch_mode > 2 || o->persistent_blocks < 0)
     fail(XPBD_ERR_INVALID, "bad launch_mode / persistent_blocks");
+  if (o->block_size != 0 &&
+      (o->block_size < 64 || o->block_size > kMaxBlock || (o->block_size & (o->block_size - 1)) != 0))
+    fail(XPBD_ERR_INVALID, "block_size must be 0 or a power of two in [64, %d]", kMaxBlock);
+  c->block = o->block_size ? o->block_size : kBlock;
   c->dtype = o->dtype;
   c->tsz = o->dtype == XPBD_F32 ? 4 : 8;
   c->V = m->n_verts;

@@ -21,12 +21,24 @@ template <class T> struct ImpOps {
     double* part; // [nblocks(V)]
     double* sum;  // [1]
     int* bad;     // [1]
+    double* nb[4];  // projected blocks per constraint type (PD projection only)
   };
 
-  static Work work(xpbd_ctx c) {
+  static size_t block_doubles(xpbd_ctx c, int ty) {
+    switch (ty) {
+      case XPBD_DIST: return (size_t)c->n_dist * 36;
+      case XPBD_BEND: return (size_t)c->n_bend * 144;
+      case XPBD_TET: return (size_t)c->n_tet * 288;
+      default: return (size_t)c->n_contact * 9;
+    }
+  }
+
+  static Work work(xpbd_ctx c, bool pd) {
     const size_t V = (size_t)c->V, nb = nblocks(V);
-    const size_t need = align256((size_t)c->S * V * sizeof(V4)) + 6 * align256(V * sizeof(D4)) +
-                        align256(nb * sizeof(double)) + 256 + 256;
+    size_t need = align256((size_t)c->S * V * sizeof(V4)) + 6 * align256(V * sizeof(D4)) +
+                  align256(nb * sizeof(double)) + 256 + 256;
+    if (pd)
+      for (int ty = 0; ty < 4; ++ty) need += align256(block_doubles(c, ty) * sizeof(double));
     if (c->imp_cap < need) {
       c->release(c->imp_buf);
       c->imp_cap = 0;
@@ -46,31 +58,47 @@ template <class T> struct ImpOps {
     w.part = (double*)take(nb * sizeof(double));
     w.sum = (double*)take(sizeof(double));
     w.bad = (int*)take(sizeof(int));
+    for (int ty = 0; ty < 4; ++ty) w.nb[ty] = pd && block_doubles(c, ty) ? (double*)take(block_doubles(c, ty) * sizeof(double)) : nullptr;
     return w;
   }
 
   template <int MODE>
   static void sets(xpbd_ctx c, const Dev<T>& D, const V4* XE, const D4* P, D4* Q, double ih2, int* bad,
-                   hipStream_t st) {
+                   const Work& w, hipStream_t st) {
+    // the projected blocks are built with one thread per constraint and a
+    // 12 x 12 eigen-decomposition each: smaller workgroups
+    const int bs = MODE == IMP_BUILD ? 64 : kBlock;
     for (const SetInfo& si : c->sets) {
       if (si.count == 0) continue;
       if (MODE == IMP_GRAD && (si.type == XPBD_TET || si.type == XPBD_CONTACT)) continue;
-      unsigned nb = nblocks(si.count);
+      unsigned nb = nblocks(si.count, bs);
+      double* NB = w.nb[si.type];
       switch (si.type) {
-        case XPBD_DIST: k_imp_set<T, 0, MODE><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad); break;
-        case XPBD_BEND: k_imp_set<T, 1, MODE><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad); break;
-        case XPBD_TET: k_imp_set<T, 2, MODE><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad); break;
-        default: k_imp_set<T, 3, MODE><<<nb, kBlock, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad); break;
+        case XPBD_DIST:
+          k_imp_set<T, 0, MODE><<<nb, bs, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad, NB);
+          break;
+        case XPBD_BEND:
+          k_imp_set<T, 1, MODE><<<nb, bs, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad, NB);
+          break;
+        case XPBD_TET:
+          k_imp_set<T, 2, MODE><<<nb, bs, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad, NB);
+          break;
+        default:
+          k_imp_set<T, 3, MODE><<<nb, bs, 0, st>>>(D, si.begin, si.count, XE, P, Q, ih2, bad, NB);
+          break;
       }
       Ops<T>::check_launch();
     }
   }
 
-  // Q = (M - K) P on free vertices, -(K P) on pinned ones
-  static void apply(xpbd_ctx c, const Dev<T>& D, const V4* XE, const D4* P, D4* Q, int* bad, hipStream_t st) {
+  // Q = (M - K) P on free vertices, -(K P) on pinned ones (K with projected
+  // blocks when pd)
+  static void apply(xpbd_ctx c, const Dev<T>& D, const V4* XE, const D4* P, D4* Q, int* bad, const Work& w,
+                    bool pd, hipStream_t st) {
     k_imp_mass<T><<<nblocks(c->V), kBlock, 0, st>>>((const V4*)c->XB, P, Q, c->V);
     Ops<T>::check_launch();
-    sets<IMP_APPLY>(c, D, XE, P, Q, 0.0, bad, st);
+    if (pd) sets<IMP_APPLY_PD>(c, D, XE, P, Q, 0.0, bad, w, st);
+    else sets<IMP_APPLY>(c, D, XE, P, Q, 0.0, bad, w, st);
   }
 
   static double dot(xpbd_ctx c, const Work& w, const D4* a, const D4* b, const D4* diag, hipStream_t st) {
@@ -90,7 +118,8 @@ template <class T> struct ImpOps {
     const double h = c->h, ih2 = 1.0 / (h * h);
     Ops<T>::gather_params(c, p, st);
     Dev<T> D = Ops<T>::dev(c, p->sphere);
-    Work w = work(c);
+    const bool pd = cg->pd_projection != 0;
+    Work w = work(c, pd);
     HIPCHK(hipMemsetAsync(w.bad, 0, sizeof(int), st));
     Ops<T>::template fill<double>(c->dist_acc, 0.0, c->n_dist, st);
     Ops<T>::template fill<double>(c->bend_acc, 0.0, c->n_bend, st);
@@ -117,7 +146,12 @@ template <class T> struct ImpOps {
         const V4* XE = w.XS + (size_t)s * V;
         k_rev_velocity<T><<<nblocks(V), kBlock, 0, st>>>(D);
         Ops<T>::template fill<double>((double*)w.DG, 0.0, (size_t)4 * V, st);
-        sets<IMP_DIAG>(c, D, XE, nullptr, w.DG, 0.0, w.bad, st);
+        if (pd) {
+          sets<IMP_BUILD>(c, D, XE, nullptr, nullptr, 0.0, w.bad, w, st);
+          sets<IMP_DIAG_PD>(c, D, XE, nullptr, w.DG, 0.0, w.bad, w, st);
+        } else {
+          sets<IMP_DIAG>(c, D, XE, nullptr, w.DG, 0.0, w.bad, w, st);
+        }
         k_imp_diag<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->XB, w.DG, V);
         if (s == S - 1 && f == F - 1) {
           int bad0 = 0;
@@ -135,7 +169,7 @@ template <class T> struct ImpOps {
           double rz = dot(c, w, w.R, w.R, w.DG, st);
           rel = 1.0;
           while (it < cg->max_iterations) {
-            apply(c, D, XE, w.P, w.Q, w.bad, st);
+            apply(c, D, XE, w.P, w.Q, w.bad, w, pd, st);
             const double pq = dot(c, w, w.P, w.Q, nullptr, st);
             if (!(pq > 0.0))
               fail(XPBD_ERR_SOLVER,
@@ -154,8 +188,8 @@ template <class T> struct ImpOps {
         total += it;
         most = std::max(most, it);
         worst = std::max(worst, rel);
-        apply(c, D, XE, w.Y, w.Q, w.bad, st);
-        sets<IMP_GRAD>(c, D, XE, w.Y, nullptr, ih2, w.bad, st);
+        apply(c, D, XE, w.Y, w.Q, w.bad, w, pd, st);
+        sets<IMP_GRAD>(c, D, XE, w.Y, nullptr, ih2, w.bad, w, st);
         k_imp_finish<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, w.Y, w.Q, fb, h, V);
         Ops<T>::check_launch();
       }

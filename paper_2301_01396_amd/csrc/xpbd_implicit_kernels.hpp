@@ -26,8 +26,122 @@ __device__ __forceinline__ void add3(D4& o, V3<double> a) { o.x += a.x; o.y += a
 enum ImpMode {
   IMP_APPLY = 0,  // Q += -K P (every vertex of the constraint)
   IMP_DIAG = 1,   // Q += (grad C)^2 / alpha~ componentwise (Jacobi preconditioner)
-  IMP_GRAD = 2    // acc_j += (grad C_j . P) (-lambda_j / alpha~_j) / h^2
+  IMP_GRAD = 2,   // acc_j += (grad C_j . P) (-lambda_j / alpha~_j) / h^2
+  IMP_BUILD = 3,  // store the constraint's block -lambda Hess C projected to PSD
+  IMP_APPLY_PD = 4,  // Q += (N+ + g g^T / alpha~) P with the stored projected block N+
+  IMP_DIAG_PD = 5    // Q += diag(N+) + g^2 / alpha~
 };
+
+// Positive-semidefinite part of a symmetric n x n matrix (row-major, in
+// place, n <= 12): cyclic Jacobi rotations diagonalise it, eigenvalues below
+// zero are dropped and the matrix is rebuilt from the rest.
+__device__ inline void psd_part(int n, double* a) {
+  double v[144];
+  for (int i = 0; i < n * n; ++i) v[i] = 0.0;
+  for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, all = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double x = a[i * n + j] * a[i * n + j];
+        all += x;
+        if (i != j) off += x;
+      }
+    if (!(off > 1e-30 * all)) break;
+    for (int p = 0; p + 1 < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        // the rotation by phi with cot(2 phi) = (a_qq - a_pp) / (2 a_pq) zeroes a_pq
+        const double th = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double x = a[k * n + p], y = a[k * n + q];
+          a[k * n + p] = c * x - s * y;
+          a[k * n + q] = s * x + c * y;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double x = a[p * n + k], y = a[q * n + k];
+          a[p * n + k] = c * x - s * y;
+          a[q * n + k] = s * x + c * y;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double x = v[k * n + p], y = v[k * n + q];
+          v[k * n + p] = c * x - s * y;
+          v[k * n + q] = s * x + c * y;
+        }
+      }
+  }
+  double ev[12];
+  for (int k = 0; k < n; ++k) ev[k] = a[k * n + k] > 0.0 ? a[k * n + k] : 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += v[i * n + k] * ev[k] * v[j * n + k];
+      a[i * n + j] = acc;
+    }
+}
+
+// Store -lambda Hess C projected to PSD for one row with nv vertices; the
+// Hessian's columns come from Hessian-vector products with unit directions.
+template <class HVP>
+__device__ __forceinline__ void build_block(int nv, double lam, HVP hvp, double* out) {
+  const int n = 3 * nv;
+  double a[144];
+  for (int col = 0; col < n; ++col) {
+    V3<double> dir[4] = {}, hv[4] = {};
+    const int k = col / 3, b = col % 3;
+    if (b == 0) dir[k].x = 1.0; else if (b == 1) dir[k].y = 1.0; else dir[k].z = 1.0;
+    hvp(dir, hv);
+    for (int r = 0; r < nv; ++r) {
+      a[(3 * r) * n + col] = -lam * hv[r].x;
+      a[(3 * r + 1) * n + col] = -lam * hv[r].y;
+      a[(3 * r + 2) * n + col] = -lam * hv[r].z;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) a[i * n + j] = a[j * n + i] = 0.5 * (a[i * n + j] + a[j * n + i]);
+  psd_part(n, a);
+  for (int i = 0; i < n * n; ++i) out[i] = a[i];
+}
+
+// y_k += (N+ P)_k + g_k (g . P) / at  (stored block N+)
+__device__ __forceinline__ void apply_block(int nv, const int* vid, const double* nb, const V3<double>* g, double at,
+                                            const D4* __restrict__ P, D4* __restrict__ Q) {
+  const int n = 3 * nv;
+  double pv[12];
+  double s = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    D4 p = P[vid[k]];
+    pv[3 * k] = p.x; pv[3 * k + 1] = p.y; pv[3 * k + 2] = p.z;
+    s += g[k].x * p.x + g[k].y * p.y + g[k].z * p.z;
+  }
+  for (int k = 0; k < nv; ++k) {
+    double r[3];
+    for (int b = 0; b < 3; ++b) {
+      double acc = 0.0;
+      for (int l = 0; l < n; ++l) acc += nb[(3 * k + b) * n + l] * pv[l];
+      r[b] = acc;
+    }
+    D4 q = Q[vid[k]];
+    q.x += r[0] + g[k].x * s / at;
+    q.y += r[1] + g[k].y * s / at;
+    q.z += r[2] + g[k].z * s / at;
+    Q[vid[k]] = q;
+  }
+}
+__device__ __forceinline__ void diag_block(int nv, const int* vid, const double* nb, const V3<double>* g, double at,
+                                           D4* __restrict__ Q) {
+  const int n = 3 * nv;
+  for (int k = 0; k < nv; ++k) {
+    D4 q = Q[vid[k]];
+    q.x += nb[(3 * k) * n + 3 * k] + g[k].x * g[k].x / at;
+    q.y += nb[(3 * k + 1) * n + 3 * k + 1] + g[k].y * g[k].y / at;
+    q.z += nb[(3 * k + 2) * n + 3 * k + 2] + g[k].z * g[k].z / at;
+    Q[vid[k]] = q;
+  }
+}
 
 // one constraint row with n vertices: value C, gradient g, stiffness at
 template <int MODE>
@@ -56,14 +170,37 @@ __device__ __forceinline__ void imp_row(int n, const int* vid, double C, double 
   }
 }
 
+// one row (constraint, or one of a tet's two projections) in any mode
+template <int MODE, class HVP>
+__device__ __forceinline__ void imp_any(int nv, const int* vid, double C, double at, const V3<double>* g, HVP hvp,
+                                        const D4* __restrict__ P, D4* __restrict__ Q, double* acc, double* nb,
+                                        double ih2) {
+  const double lam = -C / at;
+  if (MODE == IMP_BUILD) {
+    build_block(nv, lam, hvp, nb);
+  } else if (MODE == IMP_APPLY_PD) {
+    apply_block(nv, vid, nb, g, at, P, Q);
+  } else if (MODE == IMP_DIAG_PD) {
+    diag_block(nv, vid, nb, g, at, Q);
+  } else {
+    V3<double> gb[4] = {}, hv[4] = {};
+    if (MODE == IMP_APPLY) {
+      for (int k = 0; k < nv; ++k) gb[k] = d3(P[vid[k]]);
+      hvp(gb, hv);
+    }
+    imp_row<MODE>(nv, vid, C, at, g, hv, P, Q, acc, ih2);
+  }
+}
+
+// NB: stored projected blocks of this constraint type (per internal index:
+// 36 doubles per distance, 144 per hinge, 2 x 144 per tet, 9 per contact)
 template <class T, int TY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int count, const Vec4<T>* __restrict__ XE,
                                                     const D4* __restrict__ P, D4* __restrict__ Q, double ih2,
-                                                    int* __restrict__ bad) {
+                                                    int* __restrict__ bad, double* __restrict__ NB) {
   const int t = thread_item(count);
   if (t < 0) return;
   const int j = begin + t;
-  V3<double> gb[4], hv[4] = {};
   if (TY == 0) {
     const int2 e = D.d_idx[j];
     const int vid[2] = {e.x, e.y};
@@ -72,13 +209,12 @@ __global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int cou
     const double at = (double)D.d_at[j];
     if (!(at > 0.0)) { *bad = 1; return; }
     V3<double> g[2] = {ev.n, -ev.n};
-    if (MODE == IMP_APPLY) {
-      V3<double> d = d3(P[e.x]) - d3(P[e.y]);
-      double dn = dot(d, ev.n);
-      hv[0] = (1.0 / ev.len) * (d - dn * ev.n);
+    auto hvp = [&](const V3<double>* gb, V3<double>* hv) {
+      V3<double> d = gb[0] - gb[1];
+      hv[0] = (1.0 / ev.len) * (d - dot(d, ev.n) * ev.n);
       hv[1] = -hv[0];
-    }
-    imp_row<MODE>(2, vid, ev.C, at, g, hv, P, Q, D.d_acc + j, ih2);
+    };
+    imp_any<MODE>(2, vid, ev.C, at, g, hvp, P, Q, D.d_acc + j, NB ? NB + (size_t)j * 36 : nullptr, ih2);
   } else if (TY == 1) {
     const int4 q = D.b_idx[j];
     const int vid[4] = {q.x, q.y, q.z, q.w};
@@ -88,12 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int cou
     if (!ev.ok) return;
     const double at = (double)D.b_at[j];
     if (!(at > 0.0)) { *bad = 1; return; }
-    if (MODE == IMP_APPLY) {
-      for (int k = 0; k < 4; ++k) gb[k] = d3(P[vid[k]]);
-      bend_hvp(e, a, b, gb, hv);
-    }
-    imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, D.b_acc + j, ih2);
+    auto hvp = [&](const V3<double>* gb, V3<double>* hv) { bend_hvp(e, a, b, gb, hv); };
+    imp_any<MODE>(4, vid, ev.C, at, ev.g, hvp, P, Q, D.b_acc + j, NB ? NB + (size_t)j * 144 : nullptr, ih2);
   } else if (TY == 2) {
+    if (MODE == IMP_GRAD) return;   // the tets' parameter gradient is not produced by this adjoint
     const TetRec<T>& R = D.tr;
     const int4 q = R.idx[j];
     const int vid[4] = {q.x, q.y, q.z, q.w};
@@ -103,27 +237,21 @@ __global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int cou
     M3<double> B;
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) B.m[r][c] = (double)Bt.m[r][c];
-    if (MODE == IMP_APPLY)
-      for (int k = 0; k < 4; ++k) gb[k] = d3(P[vid[k]]);
-    // deviatoric then hydrostatic row, both at the end state; the tets'
-    // parameter gradient is not produced by this adjoint
-    {
-      TetEval<double> ev = tet_dev_eval(dd, B);
+    // deviatoric and hydrostatic rows, both at the end state
+    TetEval<double> evD = tet_dev_eval(dd, B);
+    if (evD.ok) {
       const double at = (double)R.atD[j];
-      if (ev.ok) {
-        if (!(at > 0.0)) { *bad = 1; return; }
-        if (MODE == IMP_APPLY) tet_dev_hvp(ev, B, gb, hv);
-        if (MODE != IMP_GRAD) imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, nullptr, ih2);
-      }
-    }
-    {
-      TetEval<double> ev = tet_hyd_eval(dd, B, (double)R.gamma[j]);
-      const double at = (double)R.atH[j];
       if (!(at > 0.0)) { *bad = 1; return; }
-      if (MODE == IMP_APPLY) tet_hyd_hvp(ev, B, gb, hv);
-      if (MODE != IMP_GRAD) imp_row<MODE>(4, vid, ev.C, at, ev.g, hv, P, Q, nullptr, ih2);
+      auto hvp = [&](const V3<double>* gb, V3<double>* hv) { tet_dev_hvp(evD, B, gb, hv); };
+      imp_any<MODE>(4, vid, evD.C, at, evD.g, hvp, P, Q, nullptr, NB ? NB + (size_t)j * 288 : nullptr, ih2);
     }
+    TetEval<double> evH = tet_hyd_eval(dd, B, (double)R.gamma[j]);
+    const double at = (double)R.atH[j];
+    if (!(at > 0.0)) { *bad = 1; return; }
+    auto hvp = [&](const V3<double>* gb, V3<double>* hv) { tet_hyd_hvp(evH, B, gb, hv); };
+    imp_any<MODE>(4, vid, evH.C, at, evH.g, hvp, P, Q, nullptr, NB ? NB + (size_t)j * 288 + 144 : nullptr, ih2);
   } else {
+    if (MODE == IMP_GRAD) return;
     const int v = D.c_vid[j];
     const int vid[1] = {v};
     const V3<double> c = {(double)D.sph.cx, (double)D.sph.cy, (double)D.sph.cz};
@@ -132,11 +260,10 @@ __global__ __launch_bounds__(kBlock) void k_imp_set(Dev<T> D, int begin, int cou
     const double at = (double)D.sph.at;
     if (!(at > 0.0)) { *bad = 1; return; }
     V3<double> g[1] = {ev.n};
-    if (MODE == IMP_APPLY) {
-      V3<double> d = d3(P[v]);
-      hv[0] = (1.0 / ev.d) * (d - dot(d, ev.n) * ev.n);
-    }
-    if (MODE != IMP_GRAD) imp_row<MODE>(1, vid, ev.C, at, g, hv, P, Q, nullptr, ih2);
+    auto hvp = [&](const V3<double>* gb, V3<double>* hv) {
+      hv[0] = (1.0 / ev.d) * (gb[0] - dot(gb[0], ev.n) * ev.n);
+    };
+    imp_any<MODE>(1, vid, ev.C, at, g, hvp, P, Q, nullptr, NB ? NB + (size_t)j * 9 : nullptr, ih2);
   }
 }
 

@@ -27,6 +27,9 @@
 namespace xpbd {
 
 constexpr int kBlock = 256;
+// per-set kernels accept any power-of-two workgroup size up to this
+// (chosen per context; every size computes the same result)
+constexpr int kMaxBlock = 1024;
 
 template <class T> struct TetRec {
   const int4* idx;
@@ -463,13 +466,13 @@ template <class T> __device__ __forceinline__ void rev_predict_item(const Dev<T>
 // ===================================================================== plain kernels (one launch per set)
 
 __device__ __forceinline__ int thread_item(int count) {
-  int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  int t = xcd_tile(blockIdx.x, gridDim.x) * (int)blockDim.x + threadIdx.x;
   return t < count ? t : -1;
 }
 
 #define XPBD_SET_KERNEL(NAME, ITEM, TAPE_T)                                                              \
   template <class T, bool F1, bool F2>                                                                   \
-  __global__ __launch_bounds__(kBlock) void NAME(Dev<T> D, int begin, int count, TAPE_T* tape) {         \
+  __global__ __launch_bounds__(kMaxBlock) void NAME(Dev<T> D, int begin, int count, TAPE_T* tape) {      \
     int t = thread_item(count);                                                                          \
     if (t >= 0) ITEM<T, F1, F2>(D, begin, count, t, tape);                                               \
   }

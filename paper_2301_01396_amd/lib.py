@@ -52,7 +52,7 @@ class Options(C.Structure):
     _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("iterations", C.c_int32),
                 ("gravity", C.c_double * 3), ("dtype", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
                 ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32), ("launch_mode", C.c_int32),
-                ("persistent_blocks", C.c_int32)]
+                ("persistent_blocks", C.c_int32), ("block_size", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -85,7 +85,8 @@ class PackStats(C.Structure):
 
 
 class CG(C.Structure):
-    _fields_ = [("max_iterations", C.c_int32), ("rel_tolerance", C.c_double), ("total_iterations", C.c_int64),
+    _fields_ = [("max_iterations", C.c_int32), ("rel_tolerance", C.c_double), ("pd_projection", C.c_int32),
+                ("total_iterations", C.c_int64),
                 ("max_iterations_used", C.c_int32), ("worst_rel_residual", C.c_double)]
 
 
@@ -170,7 +171,7 @@ class Simulator:
     def __init__(self, scene, dtype: torch.dtype = torch.float32, device="cuda:0",
                  hbm_budget_bytes: int = 0, tape_mode: int = 0, tet_gamma_one: bool = False,
                  iterations: Optional[int] = None, substeps: Optional[int] = None, launch_mode: int = 0,
-                 persistent_blocks: int = 0, use_groups: bool = True):
+                 persistent_blocks: int = 0, use_groups: bool = True, block_size: int = 0):
         self.lib = load()
         self.scene = scene
         self.dtype = dtype
@@ -202,6 +203,7 @@ class Simulator:
         o.tape_mode = tape_mode
         o.launch_mode = launch_mode
         o.persistent_blocks = persistent_blocks
+        o.block_size = block_size
         with torch.cuda.device(self.device):
             rc = self.lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(self._ctx))
         if rc != XPBD_OK:
@@ -331,7 +333,7 @@ class Simulator:
         return g
 
     def adjoint_implicit(self, dLdx_frames, frame_mask=None, max_iterations: int = 1000,
-                         rel_tolerance: float = 1e-10, want=None):
+                         rel_tolerance: float = 1e-10, pd_projection: bool = False, want=None):
         """Implicit adjoint of the last forward (the paper's converged-step
         form, solved by CG): returns (gradients, CG report)."""
         if self._fwd_keep is None:
@@ -344,7 +346,7 @@ class Simulator:
         g.pop("tet_E", None)
         g.pop("sphere", None)
         dl = self._arg(dLdx_frames, (F, V, 3))
-        cg = CG(max_iterations, rel_tolerance, 0, 0, 0.0)
+        cg = CG(max_iterations, rel_tolerance, 1 if pd_projection else 0, 0, 0, 0.0)
         mask_ptr = None
         mask_arr = None
         if frame_mask is not None:

@@ -1,8 +1,9 @@
 """Launch-shape autotuner.
 
 Every launch structure the library offers computes bit-identical results
-(one launch per independent set, LDS group launches, the persistent frame
-kernel at any grid size), so the choice is purely a performance one.  The
+(one launch per independent set at any workgroup size, LDS group launches,
+the persistent frame kernel at any grid size), so the choice is purely a
+performance one.  The
 tuner times a short forward + adjoint rollout for each candidate and keeps
 the fastest per shape bucket (dtype, log2 of the vertex count, sets per
 iteration, groups, constraint mix) in a JSON table.
@@ -32,18 +33,21 @@ def shape_key(scene, dtype: torch.dtype) -> str:
 
 
 def candidates(scene) -> List[Dict[str, int]]:
-    c = [{"launch_mode": 1, "use_groups": 0, "persistent_blocks": 0}]
+    """Every result-invariant launch shape: one launch per set at several
+    workgroup sizes, LDS group launches (if the schedule has groups), the
+    persistent frame kernel at several grid sizes."""
+    c = [{"launch_mode": 1, "use_groups": 0, "persistent_blocks": 0, "block_size": bs} for bs in (128, 256, 512)]
     if getattr(scene, "groups", None):
-        c.append({"launch_mode": 1, "use_groups": 1, "persistent_blocks": 0})
+        c.append({"launch_mode": 1, "use_groups": 1, "persistent_blocks": 0, "block_size": 256})
     for b in (32, 64, 128):
-        c.append({"launch_mode": 2, "use_groups": 0, "persistent_blocks": b})
+        c.append({"launch_mode": 2, "use_groups": 0, "persistent_blocks": b, "block_size": 256})
     return c
 
 
 def measure(scene, cfg: Dict[str, int], dtype=torch.float32, frames: int = 1, reps: int = 2) -> float:
     """Seconds for one forward + adjoint of ``frames`` frames (best of reps)."""
     sim = Simulator(scene, dtype=dtype, launch_mode=cfg["launch_mode"], persistent_blocks=cfg["persistent_blocks"],
-                    use_groups=bool(cfg["use_groups"]))
+                    use_groups=bool(cfg["use_groups"]), block_size=cfg.get("block_size", 0))
     try:
         best = float("inf")
         mask = np.zeros(frames, np.uint8)
@@ -97,4 +101,4 @@ def simulator(scene, dtype=torch.float32, **kw) -> Simulator:
     cfg = lookup(scene, dtype) or {}
     return Simulator(scene, dtype=dtype, launch_mode=cfg.get("launch_mode", 0),
                      persistent_blocks=cfg.get("persistent_blocks", 0),
-                     use_groups=bool(cfg.get("use_groups", 1)), **kw)
+                     use_groups=bool(cfg.get("use_groups", 1)), block_size=cfg.get("block_size", 0), **kw)

@@ -55,6 +55,7 @@ def _create(sc, **opt):
     o.iterations = opt.get("iterations", sc.iterations)
     o.dtype = opt.get("dtype", 0)
     o.tape_mode = opt.get("tape_mode", 0)
+    o.block_size = opt.get("block_size", 0)
     ctx = C.c_void_p()
     rc = lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(ctx))
     msg = lib.xpbd_last_error(None).decode()
@@ -183,3 +184,9 @@ def test_profile_family_count_matches_header():
                   r"int64_t items\[(\d+)\]\)", txt)
     assert m and len(set(m.groups())) == 1
     assert int(m.group(1)) == L.N_FAMILIES
+
+
+@pytest.mark.parametrize("bs", [32, 96, 2048, -64])
+def test_rejects_bad_block_size(bs):
+    rc, _, msg = _create(scenes.small_cloth(n=4), block_size=bs)
+    assert rc == L.XPBD_ERR_INVALID and "block_size" in msg

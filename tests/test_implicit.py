@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 GROUPS = ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext")
 
 
-def _case(sc, F, dtype, tol, seed=0, mask=None):
+def _case(sc, F, dtype, tol, seed=0, mask=None, pd=False):
     import torch
     from paper_2301_01396_amd.lib import Simulator
     needs_gpu()
@@ -23,10 +23,11 @@ def _case(sc, F, dtype, tol, seed=0, mask=None):
     dL = rng.standard_normal(xf.shape)
     if mask is not None:
         dL[~np.asarray(mask, bool)] = 0.0
-    ref = O.adjoint_implicit(osc, F, dL)
+    ref = O.adjoint_implicit(osc, F, dL, pd=pd)
     sim = Simulator(sc, dtype=dtype)
     sim.forward(F)
-    got, rep = sim.adjoint_implicit(sim.tensor(dL), frame_mask=mask, rel_tolerance=1e-13, max_iterations=2000)
+    got, rep = sim.adjoint_implicit(sim.tensor(dL), frame_mask=mask, rel_tolerance=1e-13, max_iterations=4000,
+                                    pd_projection=pd)
     torch.cuda.synchronize()
     errs = {}
     for k in GROUPS:
@@ -64,6 +65,44 @@ def test_implicit_cloth_fp32_state():
     _case(sc, 2, __import__("torch").float32, 1e-3)
 
 
+def _hanging(n=10, frames=6):
+    """A stiff hanging cloth (the 32x32 configuration's compliances on a
+    10x10 grid): compressed edges make the plain system indefinite."""
+    sc = scenes.small_cloth(n=n, frames=frames, substeps=1, iterations=20, sphere=False)
+    rng = np.random.default_rng(1)
+    sc.dist_alpha = 1e-7 * rng.uniform(0.5, 2.0, sc.n_dist)
+    sc.bend_alpha = 1e-2 * rng.uniform(0.5, 2.0, sc.n_bend)
+    return sc
+
+
+def test_implicit_pd_projection_matches_reference_fp64():
+    _case(_hanging(), 6, __import__("torch").float64, 1e-8, pd=True)
+
+
+def test_implicit_pd_projection_bending_and_contact_fp64():
+    sc = scenes.small_cloth(n=6, frames=3, substeps=2, iterations=5)
+    _case(sc, 3, __import__("torch").float64, 1e-9, pd=True)
+
+
+def test_implicit_pd_projection_tets_fp64():
+    sc = scenes.small_tets(n=2, frames=2, substeps=2, iterations=5)
+    _case(sc, 2, __import__("torch").float64, 1e-9, pd=True)
+
+
+def test_implicit_without_projection_reports_an_indefinite_system():
+    import torch
+    from paper_2301_01396_amd import lib as L
+    needs_gpu()
+    sc = _hanging()
+    sim = L.Simulator(sc, dtype=torch.float64)
+    sim.forward(6)
+    try:
+        sim.adjoint_implicit(sim.tensor(np.ones((6, sc.n_verts, 3))), max_iterations=4000, rel_tolerance=1e-13)
+    except L.XPBDError as e:
+        assert e.status == L.XPBD_ERR_SOLVER
+    sim.close()
+
+
 def test_implicit_rejects_zero_compliance_and_unsupported_outputs():
     import torch
     from paper_2301_01396_amd import lib as L
@@ -79,7 +118,7 @@ def test_implicit_rejects_zero_compliance_and_unsupported_outputs():
     sim.forward(1)
     g, gr = sim._grad_buffers(1, ("x0",))
     gr.sphere = C_ptr = sim.tensor(np.zeros(4), torch.float64).data_ptr()
-    cg = L.CG(10, 1e-8, 0, 0, 0.0)
+    cg = L.CG(10, 1e-8, 0, 0, 0, 0.0)
     dl = sim.tensor(np.ones((1, sc.n_verts, 3)))
     import ctypes as C
     rc = sim.lib.xpbd_adjoint_implicit(sim._ctx, C.byref(sim._fwd_keep[0]), C.c_void_p(dl.data_ptr()), None,

@@ -50,10 +50,12 @@ def test_tuned_simulator_matches_default(tmp_path):
     best = tune.tune(sc, torch.float32, frames=1, path=str(tmp_path / "t.json"))
     assert len(best["timings"]) == len(tune.candidates(sc))
     outs = []
-    for cfg in [best, {"launch_mode": 1, "use_groups": 0, "persistent_blocks": 0}]:
+    for cfg in [best] + tune.candidates(sc):
         sim = Simulator(sc, dtype=torch.float32, launch_mode=cfg["launch_mode"],
-                        persistent_blocks=cfg["persistent_blocks"], use_groups=bool(cfg["use_groups"]))
+                        persistent_blocks=cfg["persistent_blocks"], use_groups=bool(cfg["use_groups"]),
+                        block_size=cfg["block_size"])
         xf, xe, ve = sim.forward(1)
         outs.append(xe.cpu().numpy())
         sim.close()
-    assert np.array_equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
