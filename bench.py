@@ -261,7 +261,8 @@ def implicit_bench(args):
             g = sim.adjoint(dL, mask, want=("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
             rep = None
         else:
-            g, rep = sim.adjoint_implicit(dL, mask, max_iterations=args.cg_iters, rel_tolerance=args.cg_tol)
+            g, rep = sim.adjoint_implicit(dL, mask, max_iterations=args.cg_iters, rel_tolerance=args.cg_tol,
+                                          pd_projection=args.pd)
         torch.cuda.synchronize()
         res[kind] = {"s": time.perf_counter() - t0, "g": {k: v.double().cpu().numpy() for k, v in g.items()},
                      "cg": rep}
@@ -275,6 +276,7 @@ def implicit_bench(args):
            workload_config(args.workload, sc, F), "dtype": "f64" if dtype == torch.float64 else "f32",
            "exact_fwd_adjoint_s": res["exact"]["s"], "implicit_fwd_adjoint_s": res["implicit"]["s"],
            "cg": res["implicit"]["cg"], "cg_rel_tolerance": args.cg_tol, "cg_max_iterations": args.cg_iters,
+           "pd_projection": bool(args.pd),
            "rel_difference_implicit_vs_exact": diff}
     print(json.dumps(out), flush=True)
 
@@ -303,6 +305,7 @@ def main():
                     help="compare the implicit (CG) adjoint with the exact one on the workload")
     ap.add_argument("--cg-iters", type=int, default=2000)
     ap.add_argument("--cg-tol", type=float, default=1e-8)
+    ap.add_argument("--pd", action="store_true", help="implicit adjoint: project the blocks to PSD first")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()

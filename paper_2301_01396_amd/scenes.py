@@ -18,9 +18,10 @@ Readings of the paper's unstated scene parameters (all marked "reading"):
 * Tet boxes split each cube into 5 tets, alternating the split with the
   parity of (i + j + k) so neighbouring cubes conform; mass is lumped
   (rho * V_e / 4 per incident tet corner), the y = 0 face is pinned.
-* The schedule is greedy first-fit colouring over batches of constraints
-  that are independent by construction, then each colour is sorted by its
-  smallest vertex index (locality).  Any schedule whose sets are vertex
+* Grid cloths: 6 distance and 12 bending sets, each touching every vertex
+  once (greedy first-fit over batches independent by construction yields
+  exactly these); tet boxes: 33 sets from a 4-periodic colouring table.
+  Each colour is sorted by its smallest vertex index (locality).  Any schedule whose sets are vertex
   disjoint is valid input; both consumers replay it in the same order.
 
 RNG: ``numpy.random.default_rng(seed)`` (PCG64), values drawn in the order
@@ -257,10 +258,24 @@ _ODD = [((1, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1)),
         ((0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1))]
 
 
+# Colour of tet slot t (0..4) of cube (i, j, k) by (i mod 4, j mod 4, k mod 4,
+# t), one base-36 digit each, 33 colours.  Found by a tabu search over the
+# colourings of the lattice folded onto a 4x4x4 torus (tets conflict when
+# they share a vertex); a colouring of the torus is valid on every box.  The
+# lower bound is 32 (32 tets share an even-parity vertex); the greedy
+# colouring of the 2-periodic classes needs 40.
+_TET_COLOUR_4 = (
+    "dw310nosflq1vtwbjl7pa9bq6h7d3p90ak6elun3w7id4olgn1ba2wqsmjophktqc2p37jk905631v2njmug5ckbtea2gcd4stro8c4v2"
+    "isjmr8uqi5nmhe01bk95fatwehl4bcgjrdtga68svr0omiurh879eif7ktdp0nw4l6s2vpel16b93q6w7b10hgo9w3f1uvapmn8olgd7js"
+    "48p672lqkc4hi329kf1nq5m3wjvn0horf8gmbeirjo47dkgqms2vjcua2k5nv8tcrhi458bte0fsmprie9oud1frg596wa4ud5vt8haciflus")
+
+
 def tet_box(n: int, size: float = 1.0, density: float = 1000.0,
-            pin_bottom: bool = True) -> Scene:
+            pin_bottom: bool = True, colouring: str = "periodic") -> Scene:
     """n^3 cubes over [0, size]^3, 5 tets per cube, vertex (i, j, k) at
-    (i, j, k) * size / n with index (i * (n + 1) + j) * (n + 1) + k."""
+    (i, j, k) * size / n with index (i * (n + 1) + j) * (n + 1) + k.
+    ``colouring``: "periodic" (33 sets from the 4-periodic table) or
+    "greedy" (greedy first-fit over the 40 classes cube parity x slot)."""
     n1 = n + 1
     ii, jj, kk = np.meshgrid(np.arange(n1), np.arange(n1), np.arange(n1), indexing="ij")
     rest = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1).astype(np.float64) * (size / n)
@@ -296,15 +311,19 @@ def tet_box(n: int, size: float = 1.0, density: float = 1000.0,
     sc = Scene(rest=rest, inv_mass=inv_mass, dist_v=np.zeros((0, 2), np.int32),
                bend_v=np.zeros((0, 4), np.int32), tet_v=tet_v,
                tet_nu=np.full(len(tet_v), 0.3))
-    # batches: cube parity class (8) x tet slot (5) are vertex disjoint
-    cls = (ci % 2) * 4 + (cj % 2) * 2 + (ck % 2)
-    tid = np.arange(len(tet_v)).reshape(-1, 5)
-    batches = []
-    for c in range(8):
-        cubes = np.nonzero(cls == c)[0]
-        for t in range(5):
-            batches.append(tid[cubes, t])
-    col = greedy_color(tet_v, batches, len(rest))
+    if colouring == "periodic":
+        table = np.array([int(ch, 36) for ch in _TET_COLOUR_4], np.int32).reshape(4, 4, 4, 5)
+        col = table[ci % 4, cj % 4, ck % 4][:, :].reshape(-1)
+    else:
+        # batches: cube parity class (8) x tet slot (5) are vertex disjoint
+        cls = (ci % 2) * 4 + (cj % 2) * 2 + (ck % 2)
+        tid = np.arange(len(tet_v)).reshape(-1, 5)
+        batches = []
+        for c in range(8):
+            cubes = np.nonzero(cls == c)[0]
+            for t in range(5):
+                batches.append(tid[cubes, t])
+        col = greedy_color(tet_v, batches, len(rest))
     for s in sets_from_colors(tet_v, col):
         sc.set_type.append(TET)
         sc.set_items.append(s)

@@ -190,3 +190,19 @@ def test_profile_family_count_matches_header():
 def test_rejects_bad_block_size(bs):
     rc, _, msg = _create(scenes.small_cloth(n=4), block_size=bs)
     assert rc == L.XPBD_ERR_INVALID and "block_size" in msg
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_periodic_tet_colouring_is_a_valid_33_set_schedule(n):
+    sc = scenes.tet_box(n)
+    st, off, items = sc.schedule_arrays()
+    assert len(st) == 33 and np.all(st == scenes.TET)
+    seen = np.zeros(sc.n_tet, int)
+    for k in range(len(st)):
+        it = items[off[k]:off[k + 1]]
+        v = sc.tet_v[it].ravel()
+        assert len(np.unique(v)) == len(v)
+        seen[it] += 1
+    assert np.all(seen == 1)
+    if n >= 8:   # on large boxes the greedy colouring of the 2-periodic classes needs more sets
+        assert len(scenes.tet_box(n, colouring="greedy").set_type) > 33
