@@ -301,6 +301,10 @@ def main():
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0 = auto)")
     ap.add_argument("--tile", type=int, default=-1, help="schedule tile width (-1 = the workload's, 0 = untiled)")
     ap.add_argument("--no-groups", action="store_true", help="run every set as its own launch")
+    ap.add_argument("--block", type=int, default=0, help="workgroup size of the per-set kernels (0 = 256)")
+    ap.add_argument("--group-records", type=int, default=0,
+                    help="LDS groups: 1 records staged in LDS, 2 records streamed (0 = the library's choice)")
+    ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
     ap.add_argument("--implicit", action="store_true",
                     help="compare the implicit (CG) adjoint with the exact one on the workload")
     ap.add_argument("--cg-iters", type=int, default=2000)
@@ -339,7 +343,8 @@ def main():
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
     sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
-                    use_groups=not args.no_groups)
+                    use_groups=not args.no_groups, block_size=args.block, group_records=args.group_records,
+                    group_block=args.group_block)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
 

@@ -142,6 +142,12 @@ typedef struct {
                                 largest set (capped at what the device co-schedules) */
   int32_t block_size;        /* workgroup size of the one-launch-per-set kernels: a power
                                 of two in [64, 1024], 0 = 256; results do not depend on it */
+  int32_t group_records;     /* LDS groups: 0 or 1 = each patch's records staged in LDS
+                                with its vertices; 2 = only the vertex tile in LDS, records
+                                read and written in place in global memory (small LDS, many
+                                patches per CU); results do not depend on it */
+  int32_t group_block;       /* workgroup size of the LDS group kernels, a power of two in
+                                [64, 256], 0 = 256 */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral
@@ -157,13 +163,19 @@ xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* 
 xpbd_status xpbd_destroy(xpbd_ctx ctx);
 
 /* Controls (Sec. 4.4): device arrays in the context dtype; NULL compliance
- * arrays mean 0 (rigid); tet_E is required when there are tets. */
+ * arrays mean 0 (rigid).  Tets take either Young's moduli (with the Poisson
+ * ratios given at create) or Lame parameters: tet_mu and tet_lambda, when
+ * given, replace tet_E and the Poisson ratios (Sec. 5.2 optimises over them
+ * through a^2 = mu, b^2 = lambda); one of the two is required when there
+ * are tets. */
 typedef struct {
   const void* dist_compliance;   /* device [n_dist] alpha (m/N) */
   const void* bend_compliance;   /* device [n_bend] alpha */
   const void* tet_E;             /* device [n_tet] Young's modulus (Pa) */
   const void* f_ext;             /* device [F][V][3] per-vertex force, or NULL */
   double sphere[4];              /* cx, cy, cz, R of the contact sphere */
+  const void* tet_mu;            /* device [n_tet] first Lame parameter (Pa), or NULL */
+  const void* tet_lambda;        /* device [n_tet] second Lame parameter (Pa), or NULL */
 } xpbd_params;
 
 /* Roll out n_frames frames from (x0, v0) (device [V][3]; v0 of pinned
@@ -185,11 +197,14 @@ xpbd_status xpbd_forward(xpbd_ctx ctx, const void* x0, const void* v0, const xpb
 typedef struct {
   double* dist_compliance;   /* [n_dist] dL/dalpha */
   double* bend_compliance;   /* [n_bend] dL/dalpha */
-  double* tet_E;             /* [n_tet] dL/dE (nu fixed) */
+  double* tet_E;             /* [n_tet] dL/dE (nu fixed; Young's moduli given) */
   void* f_ext;               /* [F][V][3] dL/df_ext */
   void* x0;                  /* [V][3] dL/dx0 */
   void* v0;                  /* [V][3] dL/dv0 */
   double* sphere;            /* [4] dL/d(cx, cy, cz, R) */
+  double* tet_mu;            /* [n_tet] dL/dmu (Lame parameters given), through both
+                                compliances and gamma = 1 + mu/lambda */
+  double* tet_lambda;        /* [n_tet] dL/dlambda */
 } xpbd_grads;
 
 /* Exact adjoint of the preceding xpbd_forward on this context for a goal

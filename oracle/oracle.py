@@ -55,7 +55,7 @@ class _Scene(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("dist_alpha", _dp), ("bend_alpha", _dp), ("tet_E", _dp),
-                ("f_ext", _dp), ("sphere", C.c_double * 4)]
+                ("f_ext", _dp), ("sphere", C.c_double * 4), ("tet_mu", _dp), ("tet_lambda", _dp)]
 
 
 _lib = None
@@ -123,7 +123,8 @@ class OracleScene:
         s.n_threads = n_threads
         self.s = s
 
-    def params(self, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None, sphere=None):
+    def params(self, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None, sphere=None, tet_mu=None,
+               tet_lambda=None):
         sc = self.sc
         keep = []
 
@@ -145,6 +146,9 @@ class OracleScene:
         sph = sc.sphere if sphere is None else sphere
         for a in range(4):
             p.sphere[a] = float(sph[a])
+        if tet_mu is not None:
+            p.tet_mu = _d(arr(tet_mu, None, sc.n_tet))
+            p.tet_lambda = _d(arr(tet_lambda, None, sc.n_tet))
         return p, keep
 
 
@@ -168,7 +172,7 @@ def forward(osc: OracleScene, n_frames: int, x0=None, v0=None, **params):
 def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=None,
             **params):
     """Exact adjoint.  Returns dict of gradients (x0, v0, dist_alpha,
-    bend_alpha, tet_E, f_ext, sphere)."""
+    bend_alpha, tet_E, f_ext, sphere, tet_mu, tet_lambda)."""
     sc = osc.sc
     V = sc.n_verts
     x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)
@@ -180,12 +184,12 @@ def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=
         "x0": np.zeros((V, 3)), "v0": np.zeros((V, 3)),
         "dist_alpha": np.zeros(sc.n_dist), "bend_alpha": np.zeros(sc.n_bend),
         "tet_E": np.zeros(sc.n_tet), "f_ext": np.zeros((n_frames, V, 3)),
-        "sphere": np.zeros(4),
+        "sphere": np.zeros(4), "tet_mu": np.zeros(sc.n_tet), "tet_lambda": np.zeros(sc.n_tet),
     }
     rc = _load().orc_adjoint(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0), _d(dLdx),
                              _d(dv), _d(g["x0"]), _d(g["v0"]), _d(g["dist_alpha"]),
                              _d(g["bend_alpha"]), _d(g["tet_E"]), _d(g["f_ext"]),
-                             _d(g["sphere"]))
+                             _d(g["sphere"]), _d(g["tet_mu"]), _d(g["tet_lambda"]))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
     return g

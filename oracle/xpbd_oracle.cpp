@@ -198,6 +198,9 @@ struct Params {
   const double* tet_E;
   const double* f_ext;   // [F][V][3] or null
   double sphere[4];
+  // Lame parameters per tet (Sec. 5.2); when given they replace (E, nu)
+  const double* tet_mu;
+  const double* tet_lambda;
 };
 
 enum { T_DIST = 0, T_BEND = 1, T_TET = 2, T_CONTACT = 3 };
@@ -309,9 +312,14 @@ void set_materials(Model* m, const Params* p) {
   const Scene* s = m->s;
   m->mu.resize(s->n_tet); m->lam.resize(s->n_tet); m->gamma.resize(s->n_tet);
   for (int t = 0; t < s->n_tet; ++t) {
-    double E = p->tet_E[t], nu = s->tet_nu[t];
-    m->mu[t] = E / (2.0 * (1.0 + nu));
-    m->lam[t] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    if (p->tet_mu) {
+      m->mu[t] = p->tet_mu[t];
+      m->lam[t] = p->tet_lambda[t];
+    } else {
+      double E = p->tet_E[t], nu = s->tet_nu[t];
+      m->mu[t] = E / (2.0 * (1.0 + nu));
+      m->lam[t] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    }
     m->gamma[t] = s->tet_gamma_one ? 1.0 : 1.0 + m->mu[t] / m->lam[t];
   }
 }
@@ -476,7 +484,7 @@ void substep(const Ctx& c, double* x, double* v, double* lam, const double* f,
 // them in place to the adjoints of (x before, lam before); accumulate the
 // compliance and sphere adjoints.  x_before comes from the tape entry.
 void reverse_row(const Ctx& c, const Row& r, const TapeEntry& te, double* xb, double* lamb,
-                 double* alpha_bar_row, double* sphere_bar) {
+                 double* alpha_bar_row, double* sphere_bar, double* gamma_bar) {
   const Scene* s = c.m.s;
   // rebuild a local position array holding only this row's vertices
   double xl[12];
@@ -517,6 +525,8 @@ void reverse_row(const Ctx& c, const Row& r, const TapeEntry& te, double* xb, do
   if (r.type == T_CONTACT && sphere_bar) {
     for (int a = 0; a < 4; ++a) sphere_bar[a] += Cbar * e.g[12 + a] + hv[12 + a];
   }
+  // C_H = det F - gamma: dC/dgamma = -1 (grad C does not depend on gamma)
+  if (r.type == T_TET && r.sub == 1 && gamma_bar) *gamma_bar -= Cbar;
 }
 
 }  // namespace
@@ -598,7 +608,7 @@ int orc_forward(const orc_scene* s, const orc_params* p, int F, const double* x0
 int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                 const double* dLdx, const double* dLdv_final,
                 double* g_x0, double* g_v0, double* g_dist_alpha, double* g_bend_alpha,
-                double* g_tet_E, double* g_f, double* g_sphere) {
+                double* g_tet_E, double* g_f, double* g_sphere, double* g_tet_mu, double* g_tet_lambda) {
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);
@@ -623,6 +633,7 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
   std::vector<double> xb(n3, 0.0), vb(n3, 0.0), lamb(c.m.n_lam, 0.0);
   if (dLdv_final) std::copy(dLdv_final, dLdv_final + n3, vb.begin());
   std::vector<double> abar(c.m.n_lam, 0.0);   // per multiplier slot
+  std::vector<double> gbar(s->n_tet, 0.0);     // per tet: dL/dgamma
   double sph[4] = {0, 0, 0, 0};
   if (g_f) std::fill(g_f, g_f + (size_t)F * n3, 0.0);
   const double h = c.h;
@@ -659,7 +670,8 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
             for (int sub = nsub - 1; sub >= 0; --sub) {
               Row r = make_row(c.m, ty, s->set_items[q], sub);
               const TapeEntry& te = tp[it_base + set_base[si] + (size_t)(q - b) * nsub + sub];
-              reverse_row(c, r, te, xb.data(), lamb.data(), &abar[r.lam], &sph_part[(q - b) * 4]);
+              reverse_row(c, r, te, xb.data(), lamb.data(), &abar[r.lam], &sph_part[(q - b) * 4],
+                          r.type == T_TET ? &gbar[r.item] : nullptr);
             }
           }
           if (ty == T_CONTACT)
@@ -695,6 +707,16 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
     }
   }
   if (g_sphere) for (int a = 0; a < 4; ++a) g_sphere[a] = sph[a];
+  // Lame parameters: alpha_D = 1/(mu V), alpha_H = 1/(lambda V),
+  // gamma = 1 + mu/lambda (constant 1 with tet_gamma_one)
+  for (int t = 0; t < s->n_tet && (g_tet_mu || g_tet_lambda); ++t) {
+    double mu = c.m.mu[t], la = c.m.lam[t];
+    double aD = 1.0 / (mu * c.m.vol[t]), aH = 1.0 / (la * c.m.vol[t]);
+    double gd = abar[c.m.lam_tet + 2 * t], gh = abar[c.m.lam_tet + 2 * t + 1];
+    double gg = s->tet_gamma_one ? 0.0 : gbar[t];
+    if (g_tet_mu) g_tet_mu[t] = -gd * aD / mu + gg / la;
+    if (g_tet_lambda) g_tet_lambda[t] = -gh * aH / la - gg * mu / (la * la);
+  }
   return 0;
 }
 

@@ -5,7 +5,8 @@ backward, the library's exact adjoint (recomputing each frame from the
 checkpoint the forward kept).  ``GoalL2.apply`` is the goal of Sec. 4.1
 (W = I on the masked frames, beta = 0) reduced in FP64 on the device.
 Gradients flow to x0, v0, the distance and bending compliances, the tet
-Young's moduli, the per-frame external forces and the sphere (c, R).
+Young's moduli or Lame parameters, the per-frame external forces and the
+sphere (c, R).
 """
 from __future__ import annotations
 
@@ -19,25 +20,26 @@ from .lib import Simulator, XPBDError, XPBD_ERR_STATE
 
 class XPBDRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim: Simulator, n_frames: int, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere):
+    def forward(ctx, sim: Simulator, n_frames: int, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere,
+                tet_mu=None, tet_lambda=None):
         sph = None if sphere is None else sphere.detach().cpu().double().numpy()
         d = lambda t: None if t is None else t.detach().contiguous()
         grad = any(ctx.needs_input_grad[2:])
         xf, _, _ = sim.forward(n_frames, x0=d(x0), v0=d(v0), dist_alpha=d(dist_alpha), bend_alpha=d(bend_alpha),
-                               tet_E=d(tet_E), f_ext=d(f_ext), sphere=sph, for_adjoint=grad)
-        sim._rollout_id = getattr(sim, "_rollout_id", 0) + 1
+                               tet_E=d(tet_E), f_ext=d(f_ext), sphere=sph, for_adjoint=grad,
+                               tet_mu=d(tet_mu), tet_lambda=d(tet_lambda))
         ctx.sim = sim
-        ctx.rid = sim._rollout_id
+        ctx.rid = sim.forward_count
         ctx.meta = [(t.dtype, t.device) if t is not None else None
-                    for t in (x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)]
+                    for t in (x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu, tet_lambda)]
         return xf
 
     @staticmethod
     def backward(ctx, gx):
         sim = ctx.sim
-        if getattr(sim, "_rollout_id", None) != ctx.rid:
+        if sim.forward_count != ctx.rid:
             raise XPBDError(XPBD_ERR_STATE, "another forward ran on this simulator before this backward")
-        names = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere")
+        names = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere", "tet_mu", "tet_lambda")
         want = [n for n, m, need in zip(names, ctx.meta, ctx.needs_input_grad[2:]) if m is not None and need]
         g = sim.adjoint(gx.to(sim.dtype).contiguous(), None, want=want) if want else {}
         out = []
@@ -63,9 +65,12 @@ class GoalL2(torch.autograd.Function):
 
 
 def rollout(sim: Simulator, n_frames: int, x0, v0, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None,
-            sphere: Optional[torch.Tensor] = None):
-    """Differentiable rollout: returns the end-of-frame positions (F, V, 3)."""
-    return XPBDRollout.apply(sim, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
+            sphere: Optional[torch.Tensor] = None, tet_mu=None, tet_lambda=None):
+    """Differentiable rollout: returns the end-of-frame positions (F, V, 3).
+    Tets take tet_E (Young's moduli, Poisson ratios fixed) or tet_mu and
+    tet_lambda (Lame parameters)."""
+    return XPBDRollout.apply(sim, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu,
+                             tet_lambda)
 
 
 def goal_l2(sim: Simulator, x_frames, targets, frame_mask=None):

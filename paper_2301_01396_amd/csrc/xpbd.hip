@@ -81,6 +81,8 @@ struct xpbd_ctx_s {
   int gamma_one;
   int tape_mode_opt;
   int block = kBlock;   // workgroup size of the per-set kernels
+  bool group_stream = false;   // LDS groups: records streamed from the global image
+  int group_block = kBlock;    // workgroup size of the LDS group kernels
   int tape_mode_used = 0;
   double tau = 0, alpha_c = 0;
   std::vector<SetInfo> sets;
@@ -122,7 +124,8 @@ struct xpbd_ctx_s {
     int a, b;                 // sets [a, b)
     bool lds = false;         // run as one launch per iteration
     int P = 0;
-    size_t smem_fwd = 0, smem_rev = 0;
+    size_t smem_fwd = 0, smem_rev = 0;   // vertex tile + record image (+ record of inputs)
+    size_t smem_tile = 0;                 // vertex tile only (records streamed)
     int64_t items = 0;        // projections per iteration inside the group
     int* pv_start = nullptr; int* pv = nullptr; int* cnt = nullptr; int* set_type = nullptr;
     long long* fimg = nullptr; long long* rimg = nullptr; long long* tpos = nullptr; int* rec_first = nullptr;
@@ -407,13 +410,22 @@ template <class T> struct Ops {
     bool on;
     prof_begin(c, st, 10, g.items, &ev, &on);
     dim3 grid(g.P);
+    const bool rl = !c->group_stream;
+    const int bs = c->group_block;
+    const size_t sm = rl ? g.smem_fwd : g.smem_tile;
+#define XPBD_GF(F1, F2)                                                                             \
+  do {                                                                                              \
+    if (rl) k_group_fwd<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->fimg, tape_iter);           \
+    else k_group_fwd<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->fimg, tape_iter);             \
+  } while (0)
     if (first) {
-      if (tape_iter) k_group_fwd<T, true, true><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
-      else k_group_fwd<T, true, false><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+      if (tape_iter) XPBD_GF(true, true);
+      else XPBD_GF(true, false);
     } else {
-      if (tape_iter) k_group_fwd<T, false, true><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
-      else k_group_fwd<T, false, false><<<grid, kBlock, g.smem_fwd, st>>>(D, G, c->fimg, tape_iter);
+      if (tape_iter) XPBD_GF(false, true);
+      else XPBD_GF(false, false);
     }
+#undef XPBD_GF
     check_launch();
     prof_end(c, st, ev, on);
   }
@@ -425,13 +437,22 @@ template <class T> struct Ops {
     bool on;
     prof_begin(c, st, 11, g.items, &ev, &on);
     dim3 grid(g.P);
+    const bool rl = !c->group_stream;
+    const int bs = c->group_block;
+    const size_t sm = rl ? g.smem_rev : g.smem_tile;
+#define XPBD_GR(F1, F2)                                                                             \
+  do {                                                                                              \
+    if (rl) k_group_rev<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->rimg, tape_iter);           \
+    else k_group_rev<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->rimg, tape_iter);             \
+  } while (0)
     if (first) {
-      if (last) k_group_rev<T, true, true><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
-      else k_group_rev<T, true, false><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+      if (last) XPBD_GR(true, true);
+      else XPBD_GR(true, false);
     } else {
-      if (last) k_group_rev<T, false, true><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
-      else k_group_rev<T, false, false><<<grid, kBlock, g.smem_rev, st>>>(D, G, c->rimg, tape_iter);
+      if (last) XPBD_GR(false, true);
+      else XPBD_GR(false, false);
     }
+#undef XPBD_GR
     check_launch();
     prof_end(c, st, ev, on);
   }
@@ -453,10 +474,14 @@ template <class T> struct Ops {
 
   static void allow_lds(size_t bytes) {
     if (bytes <= 65536) return;
-    const void* ks[] = {(const void*)k_group_fwd<T, true, true>, (const void*)k_group_fwd<T, true, false>,
-                        (const void*)k_group_fwd<T, false, true>, (const void*)k_group_fwd<T, false, false>,
-                        (const void*)k_group_rev<T, true, true>, (const void*)k_group_rev<T, true, false>,
-                        (const void*)k_group_rev<T, false, true>, (const void*)k_group_rev<T, false, false>};
+    const void* ks[] = {(const void*)k_group_fwd<T, true, true, true>, (const void*)k_group_fwd<T, true, false, true>,
+                        (const void*)k_group_fwd<T, false, true, true>, (const void*)k_group_fwd<T, false, false, true>,
+                        (const void*)k_group_rev<T, true, true, true>, (const void*)k_group_rev<T, true, false, true>,
+                        (const void*)k_group_rev<T, false, true, true>, (const void*)k_group_rev<T, false, false, true>,
+                        (const void*)k_group_fwd<T, true, true, false>, (const void*)k_group_fwd<T, true, false, false>,
+                        (const void*)k_group_fwd<T, false, true, false>, (const void*)k_group_fwd<T, false, false, false>,
+                        (const void*)k_group_rev<T, true, true, false>, (const void*)k_group_rev<T, true, false, false>,
+                        (const void*)k_group_rev<T, false, true, false>, (const void*)k_group_rev<T, false, false, false>};
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
@@ -608,7 +633,13 @@ template <class T> struct Ops {
       k_gather_alpha<T><<<nblocks(c->n_bend), kBlock, 0, st>>>((const T*)p->bend_compliance, c->bend_perm,
                                                                (T*)c->bend_at, (T)ih2, c->n_bend, c->flag);
     if (c->n_tet)
-      k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_perm, c->tet_nu,
+      if (p->tet_mu)
+        k_gather_tet_lame<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_mu, (const T*)p->tet_lambda,
+                                                                   c->tet_perm, c->tet_vol, (T*)c->tet_atD,
+                                                                   (T*)c->tet_atH, (T*)c->tet_gamma, ih2,
+                                                                   c->gamma_one, c->n_tet, c->flag);
+      else
+        k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_perm, c->tet_nu,
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
     check_launch();
@@ -709,7 +740,7 @@ template <class T> struct Ops {
     const int V = c->V;
     fill<double>(c->dist_acc, 0.0, c->n_dist, st);
     fill<double>(c->bend_acc, 0.0, c->n_bend, st);
-    fill<double>(c->tet_acc, 0.0, c->n_tet, st);
+    fill<double>(c->tet_acc, 0.0, (size_t)3 * c->n_tet, st);
     if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
     if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
     k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
@@ -730,9 +761,13 @@ template <class T> struct Ops {
     if (out->bend_compliance && c->n_bend)
       k_scatter_alpha_grad<<<nblocks(c->n_bend), kBlock, 0, st>>>(c->bend_acc, c->bend_perm, out->bend_compliance,
                                                                   ih2, c->n_bend);
-    if (out->tet_E && c->n_tet)
+    if (out->tet_E && c->n_tet && p->tet_E)
       k_scatter_E_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_E,
                                                                 out->tet_E, c->n_tet);
+    if ((out->tet_mu || out->tet_lambda) && c->n_tet && p->tet_mu)
+      k_scatter_lame_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_mu,
+                                                                   (const T*)p->tet_lambda, out->tet_mu,
+                                                                   out->tet_lambda, c->gamma_one, c->n_tet);
     check_launch();
   }
 
@@ -785,6 +820,11 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
       (o->block_size < 64 || o->block_size > kMaxBlock || (o->block_size & (o->block_size - 1)) != 0))
     fail(XPBD_ERR_INVALID, "block_size must be 0 or a power of two in [64, %d]", kMaxBlock);
   c->block = o->block_size ? o->block_size : kBlock;
+  if (o->group_records < 0 || o->group_records > 2) fail(XPBD_ERR_INVALID, "group_records must be 0, 1 or 2");
+  if (o->group_block != 0 && (o->group_block < 64 || o->group_block > kBlock || (o->group_block & (o->group_block - 1))))
+    fail(XPBD_ERR_INVALID, "group_block must be 0 or a power of two in [64, %d]", kBlock);
+  c->group_stream = o->group_records == 2;
+  c->group_block = o->group_block ? o->group_block : kBlock;
   c->dtype = o->dtype;
   c->tsz = o->dtype == XPBD_F32 ? 4 : 8;
   c->V = m->n_verts;
@@ -1157,8 +1197,9 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
     }
     G.smem_fwd = mf;
     G.smem_rev = mr;
+    G.smem_tile = al32((size_t)nv_max * sizeof(Vec4<T>));
     G.tape_bytes = tsum;
-    G.lds = P > 0 && nv_max <= 65535 && std::max(mf, mr) <= c->lds_limit;
+    G.lds = P > 0 && nv_max <= 65535 && (c->group_stream ? G.smem_tile : std::max(mf, mr)) <= c->lds_limit;
     if (G.lds) {
       // record images in LDS layout
       size_t fbase = fimg.size(), rbase = rimg.size();
@@ -1216,7 +1257,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
           ro += al32((size_t)n * rev_rec_bytes<T>(ty));
         }
       }
-      c->max_group_lds = std::max(c->max_group_lds, (int)std::max(mf, mr));
+      c->max_group_lds = std::max(c->max_group_lds, (int)(c->group_stream ? G.smem_tile : std::max(mf, mr)));
       G.pv_start = (int*)c->alloc(pv_start.size() * sizeof(int));
       G.pv = (int*)c->alloc(pv.size() * sizeof(int));
       G.cnt = (int*)c->alloc(cnt.size() * sizeof(int));
@@ -1294,8 +1335,8 @@ void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
     if (c->n_tet) {
       c->tet_lambD = c->alloc(c->n_tet * T_);
       c->tet_lambH = c->alloc(c->n_tet * T_);
-      c->tet_eb = c->alloc(c->n_tet * T_);
-      c->tet_acc = (double*)c->alloc(c->n_tet * sizeof(double));
+      c->tet_eb = c->alloc(3 * c->n_tet * T_);
+      c->tet_acc = (double*)c->alloc(3 * c->n_tet * sizeof(double));
     }
     if (c->n_contact) {
       c->contact_lamb = c->alloc(c->n_contact * T_);
@@ -1390,7 +1431,9 @@ xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_
   return guarded(c, [&] {
     if (c->in_pack) fail(XPBD_ERR_STATE, "forward: the context is serving a job of a pack");
     if (!p || !x0 || !v0 || n_frames < 1) fail(XPBD_ERR_INVALID, "forward: null argument or n_frames < 1");
-    if (c->n_tet && !p->tet_E) fail(XPBD_ERR_INVALID, "forward: tet_E required");
+    if (c->n_tet && !p->tet_E && !(p->tet_mu && p->tet_lambda))
+      fail(XPBD_ERR_INVALID, "forward: tet_E, or tet_mu and tet_lambda, required");
+    if (!p->tet_mu != !p->tet_lambda) fail(XPBD_ERR_INVALID, "forward: tet_mu and tet_lambda go together");
     if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
     c->have_forward = false;
     c->fwd_recorded = false;
@@ -1424,7 +1467,8 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
     if (!c->have_forward) fail(XPBD_ERR_STATE, "adjoint: no preceding forward on this context");
     const xpbd_params& q = c->fwd_params;
     if (q.dist_compliance != p->dist_compliance || q.bend_compliance != p->bend_compliance ||
-        q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0)
+        q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0 ||
+        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda)
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
     int mode = c->tape_mode_opt;
     if (c->fwd_recorded) {

@@ -254,8 +254,11 @@ __device__ __forceinline__ bool bend_rev(Vec4<T> P[4], const Vec4<T>* tape, int 
 // tet: ebar accumulates sum over projections of (atbar_D at_D + atbar_H at_H),
 // i.e. alphabar_D alpha_D + alphabar_H alpha_H, whence dL/dE = -ebar / E.
 template <class T>
+// ebD, ebH accumulate abar~ alpha~ of the deviatoric and hydrostatic rows (the
+// compliance adjoints times the compliances), gb the adjoint of gamma
+// (C_H = det F - gamma, so gbar -= Cbar_H)
 __device__ __forceinline__ bool tet_rev(Vec4<T> P[4], const Vec4<T>* tape, int count, const M3<T>& B, T atD, T atH,
-                                        T gamma, T& lbD, T& lbH, T& eb) {
+                                        T gamma, T& lbD, T& lbH, T& ebD, T& ebH, T& gmb) {
   Vec4<T> t0 = tape[0], t1 = tape[count], t2 = tape[2 * count];
   V3<T> d[3] = {{t0.x, t0.y, t0.z}, {t0.w, t1.x, t1.y}, {t1.z, t1.w, t2.x}};
   T lD = t2.y, lH = t2.z;
@@ -269,7 +272,8 @@ __device__ __forceinline__ bool tet_rev(Vec4<T> P[4], const Vec4<T>* tape, int c
     tet_hyd_hvp(s.evH, B, gb, hv);
     T Cb = -dlb / s.DH;
     lbH = lbH - dlb * atH / s.DH;
-    eb = eb - dlb * (lH + s.dlH) / s.DH * atH;
+    ebH = ebH - dlb * (lH + s.dlH) / s.DH * atH;
+    gmb = gmb - Cb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evH.g[k] + hv[k]);
   }
@@ -278,7 +282,7 @@ __device__ __forceinline__ bool tet_rev(Vec4<T> P[4], const Vec4<T>* tape, int c
     tet_dev_hvp(s.evD, B, gb, hv);
     T Cb = -dlb / s.DD;
     lbD = lbD - dlb * atD / s.DD;
-    eb = eb - dlb * (lD + s.dlD) / s.DD * atD;
+    ebD = ebD - dlb * (lD + s.dlD) / s.DD * atD;
 #pragma unroll
     for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evD.g[k] + hv[k]);
   }
@@ -397,13 +401,20 @@ __device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int cou
   int4 q = R.idx[j];
   T lbD = FIRST ? T(0) : D.t_lambD[j];
   T lbH = FIRST ? T(0) : D.t_lambH[j];
-  T eb = FIRST ? T(0) : D.t_eb[j];
+  const int nt = R.n;
+  T ebD = FIRST ? T(0) : D.t_eb[j], ebH = FIRST ? T(0) : D.t_eb[nt + j], gb = FIRST ? T(0) : D.t_eb[2 * nt + j];
   Vec4<T> P[4] = {D.XB[q.x], D.XB[q.y], D.XB[q.z], D.XB[q.w]};
-  if (tet_rev(P, tape + t, count, load_B(R.B, R.n, j), R.atD[j], R.atH[j], R.gamma[j], lbD, lbH, eb)) {
+  if (tet_rev(P, tape + t, count, load_B(R.B, R.n, j), R.atD[j], R.atH[j], R.gamma[j], lbD, lbH, ebD, ebH, gb)) {
     D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; D.XB[q.w] = P[3];
   }
-  if (LAST) D.t_acc[j] += (double)eb;
-  else { D.t_lambD[j] = lbD; D.t_lambH[j] = lbH; D.t_eb[j] = eb; }
+  if (LAST) {
+    D.t_acc[j] += (double)ebD;
+    D.t_acc[nt + j] += (double)ebH;
+    D.t_acc[2 * nt + j] += (double)gb;
+  } else {
+    D.t_lambD[j] = lbD; D.t_lambH[j] = lbH;
+    D.t_eb[j] = ebD; D.t_eb[nt + j] = ebH; D.t_eb[2 * nt + j] = gb;
+  }
 }
 
 template <class T, bool FIRST, bool LAST>
@@ -591,14 +602,48 @@ __global__ __launch_bounds__(kBlock) void k_scatter_alpha_grad(const double* __r
   if (i >= n) return;
   out[perm[i]] = acc[i] * scale;
 }
-// dL/dE = -ebar / E
+// acc = [abar~_D alpha~_D | abar~_H alpha~_H | gammabar] per tet (internal order).
+// At fixed nu both compliances scale as 1/E and gamma does not depend on E:
+// dL/dE = -(acc_D + acc_H) / E
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_scatter_E_grad(const double* __restrict__ acc, const int* __restrict__ perm,
                                                            const T* __restrict__ E, double* __restrict__ out, int n) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   int u = perm[i];
-  out[u] = -acc[i] / (double)E[u];
+  out[u] = -(acc[i] + acc[n + i]) / (double)E[u];
+}
+// Lame parameters (Sec. 5.2): alpha_D = 1/(mu V), alpha_H = 1/(lambda V),
+// gamma = 1 + mu/lambda (1 with gamma_one):
+// dL/dmu = -acc_D / mu + gammabar / lambda,
+// dL/dlambda = -acc_H / lambda - gammabar mu / lambda^2
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scatter_lame_grad(const double* __restrict__ acc, const int* __restrict__ perm,
+                                                              const T* __restrict__ mu, const T* __restrict__ la,
+                                                              double* __restrict__ out_mu, double* __restrict__ out_la,
+                                                              int gamma_one, int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int u = perm[i];
+  double m = (double)mu[u], l = (double)la[u], g = gamma_one ? 0.0 : acc[2 * n + i];
+  if (out_mu) out_mu[u] = -acc[i] / m + g / l;
+  if (out_la) out_la[u] = -acc[n + i] / l - g * m / (l * l);
+}
+// per tet from Lame parameters: atD = 1/(mu V h^2), atH = 1/(lambda V h^2),
+// gamma = 1 + mu/lambda (or 1); flag |= non-positive or non-finite
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather_tet_lame(const T* __restrict__ mu, const T* __restrict__ la,
+                                                            const int* __restrict__ perm, const double* __restrict__ vol,
+                                                            T* __restrict__ atD, T* __restrict__ atH, T* __restrict__ gam,
+                                                            double inv_h2, int gamma_one, int n, int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int u = perm[i];
+  double m = (double)mu[u], l = (double)la[u], V = vol[i];
+  if (!finite_d(m) || !finite_d(l) || !(m > 0.0) || !(l > 0.0)) *flag = 1;
+  atD[i] = (T)(inv_h2 / (m * V));
+  atH[i] = (T)(inv_h2 / (l * V));
+  gam[i] = gamma_one ? T(1) : (T)(1.0 + m / l);
 }
 
 // Deterministic block reduction of the per-contact sphere adjoints into the
@@ -688,7 +733,7 @@ template <class T> struct STet { T B[9]; T atD, atH, gam, lD, lH; unsigned l01, 
 template <class T> struct SCon { T lam; unsigned l; };
 template <class T> struct RDist { T rest, at, lamb, ab; unsigned l; };
 template <class T> struct RBend { T th0, at, lamb, ab; unsigned l01, l23; };
-template <class T> struct RTet { T B[9]; T atD, atH, gam, lbD, lbH, eb; unsigned l01, l23; };
+template <class T> struct RTet { T B[9]; T atD, atH, gam, lbD, lbH, ebD, ebH, gb; unsigned l01, l23; };
 template <class T> struct RCon { Vec4<T> sa; T lamb; unsigned l; };
 
 __host__ __device__ __forceinline__ size_t al32(size_t b) { return (b + 31) & ~(size_t)31; }
@@ -728,23 +773,28 @@ __device__ __forceinline__ void lds_barrier() {
 __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes) {
   const uint4* s = reinterpret_cast<const uint4*>(src);
   uint4* d = reinterpret_cast<uint4*>(dst);
-  for (size_t i = threadIdx.x; i < bytes / 16; i += kBlock) d[i] = s[i];
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
 }
 
-template <class T, bool FIRST, bool TAPE>
+// RL: the patch's record image is staged in LDS with its vertices (one bulk
+// copy in and out); otherwise only the vertex tile is in LDS and each set's
+// records are read and written in place in the global image, which keeps
+// the workgroup's LDS small so many patches run per CU.
+template <class T, bool FIRST, bool TAPE, bool RL>
 __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char* __restrict__ fimg,
                                                       char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
   const int* cnt = G.cnt + (size_t)p * G.nset;
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
-  unsigned char* rec = smem + al32((size_t)nv * sizeof(Vec4<T>));
-  size_t rbytes = 0;
-  for (int q = 0; q < G.nset; ++q) rbytes += al32((size_t)cnt[q] * fwd_rec_bytes<T>(G.set_type[q]));
   char* gimg = fimg + G.fimg[p];
-  for (int i = tid; i < nv; i += kBlock) sX[i] = D.X[G.pv[v0 + i]];
-  copy16(rec, gimg, rbytes);
+  unsigned char* rec = RL ? smem + al32((size_t)nv * sizeof(Vec4<T>)) : reinterpret_cast<unsigned char*>(gimg);
+  size_t rbytes = 0;
+  if (RL)
+    for (int q = 0; q < G.nset; ++q) rbytes += al32((size_t)cnt[q] * fwd_rec_bytes<T>(G.set_type[q]));
+  for (int i = tid; i < nv; i += kB) sX[i] = D.X[G.pv[v0 + i]];
+  if (RL) copy16(rec, gimg, rbytes);
   lds_barrier();
   char* gt = TAPE ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
   unsigned char* r = rec;
@@ -753,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char
     Vec4<T>* tape = reinterpret_cast<Vec4<T>*>(gt);
     switch (ty) {
       case 0:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           SDist<T>& s = reinterpret_cast<SDist<T>*>(r)[i];
           int la = lo16(s.l), lb = hi16(s.l);
           Vec4<T> a = sX[la], bb = sX[lb];
@@ -764,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char
         }
         break;
       case 1:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           SBend<T>& s = reinterpret_cast<SBend<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
@@ -775,7 +825,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char
         }
         break;
       case 2:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           STet<T>& s = reinterpret_cast<STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
@@ -789,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char
         }
         break;
       default:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           SCon<T>& s = reinterpret_cast<SCon<T>*>(r)[i];
           int l = (int)s.l;
           Vec4<T> pp = sX[l];
@@ -804,33 +854,36 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char
     if (TAPE) gt += al32((size_t)n * tape_words(ty) * sizeof(T));
     lds_barrier();
   }
-  for (int i = tid; i < nv; i += kBlock) D.X[G.pv[v0 + i]] = sX[i];
-  copy16(gimg, rec, rbytes);
+  for (int i = tid; i < nv; i += kB) D.X[G.pv[v0 + i]] = sX[i];
+  if (RL) copy16(gimg, rec, rbytes);
 }
 
-template <class T, bool FIRST, bool LAST>
+template <class T, bool FIRST, bool LAST, bool RL>
 __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char* __restrict__ rimg,
                                                       const char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
-  const int p = blockIdx.x, tid = threadIdx.x;
+  const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
   const int* cnt = G.cnt + (size_t)p * G.nset;
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
-  unsigned char* rec = smem + al32((size_t)nv * sizeof(Vec4<T>));
   size_t rbytes = 0, tbytes = 0;
   for (int q = 0; q < G.nset; ++q) {
     rbytes += al32((size_t)cnt[q] * rev_rec_bytes<T>(G.set_type[q]));
     tbytes += al32((size_t)cnt[q] * tape_words(G.set_type[q]) * sizeof(T));
   }
-  unsigned char* tap = rec + rbytes;
   char* gimg = rimg + G.rimg[p];
-  for (int i = tid; i < nv; i += kBlock) sX[i] = D.XB[G.pv[v0 + i]];
-  copy16(rec, gimg, rbytes);
-  copy16(tap, tape_iter + G.tape_off + G.tpos[p], tbytes);
+  const char* gtap = tape_iter + G.tape_off + G.tpos[p];
+  unsigned char* rec = RL ? smem + al32((size_t)nv * sizeof(Vec4<T>)) : reinterpret_cast<unsigned char*>(gimg);
+  const unsigned char* tap = RL ? rec + rbytes : reinterpret_cast<const unsigned char*>(gtap);
+  for (int i = tid; i < nv; i += kB) sX[i] = D.XB[G.pv[v0 + i]];
+  if (RL) {
+    copy16(rec, gimg, rbytes);
+    copy16(rec + rbytes, gtap, tbytes);
+  }
   lds_barrier();
   // walk the sets backwards: start past the last region
   unsigned char* r = rec + rbytes;
-  unsigned char* t = tap + tbytes;
+  const unsigned char* t = tap + tbytes;
   for (int q = G.nset - 1; q >= 0; --q) {
     const int n = cnt[q], ty = G.set_type[q];
     r -= al32((size_t)n * rev_rec_bytes<T>(ty));
@@ -838,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char
     const Vec4<T>* st = reinterpret_cast<const Vec4<T>*>(t);
     switch (ty) {
       case 0:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           RDist<T>& s = reinterpret_cast<RDist<T>*>(r)[i];
           int la = lo16(s.l), lb = hi16(s.l);
           Vec4<T> A = sX[la], Bv = sX[lb];
@@ -848,7 +901,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char
         }
         break;
       case 1:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           RBend<T>& s = reinterpret_cast<RBend<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
@@ -860,22 +913,23 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char
         }
         break;
       case 2:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           RTet<T>& s = reinterpret_cast<RTet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
           M3<T> B;
 #pragma unroll
           for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
-          T lbD = FIRST ? T(0) : s.lbD, lbH = FIRST ? T(0) : s.lbH, eb = FIRST ? T(0) : s.eb;
-          if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, eb)) {
+          T lbD = FIRST ? T(0) : s.lbD, lbH = FIRST ? T(0) : s.lbH;
+          T ebD = FIRST ? T(0) : s.ebD, ebH = FIRST ? T(0) : s.ebH, gb = FIRST ? T(0) : s.gb;
+          if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, ebD, ebH, gb)) {
             sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
           }
-          s.lbD = lbD; s.lbH = lbH; s.eb = eb;
+          s.lbD = lbD; s.lbH = lbH; s.ebD = ebD; s.ebH = ebH; s.gb = gb;
         }
         break;
       default:
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += kB) {
           RCon<T>& s = reinterpret_cast<RCon<T>*>(r)[i];
           int l = (int)s.l;
           Vec4<T> P = sX[l];
@@ -888,9 +942,9 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char
     }
     lds_barrier();
   }
-  for (int i = tid; i < nv; i += kBlock) D.XB[G.pv[v0 + i]] = sX[i];
+  for (int i = tid; i < nv; i += kB) D.XB[G.pv[v0 + i]] = sX[i];
   if (!LAST) {
-    copy16(gimg, rec, rbytes);
+    if (RL) copy16(gimg, rec, rbytes);
     return;
   }
   // last reverse iteration of the substep: FP64 parameter adjoints and the
@@ -900,10 +954,17 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char
   for (int q = 0; q < G.nset; ++q) {
     const int n = cnt[q], ty = G.set_type[q], jb = first[q];
     switch (ty) {
-      case 0: for (int i = tid; i < n; i += kBlock) D.d_acc[jb + i] += (double)reinterpret_cast<RDist<T>*>(r)[i].ab; break;
-      case 1: for (int i = tid; i < n; i += kBlock) D.b_acc[jb + i] += (double)reinterpret_cast<RBend<T>*>(r)[i].ab; break;
-      case 2: for (int i = tid; i < n; i += kBlock) D.t_acc[jb + i] += (double)reinterpret_cast<RTet<T>*>(r)[i].eb; break;
-      default: for (int i = tid; i < n; i += kBlock) D.c_sacc[jb + i] = reinterpret_cast<RCon<T>*>(r)[i].sa; break;
+      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)reinterpret_cast<RDist<T>*>(r)[i].ab; break;
+      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)reinterpret_cast<RBend<T>*>(r)[i].ab; break;
+      case 2:
+        for (int i = tid; i < n; i += kB) {
+          const RTet<T>& rt = reinterpret_cast<RTet<T>*>(r)[i];
+          D.t_acc[jb + i] += (double)rt.ebD;
+          D.t_acc[D.tr.n + jb + i] += (double)rt.ebH;
+          D.t_acc[2 * D.tr.n + jb + i] += (double)rt.gb;
+        }
+        break;
+      default: for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = reinterpret_cast<RCon<T>*>(r)[i].sa; break;
     }
     r += al32((size_t)n * rev_rec_bytes<T>(ty));
   }

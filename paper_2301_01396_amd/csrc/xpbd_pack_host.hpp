@@ -111,7 +111,8 @@ template <class T> struct PackOps {
   static void add(xpbd_pack pk, xpbd_ctx c, const xpbd_job* j, hipStream_t st, int64_t* id) {
     const int F = j->n_frames;
     if (!j->x0 || !j->v0 || F < 1) fail(XPBD_ERR_INVALID, "pack add: null x0 / v0 or n_frames < 1");
-    if (c->n_tet && !j->params.tet_E) fail(XPBD_ERR_INVALID, "pack add: tet_E required");
+    if (c->n_tet && !j->params.tet_E && !(j->params.tet_mu && j->params.tet_lambda))
+      fail(XPBD_ERR_INVALID, "pack add: tet_E, or tet_mu and tet_lambda, required");
     const bool adj = j->targets != nullptr;
     if (adj && !j->x_frames) fail(XPBD_ERR_INVALID, "pack add: a job with an adjoint needs x_frames");
     c->have_forward = false;

@@ -52,17 +52,18 @@ class Options(C.Structure):
     _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("iterations", C.c_int32),
                 ("gravity", C.c_double * 3), ("dtype", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
                 ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32), ("launch_mode", C.c_int32),
-                ("persistent_blocks", C.c_int32), ("block_size", C.c_int32)]
+                ("persistent_blocks", C.c_int32), ("block_size", C.c_int32), ("group_records", C.c_int32),
+                ("group_block", C.c_int32)]
 
 
 class Params(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
-                ("sphere", C.c_double * 4)]
+                ("sphere", C.c_double * 4), ("tet_mu", _vp), ("tet_lambda", _vp)]
 
 
 class Grads(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
-                ("x0", _vp), ("v0", _vp), ("sphere", _vp)]
+                ("x0", _vp), ("v0", _vp), ("sphere", _vp), ("tet_mu", _vp), ("tet_lambda", _vp)]
 
 
 class Info(C.Structure):
@@ -171,7 +172,8 @@ class Simulator:
     def __init__(self, scene, dtype: torch.dtype = torch.float32, device="cuda:0",
                  hbm_budget_bytes: int = 0, tape_mode: int = 0, tet_gamma_one: bool = False,
                  iterations: Optional[int] = None, substeps: Optional[int] = None, launch_mode: int = 0,
-                 persistent_blocks: int = 0, use_groups: bool = True, block_size: int = 0):
+                 persistent_blocks: int = 0, use_groups: bool = True, block_size: int = 0,
+                 group_records: int = 0, group_block: int = 0):
         self.lib = load()
         self.scene = scene
         self.dtype = dtype
@@ -204,6 +206,8 @@ class Simulator:
         o.launch_mode = launch_mode
         o.persistent_blocks = persistent_blocks
         o.block_size = block_size
+        o.group_records = group_records
+        o.group_block = group_block
         with torch.cuda.device(self.device):
             rc = self.lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(self._ctx))
         if rc != XPBD_OK:
@@ -253,22 +257,35 @@ class Simulator:
         return t
 
     # ------------------------------------------------------------------ API
-    def _inputs(self, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere):
+    def _inputs(self, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu=None,
+                tet_lambda=None):
         sc = self.scene
         V = sc.n_verts
         x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
         v0 = self._arg(sc.v0 if v0 is None else v0, (V, 3))
         da = self._arg(sc.dist_alpha if dist_alpha is None else dist_alpha, (sc.n_dist,)) if sc.n_dist else None
         ba = self._arg(sc.bend_alpha if bend_alpha is None else bend_alpha, (sc.n_bend,)) if sc.n_bend else None
-        te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet,)) if sc.n_tet else None
+        lame = tet_mu is not None or tet_lambda is not None
+        te = None
+        if sc.n_tet and not lame:
+            te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet,))
         fe = f_ext if f_ext is not None else sc.f_ext
         fe = self._arg(fe, (n_frames, V, 3)) if fe is not None else None
-        return x0, v0, da, ba, te, fe, self._params(da, ba, te, fe, sphere)
+        p = self._params(da, ba, te, fe, sphere)
+        tm = tl = None
+        if lame:
+            tm = self._arg(tet_mu, (sc.n_tet,))
+            tl = self._arg(tet_lambda, (sc.n_tet,))
+            p.tet_mu, p.tet_lambda = _ptr(tm), _ptr(tl)
+        self._lame = lame
+        return x0, v0, da, ba, te, fe, p, (tm, tl)
 
     def _grad_buffers(self, F, want):
         sc = self.scene
         V = sc.n_verts
-        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere"))
+        lame = getattr(self, "_lame", False)
+        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext", "sphere") +
+                   (("tet_mu", "tet_lambda") if lame else ("tet_E",)))
         dev, f64 = self.device, torch.float64
         g = {}
         if "x0" in want:
@@ -285,19 +302,29 @@ class Simulator:
             g["f_ext"] = torch.empty((F, V, 3), dtype=self.dtype, device=dev)
         if "sphere" in want:
             g["sphere"] = torch.empty(4, dtype=f64, device=dev)
+        for k in ("tet_mu", "tet_lambda"):
+            if k in want and sc.n_tet and lame:
+                g[k] = torch.empty(sc.n_tet, dtype=f64, device=dev)
+        if not lame:
+            g.pop("tet_mu", None)
+            g.pop("tet_lambda", None)
+        else:
+            g.pop("tet_E", None)
         gr = Grads(*(_ptr(g.get(k)) for k in ("dist_alpha", "bend_alpha", "tet_E", "f_ext", "x0", "v0",
-                                              "sphere")))
+                                              "sphere", "tet_mu", "tet_lambda")))
         return g, gr
 
     def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
-                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False):
+                f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False,
+                tet_mu=None, tet_lambda=None):
         """Roll out; returns (x_frames or None, x_final, v_final) on the device.
 
         ``for_adjoint``: an adjoint will follow; the library may keep the record
         of every projection now so the adjoint needs no recomputation."""
         sc = self.scene
         V = sc.n_verts
-        x0, v0, da, ba, te, fe, p = self._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
+        x0, v0, da, ba, te, fe, p, lm = self._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere,
+                                                     tet_mu, tet_lambda)
         xf = None
         if frames:
             xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
@@ -307,14 +334,15 @@ class Simulator:
         rc = self.lib.xpbd_forward(self._ctx, _ptr(x0), _ptr(v0), C.byref(p), n_frames, _ptr(xf), _ptr(xe),
                                    _ptr(ve), FWD_FOR_ADJOINT if for_adjoint else 0, _stream_ptr(self.device))
         self._check(rc)
-        self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames)
+        self._fwd_keep = (p, x0, v0, da, ba, te, fe, n_frames, lm)
+        self.forward_count = getattr(self, "forward_count", 0) + 1
         return xf, xe, ve
 
     def adjoint(self, dLdx_frames=None, frame_mask=None, dLdv_final=None, want=None) -> Dict[str, torch.Tensor]:
         """Exact adjoint of the last forward; returns a dict of gradients."""
         if self._fwd_keep is None:
             raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
-        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+        p, x0, v0, da, ba, te, fe, F, _lm = self._fwd_keep
         sc = self.scene
         V = sc.n_verts
         g, gr = self._grad_buffers(F, want)
@@ -338,7 +366,7 @@ class Simulator:
         form, solved by CG): returns (gradients, CG report)."""
         if self._fwd_keep is None:
             raise XPBDError(XPBD_ERR_STATE, "adjoint without forward")
-        p, x0, v0, da, ba, te, fe, F = self._fwd_keep
+        p, x0, v0, da, ba, te, fe, F, _lm = self._fwd_keep
         V = self.scene.n_verts
         g, gr = self._grad_buffers(F, want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
         gr.tet_E = None
@@ -430,7 +458,7 @@ class Pack:
         if sim.dtype != self.dtype or sim.device != self.device:
             raise ValueError("simulator dtype / device differ from the pack's")
         V = sim.scene.n_verts
-        x0, v0, da, ba, te, fe, p = sim._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
+        x0, v0, da, ba, te, fe, p, lm = sim._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere)
         adj = targets is not None
         xf = torch.empty((n_frames, V, 3), dtype=self.dtype, device=self.device) if (frames or adj) else None
         xe = torch.empty((V, 3), dtype=self.dtype, device=self.device)

@@ -408,7 +408,7 @@ def _group_sets(typed, sel_of, V):
     return out_t, out_i
 
 
-def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
+def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0, 1, 2)) -> Scene:
     """Three-group tiled schedule for an nr x nc grid cloth.
 
     Group A: constraints inside one tile x tile tile (patch = tile).
@@ -419,6 +419,9 @@ def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
     Group C: the constraints that touch a corner vertex, then the contact
     set (patch = the tile of the half-shifted tiling around that corner).
     Every constraint is in exactly one group; an iteration runs A, B, C.
+    ``lds_groups`` selects which of A, B, C (0, 1, 2) are offered to the
+    library as LDS groups; the others run as ordinary sets.  The schedule
+    (and so every result) is the same either way.
     """
     dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
     assert np.array_equal(dist_v, sc.dist_v)
@@ -458,6 +461,7 @@ def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
             sets_i.append(np.nonzero(sc.inv_mass > 0)[0].astype(np.int32))
         if len(sets_t) > first:
             groups.append((first, len(sets_t), pm.astype(np.int32)))
+    groups = [g for k, g in enumerate(groups) if k in tuple(lds_groups)]
     # every constraint must lie within one patch of its group
     for (a, b, pm) in groups:
         for k in range(a, b):
@@ -605,13 +609,20 @@ def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int =
     return sc
 
 
-def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 0) -> Scene:
+def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 0,
+              tiling: str = "lines", lds_groups=(0,)) -> Scene:
     """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
     distance + bending, per-frame per-vertex force controls, dt 1/60,
-    2 substeps, 20 iterations.  tile > 0: tiled schedule."""
+    2 substeps, 20 iterations.  tile > 0: tiled schedule (as config_c2);
+    only the tile-interior group is offered as an LDS group by default (the
+    border and corner groups hold ~12% of the constraints in many tiny
+    patches, which run faster as ordinary sets)."""
     sc = cloth_grid(nr, nc, 1.0 / (nc - 1), pinned=(0, nc - 1))
     if tile:
-        tile_cloth(sc, nr, nc, tile)
+        if tiling == "lines":
+            tile_cloth_lines(sc, nr, nc, tile, lds_groups=lds_groups)
+        else:
+            tile_cloth(sc, nr, nc, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)
     sc.tet_E = np.zeros(0)
     sc.f_ext = force_field(force_seed, nr, nc, n_frames)

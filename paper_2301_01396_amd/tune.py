@@ -1,8 +1,9 @@
 """Launch-shape autotuner.
 
 Every launch structure the library offers computes bit-identical results
-(one launch per independent set at any workgroup size, LDS group launches,
-the persistent frame kernel at any grid size), so the choice is purely a
+(one launch per independent set at any workgroup size, LDS group launches
+with records staged in LDS or streamed at several workgroup sizes, the
+persistent frame kernel at any grid size), so the choice is purely a
 performance one.  The
 tuner times a short forward + adjoint rollout for each candidate and keeps
 the fastest per shape bucket (dtype, log2 of the vertex count, sets per
@@ -36,18 +37,22 @@ def candidates(scene) -> List[Dict[str, int]]:
     """Every result-invariant launch shape: one launch per set at several
     workgroup sizes, LDS group launches (if the schedule has groups), the
     persistent frame kernel at several grid sizes."""
-    c = [{"launch_mode": 1, "use_groups": 0, "persistent_blocks": 0, "block_size": bs} for bs in (128, 256, 512)]
+    base = {"group_records": 0, "group_block": 0}
+    c = [dict(base, launch_mode=1, use_groups=0, persistent_blocks=0, block_size=bs) for bs in (128, 256, 512)]
     if getattr(scene, "groups", None):
-        c.append({"launch_mode": 1, "use_groups": 1, "persistent_blocks": 0, "block_size": 256})
+        for rec, gb in ((1, 256), (2, 64), (2, 128), (2, 256)):
+            c.append({"launch_mode": 1, "use_groups": 1, "persistent_blocks": 0, "block_size": 256,
+                      "group_records": rec, "group_block": gb})
     for b in (32, 64, 128):
-        c.append({"launch_mode": 2, "use_groups": 0, "persistent_blocks": b, "block_size": 256})
+        c.append(dict(base, launch_mode=2, use_groups=0, persistent_blocks=b, block_size=256))
     return c
 
 
 def measure(scene, cfg: Dict[str, int], dtype=torch.float32, frames: int = 1, reps: int = 2) -> float:
     """Seconds for one forward + adjoint of ``frames`` frames (best of reps)."""
     sim = Simulator(scene, dtype=dtype, launch_mode=cfg["launch_mode"], persistent_blocks=cfg["persistent_blocks"],
-                    use_groups=bool(cfg["use_groups"]), block_size=cfg.get("block_size", 0))
+                    use_groups=bool(cfg["use_groups"]), block_size=cfg.get("block_size", 0),
+                    group_records=cfg.get("group_records", 0), group_block=cfg.get("group_block", 0))
     try:
         best = float("inf")
         mask = np.zeros(frames, np.uint8)
@@ -101,4 +106,5 @@ def simulator(scene, dtype=torch.float32, **kw) -> Simulator:
     cfg = lookup(scene, dtype) or {}
     return Simulator(scene, dtype=dtype, launch_mode=cfg.get("launch_mode", 0),
                      persistent_blocks=cfg.get("persistent_blocks", 0),
-                     use_groups=bool(cfg.get("use_groups", 1)), block_size=cfg.get("block_size", 0), **kw)
+                     use_groups=bool(cfg.get("use_groups", 1)), block_size=cfg.get("block_size", 0),
+                     group_records=cfg.get("group_records", 0), group_block=cfg.get("group_block", 0), **kw)

@@ -157,13 +157,17 @@ def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
     ref = reference_case(sc, 2, n_threads=8, noise=0.01 if kind == "cloth" else 1e-3)
     a_sim = _sim(sc, dtype)
     b_sim = _sim(sc, dtype, use_groups=False)
-    ia, ib = a_sim.info(), b_sim.info()
+    c_sim = _sim(sc, dtype, group_records=2, group_block=64)   # records streamed, one wave per patch
+    ia, ib, ic = a_sim.info(), b_sim.info(), c_sim.info()
     assert ia["n_groups_lds"] == ia["n_groups"] == len(sc.groups) and ib["n_groups"] == 0
+    assert ic["n_groups_lds"] == len(sc.groups) and ic["max_group_lds_bytes"] < ia["max_group_lds_bytes"]
     a = gpu_case(a_sim, 2, ref)
     b = gpu_case(b_sim, 2, ref)
-    assert np.array_equal(a["x_frames"], b["x_frames"])
-    for k, v in b["grads"].items():
-        assert np.array_equal(a["grads"][k], v), k
+    c = gpu_case(c_sim, 2, ref)
+    for o in (b, c):
+        assert np.array_equal(a["x_frames"], o["x_frames"])
+        for k, v in o["grads"].items():
+            assert np.array_equal(a["grads"][k], v), k
     tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
     compare(sc, ref, a, *tol)
 
@@ -195,3 +199,35 @@ def test_nonfinite_parameter_is_rejected():
         sim.forward(1, dist_alpha=a)
     assert e.value.status == XPBD_ERR_NONFINITE
     del torch
+
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_small_tets_lame_parameters(dtype, pos_tol, grad_tol):
+    """Per-tet (mu, lambda) inputs, perturbed away from any single nu: positions
+    and dL/dmu, dL/dlambda (with the gamma = 1 + mu/lambda path) against the
+    reference."""
+    import torch
+    sc = scenes.small_tets(n=3, frames=3, substeps=2, iterations=5)
+    rng = np.random.default_rng(21)
+    E, nu = sc.tet_E, sc.tet_nu
+    mu = E / (2 * (1 + nu)) * np.exp(0.3 * rng.standard_normal(sc.n_tet))
+    la = E * nu / ((1 + nu) * (1 - 2 * nu)) * np.exp(0.3 * rng.standard_normal(sc.n_tet))
+    osc = O.OracleScene(sc, n_threads=4)
+    xf, xe, ve = O.forward(osc, 3, tet_mu=mu, tet_lambda=la)
+    tgt = xf + 1e-3 * rng.standard_normal(xf.shape)
+    mask = np.array([1, 0, 1], bool)
+    L, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, 3, dL, tet_mu=mu, tet_lambda=la)
+    sim = _sim(sc, dtype)
+    gx, gxe, gve = sim.forward(3, tet_mu=sim.tensor(mu), tet_lambda=sim.tensor(la), for_adjoint=True)
+    loss, gdl = sim.goal_l2(gx, sim.tensor(tgt), mask)
+    gg = sim.adjoint(gdl, mask)
+    torch.cuda.synchronize()
+    assert "tet_E" not in gg and {"tet_mu", "tet_lambda"} <= set(gg)
+    assert rel(gx.double().cpu().numpy(), xf) <= pos_tol
+    for k in ("tet_mu", "tet_lambda", "x0", "v0"):
+        assert np.linalg.norm(g[k]) > 0, k
+        assert rel(gg[k].cpu().numpy(), g[k]) <= grad_tol, (k, rel(gg[k].cpu().numpy(), g[k]))
+    # a rollout with E afterwards goes back to the Young's-modulus gradient
+    sim.forward(3, for_adjoint=True)
+    assert "tet_E" in sim.adjoint(gdl, mask)

@@ -420,6 +420,42 @@ def test_p7_adjoint_matches_finite_differences_tets():
     _fd_check(osc, F, dirs, base, loss, g, 1e-4, 1e-6)
 
 
+def test_p7_lame_parameter_gradients_match_finite_differences():
+    """Per-tet Lame parameters (mu, lambda) drive both compliances and the
+    hydrostatic rest offset gamma = 1 + mu/lambda (Sec. 5.2): the adjoint's
+    dL/dmu and dL/dlambda, including the gamma path, against central
+    differences, and their combination at fixed nu against dL/dE."""
+    sc = scenes.small_tets(n=2, frames=3)
+    osc = O.OracleScene(sc)
+    F = 3
+    rng = np.random.default_rng(8)
+    E, nu = sc.tet_E, sc.tet_nu
+    mu = E / (2 * (1 + nu))
+    la = E * nu / ((1 + nu) * (1 - 2 * nu))
+    xf, _, _ = O.forward(osc, F, tet_mu=mu, tet_lambda=la)
+    xe, _, _ = O.forward(osc, F)
+    assert np.allclose(xf, xe, rtol=0, atol=1e-12)       # same material either way
+    tgt = xf + 0.001 * rng.standard_normal(xf.shape)
+    mask = np.array([1, 0, 1], bool)
+    _, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, F, dL, tet_mu=mu, tet_lambda=la)
+    base = dict(tet_mu=mu, tet_lambda=la)
+
+    def loss(tet_mu, tet_lambda):
+        x, _, _ = O.forward(osc, F, tet_mu=tet_mu, tet_lambda=tet_lambda)
+        return O.goal_l2(x, tgt, mask)[0]
+
+    dirs = {"tet_mu": rng.standard_normal(sc.n_tet) * mu, "tet_lambda": rng.standard_normal(sc.n_tet) * la}
+    _fd_check(osc, F, dirs, base, loss, g, 1e-4, 1e-6)
+    # at fixed nu: dL/dE = dL/dmu mu/E + dL/dlambda lambda/E
+    gE = O.adjoint(osc, F, dL)["tet_E"]
+    assert np.allclose(gE, (g["tet_mu"] * mu + g["tet_lambda"] * la) / E, rtol=1e-9, atol=0)
+    # the gamma path matters: with gamma fixed at 1 the gradients differ
+    osc1 = O.OracleScene(sc, tet_gamma_one=True)
+    g1 = O.adjoint(osc1, F, dL, tet_mu=mu, tet_lambda=la)
+    assert not np.allclose(g1["tet_mu"], g["tet_mu"])
+
+
 # ------------------------------------------------------------------ P8
 
 def test_p8_exact_adjoint_tends_to_implicit_adjoint_on_a_chain():

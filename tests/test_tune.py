@@ -53,7 +53,8 @@ def test_tuned_simulator_matches_default(tmp_path):
     for cfg in [best] + tune.candidates(sc):
         sim = Simulator(sc, dtype=torch.float32, launch_mode=cfg["launch_mode"],
                         persistent_blocks=cfg["persistent_blocks"], use_groups=bool(cfg["use_groups"]),
-                        block_size=cfg["block_size"])
+                        block_size=cfg["block_size"], group_records=cfg["group_records"],
+                        group_block=cfg["group_block"])
         xf, xe, ve = sim.forward(1)
         outs.append(xe.cpu().numpy())
         sim.close()
