@@ -116,7 +116,7 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str, tile: int = -1, frames: int = 0):
+def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = ""):
     from paper_2301_01396_amd import scenes
     kw = {} if tile < 0 else {"tile": tile}
     if name == "c1":
@@ -128,6 +128,8 @@ def make_workload(name: str, tile: int = -1, frames: int = 0):
     if name == "c4":
         if frames:
             kw["n_frames"] = frames
+        if lds_groups:
+            kw["lds_groups"] = tuple(int(ch) for ch in lds_groups)
         return scenes.config_c4(**kw), None
     raise SystemExit(f"unknown workload {name}")
 
@@ -238,7 +240,7 @@ def implicit_bench(args):
     import torch
     from paper_2301_01396_amd.lib import Simulator
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    sc, tg = make_workload(args.workload, args.tile, args.frames)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     sim = Simulator(sc, dtype=dtype)
@@ -281,6 +283,43 @@ def implicit_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def estimate_bench(args):
+    """Material estimation on the tet box of the tet workload's size
+    (Sec. 5.2): 100 random material clusters, a two-material target,
+    fixed-step gradient descent on (a, b); reports the time per descent
+    iteration (rollout + goal + exact adjoint + update) and the goal's fall."""
+    import torch
+    from paper_2301_01396_amd.estimate import estimate_materials
+    from paper_2301_01396_amd.lib import Simulator
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    n = args.estimate_n
+    F = args.frames or 20
+    model, tgt, d = scenes.material_estimation(n=n, frames=F)
+    tsim = Simulator(tgt, dtype=torch.float32)
+    targets, _, _ = tsim.forward(F, tet_mu=tsim.tensor(d["target_mu"]), tet_lambda=tsim.tensor(d["target_lambda"]))
+    tsim.close()
+    sim = Simulator(model, dtype=torch.float32)
+    w = torch.as_tensor(d["vertex_weight"], dtype=torch.float64, device="cuda")
+    estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], d["step"], 1, d["frame_mask"], w)    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, losses = estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], d["step"], args.steps,
+                                      d["frame_mask"], w,
+                                      callback=lambda i, L: log(f"iteration {i}: goal {L:.6e}"))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    proj = 2 * model.projections_per_rollout(F)
+    mu = (a * a).cpu().numpy()
+    out = {"metric": "material estimation: fixed-step gradient descent iterations", "value": 1.0 / dt,
+           "unit": "iterations/s", "ms_per_iteration": dt * 1e3, "projections_per_s": proj / dt,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"tet box {n}^3 cubes, {model.n_tet} tets, {model.n_materials} materials, "
+                                  f"two-material target, {F} frames, S={model.substeps}, K={model.iterations}"},
+           "goal_first": losses[0], "goal_last": losses[-1], "iterations": args.steps,
+           "mu_range": [float(mu.min()), float(mu.max())]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,11 +344,17 @@ def main():
     ap.add_argument("--group-records", type=int, default=0,
                     help="LDS groups: 1 records staged in LDS, 2 records streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
+    ap.add_argument("--lds-groups", default="",
+                    help="tiled cloth: which of the tiling's groups (0 interiors, 1 borders, 2 corners) run as "
+                         "LDS groups, e.g. 012 (default: the workload's)")
     ap.add_argument("--implicit", action="store_true",
                     help="compare the implicit (CG) adjoint with the exact one on the workload")
     ap.add_argument("--cg-iters", type=int, default=2000)
     ap.add_argument("--cg-tol", type=float, default=1e-8)
     ap.add_argument("--pd", action="store_true", help="implicit adjoint: project the blocks to PSD first")
+    ap.add_argument("--estimate", action="store_true",
+                    help="time material-estimation descent iterations instead (--steps iterations)")
+    ap.add_argument("--estimate-n", type=int, default=64, help="cubes per side of the estimation box")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
@@ -334,11 +379,13 @@ def main():
         return
     if args.workload == "c5":
         return serve_bench(args)
+    if args.estimate:
+        return estimate_bench(args)
     if args.implicit:
         return implicit_bench(args)
 
     dev = torch.device("cuda:0")
-    sc, tg = make_workload(args.workload, args.tile, args.frames)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]

@@ -90,6 +90,16 @@ typedef struct {
   int32_t contact;                         /* 1: contact sets may list free vertices */
   double contact_thickness;                /* tau */
   double contact_compliance;               /* alpha of every contact constraint */
+  /* Material clusters (Sec. 5.2: an object made of a few materials, each a
+   * pair of Lame parameters shared by its tets).  0 = every tet has its own
+   * parameters.  With n_materials > 0, tet_material (host [n_tet], copied)
+   * gives each tet's material in [0, n_materials), and the tet parameters of
+   * xpbd_params and their gradients in xpbd_grads are per material
+   * ([n_materials]) instead of per tet; a material's gradient is the sum over
+   * its tets, reduced in a fixed order (bitwise reproducible).  A material
+   * with no tets gets a zero gradient. */
+  int32_t n_materials;
+  const int32_t* tet_material;
 } xpbd_constraint_desc;
 
 /* One Gauss-Seidel iteration visits these sets in order.  Set s has type
@@ -171,7 +181,8 @@ xpbd_status xpbd_destroy(xpbd_ctx ctx);
 typedef struct {
   const void* dist_compliance;   /* device [n_dist] alpha (m/N) */
   const void* bend_compliance;   /* device [n_bend] alpha */
-  const void* tet_E;             /* device [n_tet] Young's modulus (Pa) */
+  const void* tet_E;             /* device [n_tet] Young's modulus (Pa); [n_materials] with
+                                    material clusters (the same for tet_mu, tet_lambda) */
   const void* f_ext;             /* device [F][V][3] per-vertex force, or NULL */
   double sphere[4];              /* cx, cy, cz, R of the contact sphere */
   const void* tet_mu;            /* device [n_tet] first Lame parameter (Pa), or NULL */
@@ -197,7 +208,8 @@ xpbd_status xpbd_forward(xpbd_ctx ctx, const void* x0, const void* v0, const xpb
 typedef struct {
   double* dist_compliance;   /* [n_dist] dL/dalpha */
   double* bend_compliance;   /* [n_bend] dL/dalpha */
-  double* tet_E;             /* [n_tet] dL/dE (nu fixed; Young's moduli given) */
+  double* tet_E;             /* [n_tet] dL/dE (nu fixed; Young's moduli given); [n_materials]
+                                with material clusters (the same for tet_mu, tet_lambda) */
   void* f_ext;               /* [F][V][3] dL/df_ext */
   void* x0;                  /* [V][3] dL/dx0 */
   void* v0;                  /* [V][3] dL/dv0 */
@@ -225,6 +237,15 @@ xpbd_status xpbd_adjoint(xpbd_ctx ctx, const xpbd_params* p, const void* dLdx_fr
 xpbd_status xpbd_goal_l2(xpbd_ctx ctx, const void* x_frames, const void* targets,
                          const uint8_t* frame_mask, int32_t n_frames, double* loss,
                          void* dLdx, void* stream);
+
+/* The same goal with a diagonal weight matrix W (Sec. 4.1), one weight per
+ * vertex: phi = 1/2 sum_f sum_v w_v^2 |x_v(f) - x*_v(f)|^2 on masked frames
+ * and dphi/dx_v(f) = w_v^2 (x_v(f) - x*_v(f)).  vertex_weight is device
+ * FP64 [V]; w_v = 0 leaves vertex v out (e.g. a goal on the boundary
+ * surface only).  NULL weights = xpbd_goal_l2. */
+xpbd_status xpbd_goal_weighted(xpbd_ctx ctx, const void* x_frames, const void* targets,
+                               const uint8_t* frame_mask, const double* vertex_weight, int32_t n_frames,
+                               double* loss, void* dLdx, void* stream);
 
 /* Implicit adjoint of Sec. 4.2 (Eq. adjointXPBD) for the preceding
  * xpbd_forward, the paper's own derivative: each substep's projection is
@@ -274,6 +295,7 @@ typedef struct {
   int32_t n_groups;                    /* LDS groups given */
   int32_t n_groups_lds;                /* of which run as one LDS launch each */
   int32_t max_group_lds_bytes;         /* largest LDS footprint of those launches */
+  int32_t n_materials;                 /* material clusters, 0 = per-tet parameters */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 

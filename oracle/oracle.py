@@ -98,6 +98,8 @@ class OracleScene:
         self.bend_v = np.ascontiguousarray(sc.bend_v, np.int32).reshape(-1)
         self.tet_v = np.ascontiguousarray(sc.tet_v, np.int32).reshape(-1)
         self.tet_nu = np.ascontiguousarray(sc.tet_nu, np.float64)
+        self.n_materials = int(getattr(sc, "n_materials", 0) or 0)
+        self.material = (None if not self.n_materials else np.asarray(sc.tet_material, np.int64))
         st, off, items = sc.schedule_arrays()
         self.set_type, self.set_off, self.set_items = st, off, items
         s = _Scene()
@@ -137,7 +139,10 @@ class OracleScene:
         p = _Params()
         p.dist_alpha = _d(arr(dist_alpha, sc.dist_alpha, sc.n_dist))
         p.bend_alpha = _d(arr(bend_alpha, sc.bend_alpha, sc.n_bend))
-        p.tet_E = _d(arr(tet_E, sc.tet_E, sc.n_tet))
+        # material clusters: tet t takes its material's parameter (a gather)
+        per_tet = (lambda a: a) if not self.n_materials else (lambda a: np.asarray(a, np.float64)[self.material])
+        E = tet_E if tet_E is not None else sc.tet_E
+        p.tet_E = _d(arr(None if E is None else per_tet(E), None, sc.n_tet))
         f = sc.f_ext if f_ext is None else f_ext
         if f is not None:
             f = np.ascontiguousarray(f, np.float64)
@@ -147,9 +152,16 @@ class OracleScene:
         for a in range(4):
             p.sphere[a] = float(sph[a])
         if tet_mu is not None:
-            p.tet_mu = _d(arr(tet_mu, None, sc.n_tet))
-            p.tet_lambda = _d(arr(tet_lambda, None, sc.n_tet))
+            p.tet_mu = _d(arr(per_tet(tet_mu), None, sc.n_tet))
+            p.tet_lambda = _d(arr(per_tet(tet_lambda), None, sc.n_tet))
         return p, keep
+
+    def material_sum(self, g_tet):
+        """Chain rule of the gather above: a material's gradient is the sum of
+        its tets' gradients."""
+        if not self.n_materials:
+            return g_tet
+        return np.bincount(self.material, weights=g_tet, minlength=self.n_materials)
 
 
 def forward(osc: OracleScene, n_frames: int, x0=None, v0=None, **params):
@@ -192,6 +204,8 @@ def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=
                              _d(g["sphere"]), _d(g["tet_mu"]), _d(g["tet_lambda"]))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
+    for k in ("tet_E", "tet_mu", "tet_lambda"):
+        g[k] = osc.material_sum(g[k])
     return g
 
 
@@ -252,11 +266,16 @@ def rest_data(osc: OracleScene):
     return L, th, B.reshape(-1, 3, 3), vol
 
 
-def goal_l2(x_frames, targets, frame_mask):
-    """Goal of Sec. 4.1 with W = I on the masked frames and beta = 0:
-    phi = 1/2 sum_{f in mask} |x(f) - x*(f)|^2 (FP64), and d phi / d x(f)."""
+def goal_l2(x_frames, targets, frame_mask, vertex_weight=None):
+    """Goal of Sec. 4.1 with beta = 0 on the masked frames:
+    phi = 1/2 sum_{f in mask} |W (x(f) - x*(f))|^2 (FP64), and d phi / d x(f)
+    = W^T W (x(f) - x*(f)).  W = I, or diag(vertex_weight) per vertex."""
     x = np.asarray(x_frames, np.float64)
     t = np.asarray(targets, np.float64)
     m = np.asarray(frame_mask, bool)
     d = np.where(m[:, None, None], x - t, 0.0)
-    return 0.5 * float(np.sum(d * d)), d
+    if vertex_weight is None:
+        return 0.5 * float(np.sum(d * d)), d
+    w = np.asarray(vertex_weight, np.float64)[None, :, None]
+    wd = w * d
+    return 0.5 * float(np.sum(wd * wd)), w * wd

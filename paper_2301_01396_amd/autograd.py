@@ -53,15 +53,15 @@ class XPBDRollout(torch.autograd.Function):
 
 class GoalL2(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim: Simulator, x_frames, targets, frame_mask):
-        loss, dL = sim.goal_l2(x_frames.detach().contiguous(), targets.contiguous(), frame_mask)
+    def forward(ctx, sim: Simulator, x_frames, targets, frame_mask, vertex_weight=None):
+        loss, dL = sim.goal_l2(x_frames.detach().contiguous(), targets.contiguous(), frame_mask, vertex_weight)
         ctx.save_for_backward(dL)
         return loss
 
     @staticmethod
     def backward(ctx, gl):
         (dL,) = ctx.saved_tensors
-        return None, dL * gl.to(dL.dtype), None, None
+        return None, dL * gl.to(dL.dtype), None, None, None
 
 
 def rollout(sim: Simulator, n_frames: int, x0, v0, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None,
@@ -73,7 +73,9 @@ def rollout(sim: Simulator, n_frames: int, x0, v0, dist_alpha=None, bend_alpha=N
                              tet_lambda)
 
 
-def goal_l2(sim: Simulator, x_frames, targets, frame_mask=None):
+def goal_l2(sim: Simulator, x_frames, targets, frame_mask=None, vertex_weight=None):
+    """Differentiable FP64 goal; vertex_weight (FP64 [V] on the device) is
+    the diagonal of W, else W = I."""
     if frame_mask is None:
         frame_mask = np.ones(x_frames.shape[0], np.uint8)
-    return GoalL2.apply(sim, x_frames, targets, frame_mask)
+    return GoalL2.apply(sim, x_frames, targets, frame_mask, vertex_weight)

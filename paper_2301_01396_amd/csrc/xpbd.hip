@@ -98,6 +98,12 @@ struct xpbd_ctx_s {
   int4* bend_idx = nullptr; void* bend_theta0 = nullptr; int* bend_perm = nullptr;
   int4* tet_idx = nullptr; void* tet_B = nullptr; int* tet_perm = nullptr; double* tet_nu = nullptr;
   double* tet_vol = nullptr;
+  // tet parameter index per tet (internal order): the caller's tet index, or
+  // its material; material clusters also keep each material's tets
+  // (internal indices, ascending) as mat_items[mat_off[m] .. mat_off[m+1])
+  int* tet_pidx = nullptr;
+  int n_mat = 0;
+  int* mat_off = nullptr; int* mat_items = nullptr;
   int* contact_vid = nullptr;
   int* contact_order = nullptr;   // per contact set: set-local items by ascending vertex
   void* w = nullptr;              // [V] inverse mass (T)
@@ -635,11 +641,11 @@ template <class T> struct Ops {
     if (c->n_tet)
       if (p->tet_mu)
         k_gather_tet_lame<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_mu, (const T*)p->tet_lambda,
-                                                                   c->tet_perm, c->tet_vol, (T*)c->tet_atD,
+                                                                   c->tet_pidx, c->tet_vol, (T*)c->tet_atD,
                                                                    (T*)c->tet_atH, (T*)c->tet_gamma, ih2,
                                                                    c->gamma_one, c->n_tet, c->flag);
       else
-        k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_perm, c->tet_nu,
+        k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_pidx, c->tet_nu,
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
     check_launch();
@@ -761,13 +767,22 @@ template <class T> struct Ops {
     if (out->bend_compliance && c->n_bend)
       k_scatter_alpha_grad<<<nblocks(c->n_bend), kBlock, 0, st>>>(c->bend_acc, c->bend_perm, out->bend_compliance,
                                                                   ih2, c->n_bend);
-    if (out->tet_E && c->n_tet && p->tet_E)
-      k_scatter_E_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_E,
-                                                                out->tet_E, c->n_tet);
-    if ((out->tet_mu || out->tet_lambda) && c->n_tet && p->tet_mu)
-      k_scatter_lame_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_mu,
-                                                                   (const T*)p->tet_lambda, out->tet_mu,
-                                                                   out->tet_lambda, c->gamma_one, c->n_tet);
+    const bool want_E = out->tet_E && p->tet_E, want_lame = (out->tet_mu || out->tet_lambda) && p->tet_mu;
+    if (c->n_mat && (want_E || want_lame)) {
+      k_material_grad<T><<<c->n_mat, kBlock, 0, st>>>(
+          c->tet_acc, c->mat_off, c->mat_items, want_E ? (const T*)p->tet_E : nullptr, (const T*)p->tet_mu,
+          (const T*)p->tet_lambda, want_E ? out->tet_E : nullptr, want_lame ? out->tet_mu : nullptr,
+          want_lame ? out->tet_lambda : nullptr, c->gamma_one, c->n_tet);
+    } else if (c->n_tet) {
+      if (want_E)
+        k_scatter_E_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm, (const T*)p->tet_E,
+                                                                  out->tet_E, c->n_tet);
+      if (want_lame)
+        k_scatter_lame_grad<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(c->tet_acc, c->tet_perm,
+                                                                     (const T*)p->tet_mu, (const T*)p->tet_lambda,
+                                                                     out->tet_mu, out->tet_lambda, c->gamma_one,
+                                                                     c->n_tet);
+    }
     check_launch();
   }
 
@@ -781,14 +796,14 @@ template <class T> struct Ops {
     }
   }
 
-  static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, int F, double* loss,
-                   void* dLdx, hipStream_t st) {
+  static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, const double* wv, int F,
+                   double* loss, void* dLdx, hipStream_t st) {
     const size_t n = (size_t)3 * c->V;
     const size_t nb = nblocks(n);
     ensure_parts(c, F);
     for (int f = 0; f < F; ++f) {
       int on = mask ? (mask[f] != 0) : 1;
-      k_goal<T><<<nb, kBlock, 0, st>>>((const T*)xf + f * n, (const T*)tg + f * n,
+      k_goal<T><<<nb, kBlock, 0, st>>>((const T*)xf + f * n, (const T*)tg + f * n, wv,
                                        dLdx ? (T*)dLdx + f * n : nullptr, n, on, c->parts + f * nb);
     }
     check_launch();
@@ -856,6 +871,12 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   check_idx(cd->tet_v, cd->n_tet, 4, "tet");
   for (int t = 0; t < cd->n_tet; ++t)
     if (!(cd->tet_nu[t] > -1.0 && cd->tet_nu[t] < 0.5)) fail(XPBD_ERR_INVALID, "Poisson ratio of tet %d out of range", t);
+  if (cd->n_materials < 0 || (cd->n_materials > 0 && cd->n_tet > 0 && !cd->tet_material))
+    fail(XPBD_ERR_INVALID, "bad material clusters");
+  c->n_mat = cd->n_materials;
+  for (int t = 0; c->n_mat && t < cd->n_tet; ++t)
+    if (cd->tet_material[t] < 0 || cd->tet_material[t] >= c->n_mat)
+      fail(XPBD_ERR_INVALID, "material of tet %d out of range", t);
 
   // ---- schedule: validate, then lay out internal order set by set
   if (sd->n_sets < 0 || (sd->n_sets > 0 && (!sd->set_type || !sd->set_offsets || !sd->set_items)))
@@ -1039,6 +1060,21 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     c->upload(c->tet_perm, perm_t);
     c->upload(c->tet_nu, tnu);
     c->upload(c->tet_vol, tvol);
+    if (c->n_mat) {
+      std::vector<int> pidx(n), moff(c->n_mat + 1, 0), mitems(n);
+      for (int i = 0; i < n; ++i) ++moff[(pidx[i] = cd->tet_material[perm_t[i]]) + 1];
+      for (int q = 0; q < c->n_mat; ++q) moff[q + 1] += moff[q];
+      std::vector<int> fillp(moff.begin(), moff.end() - 1);
+      for (int i = 0; i < n; ++i) mitems[fillp[pidx[i]]++] = i;
+      c->tet_pidx = (int*)c->alloc(n * sizeof(int));
+      c->mat_off = (int*)c->alloc((c->n_mat + 1) * sizeof(int));
+      c->mat_items = (int*)c->alloc(n * sizeof(int));
+      c->upload(c->tet_pidx, pidx);
+      c->upload(c->mat_off, moff);
+      c->upload(c->mat_items, mitems);
+    } else {
+      c->tet_pidx = c->tet_perm;
+    }
   }
   if (c->n_contact) {
     int n = c->n_contact;
@@ -1487,15 +1523,23 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
   });
 }
 
-xpbd_status xpbd_goal_l2(xpbd_ctx c, const void* x_frames, const void* targets, const uint8_t* frame_mask,
-                         int32_t n_frames, double* loss, void* dLdx, void* stream) {
+xpbd_status xpbd_goal_weighted(xpbd_ctx c, const void* x_frames, const void* targets, const uint8_t* frame_mask,
+                               const double* vertex_weight, int32_t n_frames, double* loss, void* dLdx,
+                               void* stream) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
     if (!x_frames || !targets || n_frames < 1) fail(XPBD_ERR_INVALID, "goal: null argument");
     hipStream_t st = (hipStream_t)stream;
-    if (c->dtype == XPBD_F32) Ops<float>::goal(c, x_frames, targets, frame_mask, n_frames, loss, dLdx, st);
-    else Ops<double>::goal(c, x_frames, targets, frame_mask, n_frames, loss, dLdx, st);
+    if (c->dtype == XPBD_F32)
+      Ops<float>::goal(c, x_frames, targets, frame_mask, vertex_weight, n_frames, loss, dLdx, st);
+    else
+      Ops<double>::goal(c, x_frames, targets, frame_mask, vertex_weight, n_frames, loss, dLdx, st);
   });
+}
+
+xpbd_status xpbd_goal_l2(xpbd_ctx c, const void* x_frames, const void* targets, const uint8_t* frame_mask,
+                         int32_t n_frames, double* loss, void* dLdx, void* stream) {
+  return xpbd_goal_weighted(c, x_frames, targets, frame_mask, nullptr, n_frames, loss, dLdx, stream);
 }
 
 xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
@@ -1517,6 +1561,7 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   for (auto& g : c->groups) nl += g.lds ? 1 : 0;
   info->n_groups_lds = nl;
   info->max_group_lds_bytes = c->max_group_lds;
+  info->n_materials = c->n_mat;
   return XPBD_OK;
 }
 

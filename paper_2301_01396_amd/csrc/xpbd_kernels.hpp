@@ -629,6 +629,53 @@ __global__ __launch_bounds__(kBlock) void k_scatter_lame_grad(const double* __re
   if (out_mu) out_mu[u] = -acc[i] / m + g / l;
   if (out_la) out_la[u] = -acc[n + i] / l - g * m / (l * l);
 }
+// Material clusters: the gradient of material m is the sum of the per-tet
+// terms above over its tets items[off[m] .. off[m+1]) (internal indices in
+// ascending order), one workgroup per material with strided partial sums and
+// a fixed tree, so the sum does not depend on timing.  E != nullptr: Young's
+// moduli (into oE); else Lame parameters (into oMu, oLa, either may be null).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_material_grad(const double* __restrict__ acc, const int* __restrict__ off,
+                                                          const int* __restrict__ items, const T* __restrict__ E,
+                                                          const T* __restrict__ mu, const T* __restrict__ la,
+                                                          double* __restrict__ oE, double* __restrict__ oMu,
+                                                          double* __restrict__ oLa, int gamma_one, int n) {
+  __shared__ double s0[kBlock], s1[kBlock];
+  const int m = blockIdx.x;
+  const int beg = off[m], end = off[m + 1];
+  double a = 0.0, b = 0.0;
+  if (E) {
+    const double e = (double)E[m];
+    for (int q = beg + (int)threadIdx.x; q < end; q += kBlock) {
+      int j = items[q];
+      a += -(acc[j] + acc[n + j]) / e;
+    }
+  } else {
+    const double mm = (double)mu[m], l = (double)la[m];
+    for (int q = beg + (int)threadIdx.x; q < end; q += kBlock) {
+      int j = items[q];
+      double g = gamma_one ? 0.0 : acc[2 * n + j];
+      a += -acc[j] / mm + g / l;
+      b += -acc[n + j] / l - g * mm / (l * l);
+    }
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (E) oE[m] = s0[0];
+    if (oMu) oMu[m] = s0[0];
+    if (oLa) oLa[m] = s1[0];
+  }
+}
+
 // per tet from Lame parameters: atD = 1/(mu V h^2), atH = 1/(lambda V h^2),
 // gamma = 1 + mu/lambda (or 1); flag |= non-positive or non-finite
 template <class T>
@@ -675,18 +722,26 @@ __global__ __launch_bounds__(kBlock) void k_sphere_reduce(const Vec4<T>* __restr
   sphere_reduce_block<T, kBlock>(sacc, order, begin, count, out, sh);
 }
 
-// FP64 goal: per-block partial sums of 1/2 |x - x*|^2 on masked frames, and
-// dL/dx = x - x* (0 on unmasked frames)
+// FP64 goal: per-block partial sums of 1/2 |W (x - x*)|^2 on masked frames,
+// and dL/dx = W^2 (x - x*) (0 on unmasked frames); W = I or diag(w) with
+// one weight per vertex (x is [V][3], element i belongs to vertex i / 3)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_goal(const T* __restrict__ x, const T* __restrict__ tg,
-                                                 T* __restrict__ g, size_t n, int on, double* __restrict__ part) {
+                                                 const double* __restrict__ w, T* __restrict__ g, size_t n, int on,
+                                                 double* __restrict__ part) {
   __shared__ double sh[kBlock];
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
   double s = 0.0;
   if (i < n) {
     double d = on ? (double)x[i] - (double)tg[i] : 0.0;
-    if (g) g[i] = on ? (T)(x[i] - tg[i]) : T(0);
-    s = 0.5 * d * d;
+    if (w) {
+      double ww = w[i / 3] * w[i / 3];
+      if (g) g[i] = on ? (T)(ww * d) : T(0);
+      s = 0.5 * ww * d * d;
+    } else {
+      if (g) g[i] = on ? (T)(x[i] - tg[i]) : T(0);
+      s = 0.5 * d * d;
+    }
   }
   sh[threadIdx.x] = s;
   __syncthreads();

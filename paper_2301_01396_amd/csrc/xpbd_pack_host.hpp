@@ -403,7 +403,7 @@ template <class T> struct PackOps {
           finish_job(pk, J, st);
           continue;
         }
-        if (J.j.loss) Ops<T>::goal(c, J.j.x_frames, J.j.targets, J.mask.data(), F, J.j.loss, nullptr, st);
+        if (J.j.loss) Ops<T>::goal(c, J.j.x_frames, J.j.targets, J.mask.data(), nullptr, F, J.j.loss, nullptr, st);
         Ops<T>::begin_adjoint(c, F, J.j.dLdv_final, &J.j.grads, st);
         J.phase = 1;
         J.f = F - 1;

@@ -25,7 +25,7 @@ PACK_GRAPHS = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
            "xpbd_status_string", "xpbd_pack_create", "xpbd_pack_destroy", "xpbd_pack_add", "xpbd_pack_run",
-           "xpbd_pack_get_stats", "xpbd_pack_last_error", "xpbd_adjoint_implicit")
+           "xpbd_pack_get_stats", "xpbd_pack_last_error", "xpbd_adjoint_implicit", "xpbd_goal_weighted")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -40,7 +40,8 @@ class MeshDesc(C.Structure):
 class ConstraintDesc(C.Structure):
     _fields_ = [("n_dist", C.c_int32), ("dist_v", _ip), ("n_bend", C.c_int32), ("bend_v", _ip),
                 ("n_tet", C.c_int32), ("tet_v", _ip), ("tet_nu", _dp), ("contact", C.c_int32),
-                ("contact_thickness", C.c_double), ("contact_compliance", C.c_double)]
+                ("contact_thickness", C.c_double), ("contact_compliance", C.c_double),
+                ("n_materials", C.c_int32), ("tet_material", _ip)]
 
 
 class ScheduleDesc(C.Structure):
@@ -71,7 +72,8 @@ class Info(C.Structure):
                 ("n_contact", C.c_int32), ("n_sets", C.c_int32), ("projections_per_iteration", C.c_int64),
                 ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
                 ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32),
-                ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32)]
+                ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32),
+                ("n_materials", C.c_int32)]
 
 
 class Job(C.Structure):
@@ -119,6 +121,8 @@ def load() -> C.CDLL:
                                      C.POINTER(Grads), _vp]
         lib.xpbd_goal_l2.restype = C.c_int
         lib.xpbd_goal_l2.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), C.c_int32, _vp, _vp, _vp]
+        lib.xpbd_goal_weighted.restype = C.c_int
+        lib.xpbd_goal_weighted.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, C.c_int32, _vp, _vp, _vp]
         lib.xpbd_get_info.restype = C.c_int
         lib.xpbd_get_info.argtypes = [_vp, C.POINTER(Info)]
         lib.xpbd_profile_enable.restype = C.c_int
@@ -185,11 +189,14 @@ class Simulator:
         bend_v = np.ascontiguousarray(scene.bend_v, np.int32)
         tet_v = np.ascontiguousarray(scene.tet_v, np.int32)
         tet_nu = np.ascontiguousarray(scene.tet_nu, np.float64)
+        n_mat = int(scene.n_materials or 0)
+        tet_mat = (np.ascontiguousarray(scene.tet_material, np.int32) if n_mat else np.zeros(0, np.int32))
         st, off, items = scene.schedule_arrays()
         m = MeshDesc(scene.n_verts, rest.ctypes.data_as(_dp), inv_mass.ctypes.data_as(_dp))
         cd = ConstraintDesc(scene.n_dist, dist_v.ctypes.data_as(_ip), scene.n_bend, bend_v.ctypes.data_as(_ip),
                             scene.n_tet, tet_v.ctypes.data_as(_ip), tet_nu.ctypes.data_as(_dp),
-                            1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance)
+                            1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance,
+                            n_mat, tet_mat.ctypes.data_as(_ip))
         gs, gp = schedule_groups(scene, use_groups)
         sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip),
                           len(gs) // 2, gs.ctypes.data_as(_ip), gp.ctypes.data_as(_ip))
@@ -268,14 +275,14 @@ class Simulator:
         lame = tet_mu is not None or tet_lambda is not None
         te = None
         if sc.n_tet and not lame:
-            te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet,))
+            te = self._arg(sc.tet_E if tet_E is None else tet_E, (sc.n_tet_params,))
         fe = f_ext if f_ext is not None else sc.f_ext
         fe = self._arg(fe, (n_frames, V, 3)) if fe is not None else None
         p = self._params(da, ba, te, fe, sphere)
         tm = tl = None
         if lame:
-            tm = self._arg(tet_mu, (sc.n_tet,))
-            tl = self._arg(tet_lambda, (sc.n_tet,))
+            tm = self._arg(tet_mu, (sc.n_tet_params,))
+            tl = self._arg(tet_lambda, (sc.n_tet_params,))
             p.tet_mu, p.tet_lambda = _ptr(tm), _ptr(tl)
         self._lame = lame
         return x0, v0, da, ba, te, fe, p, (tm, tl)
@@ -297,14 +304,14 @@ class Simulator:
         if "bend_alpha" in want and sc.n_bend:
             g["bend_alpha"] = torch.empty(sc.n_bend, dtype=f64, device=dev)
         if "tet_E" in want and sc.n_tet:
-            g["tet_E"] = torch.empty(sc.n_tet, dtype=f64, device=dev)
+            g["tet_E"] = torch.empty(sc.n_tet_params, dtype=f64, device=dev)
         if "f_ext" in want:
             g["f_ext"] = torch.empty((F, V, 3), dtype=self.dtype, device=dev)
         if "sphere" in want:
             g["sphere"] = torch.empty(4, dtype=f64, device=dev)
         for k in ("tet_mu", "tet_lambda"):
             if k in want and sc.n_tet and lame:
-                g[k] = torch.empty(sc.n_tet, dtype=f64, device=dev)
+                g[k] = torch.empty(sc.n_tet_params, dtype=f64, device=dev)
         if not lame:
             g.pop("tet_mu", None)
             g.pop("tet_lambda", None)
@@ -386,15 +393,24 @@ class Simulator:
         return g, {"total_iterations": cg.total_iterations, "max_iterations_used": cg.max_iterations_used,
                    "worst_rel_residual": cg.worst_rel_residual}
 
-    def goal_l2(self, x_frames: torch.Tensor, targets: torch.Tensor, frame_mask=None):
-        """FP64 goal 1/2 sum_{masked f} |x(f) - x*(f)|^2 and its gradient."""
+    def goal_l2(self, x_frames: torch.Tensor, targets: torch.Tensor, frame_mask=None, vertex_weight=None):
+        """FP64 goal 1/2 sum_{masked f} |W (x(f) - x*(f))|^2 and its gradient;
+        W = I, or diag(vertex_weight) (FP64 [V] on the device)."""
         F = x_frames.shape[0]
         loss = torch.empty((), dtype=torch.float64, device=self.device)
         dL = torch.empty_like(x_frames)
         mask_arr = None if frame_mask is None else np.ascontiguousarray(np.asarray(frame_mask, np.uint8))
         mp = None if mask_arr is None else mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
-        rc = self.lib.xpbd_goal_l2(self._ctx, _ptr(x_frames), _ptr(targets), mp, F, _ptr(loss), _ptr(dL),
-                                   _stream_ptr(self.device))
+        if vertex_weight is not None:
+            vw = vertex_weight
+            if (not isinstance(vw, torch.Tensor) or vw.dtype != torch.float64 or vw.device != self.device
+                    or tuple(vw.shape) != (self.scene.n_verts,) or not vw.is_contiguous()):
+                raise ValueError("vertex_weight must be a contiguous float64 tensor [V] on the device")
+            rc = self.lib.xpbd_goal_weighted(self._ctx, _ptr(x_frames), _ptr(targets), mp, _ptr(vw), F,
+                                             _ptr(loss), _ptr(dL), _stream_ptr(self.device))
+        else:
+            rc = self.lib.xpbd_goal_l2(self._ctx, _ptr(x_frames), _ptr(targets), mp, F, _ptr(loss), _ptr(dL),
+                                       _stream_ptr(self.device))
         self._check(rc)
         return loss, dL
 

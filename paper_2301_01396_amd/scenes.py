@@ -64,7 +64,7 @@ class Scene:
     # parameters (controls)
     dist_alpha: Optional[np.ndarray] = None   # (n_dist,) compliance [m/N]
     bend_alpha: Optional[np.ndarray] = None   # (n_bend,) compliance [1/(N m)]
-    tet_E: Optional[np.ndarray] = None        # (n_tet,) Young's modulus [Pa]
+    tet_E: Optional[np.ndarray] = None        # (n_tet,) Young's modulus [Pa]; (n_materials,) with clusters
     sphere: Tuple[float, float, float, float] = (0.0, -1e3, 0.0, 1.0)
     f_ext: Optional[np.ndarray] = None        # (F, V, 3) per-vertex force [N]
     x0: Optional[np.ndarray] = None           # (V, 3)
@@ -72,6 +72,10 @@ class Scene:
     name: str = ""
     # optional LDS groups: (first set, one past last set, patch id per vertex)
     groups: List[Tuple[int, int, np.ndarray]] = field(default_factory=list)
+    # optional material clusters: tet t uses parameter tet_material[t] of
+    # n_materials (0 = one parameter per tet)
+    n_materials: int = 0
+    tet_material: Optional[np.ndarray] = None   # (n_tet,) int32
 
     @property
     def n_verts(self) -> int:
@@ -88,6 +92,11 @@ class Scene:
     @property
     def n_tet(self) -> int:
         return int(self.tet_v.shape[0])
+
+    @property
+    def n_tet_params(self) -> int:
+        """Length of the tet parameter arrays: materials, else tets."""
+        return self.n_materials if self.n_materials else self.n_tet
 
     def schedule_arrays(self):
         """Flatten the schedule to (set_type int32, set_offsets int64, set_items int32)."""
@@ -648,6 +657,68 @@ def small_cloth(n: int = 6, frames: int = 3, substeps: int = 2, iterations: int 
     sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
     sc.name = f"cloth{n}_small"
     return sc
+
+
+def assign_materials(sc: Scene, n_materials: int, seed: int = 7) -> Scene:
+    """Material clusters drawn uniformly at random over all tets (Sec. 5.2's
+    estimation problem spreads its materials that way).  The scene's tet_E
+    becomes per material: the mean over each material's tets (E of an empty
+    material: the overall mean)."""
+    rng = np.random.default_rng(seed)
+    mat = rng.integers(0, n_materials, sc.n_tet).astype(np.int32)
+    E = np.asarray(sc.tet_E, np.float64)
+    cnt = np.bincount(mat, minlength=n_materials)
+    tot = np.bincount(mat, weights=E, minlength=n_materials)
+    sc.tet_E = np.where(cnt > 0, tot / np.maximum(cnt, 1), E.mean())
+    sc.n_materials, sc.tet_material = int(n_materials), mat
+    return sc
+
+
+def lame_from_E(E, nu):
+    """(mu, lambda) of Young's modulus E and Poisson ratio nu."""
+    E, nu = np.asarray(E, np.float64), np.asarray(nu, np.float64)
+    return E / (2 * (1 + nu)), E * nu / ((1 + nu) * (1 - 2 * nu))
+
+
+def material_estimation(n: int = 8, n_materials: int = 100, frames: int = 20, substeps: int = 2,
+                        iterations: int = 20, size: float = 1.0, E_stiff: float = 5e4, E_soft: float = 5e3,
+                        nu: float = 0.3, guess_scale: float = 0.1, seed: int = 7):
+    """Inhomogeneous volumetric material estimation (Sec. 5.2): an n^3-cube tet
+    box clamped on its x = 0 face sags under gravity.  The target is made of
+    two materials (stiff for tet centroids with x < size/2, soft beyond); the
+    model has ``n_materials`` materials spread at random over the tets, all
+    starting at guess_scale times the stiff target's Lame parameters.  The
+    goal compares the boundary-surface vertices at the last frame.
+
+    Returns (model scene, target scene, dict with the target's per-material
+    (mu, lambda) of the target scene, the model's initial (mu, lambda), the
+    boundary weights [V], the frame mask [F] and a gradient-descent step on
+    (a, b) that decreases the goal steadily from this guess)."""
+    def box():
+        sc = tet_box(n, size=size, pin_bottom=False)
+        sc.inv_mass[sc.rest[:, 0] == 0.0] = 0.0
+        sc.tet_nu = np.full(sc.n_tet, nu)
+        sc.dist_alpha, sc.bend_alpha = np.zeros(0), np.zeros(0)
+        sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
+        return sc
+    tgt = box()
+    cx = tgt.rest[tgt.tet_v].mean(axis=1)[:, 0]
+    tgt.n_materials, tgt.tet_material = 2, (cx >= 0.5 * size).astype(np.int32)
+    mu_t, la_t = lame_from_E(np.array([E_stiff, E_soft]), nu)
+    tgt.tet_E = np.array([E_stiff, E_soft])
+    tgt.name = f"tetbox{n}_two_materials"
+    model = box()
+    model.tet_E = np.full(model.n_tet, guess_scale * E_stiff)
+    assign_materials(model, n_materials, seed)
+    model.name = f"tetbox{n}_{n_materials}_materials"
+    mu0, la0 = lame_from_E(np.full(n_materials, guess_scale * E_stiff), nu)
+    r = model.rest
+    edge = np.isclose(r, 0.0) | np.isclose(r, size)
+    weight = edge.any(axis=1).astype(np.float64)
+    mask = np.zeros(frames, bool)
+    mask[-1] = True
+    return model, tgt, {"target_mu": mu_t, "target_lambda": la_t, "mu0": mu0, "lambda0": la0,
+                        "vertex_weight": weight, "frame_mask": mask, "step": 3000.0}
 
 
 def small_tets(n: int = 2, frames: int = 3, substeps: int = 2, iterations: int = 5,

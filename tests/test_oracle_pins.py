@@ -456,6 +456,76 @@ def test_p7_lame_parameter_gradients_match_finite_differences():
     assert not np.allclose(g1["tet_mu"], g["tet_mu"])
 
 
+def test_p7_material_cluster_gradients_match_finite_differences():
+    """Material clusters (Sec. 5.2): tets share their material's Lame
+    parameters; the per-material gradient against central differences of the
+    rollout in the per-material parameters, one material per tet reproduces
+    the per-tet results, and one material for all tets gives the sum."""
+    base_sc = scenes.small_tets(n=2, frames=3)
+    F = 3
+    rng = np.random.default_rng(12)
+    mu_t, la_t = scenes.lame_from_E(base_sc.tet_E, base_sc.tet_nu)
+    xf0, _, _ = O.forward(O.OracleScene(base_sc), F, tet_mu=mu_t, tet_lambda=la_t)
+    tgt = xf0 + 0.001 * rng.standard_normal(xf0.shape)
+    mask = np.array([0, 1, 1], bool)
+    # three materials at random
+    sc = scenes.small_tets(n=2, frames=3)
+    scenes.assign_materials(sc, 3, seed=4)
+    assert sc.tet_E.shape == (3,)
+    osc = O.OracleScene(sc)
+    mu = np.array([0.7, 1.0, 1.4]) * mu_t.mean()
+    la = np.array([1.2, 0.9, 1.0]) * la_t.mean()
+    xf, _, _ = O.forward(osc, F, tet_mu=mu, tet_lambda=la)
+    # the same rollout as per-tet parameters gathered by hand
+    xg, _, _ = O.forward(O.OracleScene(base_sc), F, tet_mu=mu[sc.tet_material], tet_lambda=la[sc.tet_material])
+    assert np.array_equal(xf, xg)
+    _, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, F, dL, tet_mu=mu, tet_lambda=la)
+    assert g["tet_mu"].shape == (3,)
+
+    def loss(tet_mu, tet_lambda):
+        x, _, _ = O.forward(osc, F, tet_mu=tet_mu, tet_lambda=tet_lambda)
+        return O.goal_l2(x, tgt, mask)[0]
+
+    dirs = {"tet_mu": rng.standard_normal(3) * mu, "tet_lambda": rng.standard_normal(3) * la}
+    _fd_check(osc, F, dirs, dict(tet_mu=mu, tet_lambda=la), loss, g, 1e-4, 1e-6)
+    # one material per tet: the per-tet gradients, in the clusters' order
+    one = scenes.small_tets(n=2, frames=3)
+    one.n_materials, one.tet_material = one.n_tet, np.arange(one.n_tet, dtype=np.int32)[::-1].copy()
+    _, dL0 = O.goal_l2(xf0, tgt, mask)
+    g_tet = O.adjoint(O.OracleScene(base_sc), F, dL0, tet_mu=mu_t, tet_lambda=la_t)
+    g_one = O.adjoint(O.OracleScene(one), F, dL0, tet_mu=mu_t[::-1].copy(), tet_lambda=la_t[::-1].copy())
+    assert np.array_equal(g_one["tet_mu"][::-1], g_tet["tet_mu"])
+    # Young's moduli per material: at fixed nu, dL/dE_m = sum over m's tets
+    gE = O.adjoint(osc, F, dL)["tet_E"]
+    gE_tet = O.adjoint(O.OracleScene(base_sc), F, dL, tet_E=sc.tet_E[sc.tet_material])["tet_E"]
+    assert np.allclose(gE, np.bincount(sc.tet_material, weights=gE_tet, minlength=3), rtol=1e-12, atol=0)
+
+
+def test_p7_weighted_goal():
+    """Goal of Sec. 4.1 with a diagonal per-vertex W: 0/1 weights are the goal
+    over the weighted vertices alone; weight sqrt(2) doubles a vertex's term;
+    the gradient matches central differences."""
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, 7, 3))
+    t = rng.standard_normal((3, 7, 3))
+    mask = np.array([1, 0, 1], bool)
+    w01 = np.array([1, 0, 1, 1, 0, 0, 1], np.float64)
+    L, d = O.goal_l2(x, t, mask, w01)
+    sel = w01 > 0
+    Ls, ds = O.goal_l2(x[:, sel], t[:, sel], mask)
+    assert np.isclose(L, Ls, rtol=1e-15) and np.array_equal(d[:, sel], ds) and not d[:, ~sel].any()
+    L1, _ = O.goal_l2(x, t, mask)
+    L2, _ = O.goal_l2(x, t, mask, np.full(7, np.sqrt(2.0)))
+    assert np.isclose(L2, 2 * L1, rtol=1e-14)
+    w = rng.uniform(0.5, 2.0, 7)
+    L, d = O.goal_l2(x, t, mask, w)
+    dirn = rng.standard_normal(x.shape)
+    eps = 1e-6
+    fd = (O.goal_l2(x + eps * dirn, t, mask, w)[0] - O.goal_l2(x - eps * dirn, t, mask, w)[0]) / (2 * eps)
+    assert np.isclose(fd, np.sum(d * dirn), rtol=1e-8)
+
+
 # ------------------------------------------------------------------ P8
 
 def test_p8_exact_adjoint_tends_to_implicit_adjoint_on_a_chain():
