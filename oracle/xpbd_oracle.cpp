@@ -32,6 +32,13 @@
 //     D projected before H, separate multipliers;
 //   * contact (Sec. 4.5): C = |x - c| - R - tau against a sphere (c, R),
 //     projected only while C < 0;
+//   * orthotropic StVK membrane (Sec. 5.1): per triangle the vector
+//     constraint C = (E_uu, E_vv, 2 E_uv) of the Green strain
+//     E = (F^T F - I)/2, F = Ds Dm^-1 (3x2) with Dm the triangle's edges in
+//     the warp/weft (u, v) material frame, compliance matrix
+//     alpha = (A K)^-1, K = [[C00, C01, 0], [C01, C11, 0], [0, 0, C22]], A the
+//     material-space area; projected as one vector XPBD step (a 3x3 solve
+//     for the three multipliers);
 //   * substeps: each substep is one step of Eq. xpbdUpdateRule with
 //     dt = frame dt / S; multipliers reset every substep; external force
 //     f_ext[f] is constant over the substeps of frame f;  gravity enters as
@@ -177,6 +184,19 @@ template <class S> S c_contact(const V3<S>& x, const V3<S>& c, const S& R, doubl
   return sqrt(d2) - R - tau;
 }
 
+// Green strain of a membrane triangle in Voigt form, component comp:
+// 0 -> E_uu, 1 -> E_vv, 2 -> 2 E_uv, with E = (F^T F - I)/2 and
+// F = [x1-x0, x2-x0] Bm (3x2), Bm = Dm^-1 row-major 2x2.
+template <class S> S c_membrane(const V3<S>* p, const double* Bm, int comp, bool* ok) {
+  *ok = true;
+  V3<S> d1 = sub(p[1], p[0]), d2 = sub(p[2], p[0]);
+  V3<S> fu = {d1.x * Bm[0] + d2.x * Bm[2], d1.y * Bm[0] + d2.y * Bm[2], d1.z * Bm[0] + d2.z * Bm[2]};
+  V3<S> fv = {d1.x * Bm[1] + d2.x * Bm[3], d1.y * Bm[1] + d2.y * Bm[3], d1.z * Bm[1] + d2.z * Bm[3]};
+  if (comp == 0) return 0.5 * (dot(fu, fu) - 1.0);
+  if (comp == 1) return 0.5 * (dot(fv, fv) - 1.0);
+  return dot(fu, fv);
+}
+
 // ------------------------------------------------------------------ scene ABI
 struct Scene {
   int32_t n_verts;
@@ -191,6 +211,7 @@ struct Scene {
   int32_t tet_gamma_one;
   int32_t emulate_f32;
   int32_t n_threads;
+  int32_t n_tri; const int32_t* tri_v; const double* tri_uv;   // membrane triangles, uv [n_tri][3][2]
 };
 struct Params {
   const double* dist_alpha;
@@ -201,9 +222,10 @@ struct Params {
   // Lame parameters per tet (Sec. 5.2); when given they replace (E, nu)
   const double* tet_mu;
   const double* tet_lambda;
+  const double* tri_coef;   // [n_tri][4] = C00, C01, C11, C22
 };
 
-enum { T_DIST = 0, T_BEND = 1, T_TET = 2, T_CONTACT = 3 };
+enum { T_DIST = 0, T_BEND = 1, T_TET = 2, T_CONTACT = 3, T_TRI = 4 };
 
 // one scalar constraint row ("projection"): a tet item holds two (D then H)
 struct Row {
@@ -223,6 +245,9 @@ struct Model {
   std::vector<double> vol;     // [n_tet]
   std::vector<double> mu, lam; // per tet, from E (filled per call)
   std::vector<double> gamma;
+  std::vector<double> tB;      // [n_tri][4] Dm^-1 of each membrane triangle (row-major 2x2)
+  std::vector<double> tarea;   // [n_tri] material-space area
+  int lam_tri = 0;             // membrane multipliers: 3 per triangle
   int n_lam;
   int lam_dist, lam_bend, lam_tet, lam_contact;  // offsets of each type's multipliers
   std::vector<int> contact_slot;                 // vertex -> contact multiplier slot
@@ -295,10 +320,27 @@ int build_model(const Scene* s, Model* m) {
     for (int k = 0; k < V; ++k)
       if (s->inv_mass[k] > 0.0) m->contact_slot[k] = nc++;
   m->n_lam = m->lam_contact + nc;
+  m->tB.resize(4 * (size_t)s->n_tri);
+  m->tarea.resize(s->n_tri);
+  for (int t = 0; t < s->n_tri; ++t) {
+    for (int k = 0; k < 3; ++k)
+      if (s->tri_v[3 * t + k] < 0 || s->tri_v[3 * t + k] >= V) return 1;
+    const double* uv = s->tri_uv + 6 * (size_t)t;
+    // Dm columns = material-space edges (u1-u0, v1-v0) and (u2-u0, v2-v0)
+    double a = uv[2] - uv[0], b = uv[4] - uv[0], cc = uv[3] - uv[1], d = uv[5] - uv[1];
+    double det = a * d - b * cc;
+    if (!(std::fabs(det) > 0.0)) return 1;
+    double* Bt = &m->tB[4 * (size_t)t];
+    Bt[0] = d / det; Bt[1] = -b / det; Bt[2] = -cc / det; Bt[3] = a / det;
+    m->tarea[t] = 0.5 * std::fabs(det);
+  }
+  m->lam_tri = m->n_lam;
+  m->n_lam += 3 * s->n_tri;
   // schedule check: every set's type valid and items in range
   for (int si = 0; si < s->n_sets; ++si) {
     int ty = s->set_type[si];
-    int lim = ty == T_DIST ? s->n_dist : ty == T_BEND ? s->n_bend : ty == T_TET ? s->n_tet : V;
+    if (ty < T_DIST || ty > T_TRI) return 1;
+    int lim = ty == T_DIST ? s->n_dist : ty == T_BEND ? s->n_bend : ty == T_TET ? s->n_tet : ty == T_TRI ? s->n_tri : V;
     for (int64_t q = s->set_off[si]; q < s->set_off[si + 1]; ++q) {
       int it = s->set_items[q];
       if (it < 0 || it >= lim) return 1;
@@ -331,6 +373,7 @@ Row make_row(const Model& mm, int type, int item, int sub) {
   if (type == T_DIST) { r.nv = 2; r.v[0] = s->dist_v[2 * item]; r.v[1] = s->dist_v[2 * item + 1]; r.lam = m->lam_dist + item; }
   else if (type == T_BEND) { r.nv = 4; for (int k = 0; k < 4; ++k) r.v[k] = s->bend_v[4 * item + k]; r.lam = m->lam_bend + item; }
   else if (type == T_TET) { r.nv = 4; for (int k = 0; k < 4; ++k) r.v[k] = s->tet_v[4 * item + k]; r.lam = m->lam_tet + 2 * item + sub; }
+  else if (type == T_TRI) { r.nv = 3; for (int k = 0; k < 3; ++k) r.v[k] = s->tri_v[3 * item + k]; r.lam = m->lam_tri + 3 * item; }
   else { r.nv = 1; r.v[0] = item; r.lam = m->lam_contact + m->contact_slot[item]; }
   return r;
 }
@@ -357,6 +400,7 @@ template <class S> S eval_row(const Model* m, const Row& r, const V3<S>* p, cons
     const double* B = &m->B[9 * (size_t)r.item];
     return r.sub == 0 ? c_tet_dev(p, B, ok) : c_tet_hyd(p, B, m->gamma[r.item], ok);
   }
+  if (r.type == T_TRI) return c_membrane(p, &m->tB[4 * (size_t)r.item], r.sub, ok);
   return c_contact(p[0], cs, R, s->contact_thickness, ok);
 }
 
@@ -394,7 +438,7 @@ void eval_hvp(const Model* m, const Params* P, const Row& r, const double* x, co
 
 // a tape entry: the positions of the row's vertices and its multiplier
 // before the projection, plus whether it was applied
-struct TapeEntry { double x[12]; double lam; };
+struct TapeEntry { double x[12]; double lam; double lamv[3]; };
 
 struct Ctx {
   Model m;
@@ -402,9 +446,97 @@ struct Ctx {
   double h;
 };
 
+// ---- membrane triangles: one vector projection
+// 3x3 helpers (row-major)
+void solve3(const double A[9], const double b[3], double xo[3]) {
+  // Gaussian elimination with partial pivoting
+  double M[3][4];
+  for (int i = 0; i < 3; ++i) { for (int j = 0; j < 3; ++j) M[i][j] = A[3 * i + j]; M[i][3] = b[i]; }
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int i = col + 1; i < 3; ++i) if (std::fabs(M[i][col]) > std::fabs(M[piv][col])) piv = i;
+    if (piv != col) for (int j = 0; j < 4; ++j) std::swap(M[col][j], M[piv][j]);
+    for (int i = col + 1; i < 3; ++i) {
+      double f = M[i][col] / M[col][col];
+      for (int j = col; j < 4; ++j) M[i][j] -= f * M[col][j];
+    }
+  }
+  for (int i = 2; i >= 0; --i) {
+    double acc = M[i][3];
+    for (int j = i + 1; j < 3; ++j) acc -= M[i][j] * xo[j];
+    xo[i] = acc / M[i][i];
+  }
+}
+void inverse3(const double A[9], double Ai[9]) {
+  for (int j = 0; j < 3; ++j) {
+    double e[3] = {0, 0, 0}, col[3];
+    e[j] = 1.0;
+    solve3(A, e, col);
+    for (int i = 0; i < 3; ++i) Ai[3 * i + j] = col[i];
+  }
+}
+// compliance matrix alpha = (A K)^-1 of triangle t
+void membrane_alpha(const Ctx& c, int t, double al[9]) {
+  const double* q = c.p->tri_coef + 4 * (size_t)t;
+  double A = c.m.tarea[t];
+  double K[9] = {A * q[0], A * q[1], 0.0, A * q[1], A * q[2], 0.0, 0.0, 0.0, A * q[3]};
+  inverse3(K, al);
+  for (int i = 0; i < 9; ++i) al[i] = rnd(c.m.s, al[i]);
+}
+struct MemEval { double C[3]; double G[3][9]; double J[9]; double at[9]; double w[3]; };
+// C, its 3x9 Jacobian, at = alpha / h^2 and J = G W G^T + at at positions xl
+void membrane_eval(const Ctx& c, const Row& r, const double* xl, MemEval& e) {
+  const Scene* s = c.m.s;
+  Row rl = r;
+  for (int k = 0; k < 3; ++k) rl.v[k] = k;
+  for (int comp = 0; comp < 3; ++comp) {
+    rl.sub = comp;
+    Eval ev = eval_grad(&c.m, c.p, rl, xl);
+    e.C[comp] = ev.C;
+    for (int i = 0; i < 9; ++i) e.G[comp][i] = ev.g[i];
+  }
+  double al[9];
+  membrane_alpha(c, r.item, al);
+  for (int i = 0; i < 9; ++i) e.at[i] = al[i] / (c.h * c.h);
+  for (int k = 0; k < 3; ++k) e.w[k] = s->inv_mass[r.v[k]];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double acc = e.at[3 * a + b];
+      for (int i = 0; i < 9; ++i) acc += e.G[a][i] * e.w[i / 3] * e.G[b][i];
+      e.J[3 * a + b] = acc;
+    }
+}
+void project_membrane(const Ctx& c, const Row& r, double* x, double* lam, TapeEntry* tape) {
+  const Scene* s = c.m.s;
+  double xl[9];
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 3; ++a) xl[3 * k + a] = x[3 * r.v[k] + a];
+  if (tape) {
+    for (int i = 0; i < 9; ++i) tape->x[i] = xl[i];
+    for (int a = 0; a < 3; ++a) tape->lamv[a] = lam[r.lam + a];
+  }
+  MemEval e;
+  membrane_eval(c, r, xl, e);
+  double b[3], dl[3];
+  for (int a = 0; a < 3; ++a) {
+    b[a] = -e.C[a];
+    for (int q = 0; q < 3; ++q) b[a] -= e.at[3 * a + q] * lam[r.lam + q];
+  }
+  solve3(e.J, b, dl);
+  for (int a = 0; a < 3; ++a) lam[r.lam + a] = rnd(s, lam[r.lam + a] + dl[a]);
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 3; ++a) {
+      double dx = 0.0;
+      for (int q = 0; q < 3; ++q) dx += e.G[q][3 * k + a] * dl[q];
+      double& xv = x[3 * r.v[k] + a];
+      xv = rnd(s, xv + e.w[k] * dx);
+    }
+}
+
 // project one row in place (x, lam); returns true if applied.
 bool project_row(const Ctx& c, const Row& r, double* x, double* lam, TapeEntry* tape) {
   const Scene* s = c.m.s;
+  if (r.type == T_TRI) { project_membrane(c, r, x, lam, tape); return true; }
   if (tape) {
     for (int k = 0; k < r.nv; ++k)
       for (int a = 0; a < 3; ++a) tape->x[3 * k + a] = x[3 * r.v[k] + a];
@@ -483,9 +615,73 @@ void substep(const Ctx& c, double* x, double* v, double* lam, const double* f,
 // Reverse one projection: given the adjoints of (x after, lam after) update
 // them in place to the adjoints of (x before, lam before); accumulate the
 // compliance and sphere adjoints.  x_before comes from the tape entry.
+// Reverse of one membrane projection.  Forward: b = -C - at lam,
+// J = G W G^T + at, J dl = b, lam' = lam + dl, x'_k = x_k + w_k G_k^T dl.
+// alpha_bar: 3x3 adjoint of the compliance matrix alpha (= at h^2).
+void reverse_membrane(const Ctx& c, const Row& r, const TapeEntry& te, double* xb, double* lamb, double* alpha_bar) {
+  MemEval e;
+  membrane_eval(c, r, te.x, e);
+  const double* lam = te.lamv;
+  double b[3], dl[3];
+  for (int a = 0; a < 3; ++a) {
+    b[a] = -e.C[a];
+    for (int q = 0; q < 3; ++q) b[a] -= e.at[3 * a + q] * lam[q];
+  }
+  solve3(e.J, b, dl);
+  double xbo[9];
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 3; ++a) xbo[3 * k + a] = xb[3 * r.v[k] + a];
+  // through lam' = lam + dl and x' = x + W G^T dl
+  double dlb[3];
+  for (int q = 0; q < 3; ++q) {
+    dlb[q] = lamb[r.lam + q];
+    for (int i = 0; i < 9; ++i) dlb[q] += e.G[q][i] * e.w[i / 3] * xbo[i];
+  }
+  double Gb[3][9];
+  for (int q = 0; q < 3; ++q)
+    for (int i = 0; i < 9; ++i) Gb[q][i] = dl[q] * e.w[i / 3] * xbo[i];
+  // J dl = b:  bbar = J^-T dlbar, Jbar = -bbar dl^T
+  double Jt[9];
+  for (int a = 0; a < 3; ++a) for (int q = 0; q < 3; ++q) Jt[3 * a + q] = e.J[3 * q + a];
+  double bb[3];
+  solve3(Jt, dlb, bb);
+  double Jb[9];
+  for (int a = 0; a < 3; ++a) for (int q = 0; q < 3; ++q) Jb[3 * a + q] = -bb[a] * dl[q];
+  // J = G W G^T + at
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 9; ++i) {
+      double acc = 0.0;
+      for (int q = 0; q < 3; ++q) acc += (Jb[3 * a + q] + Jb[3 * q + a]) * e.G[q][i];
+      Gb[a][i] += acc * e.w[i / 3];
+    }
+  const double h2 = c.h * c.h;
+  for (int a = 0; a < 3; ++a)
+    for (int q = 0; q < 3; ++q) alpha_bar[3 * a + q] += (Jb[3 * a + q] - bb[a] * lam[q]) / h2;
+  // b = -C - at lam
+  double Cb[3];
+  for (int a = 0; a < 3; ++a) Cb[a] = -bb[a];
+  for (int q = 0; q < 3; ++q) {
+    double acc = lamb[r.lam + q];
+    for (int a = 0; a < 3; ++a) acc -= e.at[3 * a + q] * bb[a];
+    lamb[r.lam + q] = acc;
+  }
+  // x before: pass-through, plus C and G dependence (Hessian-vector products)
+  Row rl = r;
+  for (int k = 0; k < 3; ++k) rl.v[k] = k;
+  for (int q = 0; q < 3; ++q) {
+    rl.sub = q;
+    double gdir[NG] = {0}, hv[NG];
+    for (int i = 0; i < 9; ++i) gdir[i] = Gb[q][i];
+    eval_hvp(&c.m, c.p, rl, te.x, gdir, hv);
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) xb[3 * r.v[k] + a] += Cb[q] * e.G[q][3 * k + a] + hv[3 * k + a];
+  }
+}
+
 void reverse_row(const Ctx& c, const Row& r, const TapeEntry& te, double* xb, double* lamb,
                  double* alpha_bar_row, double* sphere_bar, double* gamma_bar) {
   const Scene* s = c.m.s;
+  if (r.type == T_TRI) { reverse_membrane(c, r, te, xb, lamb, alpha_bar_row); return; }
   // rebuild a local position array holding only this row's vertices
   double xl[12];
   Row rl = r;
@@ -548,8 +744,9 @@ int orc_rest_data(const orc_scene* s, double* L, double* theta0, double* B, doub
   return 0;
 }
 
-// Single-constraint evaluation for the unit tests: type 0..3, positions
-// p[nv][3], rest data through `aux` (L; theta0; B[9] + gamma; tau),
+// Single-constraint evaluation for the unit tests: type 0..4, positions
+// p[nv][3], rest data through `aux` (L; theta0; B[9] + gamma; tau; for a
+// membrane Dm^-1[4] with sub = Voigt component),
 // sphere[4] for contact.  Outputs C, grad[16] (positions then c, R) and,
 // if gdir != null, hv[16] = Hessian * gdir.  Returns 0 if C is defined.
 int orc_constraint(int type, int sub, const double* p, const double* aux, const double* sphere,
@@ -558,11 +755,12 @@ int orc_constraint(int type, int sub, const double* p, const double* aux, const 
   Model m;
   m.s = &s;
   Row r{}; r.type = type; r.sub = sub; r.item = 0;
-  r.nv = type == T_DIST ? 2 : type == T_CONTACT ? 1 : 4;
+  r.nv = type == T_DIST ? 2 : type == T_CONTACT ? 1 : type == T_TRI ? 3 : 4;
   for (int k = 0; k < r.nv; ++k) r.v[k] = k;
   m.L = {aux[0]};
   m.theta0 = {aux[0]};
   if (type == T_TET) { m.B.assign(aux, aux + 9); m.gamma = {aux[9]}; }
+  if (type == T_TRI) m.tB.assign(aux, aux + 4);
   if (type == T_CONTACT) s.contact_thickness = aux[0];
   Params P{};
   if (sphere) for (int a = 0; a < 4; ++a) P.sphere[a] = sphere[a];
@@ -608,7 +806,8 @@ int orc_forward(const orc_scene* s, const orc_params* p, int F, const double* x0
 int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                 const double* dLdx, const double* dLdv_final,
                 double* g_x0, double* g_v0, double* g_dist_alpha, double* g_bend_alpha,
-                double* g_tet_E, double* g_f, double* g_sphere, double* g_tet_mu, double* g_tet_lambda) {
+                double* g_tet_E, double* g_f, double* g_sphere, double* g_tet_mu, double* g_tet_lambda,
+                double* g_tri_coef) {
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);
@@ -634,6 +833,7 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
   if (dLdv_final) std::copy(dLdv_final, dLdv_final + n3, vb.begin());
   std::vector<double> abar(c.m.n_lam, 0.0);   // per multiplier slot
   std::vector<double> gbar(s->n_tet, 0.0);     // per tet: dL/dgamma
+  std::vector<double> tri_abar(9 * (size_t)s->n_tri, 0.0);   // per triangle: dL/dalpha (3x3)
   double sph[4] = {0, 0, 0, 0};
   if (g_f) std::fill(g_f, g_f + (size_t)F * n3, 0.0);
   const double h = c.h;
@@ -670,7 +870,8 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
             for (int sub = nsub - 1; sub >= 0; --sub) {
               Row r = make_row(c.m, ty, s->set_items[q], sub);
               const TapeEntry& te = tp[it_base + set_base[si] + (size_t)(q - b) * nsub + sub];
-              reverse_row(c, r, te, xb.data(), lamb.data(), &abar[r.lam], &sph_part[(q - b) * 4],
+              reverse_row(c, r, te, xb.data(), lamb.data(),
+                          r.type == T_TRI ? &tri_abar[9 * (size_t)r.item] : &abar[r.lam], &sph_part[(q - b) * 4],
                           r.type == T_TET ? &gbar[r.item] : nullptr);
             }
           }
@@ -716,6 +917,31 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
     double gg = s->tet_gamma_one ? 0.0 : gbar[t];
     if (g_tet_mu) g_tet_mu[t] = -gd * aD / mu + gg / la;
     if (g_tet_lambda) g_tet_lambda[t] = -gh * aH / la - gg * mu / (la * la);
+  }
+  // membrane coefficients: alpha = (A K)^-1, so d alpha = -alpha (A dK) alpha
+  // and dL/dK = -A alpha^T alpha_bar alpha^T; K00 = C00, K01 = K10 = C01,
+  // K11 = C11, K22 = C22
+  for (int t = 0; t < s->n_tri && g_tri_coef; ++t) {
+    double al[9], T1[9], Kb[9];
+    membrane_alpha(c, t, al);
+    const double* ab = &tri_abar[9 * (size_t)t];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += al[3 * k + i] * ab[3 * k + j];   // alpha^T alpha_bar
+        T1[3 * i + j] = acc;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += T1[3 * i + k] * al[3 * j + k];   // ... alpha^T
+        Kb[3 * i + j] = -c.m.tarea[t] * acc;
+      }
+    double* g = g_tri_coef + 4 * (size_t)t;
+    g[0] = Kb[0];
+    g[1] = Kb[1] + Kb[3];
+    g[2] = Kb[4];
+    g[3] = Kb[8];
   }
   return 0;
 }
@@ -785,6 +1011,7 @@ int orc_psd_project(int n, double* a) {
 int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                          const double* dLdx, double* g_x0, double* g_v0, double* g_dist_alpha,
                          double* g_bend_alpha, double* g_f, int pd) {
+  if (s->n_tri > 0) return 2;   // membrane triangles: not part of the converged-limit cross-check
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);

@@ -35,7 +35,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-DIST, BEND, TET, CONTACT = 0, 1, 2, 3
+DIST, BEND, TET, CONTACT, TRI = 0, 1, 2, 3, 4
 TYPE_NAMES = {DIST: "dist", BEND: "bend", TET: "tet", CONTACT: "contact"}
 GRAVITY = (0.0, -9.81, 0.0)
 
@@ -76,6 +76,12 @@ class Scene:
     # n_materials (0 = one parameter per tet)
     n_materials: int = 0
     tet_material: Optional[np.ndarray] = None   # (n_tet,) int32
+    # orthotropic StVK membrane triangles: vertices, warp/weft (u, v)
+    # coordinates of their corners, and per-triangle coefficients
+    # (C00, C01, C11, C22) of the stiffness block A K = alpha^-1
+    tri_v: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    tri_uv: np.ndarray = field(default_factory=lambda: np.zeros((0, 6), np.float64))
+    tri_coef: Optional[np.ndarray] = None   # (n_tri, 4)
 
     @property
     def n_verts(self) -> int:
@@ -94,6 +100,10 @@ class Scene:
         return int(self.tet_v.shape[0])
 
     @property
+    def n_tri(self) -> int:
+        return int(self.tri_v.shape[0])
+
+    @property
     def n_tet_params(self) -> int:
         """Length of the tet parameter arrays: materials, else tets."""
         return self.n_materials if self.n_materials else self.n_tet
@@ -110,7 +120,7 @@ class Scene:
 
     def projections_per_iteration(self) -> int:
         """Constraint evaluations in one Gauss-Seidel sweep (tets count D and H)."""
-        n = self.n_dist + self.n_bend + 2 * self.n_tet
+        n = self.n_dist + self.n_bend + 2 * self.n_tet + self.n_tri
         if self.contact:
             n += int(np.count_nonzero(self.inv_mass > 0))
         return n
@@ -638,6 +648,54 @@ def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: in
     sc.n_frames = n_frames
     sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 2, 20, n_frames
     sc.name = f"cloth{nc}x{nr}_dist_bend_force"
+    return sc
+
+
+def membrane_triangles(nr: int, nc: int, rest: np.ndarray):
+    """Triangles of an nr x nc grid (each quad (i, j) split along
+    (i, j)-(i+1, j+1)), their warp/weft coordinates (u, v) = (x, z) of the
+    flat rest grid, and 8 vertex-disjoint sets: quads of equal (i mod 2,
+    j mod 2) share no vertex, times the two triangles of a quad."""
+    ii, jj = np.meshgrid(np.arange(nr - 1), np.arange(nc - 1), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    v00, v01 = ii * nc + jj, ii * nc + jj + 1
+    v10, v11 = (ii + 1) * nc + jj, (ii + 1) * nc + jj + 1
+    tri = np.concatenate([np.stack([v00, v01, v11], 1), np.stack([v00, v11, v10], 1)]).astype(np.int32)
+    uv = rest[tri][:, :, [0, 2]].reshape(-1, 6)
+    nq = len(ii)
+    cls = (ii % 2) * 2 + (jj % 2)
+    sets = []
+    for slot in range(2):
+        for c in range(4):
+            sets.append((np.nonzero(cls == c)[0] + slot * nq).astype(np.int32))
+    return tri, uv, sets
+
+
+def membrane_cloth(n: int = 6, frames: int = 3, substeps: int = 2, iterations: int = 5, sphere: bool = True,
+                   pinned=None, seed: int = 1, coef=(4.0e3, 6.0e2, 2.0e3, 8.0e2)) -> Scene:
+    """Cloth of orthotropic StVK membrane triangles (Sec. 5.1) with dihedral
+    bending and an optional sphere: per-triangle coefficients (C00, C01,
+    C11, C22) = coef times U[0.7, 1.3] each (seed), warp along x, weft
+    along z.  One iteration runs the 8 membrane sets, the bending sets and
+    the contact set."""
+    pins = (0, n - 1) if pinned is None else pinned
+    sc = cloth_grid(n, n, 1.0 / (n - 1), origin=(-0.5, 0.0, -0.5), pinned=pins, contact=sphere)
+    tri, uv, tsets = membrane_triangles(n, n, sc.rest)
+    # the distance constraints give way to the membrane
+    keep = [(t, it) for t, it in zip(sc.set_type, sc.set_items) if t != DIST]
+    sc.dist_v = np.zeros((0, 2), np.int32)
+    sc.set_type = [TRI] * len(tsets) + [t for t, _ in keep]
+    sc.set_items = list(tsets) + [it for _, it in keep]
+    sc.tri_v, sc.tri_uv = tri, uv
+    rng = np.random.default_rng(seed)
+    sc.tri_coef = np.asarray(coef, np.float64)[None, :] * rng.uniform(0.7, 1.3, (len(tri), 4))
+    sc.dist_alpha = np.zeros(0)
+    sc.bend_alpha = 1e-3 * rng.uniform(0.5, 2.0, sc.n_bend)
+    sc.tet_E = np.zeros(0)
+    sc.sphere = (0.05, -0.28, -0.03, 0.3)
+    sc.contact_thickness, sc.contact_compliance = 0.005, 1e-7
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
+    sc.name = f"cloth{n}_membrane"
     return sc
 
 

@@ -309,6 +309,116 @@ def test_cloth_rest_data():
     assert np.all(np.abs(th) < 1e-14)
 
 
+# ---- membrane (orthotropic StVK, Sec. 5.1): Green strain in Voigt form
+
+TRI_T = 4
+
+
+def _membrane_B(uv):
+    """Dm^-1 (row-major 2x2) of a triangle's warp/weft corners uv[3][2]."""
+    Dm = np.array([[uv[1][0] - uv[0][0], uv[2][0] - uv[0][0]], [uv[1][1] - uv[0][1], uv[2][1] - uv[0][1]]])
+    return np.linalg.inv(Dm).reshape(-1)
+
+
+def test_p4_membrane_green_strain_closed_forms():
+    """Rest, uniaxial stretch, pure shear and a rotated copy: the three Voigt
+    components E_uu, E_vv, 2 E_uv of E = (F^T F - I)/2."""
+    uv = np.array([[0.0, 0.0], [0.3, 0.05], [0.1, 0.4]])
+    B = _membrane_B(uv)
+    rest = np.array([[u, 0.0, v] for u, v in uv])                 # u -> x, v -> z
+    def C(p):
+        return np.array([O.constraint(TRI_T, p, B, sub=c)[0] for c in range(3)])
+    np.testing.assert_allclose(C(rest), 0.0, atol=1e-15)
+    s = 1.3
+    np.testing.assert_allclose(C(rest * np.array([s, 1.0, 1.0])), [0.5 * (s * s - 1), 0.0, 0.0], atol=1e-14)
+    np.testing.assert_allclose(C(rest * np.array([1.0, 1.0, s])), [0.0, 0.5 * (s * s - 1), 0.0], atol=1e-14)
+    k = 0.2                                                        # x += k z: F = [[1, k], [0, 0], [0, 1]]
+    sh = rest + np.outer(rest[:, 2] * k, [1.0, 0.0, 0.0])
+    np.testing.assert_allclose(C(sh), [0.0, 0.5 * k * k, k], atol=1e-14)
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    np.testing.assert_allclose(C(sh @ Q.T + 0.7), C(sh), atol=1e-13)
+
+
+def test_p4_membrane_gradient_and_hvp_against_finite_differences():
+    rng = np.random.default_rng(12)
+    uv = np.array([[0.0, 0.0], [0.25, 0.02], [0.05, 0.3]])
+    B = _membrane_B(uv)
+    for comp in range(3):
+        p = np.array([[u, 0.0, v] for u, v in uv]) + 0.05 * rng.standard_normal((3, 3))
+        gdir = np.zeros(16)
+        gdir[:9] = rng.standard_normal(9)
+        _, grad, hv, ok = O.constraint(TRI_T, p, B, None, gdir, comp)
+        assert ok
+        eps = 1e-6
+        fd = np.zeros(9)
+        fdh = np.zeros(9)
+        for i in range(9):
+            d = np.zeros(9)
+            d[i] = eps
+            cp, gp, _, _ = O.constraint(TRI_T, (p.reshape(-1) + d).reshape(3, 3), B, sub=comp)
+            cm, gm, _, _ = O.constraint(TRI_T, (p.reshape(-1) - d).reshape(3, 3), B, sub=comp)
+            fd[i] = (cp - cm) / (2 * eps)
+            fdh[i] = np.dot(gp[:9] - gm[:9], gdir[:9]) / (2 * eps)
+        np.testing.assert_allclose(grad[:9], fd, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(hv[:9], fdh, rtol=1e-6, atol=1e-8)
+
+
+def _one_triangle_step(scale):
+    """One substep of one membrane triangle (two corners pinned, no gravity,
+    many iterations): the projected positions of the two movable corners,
+    their inertial positions x~ = x + h v, and the implicit Euler energy
+    1/2 |x - x~|_M^2 + 1/2 h^2 C(x)^T (A K) C(x) as a function of them."""
+    sc = scenes.membrane_cloth(n=2, sphere=False, frames=1, substeps=1, iterations=200)
+    sc.bend_v = np.zeros((0, 4), np.int32)
+    sc.bend_alpha = np.zeros(0)
+    sc.set_type, sc.set_items = [scenes.TRI], [np.array([0], np.int32)]
+    sc.tri_v = sc.tri_v[:1].copy()
+    sc.tri_uv = sc.tri_uv[:1].copy()
+    sc.tri_coef = np.array([[4.0e4, 1.2e4, 2.5e4, 9.0e3]])
+    sc.gravity = (0.0, 0.0, 0.0)
+    mov = [int(sc.tri_v[0][1]), int(sc.tri_v[0][2])]
+    sc.inv_mass = np.zeros(4)
+    sc.inv_mass[mov] = [0.5, 2.0]
+    sc.v0 = np.zeros_like(sc.rest)
+    sc.v0[mov] = scale * np.array([[-1.0, 0.5, 0.0], [3.0, 5.0, -2.0]])
+    _, xe, _ = O.forward(O.OracleScene(sc), 1)
+    h = sc.dt
+    xt = sc.rest + h * sc.v0
+    uv = sc.tri_uv[0].reshape(3, 2)
+    B = _membrane_B(uv)
+    A = 0.5 * abs(np.linalg.det(np.array([uv[1] - uv[0], uv[2] - uv[0]])))
+    c00, c01, c11, c22 = sc.tri_coef[0]
+    Kst = A * np.array([[c00, c01, 0], [c01, c11, 0], [0, 0, c22]])   # alpha^-1
+
+    def energy(z):
+        x = xt.copy()
+        x[mov] = z.reshape(2, 3)
+        Cv = np.array([O.constraint(TRI_T, x[sc.tri_v[0]], B, sub=c)[0] for c in range(3)])
+        kin = sum(0.5 / sc.inv_mass[k] * np.sum((x[k] - xt[k]) ** 2) for k in mov)
+        return kin + 0.5 * h * h * Cv @ Kst @ Cv
+    return xe[mov].reshape(-1), xt[mov].reshape(-1), energy
+
+
+def test_p6_membrane_step_agrees_with_the_implicit_euler_minimiser():
+    """Sec. 3.1: XPBD solves the implicit Euler step up to the terms its
+    update drops (the change of grad C within the step), which are second
+    order in the displacement.  One triangle, converged iterations: the
+    result matches the energy minimiser found by a general-purpose optimiser
+    to second order (mismatch / displacement < 1%, and the mismatch falls 9x
+    when the velocities fall 3x); a wrong compliance matrix, Jacobian or
+    solve would leave a first-order mismatch."""
+    from scipy.optimize import minimize
+    mis = {}
+    for scale in (0.3, 0.1):
+        xe, xt, energy = _one_triangle_step(scale)
+        res = minimize(energy, xt, method="BFGS", options={"gtol": 1e-14, "maxiter": 20000})
+        disp = np.abs(xe - xt).max()
+        mis[scale] = np.abs(xe - res.x).max()
+        assert disp > 1e-4 * scale and mis[scale] < 0.01 * disp, (scale, mis[scale], disp)
+    assert 7.0 < mis[0.3] / mis[0.1] < 11.0, mis
+
+
 # ------------------------------------------------------------------ P5, P6
 
 def _free_cloth(n=5, K=4, S=2):
@@ -524,6 +634,42 @@ def test_p7_weighted_goal():
     eps = 1e-6
     fd = (O.goal_l2(x + eps * dirn, t, mask, w)[0] - O.goal_l2(x - eps * dirn, t, mask, w)[0]) / (2 * eps)
     assert np.isclose(fd, np.sum(d * dirn), rtol=1e-8)
+
+
+def test_p7_membrane_cloth_adjoint_matches_finite_differences():
+    """Membrane triangles with bending and sphere contact: dL/d(C00, C01,
+    C11, C22) per triangle, x0, v0, f_ext and the bending compliances against
+    central differences of the rollout."""
+    sc = scenes.membrane_cloth(n=5, frames=3, substeps=2, iterations=4)
+    osc = O.OracleScene(sc)
+    F = 3
+    rng = np.random.default_rng(31)
+    f0 = 0.2 * rng.standard_normal((F, sc.n_verts, 3))
+    xf, _, _ = O.forward(osc, F, f_ext=f0)
+    tgt = xf + 0.01 * rng.standard_normal(xf.shape)
+    mask = np.array([0, 1, 1], bool)
+    _, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, F, dL, f_ext=f0)
+    assert g["tri_coef"].shape == (sc.n_tri, 4) and np.abs(g["tri_coef"]).max() > 0
+    base = dict(tri_coef=sc.tri_coef.reshape(-1).copy(), f_ext=f0, bend_alpha=sc.bend_alpha.copy())
+    gg = dict(g)
+    gg["tri_coef"] = g["tri_coef"].reshape(-1)
+
+    def loss(**kw):
+        x, _, _ = O.forward(osc, F, **kw)
+        return O.goal_l2(x, tgt, mask)[0]
+
+    dirs = {"tri_coef": rng.standard_normal(4 * sc.n_tri) * base["tri_coef"],
+            "f_ext": rng.standard_normal(f0.shape), "bend_alpha": rng.standard_normal(sc.n_bend) * sc.bend_alpha}
+    _fd_check(osc, F, dirs, base, loss, gg, 1e-5, 1e-5)
+
+    def loss_state(x0, v0):
+        x, _, _ = O.forward(osc, F, x0=x0, v0=v0, f_ext=f0)
+        return O.goal_l2(x, tgt, mask)[0]
+    free = sc.inv_mass > 0
+    dx = rng.standard_normal(sc.rest.shape)
+    dv = rng.standard_normal(sc.rest.shape) * free[:, None]
+    _fd_check(osc, F, {"x0": dx, "v0": dv}, dict(x0=sc.x0, v0=sc.v0), loss_state, g, 1e-6, 1e-5)
 
 
 # ------------------------------------------------------------------ P8
