@@ -40,13 +40,15 @@ ALG_BYTES = {             # family: (index bytes, words of the state dtype)
     2: (16, 36), 3: (16, 48),   # bending
     4: (8, 24), 5: (8, 31),     # tet, per projection (one tet item moves twice this)
     6: (4, 10), 7: (4, 22),     # contact
+    12: (16, 35), 13: (16, 55), # membrane: Dm^-1 4, at 4, lambda r/w 6, 3 vertices r/w; reverse adds
+                                # the record 12, lambda_bar r/w 6, compliance adjoint r/w 8
 }
 
 
 # record words written per projection by a forward that keeps the adjoint's
 # record (vertex differences + multiplier): dist 4, bend 10, tet 6 (12 per
 # item), contact 4
-TAPE_WORDS = {0: 4, 2: 10, 4: 6, 6: 4}
+TAPE_WORDS = {0: 4, 2: 10, 4: 6, 6: 4, 12: 12}
 
 
 def alg_bytes(fam: int, tsz: int, recording: float = 0.0) -> float:
@@ -95,10 +97,12 @@ def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
 
 
 FAMILY = {0: "dist_fwd", 1: "dist_rev", 2: "bend_fwd", 3: "bend_rev", 4: "tet_fwd", 5: "tet_rev",
-          6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev", 10: "group_fwd", 11: "group_rev"}
+          6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev", 10: "group_fwd", 11: "group_rev",
+          12: "membrane_fwd", 13: "membrane_rev"}
 KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: "k_tet", 5: "k_tet_rev",
                  6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)",
-                 10: "k_group_fwd", 11: "k_group_rev"}
+                 10: "k_group_fwd", 11: "k_group_rev", 12: "k_tri", 13: "k_tri_rev"}
+N_FAM = len(FAMILY)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -289,6 +293,7 @@ def estimate_bench(args):
     fixed-step gradient descent on (a, b); reports the time per descent
     iteration (rollout + goal + exact adjoint + update) and the goal's fall."""
     import torch
+    from paper_2301_01396_amd import scenes
     from paper_2301_01396_amd.estimate import estimate_materials
     from paper_2301_01396_amd.lib import Simulator
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
@@ -492,7 +497,7 @@ def main():
             return group_bytes(sc, fam == 11, tsz, recording, max(info["n_groups_lds"], 1))
         return alg_bytes(fam, tsz, recording)
 
-    for fam in range(12):
+    for fam in range(N_FAM):
         if launches[fam]:
             avg_ms = ms[fam] / launches[fam]
             per_launch_items = items[fam] / launches[fam]
@@ -502,11 +507,11 @@ def main():
                                     "alg_GBps": round(gbs, 1),
                                     "share_of_sampled_ms": None}
     tot = sum(ms)
-    for fam in range(12):
+    for fam in range(N_FAM):
         if launches[fam]:
             kernels[FAMILY[fam]]["share_of_sampled_ms"] = round(ms[fam] / tot, 3)
     if tot > 0:
-        dom = max(range(12), key=lambda f: ms[f])
+        dom = max(range(N_FAM), key=lambda f: ms[f])
         k = kernels[FAMILY[dom]]
         traffic = traffic_gbs = None
         tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")

@@ -74,7 +74,7 @@ typedef enum {
 } xpbd_status;
 
 typedef enum { XPBD_F32 = 0, XPBD_F64 = 1 } xpbd_dtype;
-typedef enum { XPBD_DIST = 0, XPBD_BEND = 1, XPBD_TET = 2, XPBD_CONTACT = 3 } xpbd_ctype;
+typedef enum { XPBD_DIST = 0, XPBD_BEND = 1, XPBD_TET = 2, XPBD_CONTACT = 3, XPBD_TRI = 4 } xpbd_ctype;
 
 typedef struct {
   int32_t n_verts;
@@ -100,12 +100,26 @@ typedef struct {
    * with no tets gets a zero gradient. */
   int32_t n_materials;
   const int32_t* tet_material;
+  /* Orthotropic StVK membrane triangles (Sec. 5.1): one vector constraint
+   * C = (E_uu, E_vv, 2 E_uv) per triangle, E = (F^T F - I)/2 the Green
+   * strain of F = [x1-x0, x2-x0] Dm^-1, Dm the triangle's edges in the warp
+   * / weft (u, v) material frame given by tri_uv (host [n_tri][3][2], the
+   * corners' (u, v); zero material-space area -> XPBD_ERR_INVALID).  Its
+   * compliance is the 3x3 matrix alpha = (A K)^-1, A = material-space area,
+   * K = [[C00, C01, 0], [C01, C11, 0], [0, 0, C22]] from xpbd_params.tri_coef;
+   * each projection solves the 3x3 system for the three multipliers.
+   * Membrane sets run as one launch per set or in the persistent kernel,
+   * not in LDS groups; the implicit adjoint does not take them. */
+  int32_t n_tri;
+  const int32_t* tri_v;       /* host [n_tri][3] */
+  const double* tri_uv;       /* host [n_tri][6] */
 } xpbd_constraint_desc;
 
 /* One Gauss-Seidel iteration visits these sets in order.  Set s has type
  * set_type[s] and items set_items[set_offsets[s] .. set_offsets[s+1]):
  * constraint indices of that type (for XPBD_TET one item is both the D and
- * the H projection; for XPBD_CONTACT an item is a vertex index).  Within a
+ * the H projection; for XPBD_CONTACT an item is a vertex index; for XPBD_TRI
+ * a membrane triangle).  Within a
  * set no vertex may appear twice (the set is independent), every distance,
  * bending and tet constraint must appear exactly once in the schedule, and a
  * contact vertex at most once and only if its inverse mass is > 0.
@@ -187,6 +201,9 @@ typedef struct {
   double sphere[4];              /* cx, cy, cz, R of the contact sphere */
   const void* tet_mu;            /* device [n_tet] first Lame parameter (Pa), or NULL */
   const void* tet_lambda;        /* device [n_tet] second Lame parameter (Pa), or NULL */
+  const void* tri_coef;          /* device [n_tri][4] membrane (C00, C01, C11, C22) (N/m), K
+                                    positive definite (else XPBD_ERR_NONFINITE); required
+                                    when there are membrane triangles */
 } xpbd_params;
 
 /* Roll out n_frames frames from (x0, v0) (device [V][3]; v0 of pinned
@@ -217,6 +234,7 @@ typedef struct {
   double* tet_mu;            /* [n_tet] dL/dmu (Lame parameters given), through both
                                 compliances and gamma = 1 + mu/lambda */
   double* tet_lambda;        /* [n_tet] dL/dlambda */
+  double* tri_coef;          /* [n_tri][4] dL/d(C00, C01, C11, C22) */
 } xpbd_grads;
 
 /* Exact adjoint of the preceding xpbd_forward on this context for a goal
@@ -296,6 +314,7 @@ typedef struct {
   int32_t n_groups_lds;                /* of which run as one LDS launch each */
   int32_t max_group_lds_bytes;         /* largest LDS footprint of those launches */
   int32_t n_materials;                 /* material clusters, 0 = per-tet parameters */
+  int32_t n_tri;                       /* membrane triangles */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 
@@ -305,11 +324,11 @@ xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
  * off).  xpbd_profile_read synchronises them and returns, per kernel family
  * (index 2 * type: forward projections of that type, 2 * type + 1: their
  * reverse; 8: persistent forward frame, 9: persistent reverse frame,
- * 10: LDS group forward, 11: LDS group reverse), the number of timed
- * launches, their total milliseconds and the projections they processed,
- * then resets the counts. */
+ * 10: LDS group forward, 11: LDS group reverse, 12: membrane forward,
+ * 13: membrane reverse), the number of timed launches, their total
+ * milliseconds and the projections they processed, then resets the counts. */
 xpbd_status xpbd_profile_enable(xpbd_ctx ctx, int32_t on);
-xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[12], double ms[12], int64_t items[12]);
+xpbd_status xpbd_profile_read(xpbd_ctx ctx, int64_t launches[14], double ms[14], int64_t items[14]);
 
 /* ---------------------------------------------------------------- packs
  * A pack runs jobs on many contexts (meshes of any size and constraint mix)

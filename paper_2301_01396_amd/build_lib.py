@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxpbd.so")
 SOURCES = [os.path.join(CSRC, "xpbd.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("xpbd_device.hpp", "xpbd_kernels.hpp")] + [
+HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "xpbd.h")]
 
 # -O3 without fast-math: IEEE division and square root; multiply-adds are

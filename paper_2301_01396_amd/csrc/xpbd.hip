@@ -53,11 +53,17 @@ struct SetInfo {
 };
 
 // bytes of the per-projection record per item, by type (scaled by sizeof T / 4)
+// timed kernel families: 2 type (+1 reverse) for types 0..3, 8/9 persistent
+// frame, 10/11 LDS group, 12/13 membrane sets
+constexpr int kProfFamilies = 14;
+inline int prof_family(int type, bool rev) { return (type == XPBD_TRI ? 12 : 2 * type) + (rev ? 1 : 0); }
+
 inline size_t tape_item_bytes(int type, size_t tsz) {
   switch (type) {
     case XPBD_DIST: return 4 * tsz;
     case XPBD_BEND: return 10 * tsz;
     case XPBD_TET: return 12 * tsz;
+    case XPBD_TRI: return 12 * tsz;
     default: return 4 * tsz;
   }
 }
@@ -73,7 +79,7 @@ struct xpbd_ctx_s {
   std::string err;
   xpbd_dtype dtype;
   size_t tsz;
-  int V = 0, n_dist = 0, n_bend = 0, n_tet = 0, n_contact = 0;
+  int V = 0, n_dist = 0, n_bend = 0, n_tet = 0, n_contact = 0, n_tri = 0;
   double dt, h;
   int S, K;
   double g[3];
@@ -104,6 +110,8 @@ struct xpbd_ctx_s {
   int* tet_pidx = nullptr;
   int n_mat = 0;
   int* mat_off = nullptr; int* mat_items = nullptr;
+  // membrane triangles: corners, Dm^-1 [4][n], material-space area
+  int4* tri_idx = nullptr; void* tri_B = nullptr; int* tri_perm = nullptr; double* tri_area = nullptr;
   int* contact_vid = nullptr;
   int* contact_order = nullptr;   // per contact set: set-local items by ascending vertex
   void* w = nullptr;              // [V] inverse mass (T)
@@ -112,6 +120,7 @@ struct xpbd_ctx_s {
   void* tet_atD = nullptr; void* tet_atH = nullptr; void* tet_gamma = nullptr;
   void* dist_lam = nullptr; void* bend_lam = nullptr; void* tet_lamD = nullptr; void* tet_lamH = nullptr;
   void* contact_lam = nullptr;
+  void* tri_at = nullptr; void* tri_lam = nullptr;   // [4][n], [3][n]
   void* X = nullptr; void* Vv = nullptr; void* Xp = nullptr;
   int* flag = nullptr;
   double* parts = nullptr; size_t parts_n = 0;
@@ -123,6 +132,7 @@ struct xpbd_ctx_s {
   void* bend_lamb = nullptr; void* bend_ab = nullptr; double* bend_acc = nullptr;
   void* tet_lambD = nullptr; void* tet_lambH = nullptr; void* tet_eb = nullptr; double* tet_acc = nullptr;
   void* contact_lamb = nullptr; void* contact_sacc = nullptr;
+  void* tri_lamb = nullptr; void* tri_ab = nullptr; double* tri_acc = nullptr;   // [3][n], [4][n], [4][n]
   void* tape = nullptr; size_t tape_cap = 0;
 
   // LDS groups
@@ -177,9 +187,9 @@ struct xpbd_ctx_s {
   struct Ev { hipEvent_t a, b; int fam; int64_t items; };
   std::vector<Ev> ev_pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-  int64_t prof_launch[12] = {0};
-  double prof_ms[12] = {0};
-  int64_t prof_items[12] = {0};
+  int64_t prof_launch[kProfFamilies] = {0};
+  double prof_ms[kProfFamilies] = {0};
+  int64_t prof_items[kProfFamilies] = {0};
 
   ~xpbd_ctx_s() {
     if (pack_event) {
@@ -327,6 +337,8 @@ template <class T> struct Ops {
     D.c_vid = c->contact_vid; D.c_lam = (T*)c->contact_lam; D.c_lamb = (T*)c->contact_lamb;
     D.c_sacc = (V4*)c->contact_sacc;
     D.c_order = c->contact_order;
+    D.mr = TriRec<T>{c->tri_idx, (const T*)c->tri_B, (const T*)c->tri_at, c->n_tri};
+    D.m_lam = (T*)c->tri_lam; D.m_lamb = (T*)c->tri_lamb; D.m_ab = (T*)c->tri_ab; D.m_acc = c->tri_acc;
     D.sph = Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
     D.h = (T)c->h; D.inv_h = (T)(1.0 / c->h);
     D.gx = (T)c->g[0]; D.gy = (T)c->g[1]; D.gz = (T)c->g[2];
@@ -340,7 +352,8 @@ template <class T> struct Ops {
     unsigned nb = nblocks(si.count, bs);
     xpbd_ctx_s::Ev ev;
     bool on;
-    prof_begin(c, st, 2 * si.type, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
+    prof_begin(c, st, prof_family(si.type, false), si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev,
+               &on);
 #define XPBD_LAUNCH(KERN, TP)                                                                     \
   do {                                                                                            \
     if (first) {                                                                                  \
@@ -355,6 +368,7 @@ template <class T> struct Ops {
       case XPBD_DIST: XPBD_LAUNCH(k_dist, V4); break;
       case XPBD_BEND: XPBD_LAUNCH(k_bend, V4); break;
       case XPBD_TET: XPBD_LAUNCH(k_tet, V4); break;
+      case XPBD_TRI: XPBD_LAUNCH(k_tri, V4); break;
       default: XPBD_LAUNCH(k_contact, V4); break;
     }
     check_launch();
@@ -368,7 +382,8 @@ template <class T> struct Ops {
     unsigned nb = nblocks(si.count, bs);
     xpbd_ctx_s::Ev ev;
     bool on;
-    prof_begin(c, st, 2 * si.type + 1, si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev, &on);
+    prof_begin(c, st, prof_family(si.type, true), si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count, &ev,
+               &on);
     const bool tape_ = last;   // second template flag of the reverse kernels is LAST
     (void)tape_;
 #define XPBD_RLAUNCH(KERN)                                                                        \
@@ -385,6 +400,7 @@ template <class T> struct Ops {
       case XPBD_DIST: XPBD_RLAUNCH(k_dist_rev); break;
       case XPBD_BEND: XPBD_RLAUNCH(k_bend_rev); break;
       case XPBD_TET: XPBD_RLAUNCH(k_tet_rev); break;
+      case XPBD_TRI: XPBD_RLAUNCH(k_tri_rev); break;
       default: XPBD_RLAUNCH(k_contact_rev); break;
     }
 #undef XPBD_LAUNCH
@@ -648,6 +664,9 @@ template <class T> struct Ops {
         k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_pidx, c->tet_nu,
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
+    if (c->n_tri)
+      k_gather_tri<T><<<nblocks(c->n_tri), kBlock, 0, st>>>((const T*)p->tri_coef, c->tri_perm, c->tri_area,
+                                                            (T*)c->tri_at, ih2, c->n_tri, c->flag);
     check_launch();
     group_fill(c, st);
     int flags[2] = {0, 0};
@@ -747,6 +766,7 @@ template <class T> struct Ops {
     fill<double>(c->dist_acc, 0.0, c->n_dist, st);
     fill<double>(c->bend_acc, 0.0, c->n_bend, st);
     fill<double>(c->tet_acc, 0.0, (size_t)3 * c->n_tet, st);
+    fill<double>(c->tri_acc, 0.0, (size_t)4 * c->n_tri, st);
     if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
     if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
     k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
@@ -767,6 +787,9 @@ template <class T> struct Ops {
     if (out->bend_compliance && c->n_bend)
       k_scatter_alpha_grad<<<nblocks(c->n_bend), kBlock, 0, st>>>(c->bend_acc, c->bend_perm, out->bend_compliance,
                                                                   ih2, c->n_bend);
+    if (out->tri_coef && c->n_tri)
+      k_scatter_tri_grad<T><<<nblocks(c->n_tri), kBlock, 0, st>>>(c->tri_acc, c->tri_perm, (const T*)p->tri_coef,
+                                                                  c->tri_area, out->tri_coef, ih2, c->n_tri);
     const bool want_E = out->tet_E && p->tet_E, want_lame = (out->tet_mu || out->tet_lambda) && p->tet_mu;
     if (c->n_mat && (want_E || want_lame)) {
       k_material_grad<T><<<c->n_mat, kBlock, 0, st>>>(
@@ -871,6 +894,11 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   check_idx(cd->tet_v, cd->n_tet, 4, "tet");
   for (int t = 0; t < cd->n_tet; ++t)
     if (!(cd->tet_nu[t] > -1.0 && cd->tet_nu[t] < 0.5)) fail(XPBD_ERR_INVALID, "Poisson ratio of tet %d out of range", t);
+  if (cd->n_tri < 0 || (cd->n_tri > 0 && (!cd->tri_v || !cd->tri_uv))) fail(XPBD_ERR_INVALID, "bad membrane arrays");
+  c->n_tri = cd->n_tri;
+  check_idx(cd->tri_v, cd->n_tri, 3, "membrane");
+  for (int64_t i = 0; i < 6 * (int64_t)cd->n_tri; ++i)
+    if (!std::isfinite(cd->tri_uv[i])) fail(XPBD_ERR_INVALID, "membrane material coordinates not finite");
   if (cd->n_materials < 0 || (cd->n_materials > 0 && cd->n_tet > 0 && !cd->tet_material))
     fail(XPBD_ERR_INVALID, "bad material clusters");
   c->n_mat = cd->n_materials;
@@ -882,8 +910,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   if (sd->n_sets < 0 || (sd->n_sets > 0 && (!sd->set_type || !sd->set_offsets || !sd->set_items)))
     fail(XPBD_ERR_INVALID, "bad schedule");
   std::vector<int> seen_d(c->n_dist, 0), seen_b(c->n_bend, 0), seen_t(c->n_tet, 0), seen_c(V, 0);
+  std::vector<int> seen_m(c->n_tri, 0);
   std::vector<int> stamp(V, -1);
-  std::vector<int> perm_d, perm_b, perm_t, vid_c;
+  std::vector<int> perm_d, perm_b, perm_t, vid_c, perm_m;
   perm_d.reserve(c->n_dist);
   perm_b.reserve(c->n_bend);
   perm_t.reserve(c->n_tet);
@@ -907,7 +936,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     int ty = sd->set_type[s];
     int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
     if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
-    if (ty < 0 || ty > 3) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
+    if (ty < 0 || ty > 4) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
+    if (ty == XPBD_TRI && set_group[s] >= 0)
+      fail(XPBD_ERR_INVALID, "set %d: membrane sets cannot be part of an LDS group", s);
     if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
     // order items inside the set by patch (grouped sets), then by their
     // smallest vertex (locality)
@@ -921,10 +952,12 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
       if (ty == XPBD_DIST) { lim = c->n_dist; nv = 2; }
       else if (ty == XPBD_BEND) { lim = c->n_bend; nv = 4; }
       else if (ty == XPBD_TET) { lim = c->n_tet; nv = 4; }
+      else if (ty == XPBD_TRI) { lim = c->n_tri; nv = 3; }
       if (it < 0 || it >= lim) fail(XPBD_ERR_INVALID, "set %d: item %d out of range", s, it);
       if (ty == XPBD_DIST) vv = cd->dist_v + 2 * (int64_t)it;
       else if (ty == XPBD_BEND) vv = cd->bend_v + 4 * (int64_t)it;
       else if (ty == XPBD_TET) vv = cd->tet_v + 4 * (int64_t)it;
+      else if (ty == XPBD_TRI) vv = cd->tri_v + 3 * (int64_t)it;
       int key = INT32_MAX;
       int64_t patch = 0;
       for (int k = 0; k < nv; ++k) {
@@ -938,7 +971,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
             fail(XPBD_ERR_INVALID, "set %d (group %d): a constraint spans two patches", s, set_group[s]);
         }
       }
-      int* seen = ty == XPBD_DIST ? &seen_d[it] : ty == XPBD_BEND ? &seen_b[it] : ty == XPBD_TET ? &seen_t[it] : &seen_c[it];
+      int* seen = ty == XPBD_DIST ? &seen_d[it] : ty == XPBD_BEND ? &seen_b[it] : ty == XPBD_TET ? &seen_t[it]
+                : ty == XPBD_TRI ? &seen_m[it] : &seen_c[it];
       if (*seen) fail(XPBD_ERR_INVALID, "constraint %d of type %d appears twice in the schedule", it, ty);
       *seen = 1;
       if (ty == XPBD_CONTACT && !(m->inv_mass[it] > 0))
@@ -949,7 +983,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     SetInfo si{};
     si.type = ty;
     si.count = (int)items.size();
-    std::vector<int>& dst = ty == XPBD_DIST ? perm_d : ty == XPBD_BEND ? perm_b : ty == XPBD_TET ? perm_t : vid_c;
+    std::vector<int>& dst = ty == XPBD_DIST ? perm_d : ty == XPBD_BEND ? perm_b : ty == XPBD_TET ? perm_t
+                          : ty == XPBD_TRI ? perm_m : vid_c;
     si.begin = (int)dst.size();
     for (auto& pr : items) dst.push_back(pr.second);
     c->sets.push_back(si);
@@ -957,6 +992,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   for (int i = 0; i < c->n_dist; ++i) if (!seen_d[i]) fail(XPBD_ERR_INVALID, "distance constraint %d not scheduled", i);
   for (int i = 0; i < c->n_bend; ++i) if (!seen_b[i]) fail(XPBD_ERR_INVALID, "bending constraint %d not scheduled", i);
   for (int i = 0; i < c->n_tet; ++i) if (!seen_t[i]) fail(XPBD_ERR_INVALID, "tet %d not scheduled", i);
+  for (int i = 0; i < c->n_tri; ++i) if (!seen_m[i]) fail(XPBD_ERR_INVALID, "membrane triangle %d not scheduled", i);
   c->n_contact = (int)vid_c.size();
   // per-iteration record layout
   size_t off = 0;
@@ -1002,6 +1038,24 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     for (int r = 0; r < 9; ++r) tB[(size_t)r * c->n_tet + i] = B[r];
     tvol[i] = vol;
     tnu[i] = cd->tet_nu[u];
+  }
+
+  // membrane: Dm^-1 from the material-space (u, v) corners, area |det Dm| / 2
+  std::vector<int4> midx(c->n_tri);
+  std::vector<double> mB((size_t)4 * c->n_tri), marea(c->n_tri);
+  for (int i = 0; i < c->n_tri; ++i) {
+    int u = perm_m[i];
+    const int32_t* q = cd->tri_v + 3 * (int64_t)u;
+    const double* uv = cd->tri_uv + 6 * (int64_t)u;
+    double a = uv[2] - uv[0], b = uv[4] - uv[0], cc = uv[3] - uv[1], d = uv[5] - uv[1];
+    double det = a * d - b * cc;
+    if (!(std::fabs(det) > 0)) fail(XPBD_ERR_INVALID, "membrane triangle %d has zero material-space area", u);
+    midx[i] = make_int4(q[0], q[1], q[2], 0);
+    mB[i] = d / det;
+    mB[(size_t)c->n_tri + i] = -b / det;
+    mB[2 * (size_t)c->n_tri + i] = -cc / det;
+    mB[3 * (size_t)c->n_tri + i] = a / det;
+    marea[i] = 0.5 * std::fabs(det);
   }
 
   // ---- device allocations
@@ -1075,6 +1129,19 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     } else {
       c->tet_pidx = c->tet_perm;
     }
+  }
+  if (c->n_tri) {
+    int n = c->n_tri;
+    c->tri_idx = (int4*)c->alloc(n * sizeof(int4));
+    c->tri_B = c->alloc((size_t)4 * n * T_);
+    c->tri_perm = (int*)c->alloc(n * sizeof(int));
+    c->tri_area = (double*)c->alloc(n * sizeof(double));
+    c->tri_at = c->alloc((size_t)4 * n * T_);
+    c->tri_lam = c->alloc((size_t)3 * n * T_);
+    c->upload(c->tri_idx, midx);
+    up_T(c->tri_B, mB);
+    c->upload(c->tri_perm, perm_m);
+    c->upload(c->tri_area, marea);
   }
   if (c->n_contact) {
     int n = c->n_contact;
@@ -1378,6 +1445,11 @@ void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
       c->contact_lamb = c->alloc(c->n_contact * T_);
       c->contact_sacc = c->alloc(c->n_contact * V4b);
     }
+    if (c->n_tri) {
+      c->tri_lamb = c->alloc((size_t)3 * c->n_tri * T_);
+      c->tri_ab = c->alloc((size_t)4 * c->n_tri * T_);
+      c->tri_acc = (double*)c->alloc((size_t)4 * c->n_tri * sizeof(double));
+    }
   }
   size_t need = (size_t)slots * c->K * c->iter_tape_bytes;
   if (need > c->tape_cap) {
@@ -1395,7 +1467,7 @@ bool fits_on_device(xpbd_ctx c, size_t bytes) {
   size_t extra = bytes - have;
   // adjoint working set not yet allocated counts too (rough upper bound)
   size_t work = c->XB ? 0 : (size_t)c->V * 8 * c->tsz + (size_t)(c->n_dist + c->n_bend + 2 * c->n_tet) * 24 +
-                                (size_t)c->n_contact * 6 * c->tsz;
+                                (size_t)c->n_contact * 6 * c->tsz + (size_t)c->n_tri * (7 * c->tsz + 32);
   if (c->budget) return c->dev_bytes + extra + work <= c->budget;
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -1470,6 +1542,7 @@ xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_
     if (c->n_tet && !p->tet_E && !(p->tet_mu && p->tet_lambda))
       fail(XPBD_ERR_INVALID, "forward: tet_E, or tet_mu and tet_lambda, required");
     if (!p->tet_mu != !p->tet_lambda) fail(XPBD_ERR_INVALID, "forward: tet_mu and tet_lambda go together");
+    if (c->n_tri && !p->tri_coef) fail(XPBD_ERR_INVALID, "forward: tri_coef required");
     if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
     c->have_forward = false;
     c->fwd_recorded = false;
@@ -1504,7 +1577,7 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
     const xpbd_params& q = c->fwd_params;
     if (q.dist_compliance != p->dist_compliance || q.bend_compliance != p->bend_compliance ||
         q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0 ||
-        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda)
+        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef)
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
     int mode = c->tape_mode_opt;
     if (c->fwd_recorded) {
@@ -1562,6 +1635,7 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->n_groups_lds = nl;
   info->max_group_lds_bytes = c->max_group_lds;
   info->n_materials = c->n_mat;
+  info->n_tri = c->n_tri;
   return XPBD_OK;
 }
 
@@ -1572,7 +1646,7 @@ xpbd_status xpbd_profile_enable(xpbd_ctx c, int32_t on) {
   return XPBD_OK;
 }
 
-xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[12], double ms[12], int64_t items[12]) {
+xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[14], double ms[14], int64_t items[14]) {
   if (!c) return XPBD_ERR_INVALID;
   return guarded(c, [&] {
     for (auto& e : c->ev_pending) {
@@ -1585,7 +1659,7 @@ xpbd_status xpbd_profile_read(xpbd_ctx c, int64_t launches[12], double ms[12], i
       c->ev_free.push_back({e.a, e.b});
     }
     c->ev_pending.clear();
-    for (int i = 0; i < 12; ++i) {
+    for (int i = 0; i < kProfFamilies; ++i) {
       if (launches) launches[i] = c->prof_launch[i];
       if (ms) ms[i] = c->prof_ms[i];
       if (items) items[i] = c->prof_items[i];

@@ -42,6 +42,16 @@ template <class T> struct TetRec {
 
 template <class T> struct Sphere { T cx, cy, cz, R, tau, at; };
 
+// Membrane triangles (orthotropic StVK, Sec. 5.1): Dm^-1 and the nonzero
+// entries of at = alpha / h^2 (alpha = (A K)^-1 is block diagonal: a 2x2
+// warp/weft block and the shear entry), SoA in internal order.
+template <class T> struct TriRec {
+  const int4* idx;   // v0, v1, v2, unused
+  const T* B;        // [4][n] Dm^-1 row-major (B00, B01, B10, B11)
+  const T* at;       // [4][n] at00, at01, at11, at22
+  int n;
+};
+
 // Every device array and scalar the sweeps use (passed by value).
 template <class T> struct Dev {
   Vec4<T>* X;    // positions + inverse mass
@@ -54,6 +64,7 @@ template <class T> struct Dev {
   const int4* b_idx; const T* b_th0; const T* b_at; T* b_lam; T* b_lamb; T* b_ab; double* b_acc;
   TetRec<T> tr; T* t_lamD; T* t_lamH; T* t_lambD; T* t_lambH; T* t_eb; double* t_acc;
   const int* c_vid; T* c_lam; T* c_lamb; Vec4<T>* c_sacc; const int* c_order;
+  TriRec<T> mr; T* m_lam; T* m_lamb; T* m_ab; double* m_acc;   // lam, lamb [3][n]; ab, acc [4][n]
   Sphere<T> sph;
   T h, inv_h, gx, gy, gz;
 };
@@ -179,6 +190,86 @@ __device__ __forceinline__ T contact_fwd(Vec4<T>& p, const Sphere<T>& S, T lb, V
   T s = p.w * dl;
   p.x += s * ev.n.x; p.y += s * ev.n.y; p.z += s * ev.n.z;
   return lb + dl;
+}
+
+// ---- membrane triangle: one vector projection of C = (E_uu, E_vv, 2 E_uv)
+// With F = [d1 d2] Dm^-1 = [fu fv] the constraint depends on x only through
+// fu = sum_k bu_k x_k and fv = sum_k bv_k x_k (bu, bv: the columns of
+// Dm^-1 spread over the corners, each summing to zero), so
+//   grad_k C_uu = bu_k fu,  grad_k C_vv = bv_k fv,  grad_k C_uv = bu_k fv + bv_k fu,
+// and with S_ab = sum_k w_k a_k b_k the system J = grad C W grad C^T + at is
+//   J00 = Suu P, J11 = Svv Q, J01 = Suv R, J02 = Suu R + Suv P,
+//   J12 = Suv Q + Svv R, J22 = Suu Q + 2 Suv R + Svv P   (+ at),
+// P = |fu|^2, Q = |fv|^2, R = fu . fv.
+template <class T> struct TriStep {
+  V3<T> fu, fv;
+  T bu[3], bv[3];
+  T Suu, Svv, Suv, P, Q, R;
+  T Ji[6];      // J^-1: 00 01 02 11 12 22
+  T dl[3];
+  bool ok;
+};
+template <class T>
+__device__ __forceinline__ void tri_step(V3<T> d1, V3<T> d2, const T w[3], const T B[4], const T at[4],
+                                         const T lam[3], TriStep<T>& s) {
+  s.fu = B[0] * d1 + B[2] * d2;
+  s.fv = B[1] * d1 + B[3] * d2;
+  s.bu[0] = -(B[0] + B[2]); s.bu[1] = B[0]; s.bu[2] = B[2];
+  s.bv[0] = -(B[1] + B[3]); s.bv[1] = B[1]; s.bv[2] = B[3];
+  s.Suu = T(0); s.Svv = T(0); s.Suv = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s.Suu += w[k] * s.bu[k] * s.bu[k];
+    s.Svv += w[k] * s.bv[k] * s.bv[k];
+    s.Suv += w[k] * s.bu[k] * s.bv[k];
+  }
+  s.P = dot(s.fu, s.fu); s.Q = dot(s.fv, s.fv); s.R = dot(s.fu, s.fv);
+  const T J00 = s.Suu * s.P + at[0], J11 = s.Svv * s.Q + at[2];
+  const T J22 = s.Suu * s.Q + T(2) * s.Suv * s.R + s.Svv * s.P + at[3];
+  const T J01 = s.Suv * s.R + at[1], J02 = s.Suu * s.R + s.Suv * s.P, J12 = s.Suv * s.Q + s.Svv * s.R;
+  // symmetric inverse by cofactors
+  const T c00 = J11 * J22 - J12 * J12, c01 = J02 * J12 - J01 * J22, c02 = J01 * J12 - J02 * J11;
+  const T c11 = J00 * J22 - J02 * J02, c12 = J01 * J02 - J00 * J12, c22 = J00 * J11 - J01 * J01;
+  const T det = J00 * c00 + J01 * c01 + J02 * c02;
+  s.ok = det > T(0);
+  const T id = s.ok ? T(1) / det : T(0);
+  s.Ji[0] = c00 * id; s.Ji[1] = c01 * id; s.Ji[2] = c02 * id;
+  s.Ji[3] = c11 * id; s.Ji[4] = c12 * id; s.Ji[5] = c22 * id;
+  // b = -C - at lam  (at has no 02 / 12 entries)
+  const T b0 = -(T(0.5) * (s.P - T(1))) - (at[0] * lam[0] + at[1] * lam[1]);
+  const T b1 = -(T(0.5) * (s.Q - T(1))) - (at[1] * lam[0] + at[2] * lam[1]);
+  const T b2 = -s.R - at[3] * lam[2];
+  s.dl[0] = s.Ji[0] * b0 + s.Ji[1] * b1 + s.Ji[2] * b2;
+  s.dl[1] = s.Ji[1] * b0 + s.Ji[3] * b1 + s.Ji[4] * b2;
+  s.dl[2] = s.Ji[2] * b0 + s.Ji[4] * b1 + s.Ji[5] * b2;
+}
+
+// record of set item t: Vec4 (d1, d2.x) at tape[t], (d2.y, d2.z, lam0, lam1)
+// at tape[count + t], (lam2, 0, 0, 0) at tape[2 count + t]
+template <class T, bool TAPE>
+__device__ __forceinline__ bool tri_fwd(Vec4<T> p[3], const T B[4], const T at[4], T lam[3], Vec4<T>* tape, int t,
+                                        int count) {
+  V3<T> d1 = xyz(p[1]) - xyz(p[0]), d2 = xyz(p[2]) - xyz(p[0]);
+  if (TAPE) {
+    tape[t] = Vec4<T>{d1.x, d1.y, d1.z, d2.x};
+    tape[count + t] = Vec4<T>{d2.y, d2.z, lam[0], lam[1]};
+    tape[2 * count + t] = Vec4<T>{lam[2], T(0), T(0), T(0)};
+  }
+  T w[3] = {p[0].w, p[1].w, p[2].w};
+  TriStep<T> s;
+  tri_step(d1, d2, w, B, at, lam, s);
+  if (!s.ok) return false;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lam[c] = lam[c] + s.dl[c];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T a = w[k] * (s.bu[k] * s.dl[0] + s.bv[k] * s.dl[2]);
+    const T b = w[k] * (s.bv[k] * s.dl[1] + s.bu[k] * s.dl[2]);
+    p[k].x += a * s.fu.x + b * s.fv.x;
+    p[k].y += a * s.fu.y + b * s.fv.y;
+    p[k].z += a * s.fu.z + b * s.fv.z;
+  }
+  return true;
 }
 
 // Adjoint of one projection given the adjoints of its outputs: gradient g_k,
@@ -316,6 +407,69 @@ __device__ __forceinline__ bool contact_rev(Vec4<T>& P, Vec4<T> tp, const Sphere
   return true;
 }
 
+// Reverse of one membrane projection.  From the adjoints xbar_k of the
+// corrected positions and lbar of the multipliers after it:
+//   dlbar = lbar + grad C W xbar,  bbar = J^-1 dlbar,  Cbar = -bbar,
+//   lbar <- lbar - at bbar,  Jbar = -bbar dl^T,  atbar += -bbar (lam + dl)^T,
+// and the adjoints of fu, fv collect the position update's dependence on
+// them, J's (through P, Q, R) and C's, then spread to the corners with bu,
+// bv.  ab accumulates the symmetric part of atbar: (00, 01 + 10, 11, 22).
+template <class T>
+__device__ __forceinline__ bool tri_rev(Vec4<T> P[3], const Vec4<T>* tape, int t, int count, const T B[4],
+                                        const T at[4], T lbar[3], T ab[4]) {
+  Vec4<T> t0 = tape[t], t1 = tape[count + t], t2 = tape[2 * count + t];
+  V3<T> d1 = {t0.x, t0.y, t0.z}, d2 = {t0.w, t1.x, t1.y};
+  T lam[3] = {t1.z, t1.w, t2.x};
+  T w[3] = {P[0].w, P[1].w, P[2].w};
+  TriStep<T> s;
+  tri_step(d1, d2, w, B, at, lam, s);
+  if (!s.ok) return false;
+  V3<T> xb[3] = {xyz(P[0]), xyz(P[1]), xyz(P[2])};
+  T pu[3], pv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { pu[k] = dot(s.fu, xb[k]); pv[k] = dot(s.fv, xb[k]); }
+  T dlb0 = lbar[0], dlb1 = lbar[1], dlb2 = lbar[2];
+  V3<T> fub = {T(0), T(0), T(0)}, fvb = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dlb0 += w[k] * s.bu[k] * pu[k];
+    dlb1 += w[k] * s.bv[k] * pv[k];
+    dlb2 += w[k] * (s.bv[k] * pu[k] + s.bu[k] * pv[k]);
+    const T a = w[k] * (s.bu[k] * s.dl[0] + s.bv[k] * s.dl[2]);
+    const T b = w[k] * (s.bv[k] * s.dl[1] + s.bu[k] * s.dl[2]);
+    fub = fub + a * xb[k];
+    fvb = fvb + b * xb[k];
+  }
+  const T bb0 = s.Ji[0] * dlb0 + s.Ji[1] * dlb1 + s.Ji[2] * dlb2;
+  const T bb1 = s.Ji[1] * dlb0 + s.Ji[3] * dlb1 + s.Ji[4] * dlb2;
+  const T bb2 = s.Ji[2] * dlb0 + s.Ji[4] * dlb1 + s.Ji[5] * dlb2;
+  const T ln0 = lam[0] + s.dl[0], ln1 = lam[1] + s.dl[1], ln2 = lam[2] + s.dl[2];
+  lbar[0] = lbar[0] - (at[0] * bb0 + at[1] * bb1);
+  lbar[1] = lbar[1] - (at[1] * bb0 + at[2] * bb1);
+  lbar[2] = lbar[2] - at[3] * bb2;
+  ab[0] -= bb0 * ln0;
+  ab[1] -= bb0 * ln1 + bb1 * ln0;
+  ab[2] -= bb1 * ln1;
+  ab[3] -= bb2 * ln2;
+  // J's weights: M_cc = Jbar_cc, M_cd = Jbar_cd + Jbar_dc (c < d), Jbar = -bbar dl^T
+  const T M00 = -bb0 * s.dl[0], M11 = -bb1 * s.dl[1], M22 = -bb2 * s.dl[2];
+  const T M01 = -(bb0 * s.dl[1] + bb1 * s.dl[0]), M02 = -(bb0 * s.dl[2] + bb2 * s.dl[0]);
+  const T M12 = -(bb1 * s.dl[2] + bb2 * s.dl[1]);
+  // adjoints of P, Q, R through J, plus C = (P/2 - 1/2, Q/2 - 1/2, R) with Cbar = -bbar
+  const T Pb = M00 * s.Suu + M02 * s.Suv + M22 * s.Svv - T(0.5) * bb0;
+  const T Qb = M11 * s.Svv + M12 * s.Suv + M22 * s.Suu - T(0.5) * bb1;
+  const T Rb = M01 * s.Suv + M02 * s.Suu + M12 * s.Svv + T(2) * M22 * s.Suv - bb2;
+  fub = fub + (T(2) * Pb) * s.fu + Rb * s.fv;
+  fvb = fvb + (T(2) * Qb) * s.fv + Rb * s.fu;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P[k].x += s.bu[k] * fub.x + s.bv[k] * fvb.x;
+    P[k].y += s.bu[k] * fub.y + s.bv[k] * fvb.y;
+    P[k].z += s.bu[k] * fub.z + s.bv[k] * fvb.z;
+  }
+  return true;
+}
+
 // ===================================================================== items on global vertex state
 
 template <class T, bool FIRST, bool TAPE>
@@ -363,6 +517,24 @@ __device__ __forceinline__ void contact_item(const Dev<T>& D, int begin, int cou
   T ln = contact_fwd<T, TAPE>(p, D.sph, lb, tape + t);
   D.c_lam[j] = ln;
   if (ln != lb) D.X[v] = p;
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void tri_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  const TriRec<T>& R = D.mr;
+  const int n = R.n;
+  int4 q = R.idx[j];
+  Vec4<T> p[3] = {D.X[q.x], D.X[q.y], D.X[q.z]};
+  T B[4] = {R.B[j], R.B[n + j], R.B[2 * n + j], R.B[3 * n + j]};
+  T at[4] = {R.at[j], R.at[n + j], R.at[2 * n + j], R.at[3 * n + j]};
+  T lam[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lam[c] = FIRST ? T(0) : D.m_lam[c * n + j];
+  bool moved = tri_fwd<T, TAPE>(p, B, at, lam, tape, t, count);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) D.m_lam[c * n + j] = lam[c];
+  if (moved) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; }
 }
 
 template <class T, bool FIRST, bool LAST>
@@ -414,6 +586,33 @@ __device__ __forceinline__ void tet_rev_item(const Dev<T>& D, int begin, int cou
   } else {
     D.t_lambD[j] = lbD; D.t_lambH[j] = lbH;
     D.t_eb[j] = ebD; D.t_eb[nt + j] = ebH; D.t_eb[2 * nt + j] = gb;
+  }
+}
+
+template <class T, bool FIRST, bool LAST>
+__device__ __forceinline__ void tri_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                             const Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  const TriRec<T>& R = D.mr;
+  const int n = R.n;
+  int4 q = R.idx[j];
+  T B[4] = {R.B[j], R.B[n + j], R.B[2 * n + j], R.B[3 * n + j]};
+  T at[4] = {R.at[j], R.at[n + j], R.at[2 * n + j], R.at[3 * n + j]};
+  T lbar[3], ab[4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lbar[c] = FIRST ? T(0) : D.m_lamb[c * n + j];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ab[c] = FIRST ? T(0) : D.m_ab[c * n + j];
+  Vec4<T> P[3] = {D.XB[q.x], D.XB[q.y], D.XB[q.z]};
+  if (tri_rev(P, tape, t, count, B, at, lbar, ab)) { D.XB[q.x] = P[0]; D.XB[q.y] = P[1]; D.XB[q.z] = P[2]; }
+  if (LAST) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) D.m_acc[c * n + j] += (double)ab[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.m_lamb[c * n + j] = lbar[c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) D.m_ab[c * n + j] = ab[c];
   }
 }
 
@@ -491,10 +690,12 @@ XPBD_SET_KERNEL(k_dist, dist_item, Vec4<T>)
 XPBD_SET_KERNEL(k_bend, bend_item, Vec4<T>)
 XPBD_SET_KERNEL(k_tet, tet_item, Vec4<T>)
 XPBD_SET_KERNEL(k_contact, contact_item, Vec4<T>)
+XPBD_SET_KERNEL(k_tri, tri_item, Vec4<T>)
 XPBD_SET_KERNEL(k_dist_rev, dist_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_bend_rev, bend_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_tet_rev, tet_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_contact_rev, contact_rev_item, const Vec4<T>)
+XPBD_SET_KERNEL(k_tri_rev, tri_rev_item, const Vec4<T>)
 #undef XPBD_SET_KERNEL
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_predict(Dev<T> D, const T* f) {
@@ -629,6 +830,55 @@ __global__ __launch_bounds__(kBlock) void k_scatter_lame_grad(const double* __re
   if (out_mu) out_mu[u] = -acc[i] / m + g / l;
   if (out_la) out_la[u] = -acc[n + i] / l - g * m / (l * l);
 }
+// Membrane compliance per triangle from its coefficients (C00, C01, C11, C22)
+// (caller order, [n][4]): alpha = (A K)^-1 with K = [[C00, C01, 0],
+// [C01, C11, 0], [0, 0, C22]]; at = alpha / h^2 keeps the 2x2 block and the
+// shear entry.  flag |= non-finite or K not positive definite.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather_tri(const T* __restrict__ coef, const int* __restrict__ perm,
+                                                       const double* __restrict__ area, T* __restrict__ at,
+                                                       double inv_h2, int n, int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T* q = coef + 4 * (size_t)perm[i];
+  double c00 = (double)q[0], c01 = (double)q[1], c11 = (double)q[2], c22 = (double)q[3];
+  double det = c00 * c11 - c01 * c01;
+  if (!finite_d(c00) || !finite_d(c01) || !finite_d(c11) || !finite_d(c22) || !(c00 > 0.0) || !(c22 > 0.0) ||
+      !(det > 0.0))
+    *flag = 1;
+  double s = inv_h2 / area[i];
+  at[i] = (T)(s * c11 / det);
+  at[n + i] = (T)(-s * c01 / det);
+  at[2 * n + i] = (T)(s * c00 / det);
+  at[3 * n + i] = (T)(s / c22);
+}
+// dL/dK = -A h^2 at Sym(atbar) at with at = K^-1 / (A h^2), i.e.
+// -K^-1 Sym(atbar) K^-1 / (A h^2); acc = Sym(atbar) entries (00, 01 + 10,
+// 11, 22); C01 enters K twice.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scatter_tri_grad(const double* __restrict__ acc, const int* __restrict__ perm,
+                                                             const T* __restrict__ coef, const double* __restrict__ area,
+                                                             double* __restrict__ out, double inv_h2, int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int u = perm[i];
+  const T* q = coef + 4 * (size_t)u;
+  double c00 = (double)q[0], c01 = (double)q[1], c11 = (double)q[2], c22 = (double)q[3];
+  double det = c00 * c11 - c01 * c01;
+  double i00 = c11 / det, i01 = -c01 / det, i11 = c00 / det, i22 = 1.0 / c22;   // K^-1
+  double s00 = acc[i], s01 = 0.5 * acc[n + i], s11 = acc[2 * n + i], s22 = acc[3 * n + i];
+  // Y = K^-1 S K^-1 on the 2x2 block
+  double a00 = i00 * s00 + i01 * s01, a01 = i00 * s01 + i01 * s11;
+  double a10 = i01 * s00 + i11 * s01, a11 = i01 * s01 + i11 * s11;
+  double y00 = a00 * i00 + a01 * i01, y01 = a00 * i01 + a01 * i11, y11 = a10 * i01 + a11 * i11;
+  double k = -inv_h2 / area[i];
+  double* o = out + 4 * (size_t)u;
+  o[0] = k * y00;
+  o[1] = 2.0 * k * y01;
+  o[2] = k * y11;
+  o[3] = k * i22 * s22 * i22;
+}
+
 // Material clusters: the gradient of material m is the sum of the per-tet
 // terms above over its tets items[off[m] .. off[m+1]) (internal indices in
 // ascending order), one workgroup per material with strided partial sums and
@@ -1058,7 +1308,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const lo
 
 enum PhaseOp : int {
   OP_PREDICT = 0, OP_VELOCITY = 1, OP_REV_VELOCITY = 2, OP_REV_PREDICT = 3, OP_SPHERE = 4,
-  OP_SET = 8,        // + type (0 dist, 1 bend, 2 tet, 3 contact): forward projection of a set
+  OP_SET = 8,        // + type (0 dist, 1 bend, 2 tet, 3 contact, 4 membrane): forward projection of a set
   OP_SET_REV = 16,   // + type: reverse of a set
 };
 enum PhaseFlag : int { PF_FIRST = 1, PF_SECOND = 2 };   // SECOND = record (forward) or LAST (reverse)
@@ -1174,10 +1424,12 @@ __global__ __launch_bounds__(kBlock) void k_program(Dev<T> D, const Phase* __res
       case OP_SET + 1: XPBD_GRID_LOOP(bend_item, Vec4<T>) break;
       case OP_SET + 2: XPBD_GRID_LOOP(tet_item, Vec4<T>) break;
       case OP_SET + 3: XPBD_GRID_LOOP(contact_item, Vec4<T>) break;
+      case OP_SET + 4: XPBD_GRID_LOOP(tri_item, Vec4<T>) break;
       case OP_SET_REV + 0: XPBD_GRID_LOOP(dist_rev_item, const Vec4<T>) break;
       case OP_SET_REV + 1: XPBD_GRID_LOOP(bend_rev_item, const Vec4<T>) break;
       case OP_SET_REV + 2: XPBD_GRID_LOOP(tet_rev_item, const Vec4<T>) break;
       case OP_SET_REV + 3: XPBD_GRID_LOOP(contact_rev_item, const Vec4<T>) break;
+      case OP_SET_REV + 4: XPBD_GRID_LOOP(tri_rev_item, const Vec4<T>) break;
       default: break;
     }
     if (p + 1 == n_phases) break;   // kernel end orders the last phase

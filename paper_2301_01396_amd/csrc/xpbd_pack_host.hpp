@@ -113,6 +113,7 @@ template <class T> struct PackOps {
     if (!j->x0 || !j->v0 || F < 1) fail(XPBD_ERR_INVALID, "pack add: null x0 / v0 or n_frames < 1");
     if (c->n_tet && !j->params.tet_E && !(j->params.tet_mu && j->params.tet_lambda))
       fail(XPBD_ERR_INVALID, "pack add: tet_E, or tet_mu and tet_lambda, required");
+    if (c->n_tri && !j->params.tri_coef) fail(XPBD_ERR_INVALID, "pack add: tri_coef required");
     const bool adj = j->targets != nullptr;
     if (adj && !j->x_frames) fail(XPBD_ERR_INVALID, "pack add: a job with an adjoint needs x_frames");
     c->have_forward = false;
@@ -344,6 +345,7 @@ template <class T> struct PackOps {
             case 1: fwd<1>(L, mem, sg, st); break;
             case 2: fwd<2>(L, mem, sg, st); break;
             case 3: fwd<3>(L, mem, sg, st); break;
+            case 4: fwd<4>(L, mem, sg, st); break;
             default: fwd<-1>(L, mem, sg, st); break;
           }
           break;
@@ -353,6 +355,7 @@ template <class T> struct PackOps {
             case 1: rev<1>(L, mem, sg, st); break;
             case 2: rev<2>(L, mem, sg, st); break;
             case 3: rev<3>(L, mem, sg, st); break;
+            case 4: rev<4>(L, mem, sg, st); break;
             default: rev<-1>(L, mem, sg, st); break;
           }
           break;

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_fwd(const PackMember<T>* __rest
       case 0: dist_item<T, FIRST, true>(M.D, S.begin, S.count, t, tp); break;
       case 1: bend_item<T, FIRST, true>(M.D, S.begin, S.count, t, tp); break;
       case 2: tet_item<T, FIRST, true>(M.D, S.begin, S.count, t, tp); break;
+      case 4: tri_item<T, FIRST, true>(M.D, S.begin, S.count, t, tp); break;
       default: contact_item<T, FIRST, true>(M.D, S.begin, S.count, t, tp); break;
     }
   } else {
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_fwd(const PackMember<T>* __rest
       case 0: dist_item<T, FIRST, false>(M.D, S.begin, S.count, t, nullptr); break;
       case 1: bend_item<T, FIRST, false>(M.D, S.begin, S.count, t, nullptr); break;
       case 2: tet_item<T, FIRST, false>(M.D, S.begin, S.count, t, nullptr); break;
+      case 4: tri_item<T, FIRST, false>(M.D, S.begin, S.count, t, nullptr); break;
       default: contact_item<T, FIRST, false>(M.D, S.begin, S.count, t, nullptr); break;
     }
   }
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_rev(const PackMember<T>* __rest
     case 0: dist_rev_item<T, FIRST, LAST>(M.D, S.begin, S.count, t, tp); break;
     case 1: bend_rev_item<T, FIRST, LAST>(M.D, S.begin, S.count, t, tp); break;
     case 2: tet_rev_item<T, FIRST, LAST>(M.D, S.begin, S.count, t, tp); break;
+    case 4: tri_rev_item<T, FIRST, LAST>(M.D, S.begin, S.count, t, tp); break;
     default: contact_rev_item<T, FIRST, LAST>(M.D, S.begin, S.count, t, tp); break;
   }
 }

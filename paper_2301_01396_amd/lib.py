@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libxpbd.so")
 XPBD_OK, XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP, XPBD_ERR_STATE, XPBD_ERR_NONFINITE, XPBD_ERR_SOLVER = range(7)
 F32, F64 = 0, 1
 FWD_FOR_ADJOINT = 1
-N_FAMILIES = 12   # kernel families reported by xpbd_profile_read
+N_FAMILIES = 14   # kernel families reported by xpbd_profile_read
 PACK_GRAPHS = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
@@ -41,7 +41,8 @@ class ConstraintDesc(C.Structure):
     _fields_ = [("n_dist", C.c_int32), ("dist_v", _ip), ("n_bend", C.c_int32), ("bend_v", _ip),
                 ("n_tet", C.c_int32), ("tet_v", _ip), ("tet_nu", _dp), ("contact", C.c_int32),
                 ("contact_thickness", C.c_double), ("contact_compliance", C.c_double),
-                ("n_materials", C.c_int32), ("tet_material", _ip)]
+                ("n_materials", C.c_int32), ("tet_material", _ip),
+                ("n_tri", C.c_int32), ("tri_v", _ip), ("tri_uv", _dp)]
 
 
 class ScheduleDesc(C.Structure):
@@ -59,12 +60,13 @@ class Options(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
-                ("sphere", C.c_double * 4), ("tet_mu", _vp), ("tet_lambda", _vp)]
+                ("sphere", C.c_double * 4), ("tet_mu", _vp), ("tet_lambda", _vp), ("tri_coef", _vp)]
 
 
 class Grads(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
-                ("x0", _vp), ("v0", _vp), ("sphere", _vp), ("tet_mu", _vp), ("tet_lambda", _vp)]
+                ("x0", _vp), ("v0", _vp), ("sphere", _vp), ("tet_mu", _vp), ("tet_lambda", _vp),
+                ("tri_coef", _vp)]
 
 
 class Info(C.Structure):
@@ -73,7 +75,7 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
                 ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32),
                 ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32),
-                ("n_materials", C.c_int32)]
+                ("n_materials", C.c_int32), ("n_tri", C.c_int32)]
 
 
 class Job(C.Structure):
@@ -191,12 +193,15 @@ class Simulator:
         tet_nu = np.ascontiguousarray(scene.tet_nu, np.float64)
         n_mat = int(scene.n_materials or 0)
         tet_mat = (np.ascontiguousarray(scene.tet_material, np.int32) if n_mat else np.zeros(0, np.int32))
+        tri_v = np.ascontiguousarray(scene.tri_v, np.int32)
+        tri_uv = np.ascontiguousarray(scene.tri_uv, np.float64)
         st, off, items = scene.schedule_arrays()
         m = MeshDesc(scene.n_verts, rest.ctypes.data_as(_dp), inv_mass.ctypes.data_as(_dp))
         cd = ConstraintDesc(scene.n_dist, dist_v.ctypes.data_as(_ip), scene.n_bend, bend_v.ctypes.data_as(_ip),
                             scene.n_tet, tet_v.ctypes.data_as(_ip), tet_nu.ctypes.data_as(_dp),
                             1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance,
-                            n_mat, tet_mat.ctypes.data_as(_ip))
+                            n_mat, tet_mat.ctypes.data_as(_ip), scene.n_tri, tri_v.ctypes.data_as(_ip),
+                            tri_uv.ctypes.data_as(_dp))
         gs, gp = schedule_groups(scene, use_groups)
         sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip),
                           len(gs) // 2, gs.ctypes.data_as(_ip), gp.ctypes.data_as(_ip))
@@ -265,7 +270,7 @@ class Simulator:
 
     # ------------------------------------------------------------------ API
     def _inputs(self, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu=None,
-                tet_lambda=None):
+                tet_lambda=None, tri_coef=None):
         sc = self.scene
         V = sc.n_verts
         x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
@@ -284,14 +289,18 @@ class Simulator:
             tm = self._arg(tet_mu, (sc.n_tet_params,))
             tl = self._arg(tet_lambda, (sc.n_tet_params,))
             p.tet_mu, p.tet_lambda = _ptr(tm), _ptr(tl)
+        tc = None
+        if sc.n_tri:
+            tc = self._arg(sc.tri_coef if tri_coef is None else tri_coef, (sc.n_tri, 4))
+            p.tri_coef = _ptr(tc)
         self._lame = lame
-        return x0, v0, da, ba, te, fe, p, (tm, tl)
+        return x0, v0, da, ba, te, fe, p, (tm, tl, tc)
 
     def _grad_buffers(self, F, want):
         sc = self.scene
         V = sc.n_verts
         lame = getattr(self, "_lame", False)
-        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext", "sphere") +
+        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext", "sphere", "tri_coef") +
                    (("tet_mu", "tet_lambda") if lame else ("tet_E",)))
         dev, f64 = self.device, torch.float64
         g = {}
@@ -317,13 +326,15 @@ class Simulator:
             g.pop("tet_lambda", None)
         else:
             g.pop("tet_E", None)
+        if "tri_coef" in want and sc.n_tri:
+            g["tri_coef"] = torch.empty((sc.n_tri, 4), dtype=f64, device=dev)
         gr = Grads(*(_ptr(g.get(k)) for k in ("dist_alpha", "bend_alpha", "tet_E", "f_ext", "x0", "v0",
-                                              "sphere", "tet_mu", "tet_lambda")))
+                                              "sphere", "tet_mu", "tet_lambda", "tri_coef")))
         return g, gr
 
     def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
                 f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False,
-                tet_mu=None, tet_lambda=None):
+                tet_mu=None, tet_lambda=None, tri_coef=None):
         """Roll out; returns (x_frames or None, x_final, v_final) on the device.
 
         ``for_adjoint``: an adjoint will follow; the library may keep the record
@@ -331,7 +342,7 @@ class Simulator:
         sc = self.scene
         V = sc.n_verts
         x0, v0, da, ba, te, fe, p, lm = self._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere,
-                                                     tet_mu, tet_lambda)
+                                                     tet_mu, tet_lambda, tri_coef)
         xf = None
         if frames:
             xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
@@ -376,6 +387,8 @@ class Simulator:
         p, x0, v0, da, ba, te, fe, F, _lm = self._fwd_keep
         V = self.scene.n_verts
         g, gr = self._grad_buffers(F, want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
+        gr.tri_coef = None
+        g.pop("tri_coef", None)
         gr.tet_E = None
         gr.sphere = None
         g.pop("tet_E", None)

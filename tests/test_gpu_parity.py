@@ -265,10 +265,83 @@ def test_material_clusters_and_weighted_goal(dtype, pos_tol, grad_tol):
             torch.cuda.synchronize()
             runs.append({k: v.cpu().numpy() for k, v in gg.items()})
         assert abs(float(loss) - L) <= (1e-10 if dtype == "f64" else 1e-4) * L
-        assert rel(gdl.double().cpu().numpy(), dL) <= (1e-10 if dtype == "f64" else 1e-5)
+        if dtype == "f64":
+            assert rel(gdl.double().cpu().numpy(), dL) <= 1e-10
+        else:
+            # FP32 positions differ from the reference's by ~1e-7 relative, which
+            # is ~1e-4 of the small x - x*; the goal kernel itself is checked on
+            # the GPU's own positions and FP32 targets
+            _, own = O.goal_l2(gx.double().cpu().numpy(), sim.tensor(tgt).double().cpu().numpy(), mask, w)
+            err = rel(gdl.double().cpu().numpy(), own)
+            assert err <= 1e-6, err
         names = ("tet_mu", "tet_lambda") if "tet_mu" in kw else ("tet_E",)
         for k in names:
             assert runs[0][k].shape == (5,)
             assert runs[0][k][4] == 0.0 and g[k][4] == 0.0
             assert rel(runs[0][k], g[k]) <= grad_tol, (k, rel(runs[0][k], g[k]))
             assert np.array_equal(runs[0][k], runs[1][k])
+
+
+# ---------------------------------------------------------------- membranes
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_membrane_cloth_bending_contact(dtype, pos_tol, grad_tol):
+    """Orthotropic StVK membrane triangles (vector projections), dihedral
+    bending and sphere contact: positions and every gradient, including
+    dL/d(C00, C01, C11, C22) per triangle, against the reference."""
+    sc = scenes.membrane_cloth(n=7, frames=3, substeps=2, iterations=5)
+    rng = np.random.default_rng(17)
+    f = 0.3 * rng.standard_normal((3, sc.n_verts, 3))
+    ref = reference_case(sc, 3, mask=np.array([0, 1, 1], bool), f_ext=f)
+    assert np.abs(ref["grads"]["tri_coef"]).max() > 0 and np.linalg.norm(ref["grads"]["sphere"]) > 0
+    got = gpu_case(_sim(sc, dtype), 3, ref, f_ext=f)
+    assert got["grads"]["tri_coef"].shape == (sc.n_tri, 4)
+    compare(sc, ref, got, pos_tol, grad_tol)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_membrane_launch_structures_agree_bitwise(dtype):
+    """Membrane sets: one launch per set (two workgroup sizes), the persistent
+    frame kernel, and every record mode give the same bits."""
+    sc = scenes.membrane_cloth(n=24, frames=2, substeps=2, iterations=3)
+    ref = reference_case(sc, 2, n_threads=8)
+    outs = []
+    for kw in ({}, {"block_size": 64}, {"launch_mode": 2}, {"launch_mode": 2, "persistent_blocks": 5},
+               {"tape_mode": 1}, {"tape_mode": 2}):
+        outs.append(gpu_case(_sim(sc, dtype, **kw), 2, ref))
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            assert np.array_equal(o["grads"][k], v), k
+    tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
+    compare(sc, ref, outs[0], *tol)
+
+
+def test_membrane_validation():
+    """Invalid membrane input is refused: a triangle with zero material-space
+    area, a membrane set inside an LDS group, a non-positive-definite
+    stiffness block, and the implicit adjoint on a mesh with membranes."""
+    import torch
+    from paper_2301_01396_amd.lib import XPBDError, XPBD_ERR_INVALID, XPBD_ERR_NONFINITE
+    sc = scenes.membrane_cloth(n=4, frames=1)
+    bad = scenes.membrane_cloth(n=4, frames=1)
+    bad.tri_uv = bad.tri_uv.copy()
+    bad.tri_uv[2] = [0.0, 0.0, 1.0, 1.0, 2.0, 2.0]               # collinear corners
+    with pytest.raises(XPBDError) as e:
+        _sim(bad, "f32")
+    assert e.value.status == XPBD_ERR_INVALID
+    grp = scenes.membrane_cloth(n=4, frames=1)
+    grp.groups = [(0, 1, np.zeros(grp.n_verts, np.int32))]
+    with pytest.raises(XPBDError) as e:
+        _sim(grp, "f32")
+    assert e.value.status == XPBD_ERR_INVALID
+    sim = _sim(sc, "f32")
+    coef = sc.tri_coef.copy()
+    coef[1, 1] = 2.0 * np.sqrt(coef[1, 0] * coef[1, 2])          # C01^2 > C00 C11
+    with pytest.raises(XPBDError) as e:
+        sim.forward(1, tri_coef=sim.tensor(coef))
+    assert e.value.status == XPBD_ERR_NONFINITE
+    xf, _, _ = sim.forward(1)
+    with pytest.raises(XPBDError) as e:
+        sim.adjoint_implicit(torch.ones_like(xf))
+    assert e.value.status == XPBD_ERR_INVALID

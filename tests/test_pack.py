@@ -40,7 +40,8 @@ def _scenes(S=2, K=5):
     b = scenes.small_tets(n=2, frames=4, substeps=S, iterations=K)
     c = scenes.small_cloth(n=9, frames=2, substeps=S, iterations=K, sphere=False, seed=3)
     d = scenes.small_cloth(n=5, frames=5, substeps=S, iterations=K, seed=4)
-    return [a, b, c, d]
+    e = scenes.membrane_cloth(n=6, frames=3, substeps=S, iterations=K)
+    return [a, b, c, d, e]
 
 
 def _targets(sc, F, seed):
@@ -80,8 +81,8 @@ def _case(dtype, graphs, tape_mode=0, late=False):
     from tests._cases import needs_gpu
     needs_gpu()
     scs = _scenes()
-    adj = [True, True, False, True]
-    masks = [None, np.array([0, 1, 0, 1], np.uint8), None, np.array([1, 0, 0, 0, 1], np.uint8)]
+    adj = [True, True, False, True, True]
+    masks = [None, np.array([0, 1, 0, 1], np.uint8), None, np.array([1, 0, 0, 0, 1], np.uint8), None]
     ref = []
     for i, sc in enumerate(scs):
         sim = L.Simulator(sc, dtype=dtype, tape_mode=tape_mode)
