@@ -290,7 +290,9 @@ def implicit_bench(args):
 def estimate_bench(args):
     """Material estimation on the tet box of the tet workload's size
     (Sec. 5.2): 100 random material clusters, a two-material target,
-    fixed-step gradient descent on (a, b); reports the time per descent
+    fixed-step gradient descent on (a, b) (the step set from the first
+    gradient so the first update changes a control by at most 5%, then kept);
+    reports the time per descent
     iteration (rollout + goal + exact adjoint + update) and the goal's fall."""
     import torch
     from paper_2301_01396_amd import scenes
@@ -305,12 +307,12 @@ def estimate_bench(args):
     tsim.close()
     sim = Simulator(model, dtype=torch.float32)
     w = torch.as_tensor(d["vertex_weight"], dtype=torch.float64, device="cuda")
-    estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], d["step"], 1, d["frame_mask"], w)    # warm-up
+    estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], None, 1, d["frame_mask"], w)    # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    a, b, losses = estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], d["step"], args.steps,
-                                      d["frame_mask"], w,
-                                      callback=lambda i, L: log(f"iteration {i}: goal {L:.6e}"))
+    a, b, losses, step = estimate_materials(sim, F, targets, d["mu0"], d["lambda0"], None, args.steps,
+                                            d["frame_mask"], w,
+                                            callback=lambda i, L: log(f"iteration {i}: goal {L:.6e}"))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     proj = 2 * model.projections_per_rollout(F)
@@ -320,7 +322,7 @@ def estimate_bench(args):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"tet box {n}^3 cubes, {model.n_tet} tets, {model.n_materials} materials, "
                                   f"two-material target, {F} frames, S={model.substeps}, K={model.iterations}"},
-           "goal_first": losses[0], "goal_last": losses[-1], "iterations": args.steps,
+           "goal_first": losses[0], "goal_last": losses[-1], "iterations": args.steps, "step": step,
            "mu_range": [float(mu.min()), float(mu.max())]}
     print(json.dumps(out), flush=True)
 

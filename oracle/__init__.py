@@ -24,6 +24,6 @@ Pins (tests/test_oracle_*.py):
     as the iteration count grows.
 """
 from .oracle import (  # noqa: F401
-    OracleScene, build_library, library_path, forward, adjoint, adjoint_implicit, psd_project,
+    OracleScene, build_library, library_path, forward, adjoint, adjoint_implicit, psd_project, point_triangle_d2,
     constraint, rest_data, goal_l2, max_threads,
 )

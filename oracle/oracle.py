@@ -51,13 +51,15 @@ class _Scene(C.Structure):
         ("gravity", C.c_double * 3),
         ("tet_gamma_one", C.c_int32), ("emulate_f32", C.c_int32), ("n_threads", C.c_int32),
         ("n_tri", C.c_int32), ("tri_v", _ip), ("tri_uv", _dp),
+        ("n_body_verts", C.c_int32), ("n_body_tris", C.c_int32), ("body_tris", _ip),
+        ("body_thickness", C.c_double), ("body_compliance", C.c_double), ("body_radius", C.c_double),
     ]
 
 
 class _Params(C.Structure):
     _fields_ = [("dist_alpha", _dp), ("bend_alpha", _dp), ("tet_E", _dp),
                 ("f_ext", _dp), ("sphere", C.c_double * 4), ("tet_mu", _dp), ("tet_lambda", _dp),
-                ("tri_coef", _dp)]
+                ("tri_coef", _dp), ("body_x", _dp)]
 
 
 _lib = None
@@ -102,6 +104,7 @@ class OracleScene:
         self.tet_nu = np.ascontiguousarray(sc.tet_nu, np.float64)
         self.tri_v = np.ascontiguousarray(sc.tri_v, np.int32)
         self.tri_uv = np.ascontiguousarray(sc.tri_uv, np.float64)
+        self.body_tris = np.ascontiguousarray(sc.body_tris, np.int32)
         self.n_materials = int(getattr(sc, "n_materials", 0) or 0)
         self.material = (None if not self.n_materials else np.asarray(sc.tet_material, np.int64))
         st, off, items = sc.schedule_arrays()
@@ -126,12 +129,16 @@ class OracleScene:
             s.gravity[a] = sc.gravity[a]
         s.tet_gamma_one = 1 if tet_gamma_one else 0
         s.n_tri, s.tri_v, s.tri_uv = sc.n_tri, self.tri_v.ctypes.data_as(_ip), _d(self.tri_uv)
+        s.n_body_verts, s.n_body_tris = sc.n_body_verts, sc.n_body_tris
+        s.body_tris = self.body_tris.ctypes.data_as(_ip)
+        s.body_thickness, s.body_compliance = sc.body_thickness, sc.body_compliance
+        s.body_radius = sc.body_radius
         s.emulate_f32 = 1 if emulate_f32 else 0
         s.n_threads = n_threads
         self.s = s
 
     def params(self, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None, sphere=None, tet_mu=None,
-               tet_lambda=None, tri_coef=None):
+               tet_lambda=None, tri_coef=None, body_x=None):
         sc = self.sc
         keep = []
 
@@ -157,6 +164,7 @@ class OracleScene:
         for a in range(4):
             p.sphere[a] = float(sph[a])
         p.tri_coef = _d(arr(tri_coef, sc.tri_coef, 4 * sc.n_tri))
+        p.body_x = _d(arr(body_x, sc.body_x, 3 * sc.n_body_verts))
         if tet_mu is not None:
             p.tet_mu = _d(arr(per_tet(tet_mu), None, sc.n_tet))
             p.tet_lambda = _d(arr(per_tet(tet_lambda), None, sc.n_tet))
@@ -203,17 +211,27 @@ def adjoint(osc: OracleScene, n_frames: int, dLdx, dLdv_final=None, x0=None, v0=
         "dist_alpha": np.zeros(sc.n_dist), "bend_alpha": np.zeros(sc.n_bend),
         "tet_E": np.zeros(sc.n_tet), "f_ext": np.zeros((n_frames, V, 3)),
         "sphere": np.zeros(4), "tet_mu": np.zeros(sc.n_tet), "tet_lambda": np.zeros(sc.n_tet),
-        "tri_coef": np.zeros((sc.n_tri, 4)),
+        "tri_coef": np.zeros((sc.n_tri, 4)), "body_x": np.zeros((sc.n_body_verts, 3)),
     }
     rc = _load().orc_adjoint(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0), _d(dLdx),
                              _d(dv), _d(g["x0"]), _d(g["v0"]), _d(g["dist_alpha"]),
                              _d(g["bend_alpha"]), _d(g["tet_E"]), _d(g["f_ext"]),
-                             _d(g["sphere"]), _d(g["tet_mu"]), _d(g["tet_lambda"]), _d(g["tri_coef"]))
+                             _d(g["sphere"]), _d(g["tet_mu"]), _d(g["tet_lambda"]), _d(g["tri_coef"]),
+                             _d(g["body_x"]))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
     for k in ("tet_E", "tet_mu", "tet_lambda"):
         g[k] = osc.material_sum(g[k])
     return g
+
+
+def point_triangle_d2(p, tri):
+    """Squared distance from point p (3,) to triangle tri (3, 3)."""
+    lib = _load()
+    lib.orc_point_triangle_d2.restype = C.c_double
+    pp = np.ascontiguousarray(p, np.float64)
+    tt = np.ascontiguousarray(tri, np.float64)
+    return float(lib.orc_point_triangle_d2(_d(pp), _d(tt)))
 
 
 def psd_project(a):

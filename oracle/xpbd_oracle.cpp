@@ -39,6 +39,14 @@
 //     alpha = (A K)^-1, K = [[C00, C01, 0], [C01, C11, 0], [0, 0, C22]], A the
 //     material-space area; projected as one vector XPBD step (a 3x3 solve
 //     for the three multipliers);
+//   * body collider (Sec. 4.5, 5.3): a triangle mesh with kinematic vertices
+//     x_body (a control).  At the start of each substep, after the
+//     prediction, every body-contact vertex is paired with the body triangle
+//     closest to it (point-triangle distance in FP64, ties to the lower
+//     triangle index), or with none if that distance exceeds the search
+//     radius; during the substep it keeps C = n . (x - a) - tau >= 0 against
+//     the plane of that triangle (a, b, c), n the unit normal of
+//     (b - a) x (c - a), projected only while C < 0;
 //   * substeps: each substep is one step of Eq. xpbdUpdateRule with
 //     dt = frame dt / S; multipliers reset every substep; external force
 //     f_ext[f] is constant over the substeps of frame f;  gravity enters as
@@ -197,6 +205,50 @@ template <class S> S c_membrane(const V3<S>* p, const double* Bm, int comp, bool
   return dot(fu, fv);
 }
 
+// Body contact: signed distance of x to the plane of triangle (a, b, c)
+// minus the thickness; undefined for a degenerate triangle.
+template <class S> S c_body(const V3<S>& x, const V3<S>& a, const V3<S>& b, const V3<S>& c, double tau, bool* ok) {
+  V3<S> n = cross(sub(b, a), sub(c, a));
+  S n2 = dot(n, n);
+  *ok = val(n2) > 0.0;
+  if (!*ok) return n2;
+  return dot(n, sub(x, a)) / sqrt(n2) - tau;
+}
+
+// Squared distance from p to the closest point of triangle (a, b, c): the
+// closest point is a vertex, a point on an edge or the projection into the
+// face, found from the barycentric regions of p's projection.
+double point_triangle_d2(const V3<double>& p, const V3<double>& a, const V3<double>& b, const V3<double>& c) {
+  V3<double> ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
+  double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  auto dist2 = [&](const V3<double>& q) { V3<double> r = sub(p, q); return dot(r, r); };
+  if (d1 <= 0.0 && d2 <= 0.0) return dist2(a);
+  V3<double> bp = sub(p, b);
+  double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0.0 && d4 <= d3) return dist2(b);
+  double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+    double t = d1 / (d1 - d3);
+    return dist2({a.x + t * ab.x, a.y + t * ab.y, a.z + t * ab.z});
+  }
+  V3<double> cp = sub(p, c);
+  double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0.0 && d5 <= d6) return dist2(c);
+  double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+    double t = d2 / (d2 - d6);
+    return dist2({a.x + t * ac.x, a.y + t * ac.y, a.z + t * ac.z});
+  }
+  double va = d3 * d6 - d5 * d4;
+  if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+    double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    return dist2({b.x + t * (c.x - b.x), b.y + t * (c.y - b.y), b.z + t * (c.z - b.z)});
+  }
+  double den = 1.0 / (va + vb + vc);
+  double v = vb * den, w = vc * den;
+  return dist2({a.x + v * ab.x + w * ac.x, a.y + v * ab.y + w * ac.y, a.z + v * ab.z + w * ac.z});
+}
+
 // ------------------------------------------------------------------ scene ABI
 struct Scene {
   int32_t n_verts;
@@ -212,6 +264,8 @@ struct Scene {
   int32_t emulate_f32;
   int32_t n_threads;
   int32_t n_tri; const int32_t* tri_v; const double* tri_uv;   // membrane triangles, uv [n_tri][3][2]
+  int32_t n_body_verts; int32_t n_body_tris; const int32_t* body_tris;   // body collider mesh
+  double body_thickness; double body_compliance; double body_radius;
 };
 struct Params {
   const double* dist_alpha;
@@ -223,9 +277,10 @@ struct Params {
   const double* tet_mu;
   const double* tet_lambda;
   const double* tri_coef;   // [n_tri][4] = C00, C01, C11, C22
+  const double* body_x;     // [n_body_verts][3] body vertex positions
 };
 
-enum { T_DIST = 0, T_BEND = 1, T_TET = 2, T_CONTACT = 3, T_TRI = 4 };
+enum { T_DIST = 0, T_BEND = 1, T_TET = 2, T_CONTACT = 3, T_TRI = 4, T_BODY = 5 };
 
 // one scalar constraint row ("projection"): a tet item holds two (D then H)
 struct Row {
@@ -248,6 +303,8 @@ struct Model {
   std::vector<double> tB;      // [n_tri][4] Dm^-1 of each membrane triangle (row-major 2x2)
   std::vector<double> tarea;   // [n_tri] material-space area
   int lam_tri = 0;             // membrane multipliers: 3 per triangle
+  int lam_body = 0;            // body-contact multipliers, one per listed vertex
+  std::vector<int> body_slot;  // vertex -> body-contact multiplier slot (-1: none)
   int n_lam;
   int lam_dist, lam_bend, lam_tet, lam_contact;  // offsets of each type's multipliers
   std::vector<int> contact_slot;                 // vertex -> contact multiplier slot
@@ -336,10 +393,22 @@ int build_model(const Scene* s, Model* m) {
   }
   m->lam_tri = m->n_lam;
   m->n_lam += 3 * s->n_tri;
+  for (int64_t i = 0; i < 3 * (int64_t)s->n_body_tris; ++i)
+    if (s->body_tris[i] < 0 || s->body_tris[i] >= s->n_body_verts) return 1;
+  m->lam_body = m->n_lam;
+  m->body_slot.assign(V, -1);
+  for (int si = 0; si < s->n_sets; ++si)
+    if (s->set_type[si] == T_BODY)
+      for (int64_t q = s->set_off[si]; q < s->set_off[si + 1]; ++q) {
+        int it = s->set_items[q];
+        if (it < 0 || it >= V || s->inv_mass[it] <= 0.0 || m->body_slot[it] >= 0) return 1;
+        m->body_slot[it] = m->n_lam++;
+      }
   // schedule check: every set's type valid and items in range
   for (int si = 0; si < s->n_sets; ++si) {
     int ty = s->set_type[si];
-    if (ty < T_DIST || ty > T_TRI) return 1;
+    if (ty < T_DIST || ty > T_BODY) return 1;
+    if (ty == T_BODY) continue;   // checked above
     int lim = ty == T_DIST ? s->n_dist : ty == T_BEND ? s->n_bend : ty == T_TET ? s->n_tet : ty == T_TRI ? s->n_tri : V;
     for (int64_t q = s->set_off[si]; q < s->set_off[si + 1]; ++q) {
       int it = s->set_items[q];
@@ -374,6 +443,7 @@ Row make_row(const Model& mm, int type, int item, int sub) {
   else if (type == T_BEND) { r.nv = 4; for (int k = 0; k < 4; ++k) r.v[k] = s->bend_v[4 * item + k]; r.lam = m->lam_bend + item; }
   else if (type == T_TET) { r.nv = 4; for (int k = 0; k < 4; ++k) r.v[k] = s->tet_v[4 * item + k]; r.lam = m->lam_tet + 2 * item + sub; }
   else if (type == T_TRI) { r.nv = 3; for (int k = 0; k < 3; ++k) r.v[k] = s->tri_v[3 * item + k]; r.lam = m->lam_tri + 3 * item; }
+  else if (type == T_BODY) { r.nv = 1; r.v[0] = item; r.lam = m->body_slot[item]; }
   else { r.nv = 1; r.v[0] = item; r.lam = m->lam_contact + m->contact_slot[item]; }
   return r;
 }
@@ -438,13 +508,117 @@ void eval_hvp(const Model* m, const Params* P, const Row& r, const double* x, co
 
 // a tape entry: the positions of the row's vertices and its multiplier
 // before the projection, plus whether it was applied
-struct TapeEntry { double x[12]; double lam; double lamv[3]; };
+struct TapeEntry { double x[12]; double lam; double lamv[3]; int tri; };
 
 struct Ctx {
   Model m;
   const Params* p;
   double h;
+  std::vector<int>* pair = nullptr;   // vertex -> paired body triangle of this substep (-1: none)
 };
+
+// ---- body collider
+V3<double> body_vtx(const Ctx& c, int k) { const double* b = c.p->body_x; return {b[3 * k], b[3 * k + 1], b[3 * k + 2]}; }
+
+// pair every body-contact vertex with its closest body triangle (brute force)
+void body_detect(const Ctx& c, const double* x) {
+  const Scene* s = c.m.s;
+  std::vector<int>& pr = *c.pair;
+  pr.assign(s->n_verts, -1);
+  const double r2 = s->body_radius * s->body_radius;
+#pragma omp parallel for schedule(static) num_threads(s->n_threads > 0 ? s->n_threads : 1)
+  for (int k = 0; k < s->n_verts; ++k) {
+    if (c.m.body_slot[k] < 0) continue;
+    V3<double> p = {x[3 * k], x[3 * k + 1], x[3 * k + 2]};
+    int best = -1;
+    double bd = 0.0;
+    for (int t = 0; t < s->n_body_tris; ++t) {
+      const int32_t* q = s->body_tris + 3 * (int64_t)t;
+      double d2 = point_triangle_d2(p, body_vtx(c, q[0]), body_vtx(c, q[1]), body_vtx(c, q[2]));
+      if (best < 0 || d2 < bd) { best = t; bd = d2; }
+    }
+    pr[k] = (best >= 0 && bd <= r2) ? best : -1;
+  }
+}
+
+struct BodyEval { bool ok; double C; double g[NG]; };
+// C and its partials: slots 0..2 the cloth vertex, 3..11 the triangle's corners
+BodyEval body_eval(const Ctx& c, const double* xk, int tri) {
+  const int32_t* q = c.m.s->body_tris + 3 * (int64_t)tri;
+  V3<G> v[4];
+  v[0] = {gvar(xk[0], 0), gvar(xk[1], 1), gvar(xk[2], 2)};
+  for (int j = 0; j < 3; ++j) {
+    V3<double> b = body_vtx(c, q[j]);
+    v[1 + j] = {gvar(b.x, 3 + 3 * j), gvar(b.y, 4 + 3 * j), gvar(b.z, 5 + 3 * j)};
+  }
+  BodyEval e;
+  G cc = c_body(v[0], v[1], v[2], v[3], c.m.s->body_thickness, &e.ok);
+  e.C = cc.v;
+  for (int i = 0; i < NG; ++i) e.g[i] = cc.d[i];
+  return e;
+}
+void body_hvp(const Ctx& c, const double* xk, int tri, const double* gdir, double* hv) {
+  const int32_t* q = c.m.s->body_tris + 3 * (int64_t)tri;
+  V3<H> v[4];
+  H c0[3];
+  for (int a = 0; a < 3; ++a) c0[a] = H{gvar(xk[a], a), gc(gdir[a])};
+  v[0] = {c0[0], c0[1], c0[2]};
+  for (int j = 0; j < 3; ++j) {
+    V3<double> b = body_vtx(c, q[j]);
+    double bb[3] = {b.x, b.y, b.z};
+    H cj[3];
+    for (int a = 0; a < 3; ++a) cj[a] = H{gvar(bb[a], 3 + 3 * j + a), gc(gdir[3 + 3 * j + a])};
+    v[1 + j] = {cj[0], cj[1], cj[2]};
+  }
+  bool ok;
+  H cc = c_body(v[0], v[1], v[2], v[3], c.m.s->body_thickness, &ok);
+  for (int i = 0; i < NG; ++i) hv[i] = cc.t.d[i];
+}
+void project_body(const Ctx& c, int k, double* x, double* lam, TapeEntry* tape) {
+  const Scene* s = c.m.s;
+  const int slot = c.m.body_slot[k];
+  const int tri = (*c.pair)[k];
+  if (tape) {
+    for (int a = 0; a < 3; ++a) tape->x[a] = x[3 * k + a];
+    tape->lam = lam[slot];
+    tape->tri = tri;
+  }
+  if (tri < 0) return;
+  BodyEval e = body_eval(c, x + 3 * k, tri);
+  if (!e.ok || e.C >= 0.0) return;
+  const double w = s->inv_mass[k];
+  const double at = s->body_compliance / (c.h * c.h);
+  const double D = w * (e.g[0] * e.g[0] + e.g[1] * e.g[1] + e.g[2] * e.g[2]) + at;
+  if (D == 0.0) return;
+  const double dl = (-e.C - at * lam[slot]) / D;
+  lam[slot] = rnd(s, lam[slot] + dl);
+  for (int a = 0; a < 3; ++a) x[3 * k + a] = rnd(s, x[3 * k + a] + w * dl * e.g[a]);
+}
+// reverse of one body-contact projection; the body corners' adjoints go to
+// part[9] (corner j, axis a at 3 j + a)
+void reverse_body(const Ctx& c, int k, const TapeEntry& te, double* xb, double* lamb, double* part) {
+  const Scene* s = c.m.s;
+  const int slot = c.m.body_slot[k];
+  if (te.tri < 0) return;
+  BodyEval e = body_eval(c, te.x, te.tri);
+  if (!e.ok || e.C >= 0.0) return;
+  const double w = s->inv_mass[k];
+  const double at = s->body_compliance / (c.h * c.h);
+  const double D = w * (e.g[0] * e.g[0] + e.g[1] * e.g[1] + e.g[2] * e.g[2]) + at;
+  if (D == 0.0) return;
+  const double lb = te.lam;
+  const double dl = (-e.C - at * lb) / D;
+  double dlb = lamb[slot];
+  for (int a = 0; a < 3; ++a) dlb += w * e.g[a] * xb[3 * k + a];
+  double gbar[NG] = {0};   // adjoint of grad_x C (the corners do not move)
+  for (int a = 0; a < 3; ++a) gbar[a] = w * dl * xb[3 * k + a] - 2.0 * w * e.g[a] * dlb * dl / D;
+  const double Cbar = -dlb / D;
+  lamb[slot] = lamb[slot] - dlb * at / D;
+  double hv[NG];
+  body_hvp(c, te.x, te.tri, gbar, hv);
+  for (int a = 0; a < 3; ++a) xb[3 * k + a] += Cbar * e.g[a] + hv[a];
+  for (int i = 0; i < 9; ++i) part[i] += Cbar * e.g[3 + i] + hv[3 + i];
+}
 
 // ---- membrane triangles: one vector projection
 // 3x3 helpers (row-major)
@@ -537,6 +711,7 @@ void project_membrane(const Ctx& c, const Row& r, double* x, double* lam, TapeEn
 bool project_row(const Ctx& c, const Row& r, double* x, double* lam, TapeEntry* tape) {
   const Scene* s = c.m.s;
   if (r.type == T_TRI) { project_membrane(c, r, x, lam, tape); return true; }
+  if (r.type == T_BODY) { project_body(c, r.item, x, lam, tape); return true; }
   if (tape) {
     for (int k = 0; k < r.nv; ++k)
       for (int a = 0; a < 3; ++a) tape->x[3 * k + a] = x[3 * r.v[k] + a];
@@ -605,6 +780,7 @@ void substep(const Ctx& c, double* x, double* v, double* lam, const double* f,
     for (int a = 0; a < 3; ++a) x[3 * k + a] = rnd(s, x[3 * k + a] + h * v[3 * k + a]);
   }
   std::fill(lam, lam + c.m.n_lam, 0.0);
+  if (c.pair) body_detect(c, x);
   for (int it = 0; it < s->iterations; ++it) sweep(c, x, lam, tape);
   for (size_t i = 0; i < 3 * (size_t)V; ++i) v[i] = rnd(s, (x[i] - xprev[i]) / h);
   if (xprev_out) *xprev_out = xprev;
@@ -771,6 +947,13 @@ int orc_constraint(int type, int sub, const double* p, const double* aux, const 
   return e.ok ? 0 : 1;
 }
 
+// Squared distance from p[3] to the triangle tri[3][3] (the body pairing's
+// distance), exported for the unit tests.
+double orc_point_triangle_d2(const double* p, const double* tri) {
+  return point_triangle_d2({p[0], p[1], p[2]}, {tri[0], tri[1], tri[2]}, {tri[3], tri[4], tri[5]},
+                           {tri[6], tri[7], tri[8]});
+}
+
 // Forward rollout.  x_frames [F][V][3] receives the state at the end of
 // each frame (may be null); x_final / v_final [V][3] the last state.
 int orc_forward(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
@@ -780,6 +963,11 @@ int orc_forward(const orc_scene* s, const orc_params* p, int F, const double* x0
   set_materials(&c.m, p);
   c.p = p;
   c.h = s->dt / s->substeps;
+  std::vector<int> pairv;
+  if (s->n_body_tris > 0) {
+    if (!p->body_x) return 1;
+    c.pair = &pairv;
+  }
   const int V = s->n_verts;
   std::vector<double> x(x0, x0 + 3 * (size_t)V), v(v0, v0 + 3 * (size_t)V), lam(c.m.n_lam, 0.0);
   for (int k = 0; k < V; ++k) {
@@ -807,12 +995,17 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
                 const double* dLdx, const double* dLdv_final,
                 double* g_x0, double* g_v0, double* g_dist_alpha, double* g_bend_alpha,
                 double* g_tet_E, double* g_f, double* g_sphere, double* g_tet_mu, double* g_tet_lambda,
-                double* g_tri_coef) {
+                double* g_tri_coef, double* g_body_x) {
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);
   c.p = p;
   c.h = s->dt / s->substeps;
+  std::vector<int> pairv;
+  if (s->n_body_tris > 0) {
+    if (!p->body_x) return 1;
+    c.pair = &pairv;
+  }
   const int V = s->n_verts;
   const size_t n3 = 3 * (size_t)V;
   // forward with per-frame checkpoints (state at the start of each frame)
@@ -834,6 +1027,7 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
   std::vector<double> abar(c.m.n_lam, 0.0);   // per multiplier slot
   std::vector<double> gbar(s->n_tet, 0.0);     // per tet: dL/dgamma
   std::vector<double> tri_abar(9 * (size_t)s->n_tri, 0.0);   // per triangle: dL/dalpha (3x3)
+  std::vector<double> body_bar(3 * (size_t)s->n_body_verts, 0.0);   // dL/dx_body
   double sph[4] = {0, 0, 0, 0};
   if (g_f) std::fill(g_f, g_f + (size_t)F * n3, 0.0);
   const double h = c.h;
@@ -865,11 +1059,16 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
           int64_t b = s->set_off[si], e = s->set_off[si + 1];
           int nsub = set_rows(c.m, si);
           std::vector<double> sph_part((size_t)(e - b) * 4, 0.0);
+          std::vector<double> body_part(ty == T_BODY ? (size_t)(e - b) * 9 : 0, 0.0);
 #pragma omp parallel for schedule(static) num_threads(s->n_threads > 0 ? s->n_threads : 1)
           for (int64_t q = b; q < e; ++q) {
             for (int sub = nsub - 1; sub >= 0; --sub) {
               Row r = make_row(c.m, ty, s->set_items[q], sub);
               const TapeEntry& te = tp[it_base + set_base[si] + (size_t)(q - b) * nsub + sub];
+              if (ty == T_BODY) {
+                reverse_body(c, r.item, te, xb.data(), lamb.data(), &body_part[(q - b) * 9]);
+                continue;
+              }
               reverse_row(c, r, te, xb.data(), lamb.data(),
                           r.type == T_TRI ? &tri_abar[9 * (size_t)r.item] : &abar[r.lam], &sph_part[(q - b) * 4],
                           r.type == T_TET ? &gbar[r.item] : nullptr);
@@ -878,6 +1077,14 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
           if (ty == T_CONTACT)
             for (int64_t q = 0; q < e - b; ++q)
               for (int a = 0; a < 4; ++a) sph[a] += sph_part[q * 4 + a];
+          if (ty == T_BODY)
+            for (int64_t q = 0; q < e - b; ++q) {
+              const TapeEntry& te = tp[it_base + set_base[si] + (size_t)q];
+              if (te.tri < 0) continue;
+              const int32_t* tv = s->body_tris + 3 * (int64_t)te.tri;
+              for (int j = 0; j < 3; ++j)
+                for (int a = 0; a < 3; ++a) body_bar[3 * (size_t)tv[j] + a] += body_part[q * 9 + 3 * j + a];
+            }
         }
       }
       // predict: v' = v + h (g + w f) (free), x' = x + h v'
@@ -918,6 +1125,7 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
     if (g_tet_mu) g_tet_mu[t] = -gd * aD / mu + gg / la;
     if (g_tet_lambda) g_tet_lambda[t] = -gh * aH / la - gg * mu / (la * la);
   }
+  if (g_body_x) std::copy(body_bar.begin(), body_bar.end(), g_body_x);
   // membrane coefficients: alpha = (A K)^-1, so d alpha = -alpha (A dK) alpha
   // and dL/dK = -A alpha^T alpha_bar alpha^T; K00 = C00, K01 = K10 = C01,
   // K11 = C11, K22 = C22
@@ -1011,12 +1219,17 @@ int orc_psd_project(int n, double* a) {
 int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                          const double* dLdx, double* g_x0, double* g_v0, double* g_dist_alpha,
                          double* g_bend_alpha, double* g_f, int pd) {
-  if (s->n_tri > 0) return 2;   // membrane triangles: not part of the converged-limit cross-check
+  if (s->n_tri > 0 || s->n_body_tris > 0) return 2;   // membrane triangles: not part of the converged-limit cross-check
   Ctx c;
   if (build_model(s, &c.m)) return 1;
   set_materials(&c.m, p);
   c.p = p;
   c.h = s->dt / s->substeps;
+  std::vector<int> pairv;
+  if (s->n_body_tris > 0) {
+    if (!p->body_x) return 1;
+    c.pair = &pairv;
+  }
   const int V = s->n_verts;
   const size_t n3 = 3 * (size_t)V;
   if (n3 > 1200) return 2;

@@ -35,7 +35,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-DIST, BEND, TET, CONTACT, TRI = 0, 1, 2, 3, 4
+DIST, BEND, TET, CONTACT, TRI, BODY = 0, 1, 2, 3, 4, 5
 TYPE_NAMES = {DIST: "dist", BEND: "bend", TET: "tet", CONTACT: "contact"}
 GRAVITY = (0.0, -9.81, 0.0)
 
@@ -82,6 +82,13 @@ class Scene:
     tri_v: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
     tri_uv: np.ndarray = field(default_factory=lambda: np.zeros((0, 6), np.float64))
     tri_coef: Optional[np.ndarray] = None   # (n_tri, 4)
+    # body collider: a triangle mesh with outward normals ((b - a) x (c - a));
+    # body_x is a control (the body's vertex positions, constant over a rollout)
+    body_tris: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    body_x: Optional[np.ndarray] = None     # (n_body_verts, 3)
+    body_thickness: float = 0.005
+    body_compliance: float = 1e-9
+    body_radius: float = 0.05               # pairing search radius
 
     @property
     def n_verts(self) -> int:
@@ -104,6 +111,14 @@ class Scene:
         return int(self.tri_v.shape[0])
 
     @property
+    def n_body_tris(self) -> int:
+        return int(self.body_tris.shape[0])
+
+    @property
+    def n_body_verts(self) -> int:
+        return 0 if self.body_x is None else int(np.asarray(self.body_x).shape[0])
+
+    @property
     def n_tet_params(self) -> int:
         """Length of the tet parameter arrays: materials, else tets."""
         return self.n_materials if self.n_materials else self.n_tet
@@ -123,6 +138,7 @@ class Scene:
         n = self.n_dist + self.n_bend + 2 * self.n_tet + self.n_tri
         if self.contact:
             n += int(np.count_nonzero(self.inv_mass > 0))
+        n += sum(len(it) for t, it in zip(self.set_type, self.set_items) if t == BODY)
         return n
 
     def projections_per_rollout(self, n_frames: Optional[int] = None) -> int:
@@ -696,6 +712,65 @@ def membrane_cloth(n: int = 6, frames: int = 3, substeps: int = 2, iterations: i
     sc.contact_thickness, sc.contact_compliance = 0.005, 1e-7
     sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, substeps, iterations, frames
     sc.name = f"cloth{n}_membrane"
+    return sc
+
+
+def uv_sphere(center=(0.0, 0.0, 0.0), radius: float = 0.3, n_lat: int = 8, n_lon: int = 16):
+    """Closed triangle mesh of a sphere: two poles and n_lat - 1 rings of
+    n_lon vertices; triangles oriented so (b - a) x (c - a) points outward."""
+    c = np.asarray(center, np.float64)
+    verts = [c + [0.0, radius, 0.0]]
+    for i in range(1, n_lat):
+        th = np.pi * i / n_lat
+        for j in range(n_lon):
+            ph = 2 * np.pi * j / n_lon
+            verts.append(c + radius * np.array([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)]))
+    verts.append(c + [0.0, -radius, 0.0])
+    V = np.array(verts)
+    south = len(verts) - 1
+    ring = lambda i, j: 1 + (i - 1) * n_lon + (j % n_lon)
+    tris = []
+    for j in range(n_lon):
+        tris.append((0, ring(1, j), ring(1, j + 1)))
+        tris.append((south, ring(n_lat - 1, j + 1), ring(n_lat - 1, j)))
+    for i in range(1, n_lat - 1):
+        for j in range(n_lon):
+            a, b, cc, d = ring(i, j), ring(i, j + 1), ring(i + 1, j), ring(i + 1, j + 1)
+            tris += [(a, cc, b), (b, cc, d)]
+    T = np.array(tris, np.int32)
+    nrm = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    flip = np.einsum("ij,ij->i", nrm, V[T].mean(axis=1) - c) < 0
+    T[flip, 1], T[flip, 2] = T[flip, 2].copy(), T[flip, 1].copy()
+    return V, T
+
+
+def body_shape_modes(body_x, center):
+    """Synthetic linear shape model of the body (the stand-in for a
+    statistical body model's blend shapes): x_body(a) = x0 + sum_k a_k S_k
+    with S_0..S_2 stretching along x, y, z about the centre and S_3 a smooth
+    bulge on the upper half.  Returns S (4, n_body_verts, 3)."""
+    d = np.asarray(body_x, np.float64) - np.asarray(center, np.float64)
+    S = np.zeros((4,) + d.shape)
+    for k in range(3):
+        S[k][:, k] = d[:, k]
+    r = np.linalg.norm(d, axis=1, keepdims=True)
+    up = np.clip(d[:, 1:2] / np.maximum(r, 1e-12), 0.0, None)
+    S[3] = up ** 2 * d / np.maximum(r, 1e-12)
+    return S
+
+
+def body_cloth(n: int = 8, frames: int = 3, substeps: int = 2, iterations: int = 5, seed: int = 1,
+               body_res=(8, 16), center=(0.05, -0.28, -0.03), radius: float = 0.3) -> Scene:
+    """Cloth (distance + bending, row-0 corners pinned) falling onto a body
+    collider given as a closed triangle mesh (a sphere mesh standing in for a
+    body), one body-contact set of every free vertex."""
+    sc = small_cloth(n=n, frames=frames, substeps=substeps, iterations=iterations, sphere=False, seed=seed)
+    bx, bt = uv_sphere(center, radius, *body_res)
+    sc.body_x, sc.body_tris = bx, bt
+    sc.body_thickness, sc.body_compliance, sc.body_radius = 0.01, 1e-8, 0.1
+    sc.set_type.append(BODY)
+    sc.set_items.append(np.nonzero(sc.inv_mass > 0)[0].astype(np.int32))
+    sc.name = f"cloth{n}_body"
     return sc
 
 

@@ -51,8 +51,9 @@ def test_gpu_descent_follows_reference(dtype):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     sim = Simulator(model, dtype=tdt)
     w = torch.as_tensor(d["vertex_weight"], dtype=torch.float64, device="cuda")
-    a, b, losses = estimate_materials(sim, F, sim.tensor(xt), d["mu0"], d["lambda0"], d["step"], iters,
-                                      d["frame_mask"], w)
+    a, b, losses, step = estimate_materials(sim, F, sim.tensor(xt), d["mu0"], d["lambda0"], d["step"], iters,
+                                            d["frame_mask"], w)
+    assert step == d["step"]
     torch.cuda.synchronize()
     ref_losses = np.array([h[0] for h in ref[:-1]])
     assert all(l1 < l0 for l0, l1 in zip(losses, losses[1:])), losses

@@ -672,6 +672,106 @@ def test_p7_membrane_cloth_adjoint_matches_finite_differences():
     _fd_check(osc, F, {"x0": dx, "v0": dv}, dict(x0=sc.x0, v0=sc.v0), loss_state, g, 1e-6, 1e-5)
 
 
+# ---- body collider (Sec. 4.5 contacts against a triangle mesh, Sec. 5.3 chain to the body)
+
+def test_p4_point_triangle_distance_against_dense_sampling():
+    """The pairing distance: exact point-triangle distance against the
+    minimum over a dense barycentric sampling of the triangle (never below it
+    by more than rounding, never above it by more than the sampling step's
+    reach), for points in every Voronoi region (face, edges, vertices)."""
+    rng = np.random.default_rng(21)
+    m = 200
+    u, v = np.meshgrid(np.linspace(0, 1, m + 1), np.linspace(0, 1, m + 1))
+    keep = u + v <= 1.0
+    u, v = u[keep], v[keep]
+    for _ in range(40):
+        tri = rng.standard_normal((3, 3))
+        p = tri.mean(0) + 1.5 * rng.standard_normal(3)
+        pts = tri[0] + u[:, None] * (tri[1] - tri[0]) + v[:, None] * (tri[2] - tri[0])
+        ds = np.min(np.sum((pts - p) ** 2, axis=1))
+        d2 = O.point_triangle_d2(p, tri)
+        edge = max(np.linalg.norm(tri[1] - tri[0]), np.linalg.norm(tri[2] - tri[0]), np.linalg.norm(tri[2] - tri[1]))
+        assert d2 <= ds + 1e-12
+        assert np.sqrt(ds) - np.sqrt(d2) <= 2.0 * edge / m
+
+
+def _floor_scene(v0, y0=0.3, K=10, F=8, radius=0.5):
+    """One free vertex over a large floor triangle (normal +y at y = 0)."""
+    sc = scenes.small_cloth(n=2, sphere=False, pinned=(0, 1, 2), frames=F, substeps=2, iterations=K)
+    sc.bend_v = np.zeros((0, 4), np.int32)
+    sc.bend_alpha = np.zeros(0)
+    sc.dist_v = np.zeros((0, 2), np.int32)
+    sc.dist_alpha = np.zeros(0)
+    sc.set_type, sc.set_items = [scenes.BODY], [np.array([3], np.int32)]
+    sc.x0 = sc.rest.copy()
+    sc.x0[3] = [0.1, y0, -0.2]
+    sc.v0 = np.zeros_like(sc.rest)
+    sc.v0[3] = v0
+    sc.body_x = np.array([[-50.0, 0.0, -50.0], [-50.0, 0.0, 50.0], [50.0, 0.0, 0.0]])
+    sc.body_tris = np.array([[0, 1, 2]], np.int32)
+    sc.body_thickness, sc.body_compliance, sc.body_radius = 0.02, 0.0, radius
+    return sc
+
+
+def test_p3_vertex_lands_on_a_floor_triangle():
+    """A falling vertex paired with a stiff floor stops at the thickness
+    (y = tau exactly once it has touched, zero compliance), its horizontal
+    motion stays ballistic (no friction); beyond the search radius it is
+    never paired and falls freely."""
+    vx, vz = 0.7, -0.4
+    sc = _floor_scene([vx, -2.0, vz])
+    xf, _, _ = O.forward(O.OracleScene(sc), sc.n_frames)
+    t = sc.dt * np.arange(1, sc.n_frames + 1)
+    np.testing.assert_allclose(xf[:, 3, 0], 0.1 + vx * t, atol=1e-12)
+    np.testing.assert_allclose(xf[:, 3, 2], -0.2 + vz * t, atol=1e-12)
+    at_rest = np.isclose(xf[:, 3, 1], sc.body_thickness, rtol=0, atol=1e-12)
+    assert at_rest[-1] and not at_rest[0]
+    first = int(at_rest.argmax())
+    assert at_rest[first:].all() and (xf[:first, 3, 1] > sc.body_thickness).all()
+    far = _floor_scene([vx, -2.0, vz], radius=1e-3)
+    xg, _, _ = O.forward(O.OracleScene(far), far.n_frames)
+    h = far.dt / far.substeps
+    y, vy = 0.3, -2.0
+    for _ in range(far.n_frames * far.substeps):
+        vy += h * far.gravity[1]
+        y += h * vy
+    np.testing.assert_allclose(xg[-1, 3, 1], y, atol=1e-12)
+
+
+def test_p7_body_collider_adjoint_matches_finite_differences():
+    """Cloth falling onto a sphere-shaped triangle mesh: dL/dx_body, x0, v0,
+    f_ext and the bending compliances against central differences, and the
+    chain to a linear shape model's coefficients (Sec. 5.3)."""
+    sc = scenes.body_cloth(n=8, frames=3)
+    osc = O.OracleScene(sc)
+    F = 3
+    rng = np.random.default_rng(41)
+    f0 = 0.2 * rng.standard_normal((F, sc.n_verts, 3))
+    xf, _, _ = O.forward(osc, F, f_ext=f0)
+    tgt = xf + 0.01 * rng.standard_normal(xf.shape)
+    mask = np.array([0, 1, 1], bool)
+    _, dL = O.goal_l2(xf, tgt, mask)
+    g = O.adjoint(osc, F, dL, f_ext=f0)
+    assert np.abs(g["body_x"]).max() > 0
+    base = dict(body_x=sc.body_x.copy(), f_ext=f0, bend_alpha=sc.bend_alpha.copy())
+
+    def loss(**kw):
+        x, _, _ = O.forward(osc, F, **kw)
+        return O.goal_l2(x, tgt, mask)[0]
+
+    dirs = {"body_x": rng.standard_normal(sc.body_x.shape), "f_ext": rng.standard_normal(f0.shape),
+            "bend_alpha": rng.standard_normal(sc.n_bend) * sc.bend_alpha}
+    _fd_check(osc, F, dirs, base, loss, g, 1e-6, 1e-5)
+    # chain to the shape coefficients: dL/da_k = sum_v dL/dx_body,v . S_k,v
+    S = scenes.body_shape_modes(sc.body_x, (0.05, -0.28, -0.03))
+    ga = np.einsum("kvd,vd->k", S, g["body_x"])
+    eps = 1e-6
+    for k in range(S.shape[0]):
+        lp = loss(body_x=sc.body_x + eps * S[k], f_ext=f0)
+        lm = loss(body_x=sc.body_x - eps * S[k], f_ext=f0)
+        assert abs((lp - lm) / (2 * eps) - ga[k]) <= 1e-5 * abs(ga[k]) + 1e-12, (k, (lp - lm) / (2 * eps), ga[k])
+
+
 # ------------------------------------------------------------------ P8
 
 def test_p8_exact_adjoint_tends_to_implicit_adjoint_on_a_chain():
