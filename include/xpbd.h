@@ -74,7 +74,7 @@ typedef enum {
 } xpbd_status;
 
 typedef enum { XPBD_F32 = 0, XPBD_F64 = 1 } xpbd_dtype;
-typedef enum { XPBD_DIST = 0, XPBD_BEND = 1, XPBD_TET = 2, XPBD_CONTACT = 3, XPBD_TRI = 4 } xpbd_ctype;
+typedef enum { XPBD_DIST = 0, XPBD_BEND = 1, XPBD_TET = 2, XPBD_CONTACT = 3, XPBD_TRI = 4, XPBD_BODY = 5 } xpbd_ctype;
 
 typedef struct {
   int32_t n_verts;
@@ -113,13 +113,34 @@ typedef struct {
   int32_t n_tri;
   const int32_t* tri_v;       /* host [n_tri][3] */
   const double* tri_uv;       /* host [n_tri][6] */
+  /* Body collider (Sec. 4.5 contacts with the body; Sec. 5.3 gradients to
+   * it): a triangle mesh whose vertex positions are a control
+   * (xpbd_params.body_x, kinematic, constant over a rollout); triangles
+   * oriented so (b - a) x (c - a) points out of the body.  Items of
+   * XPBD_BODY sets are free cloth vertices (each at most once).  At the start
+   * of every substep, after the prediction, each item is paired with the
+   * body triangle closest to it (point-triangle distance in FP64, ties to the
+   * lower triangle index) if that distance is at most body_radius; during
+   * the substep it keeps C = n^ . (x - a) - body_thickness >= 0 against the
+   * plane of that triangle (n^ the unit normal), compliance body_compliance,
+   * projected only while C < 0.  The gradient reaches the body vertices
+   * (xpbd_grads.body_x), summed with FP64 atomics (rounding may differ in
+   * the last bits between runs).  Body-contact sets run one launch per set;
+   * they are refused by the persistent kernel, LDS groups, packs and the
+   * implicit adjoint. */
+  int32_t n_body_verts;
+  int32_t n_body_tris;
+  const int32_t* body_tris;   /* host [n_body_tris][3] */
+  double body_thickness;      /* tau (m) */
+  double body_compliance;     /* alpha (m/N), >= 0 */
+  double body_radius;         /* pairing search radius (m), > 0 */
 } xpbd_constraint_desc;
 
 /* One Gauss-Seidel iteration visits these sets in order.  Set s has type
  * set_type[s] and items set_items[set_offsets[s] .. set_offsets[s+1]):
  * constraint indices of that type (for XPBD_TET one item is both the D and
- * the H projection; for XPBD_CONTACT an item is a vertex index; for XPBD_TRI
- * a membrane triangle).  Within a
+ * the H projection; for XPBD_CONTACT and XPBD_BODY an item is a vertex
+ * index; for XPBD_TRI a membrane triangle).  Within a
  * set no vertex may appear twice (the set is independent), every distance,
  * bending and tet constraint must appear exactly once in the schedule, and a
  * contact vertex at most once and only if its inverse mass is > 0.
@@ -204,6 +225,8 @@ typedef struct {
   const void* tri_coef;          /* device [n_tri][4] membrane (C00, C01, C11, C22) (N/m), K
                                     positive definite (else XPBD_ERR_NONFINITE); required
                                     when there are membrane triangles */
+  const void* body_x;            /* device [n_body_verts][3] body vertex positions (ctx dtype);
+                                    required when there are body-contact sets */
 } xpbd_params;
 
 /* Roll out n_frames frames from (x0, v0) (device [V][3]; v0 of pinned
@@ -235,6 +258,7 @@ typedef struct {
                                 compliances and gamma = 1 + mu/lambda */
   double* tet_lambda;        /* [n_tet] dL/dlambda */
   double* tri_coef;          /* [n_tri][4] dL/d(C00, C01, C11, C22) */
+  double* body_x;            /* [n_body_verts][3] dL/dx_body */
 } xpbd_grads;
 
 /* Exact adjoint of the preceding xpbd_forward on this context for a goal
@@ -315,6 +339,7 @@ typedef struct {
   int32_t max_group_lds_bytes;         /* largest LDS footprint of those launches */
   int32_t n_materials;                 /* material clusters, 0 = per-tet parameters */
   int32_t n_tri;                       /* membrane triangles */
+  int32_t n_body_contacts;             /* body-contact items */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 
@@ -323,7 +348,8 @@ xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
  * persistent kernels is bracketed by HIP events on the call's stream (0 =
  * off).  xpbd_profile_read synchronises them and returns, per kernel family
  * (index 2 * type: forward projections of that type, 2 * type + 1: their
- * reverse; 8: persistent forward frame, 9: persistent reverse frame,
+ * reverse, with body contacts counted with the sphere's at 6 and 7; 8:
+ * persistent forward frame, 9: persistent reverse frame,
  * 10: LDS group forward, 11: LDS group reverse, 12: membrane forward,
  * 13: membrane reverse), the number of timed launches, their total
  * milliseconds and the projections they processed, then resets the counts. */

@@ -6,7 +6,7 @@ checkpoint the forward kept).  ``GoalL2.apply`` is the goal of Sec. 4.1
 (W = I on the masked frames, beta = 0) reduced in FP64 on the device.
 Gradients flow to x0, v0, the distance and bending compliances, the tet
 Young's moduli or Lame parameters, the membrane coefficients, the per-frame
-external forces and the sphere (c, R).
+external forces, the sphere (c, R) and the body collider's vertices.
 """
 from __future__ import annotations
 
@@ -21,17 +21,18 @@ from .lib import Simulator, XPBDError, XPBD_ERR_STATE
 class XPBDRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, sim: Simulator, n_frames: int, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere,
-                tet_mu=None, tet_lambda=None, tri_coef=None):
+                tet_mu=None, tet_lambda=None, tri_coef=None, body_x=None):
         sph = None if sphere is None else sphere.detach().cpu().double().numpy()
         d = lambda t: None if t is None else t.detach().contiguous()
         grad = any(ctx.needs_input_grad[2:])
         xf, _, _ = sim.forward(n_frames, x0=d(x0), v0=d(v0), dist_alpha=d(dist_alpha), bend_alpha=d(bend_alpha),
                                tet_E=d(tet_E), f_ext=d(f_ext), sphere=sph, for_adjoint=grad,
-                               tet_mu=d(tet_mu), tet_lambda=d(tet_lambda), tri_coef=d(tri_coef))
+                               tet_mu=d(tet_mu), tet_lambda=d(tet_lambda), tri_coef=d(tri_coef), body_x=d(body_x))
         ctx.sim = sim
         ctx.rid = sim.forward_count
         ctx.meta = [(t.dtype, t.device) if t is not None else None
-                    for t in (x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu, tet_lambda, tri_coef)]
+                    for t in (x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu, tet_lambda, tri_coef,
+                              body_x)]
         return xf
 
     @staticmethod
@@ -40,7 +41,7 @@ class XPBDRollout(torch.autograd.Function):
         if sim.forward_count != ctx.rid:
             raise XPBDError(XPBD_ERR_STATE, "another forward ran on this simulator before this backward")
         names = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere", "tet_mu", "tet_lambda",
-                 "tri_coef")
+                 "tri_coef", "body_x")
         want = [n for n, m, need in zip(names, ctx.meta, ctx.needs_input_grad[2:]) if m is not None and need]
         g = sim.adjoint(gx.to(sim.dtype).contiguous(), None, want=want) if want else {}
         out = []
@@ -66,12 +67,13 @@ class GoalL2(torch.autograd.Function):
 
 
 def rollout(sim: Simulator, n_frames: int, x0, v0, dist_alpha=None, bend_alpha=None, tet_E=None, f_ext=None,
-            sphere: Optional[torch.Tensor] = None, tet_mu=None, tet_lambda=None, tri_coef=None):
+            sphere: Optional[torch.Tensor] = None, tet_mu=None, tet_lambda=None, tri_coef=None, body_x=None):
     """Differentiable rollout: returns the end-of-frame positions (F, V, 3).
     Tets take tet_E (Young's moduli, Poisson ratios fixed) or tet_mu and
-    tet_lambda (Lame parameters); membrane triangles take tri_coef (n_tri, 4)."""
+    tet_lambda (Lame parameters); membrane triangles take tri_coef (n_tri, 4);
+    a body collider takes its vertex positions body_x (n_body_verts, 3)."""
     return XPBDRollout.apply(sim, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu,
-                             tet_lambda, tri_coef)
+                             tet_lambda, tri_coef, body_x)
 
 
 def goal_l2(sim: Simulator, x_frames, targets, frame_mask=None, vertex_weight=None):

@@ -53,10 +53,12 @@ struct SetInfo {
 };
 
 // bytes of the per-projection record per item, by type (scaled by sizeof T / 4)
-// timed kernel families: 2 type (+1 reverse) for types 0..3, 8/9 persistent
-// frame, 10/11 LDS group, 12/13 membrane sets
+// timed kernel families: 2 type (+1 reverse) for types 0..3 (6/7: sphere and
+// body contact), 8/9 persistent frame, 10/11 LDS group, 12/13 membrane sets
 constexpr int kProfFamilies = 14;
-inline int prof_family(int type, bool rev) { return (type == XPBD_TRI ? 12 : 2 * type) + (rev ? 1 : 0); }
+inline int prof_family(int type, bool rev) {
+  return (type == XPBD_TRI ? 12 : type == XPBD_BODY ? 6 : 2 * type) + (rev ? 1 : 0);
+}
 
 inline size_t tape_item_bytes(int type, size_t tsz) {
   switch (type) {
@@ -80,6 +82,16 @@ struct xpbd_ctx_s {
   xpbd_dtype dtype;
   size_t tsz;
   int V = 0, n_dist = 0, n_bend = 0, n_tet = 0, n_contact = 0, n_tri = 0;
+  // body collider: mesh, contact items, pairing per substep, pairing grid
+  int body_nv = 0, body_nt = 0, n_bc = 0;
+  double b_tau = 0, b_alpha = 0, b_radius = 0;
+  int4* body_tris = nullptr;
+  int* bc_vid = nullptr; void* bc_lam = nullptr; void* bc_lamb = nullptr;
+  int* body_pair = nullptr; size_t body_pair_cap = 0;   // [F * S][n_bc]
+  int* grid_off = nullptr; size_t grid_off_cap = 0; int* grid_tris = nullptr; size_t grid_tris_cap = 0;
+  BodyGrid grid{};
+  std::vector<int> body_tris_h;     // host copy [body_nt][3]
+  const void* cur_body_x = nullptr;
   double dt, h;
   int S, K;
   double g[3];
@@ -303,6 +315,19 @@ void prof_end(xpbd_ctx c, hipStream_t st, xpbd_ctx_s::Ev& e, bool on) {
 
 // ===================================================================== launches
 
+// body pairing of every substep of an F-frame rollout
+void ensure_body_pairs(xpbd_ctx c, int F) {
+  if (!c->n_bc) return;
+  size_t need = (size_t)F * c->S * c->n_bc;
+  if (need <= c->body_pair_cap) return;
+  void* pp = c->body_pair;
+  c->release(pp);
+  c->body_pair = nullptr;
+  c->body_pair_cap = 0;
+  c->body_pair = (int*)c->alloc(need * sizeof(int));
+  c->body_pair_cap = need;
+}
+
 // per-frame checkpoints of (x, v) for F frames
 void ensure_checkpoints(xpbd_ctx c, int F) {
   if (c->ck_frames >= F) return;
@@ -339,6 +364,9 @@ template <class T> struct Ops {
     D.c_order = c->contact_order;
     D.mr = TriRec<T>{c->tri_idx, (const T*)c->tri_B, (const T*)c->tri_at, c->n_tri};
     D.m_lam = (T*)c->tri_lam; D.m_lamb = (T*)c->tri_lamb; D.m_ab = (T*)c->tri_ab; D.m_acc = c->tri_acc;
+    D.bc_vid = c->bc_vid; D.bc_lam = (T*)c->bc_lam; D.bc_lamb = (T*)c->bc_lamb; D.bpair = nullptr;
+    D.bx = (const T*)c->cur_body_x; D.btri = c->body_tris; D.bgrad = nullptr;
+    D.bc_tau = (T)c->b_tau; D.bc_at = (T)(c->b_alpha / (c->h * c->h));
     D.sph = Sphere<T>{(T)s[0], (T)s[1], (T)s[2], (T)s[3], (T)c->tau, (T)(c->alpha_c / (c->h * c->h))};
     D.h = (T)c->h; D.inv_h = (T)(1.0 / c->h);
     D.gx = (T)c->g[0]; D.gy = (T)c->g[1]; D.gz = (T)c->g[2];
@@ -369,6 +397,7 @@ template <class T> struct Ops {
       case XPBD_BEND: XPBD_LAUNCH(k_bend, V4); break;
       case XPBD_TET: XPBD_LAUNCH(k_tet, V4); break;
       case XPBD_TRI: XPBD_LAUNCH(k_tri, V4); break;
+      case XPBD_BODY: XPBD_LAUNCH(k_body, V4); break;
       default: XPBD_LAUNCH(k_contact, V4); break;
     }
     check_launch();
@@ -401,6 +430,7 @@ template <class T> struct Ops {
       case XPBD_BEND: XPBD_RLAUNCH(k_bend_rev); break;
       case XPBD_TET: XPBD_RLAUNCH(k_tet_rev); break;
       case XPBD_TRI: XPBD_RLAUNCH(k_tri_rev); break;
+      case XPBD_BODY: XPBD_RLAUNCH(k_body_rev); break;
       default: XPBD_RLAUNCH(k_contact_rev); break;
     }
 #undef XPBD_LAUNCH
@@ -507,10 +537,25 @@ template <class T> struct Ops {
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
-  // one substep of Eq. xpbdUpdateRule; record slot < 0 means no record
-  static void substep(xpbd_ctx c, const Dev<T>& D, const T* f, int slot, hipStream_t st) {
+  // body pairing of global substep gsub (frame * S + substep)
+  static int* pairs_of(xpbd_ctx c, int gsub) {
+    if (!c->n_bc) return nullptr;
+    if (gsub < 0 || (size_t)(gsub + 1) * c->n_bc > c->body_pair_cap) fail(XPBD_ERR_STATE, "body pairing slot");
+    return c->body_pair + (size_t)gsub * c->n_bc;
+  }
+
+  // one substep of Eq. xpbdUpdateRule; record slot < 0 means no record;
+  // gsub = frame * S + substep (the body pairing's slot)
+  static void substep(xpbd_ctx c, const Dev<T>& D0, const T* f, int slot, hipStream_t st, int gsub = -1) {
+    Dev<T> D = D0;
     k_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, f);
     check_launch();
+    if (c->n_bc) {
+      D.bpair = pairs_of(c, gsub);
+      k_body_detect<T><<<nblocks(c->n_bc), kBlock, 0, st>>>((const V4*)c->X, c->bc_vid, c->n_bc, D.bx, c->body_tris,
+                                                            c->grid, c->b_radius * c->b_radius, (int*)D.bpair);
+      check_launch();
+    }
     const int ns = (int)c->sets.size();
     for (int it = 0; it < c->K; ++it)
       for (int k = 0; k < ns; ++k) {
@@ -528,7 +573,10 @@ template <class T> struct Ops {
     check_launch();
   }
 
-  static void reverse_substep(xpbd_ctx c, const Dev<T>& D, T* fbar, double* dsph, int slot, hipStream_t st) {
+  static void reverse_substep(xpbd_ctx c, const Dev<T>& D0, T* fbar, double* dsph, int slot, hipStream_t st,
+                              int gsub = -1) {
+    Dev<T> D = D0;
+    if (c->n_bc) D.bpair = pairs_of(c, gsub);
     k_rev_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
     for (int it = c->K - 1; it >= 0; --it)
@@ -639,6 +687,80 @@ template <class T> struct Ops {
   }
 
   // ------------------------------------------------------------ frame loops
+  // The pairing grid of the body in its current position (host, FP64):
+  // cells of edge >= the search radius over the body's box grown by it.
+  static void build_body_grid(xpbd_ctx c, const T* bx_dev, hipStream_t st) {
+    const int nv = c->body_nv, nt = c->body_nt;
+    std::vector<T> bt((size_t)3 * nv);
+    HIPCHK(hipMemcpyAsync(bt.data(), bx_dev, bt.size() * sizeof(T), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> b(bt.begin(), bt.end());
+    for (double v : b)
+      if (!std::isfinite(v)) fail(XPBD_ERR_NONFINITE, "body vertex position not finite");
+    const double r = c->b_radius;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
+    for (int k = 0; k < nv; ++k)
+      for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], b[3 * k + a]); hi[a] = std::max(hi[a], b[3 * k + a]); }
+    double ext = 0;
+    for (int a = 0; a < 3; ++a) { lo[a] -= r; hi[a] += r; ext = std::max(ext, hi[a] - lo[a]); }
+    const double cell = std::max(r, ext / 64.0);
+    int dims[3];
+    for (int a = 0; a < 3; ++a) dims[a] = std::max(1, (int)std::ceil((hi[a] - lo[a]) / cell));
+    const size_t ncell = (size_t)dims[0] * dims[1] * dims[2];
+    auto cell_range = [&](int t, int a, int& i0, int& i1) {
+      double mn = 1e300, mx = -1e300;
+      for (int j = 0; j < 3; ++j) {
+        double v = b[3 * (size_t)c->body_tris_h[3 * (size_t)t + j] + a];
+        mn = std::min(mn, v);
+        mx = std::max(mx, v);
+      }
+      i0 = std::max(0, (int)std::floor((mn - r - lo[a]) / cell));
+      i1 = std::min(dims[a] - 1, (int)std::floor((mx + r - lo[a]) / cell));
+    };
+    std::vector<int> off(ncell + 1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int> fillp;
+      std::vector<int> lists;
+      if (pass == 1) {
+        for (size_t q = 0; q < ncell; ++q) off[q + 1] += off[q];
+        fillp.assign(off.begin(), off.end() - 1);
+        lists.resize(off[ncell]);
+      }
+      for (int t = 0; t < nt; ++t) {
+        int r0[3], r1[3];
+        for (int a = 0; a < 3; ++a) cell_range(t, a, r0[a], r1[a]);
+        for (int i = r0[0]; i <= r1[0]; ++i)
+          for (int j = r0[1]; j <= r1[1]; ++j)
+            for (int k = r0[2]; k <= r1[2]; ++k) {
+              size_t q = ((size_t)i * dims[1] + j) * dims[2] + k;
+              if (pass == 0) ++off[q + 1];
+              else lists[fillp[q]++] = t;
+            }
+      }
+      if (pass == 1) {
+        if (off.size() > c->grid_off_cap) {
+          void* pp = c->grid_off;
+          c->release(pp);
+          c->grid_off = (int*)c->alloc(off.size() * sizeof(int));
+          c->grid_off_cap = off.size();
+        }
+        if (std::max<size_t>(lists.size(), 1) > c->grid_tris_cap) {
+          void* pp = c->grid_tris;
+          c->release(pp);
+          c->grid_tris = (int*)c->alloc(std::max<size_t>(lists.size(), 1) * sizeof(int));
+          c->grid_tris_cap = std::max<size_t>(lists.size(), 1);
+        }
+        c->upload(c->grid_off, off);
+        c->upload(c->grid_tris, lists);
+      }
+    }
+    for (int a = 0; a < 3; ++a) { c->grid.lo[a] = lo[a]; c->grid.dims[a] = dims[a]; }
+    c->grid.inv_cell = 1.0 / cell;
+    c->grid.off = c->grid_off;
+    c->grid.tris = c->grid_tris;
+  }
+
   template <class U> static void fill(U* p, U v, size_t n, hipStream_t st) {
     if (!n || !p) return;
     k_fill<U><<<nblocks(n), kBlock, 0, st>>>(p, v, n);
@@ -667,6 +789,8 @@ template <class T> struct Ops {
     if (c->n_tri)
       k_gather_tri<T><<<nblocks(c->n_tri), kBlock, 0, st>>>((const T*)p->tri_coef, c->tri_perm, c->tri_area,
                                                             (T*)c->tri_at, ih2, c->n_tri, c->flag);
+    c->cur_body_x = p->body_x;
+    if (c->n_bc) build_body_grid(c, (const T*)p->body_x, st);
     check_launch();
     group_fill(c, st);
     int flags[2] = {0, 0};
@@ -687,6 +811,7 @@ template <class T> struct Ops {
     const int V = c->V;
     const size_t vb = (size_t)V * sizeof(V4);
     ensure_checkpoints(c, F);
+    ensure_body_pairs(c, F);
     gather_params(c, p, st);
     Dev<T> D = dev(c, p->sphere);
     k_pack<T><<<nblocks(V), kBlock, 0, st>>>((const T*)x0, (const T*)v0, (const T*)c->w, (V4*)c->X, (V4*)c->Vv, V);
@@ -700,7 +825,7 @@ template <class T> struct Ops {
         run_program(c, D, false, record ? (char*)c->tape + (size_t)f * frame_tape : nullptr, ff, nullptr, nullptr,
                     record, st);
       } else {
-        for (int s = 0; s < c->S; ++s) substep(c, D, ff, record ? f * c->S + s : -1, st);
+        for (int s = 0; s < c->S; ++s) substep(c, D, ff, record ? f * c->S + s : -1, st, f * c->S + s);
       }
       if (xf) {
         k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (T*)xf + (size_t)f * 3 * V, V);
@@ -725,6 +850,7 @@ template <class T> struct Ops {
     gather_params(c, p, st);
     begin_adjoint(c, F, dLdv, out, st);
     Dev<T> D = dev(c, p->sphere);
+    D.bgrad = out->body_x;
     const size_t frame_tape = (size_t)S * c->K * c->iter_tape_bytes;
     for (int f = F - 1; f >= 0; --f) {
       if (dLdx && (!mask || mask[f])) {
@@ -738,20 +864,20 @@ template <class T> struct Ops {
         if (mode == 1) {
           restore(c, f, st);
           if (c->persistent) run_program(c, D, false, base, ff, nullptr, nullptr, true, st);
-          else for (int s = 0; s < S; ++s) substep(c, D, ff, s, st);
+          else for (int s = 0; s < S; ++s) substep(c, D, ff, s, st, f * S + s);
         }
         if (c->persistent) {
           run_program(c, D, true, base, nullptr, fb, out->sphere, false, st);
         } else {
           int slot0 = mode == 3 ? f * S : 0;
-          for (int s = S - 1; s >= 0; --s) reverse_substep(c, D, fb, out->sphere, slot0 + s, st);
+          for (int s = S - 1; s >= 0; --s) reverse_substep(c, D, fb, out->sphere, slot0 + s, st, f * S + s);
         }
       } else {
         for (int s = S - 1; s >= 0; --s) {
           restore(c, f, st);
-          for (int q = 0; q < s; ++q) substep(c, D, ff, -1, st);
-          substep(c, D, ff, 0, st);
-          reverse_substep(c, D, fb, out->sphere, 0, st);
+          for (int q = 0; q < s; ++q) substep(c, D, ff, -1, st, f * S + q);
+          substep(c, D, ff, 0, st, f * S + s);
+          reverse_substep(c, D, fb, out->sphere, 0, st, f * S + s);
         }
       }
     }
@@ -767,6 +893,7 @@ template <class T> struct Ops {
     fill<double>(c->bend_acc, 0.0, c->n_bend, st);
     fill<double>(c->tet_acc, 0.0, (size_t)3 * c->n_tet, st);
     fill<double>(c->tri_acc, 0.0, (size_t)4 * c->n_tri, st);
+    if (out->body_x) fill<double>(out->body_x, 0.0, (size_t)3 * c->body_nv, st);
     if (out->sphere) fill<double>(out->sphere, 0.0, 4, st);
     if (out->f_ext) fill<T>((T*)out->f_ext, T(0), (size_t)F * 3 * V, st);
     k_adj_init<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (V4*)c->VB, (const T*)c->w, (const T*)dLdv, V);
@@ -899,6 +1026,20 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   check_idx(cd->tri_v, cd->n_tri, 3, "membrane");
   for (int64_t i = 0; i < 6 * (int64_t)cd->n_tri; ++i)
     if (!std::isfinite(cd->tri_uv[i])) fail(XPBD_ERR_INVALID, "membrane material coordinates not finite");
+  if (cd->n_body_tris < 0 || cd->n_body_verts < 0 || (cd->n_body_tris > 0 && !cd->body_tris))
+    fail(XPBD_ERR_INVALID, "bad body collider arrays");
+  c->body_nv = cd->n_body_verts;
+  c->body_nt = cd->n_body_tris;
+  for (int64_t i = 0; i < 3 * (int64_t)cd->n_body_tris; ++i)
+    if (cd->body_tris[i] < 0 || cd->body_tris[i] >= cd->n_body_verts) fail(XPBD_ERR_INVALID, "body triangle index out of range");
+  if (cd->n_body_tris > 0 &&
+      (!(cd->body_radius > 0) || !std::isfinite(cd->body_radius) || !std::isfinite(cd->body_thickness) ||
+       !(cd->body_compliance >= 0) || !std::isfinite(cd->body_compliance)))
+    fail(XPBD_ERR_INVALID, "body collider: radius > 0, finite thickness and compliance >= 0 required");
+  c->b_tau = cd->body_thickness;
+  c->b_alpha = cd->body_compliance;
+  c->b_radius = cd->body_radius;
+  c->body_tris_h.assign(cd->body_tris, cd->body_tris + 3 * (int64_t)std::max(cd->n_body_tris, 0));
   if (cd->n_materials < 0 || (cd->n_materials > 0 && cd->n_tet > 0 && !cd->tet_material))
     fail(XPBD_ERR_INVALID, "bad material clusters");
   c->n_mat = cd->n_materials;
@@ -910,9 +1051,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   if (sd->n_sets < 0 || (sd->n_sets > 0 && (!sd->set_type || !sd->set_offsets || !sd->set_items)))
     fail(XPBD_ERR_INVALID, "bad schedule");
   std::vector<int> seen_d(c->n_dist, 0), seen_b(c->n_bend, 0), seen_t(c->n_tet, 0), seen_c(V, 0);
-  std::vector<int> seen_m(c->n_tri, 0);
+  std::vector<int> seen_m(c->n_tri, 0), seen_bc(V, 0);
   std::vector<int> stamp(V, -1);
-  std::vector<int> perm_d, perm_b, perm_t, vid_c, perm_m;
+  std::vector<int> perm_d, perm_b, perm_t, vid_c, perm_m, vid_bc;
   perm_d.reserve(c->n_dist);
   perm_b.reserve(c->n_bend);
   perm_t.reserve(c->n_tet);
@@ -936,9 +1077,10 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     int ty = sd->set_type[s];
     int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
     if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
-    if (ty < 0 || ty > 4) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
-    if (ty == XPBD_TRI && set_group[s] >= 0)
-      fail(XPBD_ERR_INVALID, "set %d: membrane sets cannot be part of an LDS group", s);
+    if (ty < 0 || ty > 5) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
+    if ((ty == XPBD_TRI || ty == XPBD_BODY) && set_group[s] >= 0)
+      fail(XPBD_ERR_INVALID, "set %d: membrane and body-contact sets cannot be part of an LDS group", s);
+    if (ty == XPBD_BODY && c->body_nt == 0) fail(XPBD_ERR_INVALID, "set %d: body-contact set without a body", s);
     if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
     // order items inside the set by patch (grouped sets), then by their
     // smallest vertex (locality)
@@ -972,10 +1114,10 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
         }
       }
       int* seen = ty == XPBD_DIST ? &seen_d[it] : ty == XPBD_BEND ? &seen_b[it] : ty == XPBD_TET ? &seen_t[it]
-                : ty == XPBD_TRI ? &seen_m[it] : &seen_c[it];
+                : ty == XPBD_TRI ? &seen_m[it] : ty == XPBD_BODY ? &seen_bc[it] : &seen_c[it];
       if (*seen) fail(XPBD_ERR_INVALID, "constraint %d of type %d appears twice in the schedule", it, ty);
       *seen = 1;
-      if (ty == XPBD_CONTACT && !(m->inv_mass[it] > 0))
+      if ((ty == XPBD_CONTACT || ty == XPBD_BODY) && !(m->inv_mass[it] > 0))
         fail(XPBD_ERR_INVALID, "contact on pinned vertex %d", it);
       items.push_back({(patch << 32) | (int64_t)key, it});
     }
@@ -984,7 +1126,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     si.type = ty;
     si.count = (int)items.size();
     std::vector<int>& dst = ty == XPBD_DIST ? perm_d : ty == XPBD_BEND ? perm_b : ty == XPBD_TET ? perm_t
-                          : ty == XPBD_TRI ? perm_m : vid_c;
+                          : ty == XPBD_TRI ? perm_m : ty == XPBD_BODY ? vid_bc : vid_c;
     si.begin = (int)dst.size();
     for (auto& pr : items) dst.push_back(pr.second);
     c->sets.push_back(si);
@@ -994,6 +1136,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   for (int i = 0; i < c->n_tet; ++i) if (!seen_t[i]) fail(XPBD_ERR_INVALID, "tet %d not scheduled", i);
   for (int i = 0; i < c->n_tri; ++i) if (!seen_m[i]) fail(XPBD_ERR_INVALID, "membrane triangle %d not scheduled", i);
   c->n_contact = (int)vid_c.size();
+  c->n_bc = (int)vid_bc.size();
   // per-iteration record layout
   size_t off = 0;
   for (SetInfo& si : c->sets) {
@@ -1142,6 +1285,18 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     up_T(c->tri_B, mB);
     c->upload(c->tri_perm, perm_m);
     c->upload(c->tri_area, marea);
+  }
+  if (c->body_nt) {
+    std::vector<int4> bt(c->body_nt);
+    for (int t = 0; t < c->body_nt; ++t)
+      bt[t] = make_int4(cd->body_tris[3 * t], cd->body_tris[3 * t + 1], cd->body_tris[3 * t + 2], 0);
+    c->body_tris = (int4*)c->alloc(c->body_nt * sizeof(int4));
+    c->upload(c->body_tris, bt);
+  }
+  if (c->n_bc) {
+    c->bc_vid = (int*)c->alloc(c->n_bc * sizeof(int));
+    c->bc_lam = c->alloc(c->n_bc * T_);
+    c->upload(c->bc_vid, vid_bc);
   }
   if (c->n_contact) {
     int n = c->n_contact;
@@ -1407,6 +1562,7 @@ void choose_launch(xpbd_ctx c, const xpbd_options* o) {
   HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (o->launch_mode == 2) {
     if (!coop) fail(XPBD_ERR_INVALID, "launch_mode 2 needs cooperative launch support");
+    if (c->n_bc) fail(XPBD_ERR_INVALID, "launch_mode 2 does not run body-contact sets (per-substep pairing)");
     c->persistent = true;
     return;
   }
@@ -1445,6 +1601,7 @@ void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
       c->contact_lamb = c->alloc(c->n_contact * T_);
       c->contact_sacc = c->alloc(c->n_contact * V4b);
     }
+    if (c->n_bc) c->bc_lamb = c->alloc(c->n_bc * T_);
     if (c->n_tri) {
       c->tri_lamb = c->alloc((size_t)3 * c->n_tri * T_);
       c->tri_ab = c->alloc((size_t)4 * c->n_tri * T_);
@@ -1543,6 +1700,7 @@ xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_
       fail(XPBD_ERR_INVALID, "forward: tet_E, or tet_mu and tet_lambda, required");
     if (!p->tet_mu != !p->tet_lambda) fail(XPBD_ERR_INVALID, "forward: tet_mu and tet_lambda go together");
     if (c->n_tri && !p->tri_coef) fail(XPBD_ERR_INVALID, "forward: tri_coef required");
+    if (c->n_bc && !p->body_x) fail(XPBD_ERR_INVALID, "forward: body_x required");
     if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
     c->have_forward = false;
     c->fwd_recorded = false;
@@ -1577,7 +1735,8 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
     const xpbd_params& q = c->fwd_params;
     if (q.dist_compliance != p->dist_compliance || q.bend_compliance != p->bend_compliance ||
         q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0 ||
-        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef)
+        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef ||
+        q.body_x != p->body_x)
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
     int mode = c->tape_mode_opt;
     if (c->fwd_recorded) {
@@ -1636,6 +1795,7 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->max_group_lds_bytes = c->max_group_lds;
   info->n_materials = c->n_mat;
   info->n_tri = c->n_tri;
+  info->n_body_contacts = c->n_bc;
   return XPBD_OK;
 }
 

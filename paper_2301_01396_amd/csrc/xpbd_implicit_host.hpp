@@ -225,15 +225,17 @@ xpbd_status xpbd_adjoint_implicit(xpbd_ctx c, const xpbd_params* p, const void* 
     if (!p || !out || !cg) fail(XPBD_ERR_INVALID, "implicit adjoint: null argument");
     if (cg->max_iterations < 1 || !(cg->rel_tolerance > 0.0))
       fail(XPBD_ERR_INVALID, "implicit adjoint: max_iterations >= 1 and rel_tolerance > 0 required");
-    if (out->tet_E || out->sphere || out->tet_mu || out->tet_lambda || out->tri_coef)
+    if (out->tet_E || out->sphere || out->tet_mu || out->tet_lambda || out->tri_coef || out->body_x)
       fail(XPBD_ERR_INVALID,
            "implicit adjoint: tet, membrane and sphere parameter gradients are not produced (pass NULL)");
-    if (c->n_tri) fail(XPBD_ERR_INVALID, "implicit adjoint: membrane triangles are not supported");
+    if (c->n_tri || c->n_bc)
+      fail(XPBD_ERR_INVALID, "implicit adjoint: membrane triangles and body contacts are not supported");
     if (!c->have_forward) fail(XPBD_ERR_STATE, "implicit adjoint: no preceding forward on this context");
     const xpbd_params& q = c->fwd_params;
     if (q.dist_compliance != p->dist_compliance || q.bend_compliance != p->bend_compliance ||
         q.tet_E != p->tet_E || q.f_ext != p->f_ext || std::memcmp(q.sphere, p->sphere, sizeof q.sphere) != 0 ||
-        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef)
+        q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef ||
+        q.body_x != p->body_x)
       fail(XPBD_ERR_STATE, "implicit adjoint: parameters differ from the preceding forward");
     ensure_adjoint_buffers(c, 0);
     hipStream_t st = (hipStream_t)stream;

@@ -65,6 +65,11 @@ template <class T> struct Dev {
   TetRec<T> tr; T* t_lamD; T* t_lamH; T* t_lambD; T* t_lambH; T* t_eb; double* t_acc;
   const int* c_vid; T* c_lam; T* c_lamb; Vec4<T>* c_sacc; const int* c_order;
   TriRec<T> mr; T* m_lam; T* m_lamb; T* m_ab; double* m_acc;   // lam, lamb [3][n]; ab, acc [4][n]
+  // body collider: contact items (cloth vertex, multiplier, its adjoint), the
+  // substep's pairing (body triangle per item, -1 none), body vertices
+  // [n_bv][3], triangles, FP64 body-vertex gradient (null: not wanted)
+  const int* bc_vid; T* bc_lam; T* bc_lamb; const int* bpair; const T* bx; const int4* btri; double* bgrad;
+  T bc_tau, bc_at;
   Sphere<T> sph;
   T h, inv_h, gx, gy, gz;
 };
@@ -470,6 +475,68 @@ __device__ __forceinline__ bool tri_rev(Vec4<T> P[3], const Vec4<T>* tape, int t
   return true;
 }
 
+// ---- body collider: C = n^ . (x - a) - tau against the plane of the paired
+// triangle (a, b, c), n^ the unit normal of n = (b - a) x (c - a); the body is
+// kinematic (only x moves), so D = w |grad_x C|^2 + at with grad_x C = n^.
+template <class T> struct BodyEval { V3<T> a, e1, e2, nh; T len, C; bool ok; };
+template <class T>
+__device__ __forceinline__ BodyEval<T> body_eval(V3<T> x, const T* __restrict__ bx, int4 tv, T tau) {
+  BodyEval<T> e;
+  e.a = {bx[3 * tv.x], bx[3 * tv.x + 1], bx[3 * tv.x + 2]};
+  V3<T> b = {bx[3 * tv.y], bx[3 * tv.y + 1], bx[3 * tv.y + 2]};
+  V3<T> c = {bx[3 * tv.z], bx[3 * tv.z + 1], bx[3 * tv.z + 2]};
+  e.e1 = b - e.a;
+  e.e2 = c - e.a;
+  V3<T> n = cross(e.e1, e.e2);
+  T n2 = dot(n, n);
+  e.ok = n2 > T(0);
+  e.len = e.ok ? sqrt(n2) : T(1);
+  e.nh = (T(1) / e.len) * n;
+  e.C = dot(e.nh, x - e.a) - tau;
+  return e;
+}
+
+// Reverse: with r = x - a, q = (I - n^ n^T) r / |n| and q' the same for the
+// adjoint gbar of grad_x C, the partials of C and of n^ . gbar give
+//   bbar += e2 x Q,  cbar += Q x e1,  abar -= e2 x Q + Q x e1 + Cbar n^,
+// Q = Cbar q + q'; x gets Cbar n^ (n^ does not depend on x).
+template <class T>
+__device__ __forceinline__ bool body_rev(Vec4<T>& P, Vec4<T> tp, const T* __restrict__ bx, int4 tv, T tau, T at,
+                                         T& lbar, double* __restrict__ bgrad) {
+  V3<T> x = {tp.x, tp.y, tp.z};
+  BodyEval<T> ev = body_eval(x, bx, tv, tau);
+  T Dn = P.w * dot(ev.nh, ev.nh) + at;
+  if (!(ev.ok && ev.C < T(0) && Dn > T(0))) return false;
+  T lb = tp.w;
+  T dl = (-ev.C - at * lb) / Dn;
+  V3<T> xb = xyz(P);
+  T dlb = lbar + P.w * dot(ev.nh, xb);
+  T cc = T(2) * dlb * dl / Dn;
+  V3<T> gb = {P.w * (dl * xb.x - cc * ev.nh.x), P.w * (dl * xb.y - cc * ev.nh.y), P.w * (dl * xb.z - cc * ev.nh.z)};
+  T Cb = -dlb / Dn;
+  lbar = lbar - dlb * at / Dn;
+  P.x += Cb * ev.nh.x; P.y += Cb * ev.nh.y; P.z += Cb * ev.nh.z;
+  if (bgrad) {
+    V3<T> r = x - ev.a;
+    T il = T(1) / ev.len;
+    T rn = dot(r, ev.nh), gn = dot(gb, ev.nh);
+    V3<T> Q = {il * (Cb * (r.x - rn * ev.nh.x) + (gb.x - gn * ev.nh.x)),
+               il * (Cb * (r.y - rn * ev.nh.y) + (gb.y - gn * ev.nh.y)),
+               il * (Cb * (r.z - rn * ev.nh.z) + (gb.z - gn * ev.nh.z))};
+    V3<T> db = cross(ev.e2, Q), dc = cross(Q, ev.e1);
+    V3<T> da = {-(db.x + dc.x + Cb * ev.nh.x), -(db.y + dc.y + Cb * ev.nh.y), -(db.z + dc.z + Cb * ev.nh.z)};
+    const int vs[3] = {tv.x, tv.y, tv.z};
+    const V3<T> gs[3] = {da, db, dc};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      atomicAdd(bgrad + 3 * vs[k], (double)gs[k].x);
+      atomicAdd(bgrad + 3 * vs[k] + 1, (double)gs[k].y);
+      atomicAdd(bgrad + 3 * vs[k] + 2, (double)gs[k].z);
+    }
+  }
+  return true;
+}
+
 // ===================================================================== items on global vertex state
 
 template <class T, bool FIRST, bool TAPE>
@@ -535,6 +602,29 @@ __device__ __forceinline__ void tri_item(const Dev<T>& D, int begin, int count, 
 #pragma unroll
   for (int c = 0; c < 3; ++c) D.m_lam[c * n + j] = lam[c];
   if (moved) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; }
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void body_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int v = D.bc_vid[j];
+  Vec4<T> p = D.X[v];
+  T lb = FIRST ? T(0) : D.bc_lam[j];
+  if (TAPE) tape[t] = Vec4<T>{p.x, p.y, p.z, lb};
+  const int tri = D.bpair[j];
+  T ln = lb;
+  if (tri >= 0) {
+    BodyEval<T> ev = body_eval(xyz(p), D.bx, D.btri[tri], D.bc_tau);
+    T Dn = p.w * dot(ev.nh, ev.nh) + D.bc_at;
+    if (ev.ok && ev.C < T(0) && Dn > T(0)) {
+      T dl = (-ev.C - D.bc_at * lb) / Dn;
+      T s = p.w * dl;
+      p.x += s * ev.nh.x; p.y += s * ev.nh.y; p.z += s * ev.nh.z;
+      ln = lb + dl;
+      D.X[v] = p;
+    }
+  }
+  D.bc_lam[j] = ln;
 }
 
 template <class T, bool FIRST, bool LAST>
@@ -617,6 +707,20 @@ __device__ __forceinline__ void tri_rev_item(const Dev<T>& D, int begin, int cou
 }
 
 template <class T, bool FIRST, bool LAST>
+__device__ __forceinline__ void body_rev_item(const Dev<T>& D, int begin, int count, int t,
+                                              const Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  const int tri = D.bpair[j];
+  T lbar = FIRST ? T(0) : D.bc_lamb[j];
+  if (tri >= 0) {
+    int v = D.bc_vid[j];
+    Vec4<T> P = D.XB[v];
+    if (body_rev(P, tape[t], D.bx, D.btri[tri], D.bc_tau, D.bc_at, lbar, D.bgrad)) D.XB[v] = P;
+  }
+  if (!LAST) D.bc_lamb[j] = lbar;
+}
+
+template <class T, bool FIRST, bool LAST>
 __device__ __forceinline__ void contact_rev_item(const Dev<T>& D, int begin, int count, int t,
                                                  const Vec4<T>* __restrict__ tape) {
   int j = begin + t;
@@ -691,11 +795,13 @@ XPBD_SET_KERNEL(k_bend, bend_item, Vec4<T>)
 XPBD_SET_KERNEL(k_tet, tet_item, Vec4<T>)
 XPBD_SET_KERNEL(k_contact, contact_item, Vec4<T>)
 XPBD_SET_KERNEL(k_tri, tri_item, Vec4<T>)
+XPBD_SET_KERNEL(k_body, body_item, Vec4<T>)
 XPBD_SET_KERNEL(k_dist_rev, dist_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_bend_rev, bend_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_tet_rev, tet_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_contact_rev, contact_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_tri_rev, tri_rev_item, const Vec4<T>)
+XPBD_SET_KERNEL(k_body_rev, body_rev_item, const Vec4<T>)
 #undef XPBD_SET_KERNEL
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_predict(Dev<T> D, const T* f) {
@@ -877,6 +983,87 @@ __global__ __launch_bounds__(kBlock) void k_scatter_tri_grad(const double* __res
   o[1] = 2.0 * k * y01;
   o[2] = k * y11;
   o[3] = k * i22 * s22 * i22;
+}
+
+// Body pairing: a uniform grid over the body's bounding box grown by the
+// search radius r, each cell listing (ascending) the triangles whose own box
+// grown by r meets it, so every triangle within r of a point is listed in the
+// point's cell.
+struct BodyGrid {
+  double lo[3];
+  double inv_cell;
+  int dims[3];
+  const int* off;    // [cells + 1]
+  const int* tris;   // cell lists
+};
+
+// squared distance from p to triangle (a, b, c): closest point by the
+// barycentric region of p's projection (vertex, edge or face)
+__device__ __forceinline__ double point_tri_d2(V3<double> p, V3<double> a, V3<double> b, V3<double> c) {
+  V3<double> ab = b - a, ac = c - a, ap = p - a;
+  double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  V3<double> q;
+  if (d1 <= 0.0 && d2 <= 0.0) { q = a; }
+  else {
+    V3<double> bp = p - b;
+    double d3 = dot(ab, bp), d4 = dot(ac, bp);
+    double vc = d1 * d4 - d3 * d2;
+    if (d3 >= 0.0 && d4 <= d3) { q = b; }
+    else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) { double t = d1 / (d1 - d3); q = a + t * ab; }
+    else {
+      V3<double> cp = p - c;
+      double d5 = dot(ab, cp), d6 = dot(ac, cp);
+      double vb = d5 * d2 - d1 * d6;
+      double va = d3 * d6 - d5 * d4;
+      if (d6 >= 0.0 && d5 <= d6) { q = c; }
+      else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) { double t = d2 / (d2 - d6); q = a + t * ac; }
+      else if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+        double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        q = b + t * (c - b);
+      } else {
+        double den = 1.0 / (va + vb + vc);
+        q = a + (vb * den) * ab + (vc * den) * ac;
+      }
+    }
+  }
+  V3<double> r = p - q;
+  return dot(r, r);
+}
+
+// pair each body-contact item with its closest triangle within r (ties to the
+// lower triangle index), -1 if none
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_body_detect(const Vec4<T>* __restrict__ X, const int* __restrict__ vid, int n,
+                                                        const T* __restrict__ bx, const int4* __restrict__ btri,
+                                                        BodyGrid G, double r2, int* __restrict__ pair) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  Vec4<T> xp = X[vid[j]];
+  V3<double> p = {(double)xp.x, (double)xp.y, (double)xp.z};
+  int ci[3];
+  const double pc[3] = {p.x, p.y, p.z};
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double u = (pc[a] - G.lo[a]) * G.inv_cell;
+    inside = inside && u >= 0.0 && u < (double)G.dims[a];
+    ci[a] = inside ? (int)u : 0;
+  }
+  int best = -1;
+  double bd = 0.0;
+  if (inside) {
+    const int cell = (ci[0] * G.dims[1] + ci[1]) * G.dims[2] + ci[2];
+    for (int q = G.off[cell]; q < G.off[cell + 1]; ++q) {
+      int t = G.tris[q];
+      int4 tv = btri[t];
+      V3<double> a = {(double)bx[3 * tv.x], (double)bx[3 * tv.x + 1], (double)bx[3 * tv.x + 2]};
+      V3<double> b = {(double)bx[3 * tv.y], (double)bx[3 * tv.y + 1], (double)bx[3 * tv.y + 2]};
+      V3<double> c = {(double)bx[3 * tv.z], (double)bx[3 * tv.z + 1], (double)bx[3 * tv.z + 2]};
+      double d2 = point_tri_d2(p, a, b, c);
+      if (best < 0 || d2 < bd) { best = t; bd = d2; }
+    }
+  }
+  pair[j] = (best >= 0 && bd <= r2) ? best : -1;
 }
 
 // Material clusters: the gradient of material m is the sum of the per-tet

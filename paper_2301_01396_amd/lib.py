@@ -42,7 +42,9 @@ class ConstraintDesc(C.Structure):
                 ("n_tet", C.c_int32), ("tet_v", _ip), ("tet_nu", _dp), ("contact", C.c_int32),
                 ("contact_thickness", C.c_double), ("contact_compliance", C.c_double),
                 ("n_materials", C.c_int32), ("tet_material", _ip),
-                ("n_tri", C.c_int32), ("tri_v", _ip), ("tri_uv", _dp)]
+                ("n_tri", C.c_int32), ("tri_v", _ip), ("tri_uv", _dp),
+                ("n_body_verts", C.c_int32), ("n_body_tris", C.c_int32), ("body_tris", _ip),
+                ("body_thickness", C.c_double), ("body_compliance", C.c_double), ("body_radius", C.c_double)]
 
 
 class ScheduleDesc(C.Structure):
@@ -60,13 +62,14 @@ class Options(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
-                ("sphere", C.c_double * 4), ("tet_mu", _vp), ("tet_lambda", _vp), ("tri_coef", _vp)]
+                ("sphere", C.c_double * 4), ("tet_mu", _vp), ("tet_lambda", _vp), ("tri_coef", _vp),
+                ("body_x", _vp)]
 
 
 class Grads(C.Structure):
     _fields_ = [("dist_compliance", _vp), ("bend_compliance", _vp), ("tet_E", _vp), ("f_ext", _vp),
                 ("x0", _vp), ("v0", _vp), ("sphere", _vp), ("tet_mu", _vp), ("tet_lambda", _vp),
-                ("tri_coef", _vp)]
+                ("tri_coef", _vp), ("body_x", _vp)]
 
 
 class Info(C.Structure):
@@ -75,7 +78,7 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("tape_bytes_per_iteration", C.c_int64),
                 ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32),
                 ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32),
-                ("n_materials", C.c_int32), ("n_tri", C.c_int32)]
+                ("n_materials", C.c_int32), ("n_tri", C.c_int32), ("n_body_contacts", C.c_int32)]
 
 
 class Job(C.Structure):
@@ -195,13 +198,16 @@ class Simulator:
         tet_mat = (np.ascontiguousarray(scene.tet_material, np.int32) if n_mat else np.zeros(0, np.int32))
         tri_v = np.ascontiguousarray(scene.tri_v, np.int32)
         tri_uv = np.ascontiguousarray(scene.tri_uv, np.float64)
+        body_tris = np.ascontiguousarray(scene.body_tris, np.int32)
         st, off, items = scene.schedule_arrays()
         m = MeshDesc(scene.n_verts, rest.ctypes.data_as(_dp), inv_mass.ctypes.data_as(_dp))
         cd = ConstraintDesc(scene.n_dist, dist_v.ctypes.data_as(_ip), scene.n_bend, bend_v.ctypes.data_as(_ip),
                             scene.n_tet, tet_v.ctypes.data_as(_ip), tet_nu.ctypes.data_as(_dp),
                             1 if scene.contact else 0, scene.contact_thickness, scene.contact_compliance,
                             n_mat, tet_mat.ctypes.data_as(_ip), scene.n_tri, tri_v.ctypes.data_as(_ip),
-                            tri_uv.ctypes.data_as(_dp))
+                            tri_uv.ctypes.data_as(_dp), scene.n_body_verts, scene.n_body_tris,
+                            body_tris.ctypes.data_as(_ip), scene.body_thickness, scene.body_compliance,
+                            scene.body_radius)
         gs, gp = schedule_groups(scene, use_groups)
         sd = ScheduleDesc(len(st), st.ctypes.data_as(_ip), off.ctypes.data_as(_lp), items.ctypes.data_as(_ip),
                           len(gs) // 2, gs.ctypes.data_as(_ip), gp.ctypes.data_as(_ip))
@@ -270,7 +276,7 @@ class Simulator:
 
     # ------------------------------------------------------------------ API
     def _inputs(self, n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere, tet_mu=None,
-                tet_lambda=None, tri_coef=None):
+                tet_lambda=None, tri_coef=None, body_x=None):
         sc = self.scene
         V = sc.n_verts
         x0 = self._arg(sc.x0 if x0 is None else x0, (V, 3))
@@ -293,14 +299,18 @@ class Simulator:
         if sc.n_tri:
             tc = self._arg(sc.tri_coef if tri_coef is None else tri_coef, (sc.n_tri, 4))
             p.tri_coef = _ptr(tc)
+        bxx = None
+        if sc.n_body_tris:
+            bxx = self._arg(sc.body_x if body_x is None else body_x, (sc.n_body_verts, 3))
+            p.body_x = _ptr(bxx)
         self._lame = lame
-        return x0, v0, da, ba, te, fe, p, (tm, tl, tc)
+        return x0, v0, da, ba, te, fe, p, (tm, tl, tc, bxx)
 
     def _grad_buffers(self, F, want):
         sc = self.scene
         V = sc.n_verts
         lame = getattr(self, "_lame", False)
-        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext", "sphere", "tri_coef") +
+        want = set(want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext", "sphere", "tri_coef", "body_x") +
                    (("tet_mu", "tet_lambda") if lame else ("tet_E",)))
         dev, f64 = self.device, torch.float64
         g = {}
@@ -328,13 +338,15 @@ class Simulator:
             g.pop("tet_E", None)
         if "tri_coef" in want and sc.n_tri:
             g["tri_coef"] = torch.empty((sc.n_tri, 4), dtype=f64, device=dev)
+        if "body_x" in want and sc.n_body_tris:
+            g["body_x"] = torch.empty((sc.n_body_verts, 3), dtype=f64, device=dev)
         gr = Grads(*(_ptr(g.get(k)) for k in ("dist_alpha", "bend_alpha", "tet_E", "f_ext", "x0", "v0",
-                                              "sphere", "tet_mu", "tet_lambda", "tri_coef")))
+                                              "sphere", "tet_mu", "tet_lambda", "tri_coef", "body_x")))
         return g, gr
 
     def forward(self, n_frames: int, x0=None, v0=None, dist_alpha=None, bend_alpha=None, tet_E=None,
                 f_ext=None, sphere=None, frames: bool = True, x_frames_out=None, for_adjoint: bool = False,
-                tet_mu=None, tet_lambda=None, tri_coef=None):
+                tet_mu=None, tet_lambda=None, tri_coef=None, body_x=None):
         """Roll out; returns (x_frames or None, x_final, v_final) on the device.
 
         ``for_adjoint``: an adjoint will follow; the library may keep the record
@@ -342,7 +354,7 @@ class Simulator:
         sc = self.scene
         V = sc.n_verts
         x0, v0, da, ba, te, fe, p, lm = self._inputs(n_frames, x0, v0, dist_alpha, bend_alpha, tet_E, f_ext, sphere,
-                                                     tet_mu, tet_lambda, tri_coef)
+                                                     tet_mu, tet_lambda, tri_coef, body_x)
         xf = None
         if frames:
             xf = x_frames_out if x_frames_out is not None else torch.empty((n_frames, V, 3), dtype=self.dtype,
@@ -388,7 +400,9 @@ class Simulator:
         V = self.scene.n_verts
         g, gr = self._grad_buffers(F, want or ("x0", "v0", "dist_alpha", "bend_alpha", "f_ext"))
         gr.tri_coef = None
+        gr.body_x = None
         g.pop("tri_coef", None)
+        g.pop("body_x", None)
         gr.tet_E = None
         gr.sphere = None
         g.pop("tet_E", None)

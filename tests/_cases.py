@@ -50,7 +50,7 @@ def gpu_case(sim, F, ref, f_ext=None, for_adjoint=True):
     return out
 
 
-GROUPS = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere", "tri_coef")
+GROUPS = ("x0", "v0", "dist_alpha", "bend_alpha", "tet_E", "f_ext", "sphere", "tri_coef", "body_x")
 
 
 def compare(sc, ref, got, pos_tol, grad_tol, groups=GROUPS, report=None):

@@ -345,3 +345,77 @@ def test_membrane_validation():
     with pytest.raises(XPBDError) as e:
         sim.adjoint_implicit(torch.ones_like(xf))
     assert e.value.status == XPBD_ERR_INVALID
+
+
+# ---------------------------------------------------------------- body collider
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-5, 1e-3)])
+def test_body_collider_cloth(dtype, pos_tol, grad_tol):
+    """Cloth falling onto a triangle-mesh body: positions and every gradient,
+    including dL/dx_body (Sec. 5.3's route to body parameters), against the
+    reference; the pairing decisions are the reference's."""
+    sc = scenes.body_cloth(n=9, frames=3, substeps=2, iterations=5)
+    rng = np.random.default_rng(23)
+    f = 0.3 * rng.standard_normal((3, sc.n_verts, 3))
+    ref = reference_case(sc, 3, mask=np.array([0, 1, 1], bool), f_ext=f)
+    assert np.abs(ref["grads"]["body_x"]).max() > 0
+    got = gpu_case(_sim(sc, dtype), 3, ref, f_ext=f)
+    assert got["grads"]["body_x"].shape == (sc.n_body_verts, 3)
+    compare(sc, ref, got, pos_tol, grad_tol)
+
+
+def test_body_collider_record_modes_agree():
+    """Whole-rollout record, per-frame and per-substep recomputation pair the
+    vertices the same way and give the same results (bitwise, except the
+    body-vertex gradient, summed with FP64 atomics: 1e-13)."""
+    sc = scenes.body_cloth(n=10, frames=2, substeps=2, iterations=4)
+    ref = reference_case(sc, 2, n_threads=8)
+    outs = [gpu_case(_sim(sc, "f32", tape_mode=m), 2, ref) for m in (3, 1, 2)]
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            if k == "body_x":
+                err = rel(o["grads"][k], v)
+                assert err <= 1e-13, err
+            else:
+                assert np.array_equal(o["grads"][k], v), k
+    compare(sc, ref, outs[0], 1e-5, 1e-3)
+
+
+def test_body_collider_validation():
+    """Refused: the persistent kernel, an LDS group, a pack, the implicit
+    adjoint, a body triangle index out of range, a body-contact set without
+    a body."""
+    import torch
+    from paper_2301_01396_amd import lib as L
+    from paper_2301_01396_amd.lib import XPBDError, XPBD_ERR_INVALID
+    sc = scenes.body_cloth(n=5, frames=1)
+    with pytest.raises(XPBDError) as e:
+        _sim(sc, "f32", launch_mode=2)
+    assert e.value.status == XPBD_ERR_INVALID
+    grp = scenes.body_cloth(n=5, frames=1)
+    grp.groups = [(len(grp.set_type) - 1, len(grp.set_type), np.zeros(grp.n_verts, np.int32))]
+    with pytest.raises(XPBDError) as e:
+        _sim(grp, "f32")
+    assert e.value.status == XPBD_ERR_INVALID
+    bad = scenes.body_cloth(n=5, frames=1)
+    bad.body_tris = bad.body_tris.copy()
+    bad.body_tris[3, 1] = bad.n_body_verts
+    with pytest.raises(XPBDError) as e:
+        _sim(bad, "f32")
+    assert e.value.status == XPBD_ERR_INVALID
+    nob = scenes.body_cloth(n=5, frames=1)
+    nob.body_tris = np.zeros((0, 3), np.int32)
+    with pytest.raises(XPBDError) as e:
+        _sim(nob, "f32")
+    assert e.value.status == XPBD_ERR_INVALID
+    sim = _sim(sc, "f32")
+    xf, _, _ = sim.forward(1)
+    with pytest.raises(XPBDError) as e:
+        sim.adjoint_implicit(torch.ones_like(xf))
+    assert e.value.status == XPBD_ERR_INVALID
+    pk = L.Pack(dtype=torch.float32)
+    with pytest.raises(XPBDError) as e:
+        pk.add(sim, 1)
+    assert e.value.status == XPBD_ERR_INVALID
+    pk.close()
