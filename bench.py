@@ -68,21 +68,40 @@ def alg_bytes(fam: int, tsz: int, recording: float = 0.0) -> float:
 GROUP_REC_WORDS = {0: (4, 5), 2: (5, 6), 4: (8, 8.5), 6: (2, 8)}
 
 
-def group_bytes(sc, reverse: bool, tsz: int, recording: bool, n_groups: int) -> float:
-    """Average algorithmic bytes per projection of an LDS group launch:
-    record image read + write, record of inputs (written by the forward
-    when recording, read by the reverse), and each group's vertex tiles read
-    and written once per launch."""
+def group_vertices(sc) -> int:
+    """Vertices the LDS groups stage, summed over the groups: each group
+    loads (and stores) exactly the vertices its constraints touch."""
+    tot = 0
+    for a, b, _ in sc.groups:
+        parts = []
+        for t, items in zip(sc.set_type[a:b], sc.set_items[a:b]):
+            if t == 0:
+                parts.append(sc.dist_v[items].ravel())
+            elif t == 1:
+                parts.append(sc.bend_v[items].ravel())
+            elif t == 2:
+                parts.append(sc.tet_v[items].ravel())
+            else:
+                parts.append(np.asarray(items))
+        if parts:
+            tot += int(np.unique(np.concatenate(parts)).size)
+    return tot
+
+
+def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: int) -> float:
+    """Average algorithmic bytes per projection of the LDS group launches of
+    one iteration: record image read + write, record of inputs (written by
+    the forward launches that record, read by the reverse), and the staged
+    vertices of every group read and written once per launch."""
     n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
          6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
     tot = max(sum(n.values()), 1)
     b = 0.0
     for f, cnt in n.items():
         words = 2 * GROUP_REC_WORDS[f][1 if reverse else 0]
-        if reverse or recording:
-            words += TAPE_WORDS[f]
+        words += TAPE_WORDS[f] * (1.0 if reverse else float(recording))
         b += cnt * words * tsz
-    b += n_groups * sc.n_verts * 2 * 4 * tsz
+    b += staged_vertices * 2 * 4 * tsz
     return b / tot
 
 
@@ -103,6 +122,7 @@ KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: 
                  6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)",
                  10: "k_group_fwd", 11: "k_group_rev", 12: "k_tri", 13: "k_tri_rev"}
 N_FAM = len(FAMILY)
+WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 128}}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -120,7 +140,7 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = ""):
+def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = "", merge: str = ""):
     from paper_2301_01396_amd import scenes
     kw = {} if tile < 0 else {"tile": tile}
     if name == "c1":
@@ -129,20 +149,28 @@ def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = 
         return scenes.config_c2(**kw), scenes.config_c2(target=True, **kw)
     if name == "c3":
         return scenes.config_c3(**kw), scenes.config_c3(target=True, **kw)
+    if name == "c2m":
+        return scenes.config_c2_membrane(), scenes.config_c2_membrane(target=True)
+    if name == "c2b":
+        return scenes.config_c2_body(), scenes.config_c2_body(target=True)
     if name == "c4":
         if frames:
             kw["n_frames"] = frames
         if lds_groups:
             kw["lds_groups"] = tuple(int(ch) for ch in lds_groups)
+        if merge:
+            kw["merge"] = tuple(int(v) for v in merge.split(","))
         return scenes.config_c4(**kw), None
     raise SystemExit(f"unknown workload {name}")
 
 
 def workload_config(name, sc, F):
     return {"workload": {"c1": "cloth32_distance_fp64", "c2": "cloth256_dist_bend_sphere",
-                         "c3": "tetbox64_neohookean", "c4": "cloth2048x4096_dist_bend_force"}[name],
+                         "c3": "tetbox64_neohookean", "c4": "cloth2048x4096_dist_bend_force",
+                         "c2m": "cloth256_membrane_bend_sphere", "c2b": "cloth256_dist_bend_body_mesh"}[name],
             "verts": sc.n_verts, "dist": sc.n_dist, "bend": sc.n_bend, "tets": sc.n_tet,
             "contacts": int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0,
+            "membrane_triangles": sc.n_tri, "body_triangles": sc.n_body_tris,
             "frames": F, "substeps": sc.substeps, "iterations": sc.iterations, "dt": sc.dt,
             "sets_per_iteration": len(sc.set_type), "lds_groups": len(sc.groups)}
 
@@ -244,7 +272,7 @@ def implicit_bench(args):
     import torch
     from paper_2301_01396_amd.lib import Simulator
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     sim = Simulator(sc, dtype=dtype)
@@ -332,7 +360,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "c2m", "c2b"])
     ap.add_argument("--requests", type=int, default=24, help="serving mix size (c5)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy kernel over this many bytes (counter calibration)")
@@ -351,6 +379,8 @@ def main():
     ap.add_argument("--group-records", type=int, default=0,
                     help="LDS groups: 1 records staged in LDS, 2 records streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
+    ap.add_argument("--merge", default="",
+                    help="tiled cloth: border segments and corner clusters per patch, e.g. 8,16 (default: the workload's)")
     ap.add_argument("--lds-groups", default="",
                     help="tiled cloth: which of the tiling's groups (0 interiors, 1 borders, 2 corners) run as "
                          "LDS groups, e.g. 012 (default: the workload's)")
@@ -365,6 +395,11 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
+    # launch shape of the LDS group kernels per workload (measured fastest):
+    # the 25.2M-DoF cloth streams its records with 128-thread workgroups
+    for k, v in WORKLOAD_LAUNCH.get(args.workload, {}).items():
+        if getattr(args, k) == 0:
+            setattr(args, k, v)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
@@ -392,7 +427,7 @@ def main():
         return implicit_bench(args)
 
     dev = torch.device("cuda:0")
-    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
@@ -421,19 +456,21 @@ def main():
     torch.cuda.synchronize()
 
     x0 = sim.tensor(sc.x0)
-    v0 = sim.tensor(sc.v0).requires_grad_(args.workload in ("c2",))
-    da = sim.tensor(sc.dist_alpha).requires_grad_(args.workload in ("c1", "c2")) if sc.n_dist else None
-    ba = sim.tensor(sc.bend_alpha).requires_grad_(args.workload == "c2") if sc.n_bend else None
+    v0 = sim.tensor(sc.v0).requires_grad_(args.workload in ("c2", "c2m", "c2b"))
+    da = sim.tensor(sc.dist_alpha).requires_grad_(args.workload in ("c1", "c2", "c2b")) if sc.n_dist else None
+    ba = sim.tensor(sc.bend_alpha).requires_grad_(args.workload in ("c2", "c2m", "c2b")) if sc.n_bend else None
     te = sim.tensor(sc.tet_E).requires_grad_(True) if sc.n_tet else None
+    tc = sim.tensor(sc.tri_coef).requires_grad_(True) if sc.n_tri else None
+    bxx = sim.tensor(sc.body_x).requires_grad_(True) if sc.n_body_tris else None
     if f_ctrl is not None:
         f_ctrl.requires_grad_(True)
     sphere = torch.tensor(sc.sphere, dtype=torch.float64) if sc.contact else None
-    leaves = [t for t in (v0, da, ba, te, f_ctrl) if t is not None and t.requires_grad]
+    leaves = [t for t in (v0, da, ba, te, f_ctrl, tc, bxx) if t is not None and t.requires_grad]
 
     def step(s=sim):
         for t in leaves:
             t.grad = None
-        xf = AG.rollout(s, F, x0, v0, da, ba, te, f_ctrl, sphere)
+        xf = AG.rollout(s, F, x0, v0, da, ba, te, f_ctrl, sphere, tri_coef=tc, body_x=bxx)
         loss = AG.goal_l2(s, xf, targets, mask)
         loss.backward()
         return loss
@@ -490,13 +527,14 @@ def main():
     roof = None
     kernels = {}
     tsz = 8 if dtype == torch.float64 else 4
+    staged = group_vertices(sc) if info["n_groups_lds"] else 0
     def fam_bytes(fam):
         if fam == 8:
             return mix_bytes(sc, False, tsz, recording)
         if fam == 9:
             return mix_bytes(sc, True, tsz, recording)
         if fam in (10, 11):
-            return group_bytes(sc, fam == 11, tsz, recording, max(info["n_groups_lds"], 1))
+            return group_bytes(sc, fam == 11, tsz, recording, staged)
         return alg_bytes(fam, tsz, recording)
 
     for fam in range(N_FAM):
@@ -506,6 +544,7 @@ def main():
             gbs = fam_bytes(fam) * per_launch_items / (avg_ms * 1e-3) / 1e9
             kernels[FAMILY[fam]] = {"launches_sampled": launches[fam], "avg_us": round(avg_ms * 1e3, 3),
                                     "items_per_launch": round(per_launch_items, 1),
+                                    "bytes_per_projection": round(fam_bytes(fam), 1),
                                     "alg_GBps": round(gbs, 1),
                                     "share_of_sampled_ms": None}
     tot = sum(ms)

@@ -443,7 +443,7 @@ def _group_sets(typed, sel_of, V):
     return out_t, out_i
 
 
-def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0, 1, 2)) -> Scene:
+def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0, 1, 2), merge=(1, 1)) -> Scene:
     """Three-group tiled schedule for an nr x nc grid cloth.
 
     Group A: constraints inside one tile x tile tile (patch = tile).
@@ -455,8 +455,11 @@ def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0,
     set (patch = the tile of the half-shifted tiling around that corner).
     Every constraint is in exactly one group; an iteration runs A, B, C.
     ``lds_groups`` selects which of A, B, C (0, 1, 2) are offered to the
-    library as LDS groups; the others run as ordinary sets.  The schedule
-    (and so every result) is the same either way.
+    library as LDS groups; the others run as ordinary sets.  ``merge`` = (mB,
+    mC) joins runs of mB consecutive border segments and mC corner clusters
+    into one patch (still vertex-disjoint), so one workgroup serves several
+    of these small patches.  The schedule (and so every result) is the same
+    either way.
     """
     dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
     assert np.array_equal(dist_v, sc.dist_v)
@@ -486,7 +489,7 @@ def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0,
         touches_corner = np.any(corner[cv], axis=1)
         sel[ty] = (in_a, ~in_a & ~touches_corner, ~in_a & touches_corner)
     sets_t, sets_i, groups = [], [], []
-    for g, pm in enumerate((tile_id, seg_id, corner_tile)):
+    for g, pm in enumerate((tile_id, seg_id // max(1, merge[0]), corner_tile // max(1, merge[1]))):
         first = len(sets_t)
         st, si = _group_sets(typed, {ty: sel[ty][g] for ty, _, _ in typed}, V)
         sets_t += st
@@ -627,6 +630,37 @@ def config_c2(n_frames: int = 30, target: bool = False, n: int = 256, tile: int 
     return sc
 
 
+def config_c2_membrane(n_frames: int = 30, target: bool = False, n: int = 256) -> Scene:
+    """The 256x256 cloth with orthotropic StVK membrane triangles in place of
+    the distance constraints (Sec. 5.1's cloth model), dihedral bending and
+    the sphere; per-triangle coefficients (C00, C01, C11, C22) =
+    (4e3, 6e2, 2e3, 8e2) N/m x U[0.7, 1.3] (seed 1, seed 2 for the target);
+    8 membrane sets, 12 bending sets, 1 contact set per iteration."""
+    sc = membrane_cloth(n=n, frames=n_frames, substeps=4, iterations=30, sphere=True, pinned=(),
+                        seed=2 if target else 1)
+    sc.sphere = (0.0, -0.35, 0.0, 0.3)
+    sc.contact_thickness, sc.contact_compliance = 0.005, 1e-9
+    sc.name = f"cloth{n}_membrane_bend_sphere"
+    return sc
+
+
+def config_c2_body(n_frames: int = 30, target: bool = False, n: int = 256, body_res=(64, 128)) -> Scene:
+    """The 256x256 cloth (distance + bending) falling onto a body collider
+    given as a triangle mesh: a UV sphere of 64 x 128 (16,128 triangles)
+    standing where the sphere collider is, tau 0.005, alpha 1e-9, search
+    radius 0.02; one body-contact set of every vertex."""
+    sc = config_c2(n_frames=n_frames, target=target, n=n, tile=0)
+    sc.contact = False
+    keep = [(t, it) for t, it in zip(sc.set_type, sc.set_items) if t != CONTACT]
+    sc.set_type = [t for t, _ in keep] + [BODY]
+    sc.set_items = [it for _, it in keep] + [np.nonzero(sc.inv_mass > 0)[0].astype(np.int32)]
+    bx, bt = uv_sphere((0.0, -0.35, 0.0), 0.3, *body_res)
+    sc.body_x, sc.body_tris = bx, bt
+    sc.body_thickness, sc.body_compliance, sc.body_radius = 0.005, 1e-9, 0.02
+    sc.name = f"cloth{n}_dist_bend_body{len(bt)}"
+    return sc
+
+
 def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int = 0) -> Scene:
     """64^3-cube tet box (5 tets per cube), bottom pinned, Neo-Hookean,
     dt 1/60, 2 substeps, 20 iterations.  tile > 0: tiled schedule (8 shifted
@@ -644,18 +678,19 @@ def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int =
     return sc
 
 
-def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 0,
-              tiling: str = "lines", lds_groups=(0,)) -> Scene:
+def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 32,
+              tiling: str = "lines", lds_groups=(0, 1, 2), merge=(1, 1)) -> Scene:
     """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
     distance + bending, per-frame per-vertex force controls, dt 1/60,
-    2 substeps, 20 iterations.  tile > 0: tiled schedule (as config_c2);
-    only the tile-interior group is offered as an LDS group by default (the
-    border and corner groups hold ~12% of the constraints in many tiny
-    patches, which run faster as ordinary sets)."""
+    2 substeps, 20 iterations.  tile > 0: three-group tiled schedule (tile
+    interiors, border segments, corners) with the groups in ``lds_groups``
+    offered as LDS groups; 0: the dense 6 + 12 set schedule.  32 x 32 tiles
+    with all three groups in LDS measured fastest on MI355X (with records
+    streamed from global memory and 128-thread workgroups)."""
     sc = cloth_grid(nr, nc, 1.0 / (nc - 1), pinned=(0, nc - 1))
     if tile:
         if tiling == "lines":
-            tile_cloth_lines(sc, nr, nc, tile, lds_groups=lds_groups)
+            tile_cloth_lines(sc, nr, nc, tile, lds_groups=lds_groups, merge=merge)
         else:
             tile_cloth(sc, nr, nc, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)
