@@ -369,7 +369,7 @@ def main():
     ap.add_argument("--packs", type=int, default=4, help="packs, one stream each (c5)")
     ap.add_argument("--frames", type=int, default=0, help="override frame count (0 = the workload's)")
     ap.add_argument("--profile-stride", type=int, default=7,
-                    help="bracket every n-th projection launch with HIP events (0 = off)")
+                    help="bracket one in n projection launches (hash-picked) with HIP events (0 = off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto", choices=["auto", "plain", "persistent"])
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0 = auto)")
@@ -507,6 +507,7 @@ def main():
 
     plain = None
     if args.plain_steps > 0 and (info["persistent"] or info["n_groups_lds"]):
+        sim.close()          # its record of the last frames would crowd the plain run's memory
         psim = Simulator(sc, dtype=dtype, device=dev, launch_mode=1, use_groups=False)
         step(psim)
         torch.cuda.synchronize()

@@ -179,7 +179,12 @@ typedef struct {
                                   the whole frame;
                                 2 recompute one substep at a time (least memory);
                                 3 record the whole rollout during the forward (needs
-                                  XPBD_FWD_FOR_ADJOINT; XPBD_ERR_OOM if it does not fit) */
+                                  XPBD_FWD_FOR_ADJOINT; XPBD_ERR_OOM if it does not fit);
+                                4 the forward flagged XPBD_FWD_FOR_ADJOINT records the
+                                  last frames, as many as fit (at most record_frames),
+                                  the adjoint recomputes the others per frame.
+                                Mode 0 falls back from the whole rollout to mode 4's
+                                split, then to per-frame recomputation. */
   int32_t launch_mode;       /* 0 auto, 1 one kernel launch per independent set,
                                 2 persistent: one cooperative launch runs a whole frame's
                                   sets with a grid-wide barrier between sets */
@@ -193,6 +198,8 @@ typedef struct {
                                 patches per CU); results do not depend on it */
   int32_t group_block;       /* workgroup size of the LDS group kernels, a power of two in
                                 [64, 256], 0 = 256 */
+  int32_t record_frames;     /* tape_mode 4: most final frames the forward records, 0 = as
+                                many as fit */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral
@@ -234,7 +241,7 @@ typedef struct {
  * (device [F][V][3], may be NULL) and the final state to x_final, v_final
  * (device [V][3], may be NULL).  Keeps per-frame checkpoints for
  * xpbd_adjoint; with flags & XPBD_FWD_FOR_ADJOINT it may also keep the
- * record of every projection's inputs (tape_mode 0 or 3) so that the
+ * record of every projection's inputs (tape_mode 0, 3 or 4) so that the
  * adjoint needs no recomputation.  Errors: XPBD_ERR_INVALID, XPBD_ERR_OOM,
  * XPBD_ERR_NONFINITE, XPBD_ERR_HIP. */
 #define XPBD_FWD_FOR_ADJOINT 1
@@ -331,7 +338,8 @@ typedef struct {
   int64_t projections_per_iteration;   /* tets count D and H; contacts counted as evaluated */
   int64_t device_bytes;                /* device memory held by the context now */
   int64_t tape_bytes_per_iteration;    /* record of projection inputs, one iteration */
-  int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep, 3 forward record) */
+  int32_t tape_mode;                   /* mode the last adjoint used (1 frame, 2 substep, 3 forward
+                                          record, 4 forward record of the last frames) */
   int32_t persistent;                  /* 1 if frames run as persistent launches */
   int32_t persistent_blocks;           /* their workgroup count (0 before the first) */
   int32_t n_groups;                    /* LDS groups given */
@@ -343,10 +351,11 @@ typedef struct {
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 
-/* Kernel timing for measurement: with on = n > 0, every n-th launch of the
- * projection and reverse kernels (plain mode) or of the per-frame
- * persistent kernels is bracketed by HIP events on the call's stream (0 =
- * off).  xpbd_profile_read synchronises them and returns, per kernel family
+/* Kernel timing for measurement: with on = n > 0, one in n launches of the
+ * projection and reverse kernels (plain mode, LDS groups) or of the
+ * per-frame persistent kernels, picked by a hash of the launch count (so no
+ * launch pattern aliases with n), is bracketed by HIP events on the call's
+ * stream (0 = off).  xpbd_profile_read synchronises them and returns, per kernel family
  * (index 2 * type: forward projections of that type, 2 * type + 1: their
  * reverse, with body contacts counted with the sphere's at 6 and 7; 8:
  * persistent forward frame, 9: persistent reverse frame,

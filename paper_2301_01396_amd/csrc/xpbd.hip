@@ -190,6 +190,8 @@ struct xpbd_ctx_s {
   // forward bookkeeping for the adjoint
   bool have_forward = false;
   bool fwd_recorded = false;
+  int fwd_rec_from = 0;          // first frame whose record the forward kept (frames >= it)
+  int record_frames_opt = 0;     // tape_mode 4: most final frames the forward records (0 = all that fit)
   int fwd_frames = 0;
   xpbd_params fwd_params{};
 
@@ -293,7 +295,11 @@ template <class T> std::vector<T> cast_vec(const std::vector<double>& v) {
 void prof_begin(xpbd_ctx c, hipStream_t st, int fam, int64_t items, xpbd_ctx_s::Ev* out, bool* on) {
   *on = false;
   if (!c->prof_stride) return;
-  if ((c->prof_counter++ % c->prof_stride) != 0) return;
+  // sample one launch in prof_stride, chosen by a hash of the launch count
+  // rather than every n-th, so launch sequences whose period shares a factor
+  // with the stride (e.g. 21 sets per iteration, stride 7) are not aliased
+  const uint64_t k = (uint64_t)(c->prof_counter++) * 0x9E3779B97F4A7C15ull;
+  if (((k >> 32) % (uint64_t)c->prof_stride) != 0) return;
   hipEvent_t a, b;
   if (!c->ev_free.empty()) {
     a = c->ev_free.back().first;
@@ -776,7 +782,7 @@ template <class T> struct Ops {
     if (c->n_bend)
       k_gather_alpha<T><<<nblocks(c->n_bend), kBlock, 0, st>>>((const T*)p->bend_compliance, c->bend_perm,
                                                                (T*)c->bend_at, (T)ih2, c->n_bend, c->flag);
-    if (c->n_tet)
+    if (c->n_tet) {
       if (p->tet_mu)
         k_gather_tet_lame<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_mu, (const T*)p->tet_lambda,
                                                                    c->tet_pidx, c->tet_vol, (T*)c->tet_atD,
@@ -786,6 +792,7 @@ template <class T> struct Ops {
         k_gather_tet<T><<<nblocks(c->n_tet), kBlock, 0, st>>>((const T*)p->tet_E, c->tet_pidx, c->tet_nu,
                                                             c->tet_vol, (T*)c->tet_atD, (T*)c->tet_atH,
                                                             (T*)c->tet_gamma, ih2, c->gamma_one, c->n_tet, c->flag);
+    }
     if (c->n_tri)
       k_gather_tri<T><<<nblocks(c->n_tri), kBlock, 0, st>>>((const T*)p->tri_coef, c->tri_perm, c->tri_area,
                                                             (T*)c->tri_at, ih2, c->n_tri, c->flag);
@@ -806,8 +813,9 @@ template <class T> struct Ops {
       if (!std::isfinite(p->sphere[a])) fail(XPBD_ERR_NONFINITE, "sphere parameter %d is not finite", a);
   }
 
+  // frames f >= rec_from keep their record in slot (f - rec_from) (rec_from = F: none)
   static void forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_params* p, int F, void* xf,
-                      void* x_final, void* v_final, bool record, hipStream_t st) {
+                      void* x_final, void* v_final, int rec_from, hipStream_t st) {
     const int V = c->V;
     const size_t vb = (size_t)V * sizeof(V4);
     ensure_checkpoints(c, F);
@@ -821,11 +829,13 @@ template <class T> struct Ops {
       HIPCHK(hipMemcpyAsync((char*)c->ckX + f * vb, c->X, vb, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync((char*)c->ckV + f * vb, c->Vv, vb, hipMemcpyDeviceToDevice, st));
       const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
+      const bool record = f >= rec_from;
+      const int fr = f - rec_from;
       if (c->persistent) {
-        run_program(c, D, false, record ? (char*)c->tape + (size_t)f * frame_tape : nullptr, ff, nullptr, nullptr,
+        run_program(c, D, false, record ? (char*)c->tape + (size_t)fr * frame_tape : nullptr, ff, nullptr, nullptr,
                     record, st);
       } else {
-        for (int s = 0; s < c->S; ++s) substep(c, D, ff, record ? f * c->S + s : -1, st, f * c->S + s);
+        for (int s = 0; s < c->S; ++s) substep(c, D, ff, record ? fr * c->S + s : -1, st, f * c->S + s);
       }
       if (xf) {
         k_unpack<T><<<nblocks(V), kBlock, 0, st>>>((const V4*)c->X, (T*)xf + (size_t)f * 3 * V, V);
@@ -843,8 +853,10 @@ template <class T> struct Ops {
     HIPCHK(hipMemcpyAsync(c->Vv, (char*)c->ckV + f * vb, vb, hipMemcpyDeviceToDevice, st));
   }
 
+  // frames f >= rec_from use the record the forward kept (slot f - rec_from);
+  // the others are recomputed per frame (mode 1) or per substep (mode 2)
   static void adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx, const uint8_t* mask, const void* dLdv,
-                      const xpbd_grads* out, int mode, hipStream_t st) {
+                      const xpbd_grads* out, int mode, int rec_from, hipStream_t st) {
     const int V = c->V, F = c->fwd_frames, S = c->S;
     // parameters used by the recomputation (same as the forward's)
     gather_params(c, p, st);
@@ -859,9 +871,10 @@ template <class T> struct Ops {
       }
       const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
       T* fb = out->f_ext ? (T*)out->f_ext + (size_t)f * 3 * V : nullptr;
-      if (mode == 3 || mode == 1) {
-        char* base = mode == 3 ? (char*)c->tape + (size_t)f * frame_tape : (char*)c->tape;
-        if (mode == 1) {
+      const bool kept = f >= rec_from;
+      if (kept || mode == 1) {
+        char* base = kept ? (char*)c->tape + (size_t)(f - rec_from) * frame_tape : (char*)c->tape;
+        if (!kept) {
           restore(c, f, st);
           if (c->persistent) run_program(c, D, false, base, ff, nullptr, nullptr, true, st);
           else for (int s = 0; s < S; ++s) substep(c, D, ff, s, st, f * S + s);
@@ -869,7 +882,7 @@ template <class T> struct Ops {
         if (c->persistent) {
           run_program(c, D, true, base, nullptr, fb, out->sphere, false, st);
         } else {
-          int slot0 = mode == 3 ? f * S : 0;
+          int slot0 = kept ? (f - rec_from) * S : 0;
           for (int s = S - 1; s >= 0; --s) reverse_substep(c, D, fb, out->sphere, slot0 + s, st, f * S + s);
         }
       } else {
@@ -978,7 +991,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   if (cd->n_dist < 0 || cd->n_bend < 0 || cd->n_tet < 0) fail(XPBD_ERR_INVALID, "negative counts");
   if ((cd->n_dist && !cd->dist_v) || (cd->n_bend && !cd->bend_v) || (cd->n_tet && (!cd->tet_v || !cd->tet_nu)))
     fail(XPBD_ERR_INVALID, "missing constraint arrays");
-  if (o->tape_mode < 0 || o->tape_mode > 3) fail(XPBD_ERR_INVALID, "bad tape_mode");
+  if (o->tape_mode < 0 || o->tape_mode > 4) fail(XPBD_ERR_INVALID, "bad tape_mode");
+  if (o->record_frames < 0) fail(XPBD_ERR_INVALID, "bad record_frames");
   if (o->launch_mode < 0 || o->launch_mode > 2 || o->persistent_blocks < 0)
     fail(XPBD_ERR_INVALID, "bad launch_mode / persistent_blocks");
   if (o->block_size != 0 &&
@@ -1004,6 +1018,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   c->budget = o->hbm_budget_bytes;
   c->gamma_one = o->tet_gamma_one ? 1 : 0;
   c->tape_mode_opt = o->tape_mode;
+  c->record_frames_opt = o->record_frames;
   c->tau = cd->contact_thickness;
   c->alpha_c = cd->contact_compliance;
   const int V = c->V;
@@ -1628,7 +1643,7 @@ bool fits_on_device(xpbd_ctx c, size_t bytes) {
   if (c->budget) return c->dev_bytes + extra + work <= c->budget;
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
-  const size_t margin = (size_t)4 << 30;
+  const size_t margin = (size_t)8 << 30;   // torch-side tensors of the call (gradients) come on top
   return extra + work + margin <= fr;
 }
 
@@ -1704,22 +1719,33 @@ xpbd_status xpbd_forward(xpbd_ctx c, const void* x0, const void* v0, const xpbd_
     if (flags & ~XPBD_FWD_FOR_ADJOINT) fail(XPBD_ERR_INVALID, "forward: unknown flags");
     c->have_forward = false;
     c->fwd_recorded = false;
-    bool record = false;
-    if ((flags & XPBD_FWD_FOR_ADJOINT) && (c->tape_mode_opt == 0 || c->tape_mode_opt == 3)) {
-      size_t need = (size_t)n_frames * c->S * c->K * c->iter_tape_bytes;
-      bool fits = fits_on_device(c, need);
-      if (c->tape_mode_opt == 3 && !fits)
-        fail(XPBD_ERR_OOM, "forward: the record of the whole rollout (%zu bytes) does not fit", need);
-      record = fits;
-      if (record) ensure_adjoint_buffers(c, n_frames * c->S);
-    } else if (c->tape_mode_opt == 3) {
+    // how many final frames keep their record: all (whole rollout) if it
+    // fits; with tape_mode 0 or 4 otherwise as many as fit (tape_mode 4: at
+    // most record_frames), the rest recomputed by the adjoint
+    int kept = 0;
+    const size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
+    const int m = c->tape_mode_opt;
+    if ((flags & XPBD_FWD_FOR_ADJOINT) && (m == 0 || m == 3 || m == 4)) {
+      int cap = n_frames;
+      if (m == 4 && c->record_frames_opt > 0) cap = std::min(cap, c->record_frames_opt);
+      if (fits_on_device(c, (size_t)cap * frame_tape)) kept = cap;
+      if (m == 3 && kept < n_frames)
+        fail(XPBD_ERR_OOM, "forward: the record of the whole rollout (%zu bytes) does not fit",
+             (size_t)n_frames * frame_tape);
+      if (m != 3)
+        for (int r = cap - 1; kept == 0 && r >= 1; --r)
+          if (fits_on_device(c, (size_t)r * frame_tape)) kept = r;
+      if (kept) ensure_adjoint_buffers(c, kept * c->S);
+    } else if (m == 3) {
       fail(XPBD_ERR_INVALID, "forward: tape_mode 3 needs XPBD_FWD_FOR_ADJOINT");
     }
+    const int rec_from = n_frames - kept;
     hipStream_t st = (hipStream_t)stream;
-    if (c->dtype == XPBD_F32) Ops<float>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, record, st);
-    else Ops<double>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, record, st);
+    if (c->dtype == XPBD_F32) Ops<float>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, rec_from, st);
+    else Ops<double>::forward(c, x0, v0, p, n_frames, x_frames, x_final, v_final, rec_from, st);
     c->have_forward = true;
-    c->fwd_recorded = record;
+    c->fwd_recorded = kept > 0;
+    c->fwd_rec_from = rec_from;
     c->fwd_frames = n_frames;
     c->fwd_params = *p;
   });
@@ -1738,20 +1764,25 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
         q.tet_mu != p->tet_mu || q.tet_lambda != p->tet_lambda || q.tri_coef != p->tri_coef ||
         q.body_x != p->body_x)
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
-    int mode = c->tape_mode_opt;
-    if (c->fwd_recorded) {
-      mode = 3;
-    } else if (mode == 0 || mode == 3) {
-      // whole-frame record if it fits, else one substep at a time
+    const int F = c->fwd_frames;
+    const int rec_from = c->fwd_recorded ? c->fwd_rec_from : F;
+    // frames without a kept record: recomputed per frame if a frame's record
+    // fits (the kept frames' slots are reused once consumed), else per substep
+    int mode = c->tape_mode_opt == 1 || c->tape_mode_opt == 2 ? c->tape_mode_opt : 1;
+    if (rec_from > 0 && mode == 1 && rec_from == F) {
       size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
-      mode = fits_on_device(c, frame_tape) ? 1 : 2;
+      if (c->tape_mode_opt != 1 && !fits_on_device(c, frame_tape)) mode = 2;
     }
-    ensure_adjoint_buffers(c, mode == 3 ? c->fwd_frames * c->S : mode == 1 ? c->S : 1);
-    c->tape_mode_used = mode;
-    if (mode == 3) c->fwd_recorded = false;   // the record is consumed by this adjoint
+    if (rec_from > 0 && rec_from < F) mode = 1;   // the kept slots hold at least one frame
+    const int kept_slots = (F - rec_from) * c->S;
+    ensure_adjoint_buffers(c, std::max(kept_slots, rec_from > 0 ? (mode == 1 ? c->S : 1) : 0));
+    c->tape_mode_used = rec_from == 0 ? 3 : rec_from < F ? 4 : mode;
+    c->fwd_recorded = false;   // a kept record is consumed by this adjoint
     hipStream_t st = (hipStream_t)stream;
-    if (c->dtype == XPBD_F32) Ops<float>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
-    else Ops<double>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, st);
+    if (c->dtype == XPBD_F32)
+      Ops<float>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, rec_from, st);
+    else
+      Ops<double>::adjoint(c, p, dLdx_frames, frame_mask, dLdv_final, out, mode, rec_from, st);
   });
 }
 

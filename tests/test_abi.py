@@ -56,6 +56,7 @@ def _create(sc, **opt):
     o.dtype = opt.get("dtype", 0)
     o.tape_mode = opt.get("tape_mode", 0)
     o.block_size = opt.get("block_size", 0)
+    o.record_frames = opt.get("record_frames", 0)
     ctx = C.c_void_p()
     rc = lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(ctx))
     msg = lib.xpbd_last_error(None).decode()
@@ -105,7 +106,8 @@ def test_rejects_contact_on_pinned_vertex_and_bad_options():
     assert _create(sc, substeps=0)[0] == L.XPBD_ERR_INVALID
     assert _create(sc, dt=-1.0)[0] == L.XPBD_ERR_INVALID
     assert _create(sc, dtype=7)[0] == L.XPBD_ERR_INVALID
-    assert _create(sc, tape_mode=4)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, tape_mode=5)[0] == L.XPBD_ERR_INVALID
+    assert _create(sc, record_frames=-1)[0] == L.XPBD_ERR_INVALID
 
 
 def test_null_context_calls_fail_cleanly():

@@ -103,12 +103,13 @@ def test_bitwise_determinism_and_tape_modes():
     ref = reference_case(sc, 3, n_threads=8)
     outs = []
     infos = []
-    for mode in (1, 1, 2, 3, 0):
-        sim = _sim(sc, "f32", tape_mode=mode)
+    for mode, kw in ((1, {}), (1, {}), (2, {}), (3, {}), (0, {}), (4, {"record_frames": 1}),
+                     (4, {"record_frames": 2})):
+        sim = _sim(sc, "f32", tape_mode=mode, **kw)
         got = gpu_case(sim, 3, ref)
         outs.append(got)
         infos.append(sim.info()["tape_mode"])
-    assert infos == [1, 1, 2, 3, 3]
+    assert infos == [1, 1, 2, 3, 3, 4, 4]
     for o in outs[1:]:
         assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
         for k, v in outs[0]["grads"].items():
