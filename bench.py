@@ -500,10 +500,11 @@ def main():
     grads_finite = all(bool(torch.isfinite(t.grad).all()) for t in leaves)
     info = sim.info()
     log(f"timed {args.steps} steps: {elapsed / args.steps * 1e3:.1f} ms/step, info {info}")
-    # share of forward launches that write the record: all of them when the
-    # forward keeps the whole rollout's record, half when every frame is
-    # recomputed once by the adjoint
-    recording = {3: 1.0, 1: 0.5}.get(info["tape_mode"], 0.0)
+    # share of forward launches that write the record: every frame is recorded
+    # once, by the forward (its last forward_record_frames frames) or by the
+    # adjoint's recomputation (the others, which run the forward twice)
+    kept = info["forward_record_frames"] if info["tape_mode"] in (3, 4) else 0
+    recording = F / (F + (F - kept)) if info["tape_mode"] in (1, 3, 4) else 0.0
 
     plain = None
     if args.plain_steps > 0 and (info["persistent"] or info["n_groups_lds"]):

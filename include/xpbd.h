@@ -348,6 +348,7 @@ typedef struct {
   int32_t n_materials;                 /* material clusters, 0 = per-tet parameters */
   int32_t n_tri;                       /* membrane triangles */
   int32_t n_body_contacts;             /* body-contact items */
+  int32_t forward_record_frames;       /* final frames whose record the last forward kept */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 

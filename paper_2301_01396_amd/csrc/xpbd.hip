@@ -1774,8 +1774,11 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
       if (c->tape_mode_opt != 1 && !fits_on_device(c, frame_tape)) mode = 2;
     }
     if (rec_from > 0 && rec_from < F) mode = 1;   // the kept slots hold at least one frame
-    const int kept_slots = (F - rec_from) * c->S;
-    ensure_adjoint_buffers(c, std::max(kept_slots, rec_from > 0 ? (mode == 1 ? c->S : 1) : 0));
+    // record slots: the kept frames', and one frame (mode 1) or one substep
+    // (mode 2) for the recomputed frames
+    int slots = (F - rec_from) * c->S;
+    if (rec_from > 0) slots = std::max(slots, mode == 1 ? c->S : 1);
+    ensure_adjoint_buffers(c, slots);
     c->tape_mode_used = rec_from == 0 ? 3 : rec_from < F ? 4 : mode;
     c->fwd_recorded = false;   // a kept record is consumed by this adjoint
     hipStream_t st = (hipStream_t)stream;
@@ -1827,6 +1830,7 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->n_materials = c->n_mat;
   info->n_tri = c->n_tri;
   info->n_body_contacts = c->n_bc;
+  info->forward_record_frames = c->have_forward ? c->fwd_frames - c->fwd_rec_from : 0;
   return XPBD_OK;
 }
 
