@@ -62,10 +62,14 @@ def alg_bytes(fam: int, tsz: int, recording: float = 0.0) -> float:
     return ib + words * tsz
 
 
-# LDS group kernels: words of the record image read and written per
-# projection (forward: rest/theta0, at, lambda + packed slots; reverse adds
-# lambda_bar and the compliance adjoint), plus the record of inputs
-GROUP_REC_WORDS = {0: (4, 5), 2: (5, 6), 4: (8, 8.5), 6: (2, 8)}
+# LDS group kernels: words moved per projection for the constraint's entry
+# (constant part read: rest/theta0, at, packed vertex slots; tets B, two
+# compliances, gamma) and its state (read and written: forward lambda;
+# reverse lambda_bar and the compliance adjoint, tets five words per pair,
+# contacts the sphere adjoint and lambda_bar), forward and reverse; the
+# record of inputs is added separately.  The first iteration's launches do
+# not read the state; the model counts it anyway (1 launch in K).
+GROUP_REC_WORDS = {0: (5, 7), 2: (6, 8), 4: (9, 12), 6: (3, 11)}
 
 
 def group_vertices(sc) -> int:
@@ -90,15 +94,16 @@ def group_vertices(sc) -> int:
 
 def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: int) -> float:
     """Average algorithmic bytes per projection of the LDS group launches of
-    one iteration: record image read + write, record of inputs (written by
-    the forward launches that record, read by the reverse), and the staged
-    vertices of every group read and written once per launch."""
+    one iteration: constant entries read, state read and written, record of
+    inputs (written by the forward launches that record, read by the
+    reverse), and the staged vertices of every group read and written once
+    per launch."""
     n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
          6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
     tot = max(sum(n.values()), 1)
     b = 0.0
     for f, cnt in n.items():
-        words = 2 * GROUP_REC_WORDS[f][1 if reverse else 0]
+        words = GROUP_REC_WORDS[f][1 if reverse else 0]
         words += TAPE_WORDS[f] * (1.0 if reverse else float(recording))
         b += cnt * words * tsz
     b += staged_vertices * 2 * 4 * tsz
@@ -401,7 +406,7 @@ def main():
         if getattr(args, k) == 0:
             setattr(args, k, v)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "one GPU per process: the path and its measurement run on a single GPU, --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     import torch

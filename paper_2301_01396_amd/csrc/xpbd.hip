@@ -152,19 +152,20 @@ struct xpbd_ctx_s {
     int a, b;                 // sets [a, b)
     bool lds = false;         // run as one launch per iteration
     int P = 0;
-    size_t smem_fwd = 0, smem_rev = 0;   // vertex tile + record image (+ record of inputs)
-    size_t smem_tile = 0;                 // vertex tile only (records streamed)
+    size_t smem_fwd = 0, smem_rev = 0;   // vertex tile + constant entries + state (+ record of inputs)
+    size_t smem_tile = 0;                 // vertex tile only (entries and state streamed)
     int64_t items = 0;        // projections per iteration inside the group
     int* pv_start = nullptr; int* pv = nullptr; int* cnt = nullptr; int* set_type = nullptr;
-    long long* fimg = nullptr; long long* rimg = nullptr; long long* tpos = nullptr; int* rec_first = nullptr;
+    long long* img = nullptr; long long* fmul = nullptr; long long* rmul = nullptr;   // per patch offsets
+    long long* tpos = nullptr; int* rec_first = nullptr;
     long long tape_off = 0;   // inside one iteration's record
     size_t tape_bytes = 0;
   };
   std::vector<Group> groups;
   std::vector<int> group_at_start, group_at_end;   // per set: group starting / ending there, -1 none
-  char* fimg = nullptr; char* rimg = nullptr;            // group record images
-  long long* fpos[3] = {nullptr, nullptr, nullptr};     // per dist / bend / tet: record offset in fimg, -1 none
-  long long* rpos[3] = {nullptr, nullptr, nullptr};
+  char* gimg = nullptr;                                 // group constant entries
+  char* gfmul = nullptr; char* grmul = nullptr;         // group forward multipliers, reverse state
+  long long* gpos[3] = {nullptr, nullptr, nullptr};     // per dist / bend / tet: entry offset in gimg, -1 none
   size_t lds_limit = 65536;
   int max_group_lds = 0;
 
@@ -454,7 +455,7 @@ template <class T> struct Ops {
   static GroupDev group_dev(const xpbd_ctx_s::Group& g) {
     GroupDev G;
     G.pv_start = g.pv_start; G.pv = g.pv; G.cnt = g.cnt; G.set_type = g.set_type;
-    G.fimg = g.fimg; G.rimg = g.rimg; G.tpos = g.tpos; G.rec_first = g.rec_first;
+    G.img = g.img; G.fmul = g.fmul; G.rmul = g.rmul; G.tpos = g.tpos; G.rec_first = g.rec_first;
     G.nset = g.b - g.a;
     G.P = g.P;
     G.tape_off = g.tape_off;
@@ -473,8 +474,8 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_fwd : g.smem_tile;
 #define XPBD_GF(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl) k_group_fwd<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->fimg, tape_iter);           \
-    else k_group_fwd<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->fimg, tape_iter);             \
+    if (rl) k_group_fwd<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
+    else k_group_fwd<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);   \
   } while (0)
     if (first) {
       if (tape_iter) XPBD_GF(true, true);
@@ -500,8 +501,8 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_rev : g.smem_tile;
 #define XPBD_GR(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl) k_group_rev<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->rimg, tape_iter);           \
-    else k_group_rev<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->rimg, tape_iter);             \
+    if (rl) k_group_rev<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
+    else k_group_rev<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
   } while (0)
     if (first) {
       if (last) XPBD_GR(true, true);
@@ -516,15 +517,15 @@ template <class T> struct Ops {
   }
 
   static void group_fill(xpbd_ctx c, hipStream_t st) {
-    if (!c->fimg) return;
-    if (c->n_dist && c->fpos[0])
-      k_group_fill<T><<<nblocks(c->n_dist), kBlock, 0, st>>>(0, c->n_dist, c->fpos[0], c->rpos[0], c->fimg, c->rimg,
+    if (!c->gimg) return;
+    if (c->n_dist && c->gpos[0])
+      k_group_fill<T><<<nblocks(c->n_dist), kBlock, 0, st>>>(0, c->n_dist, c->gpos[0], c->gimg,
                                                              (const T*)c->dist_at, nullptr, nullptr);
-    if (c->n_bend && c->fpos[1])
-      k_group_fill<T><<<nblocks(c->n_bend), kBlock, 0, st>>>(1, c->n_bend, c->fpos[1], c->rpos[1], c->fimg, c->rimg,
+    if (c->n_bend && c->gpos[1])
+      k_group_fill<T><<<nblocks(c->n_bend), kBlock, 0, st>>>(1, c->n_bend, c->gpos[1], c->gimg,
                                                              (const T*)c->bend_at, nullptr, nullptr);
-    if (c->n_tet && c->fpos[2])
-      k_group_fill<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(2, c->n_tet, c->fpos[2], c->rpos[2], c->fimg, c->rimg,
+    if (c->n_tet && c->gpos[2])
+      k_group_fill<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(2, c->n_tet, c->gpos[2], c->gimg,
                                                             (const T*)c->tet_atD, (const T*)c->tet_atH,
                                                             (const T*)c->tet_gamma);
     check_launch();
@@ -1390,9 +1391,10 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
     }
   };
   const int ntype[3] = {c->n_dist, c->n_bend, c->n_tet};
-  std::vector<long long> fpos[3], rpos[3];
-  for (int t = 0; t < 3; ++t) { fpos[t].assign(ntype[t], -1); rpos[t].assign(ntype[t], -1); }
-  std::vector<unsigned char> fimg, rimg;
+  std::vector<long long> gpos[3];
+  for (int t = 0; t < 3; ++t) gpos[t].assign(ntype[t], -1);
+  std::vector<unsigned char> img;          // constant entries of every LDS group
+  size_t fmul_total = 0, rmul_total = 0;   // bytes of the two state images
   std::vector<int> lidx(V, -1);
   std::vector<char> ref(V, 0);
   for (int g = 0; g < sd->n_groups; ++g) {
@@ -1450,23 +1452,25 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
       }
     }
     // sizes per patch
-    std::vector<long long> foff(P), roff(P), tpos(P);
-    size_t mf = 0, mr = 0, fsum = 0, rsum = 0, tsum = 0;
+    std::vector<long long> ioff(P), fmoff(P), rmoff(P), tpos(P);
+    size_t mf = 0, mr = 0, isum = 0, fmsum = 0, rmsum = 0, tsum = 0;
     for (int p = 0; p < P; ++p) {
       size_t vb = al32((size_t)(pv_start[p + 1] - pv_start[p]) * sizeof(Vec4<T>));
-      size_t rf = 0, rr = 0, tb = 0;
+      size_t ib = 0, fb = 0, rb = 0, tb = 0;
       for (int q = 0; q < ns; ++q) {
         size_t n = cnt[(size_t)p * ns + q];
-        rf += al32(n * fwd_rec_bytes<T>(stype[q]));
-        rr += al32(n * rev_rec_bytes<T>(stype[q]));
+        ib += al32(n * rec_bytes<T>(stype[q]));
+        fb += al32(n * fmul_words(stype[q]) * sizeof(T));
+        rb += al32(n * rmul_words(stype[q]) * sizeof(T));
         tb += al32(n * tape_words(stype[q]) * sizeof(T));
       }
-      foff[p] = (long long)(fimg.size() + fsum);
-      roff[p] = (long long)(rimg.size() + rsum);
+      ioff[p] = (long long)(img.size() + isum);
+      fmoff[p] = (long long)(fmul_total + fmsum);
+      rmoff[p] = (long long)(rmul_total + rmsum);
       tpos[p] = (long long)tsum;
-      fsum += rf; rsum += rr; tsum += tb;
-      mf = std::max(mf, vb + rf);
-      mr = std::max(mr, vb + rr + tb);
+      isum += ib; fmsum += fb; rmsum += rb; tsum += tb;
+      mf = std::max(mf, vb + ib + fb);
+      mr = std::max(mr, vb + ib + rb + tb);
     }
     G.smem_fwd = mf;
     G.smem_rev = mr;
@@ -1474,12 +1478,12 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
     G.tape_bytes = tsum;
     G.lds = P > 0 && nv_max <= 65535 && (c->group_stream ? G.smem_tile : std::max(mf, mr)) <= c->lds_limit;
     if (G.lds) {
-      // record images in LDS layout
-      size_t fbase = fimg.size(), rbase = rimg.size();
-      fimg.resize(fbase + fsum, 0);
-      rimg.resize(rbase + rsum, 0);
+      // constant entries in LDS layout; the state images are zeroed on the device
+      img.resize(img.size() + isum, 0);
+      fmul_total += fmsum;
+      rmul_total += rmsum;
       for (int p = 0; p < P; ++p) {
-        size_t fo = (size_t)foff[p], ro = (size_t)roff[p];
+        size_t io = (size_t)ioff[p];
         for (int q = 0; q < ns; ++q) {
           const int n = cnt[(size_t)p * ns + q], ty = stype[q];
           for (int i = 0; i < n; ++i) {
@@ -1489,45 +1493,35 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
             unsigned l[4] = {0, 0, 0, 0};
             for (int k = 0; k < nv; ++k) l[k] = (unsigned)lidx[vv[k]];
             unsigned l01 = l[0] | (l[1] << 16), l23 = l[2] | (l[3] << 16);
-            unsigned char* fp = &fimg[fo + i * fwd_rec_bytes<T>(ty)];
-            unsigned char* rp = &rimg[ro + i * rev_rec_bytes<T>(ty)];
+            unsigned char* ip = &img[io + i * rec_bytes<T>(ty)];
             switch (ty) {
               case XPBD_DIST: {
-                SDist<T> f{(T)drest[j], T(0), T(0), l01};
-                RDist<T> r{(T)drest[j], T(0), T(0), T(0), l01};
-                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                SDist<T> e{(T)drest[j], T(0), l01};
+                std::memcpy(ip, &e, sizeof e);
                 break;
               }
               case XPBD_BEND: {
-                SBend<T> f{(T)btheta[j], T(0), T(0), l01, l23};
-                RBend<T> r{(T)btheta[j], T(0), T(0), T(0), l01, l23};
-                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                SBend<T> e{(T)btheta[j], T(0), l01, l23};
+                std::memcpy(ip, &e, sizeof e);
                 break;
               }
               case XPBD_TET: {
-                STet<T> f{};
-                RTet<T> r{};
-                for (int k = 0; k < 9; ++k) f.B[k] = r.B[k] = (T)tB[(size_t)k * c->n_tet + j];
-                f.l01 = r.l01 = l01;
-                f.l23 = r.l23 = l23;
-                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                STet<T> e{};
+                for (int k = 0; k < 9; ++k) e.B[k] = (T)tB[(size_t)k * c->n_tet + j];
+                e.l01 = l01;
+                e.l23 = l23;
+                std::memcpy(ip, &e, sizeof e);
                 break;
               }
               default: {
-                SCon<T> f{T(0), l[0]};
-                RCon<T> r{};
-                r.l = l[0];
-                std::memcpy(fp, &f, sizeof f); std::memcpy(rp, &r, sizeof r);
+                SCon<T> e{l[0]};
+                std::memcpy(ip, &e, sizeof e);
                 break;
               }
             }
-            if (ty != XPBD_CONTACT) {
-              fpos[ty][j] = (long long)(fo + i * fwd_rec_bytes<T>(ty));
-              rpos[ty][j] = (long long)(ro + i * rev_rec_bytes<T>(ty));
-            }
+            if (ty != XPBD_CONTACT) gpos[ty][j] = (long long)(io + i * rec_bytes<T>(ty));
           }
-          fo += al32((size_t)n * fwd_rec_bytes<T>(ty));
-          ro += al32((size_t)n * rev_rec_bytes<T>(ty));
+          io += al32((size_t)n * rec_bytes<T>(ty));
         }
       }
       c->max_group_lds = std::max(c->max_group_lds, (int)(c->group_stream ? G.smem_tile : std::max(mf, mr)));
@@ -1536,33 +1530,35 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
       G.cnt = (int*)c->alloc(cnt.size() * sizeof(int));
       G.rec_first = (int*)c->alloc(first.size() * sizeof(int));
       G.set_type = (int*)c->alloc(ns * sizeof(int));
-      G.fimg = (long long*)c->alloc(P * sizeof(long long));
-      G.rimg = (long long*)c->alloc(P * sizeof(long long));
+      G.img = (long long*)c->alloc(P * sizeof(long long));
+      G.fmul = (long long*)c->alloc(P * sizeof(long long));
+      G.rmul = (long long*)c->alloc(P * sizeof(long long));
       G.tpos = (long long*)c->alloc(P * sizeof(long long));
       c->upload(G.pv_start, pv_start);
       c->upload(G.pv, pv);
       c->upload(G.cnt, cnt);
       c->upload(G.rec_first, first);
       c->upload(G.set_type, stype);
-      c->upload(G.fimg, foff);
-      c->upload(G.rimg, roff);
+      c->upload(G.img, ioff);
+      c->upload(G.fmul, fmoff);
+      c->upload(G.rmul, rmoff);
       c->upload(G.tpos, tpos);
       c->group_at_start[G.a] = g;
       c->group_at_end[G.b - 1] = g;
     }
     c->groups.push_back(G);
   }
-  if (!fimg.empty()) {
-    c->fimg = (char*)c->alloc(fimg.size());
-    c->rimg = (char*)c->alloc(rimg.size());
-    c->upload(c->fimg, fimg);
-    c->upload(c->rimg, rimg);
+  if (!img.empty()) {
+    c->gimg = (char*)c->alloc(img.size());
+    c->upload(c->gimg, img);
+    c->gfmul = (char*)c->alloc(fmul_total);
+    c->grmul = (char*)c->alloc(rmul_total);
+    HIPCHK(hipMemset(c->gfmul, 0, fmul_total));
+    HIPCHK(hipMemset(c->grmul, 0, rmul_total));
     for (int t = 0; t < 3; ++t)
       if (ntype[t]) {
-        c->fpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
-        c->rpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
-        c->upload(c->fpos[t], fpos[t]);
-        c->upload(c->rpos[t], rpos[t]);
+        c->gpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
+        c->upload(c->gpos[t], gpos[t]);
       }
     Ops<T>::allow_lds((size_t)c->max_group_lds);
   }

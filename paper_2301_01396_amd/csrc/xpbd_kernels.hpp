@@ -1211,33 +1211,39 @@ __global__ __launch_bounds__(1024) void k_sum_parts(const double* __restrict__ p
 // vertex inside the group, so the result equals running the sets one launch
 // at a time, bit for bit.
 //
-// The records of a group live in global memory as patch-major images laid
-// out exactly like the LDS copy (set after set, each padded to 32 bytes), so
-// staging is one contiguous 16-byte copy per patch.  The forward writes the
-// adjoint's record of projection inputs in the same patch-major layout,
-// which the reverse stages the same way.
+// The constraints of a group live in global memory as patch-major images
+// laid out exactly like the LDS copy (set after set, each padded to 32
+// bytes), so staging is one contiguous 16-byte copy per patch.  Each
+// constraint has a constant entry (vertex slots in the patch's tile, rest
+// data, compliances), shared by the forward and the reverse, and mutable
+// state in two separate images of the same layout: the multipliers of the
+// forward and the reverse's multiplier and compliance adjoints, stored per
+// set as arrays of the set's items.  A launch reads the constant image and
+// writes back only the state it changes.  The forward writes the adjoint's
+// record of projection inputs in the same patch-major layout, which the
+// reverse stages the same way.
 
 constexpr int kMaxGroupSets = 64;
 
-template <class T> struct SDist { T rest, at, lam; unsigned l; };
-template <class T> struct SBend { T th0, at, lam; unsigned l01, l23; };
-template <class T> struct STet { T B[9]; T atD, atH, gam, lD, lH; unsigned l01, l23; };
-template <class T> struct SCon { T lam; unsigned l; };
-template <class T> struct RDist { T rest, at, lamb, ab; unsigned l; };
-template <class T> struct RBend { T th0, at, lamb, ab; unsigned l01, l23; };
-template <class T> struct RTet { T B[9]; T atD, atH, gam, lbD, lbH, ebD, ebH, gb; unsigned l01, l23; };
-template <class T> struct RCon { Vec4<T> sa; T lamb; unsigned l; };
+template <class T> struct SDist { T rest, at; unsigned l; };
+template <class T> struct SBend { T th0, at; unsigned l01, l23; };
+template <class T> struct STet { T B[9]; T atD, atH, gam; unsigned l01, l23; };
+template <class T> struct SCon { unsigned l; };
 
 __host__ __device__ __forceinline__ size_t al32(size_t b) { return (b + 31) & ~(size_t)31; }
 __device__ __forceinline__ int lo16(unsigned v) { return (int)(v & 0xffffu); }
 __device__ __forceinline__ int hi16(unsigned v) { return (int)(v >> 16); }
 
-template <class T> __host__ __device__ inline size_t fwd_rec_bytes(int type) {
+template <class T> __host__ __device__ inline size_t rec_bytes(int type) {
   return type == 0 ? sizeof(SDist<T>) : type == 1 ? sizeof(SBend<T>) : type == 2 ? sizeof(STet<T>) : sizeof(SCon<T>);
 }
-template <class T> __host__ __device__ inline size_t rev_rec_bytes(int type) {
-  return type == 0 ? sizeof(RDist<T>) : type == 1 ? sizeof(RBend<T>) : type == 2 ? sizeof(RTet<T>) : sizeof(RCon<T>);
-}
+// words of mutable state per item, each word an array over the set's items:
+// forward lambda (tets lambda_D, lambda_H); reverse lambda_bar and the
+// compliance adjoint (tets lambda_bar_D, lambda_bar_H, the two compliance
+// adjoints and gamma_bar; contacts the sphere adjoint, a Vec4 array, then
+// lambda_bar)
+__host__ __device__ inline size_t fmul_words(int type) { return type == 2 ? 2 : 1; }
+__host__ __device__ inline size_t rmul_words(int type) { return type <= 1 ? 2 : 5; }
 __host__ __device__ inline size_t tape_words(int type) { return type == 1 ? 10 : type == 2 ? 12 : 4; }
 
 struct GroupDev {
@@ -1245,8 +1251,9 @@ struct GroupDev {
   const int* pv;            // global vertex of each patch slot
   const int* cnt;           // [P][nset] items of each set in each patch
   const int* set_type;      // [nset]
-  const long long* fimg;    // [P] byte offset of each patch's forward record image
-  const long long* rimg;    // [P] ... reverse record image
+  const long long* img;     // [P] byte offset of each patch's constant entries
+  const long long* fmul;    // [P] ... forward multipliers
+  const long long* rmul;    // [P] ... reverse state
   const long long* tpos;    // [P] byte offset of each patch's record of inputs in the group's chunk
   const int* rec_first;     // [P][nset] internal index of the patch's first item in each set
   int nset, P;
@@ -1268,224 +1275,241 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
 }
 
-// RL: the patch's record image is staged in LDS with its vertices (one bulk
-// copy in and out); otherwise only the vertex tile is in LDS and each set's
-// records are read and written in place in the global image, which keeps
-// the workgroup's LDS small so many patches run per CU.
+// RL: the patch's constant entries and state are staged in LDS with its
+// vertices (one bulk copy in, the state copied out); otherwise only the
+// vertex tile is in LDS and each set's entries are read, and its state read
+// and written, in place in the global images, which keeps the workgroup's
+// LDS small so many patches run per CU.
 template <class T, bool FIRST, bool TAPE, bool RL>
-__global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, char* __restrict__ fimg,
-                                                      char* __restrict__ tape_iter) {
+__global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
+                                                      char* __restrict__ fmul, char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
   const int* cnt = G.cnt + (size_t)p * G.nset;
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
-  char* gimg = fimg + G.fimg[p];
-  unsigned char* rec = RL ? smem + al32((size_t)nv * sizeof(Vec4<T>)) : reinterpret_cast<unsigned char*>(gimg);
-  size_t rbytes = 0;
+  const char* gimg = img + G.img[p];
+  char* gmul = fmul + G.fmul[p];
+  unsigned char* lrec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  size_t rbytes = 0, mbytes = 0;
   if (RL)
-    for (int q = 0; q < G.nset; ++q) rbytes += al32((size_t)cnt[q] * fwd_rec_bytes<T>(G.set_type[q]));
+    for (int q = 0; q < G.nset; ++q) {
+      rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
+      mbytes += al32((size_t)cnt[q] * fmul_words(G.set_type[q]) * sizeof(T));
+    }
+  const unsigned char* r = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
+  unsigned char* m = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
   for (int i = tid; i < nv; i += kB) sX[i] = D.X[G.pv[v0 + i]];
-  if (RL) copy16(rec, gimg, rbytes);
+  if (RL) {
+    copy16(lrec, gimg, rbytes);
+    if (!FIRST) copy16(lrec + rbytes, gmul, mbytes);   // the first iteration starts from lambda = 0
+  }
   lds_barrier();
   char* gt = TAPE ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
-  unsigned char* r = rec;
   for (int q = 0; q < G.nset; ++q) {
     const int n = cnt[q], ty = G.set_type[q];
     Vec4<T>* tape = reinterpret_cast<Vec4<T>*>(gt);
+    T* lam = reinterpret_cast<T*>(m);
     switch (ty) {
       case 0:
         for (int i = tid; i < n; i += kB) {
-          SDist<T>& s = reinterpret_cast<SDist<T>*>(r)[i];
+          const SDist<T> s = reinterpret_cast<const SDist<T>*>(r)[i];
           int la = lo16(s.l), lb = hi16(s.l);
           Vec4<T> a = sX[la], bb = sX[lb];
-          T l0 = FIRST ? T(0) : s.lam;
+          T l0 = FIRST ? T(0) : lam[i];
           T ln = dist_fwd<T, TAPE>(a, bb, s.rest, s.at, l0, tape + i);
           if (ln != l0) { sX[la] = a; sX[lb] = bb; }
-          s.lam = ln;
+          lam[i] = ln;
         }
         break;
       case 1:
         for (int i = tid; i < n; i += kB) {
-          SBend<T>& s = reinterpret_cast<SBend<T>*>(r)[i];
+          const SBend<T> s = reinterpret_cast<const SBend<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
-          T l0 = FIRST ? T(0) : s.lam;
+          T l0 = FIRST ? T(0) : lam[i];
           T ln = bend_fwd<T, TAPE>(pp, s.th0, s.at, l0, tape, i, n);
           if (ln != l0) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3]; }
-          s.lam = ln;
+          lam[i] = ln;
         }
         break;
       case 2:
         for (int i = tid; i < n; i += kB) {
-          STet<T>& s = reinterpret_cast<STet<T>*>(r)[i];
+          const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
           M3<T> B;
 #pragma unroll
           for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
-          T lD = FIRST ? T(0) : s.lD, lH = FIRST ? T(0) : s.lH;
+          T lD = FIRST ? T(0) : lam[i], lH = FIRST ? T(0) : lam[n + i];
           tet_fwd<T, TAPE>(pp, B, s.atD, s.atH, s.gam, lD, lH, tape + i, n);
-          s.lD = lD; s.lH = lH;
+          lam[i] = lD; lam[n + i] = lH;
           sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3];
         }
         break;
       default:
         for (int i = tid; i < n; i += kB) {
-          SCon<T>& s = reinterpret_cast<SCon<T>*>(r)[i];
-          int l = (int)s.l;
+          const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
           Vec4<T> pp = sX[l];
-          T l0 = FIRST ? T(0) : s.lam;
+          T l0 = FIRST ? T(0) : lam[i];
           T ln = contact_fwd<T, TAPE>(pp, D.sph, l0, tape + i);
           if (ln != l0) sX[l] = pp;
-          s.lam = ln;
+          lam[i] = ln;
         }
         break;
     }
-    r += al32((size_t)n * fwd_rec_bytes<T>(ty));
+    r += al32((size_t)n * rec_bytes<T>(ty));
+    m += al32((size_t)n * fmul_words(ty) * sizeof(T));
     if (TAPE) gt += al32((size_t)n * tape_words(ty) * sizeof(T));
     lds_barrier();
   }
   for (int i = tid; i < nv; i += kB) D.X[G.pv[v0 + i]] = sX[i];
-  if (RL) copy16(gimg, rec, rbytes);
+  if (RL) copy16(gmul, lrec + rbytes, mbytes);
 }
 
 template <class T, bool FIRST, bool LAST, bool RL>
-__global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, char* __restrict__ rimg,
-                                                      const char* __restrict__ tape_iter) {
+__global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, const char* __restrict__ img,
+                                                      char* __restrict__ rmul, const char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
   const int* cnt = G.cnt + (size_t)p * G.nset;
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
-  size_t rbytes = 0, tbytes = 0;
+  size_t rbytes = 0, mbytes = 0, tbytes = 0;
   for (int q = 0; q < G.nset; ++q) {
-    rbytes += al32((size_t)cnt[q] * rev_rec_bytes<T>(G.set_type[q]));
+    rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
+    mbytes += al32((size_t)cnt[q] * rmul_words(G.set_type[q]) * sizeof(T));
     tbytes += al32((size_t)cnt[q] * tape_words(G.set_type[q]) * sizeof(T));
   }
-  char* gimg = rimg + G.rimg[p];
+  const char* gimg = img + G.img[p];
+  char* gmul = rmul + G.rmul[p];
   const char* gtap = tape_iter + G.tape_off + G.tpos[p];
-  unsigned char* rec = RL ? smem + al32((size_t)nv * sizeof(Vec4<T>)) : reinterpret_cast<unsigned char*>(gimg);
-  const unsigned char* tap = RL ? rec + rbytes : reinterpret_cast<const unsigned char*>(gtap);
+  unsigned char* lrec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  const unsigned char* rec = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
+  unsigned char* mul = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
+  const unsigned char* tap = RL ? lrec + rbytes + mbytes : reinterpret_cast<const unsigned char*>(gtap);
   for (int i = tid; i < nv; i += kB) sX[i] = D.XB[G.pv[v0 + i]];
   if (RL) {
-    copy16(rec, gimg, rbytes);
-    copy16(rec + rbytes, gtap, tbytes);
+    copy16(lrec, gimg, rbytes);
+    if (!FIRST) copy16(lrec + rbytes, gmul, mbytes);   // the last iteration's reverse starts from zero
+    copy16(lrec + rbytes + mbytes, gtap, tbytes);
   }
   lds_barrier();
   // walk the sets backwards: start past the last region
-  unsigned char* r = rec + rbytes;
+  const unsigned char* r = rec + rbytes;
+  unsigned char* m = mul + mbytes;
   const unsigned char* t = tap + tbytes;
   for (int q = G.nset - 1; q >= 0; --q) {
     const int n = cnt[q], ty = G.set_type[q];
-    r -= al32((size_t)n * rev_rec_bytes<T>(ty));
+    r -= al32((size_t)n * rec_bytes<T>(ty));
+    m -= al32((size_t)n * rmul_words(ty) * sizeof(T));
     t -= al32((size_t)n * tape_words(ty) * sizeof(T));
     const Vec4<T>* st = reinterpret_cast<const Vec4<T>*>(t);
+    T* mb = reinterpret_cast<T*>(m);
     switch (ty) {
       case 0:
         for (int i = tid; i < n; i += kB) {
-          RDist<T>& s = reinterpret_cast<RDist<T>*>(r)[i];
+          const SDist<T> s = reinterpret_cast<const SDist<T>*>(r)[i];
           int la = lo16(s.l), lb = hi16(s.l);
           Vec4<T> A = sX[la], Bv = sX[lb];
-          T lbar = FIRST ? T(0) : s.lamb, ab = FIRST ? T(0) : s.ab;
+          T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
           if (dist_rev(A, Bv, st[i], s.rest, s.at, lbar, ab)) { sX[la] = A; sX[lb] = Bv; }
-          s.lamb = lbar; s.ab = ab;
+          mb[i] = lbar; mb[n + i] = ab;
         }
         break;
       case 1:
         for (int i = tid; i < n; i += kB) {
-          RBend<T>& s = reinterpret_cast<RBend<T>*>(r)[i];
+          const SBend<T> s = reinterpret_cast<const SBend<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
-          T lbar = FIRST ? T(0) : s.lamb, ab = FIRST ? T(0) : s.ab;
+          T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
           if (bend_rev(P, st, i, n, s.th0, s.at, lbar, ab)) {
             sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
           }
-          s.lamb = lbar; s.ab = ab;
+          mb[i] = lbar; mb[n + i] = ab;
         }
         break;
       case 2:
         for (int i = tid; i < n; i += kB) {
-          RTet<T>& s = reinterpret_cast<RTet<T>*>(r)[i];
+          const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
           M3<T> B;
 #pragma unroll
           for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
-          T lbD = FIRST ? T(0) : s.lbD, lbH = FIRST ? T(0) : s.lbH;
-          T ebD = FIRST ? T(0) : s.ebD, ebH = FIRST ? T(0) : s.ebH, gb = FIRST ? T(0) : s.gb;
+          T lbD = FIRST ? T(0) : mb[i], lbH = FIRST ? T(0) : mb[n + i];
+          T ebD = FIRST ? T(0) : mb[2 * n + i], ebH = FIRST ? T(0) : mb[3 * n + i];
+          T gb = FIRST ? T(0) : mb[4 * n + i];
           if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, ebD, ebH, gb)) {
             sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
           }
-          s.lbD = lbD; s.lbH = lbH; s.ebD = ebD; s.ebH = ebH; s.gb = gb;
+          mb[i] = lbD; mb[n + i] = lbH; mb[2 * n + i] = ebD; mb[3 * n + i] = ebH; mb[4 * n + i] = gb;
         }
         break;
-      default:
+      default: {
+        Vec4<T>* sam = reinterpret_cast<Vec4<T>*>(m);
+        T* lbm = reinterpret_cast<T*>(sam + n);
         for (int i = tid; i < n; i += kB) {
-          RCon<T>& s = reinterpret_cast<RCon<T>*>(r)[i];
-          int l = (int)s.l;
+          const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
           Vec4<T> P = sX[l];
-          T lbar = FIRST ? T(0) : s.lamb;
-          Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : s.sa;
+          T lbar = FIRST ? T(0) : lbm[i];
+          Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : sam[i];
           if (contact_rev(P, st[i], D.sph, lbar, sa)) sX[l] = P;
-          s.lamb = lbar; s.sa = sa;
+          lbm[i] = lbar; sam[i] = sa;
         }
         break;
+      }
     }
     lds_barrier();
   }
   for (int i = tid; i < nv; i += kB) D.XB[G.pv[v0 + i]] = sX[i];
   if (!LAST) {
-    if (RL) copy16(gimg, rec, rbytes);
+    if (RL) copy16(gmul, lrec + rbytes, mbytes);
     return;
   }
   // last reverse iteration of the substep: FP64 parameter adjoints and the
-  // per-contact sphere adjoints leave the image
+  // per-contact sphere adjoints leave the state (each thread reads the items
+  // it wrote itself)
   const int* first = G.rec_first + (size_t)p * G.nset;
-  r = rec;
+  m = mul;
   for (int q = 0; q < G.nset; ++q) {
     const int n = cnt[q], ty = G.set_type[q], jb = first[q];
+    const T* mb = reinterpret_cast<const T*>(m);
     switch (ty) {
-      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)reinterpret_cast<RDist<T>*>(r)[i].ab; break;
-      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)reinterpret_cast<RBend<T>*>(r)[i].ab; break;
+      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
+      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
       case 2:
         for (int i = tid; i < n; i += kB) {
-          const RTet<T>& rt = reinterpret_cast<RTet<T>*>(r)[i];
-          D.t_acc[jb + i] += (double)rt.ebD;
-          D.t_acc[D.tr.n + jb + i] += (double)rt.ebH;
-          D.t_acc[2 * D.tr.n + jb + i] += (double)rt.gb;
+          D.t_acc[jb + i] += (double)mb[2 * n + i];
+          D.t_acc[D.tr.n + jb + i] += (double)mb[3 * n + i];
+          D.t_acc[2 * D.tr.n + jb + i] += (double)mb[4 * n + i];
         }
         break;
-      default: for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = reinterpret_cast<RCon<T>*>(r)[i].sa; break;
+      default: {
+        const Vec4<T>* sam = reinterpret_cast<const Vec4<T>*>(m);
+        for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = sam[i];
+        break;
+      }
     }
-    r += al32((size_t)n * rev_rec_bytes<T>(ty));
+    m += al32((size_t)n * rmul_words(ty) * sizeof(T));
   }
 }
 
 // copy the per-call compliances (alpha / h^2 and the tet constants) into the
-// group record images: pos[j] is the byte offset of constraint j's record,
+// constant group image: pos[j] is the byte offset of constraint j's entry,
 // -1 outside LDS groups
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const long long* __restrict__ fpos,
-                                                       const long long* __restrict__ rpos, char* __restrict__ fimg,
-                                                       char* __restrict__ rimg, const T* __restrict__ at,
+__global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const long long* __restrict__ pos,
+                                                       char* __restrict__ img, const T* __restrict__ at,
                                                        const T* __restrict__ atH, const T* __restrict__ gam) {
   int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n || fpos[j] < 0) return;
+  if (j >= n || pos[j] < 0) return;
   switch (type) {
-    case 0:
-      reinterpret_cast<SDist<T>*>(fimg + fpos[j])->at = at[j];
-      reinterpret_cast<RDist<T>*>(rimg + rpos[j])->at = at[j];
-      break;
-    case 1:
-      reinterpret_cast<SBend<T>*>(fimg + fpos[j])->at = at[j];
-      reinterpret_cast<RBend<T>*>(rimg + rpos[j])->at = at[j];
-      break;
+    case 0: reinterpret_cast<SDist<T>*>(img + pos[j])->at = at[j]; break;
+    case 1: reinterpret_cast<SBend<T>*>(img + pos[j])->at = at[j]; break;
     default: {
-      STet<T>* f = reinterpret_cast<STet<T>*>(fimg + fpos[j]);
-      RTet<T>* r = reinterpret_cast<RTet<T>*>(rimg + rpos[j]);
+      STet<T>* f = reinterpret_cast<STet<T>*>(img + pos[j]);
       f->atD = at[j]; f->atH = atH[j]; f->gam = gam[j];
-      r->atD = at[j]; r->atH = atH[j]; r->gam = gam[j];
       break;
     }
   }
