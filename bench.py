@@ -127,7 +127,7 @@ KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: 
                  6: "k_contact", 7: "k_contact_rev", 8: "k_program(forward frame)", 9: "k_program(reverse frame)",
                  10: "k_group_fwd", 11: "k_group_rev", 12: "k_tri", 13: "k_tri_rev"}
 N_FAM = len(FAMILY)
-WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 128}}
+WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 256}}
 HBM_PEAK_GBS = 8000.0
 
 

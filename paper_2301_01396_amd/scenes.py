@@ -679,15 +679,15 @@ def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int =
 
 
 def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: int = 4, tile: int = 32,
-              tiling: str = "lines", lds_groups=(0, 1, 2), merge=(4, 8)) -> Scene:
+              tiling: str = "lines", lds_groups=(0, 1, 2), merge=(16, 32)) -> Scene:
     """2048 x 4096 cloth (8.4M vertices, 25.2M DoF), row-0 corners pinned,
     distance + bending, per-frame per-vertex force controls, dt 1/60,
     2 substeps, 20 iterations.  tile > 0: three-group tiled schedule (tile
     interiors, border segments, corners) with the groups in ``lds_groups``
     offered as LDS groups; 0: the dense 6 + 12 set schedule.  32 x 32 tiles
-    with all three groups in LDS, 4 border segments and 8 corner clusters per
-    patch, measured fastest on MI355X (with records streamed from global
-    memory and 128-thread workgroups)."""
+    with all three groups in LDS, 16 border segments and 32 corner clusters
+    per patch, measured fastest on MI355X (with constraint entries and state
+    streamed from global memory and 256-thread workgroups)."""
     sc = cloth_grid(nr, nc, 1.0 / (nc - 1), pinned=(0, nc - 1))
     if tile:
         if tiling == "lines":

@@ -105,10 +105,10 @@ def test_cloth2048x4096_one_substep_with_forces():
     distance compliances, alpha~ about 1e-3 against w |grad C|^2 = 2, give
     dL/dalpha an intrinsic FP32 error of about 3.4e-3).  The schedule and
     launch shape are the benchmark's: 32 x 32 tiles, three LDS groups,
-    records streamed, 128-thread workgroups."""
+    entries and state streamed, 256-thread workgroups."""
     sc = scenes.config_c4(n_frames=1)
     sc.substeps, sc.iterations = 1, 2
-    sim = _sim(sc, group_records=2, group_block=128)
+    sim = _sim(sc, group_records=2, group_block=256)
     assert sim.info()["n_groups_lds"] == 3
     rng = np.random.default_rng(3)
     mask = np.ones(1, bool)

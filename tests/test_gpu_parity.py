@@ -429,11 +429,13 @@ def test_merged_border_patches_give_the_same_bits():
     def build(merge):
         sc = scenes.small_cloth(n=70, frames=2, substeps=2, iterations=3)
         return scenes.tile_cloth_lines(sc, 70, 70, 16, merge=merge)
-    a_sc, b_sc = build((1, 1)), build((4, 8))
+    a_sc, b_sc, c_sc = build((1, 1)), build((4, 8)), build((16, 32))
     ref = reference_case(a_sc, 2, n_threads=8)
     a = gpu_case(_sim(a_sc, "f32", group_records=2, group_block=128), 2, ref)
     b = gpu_case(_sim(b_sc, "f32", group_records=2, group_block=128), 2, ref)
-    assert np.array_equal(a["x_frames"], b["x_frames"])
-    for k, v in a["grads"].items():
-        assert np.array_equal(b["grads"][k], v), k
+    c = gpu_case(_sim(c_sc, "f32", group_records=2, group_block=256), 2, ref)
+    for o in (b, c):
+        assert np.array_equal(a["x_frames"], o["x_frames"])
+        for k, v in a["grads"].items():
+            assert np.array_equal(o["grads"][k], v), k
     compare(a_sc, ref, a, 1e-5, 1e-3)
