@@ -155,6 +155,7 @@ struct xpbd_ctx_s {
     size_t smem_fwd = 0, smem_rev = 0;   // vertex tile + constant entries + state (+ record of inputs)
     size_t smem_tile = 0;                 // vertex tile only (entries and state streamed)
     int64_t items = 0;        // projections per iteration inside the group
+    bool tet = false;         // has tet sets (kernels with the tet projection)
     int* pv_start = nullptr; int* pv = nullptr; int* cnt = nullptr; int* set_type = nullptr;
     long long* img = nullptr; long long* fmul = nullptr; long long* rmul = nullptr;   // per patch offsets
     long long* tpos = nullptr; int* rec_first = nullptr;
@@ -474,8 +475,10 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_fwd : g.smem_tile;
 #define XPBD_GF(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl) k_group_fwd<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
-    else k_group_fwd<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);   \
+    if (rl && g.tet) k_group_fwd<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);   \
+    else if (rl) k_group_fwd<T, F1, F2, true, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);  \
+    else if (g.tet) k_group_fwd<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
+    else k_group_fwd<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);         \
   } while (0)
     if (first) {
       if (tape_iter) XPBD_GF(true, true);
@@ -501,8 +504,10 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_rev : g.smem_tile;
 #define XPBD_GR(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl) k_group_rev<T, F1, F2, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
-    else k_group_rev<T, F1, F2, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
+    if (rl && g.tet) k_group_rev<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
+    else if (rl) k_group_rev<T, F1, F2, true, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);  \
+    else if (g.tet) k_group_rev<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
+    else k_group_rev<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);         \
   } while (0)
     if (first) {
       if (last) XPBD_GR(true, true);
@@ -533,14 +538,19 @@ template <class T> struct Ops {
 
   static void allow_lds(size_t bytes) {
     if (bytes <= 65536) return;
-    const void* ks[] = {(const void*)k_group_fwd<T, true, true, true>, (const void*)k_group_fwd<T, true, false, true>,
-                        (const void*)k_group_fwd<T, false, true, true>, (const void*)k_group_fwd<T, false, false, true>,
-                        (const void*)k_group_rev<T, true, true, true>, (const void*)k_group_rev<T, true, false, true>,
-                        (const void*)k_group_rev<T, false, true, true>, (const void*)k_group_rev<T, false, false, true>,
-                        (const void*)k_group_fwd<T, true, true, false>, (const void*)k_group_fwd<T, true, false, false>,
-                        (const void*)k_group_fwd<T, false, true, false>, (const void*)k_group_fwd<T, false, false, false>,
-                        (const void*)k_group_rev<T, true, true, false>, (const void*)k_group_rev<T, true, false, false>,
-                        (const void*)k_group_rev<T, false, true, false>, (const void*)k_group_rev<T, false, false, false>};
+    allow_lds_tet<true>(bytes);
+    allow_lds_tet<false>(bytes);
+  }
+  template <bool TET> static void allow_lds_tet(size_t bytes) {
+    const void* ks[] = {
+        (const void*)k_group_fwd<T, true, true, true, TET>,   (const void*)k_group_fwd<T, true, false, true, TET>,
+        (const void*)k_group_fwd<T, false, true, true, TET>,  (const void*)k_group_fwd<T, false, false, true, TET>,
+        (const void*)k_group_rev<T, true, true, true, TET>,   (const void*)k_group_rev<T, true, false, true, TET>,
+        (const void*)k_group_rev<T, false, true, true, TET>,  (const void*)k_group_rev<T, false, false, true, TET>,
+        (const void*)k_group_fwd<T, true, true, false, TET>,  (const void*)k_group_fwd<T, true, false, false, TET>,
+        (const void*)k_group_fwd<T, false, true, false, TET>, (const void*)k_group_fwd<T, false, false, false, TET>,
+        (const void*)k_group_rev<T, true, true, false, TET>,  (const void*)k_group_rev<T, true, false, false, TET>,
+        (const void*)k_group_rev<T, false, true, false, TET>, (const void*)k_group_rev<T, false, false, false, TET>};
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
@@ -1412,6 +1422,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
         for (int k = 0; k < nv; ++k) ref[vv[k]] = 1;
       }
       G.items += si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count;
+      if (si.type == XPBD_TET) G.tet = true;
     }
     std::vector<int> raw;
     for (int v = 0; v < V; ++v) if (ref[v]) raw.push_back(gp[v]);

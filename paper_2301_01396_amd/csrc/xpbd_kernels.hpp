@@ -1279,8 +1279,10 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
 // vertices (one bulk copy in, the state copied out); otherwise only the
 // vertex tile is in LDS and each set's entries are read, and its state read
 // and written, in place in the global images, which keeps the workgroup's
-// LDS small so many patches run per CU.
-template <class T, bool FIRST, bool TAPE, bool RL>
+// LDS small so many patches run per CU.  TET: the group has tet sets; the
+// kernels without the tet projection need far fewer registers, so more
+// waves of a cloth group run per SIMD.
+template <class T, bool FIRST, bool TAPE, bool RL, bool TET>
 __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ fmul, char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
@@ -1334,6 +1336,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
         }
         break;
       case 2:
+        if constexpr (TET)
         for (int i = tid; i < n; i += kB) {
           const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
@@ -1367,7 +1370,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
   if (RL) copy16(gmul, lrec + rbytes, mbytes);
 }
 
-template <class T, bool FIRST, bool LAST, bool RL>
+template <class T, bool FIRST, bool LAST, bool RL, bool TET>
 __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ rmul, const char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
@@ -1430,6 +1433,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
         }
         break;
       case 2:
+        if constexpr (TET)
         for (int i = tid; i < n; i += kB) {
           const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
@@ -1479,6 +1483,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
       case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
       case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
       case 2:
+        if constexpr (TET)
         for (int i = tid; i < n; i += kB) {
           D.t_acc[jb + i] += (double)mb[2 * n + i];
           D.t_acc[D.tr.n + jb + i] += (double)mb[3 * n + i];
