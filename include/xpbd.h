@@ -200,6 +200,12 @@ typedef struct {
                                 [64, 256], 0 = 256 */
   int32_t record_frames;     /* tape_mode 4: most final frames the forward records, 0 = as
                                 many as fit */
+  int32_t serial_adjoint;    /* 0: while the adjoint reverses a frame on a stream of the
+                                library's, the recomputation of an earlier frame runs on
+                                another (both default priority, created on first use and
+                                destroyed with the context), ordered by events, when the
+                                record holds two frames or more; 1: every step on the
+                                call's stream.  Results do not depend on it */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral

@@ -194,6 +194,12 @@ struct xpbd_ctx_s {
   bool fwd_recorded = false;
   int fwd_rec_from = 0;          // first frame whose record the forward kept (frames >= it)
   int record_frames_opt = 0;     // tape_mode 4: most final frames the forward records (0 = all that fit)
+  // adjoint: while one library stream reverses a frame, another recomputes
+  // an earlier frame's record (events order the two); serial_adjoint = 1
+  // runs every step on the call's stream
+  int serial_adjoint = 0;
+  hipStream_t adj_rec = nullptr, adj_rev = nullptr;
+  std::vector<hipEvent_t> adj_events;
   int fwd_frames = 0;
   xpbd_params fwd_params{};
 
@@ -208,6 +214,12 @@ struct xpbd_ctx_s {
   int64_t prof_items[kProfFamilies] = {0};
 
   ~xpbd_ctx_s() {
+    for (hipStream_t* s : {&adj_rec, &adj_rev})
+      if (*s) {
+        (void)hipStreamSynchronize(*s);
+        (void)hipStreamDestroy(*s);
+      }
+    for (hipEvent_t e : adj_events) (void)hipEventDestroy(e);
     if (pack_event) {
       (void)hipEventSynchronize(pack_event);
       (void)hipEventDestroy(pack_event);
@@ -875,6 +887,12 @@ template <class T> struct Ops {
     Dev<T> D = dev(c, p->sphere);
     D.bgrad = out->body_x;
     const size_t frame_tape = (size_t)S * c->K * c->iter_tape_bytes;
+    const int nslot = frame_tape ? (int)std::min<size_t>(c->tape_cap / frame_tape, (size_t)F) : 0;
+    if (!c->persistent && !c->serial_adjoint && mode == 1 && rec_from > 0 && nslot >= 2) {
+      adjoint_overlapped(c, p, D, dLdx, mask, out, rec_from, nslot, st);
+      finish_adjoint(c, p, out, st);
+      return;
+    }
     for (int f = F - 1; f >= 0; --f) {
       if (dLdx && (!mask || mask[f])) {
         k_adj_inject<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);
@@ -906,6 +924,69 @@ template <class T> struct Ops {
       }
     }
     finish_adjoint(c, p, out, st);
+  }
+
+  // Adjoint with the recomputation of earlier frames beside the reverse.
+  // The record holds nslot frames: the kept frames f >= rec_from in slot
+  // f - rec_from, the others free.  A recomputed frame g takes the slot of
+  // frame g + nslot once that frame has been reversed (or a free slot), so
+  // its recomputation on one library stream runs while the frames between
+  // are reversed on another.  The recomputation touches only the forward
+  // state (positions, velocities, multipliers, forward group state) and its
+  // slot; the reverse only the adjoint state, the gradient outputs and the
+  // slots of frames already recorded.  Events order each reverse after its
+  // frame's recomputation and each slot's reuse after the reverse that read
+  // it; the call's stream waits for both streams at the start and for the
+  // reverse stream at the end.  Every kernel sees the same inputs as in the
+  // serial order, so the results are bitwise those of one stream.
+  static void adjoint_overlapped(xpbd_ctx c, const xpbd_params* p, const Dev<T>& D, const void* dLdx,
+                                 const uint8_t* mask, const xpbd_grads* out, int rec_from, int nslot,
+                                 hipStream_t st) {
+    const int V = c->V, F = c->fwd_frames, S = c->S;
+    if (!c->adj_rec) HIPCHK(hipStreamCreateWithFlags(&c->adj_rec, hipStreamNonBlocking));
+    if (!c->adj_rev) HIPCHK(hipStreamCreateWithFlags(&c->adj_rev, hipStreamNonBlocking));
+    hipStream_t sr = c->adj_rec, sv = c->adj_rev;
+    // events: [0, F) frame recomputed, [F, 2F) frame reversed, start, end
+    while (c->adj_events.size() < (size_t)2 * F + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->adj_events.push_back(e);
+    }
+    hipEvent_t* ev_rec = c->adj_events.data();
+    hipEvent_t* ev_rev = ev_rec + F;
+    hipEvent_t ev_start = ev_rec[2 * F], ev_end = ev_rec[2 * F + 1];
+    const int kept_n = F - rec_from;
+    std::vector<int> slot(F, -1);
+    for (int f = rec_from; f < F; ++f) slot[f] = f - rec_from;
+    for (int g = rec_from - 1; g >= 0; --g)
+      slot[g] = g + nslot <= F - 1 ? slot[g + nslot] : kept_n + (rec_from - 1 - g);
+    HIPCHK(hipEventRecord(ev_start, st));
+    HIPCHK(hipStreamWaitEvent(sr, ev_start, 0));
+    HIPCHK(hipStreamWaitEvent(sv, ev_start, 0));
+    int next = rec_from - 1;   // next frame to recompute, descending
+    for (int f = F - 1; f >= 0; --f) {
+      // enqueue every recomputation whose slot is free once the reverses
+      // enqueued so far have run
+      while (next >= 0 && next + nslot > f) {
+        const int g = next--;
+        if (g + nslot <= F - 1) HIPCHK(hipStreamWaitEvent(sr, ev_rev[g + nslot], 0));
+        const T* fg = p->f_ext ? (const T*)p->f_ext + (size_t)g * 3 * V : nullptr;
+        restore(c, g, sr);
+        for (int s = 0; s < S; ++s) substep(c, D, fg, slot[g] * S + s, sr, g * S + s);
+        HIPCHK(hipEventRecord(ev_rec[g], sr));
+      }
+      if (f < rec_from) HIPCHK(hipStreamWaitEvent(sv, ev_rec[f], 0));
+      if (dLdx && (!mask || mask[f])) {
+        k_adj_inject<T><<<nblocks(V), kBlock, 0, sv>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);
+        check_launch();
+      }
+      T* fb = out->f_ext ? (T*)out->f_ext + (size_t)f * 3 * V : nullptr;
+      for (int s = S - 1; s >= 0; --s) reverse_substep(c, D, fb, out->sphere, slot[f] * S + s, sv, f * S + s);
+      HIPCHK(hipEventRecord(ev_rev[f], sv));
+    }
+    // the reverse stream waited for the last recomputation before frame 0
+    HIPCHK(hipEventRecord(ev_end, sv));
+    HIPCHK(hipStreamWaitEvent(st, ev_end, 0));
   }
 
   // adjoint state and gradient outputs before the first reversed frame:
@@ -1030,6 +1111,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   c->gamma_one = o->tet_gamma_one ? 1 : 0;
   c->tape_mode_opt = o->tape_mode;
   c->record_frames_opt = o->record_frames;
+  c->serial_adjoint = o->serial_adjoint ? 1 : 0;
   c->tau = cd->contact_thickness;
   c->alpha_c = cd->contact_compliance;
   const int V = c->V;
@@ -1782,9 +1864,18 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
     }
     if (rec_from > 0 && rec_from < F) mode = 1;   // the kept slots hold at least one frame
     // record slots: the kept frames', and one frame (mode 1) or one substep
-    // (mode 2) for the recomputed frames
+    // (mode 2) for the recomputed frames.  With nothing kept, two frames when
+    // they fit, so a frame can be recomputed while the next is reversed;
+    // kept frames are never moved (growing the record would drop them), and
+    // two or more kept frames give the overlap their slots
     int slots = (F - rec_from) * c->S;
-    if (rec_from > 0) slots = std::max(slots, mode == 1 ? c->S : 1);
+    if (rec_from > 0) {
+      int want = 1;
+      if (mode == 1 && rec_from == F && !c->persistent && !c->serial_adjoint &&
+          fits_on_device(c, 2 * (size_t)c->S * c->K * c->iter_tape_bytes))
+        want = 2;
+      slots = std::max(slots, mode == 1 ? want * c->S : 1);
+    }
     ensure_adjoint_buffers(c, slots);
     c->tape_mode_used = rec_from == 0 ? 3 : rec_from < F ? 4 : mode;
     c->fwd_recorded = false;   // a kept record is consumed by this adjoint

@@ -57,6 +57,7 @@ def _create(sc, **opt):
     o.tape_mode = opt.get("tape_mode", 0)
     o.block_size = opt.get("block_size", 0)
     o.record_frames = opt.get("record_frames", 0)
+    o.serial_adjoint = opt.get("serial_adjoint", 0)
     ctx = C.c_void_p()
     rc = lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(ctx))
     msg = lib.xpbd_last_error(None).decode()

@@ -103,18 +103,39 @@ def test_bitwise_determinism_and_tape_modes():
     ref = reference_case(sc, 3, n_threads=8)
     outs = []
     infos = []
-    for mode, kw in ((1, {}), (1, {}), (2, {}), (3, {}), (0, {}), (4, {"record_frames": 1}),
-                     (4, {"record_frames": 2})):
+    # mode 1 and 4 with two kept frames overlap the recomputation with the
+    # reverse on two streams; serial_adjoint runs them on one
+    for mode, kw in ((1, {"serial_adjoint": True}), (1, {}), (2, {}), (3, {}), (0, {}),
+                     (4, {"record_frames": 1}), (4, {"record_frames": 2}),
+                     (4, {"record_frames": 2, "serial_adjoint": True})):
         sim = _sim(sc, "f32", tape_mode=mode, **kw)
         got = gpu_case(sim, 3, ref)
         outs.append(got)
         infos.append(sim.info()["tape_mode"])
-    assert infos == [1, 1, 2, 3, 3, 4, 4]
+    assert infos == [1, 1, 2, 3, 3, 4, 4, 4]
     for o in outs[1:]:
         assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
         for k, v in outs[0]["grads"].items():
             assert np.array_equal(o["grads"][k], v), k
     del torch
+
+
+def test_overlapped_adjoint_matches_one_stream():
+    """Longer rollouts through the two-stream adjoint (recomputation beside
+    the reverse): nothing kept (two frame slots), three kept frames (three
+    slots, seven frames recomputed) and nine kept frames (one recomputed,
+    beside eight reverses); each bitwise equal to the one-stream order."""
+    sc = scenes.small_cloth(n=10, frames=10, substeps=2, iterations=3)
+    ref = reference_case(sc, 10, n_threads=8)
+    for mode, kw, info in ((1, {}, 1), (4, {"record_frames": 3}, 4), (4, {"record_frames": 9}, 4)):
+        a = gpu_case(_sim(sc, "f32", tape_mode=mode, **kw), 10, ref)
+        sim = _sim(sc, "f32", tape_mode=mode, serial_adjoint=True, **kw)
+        b = gpu_case(sim, 10, ref)
+        assert sim.info()["tape_mode"] == info
+        assert np.array_equal(a["x_frames"], b["x_frames"])
+        for k, v in b["grads"].items():
+            assert np.array_equal(a["grads"][k], v), (mode, kw, k)
+        compare(sc, ref, a, 1e-5, 1e-3)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
