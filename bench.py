@@ -575,6 +575,31 @@ def main():
                 "bytes_per_projection": round(fam_bytes(dom), 1),
                 "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"]}
 
+        # the whole path per step: algorithmic bytes of every projection run
+        # (forward frames, the adjoint's recomputed frames, reversed frames)
+        # over the step's wall time.  Per-launch figures above are taken on
+        # launches that, in the adjoint, share the GPU with the other stream
+        # (recomputation beside the reverse), so they understate a kernel
+        # running alone; the path figure does not depend on that.
+        covered = set()
+        for (a, b, _pm) in sc.groups:
+            covered.update(range(a, b))
+        all_grouped = (info["n_groups_lds"] == len(sc.groups) > 0 and len(covered) == len(sc.set_type))
+        if info["tape_mode"] in (1, 3, 4) and (all_grouped or not sc.groups) and not info["persistent"]:
+            half = proj_step / 2
+            frames_fwd = F + (F - kept)
+            if all_grouped:
+                fb = group_bytes(sc, False, tsz, recording, staged)
+                rb = group_bytes(sc, True, tsz, recording, staged)
+            else:
+                fb = recording * mix_bytes(sc, False, tsz, True) + (1 - recording) * mix_bytes(sc, False, tsz, False)
+                rb = mix_bytes(sc, True, tsz, False)
+            pb = half * frames_fwd / F * fb + half * rb
+            sec = elapsed / args.steps
+            roof["path"] = {"bytes_per_step": round(pb), "achieved": round(pb / sec / 1e9, 1),
+                            "frac": round(pb / sec / 1e9 / HBM_PEAK_GBS, 4), "frames_run_forward": frames_fwd}
+        roof["adjoint_streams"] = info["adjoint_streams"]
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, sc)

@@ -355,6 +355,8 @@ typedef struct {
   int32_t n_tri;                       /* membrane triangles */
   int32_t n_body_contacts;             /* body-contact items */
   int32_t forward_record_frames;       /* final frames whose record the last forward kept */
+  int32_t adjoint_streams;             /* streams the last adjoint ran on: 2 when earlier frames
+                                          were recomputed beside the reverse, 1 otherwise, 0 none */
 } xpbd_info;
 xpbd_status xpbd_get_info(xpbd_ctx ctx, xpbd_info* info);
 

@@ -199,6 +199,7 @@ struct xpbd_ctx_s {
   // runs every step on the call's stream
   int serial_adjoint = 0;
   hipStream_t adj_rec = nullptr, adj_rev = nullptr;
+  int adj_streams_used = 0;   // streams the last adjoint ran on (1 or 2)
   std::vector<hipEvent_t> adj_events;
   int fwd_frames = 0;
   xpbd_params fwd_params{};
@@ -888,7 +889,9 @@ template <class T> struct Ops {
     D.bgrad = out->body_x;
     const size_t frame_tape = (size_t)S * c->K * c->iter_tape_bytes;
     const int nslot = frame_tape ? (int)std::min<size_t>(c->tape_cap / frame_tape, (size_t)F) : 0;
+    c->adj_streams_used = 1;
     if (!c->persistent && !c->serial_adjoint && mode == 1 && rec_from > 0 && nslot >= 2) {
+      c->adj_streams_used = 2;
       adjoint_overlapped(c, p, D, dLdx, mask, out, rec_from, nslot, st);
       finish_adjoint(c, p, out, st);
       return;
@@ -1929,6 +1932,7 @@ xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {
   info->n_tri = c->n_tri;
   info->n_body_contacts = c->n_bc;
   info->forward_record_frames = c->have_forward ? c->fwd_frames - c->fwd_rec_from : 0;
+  info->adjoint_streams = c->adj_streams_used;
   return XPBD_OK;
 }
 

@@ -79,7 +79,7 @@ class Info(C.Structure):
                 ("tape_mode", C.c_int32), ("persistent", C.c_int32), ("persistent_blocks", C.c_int32),
                 ("n_groups", C.c_int32), ("n_groups_lds", C.c_int32), ("max_group_lds_bytes", C.c_int32),
                 ("n_materials", C.c_int32), ("n_tri", C.c_int32), ("n_body_contacts", C.c_int32),
-                ("forward_record_frames", C.c_int32)]
+                ("forward_record_frames", C.c_int32), ("adjoint_streams", C.c_int32)]
 
 
 class Job(C.Structure):

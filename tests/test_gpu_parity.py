@@ -128,10 +128,12 @@ def test_overlapped_adjoint_matches_one_stream():
     sc = scenes.small_cloth(n=10, frames=10, substeps=2, iterations=3)
     ref = reference_case(sc, 10, n_threads=8)
     for mode, kw, info in ((1, {}, 1), (4, {"record_frames": 3}, 4), (4, {"record_frames": 9}, 4)):
-        a = gpu_case(_sim(sc, "f32", tape_mode=mode, **kw), 10, ref)
+        sa = _sim(sc, "f32", tape_mode=mode, **kw)
+        a = gpu_case(sa, 10, ref)
+        assert sa.info()["adjoint_streams"] == 2
         sim = _sim(sc, "f32", tape_mode=mode, serial_adjoint=True, **kw)
         b = gpu_case(sim, 10, ref)
-        assert sim.info()["tape_mode"] == info
+        assert sim.info()["tape_mode"] == info and sim.info()["adjoint_streams"] == 1
         assert np.array_equal(a["x_frames"], b["x_frames"])
         for k, v in b["grads"].items():
             assert np.array_equal(a["grads"][k], v), (mode, kw, k)
