@@ -145,7 +145,8 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = "", merge: str = ""):
+def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = "", merge: str = "",
+                  tiling: str = ""):
     from paper_2301_01396_amd import scenes
     kw = {} if tile < 0 else {"tile": tile}
     if name == "c1":
@@ -165,6 +166,8 @@ def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = 
             kw["lds_groups"] = tuple(int(ch) for ch in lds_groups)
         if merge:
             kw["merge"] = tuple(int(v) for v in merge.split(","))
+        if tiling:
+            kw["tiling"] = tiling
         return scenes.config_c4(**kw), None
     raise SystemExit(f"unknown workload {name}")
 
@@ -277,7 +280,7 @@ def implicit_bench(args):
     import torch
     from paper_2301_01396_amd.lib import Simulator
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge, args.tiling)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     sim = Simulator(sc, dtype=dtype)
@@ -386,6 +389,9 @@ def main():
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
     ap.add_argument("--merge", default="",
                     help="tiled cloth: border segments and corner clusters per patch, e.g. 8,16 (default: the workload's)")
+    ap.add_argument("--tiling", default="", choices=["", "lines", "quads"],
+                    help="tiled cloth: interiors + border lines + corners (lines) or four colours of whole "
+                         "tiles (quads); default: the workload's")
     ap.add_argument("--lds-groups", default="",
                     help="tiled cloth: which of the tiling's groups (0 interiors, 1 borders, 2 corners) run as "
                          "LDS groups, e.g. 012 (default: the workload's)")
@@ -432,7 +438,7 @@ def main():
         return implicit_bench(args)
 
     dev = torch.device("cuda:0")
-    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge)
+    sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge, args.tiling)
     F = args.frames or sc.n_frames
     dtype = torch.float64 if args.workload == "c1" else torch.float32
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]

@@ -512,6 +512,65 @@ def tile_cloth_lines(sc: Scene, nr: int, nc: int, tile: int = 16, lds_groups=(0,
     return sc
 
 
+def tile_cloth_quads(sc: Scene, nr: int, nc: int, tile: int = 32) -> Scene:
+    """Four-group tiled schedule for an nr x nc grid cloth.
+
+    Every constraint belongs to the tile of its anchor (the smallest row and
+    the smallest column among its vertices); its vertices lie within two rows
+    and two columns of the anchor, so the patch of a tile is the tile plus
+    the two rows and columns after it.  Group g = (tile row parity, tile
+    column parity) holds the constraints of the tiles of that colour: two
+    tiles of one colour are at least a tile apart, so their patches share no
+    vertex, and every group is a set of whole tiles with no border groups.
+    An iteration runs the four groups in colour order, then the contact set
+    as a fifth group of whole tiles (patch = the tile holding the vertex).
+    """
+    dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
+    assert np.array_equal(dist_v, sc.dist_v)
+    V = sc.n_verts
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    ntj = (nc + tile - 1) // tile
+    typed = [(DIST, sc.dist_v, dist_batches)]
+    if sc.n_bend:
+        typed.append((BEND, sc.bend_v, bend_batches))
+    anchor, colour = {}, {}
+    for ty, cv, _ in typed:
+        ar, ac = ii[cv].min(axis=1) // tile, jj[cv].min(axis=1) // tile
+        assert np.all(ii[cv].max(axis=1) - ii[cv].min(axis=1) <= 2)
+        assert np.all(jj[cv].max(axis=1) - jj[cv].min(axis=1) <= 2)
+        anchor[ty] = ar * ntj + ac
+        colour[ty] = (ar % 2) * 2 + ac % 2
+    sets_t, sets_i, groups = [], [], []
+    for g in range(4):
+        sel = {ty: colour[ty] == g for ty, _, _ in typed}
+        first = len(sets_t)
+        st, si = _group_sets(typed, sel, V)
+        sets_t += st
+        sets_i += si
+        if len(sets_t) == first:
+            continue
+        pm = (ii // tile) * ntj + jj // tile        # vertices outside the group: any
+        for ty, cv, _ in typed:
+            k = sel[ty]
+            pm[cv[k].ravel()] = np.repeat(anchor[ty][k], cv.shape[1])
+        groups.append((first, len(sets_t), pm.astype(np.int32)))
+    if sc.contact:
+        first = len(sets_t)
+        sets_t.append(CONTACT)
+        sets_i.append(np.nonzero(sc.inv_mass > 0)[0].astype(np.int32))
+        groups.append((first, first + 1, ((ii // tile) * ntj + jj // tile).astype(np.int32)))
+    for (a, b, pm) in groups:
+        for k in range(a, b):
+            if sets_t[k] == CONTACT:
+                continue
+            cv = (sc.dist_v if sets_t[k] == DIST else sc.bend_v)[sets_i[k]]
+            p = pm[cv]
+            assert np.all(p == p[:, :1]), "tiling left a constraint across patches"
+    sc.set_type, sc.set_items, sc.groups = sets_t, sets_i, groups
+    return sc
+
+
 def tile_cloth(sc: Scene, nr: int, nc: int, tile: int = 16) -> Scene:
     """Tiled schedule for an nr x nc grid cloth (4 tilings of tile x tile)."""
     dist_v, dist_batches, bend_v, bend_batches = cloth_grid_topology(nr, nc)
@@ -692,6 +751,8 @@ def config_c4(n_frames: int = 20, nr: int = 4096, nc: int = 2048, force_seed: in
     if tile:
         if tiling == "lines":
             tile_cloth_lines(sc, nr, nc, tile, lds_groups=lds_groups, merge=merge)
+        elif tiling == "quads":
+            tile_cloth_quads(sc, nr, nc, tile)
         else:
             tile_cloth(sc, nr, nc, tile)
     sc.dist_alpha, sc.bend_alpha = cloth_alpha(1, sc.n_dist, sc.n_bend)

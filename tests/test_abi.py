@@ -156,6 +156,8 @@ def test_rejects_groups_whose_constraints_span_patches():
 @pytest.mark.parametrize("maker", [lambda: scenes.tile_cloth(scenes.small_cloth(n=40), 40, 40, 16),
                                    lambda: scenes.tile_cloth_lines(scenes.small_cloth(n=40), 40, 40, 16),
                                    lambda: scenes.tile_cloth_lines(scenes.small_cloth(n=37), 37, 37, 8),
+                                   lambda: scenes.tile_cloth_quads(scenes.small_cloth(n=45), 45, 45, 8),
+                                   lambda: scenes.tile_cloth_quads(scenes.small_cloth(n=40), 40, 40, 16),
                                    lambda: scenes.tile_box(scenes.small_tets(n=8), 8, 4)])
 def test_tiled_schedules_are_valid_and_grouped(maker):
     sc = maker()

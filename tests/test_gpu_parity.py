@@ -161,8 +161,10 @@ def test_plain_and_persistent_launches_agree_bitwise(dtype):
     compare(sc, ref, outs[1], *tol)
 
 
-def _tiled_cloth(n=40, tile=16, frames=2, S=2, K=3, lines=False):
+def _tiled_cloth(n=40, tile=16, frames=2, S=2, K=3, lines=False, quads=False):
     sc = scenes.small_cloth(n=n, frames=frames, substeps=S, iterations=K)
+    if quads:
+        return scenes.tile_cloth_quads(sc, n, n, tile)
     return (scenes.tile_cloth_lines if lines else scenes.tile_cloth)(sc, n, n, tile)
 
 
@@ -172,12 +174,12 @@ def _tiled_tets(n=6, tile=4, frames=2):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("kind", ["cloth", "cloth_lines", "tets"])
+@pytest.mark.parametrize("kind", ["cloth", "cloth_lines", "cloth_quads", "tets"])
 def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
     """LDS group launches compute exactly what one launch per set computes
     on the same (tiled) schedule; both match the FP64 reference."""
     sc = {"cloth": _tiled_cloth, "cloth_lines": lambda: _tiled_cloth(n=37, tile=8, lines=True),
-          "tets": _tiled_tets}[kind]()
+          "cloth_quads": lambda: _tiled_cloth(n=45, tile=8, quads=True), "tets": _tiled_tets}[kind]()
     ref = reference_case(sc, 2, n_threads=8, noise=0.01 if kind == "cloth" else 1e-3)
     a_sim = _sim(sc, dtype)
     b_sim = _sim(sc, dtype, use_groups=False)
