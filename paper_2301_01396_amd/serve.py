@@ -87,8 +87,11 @@ class Server:
     def _run_one(self, req: Request, stream: torch.cuda.Stream):
         sc = req.scene
         with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            # every step of a request on its slot's stream: the server
+            # overlaps requests, and one request at a time stays the plain
+            # one-stream baseline
             sim = Simulator(sc, dtype=self.dtype, device=self.device,
-                            tape_mode=0 if self.record else 1)
+                            tape_mode=0 if self.record else 1, serial_adjoint=True)
             try:
                 xf, xe, ve = sim.forward(req.n_frames, for_adjoint=req.adjoint)
                 res = {}
