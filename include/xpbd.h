@@ -278,7 +278,11 @@ typedef struct {
  * with gradient dLdx_frames (device [F][V][3], row f = dL/dx(end of frame
  * f); frames with frame_mask[f] == 0 are not read; frame_mask is host [F]
  * or NULL = all) plus dLdv_final (device [V][3] or NULL).  `p` must be the
- * same parameters, with unchanged contents, as in that forward.
+ * same parameters, with unchanged contents, as in that forward.  Stream
+ * ordered like every call: work the call puts on the library's own streams
+ * (the recomputation beside the reverse, see serial_adjoint) starts after
+ * the call's stream reaches the call and has finished when the call's
+ * stream passes the end of the call.
  * Errors: XPBD_ERR_STATE (no forward, or different parameter pointers),
  * XPBD_ERR_INVALID, XPBD_ERR_OOM, XPBD_ERR_HIP. */
 xpbd_status xpbd_adjoint(xpbd_ctx ctx, const xpbd_params* p, const void* dLdx_frames,
