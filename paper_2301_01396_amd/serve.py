@@ -45,6 +45,7 @@ class Request:
     result: Dict[str, np.ndarray] = field(default_factory=dict)
     projections: int = 0
     device_bytes: int = 0
+    cancelled: bool = False         # set by Server.cancel
 
 
 def estimate_bytes(sc, n_frames: int, adjoint: bool, dtype_bytes: int = 4) -> int:
@@ -78,6 +79,8 @@ class Server:
         self._in_use = 0
         self._free_slots = list(range(slots))
         self._finished: List[Request] = []
+        self._cancelled: List[Request] = []
+        self._running: Dict[int, Request] = {}
         self._closed = False
         self._t0 = 0.0
         self._queue_depth: List[int] = []
@@ -95,6 +98,9 @@ class Server:
             try:
                 xf, xe, ve = sim.forward(req.n_frames, for_adjoint=req.adjoint)
                 res = {}
+                if req.cancelled:                 # stop at the call boundary, no result
+                    stream.synchronize()
+                    return
                 if req.adjoint:
                     mask = np.zeros(req.n_frames, np.uint8)
                     mask[-1] = 1
@@ -105,6 +111,8 @@ class Server:
                     res.update({k: v for k, v in g.items()})
                 res["x_final"] = xe
                 stream.synchronize()
+                if req.cancelled:
+                    return
                 req.result = {k: (v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else v)
                               for k, v in res.items()}
                 req.projections = sc.projections_per_rollout(req.n_frames) * (2 if req.adjoint else 1)
@@ -113,6 +121,27 @@ class Server:
 
     def _make_stream(self):
         return torch.cuda.Stream(device=self.device)      # default priority
+
+    def cancel(self, rid: int) -> bool:
+        """Cancel request ``rid``: a pending one is dropped before it is
+        admitted; a running one stops at its next call boundary (after its
+        forward, before its adjoint) and returns no result.  Other requests
+        are unaffected (each has its own context and stream).  Returns
+        whether the request was found unfinished."""
+        with self._lock:
+            for k, (_, r_id, req) in enumerate(self._pending):
+                if r_id == rid:
+                    self._pending.pop(k)
+                    heapq.heapify(self._pending)
+                    req.cancelled = True
+                    self._cancelled.append(req)
+                    self._lock.notify_all()
+                    return True
+            req = self._running.get(rid)
+            if req is not None:
+                req.cancelled = True
+                return True
+        return False
 
     def _worker(self, slot: int):
         stream = self._make_stream()
@@ -129,6 +158,7 @@ class Server:
                             admissible = heapq.heappop(self._pending)[2]
                     if admissible is not None:
                         req = admissible
+                        self._running[req.rid] = req
                         self._in_use += req.device_bytes
                         self._queue_depth.append(sum(1 for a, _, _ in self._pending if a <= now))
                         break
@@ -145,7 +175,8 @@ class Server:
             req.done = time.perf_counter() - self._t0
             with self._lock:
                 self._in_use -= req.device_bytes
-                self._finished.append(req)
+                self._running.pop(req.rid, None)
+                (self._cancelled if req.cancelled else self._finished).append(req)
                 self._lock.notify_all()
 
     def run(self, requests: List[Request]) -> Dict[str, Any]:
@@ -156,6 +187,8 @@ class Server:
         self._pending = [(r.arrival, r.rid, r) for r in requests]
         heapq.heapify(self._pending)
         self._finished = []
+        self._cancelled = []
+        self._running = {}
         self._closed = True
         self._queue_depth = []
         if torch.cuda.is_available():
@@ -169,7 +202,9 @@ class Server:
         wall = time.perf_counter() - self._t0
         if self._errors:
             raise RuntimeError("; ".join(self._errors))
-        return report(self._finished, wall, self._queue_depth)
+        rep = report(self._finished, wall, self._queue_depth)
+        rep["cancelled"] = len(self._cancelled)
+        return rep
 
 
 class PackedServer:

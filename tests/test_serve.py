@@ -23,6 +23,16 @@ class FakeServer(serve.Server):
         req.result = {"rid": req.rid}
 
 
+class CancellingFake(FakeServer):
+    """As FakeServer, but a request cancelled while it 'runs' returns no
+    result (the real server stops at its next call boundary)."""
+
+    def _run_one(self, req, stream):
+        time.sleep(self.run_s)
+        if not req.cancelled:
+            req.result = {"rid": req.rid}
+
+
 def _reqs(n, gap, size=5):
     out = []
     for i in range(n):
@@ -48,6 +58,22 @@ def test_admission_respects_memory_budget():
     assert rep["requests"] == 4 and rep["max_concurrent"] == 1
     srv = FakeServer(run_s=0.05, slots=4, hbm_budget=int(2.5 * one))
     assert srv.run(_reqs(4, gap=0.0))["max_concurrent"] == 2
+
+
+def test_cancelled_requests_leave_the_others_unaffected():
+    """Two slots, four requests at t = 0: request 0 is cancelled while it
+    runs, request 3 while it waits; 1 and 2 complete with their results."""
+    import threading
+    srv = CancellingFake(run_s=0.3, slots=2, hbm_budget=1 << 40)
+    timer = threading.Timer(0.1, lambda: (srv.cancel(0), srv.cancel(3)))
+    timer.start()
+    rep = srv.run(_reqs(4, gap=0.0))
+    timer.join()
+    assert rep["requests"] == 2 and rep["cancelled"] == 2
+    assert sorted(r.rid for r in srv._finished) == [1, 2]
+    assert all(r.result == {"rid": r.rid} for r in srv._finished)
+    assert sorted(r.rid for r in srv._cancelled) == [0, 3] and all(not r.result for r in srv._cancelled)
+    assert not srv.cancel(1)                      # finished: nothing to cancel
 
 
 def test_sequential_is_one_slot():
@@ -81,6 +107,29 @@ def test_results_are_the_same_alone_and_in_the_mix():
         got = s1._finished[0].result
         for k, v in got.items():
             assert np.array_equal(np.asarray(v), np.asarray(by_id[r.rid].result[k])), (r.rid, k)
+
+
+@pytest.mark.gpu
+def test_cancelling_requests_mid_mix_leaves_the_others_bitwise_unchanged():
+    import threading
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mix = serve.make_mix(6, qps=50.0, seed=6, vmax=6000, frames_scale=0.1)
+    srv = serve.Server(slots=2, hbm_budget=32 << 30)
+    timer = threading.Timer(0.05, lambda: (srv.cancel(0), srv.cancel(5)))
+    timer.start()
+    rep = srv.run(mix)
+    timer.join()
+    done = {r.rid: r for r in srv._finished}
+    assert 5 not in done and rep["requests"] + rep["cancelled"] == 6
+    for rid, r in done.items():
+        alone = serve.make_mix(6, qps=50.0, seed=6, vmax=6000, frames_scale=0.1)[rid]
+        alone.arrival = 0.0
+        s1 = serve.Server(slots=1, hbm_budget=32 << 30)
+        s1.run([alone])
+        for k, v in s1._finished[0].result.items():
+            assert np.array_equal(np.asarray(v), np.asarray(r.result[k])), (rid, k)
 
 
 @pytest.mark.gpu
