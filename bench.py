@@ -385,7 +385,7 @@ def main():
     ap.add_argument("--no-groups", action="store_true", help="run every set as its own launch")
     ap.add_argument("--block", type=int, default=0, help="workgroup size of the per-set kernels (0 = 256)")
     ap.add_argument("--group-records", type=int, default=0,
-                    help="LDS groups: 1 records staged in LDS, 2 records streamed (0 = the library's choice)")
+                    help="LDS groups: 1 entries and state staged in LDS, 2 streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
     ap.add_argument("--merge", default="",
                     help="tiled cloth: border segments and corner clusters per patch, e.g. 8,16 (default: the workload's)")
@@ -407,7 +407,8 @@ def main():
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
     # launch shape of the LDS group kernels per workload (measured fastest):
-    # the 25.2M-DoF cloth streams its records with 128-thread workgroups
+    # the 25.2M-DoF cloth streams its constraint entries and state with
+    # 256-thread workgroups
     for k, v in WORKLOAD_LAUNCH.get(args.workload, {}).items():
         if getattr(args, k) == 0:
             setattr(args, k, v)

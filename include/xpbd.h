@@ -192,10 +192,11 @@ typedef struct {
                                 largest set (capped at what the device co-schedules) */
   int32_t block_size;        /* workgroup size of the one-launch-per-set kernels: a power
                                 of two in [64, 1024], 0 = 256; results do not depend on it */
-  int32_t group_records;     /* LDS groups: 0 or 1 = each patch's records staged in LDS
-                                with its vertices; 2 = only the vertex tile in LDS, records
-                                read and written in place in global memory (small LDS, many
-                                patches per CU); results do not depend on it */
+  int32_t group_records;     /* LDS groups: 0 or 1 = each patch's constraint entries and
+                                multiplier state staged in LDS with its vertices; 2 = only
+                                the vertex tile in LDS, entries read and state read and
+                                written in place in global memory (small LDS, many patches
+                                per CU); results do not depend on it */
   int32_t group_block;       /* workgroup size of the LDS group kernels, a power of two in
                                 [64, 256], 0 = 256 */
   int32_t record_frames;     /* tape_mode 4: most final frames the forward records, 0 = as

@@ -1460,8 +1460,9 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
 }
 
 // Build the LDS launch data of every schedule group: patch vertex lists,
-// per-patch item counts, and the forward / reverse record images in their
-// LDS layout (static fields here; compliances are filled per call).
+// per-patch item counts, the constant entry image in its LDS layout (static
+// fields here; compliances are filled per call) and the offsets of the
+// forward and reverse state images.
 template <class T>
 void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
                   const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
