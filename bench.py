@@ -479,12 +479,18 @@ def main():
     sphere = torch.tensor(sc.sphere, dtype=torch.float64) if sc.contact else None
     leaves = [t for t in (v0, da, ba, te, f_ctrl, tc, bxx) if t is not None and t.requires_grad]
 
-    def step(s=sim):
+    def step(s=sim, ev=None):
         for t in leaves:
             t.grad = None
+        if ev:
+            ev[0].record()
         xf = AG.rollout(s, F, x0, v0, da, ba, te, f_ctrl, sphere, tri_coef=tc, body_x=bxx)
         loss = AG.goal_l2(s, xf, targets, mask)
+        if ev:
+            ev[1].record()
         loss.backward()
+        if ev:
+            ev[2].record()
         return loss
 
     for _ in range(args.warmup):
@@ -499,11 +505,16 @@ def main():
         stride = 1
     sim.profile_enable(stride)
     torch.cuda.synchronize()
+    # phases on the call's stream (the adjoint's own streams join it before
+    # the call ends): forward + goal, then the adjoint with its recomputation
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        loss = step()
+    for k in range(args.steps):
+        loss = step(ev=evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    phases = {"forward_and_goal_ms": round(sum(e[0].elapsed_time(e[1]) for e in evs) / max(args.steps, 1), 1),
+              "adjoint_ms": round(sum(e[1].elapsed_time(e[2]) for e in evs) / max(args.steps, 1), 1)}
     sim.profile_enable(0)
     launches, ms, items = sim.profile_read()
     elapsed = t1 - t0
@@ -619,7 +630,7 @@ def main():
         "data": "synthetic (seeded grid cloth / tet box, parameters and targets generated)",
         "config": workload_config(args.workload, sc, F),
         "projections_per_step": proj_step, "loss": float(loss.detach().cpu()), "grads_finite": grads_finite,
-        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu, "plain_launch": plain,
+        "roofline": roof, "kernels": kernels, "phases": phases, "cpu_baseline": cpu, "plain_launch": plain,
         "launch": ("persistent frame kernel" if info["persistent"] else
                    f"LDS group launches ({info['n_groups_lds']} groups), one launch per other set"
                    if info["n_groups_lds"] else "one kernel launch per set"),
