@@ -212,7 +212,15 @@ def cpu_baseline(name, sc, max_projections: int = 60_000_000):
     t2 = time.perf_counter()
     proj = sample.projections_per_rollout(frames)
     value = 2 * proj / (t2 - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": value, "unit": "projections/s", "cores": threads, "kind": "oracle",
+            "forward_projections_per_s": proj / (t1 - t0), "adjoint_projections_per_s": proj / (t2 - t1),
+            "cpu_model": model,
             "sample": f"{frames} frame(s) of the workload with {sample.substeps} substep(s) x {sample.iterations} "
                       f"iterations ({proj} forward + {proj} reverse projections, FP64): "
                       f"forward {t1 - t0:.2f} s, adjoint incl. recompute {t2 - t1:.2f} s"}
