@@ -156,7 +156,7 @@ def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = 
     if name == "c3":
         return scenes.config_c3(**kw), scenes.config_c3(target=True, **kw)
     if name == "c2m":
-        return scenes.config_c2_membrane(), scenes.config_c2_membrane(target=True)
+        return scenes.config_c2_membrane(**kw), scenes.config_c2_membrane(target=True, **kw)
     if name == "c2b":
         return scenes.config_c2_body(), scenes.config_c2_body(target=True)
     if name == "c4":

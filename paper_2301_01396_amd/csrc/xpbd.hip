@@ -155,7 +155,7 @@ struct xpbd_ctx_s {
     size_t smem_fwd = 0, smem_rev = 0;   // vertex tile + constant entries + state (+ record of inputs)
     size_t smem_tile = 0;                 // vertex tile only (entries and state streamed)
     int64_t items = 0;        // projections per iteration inside the group
-    bool tet = false;         // has tet sets (kernels with the tet projection)
+    bool heavy = false;       // has tet or membrane sets (kernels with those projections)
     int* pv_start = nullptr; int* pv = nullptr; int* cnt = nullptr; int* set_type = nullptr;
     long long* img = nullptr; long long* fmul = nullptr; long long* rmul = nullptr;   // per patch offsets
     long long* tpos = nullptr; int* rec_first = nullptr;
@@ -166,7 +166,7 @@ struct xpbd_ctx_s {
   std::vector<int> group_at_start, group_at_end;   // per set: group starting / ending there, -1 none
   char* gimg = nullptr;                                 // group constant entries
   char* gfmul = nullptr; char* grmul = nullptr;         // group forward multipliers, reverse state
-  long long* gpos[3] = {nullptr, nullptr, nullptr};     // per dist / bend / tet: entry offset in gimg, -1 none
+  long long* gpos[4] = {nullptr, nullptr, nullptr, nullptr};   // dist / bend / tet / membrane: entry offset in gimg, -1 none
   size_t lds_limit = 65536;
   int max_group_lds = 0;
 
@@ -488,9 +488,9 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_fwd : g.smem_tile;
 #define XPBD_GF(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl && g.tet) k_group_fwd<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);   \
+    if (rl && g.heavy) k_group_fwd<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);   \
     else if (rl) k_group_fwd<T, F1, F2, true, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);  \
-    else if (g.tet) k_group_fwd<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
+    else if (g.heavy) k_group_fwd<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
     else k_group_fwd<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);         \
   } while (0)
     if (first) {
@@ -517,9 +517,9 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_rev : g.smem_tile;
 #define XPBD_GR(F1, F2)                                                                             \
   do {                                                                                              \
-    if (rl && g.tet) k_group_rev<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
+    if (rl && g.heavy) k_group_rev<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
     else if (rl) k_group_rev<T, F1, F2, true, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);  \
-    else if (g.tet) k_group_rev<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
+    else if (g.heavy) k_group_rev<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
     else k_group_rev<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);         \
   } while (0)
     if (first) {
@@ -546,24 +546,27 @@ template <class T> struct Ops {
       k_group_fill<T><<<nblocks(c->n_tet), kBlock, 0, st>>>(2, c->n_tet, c->gpos[2], c->gimg,
                                                             (const T*)c->tet_atD, (const T*)c->tet_atH,
                                                             (const T*)c->tet_gamma);
+    if (c->n_tri && c->gpos[3])
+      k_group_fill<T><<<nblocks(c->n_tri), kBlock, 0, st>>>(4, c->n_tri, c->gpos[3], c->gimg,
+                                                            (const T*)c->tri_at, nullptr, nullptr);
     check_launch();
   }
 
   static void allow_lds(size_t bytes) {
     if (bytes <= 65536) return;
-    allow_lds_tet<true>(bytes);
-    allow_lds_tet<false>(bytes);
+    allow_lds_heavy<true>(bytes);
+    allow_lds_heavy<false>(bytes);
   }
-  template <bool TET> static void allow_lds_tet(size_t bytes) {
+  template <bool HEAVY> static void allow_lds_heavy(size_t bytes) {
     const void* ks[] = {
-        (const void*)k_group_fwd<T, true, true, true, TET>,   (const void*)k_group_fwd<T, true, false, true, TET>,
-        (const void*)k_group_fwd<T, false, true, true, TET>,  (const void*)k_group_fwd<T, false, false, true, TET>,
-        (const void*)k_group_rev<T, true, true, true, TET>,   (const void*)k_group_rev<T, true, false, true, TET>,
-        (const void*)k_group_rev<T, false, true, true, TET>,  (const void*)k_group_rev<T, false, false, true, TET>,
-        (const void*)k_group_fwd<T, true, true, false, TET>,  (const void*)k_group_fwd<T, true, false, false, TET>,
-        (const void*)k_group_fwd<T, false, true, false, TET>, (const void*)k_group_fwd<T, false, false, false, TET>,
-        (const void*)k_group_rev<T, true, true, false, TET>,  (const void*)k_group_rev<T, true, false, false, TET>,
-        (const void*)k_group_rev<T, false, true, false, TET>, (const void*)k_group_rev<T, false, false, false, TET>};
+        (const void*)k_group_fwd<T, true, true, true, HEAVY>,   (const void*)k_group_fwd<T, true, false, true, HEAVY>,
+        (const void*)k_group_fwd<T, false, true, true, HEAVY>,  (const void*)k_group_fwd<T, false, false, true, HEAVY>,
+        (const void*)k_group_rev<T, true, true, true, HEAVY>,   (const void*)k_group_rev<T, true, false, true, HEAVY>,
+        (const void*)k_group_rev<T, false, true, true, HEAVY>,  (const void*)k_group_rev<T, false, false, true, HEAVY>,
+        (const void*)k_group_fwd<T, true, true, false, HEAVY>,  (const void*)k_group_fwd<T, true, false, false, HEAVY>,
+        (const void*)k_group_fwd<T, false, true, false, HEAVY>, (const void*)k_group_fwd<T, false, false, false, HEAVY>,
+        (const void*)k_group_rev<T, true, true, false, HEAVY>,  (const void*)k_group_rev<T, true, false, false, HEAVY>,
+        (const void*)k_group_rev<T, false, true, false, HEAVY>, (const void*)k_group_rev<T, false, false, false, HEAVY>};
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
@@ -1075,7 +1078,8 @@ template <class T> struct Ops {
 template <class T>
 void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
                   const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
-                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c);
+                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c,
+                  const std::vector<int4>& midx, const std::vector<double>& mB);
 
 void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, const xpbd_schedule_desc* sd,
            const xpbd_options* o) {
@@ -1189,8 +1193,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
     if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
     if (ty < 0 || ty > 5) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
-    if ((ty == XPBD_TRI || ty == XPBD_BODY) && set_group[s] >= 0)
-      fail(XPBD_ERR_INVALID, "set %d: membrane and body-contact sets cannot be part of an LDS group", s);
+    if (ty == XPBD_BODY && set_group[s] >= 0)
+      fail(XPBD_ERR_INVALID, "set %d: body-contact sets cannot be part of an LDS group", s);
     if (ty == XPBD_BODY && c->body_nt == 0) fail(XPBD_ERR_INVALID, "set %d: body-contact set without a body", s);
     if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
     // order items inside the set by patch (grouped sets), then by their
@@ -1430,8 +1434,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   c->group_at_start.assign(c->sets.size(), -1);
   c->group_at_end.assign(c->sets.size(), -1);
   if (sd->n_groups > 0 && o->launch_mode != 2) {
-    if (c->dtype == XPBD_F32) build_groups<float>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c);
-    else build_groups<double>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c);
+    if (c->dtype == XPBD_F32) build_groups<float>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB);
+    else build_groups<double>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB);
   } else {
     for (int g = 0; g < sd->n_groups; ++g) {
       xpbd_ctx_s::Group G;
@@ -1466,7 +1470,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
 template <class T>
 void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
                   const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
-                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c) {
+                  const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c,
+                  const std::vector<int4>& midx, const std::vector<double>& mB) {
   const int V = c->V;
   {
     int dev = 0, lim = 0, optin = 0;
@@ -1483,12 +1488,15 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
       case XPBD_DIST: out[0] = didx[j].x; out[1] = didx[j].y; return 2;
       case XPBD_BEND: out[0] = bidx[j].x; out[1] = bidx[j].y; out[2] = bidx[j].z; out[3] = bidx[j].w; return 4;
       case XPBD_TET: out[0] = tidx[j].x; out[1] = tidx[j].y; out[2] = tidx[j].z; out[3] = tidx[j].w; return 4;
+      case XPBD_TRI: out[0] = midx[j].x; out[1] = midx[j].y; out[2] = midx[j].z; return 3;
       default: out[0] = vid_c[j]; return 1;
     }
   };
-  const int ntype[3] = {c->n_dist, c->n_bend, c->n_tet};
-  std::vector<long long> gpos[3];
-  for (int t = 0; t < 3; ++t) gpos[t].assign(ntype[t], -1);
+  // entry positions per constraint for the per-call compliance fill:
+  // distance, bending, tet, membrane
+  const int ntype[4] = {c->n_dist, c->n_bend, c->n_tet, c->n_tri};
+  std::vector<long long> gpos[4];
+  for (int t = 0; t < 4; ++t) gpos[t].assign(ntype[t], -1);
   std::vector<unsigned char> img;          // constant entries of every LDS group
   size_t fmul_total = 0, rmul_total = 0;   // bytes of the two state images
   std::vector<int> lidx(V, -1);
@@ -1508,7 +1516,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
         for (int k = 0; k < nv; ++k) ref[vv[k]] = 1;
       }
       G.items += si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count;
-      if (si.type == XPBD_TET) G.tet = true;
+      if (si.type == XPBD_TET || si.type == XPBD_TRI) G.heavy = true;
     }
     std::vector<int> raw;
     for (int v = 0; v < V; ++v) if (ref[v]) raw.push_back(gp[v]);
@@ -1610,13 +1618,21 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
                 std::memcpy(ip, &e, sizeof e);
                 break;
               }
+              case XPBD_TRI: {
+                STri<T> e{};
+                for (int k = 0; k < 4; ++k) e.B[k] = (T)mB[(size_t)k * c->n_tri + j];
+                e.l01 = l01;
+                e.l2 = l[2];
+                std::memcpy(ip, &e, sizeof e);
+                break;
+              }
               default: {
                 SCon<T> e{l[0]};
                 std::memcpy(ip, &e, sizeof e);
                 break;
               }
             }
-            if (ty != XPBD_CONTACT) gpos[ty][j] = (long long)(io + i * rec_bytes<T>(ty));
+            if (ty != XPBD_CONTACT) gpos[ty == XPBD_TRI ? 3 : ty][j] = (long long)(io + i * rec_bytes<T>(ty));
           }
           io += al32((size_t)n * rec_bytes<T>(ty));
         }
@@ -1652,7 +1668,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
     c->grmul = (char*)c->alloc(rmul_total);
     HIPCHK(hipMemset(c->gfmul, 0, fmul_total));
     HIPCHK(hipMemset(c->grmul, 0, rmul_total));
-    for (int t = 0; t < 3; ++t)
+    for (int t = 0; t < 4; ++t)
       if (ntype[t]) {
         c->gpos[t] = (long long*)c->alloc(ntype[t] * sizeof(long long));
         c->upload(c->gpos[t], gpos[t]);

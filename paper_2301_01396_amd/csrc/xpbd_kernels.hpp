@@ -1229,22 +1229,25 @@ template <class T> struct SDist { T rest, at; unsigned l; };
 template <class T> struct SBend { T th0, at; unsigned l01, l23; };
 template <class T> struct STet { T B[9]; T atD, atH, gam; unsigned l01, l23; };
 template <class T> struct SCon { unsigned l; };
+template <class T> struct STri { T B[4]; T at[4]; unsigned l01, l2; };   // Dm^-1, at00 at01 at11 at22
 
 __host__ __device__ __forceinline__ size_t al32(size_t b) { return (b + 31) & ~(size_t)31; }
 __device__ __forceinline__ int lo16(unsigned v) { return (int)(v & 0xffffu); }
 __device__ __forceinline__ int hi16(unsigned v) { return (int)(v >> 16); }
 
 template <class T> __host__ __device__ inline size_t rec_bytes(int type) {
-  return type == 0 ? sizeof(SDist<T>) : type == 1 ? sizeof(SBend<T>) : type == 2 ? sizeof(STet<T>) : sizeof(SCon<T>);
+  return type == 0 ? sizeof(SDist<T>) : type == 1 ? sizeof(SBend<T>) : type == 2 ? sizeof(STet<T>)
+         : type == 4 ? sizeof(STri<T>) : sizeof(SCon<T>);
 }
 // words of mutable state per item, each word an array over the set's items:
 // forward lambda (tets lambda_D, lambda_H); reverse lambda_bar and the
 // compliance adjoint (tets lambda_bar_D, lambda_bar_H, the two compliance
 // adjoints and gamma_bar; contacts the sphere adjoint, a Vec4 array, then
-// lambda_bar)
-__host__ __device__ inline size_t fmul_words(int type) { return type == 2 ? 2 : 1; }
-__host__ __device__ inline size_t rmul_words(int type) { return type <= 1 ? 2 : 5; }
-__host__ __device__ inline size_t tape_words(int type) { return type == 1 ? 10 : type == 2 ? 12 : 4; }
+// lambda_bar; membranes three multipliers, then their three adjoints and
+// the four compliance adjoints)
+__host__ __device__ inline size_t fmul_words(int type) { return type == 2 ? 2 : type == 4 ? 3 : 1; }
+__host__ __device__ inline size_t rmul_words(int type) { return type <= 1 ? 2 : type == 4 ? 7 : 5; }
+__host__ __device__ inline size_t tape_words(int type) { return type == 1 ? 10 : type == 2 || type == 4 ? 12 : 4; }
 
 struct GroupDev {
   const int* pv_start;      // [P + 1] patch vertex ranges
@@ -1279,10 +1282,10 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
 // vertices (one bulk copy in, the state copied out); otherwise only the
 // vertex tile is in LDS and each set's entries are read, and its state read
 // and written, in place in the global images, which keeps the workgroup's
-// LDS small so many patches run per CU.  TET: the group has tet sets; the
-// kernels without the tet projection need far fewer registers, so more
-// waves of a cloth group run per SIMD.
-template <class T, bool FIRST, bool TAPE, bool RL, bool TET>
+// LDS small so many patches run per CU.  HEAVY: the group has tet or
+// membrane sets; the kernels without those projections need far fewer
+// registers, so more waves of a distance / bending group run per SIMD.
+template <class T, bool FIRST, bool TAPE, bool RL, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ fmul, char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
@@ -1336,7 +1339,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
         }
         break;
       case 2:
-        if constexpr (TET)
+        if constexpr (HEAVY)
         for (int i = tid; i < n; i += kB) {
           const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
@@ -1348,6 +1351,22 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           tet_fwd<T, TAPE>(pp, B, s.atD, s.atH, s.gam, lD, lH, tape + i, n);
           lam[i] = lD; lam[n + i] = lH;
           sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3];
+        }
+        break;
+      case 4:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+          const STri<T>& s = reinterpret_cast<const STri<T>*>(r)[i];
+          int l[3] = {lo16(s.l01), hi16(s.l01), (int)s.l2};
+          Vec4<T> pp[3] = {sX[l[0]], sX[l[1]], sX[l[2]]};
+          T B[4] = {s.B[0], s.B[1], s.B[2], s.B[3]}, at[4] = {s.at[0], s.at[1], s.at[2], s.at[3]};
+          T lm[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) lm[c] = FIRST ? T(0) : lam[c * n + i];
+          bool moved = tri_fwd<T, TAPE>(pp, B, at, lm, tape, i, n);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) lam[c * n + i] = lm[c];
+          if (moved) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; }
         }
         break;
       default:
@@ -1370,7 +1389,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
   if (RL) copy16(gmul, lrec + rbytes, mbytes);
 }
 
-template <class T, bool FIRST, bool LAST, bool RL, bool TET>
+template <class T, bool FIRST, bool LAST, bool RL, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ rmul, const char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
@@ -1433,7 +1452,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
         }
         break;
       case 2:
-        if constexpr (TET)
+        if constexpr (HEAVY)
         for (int i = tid; i < n; i += kB) {
           const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
@@ -1448,6 +1467,25 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
             sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
           }
           mb[i] = lbD; mb[n + i] = lbH; mb[2 * n + i] = ebD; mb[3 * n + i] = ebH; mb[4 * n + i] = gb;
+        }
+        break;
+      case 4:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+          const STri<T>& s = reinterpret_cast<const STri<T>*>(r)[i];
+          int l[3] = {lo16(s.l01), hi16(s.l01), (int)s.l2};
+          Vec4<T> P[3] = {sX[l[0]], sX[l[1]], sX[l[2]]};
+          T B[4] = {s.B[0], s.B[1], s.B[2], s.B[3]}, at[4] = {s.at[0], s.at[1], s.at[2], s.at[3]};
+          T lbar[3], ab[4];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) lbar[c] = FIRST ? T(0) : mb[c * n + i];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) ab[c] = FIRST ? T(0) : mb[(3 + c) * n + i];
+          if (tri_rev(P, st, i, n, B, at, lbar, ab)) { sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) mb[c * n + i] = lbar[c];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) mb[(3 + c) * n + i] = ab[c];
         }
         break;
       default: {
@@ -1483,11 +1521,18 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
       case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
       case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
       case 2:
-        if constexpr (TET)
+        if constexpr (HEAVY)
         for (int i = tid; i < n; i += kB) {
           D.t_acc[jb + i] += (double)mb[2 * n + i];
           D.t_acc[D.tr.n + jb + i] += (double)mb[3 * n + i];
           D.t_acc[2 * D.tr.n + jb + i] += (double)mb[4 * n + i];
+        }
+        break;
+      case 4:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) D.m_acc[(size_t)c * D.mr.n + jb + i] += (double)mb[(3 + c) * n + i];
         }
         break;
       default: {
@@ -1500,9 +1545,9 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
   }
 }
 
-// copy the per-call compliances (alpha / h^2 and the tet constants) into the
-// constant group image: pos[j] is the byte offset of constraint j's entry,
-// -1 outside LDS groups
+// copy the per-call compliances (alpha / h^2, the tet constants, a membrane's
+// four at entries from at[4][n]) into the constant group image: pos[j] is
+// the byte offset of constraint j's entry, -1 outside LDS groups
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const long long* __restrict__ pos,
                                                        char* __restrict__ img, const T* __restrict__ at,
@@ -1512,6 +1557,12 @@ __global__ __launch_bounds__(kBlock) void k_group_fill(int type, int n, const lo
   switch (type) {
     case 0: reinterpret_cast<SDist<T>*>(img + pos[j])->at = at[j]; break;
     case 1: reinterpret_cast<SBend<T>*>(img + pos[j])->at = at[j]; break;
+    case 4: {
+      STri<T>* f = reinterpret_cast<STri<T>*>(img + pos[j]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) f->at[c] = at[(size_t)c * n + j];
+      break;
+    }
     default: {
       STet<T>* f = reinterpret_cast<STet<T>*>(img + pos[j]);
       f->atD = at[j]; f->atH = atH[j]; f->gam = gam[j];

@@ -123,7 +123,7 @@ def test_null_context_calls_fail_cleanly():
 def test_generated_schedules_are_valid_colorings(maker):
     sc = maker()
     st, off, items = sc.schedule_arrays()
-    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v}
+    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v, scenes.TRI: sc.tri_v}
     seen = {k: np.zeros(len(v), int) for k, v in cv.items()}
     for s in range(len(st)):
         it = items[off[s]:off[s + 1]]
@@ -158,11 +158,13 @@ def test_rejects_groups_whose_constraints_span_patches():
                                    lambda: scenes.tile_cloth_lines(scenes.small_cloth(n=37), 37, 37, 8),
                                    lambda: scenes.tile_cloth_quads(scenes.small_cloth(n=45), 45, 45, 8),
                                    lambda: scenes.tile_cloth_quads(scenes.small_cloth(n=40), 40, 40, 16),
+                                   lambda: scenes.tile_cloth_quads(scenes.membrane_cloth(n=41), 41, 41, 8),
+                                   lambda: scenes.tile_cloth_lines(scenes.membrane_cloth(n=37), 37, 37, 8),
                                    lambda: scenes.tile_box(scenes.small_tets(n=8), 8, 4)])
 def test_tiled_schedules_are_valid_and_grouped(maker):
     sc = maker()
     st, off, items = sc.schedule_arrays()
-    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v}
+    cv = {scenes.DIST: sc.dist_v, scenes.BEND: sc.bend_v, scenes.TET: sc.tet_v, scenes.TRI: sc.tri_v}
     seen = {k: np.zeros(len(v), int) for k, v in cv.items()}
     for s in range(len(st)):
         it = items[off[s]:off[s + 1]]
