@@ -158,7 +158,7 @@ def make_workload(name: str, tile: int = -1, frames: int = 0, lds_groups: str = 
     if name == "c2m":
         return scenes.config_c2_membrane(**kw), scenes.config_c2_membrane(target=True, **kw)
     if name == "c2b":
-        return scenes.config_c2_body(), scenes.config_c2_body(target=True)
+        return scenes.config_c2_body(**kw), scenes.config_c2_body(target=True, **kw)
     if name == "c4":
         if frames:
             kw["n_frames"] = frames

@@ -1079,7 +1079,7 @@ template <class T>
 void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
                   const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
                   const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c,
-                  const std::vector<int4>& midx, const std::vector<double>& mB);
+                  const std::vector<int4>& midx, const std::vector<double>& mB, const std::vector<int>& vid_bc);
 
 void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, const xpbd_schedule_desc* sd,
            const xpbd_options* o) {
@@ -1193,8 +1193,6 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     int64_t b = sd->set_offsets[s], e = sd->set_offsets[s + 1];
     if (e < b) fail(XPBD_ERR_INVALID, "set %d: decreasing offsets", s);
     if (ty < 0 || ty > 5) fail(XPBD_ERR_INVALID, "set %d: bad type", s);
-    if (ty == XPBD_BODY && set_group[s] >= 0)
-      fail(XPBD_ERR_INVALID, "set %d: body-contact sets cannot be part of an LDS group", s);
     if (ty == XPBD_BODY && c->body_nt == 0) fail(XPBD_ERR_INVALID, "set %d: body-contact set without a body", s);
     if (ty == XPBD_CONTACT && !cd->contact) fail(XPBD_ERR_INVALID, "set %d: contact set but contact disabled", s);
     // order items inside the set by patch (grouped sets), then by their
@@ -1434,8 +1432,8 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   c->group_at_start.assign(c->sets.size(), -1);
   c->group_at_end.assign(c->sets.size(), -1);
   if (sd->n_groups > 0 && o->launch_mode != 2) {
-    if (c->dtype == XPBD_F32) build_groups<float>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB);
-    else build_groups<double>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB);
+    if (c->dtype == XPBD_F32) build_groups<float>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB, vid_bc);
+    else build_groups<double>(c, sd, didx, drest, bidx, btheta, tidx, tB, vid_c, midx, mB, vid_bc);
   } else {
     for (int g = 0; g < sd->n_groups; ++g) {
       xpbd_ctx_s::Group G;
@@ -1471,7 +1469,7 @@ template <class T>
 void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<int2>& didx,
                   const std::vector<double>& drest, const std::vector<int4>& bidx, const std::vector<double>& btheta,
                   const std::vector<int4>& tidx, const std::vector<double>& tB, const std::vector<int>& vid_c,
-                  const std::vector<int4>& midx, const std::vector<double>& mB) {
+                  const std::vector<int4>& midx, const std::vector<double>& mB, const std::vector<int>& vid_bc) {
   const int V = c->V;
   {
     int dev = 0, lim = 0, optin = 0;
@@ -1489,6 +1487,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
       case XPBD_BEND: out[0] = bidx[j].x; out[1] = bidx[j].y; out[2] = bidx[j].z; out[3] = bidx[j].w; return 4;
       case XPBD_TET: out[0] = tidx[j].x; out[1] = tidx[j].y; out[2] = tidx[j].z; out[3] = tidx[j].w; return 4;
       case XPBD_TRI: out[0] = midx[j].x; out[1] = midx[j].y; out[2] = midx[j].z; return 3;
+      case XPBD_BODY: out[0] = vid_bc[j]; return 1;
       default: out[0] = vid_c[j]; return 1;
     }
   };
@@ -1516,7 +1515,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
         for (int k = 0; k < nv; ++k) ref[vv[k]] = 1;
       }
       G.items += si.type == XPBD_TET ? 2 * (int64_t)si.count : si.count;
-      if (si.type == XPBD_TET || si.type == XPBD_TRI) G.heavy = true;
+      if (si.type == XPBD_TET || si.type == XPBD_TRI || si.type == XPBD_BODY) G.heavy = true;
     }
     std::vector<int> raw;
     for (int v = 0; v < V; ++v) if (ref[v]) raw.push_back(gp[v]);
@@ -1618,6 +1617,11 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
                 std::memcpy(ip, &e, sizeof e);
                 break;
               }
+              case XPBD_BODY: {
+                SBody<T> e{l[0], j};
+                std::memcpy(ip, &e, sizeof e);
+                break;
+              }
               case XPBD_TRI: {
                 STri<T> e{};
                 for (int k = 0; k < 4; ++k) e.B[k] = (T)mB[(size_t)k * c->n_tri + j];
@@ -1632,7 +1636,8 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
                 break;
               }
             }
-            if (ty != XPBD_CONTACT) gpos[ty == XPBD_TRI ? 3 : ty][j] = (long long)(io + i * rec_bytes<T>(ty));
+            if (ty != XPBD_CONTACT && ty != XPBD_BODY)
+              gpos[ty == XPBD_TRI ? 3 : ty][j] = (long long)(io + i * rec_bytes<T>(ty));
           }
           io += al32((size_t)n * rec_bytes<T>(ty));
         }

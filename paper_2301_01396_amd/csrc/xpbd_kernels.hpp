@@ -604,15 +604,13 @@ __device__ __forceinline__ void tri_item(const Dev<T>& D, int begin, int count, 
   if (moved) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; }
 }
 
-template <class T, bool FIRST, bool TAPE>
-__device__ __forceinline__ void body_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
-  int j = begin + t;
-  int v = D.bc_vid[j];
-  Vec4<T> p = D.X[v];
-  T lb = FIRST ? T(0) : D.bc_lam[j];
-  if (TAPE) tape[t] = Vec4<T>{p.x, p.y, p.z, lb};
-  const int tri = D.bpair[j];
+// one body-contact projection of vertex p against the plane of its paired
+// body triangle (tri < 0: none this substep); returns lambda after it
+template <class T, bool TAPE>
+__device__ __forceinline__ T body_fwd(Vec4<T>& p, T lb, int tri, const Dev<T>& D, Vec4<T>* tape, bool& moved) {
+  if (TAPE) *tape = Vec4<T>{p.x, p.y, p.z, lb};
   T ln = lb;
+  moved = false;
   if (tri >= 0) {
     BodyEval<T> ev = body_eval(xyz(p), D.bx, D.btri[tri], D.bc_tau);
     T Dn = p.w * dot(ev.nh, ev.nh) + D.bc_at;
@@ -621,9 +619,21 @@ __device__ __forceinline__ void body_item(const Dev<T>& D, int begin, int count,
       T s = p.w * dl;
       p.x += s * ev.nh.x; p.y += s * ev.nh.y; p.z += s * ev.nh.z;
       ln = lb + dl;
-      D.X[v] = p;
+      moved = true;
     }
   }
+  return ln;
+}
+
+template <class T, bool FIRST, bool TAPE>
+__device__ __forceinline__ void body_item(const Dev<T>& D, int begin, int count, int t, Vec4<T>* __restrict__ tape) {
+  int j = begin + t;
+  int v = D.bc_vid[j];
+  Vec4<T> p = D.X[v];
+  T lb = FIRST ? T(0) : D.bc_lam[j];
+  bool moved = false;
+  T ln = body_fwd<T, TAPE>(p, lb, D.bpair[j], D, tape + t, moved);
+  if (moved) D.X[v] = p;
   D.bc_lam[j] = ln;
 }
 
@@ -1230,6 +1240,7 @@ template <class T> struct SBend { T th0, at; unsigned l01, l23; };
 template <class T> struct STet { T B[9]; T atD, atH, gam; unsigned l01, l23; };
 template <class T> struct SCon { unsigned l; };
 template <class T> struct STri { T B[4]; T at[4]; unsigned l01, l2; };   // Dm^-1, at00 at01 at11 at22
+template <class T> struct SBody { unsigned l; int j; };   // vertex slot, item (its substep pairing)
 
 __host__ __device__ __forceinline__ size_t al32(size_t b) { return (b + 31) & ~(size_t)31; }
 __device__ __forceinline__ int lo16(unsigned v) { return (int)(v & 0xffffu); }
@@ -1237,16 +1248,16 @@ __device__ __forceinline__ int hi16(unsigned v) { return (int)(v >> 16); }
 
 template <class T> __host__ __device__ inline size_t rec_bytes(int type) {
   return type == 0 ? sizeof(SDist<T>) : type == 1 ? sizeof(SBend<T>) : type == 2 ? sizeof(STet<T>)
-         : type == 4 ? sizeof(STri<T>) : sizeof(SCon<T>);
+         : type == 4 ? sizeof(STri<T>) : type == 5 ? sizeof(SBody<T>) : sizeof(SCon<T>);
 }
 // words of mutable state per item, each word an array over the set's items:
 // forward lambda (tets lambda_D, lambda_H); reverse lambda_bar and the
 // compliance adjoint (tets lambda_bar_D, lambda_bar_H, the two compliance
 // adjoints and gamma_bar; contacts the sphere adjoint, a Vec4 array, then
 // lambda_bar; membranes three multipliers, then their three adjoints and
-// the four compliance adjoints)
+// the four compliance adjoints; body contacts lambda, then lambda_bar)
 __host__ __device__ inline size_t fmul_words(int type) { return type == 2 ? 2 : type == 4 ? 3 : 1; }
-__host__ __device__ inline size_t rmul_words(int type) { return type <= 1 ? 2 : type == 4 ? 7 : 5; }
+__host__ __device__ inline size_t rmul_words(int type) { return type <= 1 ? 2 : type == 4 ? 7 : type == 5 ? 1 : 5; }
 __host__ __device__ inline size_t tape_words(int type) { return type == 1 ? 10 : type == 2 || type == 4 ? 12 : 4; }
 
 struct GroupDev {
@@ -1369,6 +1380,18 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           if (moved) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; }
         }
         break;
+      case 5:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+          const SBody<T> e = reinterpret_cast<const SBody<T>*>(r)[i];
+          Vec4<T> pp = sX[e.l];
+          T l0 = FIRST ? T(0) : lam[i];
+          bool moved = false;
+          T ln = body_fwd<T, TAPE>(pp, l0, D.bpair[e.j], D, tape + i, moved);
+          if (moved) sX[e.l] = pp;
+          lam[i] = ln;
+        }
+        break;
       default:
         for (int i = tid; i < n; i += kB) {
           const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
@@ -1488,6 +1511,19 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
           for (int c = 0; c < 4; ++c) mb[(3 + c) * n + i] = ab[c];
         }
         break;
+      case 5:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+          const SBody<T> e = reinterpret_cast<const SBody<T>*>(r)[i];
+          const int tri = D.bpair[e.j];
+          T lbar = FIRST ? T(0) : mb[i];
+          if (tri >= 0) {
+            Vec4<T> P = sX[e.l];
+            if (body_rev(P, st[i], D.bx, D.btri[tri], D.bc_tau, D.bc_at, lbar, D.bgrad)) sX[e.l] = P;
+          }
+          mb[i] = lbar;
+        }
+        break;
       default: {
         Vec4<T>* sam = reinterpret_cast<Vec4<T>*>(m);
         T* lbm = reinterpret_cast<T*>(sam + n);
@@ -1535,6 +1571,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
           for (int c = 0; c < 4; ++c) D.m_acc[(size_t)c * D.mr.n + jb + i] += (double)mb[(3 + c) * n + i];
         }
         break;
+      case 5: break;   // body-vertex gradients were added during the reverse
       default: {
         const Vec4<T>* sam = reinterpret_cast<const Vec4<T>*>(m);
         for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = sam[i];

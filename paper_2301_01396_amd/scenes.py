@@ -726,16 +726,24 @@ def config_c2_membrane(n_frames: int = 30, target: bool = False, n: int = 256, t
     return sc
 
 
-def config_c2_body(n_frames: int = 30, target: bool = False, n: int = 256, body_res=(64, 128)) -> Scene:
+def config_c2_body(n_frames: int = 30, target: bool = False, n: int = 256, body_res=(64, 128),
+                   tile: int = 16) -> Scene:
     """The 256x256 cloth (distance + bending) falling onto a body collider
     given as a triangle mesh: a UV sphere of 64 x 128 (16,128 triangles)
     standing where the sphere collider is, tau 0.005, alpha 1e-9, search
-    radius 0.02; one body-contact set of every vertex."""
-    sc = config_c2(n_frames=n_frames, target=target, n=n, tile=0)
+    radius 0.02; one body-contact set of every vertex.  tile > 0: the cloth's
+    three-group tiling with the body-contact set in the corner group (where
+    the sphere's contact set sits); 0: untiled sets, one launch each."""
+    sc = config_c2(n_frames=n_frames, target=target, n=n, tile=tile)
     sc.contact = False
-    keep = [(t, it) for t, it in zip(sc.set_type, sc.set_items) if t != CONTACT]
-    sc.set_type = [t for t, _ in keep] + [BODY]
-    sc.set_items = [it for _, it in keep] + [np.nonzero(sc.inv_mass > 0)[0].astype(np.int32)]
+    free = np.nonzero(sc.inv_mass > 0)[0].astype(np.int32)
+    if tile:
+        k = sc.set_type.index(CONTACT)
+        sc.set_type[k], sc.set_items[k] = BODY, free
+    else:
+        keep = [(t, it) for t, it in zip(sc.set_type, sc.set_items) if t != CONTACT]
+        sc.set_type = [t for t, _ in keep] + [BODY]
+        sc.set_items = [it for _, it in keep] + [free]
     bx, bt = uv_sphere((0.0, -0.35, 0.0), 0.3, *body_res)
     sc.body_x, sc.body_tris = bx, bt
     sc.body_thickness, sc.body_compliance, sc.body_radius = 0.005, 1e-9, 0.02

@@ -407,6 +407,42 @@ def test_body_collider_cloth(dtype, pos_tol, grad_tol):
     compare(sc, ref, got, pos_tol, grad_tol)
 
 
+def _tiled_body_cloth(n=25, tile=8):
+    """The line tiling of a small cloth with the body-contact set where the
+    sphere's contact set sits (the corner group)."""
+    sc = scenes.tile_cloth_lines(scenes.small_cloth(n=n, frames=2, substeps=2, iterations=3), n, n, tile)
+    k = sc.set_type.index(scenes.CONTACT)
+    sc.set_type[k] = scenes.BODY
+    sc.contact = False
+    sc.body_x, sc.body_tris = scenes.uv_sphere((0.05, -0.28, -0.03), 0.3, 8, 16)
+    sc.body_thickness, sc.body_compliance, sc.body_radius = 0.01, 1e-8, 0.1
+    return sc
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_body_contacts_in_lds_groups_match_per_set_launches_and_reference(dtype):
+    """Body contacts inside an LDS group: entries staged in LDS, streamed
+    with one wave per patch, and one launch per set pair the same vertices
+    and give the same results (bitwise, except the body-vertex gradient,
+    summed with FP64 atomics); all match the FP64 reference."""
+    sc = _tiled_body_cloth()
+    assert scenes.BODY in {sc.set_type[k] for a, b, _ in sc.groups for k in range(a, b)}
+    ref = reference_case(sc, 2, n_threads=8)
+    assert np.abs(ref["grads"]["body_x"]).max() > 0
+    sims = [_sim(sc, dtype), _sim(sc, dtype, group_records=2, group_block=64), _sim(sc, dtype, use_groups=False)]
+    assert sims[0].info()["n_groups_lds"] == len(sc.groups) and sims[2].info()["n_groups"] == 0
+    outs = [gpu_case(s, 2, ref) for s in sims]
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            if k == "body_x":
+                assert rel(o["grads"][k], v) <= 1e-12, k
+            else:
+                assert np.array_equal(o["grads"][k], v), k
+    tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
+    compare(sc, ref, outs[0], *tol)
+
+
 def test_body_collider_record_modes_agree():
     """Whole-rollout record, per-frame and per-substep recomputation pair the
     vertices the same way and give the same results (bitwise, except the
@@ -426,20 +462,14 @@ def test_body_collider_record_modes_agree():
 
 
 def test_body_collider_validation():
-    """Refused: the persistent kernel, an LDS group, a pack, the implicit
-    adjoint, a body triangle index out of range, a body-contact set without
-    a body."""
+    """Refused: the persistent kernel, a pack, the implicit adjoint, a body
+    triangle index out of range, a body-contact set without a body."""
     import torch
     from paper_2301_01396_amd import lib as L
     from paper_2301_01396_amd.lib import XPBDError, XPBD_ERR_INVALID
     sc = scenes.body_cloth(n=5, frames=1)
     with pytest.raises(XPBDError) as e:
         _sim(sc, "f32", launch_mode=2)
-    assert e.value.status == XPBD_ERR_INVALID
-    grp = scenes.body_cloth(n=5, frames=1)
-    grp.groups = [(len(grp.set_type) - 1, len(grp.set_type), np.zeros(grp.n_verts, np.int32))]
-    with pytest.raises(XPBDError) as e:
-        _sim(grp, "f32")
     assert e.value.status == XPBD_ERR_INVALID
     bad = scenes.body_cloth(n=5, frames=1)
     bad.body_tris = bad.body_tris.copy()
