@@ -160,6 +160,7 @@ def test_rejects_groups_whose_constraints_span_patches():
                                    lambda: scenes.tile_cloth_quads(scenes.small_cloth(n=40), 40, 40, 16),
                                    lambda: scenes.tile_cloth_quads(scenes.membrane_cloth(n=41), 41, 41, 8),
                                    lambda: scenes.tile_cloth_lines(scenes.membrane_cloth(n=37), 37, 37, 8),
+                                   lambda: scenes.config_c2_body(n_frames=1, n=48, body_res=(8, 16), tile=16),
                                    lambda: scenes.tile_box(scenes.small_tets(n=8), 8, 4)])
 def test_tiled_schedules_are_valid_and_grouped(maker):
     sc = maker()
@@ -168,8 +169,9 @@ def test_tiled_schedules_are_valid_and_grouped(maker):
     seen = {k: np.zeros(len(v), int) for k, v in cv.items()}
     for s in range(len(st)):
         it = items[off[s]:off[s + 1]]
-        verts = it[:, None] if st[s] == scenes.CONTACT else cv[st[s]][it]
-        if st[s] != scenes.CONTACT:
+        point = st[s] in (scenes.CONTACT, scenes.BODY)
+        verts = it[:, None] if point else cv[st[s]][it]
+        if not point:
             seen[st[s]][it] += 1
         assert len(np.unique(verts)) == verts.size
     for v in seen.values():
@@ -179,7 +181,7 @@ def test_tiled_schedules_are_valid_and_grouped(maker):
         for s in range(a, b):
             covered.add(s)
             it = items[off[s]:off[s + 1]]
-            verts = it[:, None] if st[s] == scenes.CONTACT else cv[st[s]][it]
+            verts = it[:, None] if st[s] in (scenes.CONTACT, scenes.BODY) else cv[st[s]][it]
             pc = pm[verts]
             assert np.all(pc == pc[:, :1])
     assert covered == set(range(len(st)))
