@@ -625,6 +625,10 @@ def main():
             roof["path"] = {"bytes_per_step": round(pb), "achieved": round(pb / sec / 1e9, 1),
                             "frac": round(pb / sec / 1e9 / HBM_PEAK_GBS, 4), "frames_run_forward": frames_fwd}
         roof["adjoint_streams"] = info["adjoint_streams"]
+        if info["adjoint_streams"] == 2:
+            roof["note"] = ("the adjoint recomputes earlier frames on a second stream beside the reverse, so those "
+                            "launches share the GPU and the per-launch figures above are shared rates; 'path' is "
+                            "every projection's algorithmic bytes over the step time")
 
     cpu = None
     if not args.no_cpu_baseline:
