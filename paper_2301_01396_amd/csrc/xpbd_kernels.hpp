@@ -78,17 +78,20 @@ template <class T> struct Dev {
 // Each core works on register copies of one constraint's vertices and
 // record, so the same arithmetic serves vertex state in global memory and
 // vertex tiles in LDS.  Forward cores return lambda after the projection
-// (lambda before when it is skipped) and optionally emit the adjoint's
-// record; reverse cores update the vertex adjoints, lambda_bar and the
-// compliance adjoint in place.
+// (lambda before when it is skipped), set `moved` when the projection was
+// applied (its vertex copies then hold x + w dlambda grad C and must be
+// stored, even where dlambda vanished when added to lambda) and optionally
+// emit the adjoint's record; reverse cores update the vertex adjoints,
+// lambda_bar and the compliance adjoint in place.
 
 template <class T, bool TAPE>
-__device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T lb, Vec4<T>* tape) {
+__device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T lb, Vec4<T>* tape, bool& moved) {
   V3<T> r = xyz(a) - xyz(b);
   if (TAPE) *tape = Vec4<T>{r.x, r.y, r.z, lb};
   DistEval<T> ev = dist_eval(r, rest);
   T Dn = a.w + b.w + a_t;
-  if (!ev.ok || !(Dn > T(0))) return lb;
+  moved = ev.ok && Dn > T(0);
+  if (!moved) return lb;
   T dl = (-ev.C - a_t * lb) / Dn;
   T sa = a.w * dl, sb = b.w * dl;
   a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
@@ -100,7 +103,8 @@ __device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T l
 // tape[count + t], Vec2 (b.y, b.z) at element t of the Vec2 array that
 // starts at tape + 2 * count
 template <class T, bool TAPE>
-__device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<T>* tape, int t, int count) {
+__device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<T>* tape, int t, int count,
+                                      bool& moved) {
   V3<T> e = xyz(p[1]) - xyz(p[0]), a = xyz(p[2]) - xyz(p[0]), b = xyz(p[3]) - xyz(p[0]);
   if (TAPE) {
     tape[t] = Vec4<T>{e.x, e.y, e.z, lb};
@@ -111,7 +115,8 @@ __device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += p[k].w * dot(ev.g[k], ev.g[k]);
-  if (!ev.ok || !(Dn > T(0))) return lb;
+  moved = ev.ok && Dn > T(0);
+  if (!moved) return lb;
   T dl = (-ev.C - a_t * lb) / Dn;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -186,11 +191,12 @@ __device__ __forceinline__ void tet_fwd(Vec4<T> p[4], const M3<T>& B, T atD, T a
 }
 
 template <class T, bool TAPE>
-__device__ __forceinline__ T contact_fwd(Vec4<T>& p, const Sphere<T>& S, T lb, Vec4<T>* tape) {
+__device__ __forceinline__ T contact_fwd(Vec4<T>& p, const Sphere<T>& S, T lb, Vec4<T>* tape, bool& moved) {
   if (TAPE) *tape = Vec4<T>{p.x, p.y, p.z, lb};
   ContactEval<T> ev = contact_eval(V3<T>{p.x - S.cx, p.y - S.cy, p.z - S.cz}, S.R, S.tau);
   T Dn = p.w + S.at;
-  if (!ev.ok || !(ev.C < T(0)) || !(Dn > T(0))) return lb;
+  moved = ev.ok && ev.C < T(0) && Dn > T(0);
+  if (!moved) return lb;
   T dl = (-ev.C - S.at * lb) / Dn;
   T s = p.w * dl;
   p.x += s * ev.n.x; p.y += s * ev.n.y; p.z += s * ev.n.z;
@@ -545,9 +551,10 @@ __device__ __forceinline__ void dist_item(const Dev<T>& D, int begin, int count,
   int2 e = D.d_idx[j];
   Vec4<T> a = D.X[e.x], b = D.X[e.y];
   T lb = FIRST ? T(0) : D.d_lam[j];
-  T ln = dist_fwd<T, TAPE>(a, b, D.d_rest[j], D.d_at[j], lb, tape + t);
+  bool moved;
+  T ln = dist_fwd<T, TAPE>(a, b, D.d_rest[j], D.d_at[j], lb, tape + t, moved);
   D.d_lam[j] = ln;
-  if (ln != lb) { D.X[e.x] = a; D.X[e.y] = b; }
+  if (moved) { D.X[e.x] = a; D.X[e.y] = b; }
 }
 
 template <class T, bool FIRST, bool TAPE>
@@ -556,9 +563,10 @@ __device__ __forceinline__ void bend_item(const Dev<T>& D, int begin, int count,
   int4 q = D.b_idx[j];
   Vec4<T> p[4] = {D.X[q.x], D.X[q.y], D.X[q.z], D.X[q.w]};
   T lb = FIRST ? T(0) : D.b_lam[j];
-  T ln = bend_fwd<T, TAPE>(p, D.b_th0[j], D.b_at[j], lb, tape, t, count);
+  bool moved;
+  T ln = bend_fwd<T, TAPE>(p, D.b_th0[j], D.b_at[j], lb, tape, t, count, moved);
   D.b_lam[j] = ln;
-  if (ln != lb) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3]; }
+  if (moved) { D.X[q.x] = p[0]; D.X[q.y] = p[1]; D.X[q.z] = p[2]; D.X[q.w] = p[3]; }
 }
 
 template <class T, bool FIRST, bool TAPE>
@@ -581,9 +589,10 @@ __device__ __forceinline__ void contact_item(const Dev<T>& D, int begin, int cou
   int v = D.c_vid[j];
   Vec4<T> p = D.X[v];
   T lb = FIRST ? T(0) : D.c_lam[j];
-  T ln = contact_fwd<T, TAPE>(p, D.sph, lb, tape + t);
+  bool moved;
+  T ln = contact_fwd<T, TAPE>(p, D.sph, lb, tape + t, moved);
   D.c_lam[j] = ln;
-  if (ln != lb) D.X[v] = p;
+  if (moved) D.X[v] = p;
 }
 
 template <class T, bool FIRST, bool TAPE>
@@ -1333,8 +1342,9 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           int la = lo16(s.l), lb = hi16(s.l);
           Vec4<T> a = sX[la], bb = sX[lb];
           T l0 = FIRST ? T(0) : lam[i];
-          T ln = dist_fwd<T, TAPE>(a, bb, s.rest, s.at, l0, tape + i);
-          if (ln != l0) { sX[la] = a; sX[lb] = bb; }
+          bool moved;
+          T ln = dist_fwd<T, TAPE>(a, bb, s.rest, s.at, l0, tape + i, moved);
+          if (moved) { sX[la] = a; sX[lb] = bb; }
           lam[i] = ln;
         }
         break;
@@ -1344,8 +1354,9 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
           Vec4<T> pp[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
           T l0 = FIRST ? T(0) : lam[i];
-          T ln = bend_fwd<T, TAPE>(pp, s.th0, s.at, l0, tape, i, n);
-          if (ln != l0) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3]; }
+          bool moved;
+          T ln = bend_fwd<T, TAPE>(pp, s.th0, s.at, l0, tape, i, n, moved);
+          if (moved) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3]; }
           lam[i] = ln;
         }
         break;
@@ -1397,8 +1408,9 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
           Vec4<T> pp = sX[l];
           T l0 = FIRST ? T(0) : lam[i];
-          T ln = contact_fwd<T, TAPE>(pp, D.sph, l0, tape + i);
-          if (ln != l0) sX[l] = pp;
+          bool moved;
+          T ln = contact_fwd<T, TAPE>(pp, D.sph, l0, tape + i, moved);
+          if (moved) sX[l] = pp;
           lam[i] = ln;
         }
         break;

@@ -511,3 +511,44 @@ def test_merged_border_patches_give_the_same_bits():
         for k, v in a["grads"].items():
             assert np.array_equal(o["grads"][k], v), k
     compare(a_sc, ref, a, 1e-5, 1e-3)
+
+
+def _collapsing_chain():
+    """Three particles joined by two stiff distance constraints (rest length
+    1 mm), started 100 m apart: the first iteration builds multipliers near
+    -50 while the chain collapses to millimetres around the origin, so later
+    Gauss-Seidel corrections dlambda fall below half an FP32 ulp of lambda
+    (they vanish when added to it) while w dlambda grad C stays far above an
+    ulp of the millimetre coordinates."""
+    rest = np.array([[-1e-3, 0.0, 0.0], [0.0, 0.0, 0.0], [1e-3, 0.0, 0.0]])
+    z = np.zeros((0, 4), np.int32)
+    sc = scenes.Scene(rest=rest, inv_mass=np.ones(3), dist_v=np.array([[0, 1], [1, 2]], np.int32),
+                      bend_v=z, tet_v=z, tet_nu=np.zeros(0))
+    sc.set_type = [scenes.DIST, scenes.DIST]
+    sc.set_items = [np.array([0], np.int32), np.array([1], np.int32)]
+    sc.dist_alpha = np.full(2, 1e-9 / 3600.0)
+    sc.bend_alpha = np.zeros(0)
+    sc.tet_E = np.zeros(0)
+    sc.gravity = (0.0, 0.0, 0.0)
+    sc.x0 = np.array([[-50.0, 0.0, 0.0], [0.0, 3e-3, 0.0], [50.0, 0.0, 0.0]])
+    sc.v0 = np.zeros((3, 3))
+    sc.dt, sc.substeps, sc.iterations, sc.n_frames = 1.0 / 60.0, 1, 30, 1
+    return sc
+
+
+@pytest.mark.parametrize("groups", [False, True])
+def test_fp32_applies_corrections_that_vanish_in_lambda(groups):
+    """Eq. xpbd moves the vertices by w dlambda grad C on every applied
+    projection, also when lambda + dlambda rounds back to lambda in FP32.
+    Skipping those stores leaves the FP32 chain about 8e-4 (relative) away
+    from the FP64 reference; applying them keeps it within 1e-5 (one launch
+    per set, and the same sets as one LDS group).  Positions only: the
+    forward's store is what this case checks."""
+    sc = _collapsing_chain()
+    if groups:
+        sc.groups = [(0, 2, np.zeros(3, np.int32))]
+    ref = reference_case(sc, 1, noise=1e-4)
+    sim = _sim(sc, "f32")
+    assert sim.info()["n_groups_lds"] == (1 if groups else 0)
+    got = gpu_case(sim, 1, ref)
+    compare(sc, ref, got, 1e-5, 1e-3, groups=())

@@ -96,10 +96,9 @@ def test_implicit_without_projection_reports_an_indefinite_system():
     sc = _hanging()
     sim = L.Simulator(sc, dtype=torch.float64)
     sim.forward(6)
-    try:
+    with pytest.raises(L.XPBDError) as e:
         sim.adjoint_implicit(sim.tensor(np.ones((6, sc.n_verts, 3))), max_iterations=4000, rel_tolerance=1e-13)
-    except L.XPBDError as e:
-        assert e.status == L.XPBD_ERR_SOLVER
+    assert e.value.status == L.XPBD_ERR_SOLVER
     sim.close()
 
 
