@@ -307,6 +307,21 @@ xpbd_status xpbd_goal_weighted(xpbd_ctx ctx, const void* x_frames, const void* t
                                const uint8_t* frame_mask, const double* vertex_weight, int32_t n_frames,
                                double* loss, void* dLdx, void* stream);
 
+/* xpbd_goal_weighted for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, with the
+ * reduction's partial sums in a static device array of the library (16 MiB
+ * per GPU, held until the process ends) instead of a buffer the context
+ * allocates.  It calls no hipMalloc or hipFree.  Limit: ceil(3 V / 256) *
+ * n_frames <= 2^21 partial sums (for example 20 frames of 8.4M vertices),
+ * else XPBD_ERR_INVALID.  The current device must be the one the context was
+ * created on (else XPBD_ERR_INVALID).  Every call on a GPU shares its array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * contexts or threads) race and must be ordered by the caller. */
+xpbd_status xpbd_goal_weighted_noalloc(xpbd_ctx ctx, const void* x_frames, const void* targets,
+                                       const uint8_t* frame_mask, const double* vertex_weight, int32_t n_frames,
+                                       double* loss, void* dLdx, void* stream);
+
 /* Implicit adjoint of Sec. 4.2 (Eq. adjointXPBD) for the preceding
  * xpbd_forward, the paper's own derivative: each substep's projection is
  * taken as converged, x = y + M^-1 sum_j grad C_j lambda_j with lambda_j =

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,8 +78,23 @@ struct DevBuf {
 
 }  // namespace
 
+// Partial sums of the goal reduction for xpbd_goal_weighted_noalloc: a
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of memory the context allocates.  On the host `scratch` names a
+// stand-in, not a device address: kernels get the address that
+// hipGetSymbolAddress returned for the device, kept in g_scratch_addr.
+constexpr size_t kGoalScratchDoubles = (size_t)1 << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[kGoalScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
 struct xpbd_ctx_s {
   std::string err;
+  int device = 0;   // the GPU the context was created on
   xpbd_dtype dtype;
   size_t tsz;
   int V = 0, n_dist = 0, n_bend = 0, n_tet = 0, n_contact = 0, n_tri = 0;
@@ -1059,16 +1075,22 @@ template <class T> struct Ops {
 
   static void goal(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, const double* wv, int F,
                    double* loss, void* dLdx, hipStream_t st) {
+    ensure_parts(c, F);
+    goal_into(c, xf, tg, mask, wv, F, loss, dLdx, c->parts, st);
+  }
+
+  // parts: device [nblocks(3 V) * F] partial sums, each written before read
+  static void goal_into(xpbd_ctx c, const void* xf, const void* tg, const uint8_t* mask, const double* wv, int F,
+                        double* loss, void* dLdx, double* parts, hipStream_t st) {
     const size_t n = (size_t)3 * c->V;
     const size_t nb = nblocks(n);
-    ensure_parts(c, F);
     for (int f = 0; f < F; ++f) {
       int on = mask ? (mask[f] != 0) : 1;
       k_goal<T><<<nb, kBlock, 0, st>>>((const T*)xf + f * n, (const T*)tg + f * n, wv,
-                                       dLdx ? (T*)dLdx + f * n : nullptr, n, on, c->parts + f * nb);
+                                       dLdx ? (T*)dLdx + f * n : nullptr, n, on, parts + f * nb);
     }
     check_launch();
-    if (loss) k_sum_parts<<<1, 1024, 0, st>>>(c->parts, nb * F, loss, 0);
+    if (loss) k_sum_parts<<<1, 1024, 0, st>>>(parts, nb * F, loss, 0);
     check_launch();
   }
 };
@@ -1797,8 +1819,18 @@ xpbd_status xpbd_create(const xpbd_mesh_desc* mesh, const xpbd_constraint_desc* 
     return XPBD_ERR_OOM;
   }
   xpbd_status st = guarded(c, [&] {
-    build(c, mesh, cons, schedule, opt);
+    build(c, mesh, cons, schedule, opt);   // validates everything before it touches the device
     choose_launch(c, opt);
+    HIPCHK(hipGetDevice(&c->device));
+    if (c->device < 0 || c->device >= kMaxDevices) fail(XPBD_ERR_INVALID, "device %d out of range", c->device);
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (!g_scratch_addr[c->device]) {
+        void* a = nullptr;
+        HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        g_scratch_addr[c->device] = (double*)a;
+      }
+    }
   });
   if (st != XPBD_OK) {
     g_create_err = c->err;
@@ -1929,6 +1961,29 @@ xpbd_status xpbd_goal_weighted(xpbd_ctx c, const void* x_frames, const void* tar
 xpbd_status xpbd_goal_l2(xpbd_ctx c, const void* x_frames, const void* targets, const uint8_t* frame_mask,
                          int32_t n_frames, double* loss, void* dLdx, void* stream) {
   return xpbd_goal_weighted(c, x_frames, targets, frame_mask, nullptr, n_frames, loss, dLdx, stream);
+}
+
+xpbd_status xpbd_goal_weighted_noalloc(xpbd_ctx c, const void* x_frames, const void* targets,
+                                       const uint8_t* frame_mask, const double* vertex_weight, int32_t n_frames,
+                                       double* loss, void* dLdx, void* stream) {
+  if (!c) return XPBD_ERR_INVALID;
+  return guarded(c, [&] {
+    if (!x_frames || !targets || n_frames < 1) fail(XPBD_ERR_INVALID, "goal: null argument");
+    const size_t need = (size_t)nblocks((size_t)3 * c->V) * (size_t)n_frames;
+    if (need > kGoalScratchDoubles)
+      fail(XPBD_ERR_INVALID, "goal_noalloc: %zu partial sums (3 V / %d per frame x %d frames) exceed the %zu of "
+           "the static scratch", need, kBlock, n_frames, kGoalScratchDoubles);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != c->device) fail(XPBD_ERR_INVALID, "goal_noalloc: current device %d, context on device %d", dev,
+                               c->device);
+    double* parts = g_scratch_addr[c->device];
+    hipStream_t st = (hipStream_t)stream;
+    if (c->dtype == XPBD_F32)
+      Ops<float>::goal_into(c, x_frames, targets, frame_mask, vertex_weight, n_frames, loss, dLdx, parts, st);
+    else
+      Ops<double>::goal_into(c, x_frames, targets, frame_mask, vertex_weight, n_frames, loss, dLdx, parts, st);
+  });
 }
 
 xpbd_status xpbd_get_info(xpbd_ctx c, xpbd_info* info) {

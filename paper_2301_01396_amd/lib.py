@@ -25,7 +25,8 @@ PACK_GRAPHS = 1
 EXPORTS = ("xpbd_create", "xpbd_destroy", "xpbd_forward", "xpbd_adjoint", "xpbd_goal_l2",
            "xpbd_get_info", "xpbd_profile_enable", "xpbd_profile_read", "xpbd_last_error",
            "xpbd_status_string", "xpbd_pack_create", "xpbd_pack_destroy", "xpbd_pack_add", "xpbd_pack_run",
-           "xpbd_pack_get_stats", "xpbd_pack_last_error", "xpbd_adjoint_implicit", "xpbd_goal_weighted")
+           "xpbd_pack_get_stats", "xpbd_pack_last_error", "xpbd_adjoint_implicit", "xpbd_goal_weighted",
+           "xpbd_goal_weighted_noalloc")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -129,6 +130,9 @@ def load() -> C.CDLL:
         lib.xpbd_goal_l2.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), C.c_int32, _vp, _vp, _vp]
         lib.xpbd_goal_weighted.restype = C.c_int
         lib.xpbd_goal_weighted.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, C.c_int32, _vp, _vp, _vp]
+        lib.xpbd_goal_weighted_noalloc.restype = C.c_int
+        lib.xpbd_goal_weighted_noalloc.argtypes = [_vp, _vp, _vp, C.POINTER(C.c_uint8), _vp, C.c_int32, _vp, _vp,
+                                                   _vp]
         lib.xpbd_get_info.restype = C.c_int
         lib.xpbd_get_info.argtypes = [_vp, C.POINTER(Info)]
         lib.xpbd_profile_enable.restype = C.c_int
@@ -444,6 +448,21 @@ class Simulator:
                                        _stream_ptr(self.device))
         self._check(rc)
         return loss, dL
+
+    def goal_noalloc(self, x_frames: torch.Tensor, targets: torch.Tensor, loss: torch.Tensor, dLdx=None,
+                     frame_mask=None, vertex_weight=None, n_frames=None):
+        """The goal of goal_l2 through the entry point that allocates no device
+        memory: the caller passes the outputs (loss: float64 scalar on the
+        device; dLdx: like x_frames, or None).  n_frames overrides the frame
+        count given to the library (default: x_frames.shape[0])."""
+        F = x_frames.shape[0] if n_frames is None else int(n_frames)
+        mask_arr = None if frame_mask is None else np.ascontiguousarray(np.asarray(frame_mask, np.uint8))
+        mp = None if mask_arr is None else mask_arr.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = self.lib.xpbd_goal_weighted_noalloc(self._ctx, _ptr(x_frames), _ptr(targets), mp,
+                                                 None if vertex_weight is None else _ptr(vertex_weight), F,
+                                                 _ptr(loss), None if dLdx is None else _ptr(dLdx),
+                                                 _stream_ptr(self.device))
+        self._check(rc)
 
     def info(self) -> Dict[str, int]:
         i = Info()
