@@ -22,6 +22,11 @@ def library_path() -> str:
     return _LIB
 
 
+# XPBD_ORACLE_LIB names another build of the reference to load instead (the
+# test suite loads copies with planted mistakes to show that its pins fail).
+_OVERRIDE = os.environ.get("XPBD_ORACLE_LIB")
+
+
 def build_library(verbose: bool = False) -> str:
     """Compile the reference with g++ (-O3, OpenMP, no fast-math)."""
     cmd = ["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-shared",
@@ -68,13 +73,15 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build_library()
-        lib = C.CDLL(_LIB)
+        if _OVERRIDE:
+            lib = C.CDLL(_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build_library()
+            lib = C.CDLL(_LIB)
         lib.orc_forward.restype = C.c_int
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint_implicit.restype = C.c_int
-        lib.orc_psd_project.restype = C.c_int
         lib.orc_constraint.restype = C.c_int
         lib.orc_rest_data.restype = C.c_int
         lib.orc_max_threads.restype = C.c_int
@@ -235,13 +242,30 @@ def point_triangle_d2(p, tri):
 
 
 def psd_project(a):
-    """Projection of a symmetric matrix onto the PSD cone (Jacobi eigen)."""
-    a = np.array(a, np.float64, order="C")
-    n = a.shape[0]
-    rc = _load().orc_psd_project(C.c_int(n), _d(a))
-    if rc:
-        raise RuntimeError(f"orc_psd_project failed ({rc})")
-    return a
+    """Projection of a symmetric matrix onto the positive semidefinite cone,
+    from its definition: eigen-decomposition (numpy.linalg.eigh), negative
+    eigenvalues set to zero, matrix rebuilt (Sec. 4.3 projects each
+    constraint's derivative block this way, in the subsection after
+    Derivative Verification)."""
+    a = np.asarray(a, np.float64)
+    lam, vec = np.linalg.eigh(0.5 * (a + a.T))
+    return (vec * np.maximum(lam, 0.0)) @ vec.T
+
+
+_PSD_FN = C.CFUNCTYPE(C.c_int, C.c_int, _dp)
+
+
+def _psd_callback(n, ptr):
+    """psd_project in place on the reference's n x n row-major block."""
+    try:
+        a = np.ctypeslib.as_array(ptr, shape=(n * n,)).reshape(n, n)
+        a[:] = psd_project(a)
+        return 0
+    except Exception:
+        return 1
+
+
+_PSD_C = _PSD_FN(_psd_callback)
 
 
 def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, pd: bool = False, **params):
@@ -259,7 +283,7 @@ def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, pd
     rc = _load().orc_adjoint_implicit(C.byref(osc.s), C.byref(p), n_frames, _d(x0), _d(v0),
                                       _d(dLdx), _d(g["x0"]), _d(g["v0"]),
                                       _d(g["dist_alpha"]), _d(g["bend_alpha"]), _d(g["f_ext"]),
-                                      C.c_int(1 if pd else 0))
+                                      C.c_int(1 if pd else 0), _PSD_C)
     if rc:
         raise RuntimeError(f"orc_adjoint_implicit failed ({rc})")
     return g

@@ -215,38 +215,38 @@ template <class S> S c_body(const V3<S>& x, const V3<S>& a, const V3<S>& b, cons
   return dot(n, sub(x, a)) / sqrt(n2) - tau;
 }
 
-// Squared distance from p to the closest point of triangle (a, b, c): the
-// closest point is a vertex, a point on an edge or the projection into the
-// face, found from the barycentric regions of p's projection.
+// Squared distance from p to the segment [a, b]: to the orthogonal
+// projection of p onto the segment's line, clamped to the segment.
+double point_segment_d2(const V3<double>& p, const V3<double>& a, const V3<double>& b) {
+  V3<double> ab = sub(b, a);
+  double L2 = dot(ab, ab);
+  double t = L2 > 0.0 ? dot(sub(p, a), ab) / L2 : 0.0;
+  t = std::min(1.0, std::max(0.0, t));
+  V3<double> r = sub(p, {a.x + t * ab.x, a.y + t * ab.y, a.z + t * ab.z});
+  return dot(r, r);
+}
+
+// Squared distance from p to triangle (a, b, c), from the definition of the
+// distance to a set: when the orthogonal projection q of p onto the
+// triangle's plane lies in the triangle (the signed areas of q with each edge
+// all have the sign of the triangle's) the distance is |p - q|; otherwise the
+// closest point is on the boundary, and the distance is the least of the
+// distances to the three edges.
 double point_triangle_d2(const V3<double>& p, const V3<double>& a, const V3<double>& b, const V3<double>& c) {
-  V3<double> ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
-  double d1 = dot(ab, ap), d2 = dot(ac, ap);
-  auto dist2 = [&](const V3<double>& q) { V3<double> r = sub(p, q); return dot(r, r); };
-  if (d1 <= 0.0 && d2 <= 0.0) return dist2(a);
-  V3<double> bp = sub(p, b);
-  double d3 = dot(ab, bp), d4 = dot(ac, bp);
-  if (d3 >= 0.0 && d4 <= d3) return dist2(b);
-  double vc = d1 * d4 - d3 * d2;
-  if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
-    double t = d1 / (d1 - d3);
-    return dist2({a.x + t * ab.x, a.y + t * ab.y, a.z + t * ab.z});
+  V3<double> n = cross(sub(b, a), sub(c, a));
+  double nn = dot(n, n);
+  if (nn > 0.0) {
+    double s = dot(sub(p, a), n) / nn;
+    V3<double> q = {p.x - s * n.x, p.y - s * n.y, p.z - s * n.z};
+    double wa = dot(cross(sub(b, q), sub(c, q)), n);
+    double wb = dot(cross(sub(c, q), sub(a, q)), n);
+    double wc = dot(cross(sub(a, q), sub(b, q)), n);
+    if (wa >= 0.0 && wb >= 0.0 && wc >= 0.0) {
+      V3<double> r = sub(p, q);
+      return dot(r, r);
+    }
   }
-  V3<double> cp = sub(p, c);
-  double d5 = dot(ab, cp), d6 = dot(ac, cp);
-  if (d6 >= 0.0 && d5 <= d6) return dist2(c);
-  double vb = d5 * d2 - d1 * d6;
-  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
-    double t = d2 / (d2 - d6);
-    return dist2({a.x + t * ac.x, a.y + t * ac.y, a.z + t * ac.z});
-  }
-  double va = d3 * d6 - d5 * d4;
-  if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
-    double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-    return dist2({b.x + t * (c.x - b.x), b.y + t * (c.y - b.y), b.z + t * (c.z - b.z)});
-  }
-  double den = 1.0 / (va + vb + vc);
-  double v = vb * den, w = vc * den;
-  return dist2({a.x + v * ab.x + w * ac.x, a.y + v * ab.y + w * ac.y, a.z + v * ab.z + w * ac.z});
+  return std::min(point_segment_d2(p, a, b), std::min(point_segment_d2(p, b, c), point_segment_d2(p, c, a)));
 }
 
 // ------------------------------------------------------------------ scene ABI
@@ -530,14 +530,21 @@ void body_detect(const Ctx& c, const double* x) {
   for (int k = 0; k < s->n_verts; ++k) {
     if (c.m.body_slot[k] < 0) continue;
     V3<double> p = {x[3 * k], x[3 * k + 1], x[3 * k + 2]};
-    int best = -1;
-    double bd = 0.0;
+    // the least distance, then the lowest-index triangle within a rounding
+    // margin of it (a point nearest to an edge or corner shared by several
+    // triangles is equally near to each of them)
+    std::vector<double> d2(s->n_body_tris);
+    double bd = INFINITY;
     for (int t = 0; t < s->n_body_tris; ++t) {
       const int32_t* q = s->body_tris + 3 * (int64_t)t;
-      double d2 = point_triangle_d2(p, body_vtx(c, q[0]), body_vtx(c, q[1]), body_vtx(c, q[2]));
-      if (best < 0 || d2 < bd) { best = t; bd = d2; }
+      d2[t] = point_triangle_d2(p, body_vtx(c, q[0]), body_vtx(c, q[1]), body_vtx(c, q[2]));
+      bd = std::min(bd, d2[t]);
     }
-    pr[k] = (best >= 0 && bd <= r2) ? best : -1;
+    int best = -1;
+    if (bd <= r2)
+      for (int t = 0; t < s->n_body_tris && best < 0; ++t)
+        if (d2[t] <= bd * (1.0 + 1e-9) + 1e-20) best = t;
+    pr[k] = best;
   }
 }
 
@@ -1160,65 +1167,18 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
 // lambda_j = -C_j / alpha~_j at the end-of-substep state (contacts active
 // where C < 0 there).  Same outputs as orc_adjoint for the compliances of
 // distance and bending rows, x0, v0 and f.
-// Projection of a symmetric n x n matrix (row-major, in place) onto the
-// positive semidefinite cone: eigen-decomposition by cyclic Jacobi rotations,
-// negative eigenvalues set to zero, matrix rebuilt (Sec. 4.3.3 projects the
-// derivative blocks this way before the CG solve).
-int orc_psd_project(int n, double* a) {
-  if (n < 1 || n > NG) return 1;
-  std::vector<double> A(a, a + (size_t)n * n), Vm((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Vm[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
-        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
-      }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int pp = 0; pp < n - 1; ++pp)
-      for (int q = pp + 1; q < n; ++q) {
-        double apq = A[(size_t)pp * n + q];
-        if (apq == 0.0) continue;
-        // rotation angle that zeroes A[p][q]: tan(2 phi) = 2 apq / (aqq - app)
-        double theta = (A[(size_t)q * n + q] - A[(size_t)pp * n + pp]) / (2.0 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < n; ++k) {   // A <- A J (columns p, q)
-          double akp = A[(size_t)k * n + pp], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + pp] = cs * akp - sn * akq;
-          A[(size_t)k * n + q] = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < n; ++k) {   // A <- J^T A (rows p, q)
-          double apk = A[(size_t)pp * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)pp * n + k] = cs * apk - sn * aqk;
-          A[(size_t)q * n + k] = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < n; ++k) {   // V <- V J
-          double vkp = Vm[(size_t)k * n + pp], vkq = Vm[(size_t)k * n + q];
-          Vm[(size_t)k * n + pp] = cs * vkp - sn * vkq;
-          Vm[(size_t)k * n + q] = sn * vkp + cs * vkq;
-        }
-      }
-  }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double acc = 0.0;
-      for (int k = 0; k < n; ++k) {
-        double lk = A[(size_t)k * n + k];
-        if (lk > 0.0) acc += Vm[(size_t)i * n + k] * lk * Vm[(size_t)j * n + k];
-      }
-      a[(size_t)i * n + j] = acc;
-    }
-  return 0;
-}
-
 // pd != 0: each constraint's Hessian block -lambda_j Hess C_j is projected to
-// positive semidefinite before assembly (the rank-one block grad C grad C^T /
-// alpha~ is already), so the system is symmetric positive definite.
+// positive semidefinite before assembly (Sec. 4.3, the subsection after
+// Derivative Verification; the rank-one block grad C grad C^T / alpha~ is
+// already), so the system is symmetric positive definite.
+// psd: with pd != 0, replaces the symmetric n x n matrix a (row-major) by its
+// projection onto the positive semidefinite cone in place and returns 0; the
+// caller supplies it (eigen-decomposition with negative eigenvalues dropped).
+typedef int (*orc_psd_fn)(int n, double* a);
 int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const double* x0, const double* v0,
                          const double* dLdx, double* g_x0, double* g_v0, double* g_dist_alpha,
-                         double* g_bend_alpha, double* g_f, int pd) {
+                         double* g_bend_alpha, double* g_f, int pd, orc_psd_fn psd) {
+  if (pd && !psd) return 1;
   if (s->n_tri > 0 || s->n_body_tris > 0) return 2;   // membrane triangles: not part of the converged-limit cross-check
   Ctx c;
   if (build_model(s, &c.m)) return 1;
@@ -1292,7 +1252,7 @@ int orc_adjoint_implicit(const orc_scene* s, const orc_params* p, int F, const d
           // symmetrise exactly, then project
           for (int i = 0; i < nl; ++i)
             for (int j = i + 1; j < nl; ++j) N[i * nl + j] = N[j * nl + i] = 0.5 * (N[i * nl + j] + N[j * nl + i]);
-          if (orc_psd_project(nl, N)) return 5;
+          if (psd(nl, N)) return 5;
         }
         for (int k2 = 0; k2 < r.nv; ++k2)
           for (int b2 = 0; b2 < 3; ++b2) {

@@ -1016,8 +1016,10 @@ struct BodyGrid {
   const int* tris;   // cell lists
 };
 
-// squared distance from p to triangle (a, b, c): closest point by the
-// barycentric region of p's projection (vertex, edge or face)
+// squared distance from p to triangle (a, b, c): the closest point found by
+// classifying p against the triangle's Voronoi regions (vertex, edge or face)
+// with barycentric dot products, Ericson, Real-Time Collision Detection
+// (2005), Sec. 5.1.5
 __device__ __forceinline__ double point_tri_d2(V3<double> p, V3<double> a, V3<double> b, V3<double> c) {
   V3<double> ab = b - a, ac = c - a, ap = p - a;
   double d1 = dot(ab, ap), d2 = dot(ac, ap);
@@ -1049,8 +1051,11 @@ __device__ __forceinline__ double point_tri_d2(V3<double> p, V3<double> a, V3<do
   return dot(r, r);
 }
 
-// pair each body-contact item with its closest triangle within r (ties to the
-// lower triangle index), -1 if none
+// pair each body-contact item with its closest triangle within r, -1 if
+// none: the least distance d2min over the cell's triangles, then the
+// lowest-index triangle with d2 <= d2min (1 + 1e-9) + 1e-20 (a point nearest
+// to an edge or corner shared by several triangles is equally near to each;
+// the margin makes that choice independent of how the distance rounds)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_body_detect(const Vec4<T>* __restrict__ X, const int* __restrict__ vid, int n,
                                                         const T* __restrict__ bx, const int4* __restrict__ btri,
@@ -1069,20 +1074,26 @@ __global__ __launch_bounds__(kBlock) void k_body_detect(const Vec4<T>* __restric
     ci[a] = inside ? (int)u : 0;
   }
   int best = -1;
-  double bd = 0.0;
   if (inside) {
     const int cell = (ci[0] * G.dims[1] + ci[1]) * G.dims[2] + ci[2];
-    for (int q = G.off[cell]; q < G.off[cell + 1]; ++q) {
-      int t = G.tris[q];
+    auto d2_of = [&](int t) {
       int4 tv = btri[t];
       V3<double> a = {(double)bx[3 * tv.x], (double)bx[3 * tv.x + 1], (double)bx[3 * tv.x + 2]};
       V3<double> b = {(double)bx[3 * tv.y], (double)bx[3 * tv.y + 1], (double)bx[3 * tv.y + 2]};
       V3<double> c = {(double)bx[3 * tv.z], (double)bx[3 * tv.z + 1], (double)bx[3 * tv.z + 2]};
-      double d2 = point_tri_d2(p, a, b, c);
-      if (best < 0 || d2 < bd) { best = t; bd = d2; }
+      return point_tri_d2(p, a, b, c);
+    };
+    double bd = INFINITY;
+    for (int q = G.off[cell]; q < G.off[cell + 1]; ++q) bd = fmin(bd, d2_of(G.tris[q]));
+    if (bd <= r2) {
+      const double lim = bd * (1.0 + 1e-9) + 1e-20;
+      for (int q = G.off[cell]; q < G.off[cell + 1]; ++q) {
+        int t = G.tris[q];
+        if ((best < 0 || t < best) && d2_of(t) <= lim) best = t;
+      }
     }
   }
-  pair[j] = (best >= 0 && bd <= r2) ? best : -1;
+  pair[j] = best;
 }
 
 // Material clusters: the gradient of material m is the sum of the per-tet

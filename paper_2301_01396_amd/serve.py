@@ -48,20 +48,36 @@ class Request:
     cancelled: bool = False         # set by Server.cancel
 
 
-def estimate_bytes(sc, n_frames: int, adjoint: bool, dtype_bytes: int = 4) -> int:
-    """Upper estimate of a request's device memory (records, state,
-    checkpoints, adjoint working set and one frame of the adjoint's record)."""
+def estimate_parts(sc, n_frames: int, adjoint: bool, dtype_bytes: int = 4):
+    """Upper estimates of a request's device memory: (bytes the library
+    allocates: constraint records, state, checkpoints, the adjoint's working
+    set and one frame of its record of projection inputs; bytes the caller's
+    tensors take: frames, final state, targets, goal gradient and gradient
+    outputs).  The library part is handed to the request's context as its
+    budget, so the library never sizes beyond what was admitted (a record of
+    more frames is kept only if it fits)."""
     V, nd, nb, nt = sc.n_verts, sc.n_dist, sc.n_bend, sc.n_tet
     t = dtype_bytes
     rec = nd * (8 + 6 * t) + nb * (16 + 6 * t) + nt * (16 + 17 * t) + V * (8 + 5 * t)
     state = V * 16 * t
     ck = 2 * n_frames * V * 4 * t
-    out = n_frames * V * 3 * t * 2
     adj = 0
     if adjoint:
         adj = V * 8 * t + (nd + nb + nt) * (2 * t + 8)
         adj += sc.substeps * sc.iterations * (nd * 4 * t + nb * 10 * t + nt * 12 * t + V * 4 * t)
-    return int(1.15 * (rec + state + ck + out + adj)) + (8 << 20)
+    lib = int(1.15 * (rec + state + ck + adj)) + (8 << 20)
+    caller = (n_frames + 2) * V * 3 * t
+    if adjoint:
+        caller += 2 * n_frames * V * 3 * t + 2 * V * 3 * t + (nd + nb + nt) * 8
+        if getattr(sc, "f_ext", None) is not None:
+            caller += n_frames * V * 3 * t
+    return lib, int(1.15 * caller) + (1 << 20)
+
+
+def estimate_bytes(sc, n_frames: int, adjoint: bool, dtype_bytes: int = 4) -> int:
+    """Upper estimate of a request's device memory: both parts of
+    estimate_parts."""
+    return sum(estimate_parts(sc, n_frames, adjoint, dtype_bytes))
 
 
 class Server:
@@ -93,8 +109,7 @@ class Server:
             # every step of a request on its slot's stream: the server
             # overlaps requests, and one request at a time stays the plain
             # one-stream baseline
-            sim = Simulator(sc, dtype=self.dtype, device=self.device,
-                            tape_mode=0 if self.record else 1, serial_adjoint=True)
+            sim = Simulator(sc, **self._sim_kwargs(req))
             try:
                 xf, xe, ve = sim.forward(req.n_frames, for_adjoint=req.adjoint)
                 res = {}
@@ -118,6 +133,13 @@ class Server:
                 req.projections = sc.projections_per_rollout(req.n_frames) * (2 if req.adjoint else 1)
             finally:
                 sim.close()
+
+    def _sim_kwargs(self, req: Request) -> Dict[str, Any]:
+        """Context options of a request: its share of the admitted memory is
+        the library's budget."""
+        lib_bytes, _ = estimate_parts(req.scene, req.n_frames, req.adjoint, 8 if self.dtype == torch.float64 else 4)
+        return {"dtype": self.dtype, "device": self.device, "tape_mode": 0 if self.record else 1,
+                "serial_adjoint": True, "hbm_budget_bytes": lib_bytes}
 
     def _make_stream(self):
         return torch.cuda.Stream(device=self.device)      # default priority
@@ -233,7 +255,8 @@ class PackedServer:
 
     def _admit(self, pack, req: Request):
         sc = req.scene
-        sim = Simulator(sc, dtype=self.dtype, device=self.device, tape_mode=1)
+        lib_bytes, _ = estimate_parts(sc, req.n_frames, req.adjoint, 8 if self.dtype == torch.float64 else 4)
+        sim = Simulator(sc, dtype=self.dtype, device=self.device, tape_mode=1, hbm_budget_bytes=lib_bytes)
         mask = None
         if req.adjoint:
             mask = np.zeros(req.n_frames, np.uint8)

@@ -826,19 +826,29 @@ def test_p8_general_gap_shrinks_then_plateaus():
     assert errs[2] < 0.05
 
 
-def test_psd_projection_matches_eigh_clamp():
-    """The projection of Sec. 4.3.3 is the nearest PSD matrix: eigenvalues
-    below zero set to zero.  Checked against the library eigensolver on
-    random symmetric matrices of the block sizes used (3, 6, 12)."""
+def test_psd_projection_is_the_positive_part():
+    """Sec. 4.3 (the subsection after Derivative Verification) replaces each
+    constraint's derivative block by its projection onto the PSD cone.  A
+    symmetric A splits uniquely as A = P - Q with P, Q positive semidefinite
+    and P Q = 0; P is that projection (the nearest PSD matrix in the
+    Frobenius norm).  Checked through those three properties on random
+    symmetric matrices of the block sizes used (3, 6, 12), plus the special
+    cases PSD -> itself and NSD -> 0."""
     rng = np.random.default_rng(4)
     for n in (3, 6, 12):
         for _ in range(5):
             a = rng.standard_normal((n, n))
             a = a + a.T
-            w, v = np.linalg.eigh(a)
-            want = (v * np.maximum(w, 0.0)) @ v.T
-            got = O.psd_project(a)
-            assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(a).max())
+            p = O.psd_project(a)
+            q = p - a
+            tol = 1e-12 * np.abs(a).max()
+            assert np.allclose(p, p.T, atol=tol)
+            assert np.linalg.eigvalsh(p).min() > -tol and np.linalg.eigvalsh(q).min() > -tol
+            assert np.abs(p @ q).max() < tol * np.abs(a).max() * n
+            for _ in range(20):   # random PSD matrices are no nearer
+                b = rng.standard_normal((n, n))
+                r = b @ b.T * rng.uniform(0.01, 1.0)
+                assert np.linalg.norm(a - r) >= np.linalg.norm(a - p) - tol
         b = rng.standard_normal((n, n))
         psd = b @ b.T
         assert np.allclose(O.psd_project(psd), psd, rtol=0, atol=1e-12 * np.abs(psd).max())
@@ -871,3 +881,182 @@ def test_emulated_f32_is_close_to_f64():
     x32 = O.forward(O.OracleScene(sc, emulate_f32=True), 2)[1]
     err = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
     assert 0 < err < 1e-5
+
+
+# ------------------------------------------------------------------ FP32-storage emulation
+# The reference can store its state as FP32 values (x, v, lambda rounded to
+# FP32 after every write, initial state and compliances rounded on entry,
+# arithmetic between writes in FP64).  These pins restate the free-fall and
+# one-spring recurrences under exactly that storage rule in NumPy and require
+# the reference to reproduce them bit for bit, so dropping any one of the
+# roundings (or adding one) fails a pin.
+
+def _r32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def test_emulated_f32_storage_free_fall_bitwise():
+    """Sec. 3.1 update rule with no constraints: per substep v <- v + h (g +
+    w f), x <- x + h v, then v <- (x - x_prev) / h, each written value
+    rounded to FP32."""
+    rest = np.array([[0.1, 0.2, 0.3], [1.0, 2.0, 3.0], [0.0, 1.0, 0.0]])
+    sc = _scene(rest, [1.0, 0.37, 0.0], S=3, K=2, dt=1 / 30)
+    sc.set_type, sc.set_items = [], []
+    rng = np.random.default_rng(11)
+    x0 = rest + 0.1 * rng.standard_normal(rest.shape)
+    v0 = rng.standard_normal(rest.shape)
+    F = 5
+    f = rng.standard_normal((F, 3, 3))
+    xf, xe, ve = O.forward(O.OracleScene(sc, emulate_f32=True), F, x0=x0, v0=v0, f_ext=f)
+    h = sc.dt / sc.substeps
+    g = np.array(sc.gravity)
+    w = sc.inv_mass[:, None]
+    x = _r32(x0)
+    v = np.where(w > 0, _r32(v0), 0.0)
+    want = []
+    for fr in range(F):
+        for _ in range(sc.substeps):
+            xp = x.copy()
+            v = np.where(w > 0, _r32(v + h * (g + w * f[fr])), v)
+            x = _r32(x + h * v)
+            v = _r32((x - xp) / h)
+        want.append(x.copy())
+    assert np.array_equal(xf, np.array(want)) and np.array_equal(ve, v)
+    x64 = O.forward(O.OracleScene(sc), F, x0=x0, v0=v0, f_ext=f)[1]
+    assert not np.array_equal(x64, xe)      # the rounding is active
+
+
+def _spring_f32(alpha, w, L, y0, u0, h, G, N, K):
+    """Particle 1 below a pinned particle at the origin on the y axis, one
+    distance constraint (C = |y| - L, grad = (0, -1, 0) for particle 1):
+    each substep predicts, projects K times with dlambda = (-C - at lambda) /
+    (w + at), lambda += dlambda, y -= w dlambda, and sets v from the
+    positions; every written value rounded to FP32."""
+    at = float(_r32(alpha)) / (h * h)
+    D = at + w
+    y, u = float(_r32(y0)), float(_r32(u0))
+    ys, us = [], []
+    for _ in range(N):
+        yp = y
+        u = float(_r32(u + h * G))
+        y = float(_r32(y + h * u))
+        lam = 0.0
+        for _ in range(K):
+            C = -y - L
+            dl = (-C - at * lam) / D
+            lam = float(_r32(lam + dl))
+            y = float(_r32(y - w * dl))
+        u = float(_r32((y - yp) / h))
+        ys.append(y)
+        us.append(u)
+    return np.array(ys), np.array(us)
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_emulated_f32_storage_compliant_spring_bitwise(K):
+    """Sec. 3.1 Eq. xpbd on one compliant distance constraint (the P2
+    geometry, gravity along -y): the reference with FP32 storage equals the
+    recurrence above bit for bit at every substep (K = 3 makes the stored
+    lambda enter the later iterations)."""
+    L, m = 0.5, 0.4
+    alpha = 2.3e-5
+    rest = [[0, 0, 0], [0, -L, 0]]
+    sc = _scene(rest, [0.0, 1.0 / m], dist=[[0, 1]], K=K, S=1, dt=1 / 90)
+    x0 = np.array([[0, 0, 0], [0, -0.6173, 0.0]])
+    v0 = np.array([[0, 0, 0], [0, -0.3141, 0.0]])
+    N = 30
+    xf, xe, ve = O.forward(O.OracleScene(sc, emulate_f32=True), N, x0=x0, v0=v0, dist_alpha=[alpha])
+    ys, us = _spring_f32(alpha, 1.0 / m, L, x0[1, 1], v0[1, 1], sc.dt, sc.gravity[1], N, K)
+    assert np.array_equal(xf[:, 1, 1], ys)
+    assert ve[1, 1] == us[-1]
+    assert np.all(xf[:, 1, [0, 2]] == 0.0) and np.all(xf[:, 0] == 0.0)
+    x64 = O.forward(O.OracleScene(sc), N, x0=x0, v0=v0, dist_alpha=[alpha])[0]
+    assert not np.array_equal(x64[:, 1, 1], ys)
+
+
+def _between_pins_f32(a, b, L, alpha, w, y0, h, G, N, K):
+    """Particle 1 on the y axis between particles pinned at y = a and y = b
+    (a > y > b), joined to each by a distance constraint of rest length L,
+    one set per constraint: the upper one has C = (a - y) - L and moves y by
+    -w dlambda, the lower one C = (y - b) - L and moves y by +w dlambda; every
+    written value rounded to FP32.  The two multipliers keep changing from
+    iteration to iteration, so their stored FP32 values reach the positions."""
+    at = float(_r32(alpha)) / (h * h)
+    D = at + w
+    a, b = float(_r32(a)), float(_r32(b))
+    y, u = float(_r32(y0)), 0.0
+    ys = []
+    for _ in range(N):
+        yp = y
+        u = float(_r32(u + h * G))
+        y = float(_r32(y + h * u))
+        l1 = l2 = 0.0
+        for _ in range(K):
+            dl = (-((a - y) - L) - at * l1) / D
+            l1 = float(_r32(l1 + dl))
+            y = float(_r32(y - w * dl))
+            dl = (-((y - b) - L) - at * l2) / D
+            l2 = float(_r32(l2 + dl))
+            y = float(_r32(y + w * dl))
+        u = float(_r32((y - yp) / h))
+        ys.append(y)
+    return np.array(ys)
+
+
+def test_emulated_f32_storage_two_constraints_bitwise():
+    """Sec. 3.1 Eq. xpbd, Gauss-Seidel over two compressed springs holding a
+    particle between two pins (4 iterations per substep): the reference with
+    FP32 storage equals the recurrence above bit for bit."""
+    L, alpha, w = 1.05, 1e-3, 2.5
+    rest = [[0, 1.0, 0], [0, 0.0, 0], [0, -1.0, 0]]
+    sc = _scene(rest, [0.0, w, 0.0], dist=[[0, 1], [1, 2]], K=4, S=1, dt=1 / 90)
+    sc.rest = np.array([[0, L, 0], [0, 0.0, 0], [0, -L, 0]])   # rest length L for both
+    x0 = np.array([[0, 1.0, 0], [0, 0.2, 0], [0, -1.0, 0]])
+    N = 30
+    xf, _, _ = O.forward(O.OracleScene(sc, emulate_f32=True), N, x0=x0, dist_alpha=[alpha, alpha])
+    ys = _between_pins_f32(1.0, -1.0, L, alpha, w, 0.2, sc.dt, sc.gravity[1], N, 4)
+    assert np.array_equal(xf[:, 1, 1], ys)
+    assert np.all(xf[:, 1, [0, 2]] == 0.0)
+
+
+# Each mutation drops one FP32 rounding of the emulation (or, the last,
+# rounds a value the FP32 path never stores) in a private copy of the
+# reference's source; the pins above must fail on every one of them.
+_MUTATIONS = {
+    "lambda": ("lam[r.lam] = rnd(s, lam[r.lam] + dl);", "lam[r.lam] = lam[r.lam] + dl;"),
+    "position": ("xv = rnd(s, xv + w * dl * e.g[3 * k + a]);", "xv = xv + w * dl * e.g[3 * k + a];"),
+    "predicted velocity": ("v[3 * k + a] = rnd(s, v[3 * k + a] + h * (s->gravity[a] + w * fa));",
+                           "v[3 * k + a] = v[3 * k + a] + h * (s->gravity[a] + w * fa);"),
+    "end velocity": ("v[i] = rnd(s, (x[i] - xprev[i]) / h);", "v[i] = (x[i] - xprev[i]) / h;"),
+    "compliance": ("if (r.type == T_DIST) return rnd(s, p->dist_alpha[r.item]);",
+                   "if (r.type == T_DIST) return p->dist_alpha[r.item];"),
+    "extra rounding of h": ("c.h = s->dt / s->substeps;\n  std::vector<int> pairv;\n  if (s->n_body_tris > 0) {\n"
+                            "    if (!p->body_x) return 1;\n    c.pair = &pairv;\n  }\n  const int V = s->n_verts;\n"
+                            "  std::vector<double> x(x0,",
+                            "c.h = rnd(s, s->dt / s->substeps);\n  std::vector<int> pairv;\n"
+                            "  if (s->n_body_tris > 0) {\n    if (!p->body_x) return 1;\n    c.pair = &pairv;\n  }\n"
+                            "  const int V = s->n_verts;\n  std::vector<double> x(x0,"),
+}
+
+
+def test_emulation_pins_fail_on_planted_mistakes(tmp_path):
+    import os
+    import subprocess
+    import sys
+    src = open(O.library_path().replace("liboracle.so", "xpbd_oracle.cpp")).read()
+    procs = {}
+    for name, (a, b) in _MUTATIONS.items():
+        assert src.count(a) == 1, name
+        d = tmp_path / name.replace(" ", "_")
+        d.mkdir()
+        (d / "m.cpp").write_text(src.replace(a, b))
+        procs[name] = (d, subprocess.Popen(["g++", "-std=c++17", "-O1", "-fopenmp", "-fPIC", "-shared", "-o",
+                                            str(d / "m.so"), str(d / "m.cpp")]))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for name, (d, pr) in procs.items():
+        assert pr.wait() == 0, name
+        env = dict(os.environ, XPBD_ORACLE_LIB=str(d / "m.so"), OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                            os.path.join(root, "tests", "test_oracle_pins.py"), "-k", "emulated_f32_storage"],
+                           cwd=root, env=env, capture_output=True, text=True)
+        assert r.returncode == 1 and "failed" in r.stdout, (name, r.stdout[-2000:])

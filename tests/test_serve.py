@@ -76,6 +76,27 @@ def test_cancelled_requests_leave_the_others_unaffected():
     assert not srv.cancel(1)                      # finished: nothing to cancel
 
 
+def test_each_context_is_budgeted_within_its_admitted_bytes():
+    """The library part of a request's estimate becomes its context's memory
+    budget, so what the library sizes (records of more frames included) is
+    bounded by what admission counted; with the caller's tensors the two
+    parts are the admitted bytes."""
+    srv = serve.Server(slots=2, hbm_budget=1 << 40, device="cpu")
+    for adjoint in (False, True):
+        sc = scenes.small_cloth(n=9)
+        sc.f_ext = np.zeros((40, sc.n_verts, 3))
+        req = serve.Request(rid=0, scene=sc, n_frames=40, adjoint=adjoint)
+        kw = srv._sim_kwargs(req)
+        lib_bytes, caller_bytes = serve.estimate_parts(sc, 40, adjoint)
+        assert kw["hbm_budget_bytes"] == lib_bytes > 0
+        assert lib_bytes + caller_bytes == serve.estimate_bytes(sc, 40, adjoint)
+        # the caller's part holds at least the frames, targets, goal gradient
+        # and every gradient output the request returns
+        V = sc.n_verts
+        need = 40 * V * 3 * 4 * (3 if adjoint else 1) + (2 * V * 3 * 4 if adjoint else 0)
+        assert caller_bytes >= need
+
+
 def test_sequential_is_one_slot():
     rep = FakeServer(run_s=0.02, slots=1, hbm_budget=1 << 40).run(_reqs(5, gap=0.0))
     assert rep["max_concurrent"] == 1 and rep["requests"] == 5
