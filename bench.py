@@ -45,6 +45,13 @@ ALG_BYTES = {             # family: (index bytes, words of the state dtype)
 }
 
 
+# streamed bytes per projection of the survey's hot-path table (forward: a3,
+# reverse: a7), the per-unit figure the roofline is priced on: every
+# projection reads its record and reads and writes its vertices in HBM.
+# Types the a7 table leaves out fall back to ALG_BYTES.
+SURVEY_BYTES = {0: 80.0, 2: 144.0, 4: 98.0, 6: 40.0, 1: 116.0, 3: 204.0}
+
+
 # record words written per projection by a forward that keeps the adjoint's
 # record (vertex differences + multiplier): dist 4, bend 10, tet 6 (12 per
 # item), contact 4
@@ -120,6 +127,21 @@ def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
                for f, cnt in n.items()) / max(tot, 1)
 
 
+def survey_bytes(sc, fam: int, tsz: int) -> float:
+    """The survey's streamed bytes per projection for a kernel family; for a
+    family that runs several constraint types (LDS groups, the persistent
+    frame kernel) the average over the workload's mix."""
+    def one(f):
+        return SURVEY_BYTES[f] * tsz / 4 if f in SURVEY_BYTES else alg_bytes(f, tsz)
+    if fam in (8, 9, 10, 11):
+        rev = fam in (9, 11)
+        n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
+             6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
+        tot = max(sum(n.values()), 1)
+        return sum(cnt * one(f + (1 if rev else 0)) for f, cnt in n.items()) / tot
+    return one(fam)
+
+
 FAMILY = {0: "dist_fwd", 1: "dist_rev", 2: "bend_fwd", 3: "bend_rev", 4: "tet_fwd", 5: "tet_rev",
           6: "contact_fwd", 7: "contact_rev", 8: "frame_fwd", 9: "frame_rev", 10: "group_fwd", 11: "group_rev",
           12: "membrane_fwd", 13: "membrane_rev"}
@@ -129,6 +151,19 @@ KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: 
 N_FAM = len(FAMILY)
 WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 256}}
 HBM_PEAK_GBS = 8000.0
+
+# what the parity tests establish for each workload's results, by dtype
+ACCURACY = {
+    ("c1", "f64"): "positions and gradients within 1e-10 / 1e-8 of the FP64 reference (full rollout)",
+    ("c2", "f32"): "one full frame at full size: positions 1e-5, every gradient group 1e-3 of the FP64 reference",
+    ("c4", "f32"): "full size, the benchmark's adjoint structure: positions 1e-5, gradients 1e-3 of the "
+                   "reference with FP32 state storage (the plain FP64 reference differs from both by 3.5e-3 "
+                   "in dL/dalpha)",
+    ("c3", "f64"): "full size, one frame: positions 1e-10, gradients 1e-5 of the FP64 reference",
+    ("c3", "f32"): "gradients parity unpinned: at these moduli FP32 state storage alone moves the exact "
+                   "gradient by more than its size (the reference with FP32 storage against FP64); positions "
+                   "within twice that intrinsic error (3.3e-4 L2); run --dtype f64 for a parity-backed gradient",
+}
 
 
 # sources of the single-context kernels and their launches (the pack's
@@ -281,6 +316,47 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def serving_leg(n_requests: int, pack_slots: int, log) -> dict:
+    """The serving part of the metric, short enough for the default line: a
+    fixed mix of requests (seed 6; grid cloths and tet boxes of 1k-250k
+    vertices, 30-120 frames, half with the adjoint) served one at a time with
+    one launch per set (the sequential plain baseline), then by the packed
+    server (every admitted request in one pack, each launch serving the same
+    step of all of them) with all requests queued at t = 0 and with Poisson
+    arrivals at the sequential capacity.  p50/p99 latency from arrival to
+    result, requests/s and projections/s."""
+    import torch
+    from paper_2301_01396_amd import serve
+    reqs = serve.make_mix(n_requests, qps=1.0, seed=6)
+    base = [r.arrival for r in reqs]
+
+    def at_rate(qps):
+        for r, a in zip(reqs, base):
+            r.arrival = a / qps
+            r.admitted = r.done = -1.0
+            r.result = {}
+        return reqs
+
+    keys = ("requests", "throughput_rps", "p50_latency_s", "p99_latency_s", "projections_per_s", "wall_s")
+    pick = lambda rep: {k: rep.get(k) for k in keys}
+    serve.Server(slots=1, record_whole_rollout=False).run(serve.make_mix(2, qps=100.0, seed=7, vmax=4000,
+                                                                         frames_scale=0.1))
+    seq = serve.Server(slots=1, record_whole_rollout=False).run(at_rate(1e9))
+    log(f"serving, sequential plain launches: {pick(seq)}")
+    cap = seq["throughput_rps"]
+    sat = serve.PackedServer(slots=pack_slots, graphs=False, n_packs=1).run(at_rate(1e9))
+    log(f"serving, packed, all at t = 0: {pick(sat)}")
+    poi = serve.PackedServer(slots=pack_slots, graphs=False, n_packs=1).run(at_rate(cap))
+    log(f"serving, packed, Poisson at the sequential capacity: {pick(poi)}")
+    torch.cuda.synchronize()
+    return {"requests": n_requests, "mix": "seed 6: 50% grid cloth / 50% tet box, ln V ~ N(ln 16000, 1) in "
+                                           "[1k, 250k], frames U{30..120}, half with the adjoint, S 2, K 20",
+            "sequential_plain": pick(seq), "packed_all_at_t0": pick(sat),
+            "packed_poisson_at_sequential_capacity": dict(pick(poi), qps=cap),
+            "throughput_vs_sequential": sat["projections_per_s"] / seq["projections_per_s"],
+            "p50_vs_sequential_at_capacity": poi["p50_latency_s"] / seq["p50_latency_s"]}
+
+
 def implicit_bench(args):
     """The paper's implicit adjoint (CG per substep) against the exact
     reverse adjoint on one workload: time of each and their gradients'
@@ -411,6 +487,10 @@ def main():
     ap.add_argument("--estimate", action="store_true",
                     help="time material-estimation descent iterations instead (--steps iterations)")
     ap.add_argument("--estimate-n", type=int, default=64, help="cubes per side of the estimation box")
+    ap.add_argument("--dtype", default="auto", choices=["auto", "f32", "f64"],
+                    help="state dtype (auto: FP64 for the 32x32 cloth, FP32 otherwise)")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests of the serving leg of the default line (0 = skip)")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="also time this many steps with one launch per set (0 = skip)")
     args = ap.parse_args()
@@ -449,7 +529,8 @@ def main():
     dev = torch.device("cuda:0")
     sc, tg = make_workload(args.workload, args.tile, args.frames, args.lds_groups, args.merge, args.tiling)
     F = args.frames or sc.n_frames
-    dtype = torch.float64 if args.workload == "c1" else torch.float32
+    dtype = {"f32": torch.float32, "f64": torch.float64}.get(args.dtype) or (
+        torch.float64 if args.workload == "c1" else torch.float32)
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
     sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
                     use_groups=not args.no_groups, block_size=args.block, group_records=args.group_records,
@@ -584,22 +665,40 @@ def main():
     for fam in range(N_FAM):
         if launches[fam]:
             kernels[FAMILY[fam]]["share_of_sampled_ms"] = round(ms[fam] / tot, 3)
+    pmc = {}
+    tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if os.path.exists(tf):
+        pmc = {key: rec for key, rec in json.load(open(tf)).items() if rec.get("csrc_sha") == csrc_hash()}
     if tot > 0:
         dom = max(range(N_FAM), key=lambda f: ms[f])
         k = kernels[FAMILY[dom]]
-        traffic = traffic_gbs = None
-        tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-        if os.path.exists(tf):
-            rec = json.load(open(tf)).get(f"{args.workload}:{KERNEL_SYMBOL[dom]}")
-            if rec and rec.get("csrc_sha") == csrc_hash():
-                traffic = rec["bytes_per_dispatch_scaled"] * k["items_per_launch"] / rec["items_per_dispatch"]
-                traffic_gbs = round(traffic / (k["avg_us"] * 1e-6) / 1e9, 1)
-        roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": k["alg_GBps"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(k["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+        sb = survey_bytes(sc, dom, tsz)
+        achieved = sb * k["items_per_launch"] / (k["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_GBps": traffic_gbs,
-                "bytes_per_projection": round(fam_bytes(dom), 1),
-                "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"]}
+                "bytes_per_projection": round(sb, 1),
+                "byte_model": "the survey's streamed bytes per projection (each projection reads and writes "
+                              "its vertices in HBM); LDS group kernels stage a patch's vertices once per launch "
+                              "and move fewer bytes, so this model can exceed the HBM peak: 'counter' holds the "
+                              "measured HBM traffic",
+                "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"],
+                "staged_model": {"bytes_per_projection": k["bytes_per_projection"], "GBps": k["alg_GBps"]}}
+        rec = pmc.get(f"{args.workload}:{KERNEL_SYMBOL[dom]}")
+        if rec:
+            traffic = rec["bytes_per_dispatch_scaled"] * k["items_per_launch"] / rec["items_per_dispatch"]
+            alone_s = rec["avg_ns_under_counters"] * 1e-9 * k["items_per_launch"] / rec["items_per_dispatch"]
+            roof["traffic"] = round(traffic)
+            roof["counter"] = {
+                "bytes_per_projection": round(traffic / k["items_per_launch"], 1),
+                "shared_GBps": round(traffic / (k["avg_us"] * 1e-6) / 1e9, 1),
+                "shared_frac": round(traffic / (k["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "alone_GBps": round(traffic / alone_s / 1e9, 1),
+                "alone_frac": round(traffic / alone_s / 1e9 / HBM_PEAK_GBS, 4),
+                "lds_reuse": round(sb * k["items_per_launch"] / traffic, 2),
+                "note": "shared: over the timed run's launch time (the adjoint's second stream runs beside); "
+                        "alone: over the launch time under the counters (one dispatch at a time)"}
 
         # the whole path per step: algorithmic bytes of every projection run
         # (forward frames, the adjoint's recomputed frames, reversed frames)
@@ -623,7 +722,21 @@ def main():
             pb = half * frames_fwd / F * fb + half * rb
             sec = elapsed / args.steps
             roof["path"] = {"bytes_per_step": round(pb), "achieved": round(pb / sec / 1e9, 1),
-                            "frac": round(pb / sec / 1e9 / HBM_PEAK_GBS, 4), "frames_run_forward": frames_fwd}
+                            "frac": round(pb / sec / 1e9 / HBM_PEAK_GBS, 4), "frames_run_forward": frames_fwd,
+                            "byte_model": "staged (the group kernels' own bytes)"}
+            fr, rr = pmc.get(f"{args.workload}:k_group_fwd"), pmc.get(f"{args.workload}:k_group_rev")
+            if all_grouped and fr and rr:
+                launches_frame = sc.substeps * sc.iterations * len(sc.groups)
+                def per_dispatch(recording):     # dispatch-weighted over the template variants
+                    vs = [v for n_, v in fr["variants"].items()
+                          if (n_.split(",")[2].strip() == "true") == recording]
+                    return (sum(v["dispatches"] * (v["fetch_bytes"] + v["write_bytes"]) for v in vs)
+                            / max(sum(v["dispatches"] for v in vs), 1))
+                cb = launches_frame * (F * per_dispatch(True) + (frames_fwd - F) * per_dispatch(False)
+                                       + F * rr["bytes_per_dispatch_scaled"])
+                roof["path"]["counter_bytes_per_step"] = round(float(cb))
+                roof["path"]["counter_GBps"] = round(float(cb) / sec / 1e9, 1)
+                roof["path"]["counter_frac"] = round(float(cb) / sec / 1e9 / HBM_PEAK_GBS, 4)
         roof["adjoint_streams"] = info["adjoint_streams"]
         if info["adjoint_streams"] == 2:
             roof["note"] = ("the adjoint recomputes earlier frames on a second stream beside the reverse, so those "
@@ -633,6 +746,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, sc)
+
+    serving = None
+    if args.workload == "c4" and args.serve_requests > 0:
+        sim.close()
+        for t in leaves:
+            t.grad = None
+        torch.cuda.empty_cache()
+        serving = serving_leg(args.serve_requests, args.pack_slots, log)
 
     out = {
         "metric": "constraint projections/s fwd+adjoint vs plain launch; p50/p99 request latency",
@@ -648,6 +769,8 @@ def main():
                    if info["n_groups_lds"] else "one kernel launch per set"),
         "persistent_blocks": info["persistent_blocks"], "tape_mode": info["tape_mode"],
         "profile_stride": args.profile_stride, "csrc_sha": csrc_hash(),
+        "accuracy": ACCURACY.get((args.workload, "f64" if dtype == torch.float64 else "f32")),
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

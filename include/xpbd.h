@@ -18,10 +18,12 @@
  *   every substep, iteration and projection (the adjoint-state recurrence of
  *   the supplemental Sec. A, Eq. adjoint_state, with the gradient rule
  *   Eq. gradientRule, applied to each projection using the partial
- *   derivatives of Sec. 4.3).  Frames are recomputed from per-frame
- *   checkpoints taken by the forward call, so memory is bounded by one
- *   frame's record of projection inputs (Sec. 7 notes the linear-in-steps
- *   memory of storing everything).
+ *   derivatives of Sec. 4.3).  The adjoint reads a record of every
+ *   projection's inputs: the forward keeps it for the whole rollout or for
+ *   its last frames when memory allows (tape_mode 0, 3, 4), and the adjoint
+ *   recomputes the other frames from per-frame checkpoints, holding one
+ *   frame's record (tape_mode 1) or one substep's (tape_mode 2) at a time
+ *   (Sec. 7 notes the linear-in-steps memory of storing everything).
  *
  * Constraint types:
  *   XPBD_DIST    C = |x_i - x_j| - L, L the rest length.
@@ -108,8 +110,8 @@ typedef struct {
    * compliance is the 3x3 matrix alpha = (A K)^-1, A = material-space area,
    * K = [[C00, C01, 0], [C01, C11, 0], [0, 0, C22]] from xpbd_params.tri_coef;
    * each projection solves the 3x3 system for the three multipliers.
-   * Membrane sets run as one launch per set or in the persistent kernel,
-   * not in LDS groups; the implicit adjoint does not take them. */
+   * Membrane sets run as one launch per set, in the persistent kernel or in
+   * LDS groups; the implicit adjoint does not take them. */
   int32_t n_tri;
   const int32_t* tri_v;       /* host [n_tri][3] */
   const double* tri_uv;       /* host [n_tri][6] */
@@ -125,9 +127,9 @@ typedef struct {
    * plane of that triangle (n^ the unit normal), compliance body_compliance,
    * projected only while C < 0.  The gradient reaches the body vertices
    * (xpbd_grads.body_x), summed with FP64 atomics (rounding may differ in
-   * the last bits between runs).  Body-contact sets run one launch per set;
-   * they are refused by the persistent kernel, LDS groups, packs and the
-   * implicit adjoint. */
+   * the last bits between runs).  Body-contact sets run one launch per set or
+   * in LDS groups; the persistent kernel (launch_mode 2), packs and the
+   * implicit adjoint refuse them (XPBD_ERR_INVALID). */
   int32_t n_body_verts;
   int32_t n_body_tris;
   const int32_t* body_tris;   /* host [n_body_tris][3] */
@@ -332,7 +334,7 @@ xpbd_status xpbd_goal_weighted_noalloc(xpbd_ctx ctx, const void* x_frames, const
  * xbar, w = M y, solved by Jacobi-preconditioned conjugate gradients in FP64
  * with a matrix-free operator.  With cg->pd_projection each constraint's
  * block -lambda_j Hess C_j is first replaced by its positive semidefinite
- * part (eigenvalues below zero dropped; Sec. 4.3.3), which makes the system
+ * part (eigenvalues below zero dropped; Sec. 4.3, Positive Definite Projection), which makes the system
  * positive definite; without it, a system that is not positive definite
  * fails with XPBD_ERR_SOLVER.
  * Then vbar = h w (free vertices), dL/df_ext += h w_inv vbar, xbar = w -
@@ -350,7 +352,7 @@ typedef struct {
   int32_t max_iterations;       /* in: CG iterations per substep, >= 1 */
   double rel_tolerance;         /* in: stop at |r| <= rel_tolerance |xbar| */
   int32_t pd_projection;        /* in: 1 = project each constraint's block -lambda Hess C
-                                   to positive semidefinite first (Sec. 4.3.3) */
+                                   to positive semidefinite first (Sec. 4.3, Positive Definite Projection) */
   int64_t total_iterations;     /* out */
   int32_t max_iterations_used;  /* out: most iterations one substep took */
   double worst_rel_residual;    /* out */
@@ -451,8 +453,10 @@ typedef struct {
 } xpbd_pack_stats;
 
 #define XPBD_PACK_GRAPHS 1
-/* Errors: XPBD_ERR_INVALID (bad dtype or flags), XPBD_ERR_OOM. */
-xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, xpbd_pack* out);
+/* block_size: workgroup size of the pack's set and vertex launches, one
+ * item per thread: 64, 128 or 256 (0 = 256); results do not depend on it.
+ * Errors: XPBD_ERR_INVALID (bad dtype, flags or block size), XPBD_ERR_OOM. */
+xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, int32_t block_size, xpbd_pack* out);
 /* Synchronises the pack's last stream, then frees the pack (not its contexts). */
 xpbd_status xpbd_pack_destroy(xpbd_pack pack);
 /* Validate a job, gather and check its parameters, allocate its context's

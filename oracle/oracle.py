@@ -244,9 +244,8 @@ def point_triangle_d2(p, tri):
 def psd_project(a):
     """Projection of a symmetric matrix onto the positive semidefinite cone,
     from its definition: eigen-decomposition (numpy.linalg.eigh), negative
-    eigenvalues set to zero, matrix rebuilt (Sec. 4.3 projects each
-    constraint's derivative block this way, in the subsection after
-    Derivative Verification)."""
+    eigenvalues set to zero, matrix rebuilt (Sec. 4.3, Positive Definite
+    Projection, treats each constraint's derivative block this way)."""
     a = np.asarray(a, np.float64)
     lam, vec = np.linalg.eigh(0.5 * (a + a.T))
     return (vec * np.maximum(lam, 0.0)) @ vec.T
@@ -270,7 +269,7 @@ _PSD_C = _PSD_FN(_psd_callback)
 
 def adjoint_implicit(osc: OracleScene, n_frames: int, dLdx, x0=None, v0=None, pd: bool = False, **params):
     """Converged-limit adjoint of Eq. adjointXPBD (tiny meshes); ``pd``
-    projects each constraint's Hessian block to PSD first (Sec. 4.3.3)."""
+    projects each constraint's Hessian block to PSD first (Sec. 4.3, Positive Definite Projection)."""
     sc = osc.sc
     V = sc.n_verts
     x0 = np.ascontiguousarray(sc.x0 if x0 is None else x0, np.float64)

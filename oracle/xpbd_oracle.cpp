@@ -1168,9 +1168,9 @@ int orc_adjoint(const orc_scene* s, const orc_params* p, int F, const double* x0
 // where C < 0 there).  Same outputs as orc_adjoint for the compliances of
 // distance and bending rows, x0, v0 and f.
 // pd != 0: each constraint's Hessian block -lambda_j Hess C_j is projected to
-// positive semidefinite before assembly (Sec. 4.3, the subsection after
-// Derivative Verification; the rank-one block grad C grad C^T / alpha~ is
-// already), so the system is symmetric positive definite.
+// positive semidefinite before assembly (Sec. 4.3, Positive Definite
+// Projection; the rank-one block grad C grad C^T / alpha~ is already), so
+// the system is symmetric positive definite.
 // psd: with pd != 0, replaces the symmetric n x n matrix a (row-major) by its
 // projection onto the positive semidefinite cone in place and returns 0; the
 // caller supplies it (eigen-decomposition with negative eigenvalues dropped).

@@ -8,6 +8,7 @@ struct xpbd_pack_s {
   std::string err;
   xpbd_dtype dtype = XPBD_F32;
   bool graphs = false;
+  int block = kBlock;   // workgroup size of the set and vertex launches
   int S = -1, K = -1;
 
   struct Job {
@@ -216,7 +217,7 @@ template <class T> struct PackOps {
         if (pick(pk->jobs[m])) {
           PackSeg g{m, 0, 0, pk->jobs[m].c->V, b, 0, 0};
           seg.push_back(g);
-          b += (int)nblocks(g.count);
+          b += (int)nblocks(g.count, pk->block);
         }
       if (b) plan.push_back({xpbd_pack_s::L_VERT, op, false, false, 0, (unsigned)b, s0, (int)(seg.size() - s0)});
     };
@@ -230,7 +231,7 @@ template <class T> struct PackOps {
         if (si.count == 0) continue;
         int tape = rev ? 1 : ((J.phase == 0 && J.mode == 3) || J.phase == 1) ? 1 : 0;
         seg.push_back(PackSeg{m, si.type, si.begin, si.count, b, tape, (long long)si.tape_off});
-        b += (int)nblocks(si.count);
+        b += (int)nblocks(si.count, pk->block);
         ty = ty == -2 ? si.type : (ty == si.type ? ty : -1);
       }
       if (b)
@@ -304,17 +305,19 @@ template <class T> struct PackOps {
   }
 
   // ---------------------------------------------------------------- launches
-  template <int TY> static void fwd(const Launch& L, const PackMember<T>* mem, const PackSeg* sg, hipStream_t st) {
-    if (L.first) k_pack_fwd<T, TY, true><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
-    else k_pack_fwd<T, TY, false><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+  template <int TY>
+  static void fwd(const Launch& L, const PackMember<T>* mem, const PackSeg* sg, int blk, hipStream_t st) {
+    if (L.first) k_pack_fwd<T, TY, true><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+    else k_pack_fwd<T, TY, false><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
   }
-  template <int TY> static void rev(const Launch& L, const PackMember<T>* mem, const PackSeg* sg, hipStream_t st) {
+  template <int TY>
+  static void rev(const Launch& L, const PackMember<T>* mem, const PackSeg* sg, int blk, hipStream_t st) {
     if (L.first) {
-      if (L.last) k_pack_rev<T, TY, true, true><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
-      else k_pack_rev<T, TY, true, false><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+      if (L.last) k_pack_rev<T, TY, true, true><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+      else k_pack_rev<T, TY, true, false><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
     } else {
-      if (L.last) k_pack_rev<T, TY, false, true><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
-      else k_pack_rev<T, TY, false, false><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+      if (L.last) k_pack_rev<T, TY, false, true><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
+      else k_pack_rev<T, TY, false, false><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg, L.slot_it);
     }
   }
 
@@ -323,41 +326,42 @@ template <class T> struct PackOps {
     PackMember<T>* mem = (PackMember<T>*)SL.dmem;
     const PackSeg* seg0 = (const PackSeg*)SL.dseg;
     const int n_members = SL.n_members;
+    const int blk = pk->block;
     for (const Launch& L : SL.plan) {
       const PackSeg* sg = seg0 + L.seg;
       switch (L.kind) {
         case xpbd_pack_s::L_VERT:
           switch (L.op) {
-            case PV_CHECKPOINT: k_pack_vert<T, PV_CHECKPOINT><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
-            case PV_RESTORE: k_pack_vert<T, PV_RESTORE><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
-            case PV_PREDICT: k_pack_vert<T, PV_PREDICT><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
-            case PV_VELOCITY: k_pack_vert<T, PV_VELOCITY><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
-            case PV_UNPACK: k_pack_vert<T, PV_UNPACK><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
-            case PV_INJECT: k_pack_vert<T, PV_INJECT><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_CHECKPOINT: k_pack_vert<T, PV_CHECKPOINT><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_RESTORE: k_pack_vert<T, PV_RESTORE><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_PREDICT: k_pack_vert<T, PV_PREDICT><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_VELOCITY: k_pack_vert<T, PV_VELOCITY><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_UNPACK: k_pack_vert<T, PV_UNPACK><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
+            case PV_INJECT: k_pack_vert<T, PV_INJECT><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
             case PV_REV_VELOCITY:
-              k_pack_vert<T, PV_REV_VELOCITY><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg);
+              k_pack_vert<T, PV_REV_VELOCITY><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg);
               break;
-            default: k_pack_vert<T, PV_REV_PREDICT><<<L.grid, kBlock, 0, st>>>(mem, sg, L.nseg); break;
+            default: k_pack_vert<T, PV_REV_PREDICT><<<L.grid, blk, 0, st>>>(mem, sg, L.nseg); break;
           }
           break;
         case xpbd_pack_s::L_FWD:
           switch (L.op) {
-            case 0: fwd<0>(L, mem, sg, st); break;
-            case 1: fwd<1>(L, mem, sg, st); break;
-            case 2: fwd<2>(L, mem, sg, st); break;
-            case 3: fwd<3>(L, mem, sg, st); break;
-            case 4: fwd<4>(L, mem, sg, st); break;
-            default: fwd<-1>(L, mem, sg, st); break;
+            case 0: fwd<0>(L, mem, sg, blk, st); break;
+            case 1: fwd<1>(L, mem, sg, blk, st); break;
+            case 2: fwd<2>(L, mem, sg, blk, st); break;
+            case 3: fwd<3>(L, mem, sg, blk, st); break;
+            case 4: fwd<4>(L, mem, sg, blk, st); break;
+            default: fwd<-1>(L, mem, sg, blk, st); break;
           }
           break;
         case xpbd_pack_s::L_REV:
           switch (L.op) {
-            case 0: rev<0>(L, mem, sg, st); break;
-            case 1: rev<1>(L, mem, sg, st); break;
-            case 2: rev<2>(L, mem, sg, st); break;
-            case 3: rev<3>(L, mem, sg, st); break;
-            case 4: rev<4>(L, mem, sg, st); break;
-            default: rev<-1>(L, mem, sg, st); break;
+            case 0: rev<0>(L, mem, sg, blk, st); break;
+            case 1: rev<1>(L, mem, sg, blk, st); break;
+            case 2: rev<2>(L, mem, sg, blk, st); break;
+            case 3: rev<3>(L, mem, sg, blk, st); break;
+            case 4: rev<4>(L, mem, sg, blk, st); break;
+            default: rev<-1>(L, mem, sg, blk, st); break;
           }
           break;
         case xpbd_pack_s::L_SPHERE: k_pack_sphere<T><<<L.grid, kBlock, 0, st>>>(mem, sg); break;
@@ -471,10 +475,11 @@ template <class F> xpbd_status pack_guarded(xpbd_pack pk, F&& fn) {
 
 extern "C" {
 
-xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, xpbd_pack* out) {
+xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, int32_t block_size, xpbd_pack* out) {
   if (!out) return XPBD_ERR_INVALID;
   *out = nullptr;
   if ((dtype != XPBD_F32 && dtype != XPBD_F64) || (flags & ~XPBD_PACK_GRAPHS)) return XPBD_ERR_INVALID;
+  if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return XPBD_ERR_INVALID;
   xpbd_pack pk = nullptr;
   try {
     pk = new xpbd_pack_s();
@@ -483,6 +488,7 @@ xpbd_status xpbd_pack_create(xpbd_dtype dtype, int32_t flags, xpbd_pack* out) {
   }
   pk->dtype = dtype;
   pk->graphs = (flags & XPBD_PACK_GRAPHS) != 0;
+  pk->block = block_size ? block_size : kBlock;
   *out = pk;
   return XPBD_OK;
 }

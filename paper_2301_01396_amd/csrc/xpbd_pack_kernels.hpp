@@ -2,7 +2,8 @@
 // contexts (meshes of any size and constraint mix).  A launch's blocks are
 // split into segments, one per (context, set) or (context, vertex range);
 // each block finds its segment by binary search over the segments' first
-// block, then runs exactly the per-item code of the one-context kernels, so
+// block, then runs exactly the per-item code of the one-context kernels
+// (one item per thread; the workgroup size, 64, 128 or 256, is the pack's), so
 // every context's results are bitwise those of running it alone.
 //
 // Each context's frame index lives in device memory and is advanced by the
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_fwd(const PackMember<T>* __rest
                                                      const PackSeg* __restrict__ seg, int nseg, int slot_it) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const PackSeg& S = seg[pack_find(seg, nseg, b)];
-  const int t = (b - S.block0) * kBlock + threadIdx.x;
+  const int t = (b - S.block0) * (int)blockDim.x + threadIdx.x;
   if (t >= S.count) return;
   const PackMember<T>& M = mem[S.member];
   const int ty = TY >= 0 ? TY : S.type;
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_rev(const PackMember<T>* __rest
                                                      const PackSeg* __restrict__ seg, int nseg, int slot_it) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const PackSeg& S = seg[pack_find(seg, nseg, b)];
-  const int t = (b - S.block0) * kBlock + threadIdx.x;
+  const int t = (b - S.block0) * (int)blockDim.x + threadIdx.x;
   if (t >= S.count) return;
   const PackMember<T>& M = mem[S.member];
   const Vec4<T>* tp = reinterpret_cast<const Vec4<T>*>(pack_tape(M, S, slot_it));
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_vert(const PackMember<T>* __res
                                                       const PackSeg* __restrict__ seg, int nseg) {
   const int b = blockIdx.x;
   const PackSeg& S = seg[pack_find(seg, nseg, b)];
-  const int k = (b - S.block0) * kBlock + threadIdx.x;
+  const int k = (b - S.block0) * (int)blockDim.x + threadIdx.x;
   if (k >= S.count) return;
   const PackMember<T>& M = mem[S.member];
   const size_t V = (size_t)M.D.V, f = (size_t)M.f;

@@ -147,7 +147,7 @@ def load() -> C.CDLL:
         lib.xpbd_adjoint_implicit.argtypes = [_vp, C.POINTER(Params), _vp, C.POINTER(C.c_uint8), C.POINTER(CG),
                                               C.POINTER(Grads), _vp]
         lib.xpbd_pack_create.restype = C.c_int
-        lib.xpbd_pack_create.argtypes = [C.c_int, C.c_int32, C.POINTER(_vp)]
+        lib.xpbd_pack_create.argtypes = [C.c_int, C.c_int32, C.c_int32, C.POINTER(_vp)]
         lib.xpbd_pack_destroy.restype = C.c_int
         lib.xpbd_pack_destroy.argtypes = [_vp]
         lib.xpbd_pack_add.restype = C.c_int
@@ -500,13 +500,17 @@ class Pack:
     """Jobs on many simulators advanced together, one frame per round, each
     launch serving the same step of every job (xpbd_pack_* in xpbd.h)."""
 
-    def __init__(self, dtype: torch.dtype = torch.float32, device="cuda:0", graphs: bool = False):
+    def __init__(self, dtype: torch.dtype = torch.float32, device="cuda:0", graphs: bool = False,
+                 block_size: int = 0):
+        """block_size: workgroup size of the pack's launches (64, 128, 256;
+        0 = 256), a performance choice that never changes results."""
         self.lib = load()
         self.dtype = dtype
         self.device = torch.device(device)
+        self.block_size = block_size
         self._pk = _vp()
         rc = self.lib.xpbd_pack_create(F64 if dtype == torch.float64 else F32, PACK_GRAPHS if graphs else 0,
-                                       C.byref(self._pk))
+                                       int(block_size), C.byref(self._pk))
         if rc != XPBD_OK:
             raise XPBDError(rc, "pack create failed")
         self.jobs: Dict[int, PackJob] = {}

@@ -242,12 +242,21 @@ class PackedServer:
     captured HIP graph while a pack's membership stays the same."""
 
     def __init__(self, slots: int = 32, hbm_budget: int = 64 << 30, device="cuda:0",
-                 dtype: torch.dtype = torch.float32, graphs: bool = True, n_packs: int = 1, ahead: int = 2):
+                 dtype: torch.dtype = torch.float32, graphs: Optional[bool] = None, n_packs: int = 1,
+                 ahead: int = 2, block_size: Optional[int] = None):
+        """graphs / block_size: the packs' launch shape; None takes the
+        autotuner's entry for this dtype (``tune.tune_pack``), else graphs
+        on and 256-thread workgroups."""
         self.slots = slots
         self.budget = hbm_budget
         self.device = torch.device(device)
         self.dtype = dtype
-        self.graphs = graphs
+        tuned = {}
+        if graphs is None or block_size is None:
+            from .tune import lookup_pack
+            tuned = lookup_pack(dtype) or {}
+        self.graphs = bool(tuned.get("graphs", 1)) if graphs is None else graphs
+        self.block_size = int(tuned.get("block_size", 0)) if block_size is None else block_size
         self.n_packs = max(1, n_packs)
         self.ahead = max(1, ahead)
         self.pack_stats: List[Dict[str, int]] = []
@@ -303,7 +312,8 @@ class PackedServer:
         packs = []
         for _ in range(self.n_packs):
             st = torch.cuda.Stream(device=self.device)     # default priority
-            packs.append((Pack(dtype=self.dtype, device=self.device, graphs=self.graphs), st, []))
+            packs.append((Pack(dtype=self.dtype, device=self.device, graphs=self.graphs, block_size=self.block_size),
+                          st, []))
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
         with torch.cuda.device(self.device):

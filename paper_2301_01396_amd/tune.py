@@ -7,7 +7,9 @@ persistent frame kernel at any grid size), so the choice is purely a
 performance one.  The
 tuner times a short forward + adjoint rollout for each candidate and keeps
 the fastest per shape bucket (dtype, log2 of the vertex count, sets per
-iteration, groups, constraint mix) in a JSON table.
+iteration, groups, constraint mix) in a JSON table.  Packs are tuned the
+same way on a request mix (their workgroup size and whether rounds replay
+from HIP graphs); the packed server reads that entry.
 """
 from __future__ import annotations
 
@@ -99,6 +101,59 @@ def tune(scene, dtype=torch.float32, frames: int = 1, path: Optional[str] = TABL
 
 def lookup(scene, dtype=torch.float32, path: str = TABLE) -> Optional[Dict[str, int]]:
     return load_table(path).get(shape_key(scene, dtype))
+
+
+# ---------------------------------------------------------------- packs
+PACK_BLOCKS = (64, 128, 256)
+
+
+def pack_key(dtype: torch.dtype) -> str:
+    return f"pack:{'f64' if dtype == torch.float64 else 'f32'}"
+
+
+def pack_candidates() -> List[Dict[str, int]]:
+    """Launch shapes of a pack (all give bitwise the same results): the
+    workgroup size of its set and vertex launches (1, 2 or 4 waves, one item
+    per thread), with rounds launched directly or replayed from HIP graphs."""
+    return [{"block_size": b, "graphs": g} for g in (0, 1) for b in PACK_BLOCKS]
+
+
+def measure_pack(requests, cfg: Dict[str, int], dtype=torch.float32, slots: int = 32) -> float:
+    """Seconds for the packed server to run ``requests`` (all queued at t = 0)
+    with this launch shape."""
+    from .serve import PackedServer
+    for r in requests:
+        r.arrival, r.admitted, r.done, r.result = 0.0, -1.0, -1.0, {}
+    rep = PackedServer(slots=slots, dtype=dtype, graphs=bool(cfg["graphs"]), block_size=cfg["block_size"],
+                       n_packs=1).run(requests)
+    return rep["wall_s"]
+
+
+def tune_pack(requests, dtype=torch.float32, slots: int = 32, path: Optional[str] = TABLE,
+              log=None) -> Dict[str, int]:
+    """Time every pack launch shape on a request mix; store and return the
+    fastest (the packed server reads it when it is not given a shape)."""
+    measure_pack(requests[:2], {"block_size": 256, "graphs": 0}, dtype, slots)   # warm up
+    results = []
+    for cfg in pack_candidates():
+        t = measure_pack(requests, cfg, dtype, slots)
+        results.append((t, cfg))
+        if log:
+            log(f"tune pack {cfg}: {t * 1e3:.1f} ms")
+    results.sort(key=lambda r: r[0])
+    best = dict(results[0][1])
+    best["seconds"] = results[0][0]
+    best["timings"] = [{"cfg": c, "seconds": t} for t, c in results]
+    if path:
+        table = load_table(path)
+        table[pack_key(dtype)] = best
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return best
+
+
+def lookup_pack(dtype=torch.float32, path: str = TABLE) -> Optional[Dict[str, int]]:
+    return load_table(path).get(pack_key(dtype))
 
 
 def simulator(scene, dtype=torch.float32, **kw) -> Simulator:

@@ -827,7 +827,7 @@ def test_p8_general_gap_shrinks_then_plateaus():
 
 
 def test_psd_projection_is_the_positive_part():
-    """Sec. 4.3 (the subsection after Derivative Verification) replaces each
+    """Sec. 4.3 (Positive Definite Projection) replaces each
     constraint's derivative block by its projection onto the PSD cone.  A
     symmetric A splits uniquely as A = P - Q with P, Q positive semidefinite
     and P Q = 0; P is that projection (the nearest PSD matrix in the

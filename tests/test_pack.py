@@ -16,9 +16,11 @@ from paper_2301_01396_amd import scenes
 def test_pack_create_rejects_bad_arguments():
     lib = L.load()
     pk = C.c_void_p()
-    assert lib.xpbd_pack_create(7, 0, C.byref(pk)) == L.XPBD_ERR_INVALID
-    assert lib.xpbd_pack_create(L.F32, 4, C.byref(pk)) == L.XPBD_ERR_INVALID
-    assert lib.xpbd_pack_create(L.F32, L.PACK_GRAPHS, C.byref(pk)) == L.XPBD_OK
+    assert lib.xpbd_pack_create(7, 0, 0, C.byref(pk)) == L.XPBD_ERR_INVALID
+    assert lib.xpbd_pack_create(L.F32, 4, 0, C.byref(pk)) == L.XPBD_ERR_INVALID
+    for bad in (32, 96, 512, -1):
+        assert lib.xpbd_pack_create(L.F32, 0, bad, C.byref(pk)) == L.XPBD_ERR_INVALID
+    assert lib.xpbd_pack_create(L.F32, L.PACK_GRAPHS, 0, C.byref(pk)) == L.XPBD_OK
     st = L.PackStats()
     assert lib.xpbd_pack_get_stats(pk, C.byref(st)) == L.XPBD_OK
     assert st.active_jobs == 0 and st.rounds == 0
@@ -76,7 +78,7 @@ def _same(a, b, label):
         assert np.array_equal(a[k], b[k]), (label, k, float(np.abs(a[k] - b[k]).max()))
 
 
-def _case(dtype, graphs, tape_mode=0, late=False):
+def _case(dtype, graphs, tape_mode=0, late=False, block=0):
     import torch
     from tests._cases import needs_gpu
     needs_gpu()
@@ -90,7 +92,7 @@ def _case(dtype, graphs, tape_mode=0, late=False):
         m = masks[i] if masks[i] is not None else np.ones(F, np.uint8)
         ref.append(_alone(sim, F, _targets(sc, F, i), m, adj[i]))
         sim.close()
-    pk = L.Pack(dtype=dtype, graphs=graphs)
+    pk = L.Pack(dtype=dtype, graphs=graphs, block_size=block)
     sims = [L.Simulator(sc, dtype=dtype, tape_mode=tape_mode) for sc in scs]
     jobs = {}
     first = scs[:2] if late else scs
@@ -132,6 +134,13 @@ def test_pack_matches_alone_fp64(graphs):
 def test_pack_matches_alone_fp32_graphs():
     import torch
     _case(torch.float32, True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("block", [64, 128])
+def test_pack_workgroup_size_does_not_change_results(block):
+    import torch
+    _case(torch.float32, True, block=block)
 
 
 @pytest.mark.gpu

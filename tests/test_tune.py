@@ -39,6 +39,46 @@ def test_table_round_trip(tmp_path):
     assert tune.lookup(sc, torch.float32, p)["persistent_blocks"] == 64
 
 
+def test_packed_server_takes_the_tuned_pack_shape(tmp_path, monkeypatch):
+    import torch
+    from paper_2301_01396_amd import serve
+    p = str(tmp_path / "t.json")
+    assert {(c["block_size"], c["graphs"]) for c in tune.pack_candidates()} == {
+        (b, g) for b in (64, 128, 256) for g in (0, 1)}
+    with open(p, "w") as f:
+        json.dump({tune.pack_key(torch.float32): {"block_size": 64, "graphs": 0}}, f)
+    monkeypatch.setattr(tune, "TABLE", p)
+    monkeypatch.setattr(tune.lookup_pack, "__defaults__", (torch.float32, p))
+    srv = serve.PackedServer(device="cpu")
+    assert srv.block_size == 64 and srv.graphs is False
+    srv = serve.PackedServer(device="cpu", graphs=True, block_size=128)      # explicit shapes win
+    assert srv.block_size == 128 and srv.graphs is True
+    monkeypatch.setattr(tune.lookup_pack, "__defaults__", (torch.float32, str(tmp_path / "none.json")))
+    srv = serve.PackedServer(device="cpu")
+    assert srv.block_size == 0 and srv.graphs is True
+
+
+@pytest.mark.gpu
+def test_tuned_pack_matches_every_shape():
+    """tune_pack over a small mix; every pack shape gives the same results."""
+    import torch
+    from tests._cases import needs_gpu
+    from paper_2301_01396_amd import serve
+    needs_gpu()
+    reqs = serve.make_mix(4, qps=100.0, seed=9, vmax=3000, frames_scale=0.05)
+    best = tune.tune_pack(reqs, torch.float32, slots=8, path=None)
+    assert len(best["timings"]) == len(tune.pack_candidates())
+    outs = []
+    for cfg in tune.pack_candidates():
+        for r in reqs:
+            r.arrival, r.result = 0.0, {}
+        serve.PackedServer(slots=8, graphs=bool(cfg["graphs"]), block_size=cfg["block_size"]).run(reqs)
+        outs.append({r.rid: r.result["x_final"] for r in reqs})
+    for o in outs[1:]:
+        for k, v in o.items():
+            assert np.array_equal(outs[0][k], v)
+
+
 @pytest.mark.gpu
 def test_tuned_simulator_matches_default(tmp_path):
     import torch
