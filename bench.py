@@ -99,21 +99,29 @@ def group_vertices(sc) -> int:
     return tot
 
 
-def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: int) -> float:
+def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: int,
+                snapshots: bool = False) -> float:
     """Average algorithmic bytes per projection of the LDS group launches of
     one iteration: constant entries read, state read and written, record of
     inputs (written by the forward launches that record, read by the
     reverse), and the staged vertices of every group read and written once
-    per launch."""
+    per launch.  With snapshot records the record is the launch's staged
+    positions (3 words per vertex) and its multipliers (1 word per
+    projection, 2 per tet item); the record the reverse replays from them
+    stays within the launch (written and read back by each workgroup) and
+    is not counted."""
     n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
          6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
     tot = max(sum(n.values()), 1)
+    share = 1.0 if reverse else float(recording)
     b = 0.0
     for f, cnt in n.items():
         words = GROUP_REC_WORDS[f][1 if reverse else 0]
-        words += TAPE_WORDS[f] * (1.0 if reverse else float(recording))
+        words += (1 if snapshots else TAPE_WORDS[f]) * share
         b += cnt * words * tsz
     b += staged_vertices * 2 * 4 * tsz
+    if snapshots:
+        b += staged_vertices * 3 * tsz * share
     return b / tot
 
 
@@ -150,6 +158,9 @@ KERNEL_SYMBOL = {0: "k_dist", 1: "k_dist_rev", 2: "k_bend", 3: "k_bend_rev", 4: 
                  10: "k_group_fwd", 11: "k_group_rev", 12: "k_tri", 13: "k_tri_rev"}
 N_FAM = len(FAMILY)
 WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 256}}
+# adjoint record per workload (1: snapshots of each LDS group launch, replayed
+# by the reverse; needs every set in an LDS group)
+WORKLOAD_RECORD = {}
 HBM_PEAK_GBS = 8000.0
 
 # what the parity tests establish for each workload's results, by dtype
@@ -354,7 +365,8 @@ def serving_leg(n_requests: int, pack_slots: int, log) -> dict:
             "sequential_plain": pick(seq), "packed_all_at_t0": pick(sat),
             "packed_poisson_at_sequential_capacity": dict(pick(poi), qps=cap),
             "throughput_vs_sequential": sat["projections_per_s"] / seq["projections_per_s"],
-            "p50_vs_sequential_at_capacity": poi["p50_latency_s"] / seq["p50_latency_s"]}
+            "p50_vs_sequential": sat["p50_latency_s"] / seq["p50_latency_s"],
+            "p99_vs_sequential": sat["p99_latency_s"] / seq["p99_latency_s"]}
 
 
 def implicit_bench(args):
@@ -471,6 +483,9 @@ def main():
     ap.add_argument("--group-records", type=int, default=0,
                     help="LDS groups: 1 entries and state staged in LDS, 2 streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
+    ap.add_argument("--record-kind", type=int, default=-1, choices=[-1, 0, 1],
+                    help="adjoint record: 0 every projection's inputs, 1 snapshots of each LDS group launch "
+                         "replayed by the reverse (-1 = the workload's)")
     ap.add_argument("--merge", default="",
                     help="tiled cloth: border segments and corner clusters per patch, e.g. 8,16 (default: the workload's)")
     ap.add_argument("--tiling", default="", choices=["", "lines", "quads"],
@@ -532,9 +547,10 @@ def main():
     dtype = {"f32": torch.float32, "f64": torch.float64}.get(args.dtype) or (
         torch.float64 if args.workload == "c1" else torch.float32)
     lm = {"auto": 0, "plain": 1, "persistent": 2}[args.launch]
+    rk = args.record_kind if args.record_kind >= 0 else WORKLOAD_RECORD.get(args.workload, 0)
     sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
                     use_groups=not args.no_groups, block_size=args.block, group_records=args.group_records,
-                    group_block=args.group_block)
+                    group_block=args.group_block, record_kind=rk)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
 
@@ -648,7 +664,7 @@ def main():
         if fam == 9:
             return mix_bytes(sc, True, tsz, recording)
         if fam in (10, 11):
-            return group_bytes(sc, fam == 11, tsz, recording, staged)
+            return group_bytes(sc, fam == 11, tsz, recording, staged, rk == 1)
         return alg_bytes(fam, tsz, recording)
 
     for fam in range(N_FAM):
@@ -714,8 +730,8 @@ def main():
             half = proj_step / 2
             frames_fwd = F + (F - kept)
             if all_grouped:
-                fb = group_bytes(sc, False, tsz, recording, staged)
-                rb = group_bytes(sc, True, tsz, recording, staged)
+                fb = group_bytes(sc, False, tsz, recording, staged, rk == 1)
+                rb = group_bytes(sc, True, tsz, recording, staged, rk == 1)
             else:
                 fb = recording * mix_bytes(sc, False, tsz, True) + (1 - recording) * mix_bytes(sc, False, tsz, False)
                 rb = mix_bytes(sc, True, tsz, False)
@@ -767,7 +783,9 @@ def main():
         "launch": ("persistent frame kernel" if info["persistent"] else
                    f"LDS group launches ({info['n_groups_lds']} groups), one launch per other set"
                    if info["n_groups_lds"] else "one kernel launch per set"),
-        "persistent_blocks": info["persistent_blocks"], "tape_mode": info["tape_mode"],
+        "persistent_blocks": info["persistent_blocks"], "tape_mode": info["tape_mode"], "record_kind": rk,
+        "record_bytes_per_iteration": info["tape_bytes_per_iteration"],
+        "forward_record_frames": info["forward_record_frames"],
         "profile_stride": args.profile_stride, "csrc_sha": csrc_hash(),
         "accuracy": ACCURACY.get((args.workload, "f64" if dtype == torch.float64 else "f32")),
         "serving": serving,

@@ -209,6 +209,15 @@ typedef struct {
                                 destroyed with the context), ordered by events, when the
                                 record holds two frames or more; 1: every step on the
                                 call's stream.  Results do not depend on it */
+  int32_t record_kind;       /* what the adjoint's record holds: 0 = the inputs of every
+                                projection (vertex differences and multiplier); 1 = a
+                                snapshot of each LDS group launch (the patch's positions and
+                                multipliers as the launch finds them, about 4.3x smaller on
+                                grid cloths), from which the reverse replays the launch's
+                                sets in LDS to rebuild those inputs (the same arithmetic,
+                                so results are bitwise those of 0).  1 needs every set in an
+                                LDS group and not launch_mode 2 (else XPBD_ERR_INVALID);
+                                packs refuse such contexts */
 } xpbd_options;
 
 /* Validate and upload a problem.  Computes rest lengths, rest dihedral

@@ -116,6 +116,9 @@ struct xpbd_ctx_s {
   int tape_mode_opt;
   int block = kBlock;   // workgroup size of the per-set kernels
   bool group_stream = false;   // LDS groups: records streamed from the global image
+  int record_kind = 0;         // 0 record of every projection's inputs, 1 snapshots of each group launch
+  char* scratch = nullptr;     // record_kind 1, entries streamed: one group launch's replayed record
+  size_t scratch_bytes = 0;
   int group_block = kBlock;    // workgroup size of the LDS group kernels
   int tape_mode_used = 0;
   double tau = 0, alpha_c = 0;
@@ -177,6 +180,12 @@ struct xpbd_ctx_s {
     long long* tpos = nullptr; int* rec_first = nullptr;
     long long tape_off = 0;   // inside one iteration's record
     size_t tape_bytes = 0;
+    // snapshot records (record_kind 1): staged vertices, forward state image
+    // bytes and its first offset, positions / multipliers inside one iteration
+    size_t n_staged = 0, fmul_bytes = 0;
+    long long fmul_lo = 0, snap_x_off = 0, snap_l_off = 0;
+    size_t max_tbytes = 0;     // largest patch record of one iteration
+    bool replay_lds = false;   // entries streamed: the replayed record fits in LDS beside the two tiles
   };
   std::vector<Group> groups;
   std::vector<int> group_at_start, group_at_end;   // per set: group starting / ending there, -1 none
@@ -489,6 +498,9 @@ template <class T> struct Ops {
     G.nset = g.b - g.a;
     G.P = g.P;
     G.tape_off = g.tape_off;
+    G.snap_x_off = g.snap_x_off;
+    G.snap_l_off = g.snap_l_off;
+    G.fmul_lo = g.fmul_lo;
     return G;
   }
 
@@ -509,12 +521,16 @@ template <class T> struct Ops {
     else if (g.heavy) k_group_fwd<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter); \
     else k_group_fwd<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->gfmul, tape_iter);         \
   } while (0)
+    // REC: 0 no record, 1 every projection's inputs, 2 a snapshot of the launch's inputs
+    const int rec = !tape_iter ? 0 : c->record_kind == 1 ? 2 : 1;
     if (first) {
-      if (tape_iter) XPBD_GF(true, true);
-      else XPBD_GF(true, false);
+      if (rec == 2) XPBD_GF(true, 2);
+      else if (rec == 1) XPBD_GF(true, 1);
+      else XPBD_GF(true, 0);
     } else {
-      if (tape_iter) XPBD_GF(false, true);
-      else XPBD_GF(false, false);
+      if (rec == 2) XPBD_GF(false, 2);
+      else if (rec == 1) XPBD_GF(false, 1);
+      else XPBD_GF(false, 0);
     }
 #undef XPBD_GF
     check_launch();
@@ -530,21 +546,32 @@ template <class T> struct Ops {
     dim3 grid(g.P);
     const bool rl = !c->group_stream;
     const int bs = c->group_block;
-    const size_t sm = rl ? g.smem_rev : g.smem_tile;
-#define XPBD_GR(F1, F2)                                                                             \
+    // replay the launch from its snapshot: 0 no, 1 record to the scratch, 2 record in LDS
+    const int rp = c->record_kind != 1 ? 0 : (rl || g.replay_lds) ? 2 : 1;
+    const size_t sm = rl ? g.smem_rev + (rp ? g.smem_tile : 0)
+                         : g.smem_tile + (rp ? g.smem_tile : 0) + (rp == 2 ? g.max_tbytes : 0);
+    char* scr = c->scratch;
+#define XPBD_GR(F1, F2, RP)                                                                         \
   do {                                                                                              \
-    if (rl && g.heavy) k_group_rev<T, F1, F2, true, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);   \
-    else if (rl) k_group_rev<T, F1, F2, true, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);  \
-    else if (g.heavy) k_group_rev<T, F1, F2, false, true><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter); \
-    else k_group_rev<T, F1, F2, false, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter);         \
+    if (rl && g.heavy) k_group_rev<T, F1, F2, true, true, RP><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr);   \
+    else if (rl) k_group_rev<T, F1, F2, true, false, RP><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr);  \
+    else if (g.heavy) k_group_rev<T, F1, F2, false, true, RP><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr); \
+    else k_group_rev<T, F1, F2, false, false, RP><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr);         \
+  } while (0)
+#define XPBD_GR3(F1, F2)                                  \
+  do {                                                    \
+    if (rp == 2) XPBD_GR(F1, F2, 2);                      \
+    else if (rp == 1) XPBD_GR(F1, F2, 1);                 \
+    else XPBD_GR(F1, F2, 0);                              \
   } while (0)
     if (first) {
-      if (last) XPBD_GR(true, true);
-      else XPBD_GR(true, false);
+      if (last) XPBD_GR3(true, true);
+      else XPBD_GR3(true, false);
     } else {
-      if (last) XPBD_GR(false, true);
-      else XPBD_GR(false, false);
+      if (last) XPBD_GR3(false, true);
+      else XPBD_GR3(false, false);
     }
+#undef XPBD_GR3
 #undef XPBD_GR
     check_launch();
     prof_end(c, st, ev, on);
@@ -575,14 +602,17 @@ template <class T> struct Ops {
   }
   template <bool HEAVY> static void allow_lds_heavy(size_t bytes) {
     const void* ks[] = {
-        (const void*)k_group_fwd<T, true, true, true, HEAVY>,   (const void*)k_group_fwd<T, true, false, true, HEAVY>,
-        (const void*)k_group_fwd<T, false, true, true, HEAVY>,  (const void*)k_group_fwd<T, false, false, true, HEAVY>,
-        (const void*)k_group_rev<T, true, true, true, HEAVY>,   (const void*)k_group_rev<T, true, false, true, HEAVY>,
-        (const void*)k_group_rev<T, false, true, true, HEAVY>,  (const void*)k_group_rev<T, false, false, true, HEAVY>,
-        (const void*)k_group_fwd<T, true, true, false, HEAVY>,  (const void*)k_group_fwd<T, true, false, false, HEAVY>,
-        (const void*)k_group_fwd<T, false, true, false, HEAVY>, (const void*)k_group_fwd<T, false, false, false, HEAVY>,
-        (const void*)k_group_rev<T, true, true, false, HEAVY>,  (const void*)k_group_rev<T, true, false, false, HEAVY>,
-        (const void*)k_group_rev<T, false, true, false, HEAVY>, (const void*)k_group_rev<T, false, false, false, HEAVY>};
+#define XPBD_FWD_K(F1, RL) (const void*)k_group_fwd<T, F1, 0, RL, HEAVY>, (const void*)k_group_fwd<T, F1, 1, RL, HEAVY>, \
+                           (const void*)k_group_fwd<T, F1, 2, RL, HEAVY>
+#define XPBD_REV_K(F1, F2, RL) (const void*)k_group_rev<T, F1, F2, RL, HEAVY, 0>, \
+                               (const void*)k_group_rev<T, F1, F2, RL, HEAVY, 1>, \
+                               (const void*)k_group_rev<T, F1, F2, RL, HEAVY, 2>
+        XPBD_FWD_K(true, true), XPBD_FWD_K(false, true), XPBD_FWD_K(true, false), XPBD_FWD_K(false, false),
+        XPBD_REV_K(true, true, true), XPBD_REV_K(true, false, true), XPBD_REV_K(false, true, true),
+        XPBD_REV_K(false, false, true), XPBD_REV_K(true, true, false), XPBD_REV_K(true, false, false),
+        XPBD_REV_K(false, true, false), XPBD_REV_K(false, false, false)};
+#undef XPBD_FWD_K
+#undef XPBD_REV_K
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
@@ -1125,6 +1155,10 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
     fail(XPBD_ERR_INVALID, "group_block must be 0 or a power of two in [64, %d]", kBlock);
   c->group_stream = o->group_records == 2;
   c->group_block = o->group_block ? o->group_block : kBlock;
+  if (o->record_kind < 0 || o->record_kind > 1) fail(XPBD_ERR_INVALID, "record_kind must be 0 or 1");
+  if (o->record_kind == 1 && o->launch_mode == 2)
+    fail(XPBD_ERR_INVALID, "record_kind 1 needs LDS group launches, not the persistent kernel");
+  c->record_kind = o->record_kind;
   c->dtype = o->dtype;
   c->tsz = o->dtype == XPBD_F32 ? 4 : 8;
   c->V = m->n_verts;
@@ -1481,6 +1515,35 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
       toff += align256(G.tape_bytes);
     }
   c->iter_tape_bytes = toff;
+  if (c->record_kind == 1) {
+    // snapshots instead: every set must run inside an LDS group launch
+    for (size_t k = 0; k < c->sets.size(); ++k) {
+      bool in = false;
+      for (const auto& G : c->groups) in = in || (G.lds && (int)k >= G.a && (int)k < G.b);
+      if (!in) fail(XPBD_ERR_INVALID, "record_kind 1: set %zu does not run in an LDS group", k);
+    }
+    size_t so = 0, scr = 0;
+    for (auto& G : c->groups) {
+      if (!G.lds) continue;
+      // entries streamed: the replayed record goes to LDS when the patch's
+      // record and its two tiles fit in 64 KB (several workgroups per CU),
+      // else to a scratch buffer in global memory
+      G.replay_lds = c->group_stream && 2 * G.smem_tile + G.max_tbytes <= 65536;
+      const size_t extra = c->group_stream ? 2 * G.smem_tile + (G.replay_lds ? G.max_tbytes : 0)
+                                           : G.smem_rev + G.smem_tile;
+      if (extra > c->lds_limit) fail(XPBD_ERR_INVALID, "record_kind 1: a patch's replay needs %zu bytes of LDS", extra);
+      G.snap_x_off = (long long)so;
+      so += align256(3 * c->tsz * G.n_staged);
+      G.snap_l_off = (long long)so;
+      so += align256(G.fmul_bytes);
+      if (c->group_stream && !G.replay_lds) scr = std::max(scr, G.tape_bytes);
+      c->max_group_lds = std::max(c->max_group_lds, (int)extra);
+    }
+    c->iter_tape_bytes = so;
+    c->scratch_bytes = c->group_stream ? scr : 0;
+    if (c->dtype == XPBD_F32) Ops<float>::allow_lds((size_t)c->max_group_lds);
+    else Ops<double>::allow_lds((size_t)c->max_group_lds);
+  }
 }
 
 // Build the LDS launch data of every schedule group: patch vertex lists,
@@ -1582,7 +1645,7 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
     size_t mf = 0, mr = 0, isum = 0, fmsum = 0, rmsum = 0, tsum = 0;
     for (int p = 0; p < P; ++p) {
       size_t vb = al32((size_t)(pv_start[p + 1] - pv_start[p]) * sizeof(Vec4<T>));
-      size_t ib = 0, fb = 0, rb = 0, tb = 0;
+      size_t ib = 0, fb = 0, rb = 0, tb = 0;  // entries, forward state, reverse state, record
       for (int q = 0; q < ns; ++q) {
         size_t n = cnt[(size_t)p * ns + q];
         ib += al32(n * rec_bytes<T>(stype[q]));
@@ -1597,11 +1660,15 @@ void build_groups(xpbd_ctx c, const xpbd_schedule_desc* sd, const std::vector<in
       isum += ib; fmsum += fb; rmsum += rb; tsum += tb;
       mf = std::max(mf, vb + ib + fb);
       mr = std::max(mr, vb + ib + rb + tb);
+      G.max_tbytes = std::max(G.max_tbytes, tb);
     }
     G.smem_fwd = mf;
     G.smem_rev = mr;
     G.smem_tile = al32((size_t)nv_max * sizeof(Vec4<T>));
     G.tape_bytes = tsum;
+    G.n_staged = (size_t)pv_start[P];
+    G.fmul_lo = (long long)fmul_total;
+    G.fmul_bytes = fmsum;
     G.lds = P > 0 && nv_max <= 65535 && (c->group_stream ? G.smem_tile : std::max(mf, mr)) <= c->lds_limit;
     if (G.lds) {
       // constant entries in LDS layout; the state images are zeroed on the device
@@ -1759,6 +1826,7 @@ void ensure_adjoint_buffers(xpbd_ctx c, int slots) {
       c->tri_acc = (double*)c->alloc((size_t)4 * c->n_tri * sizeof(double));
     }
   }
+  if (c->scratch_bytes && !c->scratch) c->scratch = (char*)c->alloc(c->scratch_bytes);
   size_t need = (size_t)slots * c->K * c->iter_tape_bytes;
   if (need > c->tape_cap) {
     c->release(c->tape);
@@ -1776,6 +1844,7 @@ bool fits_on_device(xpbd_ctx c, size_t bytes) {
   // adjoint working set not yet allocated counts too (rough upper bound)
   size_t work = c->XB ? 0 : (size_t)c->V * 8 * c->tsz + (size_t)(c->n_dist + c->n_bend + 2 * c->n_tet) * 24 +
                                 (size_t)c->n_contact * 6 * c->tsz + (size_t)c->n_tri * (7 * c->tsz + 32);
+  if (!c->scratch) work += c->scratch_bytes;
   if (c->budget) return c->dev_bytes + extra + work <= c->budget;
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));

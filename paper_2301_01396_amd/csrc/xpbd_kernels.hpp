@@ -1292,11 +1292,16 @@ struct GroupDev {
   const int* rec_first;     // [P][nset] internal index of the patch's first item in each set
   int nset, P;
   long long tape_off;       // byte offset of the group's chunk inside one iteration's record
+  // snapshot records: offsets of the group's staged positions and of its
+  // multipliers inside one iteration's snapshot, and the byte offset of the
+  // group's first patch in the forward state image
+  long long snap_x_off, snap_l_off, fmul_lo;
 };
 
 // Workgroup barrier that orders LDS only: the group kernels share nothing
-// through global memory between sets, so outstanding global stores (the
-// record of projection inputs) keep draining across it.
+// through global memory between threads (a replayed record in global scratch
+// is read back only by the thread that wrote it), so outstanding global
+// stores (records of projection inputs, snapshots) keep draining across it.
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -1309,39 +1314,16 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
 }
 
-// RL: the patch's constant entries and state are staged in LDS with its
-// vertices (one bulk copy in, the state copied out); otherwise only the
-// vertex tile is in LDS and each set's entries are read, and its state read
-// and written, in place in the global images, which keeps the workgroup's
-// LDS small so many patches run per CU.  HEAVY: the group has tet or
-// membrane sets; the kernels without those projections need far fewer
-// registers, so more waves of a distance / bending group run per SIMD.
-template <class T, bool FIRST, bool TAPE, bool RL, bool HEAVY>
-__global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
-                                                      char* __restrict__ fmul, char* __restrict__ tape_iter) {
-  extern __shared__ __align__(32) unsigned char smem[];
-  const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
-  const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
-  const int* cnt = G.cnt + (size_t)p * G.nset;
-  Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
-  const char* gimg = img + G.img[p];
-  char* gmul = fmul + G.fmul[p];
-  unsigned char* lrec = smem + al32((size_t)nv * sizeof(Vec4<T>));
-  size_t rbytes = 0, mbytes = 0;
-  if (RL)
-    for (int q = 0; q < G.nset; ++q) {
-      rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
-      mbytes += al32((size_t)cnt[q] * fmul_words(G.set_type[q]) * sizeof(T));
-    }
-  const unsigned char* r = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
-  unsigned char* m = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
-  for (int i = tid; i < nv; i += kB) sX[i] = D.X[G.pv[v0 + i]];
-  if (RL) {
-    copy16(lrec, gimg, rbytes);
-    if (!FIRST) copy16(lrec + rbytes, gmul, mbytes);   // the first iteration starts from lambda = 0
-  }
-  lds_barrier();
-  char* gt = TAPE ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
+// The group's sets of one iteration in schedule order on the vertex tile sX
+// (LDS), one thread per item with a workgroup barrier between sets: constant
+// entries from r, multipliers from m (written back when KEEP), the record of
+// each projection's inputs to gt when TAPE.  The forward launch and the
+// reverse's replay of a launch (records kept as snapshots) both run this, so
+// they compute every projection bit for bit alike.
+template <class T, bool FIRST, bool TAPE, bool HEAVY, bool KEEP>
+__device__ __forceinline__ void group_sets_fwd(const Dev<T>& D, const GroupDev& G, const int* cnt, Vec4<T>* sX,
+                                               const unsigned char* r, unsigned char* m, char* gt) {
+  const int tid = threadIdx.x, kB = blockDim.x;
   for (int q = 0; q < G.nset; ++q) {
     const int n = cnt[q], ty = G.set_type[q];
     Vec4<T>* tape = reinterpret_cast<Vec4<T>*>(gt);
@@ -1356,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           bool moved;
           T ln = dist_fwd<T, TAPE>(a, bb, s.rest, s.at, l0, tape + i, moved);
           if (moved) { sX[la] = a; sX[lb] = bb; }
-          lam[i] = ln;
+          if (KEEP) lam[i] = ln;
         }
         break;
       case 1:
@@ -1368,7 +1350,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           bool moved;
           T ln = bend_fwd<T, TAPE>(pp, s.th0, s.at, l0, tape, i, n, moved);
           if (moved) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3]; }
-          lam[i] = ln;
+          if (KEEP) lam[i] = ln;
         }
         break;
       case 2:
@@ -1382,7 +1364,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
           T lD = FIRST ? T(0) : lam[i], lH = FIRST ? T(0) : lam[n + i];
           tet_fwd<T, TAPE>(pp, B, s.atD, s.atH, s.gam, lD, lH, tape + i, n);
-          lam[i] = lD; lam[n + i] = lH;
+          if (KEEP) { lam[i] = lD; lam[n + i] = lH; }
           sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; sX[l[3]] = pp[3];
         }
         break;
@@ -1398,7 +1380,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           for (int c = 0; c < 3; ++c) lm[c] = FIRST ? T(0) : lam[c * n + i];
           bool moved = tri_fwd<T, TAPE>(pp, B, at, lm, tape, i, n);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) lam[c * n + i] = lm[c];
+          for (int c = 0; c < 3; ++c) if (KEEP) lam[c * n + i] = lm[c];
           if (moved) { sX[l[0]] = pp[0]; sX[l[1]] = pp[1]; sX[l[2]] = pp[2]; }
         }
         break;
@@ -1411,7 +1393,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           bool moved = false;
           T ln = body_fwd<T, TAPE>(pp, l0, D.bpair[e.j], D, tape + i, moved);
           if (moved) sX[e.l] = pp;
-          lam[i] = ln;
+          if (KEEP) lam[i] = ln;
         }
         break;
       default:
@@ -1422,7 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
           bool moved;
           T ln = contact_fwd<T, TAPE>(pp, D.sph, l0, tape + i, moved);
           if (moved) sX[l] = pp;
-          lam[i] = ln;
+          if (KEEP) lam[i] = ln;
         }
         break;
     }
@@ -1431,13 +1413,72 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
     if (TAPE) gt += al32((size_t)n * tape_words(ty) * sizeof(T));
     lds_barrier();
   }
+}
+
+// RL: the patch's constant entries and state are staged in LDS with its
+// vertices (one bulk copy in, the state copied out); otherwise only the
+// vertex tile is in LDS and each set's entries are read, and its state read
+// and written, in place in the global images, which keeps the workgroup's
+// LDS small so many patches run per CU.  HEAVY: the group has tet or
+// membrane sets; the kernels without those projections need far fewer
+// registers, so more waves of a distance / bending group run per SIMD.
+// REC: 0 no record; 1 the record of every projection's inputs (patch-major,
+// at tape_iter + G.tape_off + G.tpos[p]); 2 a snapshot of the launch's
+// inputs instead: the patch's vertex positions (3 words per staged vertex at
+// tape_iter + G.snap_x_off) and, after the first iteration, its multipliers
+// (the forward state image of the patch, at tape_iter + G.snap_l_off), from
+// which the reverse replays the launch.
+template <class T, bool FIRST, int REC, bool RL, bool HEAVY>
+__global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
+                                                      char* __restrict__ fmul, char* __restrict__ tape_iter) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
+  const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
+  const int* cnt = G.cnt + (size_t)p * G.nset;
+  Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
+  const char* gimg = img + G.img[p];
+  char* gmul = fmul + G.fmul[p];
+  unsigned char* lrec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  size_t rbytes = 0, mbytes = 0;
+  if (RL || REC == 2)
+    for (int q = 0; q < G.nset; ++q) {
+      rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
+      mbytes += al32((size_t)cnt[q] * fmul_words(G.set_type[q]) * sizeof(T));
+    }
+  const unsigned char* r = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
+  unsigned char* m = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
+  T* snx = REC == 2 ? reinterpret_cast<T*>(tape_iter + G.snap_x_off) + 3 * (size_t)v0 : nullptr;
+  for (int i = tid; i < nv; i += kB) {
+    const Vec4<T> x = D.X[G.pv[v0 + i]];
+    sX[i] = x;
+    if (REC == 2) { snx[3 * i] = x.x; snx[3 * i + 1] = x.y; snx[3 * i + 2] = x.z; }
+  }
+  if (RL) {
+    copy16(lrec, gimg, rbytes);
+    if (!FIRST) copy16(lrec + rbytes, gmul, mbytes);   // the first iteration starts from lambda = 0
+  }
+  // the multipliers as this launch finds them (each thread's copy has its
+  // loads back before the barrier below, ahead of any update in place)
+  if (REC == 2 && !FIRST) copy16(tape_iter + G.snap_l_off + (G.fmul[p] - G.fmul_lo), gmul, mbytes);
+  lds_barrier();
+  char* gt = REC == 1 ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
+  group_sets_fwd<T, FIRST, REC == 1, HEAVY, true>(D, G, cnt, sX, r, m, gt);
   for (int i = tid; i < nv; i += kB) D.X[G.pv[v0 + i]] = sX[i];
   if (RL) copy16(gmul, lrec + rbytes, mbytes);
 }
 
-template <class T, bool FIRST, bool LAST, bool RL, bool HEAVY>
+// REPLAY (1, 2): the forward kept a snapshot of this launch's inputs (REC 2
+// of k_group_fwd) instead of the record of every projection: the patch's
+// positions go into a second LDS tile, the forward sets are replayed on it
+// from the snapshot multipliers (group_sets_fwd, so every projection repeats
+// the forward's arithmetic exactly) and write the record into LDS (with the
+// entries staged, RL, or after the two tiles, REPLAY 2) or into this
+// launch's scratch (REPLAY 1, at scratch + G.tpos[p]), where each thread
+// reads back only the items it wrote.
+template <class T, bool FIRST, bool LAST, bool RL, bool HEAVY, int REPLAY>
 __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, const char* __restrict__ img,
-                                                      char* __restrict__ rmul, const char* __restrict__ tape_iter) {
+                                                      char* __restrict__ rmul, const char* __restrict__ tape_iter,
+                                                      char* __restrict__ scratch) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
@@ -1451,18 +1492,35 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
   }
   const char* gimg = img + G.img[p];
   char* gmul = rmul + G.rmul[p];
-  const char* gtap = tape_iter + G.tape_off + G.tpos[p];
+  const char* gtap = REPLAY ? scratch + G.tpos[p] : tape_iter + G.tape_off + G.tpos[p];
   unsigned char* lrec = smem + al32((size_t)nv * sizeof(Vec4<T>));
+  Vec4<T>* sP = REPLAY ? reinterpret_cast<Vec4<T>*>(lrec + (RL ? rbytes + mbytes + tbytes : 0)) : nullptr;
+  // REPLAY 2: the replayed record in LDS after the two tiles
+  unsigned char* ltap = lrec + al32((size_t)nv * sizeof(Vec4<T>));
   const unsigned char* rec = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
   unsigned char* mul = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
-  const unsigned char* tap = RL ? lrec + rbytes + mbytes : reinterpret_cast<const unsigned char*>(gtap);
-  for (int i = tid; i < nv; i += kB) sX[i] = D.XB[G.pv[v0 + i]];
+  const unsigned char* tap = RL ? lrec + rbytes + mbytes
+                                : REPLAY == 2 ? ltap : reinterpret_cast<const unsigned char*>(gtap);
+  const T* snx = REPLAY ? reinterpret_cast<const T*>(tape_iter + G.snap_x_off) + 3 * (size_t)v0 : nullptr;
+  for (int i = tid; i < nv; i += kB) {
+    const Vec4<T> xb = D.XB[G.pv[v0 + i]];   // adjoint and inverse mass
+    sX[i] = xb;
+    if (REPLAY) sP[i] = Vec4<T>{snx[3 * i], snx[3 * i + 1], snx[3 * i + 2], xb.w};
+  }
   if (RL) {
     copy16(lrec, gimg, rbytes);
     if (!FIRST) copy16(lrec + rbytes, gmul, mbytes);   // the last iteration's reverse starts from zero
-    copy16(lrec + rbytes + mbytes, gtap, tbytes);
+    if (!REPLAY) copy16(lrec + rbytes + mbytes, gtap, tbytes);
   }
   lds_barrier();
+  if (REPLAY) {
+    // the forward of iteration 0 (LAST here) started from lambda = 0
+    unsigned char* lsn = reinterpret_cast<unsigned char*>(const_cast<char*>(tape_iter)) + G.snap_l_off +
+                         (G.fmul[p] - G.fmul_lo);
+    char* dst = RL ? reinterpret_cast<char*>(lrec + rbytes + mbytes)
+                   : REPLAY == 2 ? reinterpret_cast<char*>(ltap) : scratch + G.tpos[p];
+    group_sets_fwd<T, LAST, true, HEAVY, false>(D, G, cnt, sP, rec, lsn, dst);
+  }
   // walk the sets backwards: start past the last region
   const unsigned char* r = rec + rbytes;
   unsigned char* m = mul + mbytes;

@@ -116,6 +116,7 @@ template <class T> struct PackOps {
       fail(XPBD_ERR_INVALID, "pack add: tet_E, or tet_mu and tet_lambda, required");
     if (c->n_tri && !j->params.tri_coef) fail(XPBD_ERR_INVALID, "pack add: tri_coef required");
     if (c->n_bc) fail(XPBD_ERR_INVALID, "pack add: body-contact meshes are not packed");
+    if (c->record_kind) fail(XPBD_ERR_INVALID, "pack add: contexts with snapshot records are not packed");
     const bool adj = j->targets != nullptr;
     if (adj && !j->x_frames) fail(XPBD_ERR_INVALID, "pack add: a job with an adjoint needs x_frames");
     c->have_forward = false;

@@ -58,7 +58,8 @@ class Options(C.Structure):
                 ("gravity", C.c_double * 3), ("dtype", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
                 ("tet_gamma_one", C.c_int32), ("tape_mode", C.c_int32), ("launch_mode", C.c_int32),
                 ("persistent_blocks", C.c_int32), ("block_size", C.c_int32), ("group_records", C.c_int32),
-                ("group_block", C.c_int32), ("record_frames", C.c_int32), ("serial_adjoint", C.c_int32)]
+                ("group_block", C.c_int32), ("record_frames", C.c_int32), ("serial_adjoint", C.c_int32),
+                ("record_kind", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -188,7 +189,7 @@ class Simulator:
                  iterations: Optional[int] = None, substeps: Optional[int] = None, launch_mode: int = 0,
                  persistent_blocks: int = 0, use_groups: bool = True, block_size: int = 0,
                  group_records: int = 0, group_block: int = 0, record_frames: int = 0,
-                 serial_adjoint: bool = False):
+                 serial_adjoint: bool = False, record_kind: int = 0):
         self.lib = load()
         self.scene = scene
         self.dtype = dtype
@@ -233,6 +234,7 @@ class Simulator:
         o.group_records = group_records
         o.group_block = group_block
         o.record_frames = record_frames
+        o.record_kind = record_kind
         o.serial_adjoint = 1 if serial_adjoint else 0
         with torch.cuda.device(self.device):
             rc = self.lib.xpbd_create(C.byref(m), C.byref(cd), C.byref(sd), C.byref(o), C.byref(self._ctx))

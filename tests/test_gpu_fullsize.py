@@ -148,7 +148,8 @@ def test_cloth2048x4096_benchmark_adjoint_structure():
     while it recomputes frame 1 from its checkpoint on a second stream, and
     every frame has two substeps of records.  Three frames of 2 substeps x 1
     iteration with the goal on frames 1 and 3: bitwise equal to the
-    one-stream order; positions within 1e-5 and every gradient group's
+    one-stream order and to snapshot records (the reverse replaying each
+    group launch); positions within 1e-5 and every gradient group's
     largest element within 1e-3 of the reference with FP32 state storage;
     each group's L2 error against it within 1e-3 or that reference's own
     distance from the FP64 one, whichever is larger (with one iteration per
@@ -160,18 +161,20 @@ def test_cloth2048x4096_benchmark_adjoint_structure():
     mask = np.array([1, 0, 1], bool)
     ref, plain = _c4_reference(sc, 3, mask, 5)
     outs = []
-    for serial in (False, True):
-        sim = _sim(sc, group_records=2, group_block=256, tape_mode=4, record_frames=2, serial_adjoint=serial)
+    for serial, kind in ((False, 0), (True, 0), (False, 1)):
+        sim = _sim(sc, group_records=2, group_block=256, tape_mode=4, record_frames=2, serial_adjoint=serial,
+                   record_kind=kind)
         outs.append(gpu_case(sim, 3, ref, f_ext=sc.f_ext))
         info = sim.info()
         assert info["tape_mode"] == 4 and info["forward_record_frames"] == 2 and info["n_groups_lds"] == 3
         assert info["adjoint_streams"] == (1 if serial else 2)
         sim.close()
         del sim
-    a, b = outs
-    assert np.array_equal(a["x_frames"], b["x_frames"])
-    for k, v in b["grads"].items():
-        assert np.array_equal(a["grads"][k], v), k
+    a = outs[0]
+    for b in outs[1:]:
+        assert np.array_equal(a["x_frames"], b["x_frames"])
+        for k, v in b["grads"].items():
+            assert np.array_equal(a["grads"][k], v), k
     _c4_report("cloth2048x4096 benchmark adjoint structure", ref, plain, a)
     errs = compare(sc, ref, a, 1e-5, float("inf"), grad_max_tol=1e-3)
     for k, r in ref["grads"].items():

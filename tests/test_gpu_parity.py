@@ -190,7 +190,10 @@ def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
     a = gpu_case(a_sim, 2, ref)
     b = gpu_case(b_sim, 2, ref)
     c = gpu_case(c_sim, 2, ref)
-    for o in (b, c):
+    # snapshot records: the reverse replays each launch (entries in LDS, and streamed)
+    d = gpu_case(_sim(sc, dtype, record_kind=1), 2, ref)
+    e = gpu_case(_sim(sc, dtype, record_kind=1, group_records=2, group_block=64), 2, ref)
+    for o in (b, c, d, e):
         assert np.array_equal(a["x_frames"], o["x_frames"])
         for k, v in o["grads"].items():
             assert np.array_equal(a["grads"][k], v), k
@@ -354,7 +357,8 @@ def test_membrane_lds_groups_match_per_set_launches_and_reference(dtype, tiling)
     sc = tile(scenes.membrane_cloth(n=41, frames=2, substeps=2, iterations=3), 41, 41, 8)
     assert scenes.TRI in {sc.set_type[k] for a, b, _ in sc.groups for k in range(a, b)}
     ref = reference_case(sc, 2, n_threads=8)
-    sims = [_sim(sc, dtype), _sim(sc, dtype, group_records=2, group_block=64), _sim(sc, dtype, use_groups=False)]
+    sims = [_sim(sc, dtype), _sim(sc, dtype, group_records=2, group_block=64), _sim(sc, dtype, use_groups=False),
+            _sim(sc, dtype, record_kind=1), _sim(sc, dtype, record_kind=1, group_records=2, group_block=64)]
     assert sims[0].info()["n_groups_lds"] == len(sc.groups) and sims[2].info()["n_groups"] == 0
     outs = [gpu_case(s, 2, ref) for s in sims]
     for o in outs[1:]:
@@ -431,6 +435,8 @@ def test_body_contacts_in_lds_groups_match_per_set_launches_and_reference(dtype)
     assert np.abs(ref["grads"]["body_x"]).max() > 0
     sims = [_sim(sc, dtype), _sim(sc, dtype, group_records=2, group_block=64), _sim(sc, dtype, use_groups=False)]
     assert sims[0].info()["n_groups_lds"] == len(sc.groups) and sims[2].info()["n_groups"] == 0
+    if all(any(a <= k < b for a, b, _ in sc.groups) for k in range(len(sc.set_type))):
+        sims += [_sim(sc, dtype, record_kind=1), _sim(sc, dtype, record_kind=1, group_records=2, group_block=64)]
     outs = [gpu_case(s, 2, ref) for s in sims]
     for o in outs[1:]:
         assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
@@ -552,3 +558,46 @@ def test_fp32_applies_corrections_that_vanish_in_lambda(groups):
     assert sim.info()["n_groups_lds"] == (1 if groups else 0)
     got = gpu_case(sim, 1, ref)
     compare(sc, ref, got, 1e-5, 1e-3, groups=())
+
+
+def test_snapshot_records_in_every_tape_mode():
+    """Snapshot records (the reverse replays each group launch from the
+    positions and multipliers the launch found) in every record mode,
+    including the forward keeping its last frames and the recomputation
+    beside the reverse on a second stream: bitwise the same as the record
+    of every projection's inputs, from a smaller record."""
+    sc = _tiled_cloth(n=37, tile=8, lines=True)
+    sc.n_frames = 6
+    ref = reference_case(sc, 6, n_threads=8)
+    base = _sim(sc, "f32", group_records=2, tape_mode=1, serial_adjoint=True)
+    want = gpu_case(base, 6, ref)
+    full = base.info()["tape_bytes_per_iteration"]
+    for kind_kw in ({"group_records": 2}, {}):
+        for mode, kw in ((1, {}), (1, {"serial_adjoint": True}), (2, {}), (3, {}),
+                         (4, {"record_frames": 3}), (4, {"record_frames": 1})):
+            sim = _sim(sc, "f32", record_kind=1, tape_mode=mode, **kind_kw, **kw)
+            got = gpu_case(sim, 6, ref)
+            info = sim.info()
+            assert info["tape_mode"] == mode
+            assert info["tape_bytes_per_iteration"] < full
+            assert np.array_equal(got["x_frames"], want["x_frames"]), (mode, kw, kind_kw)
+            for k, v in want["grads"].items():
+                assert np.array_equal(got["grads"][k], v), (mode, kw, kind_kw, k)
+            sim.close()
+    compare(sc, ref, want, 1e-5, 1e-3)
+
+
+def test_snapshot_records_need_lds_groups():
+    from paper_2301_01396_amd import lib as L
+    sc = _tiled_cloth(n=37, tile=8, lines=True)
+    for kw in ({"use_groups": False}, {"launch_mode": 2}):
+        with pytest.raises(L.XPBDError) as e:
+            _sim(sc, "f32", record_kind=1, **kw)
+        assert e.value.status == L.XPBD_ERR_INVALID
+    sim = _sim(sc, "f32", record_kind=1)
+    pk = L.Pack()
+    with pytest.raises(L.XPBDError) as e:
+        pk.add(sim, 2)
+    assert e.value.status == L.XPBD_ERR_INVALID
+    pk.close()
+    sim.close()
