@@ -229,15 +229,17 @@ def workload_config(name, sc, F):
             "sets_per_iteration": len(sc.set_type), "lds_groups": len(sc.groups)}
 
 
-def cpu_baseline(name, sc, max_projections: int = 60_000_000):
-    """The FP64 reference on the host cores, on a bounded prefix of the
-    workload: one frame, with fewer substeps / iterations when one frame
-    holds more than ``max_projections`` forward projections; forward and
-    adjoint are both timed."""
+def cpu_baseline(name, sc, max_projections: int = 60_000_000, threads: int = 0):
+    """The FP64 reference on the host cores (``threads``, 0 = all the
+    process may use), on a bounded prefix of the workload: one frame, with
+    fewer substeps / iterations when one frame holds more than
+    ``max_projections`` forward projections; forward and adjoint are both
+    timed."""
     import copy
     import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1))
+    if threads <= 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = max(1, min(threads, os.cpu_count() or 1))
     sample = copy.copy(sc)
     per_it = sc.projections_per_iteration()
     if per_it * sc.iterations * sc.substeps > max_projections:
@@ -270,6 +272,16 @@ def cpu_baseline(name, sc, max_projections: int = 60_000_000):
             "sample": f"{frames} frame(s) of the workload with {sample.substeps} substep(s) x {sample.iterations} "
                       f"iterations ({proj} forward + {proj} reverse projections, FP64): "
                       f"forward {t1 - t0:.2f} s, adjoint incl. recompute {t2 - t1:.2f} s"}
+
+
+def scenes_small_for_one_core(name, sc):
+    """A sample of the workload one core times in seconds: the 2048x4096
+    cloth cut to 256 of its rows (same columns, tiling and parameters'
+    distribution), the other workloads unchanged."""
+    if name != "c4":
+        return sc
+    from paper_2301_01396_amd import scenes
+    return scenes.config_c4(n_frames=1, nr=256)
 
 
 def serve_bench(args):
@@ -762,6 +774,16 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, sc)
+        # one core, on a sample small enough for it: the 2048-column cloth
+        # cut to 256 rows (the same tiles, sets and launch structure), the
+        # smaller workloads as they are
+        one_sc = scenes_small_for_one_core(args.workload, sc)
+        one = cpu_baseline(args.workload, one_sc, max_projections=4_000_000, threads=1)
+        cpu["one_core"] = {k: one[k] for k in ("value", "forward_projections_per_s", "adjoint_projections_per_s",
+                                              "sample")}
+        if one_sc is not sc:
+            cpu["one_core"]["sample"] = (f"{one_sc.n_verts}-vertex cut of the workload ({one_sc.name}): "
+                                         + one["sample"])
 
     serving = None
     if args.workload == "c4" and args.serve_requests > 0:

@@ -18,7 +18,8 @@ HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith
 # disabled (-packed-fp32-ops) for the device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function"]
+         "-Wall", "-Wno-unused-function", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+         "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> str:

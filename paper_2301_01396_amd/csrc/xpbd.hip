@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/xpbd.h"
 #include "xpbd_kernels.hpp"
 #include "xpbd_pack_kernels.hpp"
@@ -44,6 +46,16 @@ struct Fail {
   } while (0)
 
 inline unsigned nblocks(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// Host-side roctx range over a scope (frames, substeps, Gauss-Seidel sweeps):
+// what rocprofv3 --marker-trace shows of the library's launch loops; a call
+// costs a few tens of nanoseconds when no tool listens.
+struct Range {
+  explicit Range(const char* m) { roctxRangePushA(m); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct SetInfo {
@@ -626,6 +638,7 @@ template <class T> struct Ops {
   // one substep of Eq. xpbdUpdateRule; record slot < 0 means no record;
   // gsub = frame * S + substep (the body pairing's slot)
   static void substep(xpbd_ctx c, const Dev<T>& D0, const T* f, int slot, hipStream_t st, int gsub = -1) {
+    Range range_(slot >= 0 ? "xpbd substep (recording)" : "xpbd substep");
     Dev<T> D = D0;
     k_predict<T><<<nblocks(c->V), kBlock, 0, st>>>(D, f);
     check_launch();
@@ -636,7 +649,8 @@ template <class T> struct Ops {
       check_launch();
     }
     const int ns = (int)c->sets.size();
-    for (int it = 0; it < c->K; ++it)
+    for (int it = 0; it < c->K; ++it) {
+      Range sweep_("xpbd sweep");
       for (int k = 0; k < ns; ++k) {
         int g = c->group_at_start.empty() ? -1 : c->group_at_start[k];
         if (g >= 0 && c->groups[g].lds) {
@@ -648,17 +662,20 @@ template <class T> struct Ops {
         const SetInfo& si = c->sets[k];
         project(c, D, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
       }
+    }
     k_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
   }
 
   static void reverse_substep(xpbd_ctx c, const Dev<T>& D0, T* fbar, double* dsph, int slot, hipStream_t st,
                               int gsub = -1) {
+    Range range_("xpbd reverse substep");
     Dev<T> D = D0;
     if (c->n_bc) D.bpair = pairs_of(c, gsub);
     k_rev_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
-    for (int it = c->K - 1; it >= 0; --it)
+    for (int it = c->K - 1; it >= 0; --it) {
+      Range sweep_("xpbd reverse sweep");
       for (int k = (int)c->sets.size() - 1; k >= 0; --k) {
         int g = c->group_at_end.empty() ? -1 : c->group_at_end[k];
         if (g >= 0 && c->groups[g].lds) {
@@ -670,6 +687,7 @@ template <class T> struct Ops {
         const SetInfo& si = c->sets[k];
         reverse(c, D, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), st);
       }
+    }
     if (c->K > 0 && dsph)
       for (const SetInfo& si : c->sets)
         if (si.type == XPBD_CONTACT && si.count > 0) {
@@ -899,6 +917,7 @@ template <class T> struct Ops {
     check_launch();
     const size_t frame_tape = (size_t)c->S * c->K * c->iter_tape_bytes;
     for (int f = 0; f < F; ++f) {
+      Range frame_("xpbd frame");
       HIPCHK(hipMemcpyAsync((char*)c->ckX + f * vb, c->X, vb, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync((char*)c->ckV + f * vb, c->Vv, vb, hipMemcpyDeviceToDevice, st));
       const T* ff = p->f_ext ? (const T*)p->f_ext + (size_t)f * 3 * V : nullptr;
@@ -946,6 +965,7 @@ template <class T> struct Ops {
       return;
     }
     for (int f = F - 1; f >= 0; --f) {
+      Range frame_("xpbd adjoint frame");
       if (dLdx && (!mask || mask[f])) {
         k_adj_inject<T><<<nblocks(V), kBlock, 0, st>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);
         check_launch();
@@ -1021,12 +1041,14 @@ template <class T> struct Ops {
       // enqueued so far have run
       while (next >= 0 && next + nslot > f) {
         const int g = next--;
+        Range rec_("xpbd recompute frame");
         if (g + nslot <= F - 1) HIPCHK(hipStreamWaitEvent(sr, ev_rev[g + nslot], 0));
         const T* fg = p->f_ext ? (const T*)p->f_ext + (size_t)g * 3 * V : nullptr;
         restore(c, g, sr);
         for (int s = 0; s < S; ++s) substep(c, D, fg, slot[g] * S + s, sr, g * S + s);
         HIPCHK(hipEventRecord(ev_rec[g], sr));
       }
+      Range frame_("xpbd adjoint frame");
       if (f < rec_from) HIPCHK(hipStreamWaitEvent(sv, ev_rec[f], 0));
       if (dLdx && (!mask || mask[f])) {
         k_adj_inject<T><<<nblocks(V), kBlock, 0, sv>>>((V4*)c->XB, (const T*)dLdx + (size_t)f * 3 * V, V);

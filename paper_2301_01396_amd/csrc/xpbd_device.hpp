@@ -44,7 +44,7 @@ template <class T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, Dual<
 template <class T> __device__ __forceinline__ Dual<T> operator*(T s, Dual<T> a) { return {s * a.v, s * a.d}; }
 template <class T> __device__ __forceinline__ Dual<T> dsqrt(Dual<T> a) {
   T r = sqrt(a.v);
-  return {r, a.d / (T(2) * r)};
+  return {r, T(0.5) * a.d * (T(1) / r)};   // 1/r is the quotient the gradient forms next
 }
 template <class T> __device__ __forceinline__ T dsqrt(T a) { return sqrt(a); }
 template <class T> __device__ __forceinline__ T val(T a) { return a; }
@@ -53,14 +53,14 @@ template <class T> __device__ __forceinline__ T scal(T s, T) { return s; }
 
 // ----------------------------------------------------------------- distance
 // C = |r| - L, grad_i = n, grad_j = -n (n = r/|r|).
-template <class T> struct DistEval { T C, len; V3<T> n; bool ok; };
+template <class T> struct DistEval { T C, len, inv; V3<T> n; bool ok; };
 template <class T> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L) {
   DistEval<T> e;
   T l2 = dot(r, r);
   e.ok = l2 > T(0);
   e.len = sqrt(l2);
-  T inv = T(1) / e.len;
-  e.n = inv * r;
+  e.inv = T(1) / e.len;
+  e.n = e.inv * r;
   e.C = e.len - L;
   return e;
 }
@@ -94,7 +94,7 @@ template <class T> __device__ __forceinline__ BendEval<T> bend_eval(V3<T> e, V3<
   T le2 = dot(e, e), q1 = dot(n1, n1), q2 = dot(n2, n2);
   r.ok = le2 > T(0) && q1 > T(0) && q2 > T(0);
   T le = sqrt(le2);
-  T y = dot(cross(n1, n2), e) / le;
+  T y = dot(cross(n1, n2), e) * (T(1) / le);   // 1/|e| is the quotient the gradient forms too
   T x = dot(n1, n2);
   r.C = atan2(y, x) - theta0;
   bend_gradient<T>(e, a, b, r.g);

@@ -284,15 +284,19 @@ __device__ __forceinline__ bool tri_fwd(Vec4<T> p[3], const T B[4], const T at[4
 }
 
 // Adjoint of one projection given the adjoints of its outputs: gradient g_k,
-// weights w_k, denominator D, dlambda, lambda_bar, position adjoints xb_k.
-// Returns dlambda_bar; writes gbar_k (adjoint of grad_k C).
+// weights w_k, iD = 1 / D (the denominator's reciprocal), dlambda,
+// lambda_bar, position adjoints xb_k.  Returns dlambda_bar; writes gbar_k
+// (adjoint of grad_k C).  The reverse cores divide by D once (iD) and
+// multiply: the adjoint needs no quotient that the forward also forms (only
+// dlambda must repeat the forward's division exactly, and it does), and the
+// kernels spend most of their issue slots on VALU arithmetic.
 template <class T, int N>
-__device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T D, T dl, T lbar, const V3<T> xb[N],
+__device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T iD, T dl, T lbar, const V3<T> xb[N],
                                           V3<T> gb[N]) {
   T dlb = lbar;
 #pragma unroll
   for (int k = 0; k < N; ++k) dlb += w[k] * dot(g[k], xb[k]);
-  T c = T(2) * dlb * dl / D;
+  T c = T(2) * dlb * dl * iD;
 #pragma unroll
   for (int k = 0; k < N; ++k) gb[k] = {w[k] * (dl * xb[k].x - c * g[k].x), w[k] * (dl * xb[k].y - c * g[k].y),
                                       w[k] * (dl * xb[k].z - c * g[k].z)};
@@ -307,17 +311,18 @@ __device__ __forceinline__ bool dist_rev(Vec4<T>& A, Vec4<T>& Bv, Vec4<T> tp, T 
   if (!(ev.ok && Dn > T(0))) return false;
   T lb = tp.w;
   T dl = (-ev.C - a_t * lb) / Dn;
+  const T iD = T(1) / Dn;
   V3<T> xa = xyz(A), xb = xyz(Bv);
   T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
   // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
   // along n and vanishes under P, leaving dl * P (w_i xa - w_j xb) / |r|.
   V3<T> u = A.w * xa - Bv.w * xb;
   T un = dot(ev.n, u);
-  T s = dl / ev.len;
+  T s = dl * ev.inv;
   V3<T> hv = {s * (u.x - un * ev.n.x), s * (u.y - un * ev.n.y), s * (u.z - un * ev.n.z)};
-  T Cb = -dlb / Dn;
-  lbar = lbar - dlb * a_t / Dn;
-  ab = ab - dlb * (lb + dl) / Dn;
+  T Cb = -dlb * iD;
+  lbar = lbar - dlb * a_t * iD;
+  ab = ab - dlb * (lb + dl) * iD;
   A.x += Cb * ev.n.x + hv.x; A.y += Cb * ev.n.y + hv.y; A.z += Cb * ev.n.z + hv.z;
   Bv.x -= Cb * ev.n.x + hv.x; Bv.y -= Cb * ev.n.y + hv.y; Bv.z -= Cb * ev.n.z + hv.z;
   return true;
@@ -337,13 +342,14 @@ __device__ __forceinline__ bool bend_rev(Vec4<T> P[4], const Vec4<T>* tape, int 
   for (int k = 0; k < 4; ++k) Dn += w[k] * dot(ev.g[k], ev.g[k]);
   if (!(ev.ok && Dn > T(0))) return false;
   T dl = (-ev.C - a_t * lb) / Dn;
+  const T iD = T(1) / Dn;
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
-  T dlb = proj_adjoint<T, 4>(ev.g, w, Dn, dl, lbar, xb, gb);
+  T dlb = proj_adjoint<T, 4>(ev.g, w, iD, dl, lbar, xb, gb);
   bend_hvp(e, a, b, gb, hv);
-  T Cb = -dlb / Dn;
-  lbar = lbar - dlb * a_t / Dn;
-  ab = ab - dlb * (lb + dl) / Dn;
+  T Cb = -dlb * iD;
+  lbar = lbar - dlb * a_t * iD;
+  ab = ab - dlb * (lb + dl) * iD;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     P[k].x += Cb * ev.g[k].x + hv[k].x;
@@ -370,21 +376,23 @@ __device__ __forceinline__ bool tet_rev(Vec4<T> P[4], const Vec4<T>* tape, int c
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
   if (s.appH) {
-    T dlb = proj_adjoint<T, 4>(s.evH.g, w, s.DH, s.dlH, lbH, xb, gb);
+    const T iD = T(1) / s.DH;
+    T dlb = proj_adjoint<T, 4>(s.evH.g, w, iD, s.dlH, lbH, xb, gb);
     tet_hyd_hvp(s.evH, B, gb, hv);
-    T Cb = -dlb / s.DH;
-    lbH = lbH - dlb * atH / s.DH;
-    ebH = ebH - dlb * (lH + s.dlH) / s.DH * atH;
+    T Cb = -dlb * iD;
+    lbH = lbH - dlb * atH * iD;
+    ebH = ebH - dlb * (lH + s.dlH) * iD * atH;
     gmb = gmb - Cb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evH.g[k] + hv[k]);
   }
   if (s.appD) {
-    T dlb = proj_adjoint<T, 4>(s.evD.g, w, s.DD, s.dlD, lbD, xb, gb);
+    const T iD = T(1) / s.DD;
+    T dlb = proj_adjoint<T, 4>(s.evD.g, w, iD, s.dlD, lbD, xb, gb);
     tet_dev_hvp(s.evD, B, gb, hv);
-    T Cb = -dlb / s.DD;
-    lbD = lbD - dlb * atD / s.DD;
-    ebD = ebD - dlb * (lD + s.dlD) / s.DD * atD;
+    T Cb = -dlb * iD;
+    lbD = lbD - dlb * atD * iD;
+    ebD = ebD - dlb * (lD + s.dlD) * iD * atD;
 #pragma unroll
     for (int k = 0; k < 4; ++k) xb[k] = xb[k] + (Cb * s.evD.g[k] + hv[k]);
   }
@@ -402,15 +410,16 @@ __device__ __forceinline__ bool contact_rev(Vec4<T>& P, Vec4<T> tp, const Sphere
   if (!(ev.ok && ev.C < T(0) && Dn > T(0))) return false;
   T lb = tp.w;
   T dl = (-ev.C - S.at * lb) / Dn;
+  const T iD = T(1) / Dn;
   V3<T> xb = xyz(P);
   T dlb = lbar + P.w * dot(ev.n, xb);
-  T c = T(2) * dlb * dl / Dn;
+  T c = T(2) * dlb * dl * iD;
   V3<T> gb = {P.w * (dl * xb.x - c * ev.n.x), P.w * (dl * xb.y - c * ev.n.y), P.w * (dl * xb.z - c * ev.n.z)};
   T gn = dot(ev.n, gb);
   T inv = T(1) / ev.d;
   V3<T> hv = {inv * (gb.x - gn * ev.n.x), inv * (gb.y - gn * ev.n.y), inv * (gb.z - gn * ev.n.z)};
-  T Cb = -dlb / Dn;
-  lbar = lbar - dlb * S.at / Dn;
+  T Cb = -dlb * iD;
+  lbar = lbar - dlb * S.at * iD;
   P.x += Cb * ev.n.x + hv.x; P.y += Cb * ev.n.y + hv.y; P.z += Cb * ev.n.z + hv.z;
   // C = |x - c| - R - tau: dC/dc = -n, dC/dR = -1, d(grad_x C)/dc = -P/|x-c|
   sa.x -= Cb * ev.n.x + hv.x; sa.y -= Cb * ev.n.y + hv.y; sa.z -= Cb * ev.n.z + hv.z;
