@@ -495,6 +495,9 @@ def main():
     ap.add_argument("--group-records", type=int, default=0,
                     help="LDS groups: 1 entries and state staged in LDS, 2 streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
+    ap.add_argument("--tape-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="adjoint record mode (0 auto: whole rollout if it fits, else the last frames, "
+                         "else per frame; 1 recompute every frame from its checkpoint)")
     ap.add_argument("--record-kind", type=int, default=-1, choices=[-1, 0, 1],
                     help="adjoint record: 0 every projection's inputs, 1 snapshots of each LDS group launch "
                          "replayed by the reverse (-1 = the workload's)")
@@ -562,7 +565,7 @@ def main():
     rk = args.record_kind if args.record_kind >= 0 else WORKLOAD_RECORD.get(args.workload, 0)
     sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
                     use_groups=not args.no_groups, block_size=args.block, group_records=args.group_records,
-                    group_block=args.group_block, record_kind=rk)
+                    group_block=args.group_block, record_kind=rk, tape_mode=args.tape_mode)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
 
@@ -756,8 +759,9 @@ def main():
             if all_grouped and fr and rr:
                 launches_frame = sc.substeps * sc.iterations * len(sc.groups)
                 def per_dispatch(recording):     # dispatch-weighted over the template variants
+                    # third template argument of k_group_fwd: the record kind (0 none)
                     vs = [v for n_, v in fr["variants"].items()
-                          if (n_.split(",")[2].strip() == "true") == recording]
+                          if (n_.split(",")[2].strip() not in ("0", "false")) == recording]
                     return (sum(v["dispatches"] * (v["fetch_bytes"] + v["write_bytes"]) for v in vs)
                             / max(sum(v["dispatches"] for v in vs), 1))
                 cb = launches_frame * (F * per_dispatch(True) + (frames_fwd - F) * per_dispatch(False)
