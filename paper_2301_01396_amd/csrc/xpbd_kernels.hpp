@@ -1323,6 +1323,17 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
 }
 
+// A group launch stages its patch's item count and the type of every set
+// (at most kMaxGroupSets) in LDS first, since global loads of them at each set
+// step would put a memory round trip ahead of the set's own loads.
+__device__ __forceinline__ void stage_sets(const GroupDev& G, int p, int* s_cnt, int* s_ty) {
+  for (int q = threadIdx.x; q < G.nset; q += blockDim.x) {
+    s_cnt[q] = G.cnt[(size_t)p * G.nset + q];
+    s_ty[q] = G.set_type[q];
+  }
+  lds_barrier();
+}
+
 // The group's sets of one iteration in schedule order on the vertex tile sX
 // (LDS), one thread per item with a workgroup barrier between sets: constant
 // entries from r, multipliers from m (written back when KEEP), the record of
@@ -1330,11 +1341,11 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
 // reverse's replay of a launch (records kept as snapshots) both run this, so
 // they compute every projection bit for bit alike.
 template <class T, bool FIRST, bool TAPE, bool HEAVY, bool KEEP>
-__device__ __forceinline__ void group_sets_fwd(const Dev<T>& D, const GroupDev& G, const int* cnt, Vec4<T>* sX,
-                                               const unsigned char* r, unsigned char* m, char* gt) {
+__device__ __forceinline__ void group_sets_fwd(const Dev<T>& D, const GroupDev& G, const int* cnt, const int* sty,
+                                               Vec4<T>* sX, const unsigned char* r, unsigned char* m, char* gt) {
   const int tid = threadIdx.x, kB = blockDim.x;
   for (int q = 0; q < G.nset; ++q) {
-    const int n = cnt[q], ty = G.set_type[q];
+    const int n = cnt[q], ty = sty[q];
     Vec4<T>* tape = reinterpret_cast<Vec4<T>*>(gt);
     T* lam = reinterpret_cast<T*>(m);
     switch (ty) {
@@ -1441,9 +1452,10 @@ template <class T, bool FIRST, int REC, bool RL, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ fmul, char* __restrict__ tape_iter) {
   extern __shared__ __align__(32) unsigned char smem[];
+  __shared__ int cnt[kMaxGroupSets], sty[kMaxGroupSets];
   const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
-  const int* cnt = G.cnt + (size_t)p * G.nset;
+  stage_sets(G, p, cnt, sty);
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
   const char* gimg = img + G.img[p];
   char* gmul = fmul + G.fmul[p];
@@ -1451,8 +1463,8 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
   size_t rbytes = 0, mbytes = 0;
   if (RL || REC == 2)
     for (int q = 0; q < G.nset; ++q) {
-      rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
-      mbytes += al32((size_t)cnt[q] * fmul_words(G.set_type[q]) * sizeof(T));
+      rbytes += al32((size_t)cnt[q] * rec_bytes<T>(sty[q]));
+      mbytes += al32((size_t)cnt[q] * fmul_words(sty[q]) * sizeof(T));
     }
   const unsigned char* r = RL ? lrec : reinterpret_cast<const unsigned char*>(gimg);
   unsigned char* m = RL ? lrec + rbytes : reinterpret_cast<unsigned char*>(gmul);
@@ -1471,9 +1483,150 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
   if (REC == 2 && !FIRST) copy16(tape_iter + G.snap_l_off + (G.fmul[p] - G.fmul_lo), gmul, mbytes);
   lds_barrier();
   char* gt = REC == 1 ? tape_iter + G.tape_off + G.tpos[p] : nullptr;
-  group_sets_fwd<T, FIRST, REC == 1, HEAVY, true>(D, G, cnt, sX, r, m, gt);
+  group_sets_fwd<T, FIRST, REC == 1, HEAVY, true>(D, G, cnt, sty, sX, r, m, gt);
   for (int i = tid; i < nv; i += kB) D.X[G.pv[v0 + i]] = sX[i];
   if (RL) copy16(gmul, lrec + rbytes, mbytes);
+}
+
+// The reverse of one set of a group launch (the adjoint of its projections in
+// reverse item order does not matter: the items of a set share no vertex):
+// constant entries from r, the reverse state read and written in place at m,
+// the record of the forward's inputs from t, the vertex adjoints in the LDS
+// tile sX.
+template <class T, bool FIRST, bool HEAVY>
+__device__ __forceinline__ void group_set_rev(const Dev<T>& D, int ty, int n, const unsigned char* r,
+                                              unsigned char* m, const unsigned char* t, Vec4<T>* sX) {
+  const int tid = threadIdx.x, kB = blockDim.x;
+  const Vec4<T>* st = reinterpret_cast<const Vec4<T>*>(t);
+  T* mb = reinterpret_cast<T*>(m);
+  switch (ty) {
+    case 0:
+      for (int i = tid; i < n; i += kB) {
+        const SDist<T> s = reinterpret_cast<const SDist<T>*>(r)[i];
+        int la = lo16(s.l), lb = hi16(s.l);
+        Vec4<T> A = sX[la], Bv = sX[lb];
+        T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
+        if (dist_rev(A, Bv, st[i], s.rest, s.at, lbar, ab)) { sX[la] = A; sX[lb] = Bv; }
+        mb[i] = lbar; mb[n + i] = ab;
+      }
+      break;
+    case 1:
+      for (int i = tid; i < n; i += kB) {
+        const SBend<T> s = reinterpret_cast<const SBend<T>*>(r)[i];
+        int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+        Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+        T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
+        if (bend_rev(P, st, i, n, s.th0, s.at, lbar, ab)) {
+          sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
+        }
+        mb[i] = lbar; mb[n + i] = ab;
+      }
+      break;
+    case 2:
+      if constexpr (HEAVY)
+      for (int i = tid; i < n; i += kB) {
+        const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
+        int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
+        Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
+        M3<T> B;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
+        T lbD = FIRST ? T(0) : mb[i], lbH = FIRST ? T(0) : mb[n + i];
+        T ebD = FIRST ? T(0) : mb[2 * n + i], ebH = FIRST ? T(0) : mb[3 * n + i];
+        T gb = FIRST ? T(0) : mb[4 * n + i];
+        if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, ebD, ebH, gb)) {
+          sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
+        }
+        mb[i] = lbD; mb[n + i] = lbH; mb[2 * n + i] = ebD; mb[3 * n + i] = ebH; mb[4 * n + i] = gb;
+      }
+      break;
+    case 4:
+      if constexpr (HEAVY)
+      for (int i = tid; i < n; i += kB) {
+        const STri<T>& s = reinterpret_cast<const STri<T>*>(r)[i];
+        int l[3] = {lo16(s.l01), hi16(s.l01), (int)s.l2};
+        Vec4<T> P[3] = {sX[l[0]], sX[l[1]], sX[l[2]]};
+        T B[4] = {s.B[0], s.B[1], s.B[2], s.B[3]}, at[4] = {s.at[0], s.at[1], s.at[2], s.at[3]};
+        T lbar[3], ab[4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lbar[c] = FIRST ? T(0) : mb[c * n + i];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ab[c] = FIRST ? T(0) : mb[(3 + c) * n + i];
+        if (tri_rev(P, st, i, n, B, at, lbar, ab)) { sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mb[c * n + i] = lbar[c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mb[(3 + c) * n + i] = ab[c];
+      }
+      break;
+    case 5:
+      if constexpr (HEAVY)
+      for (int i = tid; i < n; i += kB) {
+        const SBody<T> e = reinterpret_cast<const SBody<T>*>(r)[i];
+        const int tri = D.bpair[e.j];
+        T lbar = FIRST ? T(0) : mb[i];
+        if (tri >= 0) {
+          Vec4<T> P = sX[e.l];
+          if (body_rev(P, st[i], D.bx, D.btri[tri], D.bc_tau, D.bc_at, lbar, D.bgrad)) sX[e.l] = P;
+        }
+        mb[i] = lbar;
+      }
+      break;
+    default: {
+      Vec4<T>* sam = reinterpret_cast<Vec4<T>*>(m);
+      T* lbm = reinterpret_cast<T*>(sam + n);
+      for (int i = tid; i < n; i += kB) {
+        const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
+        Vec4<T> P = sX[l];
+        T lbar = FIRST ? T(0) : lbm[i];
+        Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : sam[i];
+        if (contact_rev(P, st[i], D.sph, lbar, sa)) sX[l] = P;
+        lbm[i] = lbar; sam[i] = sa;
+      }
+      break;
+    }
+  }
+}
+
+// After the last reverse iteration of a substep (the forward's first): the
+// FP64 parameter adjoints and the per-contact sphere adjoints leave the
+// reverse state of patch p (each thread reads the items it wrote itself).
+template <class T, bool HEAVY>
+__device__ __forceinline__ void group_rev_last(const Dev<T>& D, const GroupDev& G, int p, const int* cnt,
+                                               const int* sty, const unsigned char* mul) {
+  const int tid = threadIdx.x, kB = blockDim.x;
+  const int* first = G.rec_first + (size_t)p * G.nset;
+  const unsigned char* m = mul;
+  for (int q = 0; q < G.nset; ++q) {
+    const int n = cnt[q], ty = sty[q], jb = first[q];
+    const T* mb = reinterpret_cast<const T*>(m);
+    switch (ty) {
+      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
+      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
+      case 2:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+          D.t_acc[jb + i] += (double)mb[2 * n + i];
+          D.t_acc[D.tr.n + jb + i] += (double)mb[3 * n + i];
+          D.t_acc[2 * D.tr.n + jb + i] += (double)mb[4 * n + i];
+        }
+        break;
+      case 4:
+        if constexpr (HEAVY)
+        for (int i = tid; i < n; i += kB) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) D.m_acc[(size_t)c * D.mr.n + jb + i] += (double)mb[(3 + c) * n + i];
+        }
+        break;
+      case 5: break;   // body-vertex gradients were added during the reverse
+      default: {
+        const Vec4<T>* sam = reinterpret_cast<const Vec4<T>*>(m);
+        for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = sam[i];
+        break;
+      }
+    }
+    m += al32((size_t)n * rmul_words(ty) * sizeof(T));
+  }
 }
 
 // REPLAY (1, 2): the forward kept a snapshot of this launch's inputs (REC 2
@@ -1489,15 +1642,16 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
                                                       char* __restrict__ rmul, const char* __restrict__ tape_iter,
                                                       char* __restrict__ scratch) {
   extern __shared__ __align__(32) unsigned char smem[];
+  __shared__ int cnt[kMaxGroupSets], sty[kMaxGroupSets];
   const int p = blockIdx.x, tid = threadIdx.x, kB = blockDim.x;
   const int v0 = G.pv_start[p], nv = G.pv_start[p + 1] - v0;
-  const int* cnt = G.cnt + (size_t)p * G.nset;
+  stage_sets(G, p, cnt, sty);
   Vec4<T>* sX = reinterpret_cast<Vec4<T>*>(smem);
   size_t rbytes = 0, mbytes = 0, tbytes = 0;
   for (int q = 0; q < G.nset; ++q) {
-    rbytes += al32((size_t)cnt[q] * rec_bytes<T>(G.set_type[q]));
-    mbytes += al32((size_t)cnt[q] * rmul_words(G.set_type[q]) * sizeof(T));
-    tbytes += al32((size_t)cnt[q] * tape_words(G.set_type[q]) * sizeof(T));
+    rbytes += al32((size_t)cnt[q] * rec_bytes<T>(sty[q]));
+    mbytes += al32((size_t)cnt[q] * rmul_words(sty[q]) * sizeof(T));
+    tbytes += al32((size_t)cnt[q] * tape_words(sty[q]) * sizeof(T));
   }
   const char* gimg = img + G.img[p];
   char* gmul = rmul + G.rmul[p];
@@ -1528,106 +1682,18 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
                          (G.fmul[p] - G.fmul_lo);
     char* dst = RL ? reinterpret_cast<char*>(lrec + rbytes + mbytes)
                    : REPLAY == 2 ? reinterpret_cast<char*>(ltap) : scratch + G.tpos[p];
-    group_sets_fwd<T, LAST, true, HEAVY, false>(D, G, cnt, sP, rec, lsn, dst);
+    group_sets_fwd<T, LAST, true, HEAVY, false>(D, G, cnt, sty, sP, rec, lsn, dst);
   }
   // walk the sets backwards: start past the last region
   const unsigned char* r = rec + rbytes;
   unsigned char* m = mul + mbytes;
   const unsigned char* t = tap + tbytes;
   for (int q = G.nset - 1; q >= 0; --q) {
-    const int n = cnt[q], ty = G.set_type[q];
+    const int n = cnt[q], ty = sty[q];
     r -= al32((size_t)n * rec_bytes<T>(ty));
     m -= al32((size_t)n * rmul_words(ty) * sizeof(T));
     t -= al32((size_t)n * tape_words(ty) * sizeof(T));
-    const Vec4<T>* st = reinterpret_cast<const Vec4<T>*>(t);
-    T* mb = reinterpret_cast<T*>(m);
-    switch (ty) {
-      case 0:
-        for (int i = tid; i < n; i += kB) {
-          const SDist<T> s = reinterpret_cast<const SDist<T>*>(r)[i];
-          int la = lo16(s.l), lb = hi16(s.l);
-          Vec4<T> A = sX[la], Bv = sX[lb];
-          T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
-          if (dist_rev(A, Bv, st[i], s.rest, s.at, lbar, ab)) { sX[la] = A; sX[lb] = Bv; }
-          mb[i] = lbar; mb[n + i] = ab;
-        }
-        break;
-      case 1:
-        for (int i = tid; i < n; i += kB) {
-          const SBend<T> s = reinterpret_cast<const SBend<T>*>(r)[i];
-          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
-          Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
-          T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
-          if (bend_rev(P, st, i, n, s.th0, s.at, lbar, ab)) {
-            sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
-          }
-          mb[i] = lbar; mb[n + i] = ab;
-        }
-        break;
-      case 2:
-        if constexpr (HEAVY)
-        for (int i = tid; i < n; i += kB) {
-          const STet<T>& s = reinterpret_cast<const STet<T>*>(r)[i];
-          int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
-          Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
-          M3<T> B;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) B.m[k / 3][k % 3] = s.B[k];
-          T lbD = FIRST ? T(0) : mb[i], lbH = FIRST ? T(0) : mb[n + i];
-          T ebD = FIRST ? T(0) : mb[2 * n + i], ebH = FIRST ? T(0) : mb[3 * n + i];
-          T gb = FIRST ? T(0) : mb[4 * n + i];
-          if (tet_rev(P, st + i, n, B, s.atD, s.atH, s.gam, lbD, lbH, ebD, ebH, gb)) {
-            sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
-          }
-          mb[i] = lbD; mb[n + i] = lbH; mb[2 * n + i] = ebD; mb[3 * n + i] = ebH; mb[4 * n + i] = gb;
-        }
-        break;
-      case 4:
-        if constexpr (HEAVY)
-        for (int i = tid; i < n; i += kB) {
-          const STri<T>& s = reinterpret_cast<const STri<T>*>(r)[i];
-          int l[3] = {lo16(s.l01), hi16(s.l01), (int)s.l2};
-          Vec4<T> P[3] = {sX[l[0]], sX[l[1]], sX[l[2]]};
-          T B[4] = {s.B[0], s.B[1], s.B[2], s.B[3]}, at[4] = {s.at[0], s.at[1], s.at[2], s.at[3]};
-          T lbar[3], ab[4];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) lbar[c] = FIRST ? T(0) : mb[c * n + i];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) ab[c] = FIRST ? T(0) : mb[(3 + c) * n + i];
-          if (tri_rev(P, st, i, n, B, at, lbar, ab)) { sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; }
-#pragma unroll
-          for (int c = 0; c < 3; ++c) mb[c * n + i] = lbar[c];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) mb[(3 + c) * n + i] = ab[c];
-        }
-        break;
-      case 5:
-        if constexpr (HEAVY)
-        for (int i = tid; i < n; i += kB) {
-          const SBody<T> e = reinterpret_cast<const SBody<T>*>(r)[i];
-          const int tri = D.bpair[e.j];
-          T lbar = FIRST ? T(0) : mb[i];
-          if (tri >= 0) {
-            Vec4<T> P = sX[e.l];
-            if (body_rev(P, st[i], D.bx, D.btri[tri], D.bc_tau, D.bc_at, lbar, D.bgrad)) sX[e.l] = P;
-          }
-          mb[i] = lbar;
-        }
-        break;
-      default: {
-        Vec4<T>* sam = reinterpret_cast<Vec4<T>*>(m);
-        T* lbm = reinterpret_cast<T*>(sam + n);
-        for (int i = tid; i < n; i += kB) {
-          const int l = (int)reinterpret_cast<const SCon<T>*>(r)[i].l;
-          Vec4<T> P = sX[l];
-          T lbar = FIRST ? T(0) : lbm[i];
-          Vec4<T> sa = FIRST ? Vec4<T>{T(0), T(0), T(0), T(0)} : sam[i];
-          if (contact_rev(P, st[i], D.sph, lbar, sa)) sX[l] = P;
-          lbm[i] = lbar; sam[i] = sa;
-        }
-        break;
-      }
-    }
+    group_set_rev<T, FIRST, HEAVY>(D, ty, n, r, m, t, sX);
     lds_barrier();
   }
   for (int i = tid; i < nv; i += kB) D.XB[G.pv[v0 + i]] = sX[i];
@@ -1635,41 +1701,8 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
     if (RL) copy16(gmul, lrec + rbytes, mbytes);
     return;
   }
-  // last reverse iteration of the substep: FP64 parameter adjoints and the
-  // per-contact sphere adjoints leave the state (each thread reads the items
-  // it wrote itself)
-  const int* first = G.rec_first + (size_t)p * G.nset;
-  m = mul;
-  for (int q = 0; q < G.nset; ++q) {
-    const int n = cnt[q], ty = G.set_type[q], jb = first[q];
-    const T* mb = reinterpret_cast<const T*>(m);
-    switch (ty) {
-      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
-      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
-      case 2:
-        if constexpr (HEAVY)
-        for (int i = tid; i < n; i += kB) {
-          D.t_acc[jb + i] += (double)mb[2 * n + i];
-          D.t_acc[D.tr.n + jb + i] += (double)mb[3 * n + i];
-          D.t_acc[2 * D.tr.n + jb + i] += (double)mb[4 * n + i];
-        }
-        break;
-      case 4:
-        if constexpr (HEAVY)
-        for (int i = tid; i < n; i += kB) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) D.m_acc[(size_t)c * D.mr.n + jb + i] += (double)mb[(3 + c) * n + i];
-        }
-        break;
-      case 5: break;   // body-vertex gradients were added during the reverse
-      default: {
-        const Vec4<T>* sam = reinterpret_cast<const Vec4<T>*>(m);
-        for (int i = tid; i < n; i += kB) D.c_sacc[jb + i] = sam[i];
-        break;
-      }
-    }
-    m += al32((size_t)n * rmul_words(ty) * sizeof(T));
-  }
+  // last reverse iteration of the substep: the parameter adjoints leave the state
+  group_rev_last<T, HEAVY>(D, G, p, cnt, sty, mul);
 }
 
 // copy the per-call compliances (alpha / h^2, the tet constants, a membrane's
