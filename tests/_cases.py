@@ -39,6 +39,21 @@ def rounded_scene(sc):
     return r
 
 
+def split_sets(sc, total):
+    """Split the largest sets of sc's schedule in two until it has `total`
+    sets.  The items of a set share no vertex, so projecting a set's halves
+    one after the other computes exactly what projecting the set does: the
+    schedule is the same computation with more, smaller sets."""
+    st, si = list(sc.set_type), [np.asarray(x) for x in sc.set_items]
+    while len(st) < total:
+        k = max(range(len(si)), key=lambda j: len(si[j]))
+        h = len(si[k]) // 2
+        st.insert(k + 1, st[k])
+        si[k:k + 1] = [si[k][:h], si[k][h:]]
+    sc.set_type, sc.set_items = st, si
+    return sc
+
+
 def reference_case(sc, F, mask=None, seed=0, noise=0.01, f_ext=None, emulate_f32=False, n_threads=4,
                    round_inputs=False, targets=None):
     """Forward, targets, goal gradient and exact adjoint from the reference.

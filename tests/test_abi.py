@@ -96,6 +96,12 @@ def test_rejects_bad_indices_and_geometry():
     sc.tet_v[0, [2, 3]] = sc.tet_v[0, [3, 2]]      # inverted rest tet
     rc, _, msg = _create(sc)
     assert rc == L.XPBD_ERR_INVALID and "rest volume" in msg
+    lib = L.load()                                  # a mesh without vertices
+    o = L.Options()
+    o.dt, o.substeps, o.iterations = 1.0 / 60.0, 1, 1
+    rc = lib.xpbd_create(C.byref(L.MeshDesc(0, None, None)), C.byref(L.ConstraintDesc()), C.byref(L.ScheduleDesc()),
+                         C.byref(o), C.byref(C.c_void_p()))
+    assert rc == L.XPBD_ERR_INVALID and "empty mesh" in lib.xpbd_last_error(None).decode()
 
 
 def test_rejects_contact_on_pinned_vertex_and_bad_options():
@@ -151,6 +157,16 @@ def test_rejects_groups_whose_constraints_span_patches():
     sc.groups.append((0, 2, sc.groups[0][2]))          # overlaps group 0
     rc, _, msg = _create(sc)
     assert rc == L.XPBD_ERR_INVALID and "overlap" in msg
+
+
+def test_rejects_groups_of_more_than_64_sets():
+    """A group holds at most 64 consecutive sets (each group launch stages its
+    sets' item counts and types in fixed LDS arrays of that size)."""
+    from tests._cases import split_sets
+    sc = split_sets(scenes.small_cloth(n=12), 65)
+    sc.groups = [(0, 65, np.zeros(sc.n_verts, np.int32))]
+    rc, _, msg = _create(sc)
+    assert rc == L.XPBD_ERR_INVALID and "bad set range [0, 65)" in msg
 
 
 @pytest.mark.parametrize("maker", [lambda: scenes.tile_cloth(scenes.small_cloth(n=40), 40, 40, 16),

@@ -201,6 +201,31 @@ def test_lds_groups_match_per_set_launches_and_reference(dtype, kind):
     compare(sc, ref, a, *tol)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_group_of_64_sets_runs_in_one_launch(dtype):
+    """A group of the most sets a group may hold (64: the small cloth's
+    distance, bending and contact sets split into halves, and two empty sets)
+    over one patch with every vertex runs as one launch per iteration, with
+    entries staged in LDS and streamed, bitwise equal to one launch per set;
+    all match the FP64 reference."""
+    from tests._cases import split_sets
+    sc = split_sets(scenes.small_cloth(n=12, frames=2, substeps=2, iterations=3), 62)
+    for k, ty in ((10, scenes.DIST), (40, scenes.BEND)):
+        sc.set_type.insert(k, ty)
+        sc.set_items.insert(k, np.zeros(0, np.int32))
+    sc.groups = [(0, 64, np.zeros(sc.n_verts, np.int32))]
+    ref = reference_case(sc, 2, n_threads=8)
+    sims = [_sim(sc, dtype, use_groups=False), _sim(sc, dtype), _sim(sc, dtype, group_records=2)]
+    assert [s.info()["n_groups_lds"] for s in sims] == [0, 1, 1]
+    outs = [gpu_case(s, 2, ref) for s in sims]
+    for o in outs[1:]:
+        assert np.array_equal(o["x_frames"], outs[0]["x_frames"])
+        for k, v in outs[0]["grads"].items():
+            assert np.array_equal(o["grads"][k], v), k
+    tol = (1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-3)
+    compare(sc, ref, outs[1], *tol)
+
+
 def test_oversized_groups_fall_back_to_per_set_launches():
     sc = _tiled_cloth(n=130, tile=128, frames=1, S=1, K=2)
     sim = _sim(sc, "f64")
