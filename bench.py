@@ -161,6 +161,11 @@ WORKLOAD_LAUNCH = {"c4": {"group_records": 2, "group_block": 256}}
 # adjoint record per workload (1: snapshots of each LDS group launch, replayed
 # by the reverse; needs every set in an LDS group)
 WORKLOAD_RECORD = {}
+# adjoint record mode per workload when --tape-mode is not given: the 256x256
+# cloths follow their configuration's per-frame checkpoints (every frame's
+# record recomputed from its checkpoint, tape mode 1); the others take the
+# library's choice (the whole rollout if it fits, else the last frames)
+WORKLOAD_TAPE = {"c2": 1, "c2m": 1, "c2b": 1}
 HBM_PEAK_GBS = 8000.0
 
 # what the parity tests establish for each workload's results, by dtype
@@ -496,8 +501,9 @@ def main():
                     help="LDS groups: 1 entries and state staged in LDS, 2 streamed (0 = the library's choice)")
     ap.add_argument("--group-block", type=int, default=0, help="workgroup size of the group kernels (0 = 256)")
     ap.add_argument("--tape-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
-                    help="adjoint record mode (0 auto: whole rollout if it fits, else the last frames, "
-                         "else per frame; 1 recompute every frame from its checkpoint)")
+                    help="adjoint record mode (0: the workload's choice, else the library's: whole rollout if "
+                         "it fits, else the last frames, else per frame; 1 recompute every frame from its "
+                         "checkpoint)")
     ap.add_argument("--record-kind", type=int, default=-1, choices=[-1, 0, 1],
                     help="adjoint record: 0 every projection's inputs, 1 snapshots of each LDS group launch "
                          "replayed by the reverse (-1 = the workload's)")
@@ -565,7 +571,8 @@ def main():
     rk = args.record_kind if args.record_kind >= 0 else WORKLOAD_RECORD.get(args.workload, 0)
     sim = Simulator(sc, dtype=dtype, device=dev, launch_mode=lm, persistent_blocks=args.blocks,
                     use_groups=not args.no_groups, block_size=args.block, group_records=args.group_records,
-                    group_block=args.group_block, record_kind=rk, tape_mode=args.tape_mode)
+                    group_block=args.group_block, record_kind=rk,
+                    tape_mode=args.tape_mode or WORKLOAD_TAPE.get(args.workload, 0))
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     log(f"workload {args.workload}: {sc.n_verts} verts, {len(sc.set_type)} sets, {F} frames")
 
