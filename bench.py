@@ -319,7 +319,7 @@ def serve_bench(args):
         "packs_graphs": lambda: serve.PackedServer(slots=args.pack_slots, graphs=True, n_packs=args.packs),
     }
     rows = []
-    for frac in (0.5, 1.0, 1.5, 3.0, 1e9):
+    for frac in (0.25, 0.5, 0.75, 1.0, 1.5, 3.0, 1e9):
         for name, make in executors.items():
             rep = make().run(at_rate(frac * cap))
             rep["executor"] = name
