@@ -45,11 +45,12 @@ ALG_BYTES = {             # family: (index bytes, words of the state dtype)
 }
 
 
-# streamed bytes per projection of the survey's hot-path table (forward: a3,
-# reverse: a7), the per-unit figure the roofline is priced on: every
-# projection reads its record and reads and writes its vertices in HBM.
-# Types the a7 table leaves out fall back to ALG_BYTES.
-SURVEY_BYTES = {0: 80.0, 2: 144.0, 4: 98.0, 6: 40.0, 1: 116.0, 3: 204.0}
+# streamed bytes per projection, the per-unit figure the roofline is priced
+# on: every projection reads its constant data and multiplier (and, in the
+# reverse, its record) and reads and writes its vertices in HBM, with no
+# staging (forward: distance 80, bending 144, tet 98, contact 40; reverse:
+# distance 116, bending 204).  Other families fall back to ALG_BYTES.
+STREAMED_BYTES = {0: 80.0, 2: 144.0, 4: 98.0, 6: 40.0, 1: 116.0, 3: 204.0}
 
 
 # record words written per projection by a forward that keeps the adjoint's
@@ -135,12 +136,12 @@ def mix_bytes(sc, reverse: bool, tsz: int, recording: bool) -> float:
                for f, cnt in n.items()) / max(tot, 1)
 
 
-def survey_bytes(sc, fam: int, tsz: int) -> float:
-    """The survey's streamed bytes per projection for a kernel family; for a
+def streamed_bytes(sc, fam: int, tsz: int) -> float:
+    """Streamed bytes per projection for a kernel family; for a
     family that runs several constraint types (LDS groups, the persistent
     frame kernel) the average over the workload's mix."""
     def one(f):
-        return SURVEY_BYTES[f] * tsz / 4 if f in SURVEY_BYTES else alg_bytes(f, tsz)
+        return STREAMED_BYTES[f] * tsz / 4 if f in STREAMED_BYTES else alg_bytes(f, tsz)
     if fam in (8, 9, 10, 11):
         rev = fam in (9, 11)
         n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
@@ -710,15 +711,15 @@ def main():
     if tot > 0:
         dom = max(range(N_FAM), key=lambda f: ms[f])
         k = kernels[FAMILY[dom]]
-        sb = survey_bytes(sc, dom, tsz)
+        sb = streamed_bytes(sc, dom, tsz)
         achieved = sb * k["items_per_launch"] / (k["avg_us"] * 1e-6) / 1e9
         roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "bytes_per_projection": round(sb, 1),
-                "byte_model": "the survey's streamed bytes per projection (each projection reads and writes "
-                              "its vertices in HBM); LDS group kernels stage a patch's vertices once per launch "
+                "byte_model": "streamed bytes per projection (each projection reads and writes its "
+                              "vertices in HBM); LDS group kernels stage a patch's vertices once per launch "
                               "and move fewer bytes, so this model can exceed the HBM peak: 'counter' holds the "
                               "measured HBM traffic",
                 "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"],
