@@ -33,8 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic bytes per projection of each kernel family in FP32 (index =
-# 2 * type forward, 2 * type + 1 reverse), from the record and vertex traffic
-# each one must move: see the kernel table of the design notes.
+# 2 * type forward, 2 * type + 1 reverse) when one launch runs one set: the
+# vertex indices, the constant data, the multiplier and the vertices each
+# projection must read and write (and the record, added separately).
 ALG_BYTES = {             # family: (index bytes, words of the state dtype)
     0: (8, 20), 1: (8, 26),     # distance fwd: idx 8 + L, at, lambda r/w + 2 vertices r/w
     2: (16, 36), 3: (16, 48),   # bending
