@@ -184,3 +184,63 @@ def test_cloth2048x4096_benchmark_adjoint_structure():
         intrinsic = rel(r, plain["grads"][k])
         assert errs[k] <= max(1e-3, intrinsic), (k, errs[k], intrinsic)
         assert rel(a["grads"][k], plain["grads"][k]) <= max(1e-3, 2 * intrinsic), k
+
+
+def test_cloth2048x4096_fp64_gradients_match_central_differences():
+    """The full 25.2M-DoF cloth in FP64 with the benchmark's schedule and
+    launch shape (32 x 32 tiles, three LDS groups, entries and state
+    streamed) and adjoint structure (the forward keeps the record of its
+    last two frames, the first frame is recomputed on the second stream),
+    three frames of 2 substeps x 2 iterations, goal on every frame against a
+    rollout under
+    another force field: along seeded directions for the forces, the distance
+    compliances and v0, the directional derivative from the adjoint matches
+    central differences of the GPU's own rollout to 1e-6 relative.  No
+    reference in the loop, so the whole mesh runs.  The loss (about 330)
+    carries rounding of about 1e-13 of its value, so each step is chosen to
+    move it by 2e-6 of that value, capped per parameter: the stiff distance
+    constraints make the loss so insensitive to their compliances that their
+    step reaches 10% of each compliance, where the loss is linear in them to
+    about 2e-7 (measured with steps from 1e-4 to 1e-1: the central difference
+    converges to the adjoint's value as the step grows, the rounding floor
+    falling as 1/step)."""
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    needs_gpu()
+    F = 3
+    sc = scenes.config_c4(n_frames=F)
+    sc.substeps, sc.iterations = 2, 2
+    sim = Simulator(sc, dtype=torch.float64, group_records=2, group_block=256, tape_mode=4, record_frames=2)
+    info = sim.info()
+    assert info["n_groups_lds"] == 3
+    mask = np.ones(F, np.uint8)
+    f = np.asarray(sc.f_ext, np.float64)
+    tg, _, _ = sim.forward(F, f_ext=sim.tensor(scenes.force_field(5, 4096, 2048, F)))
+    tg = tg.clone()
+    free = (sc.inv_mass > 0)[:, None].astype(np.float64)
+    base = {"f_ext": f, "dist_alpha": np.asarray(sc.dist_alpha, np.float64), "v0": np.zeros((sc.n_verts, 3))}
+
+    def run(vals, adjoint):
+        xf, _, _ = sim.forward(F, for_adjoint=adjoint, **{k: sim.tensor(v) for k, v in vals.items()})
+        loss, dL = sim.goal_l2(xf, tg, mask)
+        g = sim.adjoint(dL, mask) if adjoint else None
+        torch.cuda.synchronize()
+        return float(loss.cpu()), g
+
+    L0, g = run(base, True)
+    info = sim.info()
+    assert info["tape_mode"] == 4 and info["forward_record_frames"] == 2 and info["adjoint_streams"] == 2
+    rng = np.random.default_rng(21)
+    dirs = {"f_ext": scenes.force_field(21, 4096, 2048, F, amplitude=1.0) * free[None],
+            "dist_alpha": base["dist_alpha"] * rng.standard_normal(sc.n_dist),
+            "v0": 0.1 * rng.standard_normal((sc.n_verts, 3)) * free}
+    cap = {"f_ext": 2e-3, "dist_alpha": 0.1, "v0": 1e-4}
+    for k, d in dirs.items():
+        an = float(np.sum(g[k].double().cpu().numpy() * d))
+        eps = min(1e-6 * abs(L0) / max(abs(an), 1e-300), cap[k])
+        fd = (run(dict(base, **{k: base[k] + eps * d}), False)[0] -
+              run(dict(base, **{k: base[k] - eps * d}), False)[0]) / (2 * eps)
+        print(f"cloth2048x4096 FP64 {k}: adjoint {an:.12e} central difference {fd:.12e} step {eps:.3e} "
+              f"relative {abs(fd - an) / max(abs(an), abs(fd)):.2e}", flush=True)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), abs(fd)), (k, fd, an, eps)
+
