@@ -21,6 +21,8 @@ template <class T> struct ImpOps {
     double* part; // [nblocks(V)]
     double* sum;  // [1]
     int* bad;     // [1]
+    double* cg;   // [CG_NSLOT] scalars of the CG loop
+    int* cgs;     // [2] CG state and iterations taken
     double* nb[4];  // projected blocks per constraint type (PD projection only)
   };
 
@@ -36,7 +38,7 @@ template <class T> struct ImpOps {
   static Work work(xpbd_ctx c, bool pd) {
     const size_t V = (size_t)c->V, nb = nblocks(V);
     size_t need = align256((size_t)c->S * V * sizeof(V4)) + 6 * align256(V * sizeof(D4)) +
-                  align256(nb * sizeof(double)) + 256 + 256;
+                  align256(nb * sizeof(double)) + 4 * 256;
     if (pd)
       for (int ty = 0; ty < 4; ++ty) need += align256(block_doubles(c, ty) * sizeof(double));
     if (c->imp_cap < need) {
@@ -58,6 +60,8 @@ template <class T> struct ImpOps {
     w.part = (double*)take(nb * sizeof(double));
     w.sum = (double*)take(sizeof(double));
     w.bad = (int*)take(sizeof(int));
+    w.cg = (double*)take(CG_NSLOT * sizeof(double));
+    w.cgs = (int*)take(2 * sizeof(int));
     for (int ty = 0; ty < 4; ++ty) w.nb[ty] = pd && block_doubles(c, ty) ? (double*)take(block_doubles(c, ty) * sizeof(double)) : nullptr;
     return w;
   }
@@ -99,6 +103,15 @@ template <class T> struct ImpOps {
     Ops<T>::check_launch();
     if (pd) sets<IMP_APPLY_PD>(c, D, XE, P, Q, 0.0, bad, w, st);
     else sets<IMP_APPLY>(c, D, XE, P, Q, 0.0, bad, w, st);
+  }
+
+  // a . b (see k_imp_dot) into the device scalar *out, without the host
+  static void dot_dev(xpbd_ctx c, const Work& w, const D4* a, const D4* b, const D4* diag, double* out,
+                      hipStream_t st) {
+    const unsigned nb = nblocks(c->V);
+    k_imp_dot<<<nb, kBlock, 0, st>>>(a, b, diag, c->V, w.part);
+    k_sum_parts<<<1, 1024, 0, st>>>(w.part, nb, out, 0);
+    Ops<T>::check_launch();
   }
 
   static double dot(xpbd_ctx c, const Work& w, const D4* a, const D4* b, const D4* diag, hipStream_t st) {
@@ -165,24 +178,37 @@ template <class T> struct ImpOps {
         int it = 0;
         double rel = 0.0;
         if (bn > 0.0) {
+          // preconditioned CG with its scalars on the device: batches of
+          // iterations (8, doubling to 32) between the host's looks at the
+          // state, the iterations after a stop leaving the solution as it is
           k_imp_dir<<<nblocks(V), kBlock, 0, st>>>(0.0, w.R, w.DG, w.P, V, 1);
-          double rz = dot(c, w, w.R, w.R, w.DG, st);
-          rel = 1.0;
-          while (it < cg->max_iterations) {
-            apply(c, D, XE, w.P, w.Q, w.bad, w, pd, st);
-            const double pq = dot(c, w, w.P, w.Q, nullptr, st);
-            if (!(pq > 0.0))
+          dot_dev(c, w, w.R, w.R, w.DG, w.cg + CG_RZ, st);
+          k_cg_start<<<1, 1, 0, st>>>(w.cg, w.cgs);
+          Ops<T>::check_launch();
+          int state[2] = {CG_RUN, 0};
+          for (int batch = 8; state[0] == CG_RUN; batch = std::min(2 * batch, 32)) {
+            for (int b = 0; b < batch; ++b) {
+              apply(c, D, XE, w.P, w.Q, w.bad, w, pd, st);
+              dot_dev(c, w, w.P, w.Q, nullptr, w.cg + CG_PQ, st);
+              k_cg_alpha<<<1, 1, 0, st>>>(w.cg, w.cgs);
+              k_cg_axpy2<<<nblocks(V), kBlock, 0, st>>>(w.cg, w.cgs, w.P, w.Q, w.DG, w.Y, w.R, V);
+              dot_dev(c, w, w.R, nullptr, nullptr, w.cg + CG_RR, st);
+              k_cg_check<<<1, 1, 0, st>>>(w.cg, w.cgs, bn, cg->rel_tolerance, cg->max_iterations);
+              dot_dev(c, w, w.R, w.R, w.DG, w.cg + CG_RZ2, st);
+              k_cg_beta<<<1, 1, 0, st>>>(w.cg, w.cgs);
+              k_cg_dir<<<nblocks(V), kBlock, 0, st>>>(w.cg, w.cgs, w.R, w.DG, w.P, V);
+              Ops<T>::check_launch();
+            }
+            double sc[CG_NSLOT];
+            HIPCHK(hipMemcpyAsync(state, w.cgs, sizeof(state), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(sc, w.cg, sizeof(sc), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            it = state[1];
+            rel = sc[CG_REL];
+            if (state[0] == CG_INDEFINITE)
               fail(XPBD_ERR_SOLVER,
                    "implicit adjoint: the system of frame %d, substep %d is not positive definite (p.Ap = %g)", f, s,
-                   pq);
-            const double alpha = rz / pq;
-            k_imp_axpy2<<<nblocks(V), kBlock, 0, st>>>(alpha, w.P, w.Q, w.DG, w.Y, w.R, V);
-            ++it;
-            rel = std::sqrt(dot(c, w, w.R, nullptr, nullptr, st)) / bn;
-            if (rel <= cg->rel_tolerance) break;
-            const double rz2 = dot(c, w, w.R, w.R, w.DG, st);
-            k_imp_dir<<<nblocks(V), kBlock, 0, st>>>(rz2 / rz, w.R, w.DG, w.P, V, 0);
-            rz = rz2;
+                   sc[CG_PQ]);
           }
         }
         total += it;

@@ -329,12 +329,70 @@ __global__ __launch_bounds__(kBlock) void k_imp_diag(const Vec4<T>* __restrict__
   DG[k] = w > 0.0 ? D4{d.x + 1.0 / w, d.y + 1.0 / w, d.z + 1.0 / w, 0.0} : D4{0.0, 0.0, 0.0, 0.0};
 }
 
-// y += alpha p; r -= alpha q on free vertices
-__global__ __launch_bounds__(kBlock) void k_imp_axpy2(double alpha, const D4* __restrict__ P, const D4* __restrict__ Q,
-                                                      const D4* __restrict__ DG, D4* __restrict__ Y,
-                                                      D4* __restrict__ R, int n) {
+// p = r / diag + beta p (free vertices; pinned stay 0)
+__global__ __launch_bounds__(kBlock) void k_imp_dir(double beta, const D4* __restrict__ R, const D4* __restrict__ DG,
+                                                    D4* __restrict__ P, int n, int first) {
   int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n || !(DG[k].x > 0.0)) return;
+  if (k >= n) return;
+  D4 r = R[k], dg = DG[k], p = first ? D4{0.0, 0.0, 0.0, 0.0} : P[k];
+  D4 z = {dg.x > 0.0 ? r.x / dg.x : 0.0, dg.y > 0.0 ? r.y / dg.y : 0.0, dg.z > 0.0 ? r.z / dg.z : 0.0, 0.0};
+  P[k] = D4{z.x + beta * p.x, z.y + beta * p.y, z.z + beta * p.z, 0.0};
+}
+
+// The CG loop keeps its scalars on the device, so a batch of iterations runs
+// without the host: slot CG_RZ r.z, CG_PQ p.q, CG_RR r.r, CG_RZ2 the next
+// r.z, CG_ALPHA, CG_BETA, CG_REL the relative residual |r| / |b|; state[0]
+// is CG_RUN until the solve stops (converged, p.Ap <= 0, or the iteration
+// limit), after which every step kernel leaves y, r and p as they are;
+// state[1] counts the iterations taken.  Each scalar is the same FP64
+// expression the host loop would evaluate, in the same order.
+enum CgSlot { CG_RZ = 0, CG_PQ, CG_RR, CG_RZ2, CG_ALPHA, CG_BETA, CG_REL, CG_NSLOT };
+enum CgState { CG_RUN = 0, CG_CONVERGED = 1, CG_INDEFINITE = 2, CG_LIMIT = 3 };
+
+__global__ void k_cg_start(double* __restrict__ cg, int* __restrict__ state) {
+  state[0] = CG_RUN;
+  state[1] = 0;
+  cg[CG_REL] = 1.0;
+}
+
+// alpha = r.z / p.q, or stop when the system is not positive definite
+__global__ void k_cg_alpha(double* __restrict__ cg, int* __restrict__ state) {
+  if (state[0] != CG_RUN) return;
+  const double pq = cg[CG_PQ];
+  if (!(pq > 0.0)) {
+    state[0] = CG_INDEFINITE;
+    return;
+  }
+  cg[CG_ALPHA] = cg[CG_RZ] / pq;
+}
+
+// one iteration done: stop when |r| / |b| <= tol or at the iteration limit
+__global__ void k_cg_check(double* __restrict__ cg, int* __restrict__ state, double bn, double tol, int max_it) {
+  if (state[0] != CG_RUN) return;
+  state[1] += 1;
+  const double rel = sqrt(cg[CG_RR]) / bn;
+  cg[CG_REL] = rel;
+  if (rel <= tol) state[0] = CG_CONVERGED;
+  else if (state[1] >= max_it) state[0] = CG_LIMIT;
+}
+
+// beta = (next r.z) / r.z, and the next r.z becomes r.z
+__global__ void k_cg_beta(double* __restrict__ cg, const int* __restrict__ state) {
+  if (state[0] != CG_RUN) return;
+  cg[CG_BETA] = cg[CG_RZ2] / cg[CG_RZ];
+  cg[CG_RZ] = cg[CG_RZ2];
+}
+
+// y += alpha p, r -= alpha q (free vertices) and p = r / diag + beta p, with
+// alpha and beta read from the device, doing nothing once the solve has
+// stopped
+__global__ __launch_bounds__(kBlock) void k_cg_axpy2(const double* __restrict__ cg, const int* __restrict__ state,
+                                                     const D4* __restrict__ P, const D4* __restrict__ Q,
+                                                     const D4* __restrict__ DG, D4* __restrict__ Y,
+                                                     D4* __restrict__ R, int n) {
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  if (state[0] != CG_RUN || k >= n || !(DG[k].x > 0.0)) return;
+  const double alpha = cg[CG_ALPHA];
   D4 p = P[k], q = Q[k], y = Y[k], r = R[k];
   y.x += alpha * p.x; y.y += alpha * p.y; y.z += alpha * p.z;
   r.x -= alpha * q.x; r.y -= alpha * q.y; r.z -= alpha * q.z;
@@ -342,12 +400,13 @@ __global__ __launch_bounds__(kBlock) void k_imp_axpy2(double alpha, const D4* __
   R[k] = r;
 }
 
-// p = r / diag + beta p (free vertices; pinned stay 0)
-__global__ __launch_bounds__(kBlock) void k_imp_dir(double beta, const D4* __restrict__ R, const D4* __restrict__ DG,
-                                                    D4* __restrict__ P, int n, int first) {
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const double* __restrict__ cg, const int* __restrict__ state,
+                                                   const D4* __restrict__ R, const D4* __restrict__ DG,
+                                                   D4* __restrict__ P, int n) {
   int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  D4 r = R[k], dg = DG[k], p = first ? D4{0.0, 0.0, 0.0, 0.0} : P[k];
+  if (state[0] != CG_RUN || k >= n) return;
+  const double beta = cg[CG_BETA];
+  D4 r = R[k], dg = DG[k], p = P[k];
   D4 z = {dg.x > 0.0 ? r.x / dg.x : 0.0, dg.y > 0.0 ? r.y / dg.y : 0.0, dg.z > 0.0 ? r.z / dg.z : 0.0, 0.0};
   P[k] = D4{z.x + beta * p.x, z.y + beta * p.y, z.z + beta * p.z, 0.0};
 }
