@@ -129,6 +129,7 @@ struct xpbd_ctx_s {
   int block = kBlock;   // workgroup size of the per-set kernels
   bool group_stream = false;   // LDS groups: records streamed from the global image
   int record_kind = 0;         // 0 record of every projection's inputs, 1 snapshots of each group launch
+  bool want_ab = true;         // this adjoint asks for distance or bending compliance gradients
   char* scratch = nullptr;     // record_kind 1, entries streamed: one group launch's replayed record
   size_t scratch_bytes = 0;
   int group_block = kBlock;    // workgroup size of the LDS group kernels
@@ -563,6 +564,10 @@ template <class T> struct Ops {
     const size_t sm = rl ? g.smem_rev + (rp ? g.smem_tile : 0)
                          : g.smem_tile + (rp ? g.smem_tile : 0) + (rp == 2 ? g.max_tbytes : 0);
     char* scr = c->scratch;
+    // no distance / bending compliance gradient asked for: the variant
+    // without those adjoints (distance, bending and contact groups, records
+    // of projection inputs)
+    const bool no_ab = !c->want_ab && !g.heavy && rp == 0;
 #define XPBD_GR(F1, F2, RP)                                                                         \
   do {                                                                                              \
     if (rl && g.heavy) k_group_rev<T, F1, F2, true, true, RP><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr);   \
@@ -572,7 +577,9 @@ template <class T> struct Ops {
   } while (0)
 #define XPBD_GR3(F1, F2)                                  \
   do {                                                    \
-    if (rp == 2) XPBD_GR(F1, F2, 2);                      \
+    if (no_ab && rl) k_group_rev<T, F1, F2, true, false, 0, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr); \
+    else if (no_ab) k_group_rev<T, F1, F2, false, false, 0, false><<<grid, bs, sm, st>>>(D, G, c->gimg, c->grmul, tape_iter, scr); \
+    else if (rp == 2) XPBD_GR(F1, F2, 2);                 \
     else if (rp == 1) XPBD_GR(F1, F2, 1);                 \
     else XPBD_GR(F1, F2, 0);                              \
   } while (0)
@@ -622,7 +629,11 @@ template <class T> struct Ops {
         XPBD_FWD_K(true, true), XPBD_FWD_K(false, true), XPBD_FWD_K(true, false), XPBD_FWD_K(false, false),
         XPBD_REV_K(true, true, true), XPBD_REV_K(true, false, true), XPBD_REV_K(false, true, true),
         XPBD_REV_K(false, false, true), XPBD_REV_K(true, true, false), XPBD_REV_K(true, false, false),
-        XPBD_REV_K(false, true, false), XPBD_REV_K(false, false, false)};
+        XPBD_REV_K(false, true, false), XPBD_REV_K(false, false, false),
+        (const void*)k_group_rev<T, true, true, true, false, 0, false>,
+        (const void*)k_group_rev<T, true, false, true, false, 0, false>,
+        (const void*)k_group_rev<T, false, true, true, false, 0, false>,
+        (const void*)k_group_rev<T, false, false, true, false, 0, false>};
 #undef XPBD_FWD_K
 #undef XPBD_REV_K
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
@@ -2003,6 +2014,9 @@ xpbd_status xpbd_adjoint(xpbd_ctx c, const xpbd_params* p, const void* dLdx_fram
       fail(XPBD_ERR_STATE, "adjoint: parameters differ from the preceding forward");
     const int F = c->fwd_frames;
     const int rec_from = c->fwd_recorded ? c->fwd_rec_from : F;
+    // the LDS group reverse accumulates the distance and bending compliance
+    // adjoints only for a call that asks for one of those gradients
+    c->want_ab = out->dist_compliance != nullptr || out->bend_compliance != nullptr;
     // frames without a kept record: recomputed per frame if a frame's record
     // fits (the kept frames' slots are reused once consumed), else per substep
     int mode = c->tape_mode_opt == 1 || c->tape_mode_opt == 2 ? c->tape_mode_opt : 1;

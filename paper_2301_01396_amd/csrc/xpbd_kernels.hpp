@@ -1492,8 +1492,10 @@ __global__ __launch_bounds__(kBlock) void k_group_fwd(Dev<T> D, GroupDev G, cons
 // reverse item order does not matter: the items of a set share no vertex):
 // constant entries from r, the reverse state read and written in place at m,
 // the record of the forward's inputs from t, the vertex adjoints in the LDS
-// tile sX.
-template <class T, bool FIRST, bool HEAVY>
+// tile sX.  AB: the distance and bending compliance adjoints are
+// accumulated (their words of the reverse state read and written); without
+// it they are neither read, written nor computed.
+template <class T, bool FIRST, bool HEAVY, bool AB>
 __device__ __forceinline__ void group_set_rev(const Dev<T>& D, int ty, int n, const unsigned char* r,
                                               unsigned char* m, const unsigned char* t, Vec4<T>* sX) {
   const int tid = threadIdx.x, kB = blockDim.x;
@@ -1505,9 +1507,10 @@ __device__ __forceinline__ void group_set_rev(const Dev<T>& D, int ty, int n, co
         const SDist<T> s = reinterpret_cast<const SDist<T>*>(r)[i];
         int la = lo16(s.l), lb = hi16(s.l);
         Vec4<T> A = sX[la], Bv = sX[lb];
-        T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
+        T lbar = FIRST ? T(0) : mb[i], ab = FIRST || !AB ? T(0) : mb[n + i];
         if (dist_rev(A, Bv, st[i], s.rest, s.at, lbar, ab)) { sX[la] = A; sX[lb] = Bv; }
-        mb[i] = lbar; mb[n + i] = ab;
+        mb[i] = lbar;
+        if (AB) mb[n + i] = ab;
       }
       break;
     case 1:
@@ -1515,11 +1518,12 @@ __device__ __forceinline__ void group_set_rev(const Dev<T>& D, int ty, int n, co
         const SBend<T> s = reinterpret_cast<const SBend<T>*>(r)[i];
         int l[4] = {lo16(s.l01), hi16(s.l01), lo16(s.l23), hi16(s.l23)};
         Vec4<T> P[4] = {sX[l[0]], sX[l[1]], sX[l[2]], sX[l[3]]};
-        T lbar = FIRST ? T(0) : mb[i], ab = FIRST ? T(0) : mb[n + i];
+        T lbar = FIRST ? T(0) : mb[i], ab = FIRST || !AB ? T(0) : mb[n + i];
         if (bend_rev(P, st, i, n, s.th0, s.at, lbar, ab)) {
           sX[l[0]] = P[0]; sX[l[1]] = P[1]; sX[l[2]] = P[2]; sX[l[3]] = P[3];
         }
-        mb[i] = lbar; mb[n + i] = ab;
+        mb[i] = lbar;
+        if (AB) mb[n + i] = ab;
       }
       break;
     case 2:
@@ -1591,7 +1595,7 @@ __device__ __forceinline__ void group_set_rev(const Dev<T>& D, int ty, int n, co
 // After the last reverse iteration of a substep (the forward's first): the
 // FP64 parameter adjoints and the per-contact sphere adjoints leave the
 // reverse state of patch p (each thread reads the items it wrote itself).
-template <class T, bool HEAVY>
+template <class T, bool HEAVY, bool AB>
 __device__ __forceinline__ void group_rev_last(const Dev<T>& D, const GroupDev& G, int p, const int* cnt,
                                                const int* sty, const unsigned char* mul) {
   const int tid = threadIdx.x, kB = blockDim.x;
@@ -1601,8 +1605,8 @@ __device__ __forceinline__ void group_rev_last(const Dev<T>& D, const GroupDev& 
     const int n = cnt[q], ty = sty[q], jb = first[q];
     const T* mb = reinterpret_cast<const T*>(m);
     switch (ty) {
-      case 0: for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
-      case 1: for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
+      case 0: if constexpr (AB) for (int i = tid; i < n; i += kB) D.d_acc[jb + i] += (double)mb[n + i]; break;
+      case 1: if constexpr (AB) for (int i = tid; i < n; i += kB) D.b_acc[jb + i] += (double)mb[n + i]; break;
       case 2:
         if constexpr (HEAVY)
         for (int i = tid; i < n; i += kB) {
@@ -1636,8 +1640,10 @@ __device__ __forceinline__ void group_rev_last(const Dev<T>& D, const GroupDev& 
 // the forward's arithmetic exactly) and write the record into LDS (with the
 // entries staged, RL, or after the two tiles, REPLAY 2) or into this
 // launch's scratch (REPLAY 1, at scratch + G.tpos[p]), where each thread
-// reads back only the items it wrote.
-template <class T, bool FIRST, bool LAST, bool RL, bool HEAVY, int REPLAY>
+// reads back only the items it wrote.  AB false: the call asked for no
+// distance or bending compliance gradient, so those adjoints are left out
+// (fewer registers: a fifth wave per SIMD for the distance / bending groups).
+template <class T, bool FIRST, bool LAST, bool RL, bool HEAVY, int REPLAY, bool AB = true>
 __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, const char* __restrict__ img,
                                                       char* __restrict__ rmul, const char* __restrict__ tape_iter,
                                                       char* __restrict__ scratch) {
@@ -1693,7 +1699,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
     r -= al32((size_t)n * rec_bytes<T>(ty));
     m -= al32((size_t)n * rmul_words(ty) * sizeof(T));
     t -= al32((size_t)n * tape_words(ty) * sizeof(T));
-    group_set_rev<T, FIRST, HEAVY>(D, ty, n, r, m, t, sX);
+    group_set_rev<T, FIRST, HEAVY, AB>(D, ty, n, r, m, t, sX);
     lds_barrier();
   }
   for (int i = tid; i < nv; i += kB) D.XB[G.pv[v0 + i]] = sX[i];
@@ -1702,7 +1708,7 @@ __global__ __launch_bounds__(kBlock) void k_group_rev(Dev<T> D, GroupDev G, cons
     return;
   }
   // last reverse iteration of the substep: the parameter adjoints leave the state
-  group_rev_last<T, HEAVY>(D, G, p, cnt, sty, mul);
+  group_rev_last<T, HEAVY, AB>(D, G, p, cnt, sty, mul);
 }
 
 // copy the per-call compliances (alpha / h^2, the tet constants, a membrane's

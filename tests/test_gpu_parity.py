@@ -226,6 +226,40 @@ def test_group_of_64_sets_runs_in_one_launch(dtype):
     compare(sc, ref, outs[1], *tol)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_adjoint_without_compliance_gradients_gives_the_same_other_gradients(dtype):
+    """An adjoint that asks for no distance or bending compliance gradient
+    leaves those constraints' compliance adjoints out of the LDS group
+    reverse; every other gradient is bitwise that of an adjoint asking for
+    everything (entries staged in LDS and streamed; the whole rollout's
+    record, and per-frame recomputation beside the reverse), and the next
+    adjoint asking for everything returns the same compliance gradients."""
+    sc = _tiled_cloth(n=37, tile=8, lines=True)
+    assert sc.contact
+    F = 2
+    rng = np.random.default_rng(3)
+    tg_np = sc.rest[None].repeat(F, 0) + 0.01 * rng.standard_normal((F, sc.n_verts, 3))
+    mask = np.ones(F, np.uint8)
+    part_want = ("x0", "v0", "f_ext", "sphere")
+    for kw in ({}, {"group_records": 2}, {"group_records": 2, "tape_mode": 1}):
+        sim = _sim(sc, dtype, **kw)
+        assert sim.info()["n_groups_lds"] == len(sc.groups)
+        tg = sim.tensor(tg_np)
+        outs = []
+        for want in (None, part_want, None):
+            xf, _, _ = sim.forward(F, for_adjoint=True)
+            _, dL = sim.goal_l2(xf, tg, mask)
+            outs.append({k: v.cpu().numpy().copy() for k, v in sim.adjoint(dL, mask, want=want).items()})
+        full, part, again = outs
+        assert set(part) == set(part_want) and {"dist_alpha", "bend_alpha"} <= set(full), kw
+        for k, v in part.items():
+            assert np.array_equal(v, full[k]), (kw, k)
+        for k, v in again.items():
+            assert np.array_equal(v, full[k]), (kw, k)
+        assert np.linalg.norm(full["dist_alpha"]) > 0 and np.linalg.norm(full["bend_alpha"]) > 0
+        sim.close()
+
+
 def test_oversized_groups_fall_back_to_per_set_launches():
     sc = _tiled_cloth(n=130, tile=128, frames=1, S=1, K=2)
     sim = _sim(sc, "f64")
