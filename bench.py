@@ -102,7 +102,7 @@ def group_vertices(sc) -> int:
 
 
 def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: int,
-                snapshots: bool = False) -> float:
+                snapshots: bool = False, compliance_adjoints: bool = True) -> float:
     """Average algorithmic bytes per projection of the LDS group launches of
     one iteration: constant entries read, state read and written, record of
     inputs (written by the forward launches that record, read by the
@@ -111,7 +111,9 @@ def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: 
     positions (3 words per vertex) and its multipliers (1 word per
     projection, 2 per tet item); the record the reverse replays from them
     stays within the launch (written and read back by each workgroup) and
-    is not counted."""
+    is not counted.  Without ``compliance_adjoints`` (no distance or bending
+    compliance gradient asked for) the reverse leaves those constraints'
+    compliance adjoints (a word read and written) out."""
     n = {0: sc.n_dist, 2: sc.n_bend, 4: 2 * sc.n_tet,
          6: int(np.count_nonzero(sc.inv_mass > 0)) if sc.contact else 0}
     tot = max(sum(n.values()), 1)
@@ -119,6 +121,8 @@ def group_bytes(sc, reverse: bool, tsz: int, recording: float, staged_vertices: 
     b = 0.0
     for f, cnt in n.items():
         words = GROUP_REC_WORDS[f][1 if reverse else 0]
+        if reverse and not compliance_adjoints and f in (0, 2):
+            words -= 2
         words += (1 if snapshots else TAPE_WORDS[f]) * share
         b += cnt * words * tsz
     b += staged_vertices * 2 * 4 * tsz
@@ -682,13 +686,16 @@ def main():
     kernels = {}
     tsz = 8 if dtype == torch.float64 else 4
     staged = group_vertices(sc) if info["n_groups_lds"] else 0
+    # the reverse moves the distance / bending compliance adjoints only when
+    # their gradient is asked for (the 25.2M-DoF cloth asks for dL/df_ext)
+    want_ab = any(t is not None and t.requires_grad for t in (da, ba))
     def fam_bytes(fam):
         if fam == 8:
             return mix_bytes(sc, False, tsz, recording)
         if fam == 9:
             return mix_bytes(sc, True, tsz, recording)
         if fam in (10, 11):
-            return group_bytes(sc, fam == 11, tsz, recording, staged, rk == 1)
+            return group_bytes(sc, fam == 11, tsz, recording, staged, rk == 1, want_ab)
         return alg_bytes(fam, tsz, recording)
 
     for fam in range(N_FAM):
@@ -709,28 +716,27 @@ def main():
     tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if os.path.exists(tf):
         pmc = {key: rec for key, rec in json.load(open(tf)).items() if rec.get("csrc_sha") == csrc_hash()}
-    if tot > 0:
-        dom = max(range(N_FAM), key=lambda f: ms[f])
-        k = kernels[FAMILY[dom]]
-        sb = streamed_bytes(sc, dom, tsz)
+    def kernel_roof(fam):
+        k = kernels[FAMILY[fam]]
+        sb = streamed_bytes(sc, fam, tsz)
         achieved = sb * k["items_per_launch"] / (k["avg_us"] * 1e-6) / 1e9
-        roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "bytes_per_projection": round(sb, 1),
-                "byte_model": "streamed bytes per projection (each projection reads and writes its "
-                              "vertices in HBM); LDS group kernels stage a patch's vertices once per launch "
-                              "and move fewer bytes, so this model can exceed the HBM peak: 'counter' holds the "
-                              "measured HBM traffic",
-                "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"],
-                "staged_model": {"bytes_per_projection": k["bytes_per_projection"], "GBps": k["alg_GBps"]}}
-        rec = pmc.get(f"{args.workload}:{KERNEL_SYMBOL[dom]}")
+        r = {"bound": "hbm", "kernel": KERNEL_SYMBOL[fam], "achieved": round(achieved, 1),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+             "traffic": None,
+             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+             "bytes_per_projection": round(sb, 1),
+             "byte_model": "streamed bytes per projection (each projection reads and writes its "
+                           "vertices in HBM); LDS group kernels stage a patch's vertices once per launch "
+                           "and move fewer bytes, so this model can exceed the HBM peak: 'counter' holds the "
+                           "measured HBM traffic",
+             "avg_launch_us": k["avg_us"], "projections_per_launch": k["items_per_launch"],
+             "staged_model": {"bytes_per_projection": k["bytes_per_projection"], "GBps": k["alg_GBps"]}}
+        rec = pmc.get(f"{args.workload}:{KERNEL_SYMBOL[fam]}")
         if rec:
             traffic = rec["bytes_per_dispatch_scaled"] * k["items_per_launch"] / rec["items_per_dispatch"]
             alone_s = rec["avg_ns_under_counters"] * 1e-9 * k["items_per_launch"] / rec["items_per_dispatch"]
-            roof["traffic"] = round(traffic)
-            roof["counter"] = {
+            r["traffic"] = round(traffic)
+            r["counter"] = {
                 "bytes_per_projection": round(traffic / k["items_per_launch"], 1),
                 "shared_GBps": round(traffic / (k["avg_us"] * 1e-6) / 1e9, 1),
                 "shared_frac": round(traffic / (k["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
@@ -739,6 +745,22 @@ def main():
                 "lds_reuse": round(sb * k["items_per_launch"] / traffic, 2),
                 "note": "shared: over the timed run's launch time (the adjoint's second stream runs beside); "
                         "alone: over the launch time under the counters (one dispatch at a time)"}
+        return r
+
+    if tot > 0:
+        dom = max(range(N_FAM), key=lambda f: ms[f])
+        roof = kernel_roof(dom)
+        # the forward and reverse group kernels take about equal time on the
+        # tiled cloth, so the dominant one can change from run to run: both
+        # are reported, each with its share of the sampled kernel time
+        if launches[10] and launches[11]:
+            roof["by_kernel"] = {}
+            for fam in (10, 11):
+                r = kernel_roof(fam)
+                roof["by_kernel"][KERNEL_SYMBOL[fam]] = {
+                    "share_of_sampled_ms": kernels[FAMILY[fam]]["share_of_sampled_ms"],
+                    "avg_launch_us": r["avg_launch_us"], "achieved": r["achieved"], "frac": r["frac"],
+                    "bytes_per_projection": r["bytes_per_projection"], "counter": r.get("counter")}
 
         # the whole path per step: algorithmic bytes of every projection run
         # (forward frames, the adjoint's recomputed frames, reversed frames)
@@ -754,8 +776,8 @@ def main():
             half = proj_step / 2
             frames_fwd = F + (F - kept)
             if all_grouped:
-                fb = group_bytes(sc, False, tsz, recording, staged, rk == 1)
-                rb = group_bytes(sc, True, tsz, recording, staged, rk == 1)
+                fb = group_bytes(sc, False, tsz, recording, staged, rk == 1, want_ab)
+                rb = group_bytes(sc, True, tsz, recording, staged, rk == 1, want_ab)
             else:
                 fb = recording * mix_bytes(sc, False, tsz, True) + (1 - recording) * mix_bytes(sc, False, tsz, False)
                 rb = mix_bytes(sc, True, tsz, False)
