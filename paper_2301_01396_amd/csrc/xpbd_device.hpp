@@ -30,19 +30,21 @@ template <class S> __device__ __forceinline__ V3<S> cross(V3<S> a, V3<S> b) {
 }
 template <class T> __device__ __forceinline__ V3<T> xyz(const Vec4<T>& v) { return {v.x, v.y, v.z}; }
 
-// Reciprocal in the reverse cores: the hardware's single-precision
-// reciprocal (v_rcp_f32, within 1 ulp) in FP32, a division in FP64.  The
-// reverse linearises each projection at its recorded inputs, so a 1-ulp
-// reciprocal moves its results by about 1e-7 relative, far below the FP32
-// bar, at a tenth of an IEEE division's instructions; the forward, whose
-// values the record holds, keeps IEEE division.
-template <class T> __device__ __forceinline__ T rcp_rev(T x) { return T(1) / x; }
-template <> __device__ __forceinline__ float rcp_rev<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <bool REV, class T> __device__ __forceinline__ T recip(T x) { return REV ? rcp_rev(x) : T(1) / x; }
+// Reciprocal of the distance and hinge cores: in FP32 the hardware's
+// single-precision reciprocal (v_rcp_f32, within 1 ulp) at a tenth of an
+// IEEE division's instructions, in FP64 a division.  A 1-ulp reciprocal is
+// within FP32's own rounding of the quotient it replaces: the forward moves
+// by far less than the FP32 bar, and the reverse, which linearises each
+// projection at its recorded inputs, by about 1e-7 relative.  (The tet,
+// membrane and contact cores, and the implicit adjoint's FP64 operator,
+// divide.)
+template <class T> __device__ __forceinline__ T rcp_fast(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <bool FAST, class T> __device__ __forceinline__ T recip(T x) { return FAST ? rcp_fast(x) : T(1) / x; }
 
 // ----------------------------------------------------------------- duals
 // (value, directional derivative) pairs for the dihedral Hessian-vector
-// product, which only the reverse evaluates (reciprocals by rcp_rev)
+// product of the reverse (reciprocals by rcp_fast)
 template <class T> struct Dual { T v, d; };
 template <class T> __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
 template <class T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
@@ -51,7 +53,7 @@ template <class T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<
 template <class T> __device__ __forceinline__ Dual<T> operator*(T s, Dual<T> a) { return {s * a.v, s * a.d}; }
 template <class T> __device__ __forceinline__ Dual<T> dsqrt(Dual<T> a) {
   T r = sqrt(a.v);
-  return {r, T(0.5) * a.d * rcp_rev(r)};
+  return {r, T(0.5) * a.d * rcp_fast(r)};
 }
 template <class T> __device__ __forceinline__ T dsqrt(T a) { return sqrt(a); }
 template <class T> __device__ __forceinline__ T val(T a) { return a; }
@@ -60,14 +62,14 @@ template <class T> __device__ __forceinline__ T scal(T s, T) { return s; }
 
 // ----------------------------------------------------------------- distance
 // C = |r| - L, grad_i = n, grad_j = -n (n = r/|r|).
-// REV: evaluated by the reverse (reciprocal by rcp_rev)
+// FAST: reciprocal by rcp_fast
 template <class T> struct DistEval { T C, len, inv; V3<T> n; bool ok; };
-template <class T, bool REV = false> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L) {
+template <class T, bool FAST = false> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L) {
   DistEval<T> e;
   T l2 = dot(r, r);
   e.ok = l2 > T(0);
   e.len = sqrt(l2);
-  e.inv = recip<REV>(e.len);
+  e.inv = recip<FAST>(e.len);
   e.n = e.inv * r;
   e.C = e.len - L;
   return e;
@@ -78,15 +80,15 @@ template <class T, bool REV = false> __device__ __forceinline__ DistEval<T> dist
 // theta = atan2(((n1 x n2) . e)/|e|, n1 . n2).
 // grad x2 = -|e| n1/|n1|^2, grad x3 = -|e| n2/|n2|^2,
 // grad x1 = (a.e/|e|) n1/|n1|^2 + (b.e/|e|) n2/|n2|^2, grad x0 = -(sum).
-template <bool REV, class S> __device__ __forceinline__ S one_over(S x) { return recip<REV>(x); }
-template <bool REV, class T> __device__ __forceinline__ Dual<T> one_over(Dual<T> x) {
-  T r = rcp_rev(x.v);
+template <bool FAST, class S> __device__ __forceinline__ S one_over(S x) { return recip<FAST>(x); }
+template <bool FAST, class T> __device__ __forceinline__ Dual<T> one_over(Dual<T> x) {
+  T r = rcp_fast(x.v);
   return {r, -x.d * r * r};
 }
-template <class S, bool REV = false> __device__ __forceinline__ void bend_gradient(V3<S> e, V3<S> a, V3<S> b, V3<S> g[4]) {
+template <class S, bool FAST = false> __device__ __forceinline__ void bend_gradient(V3<S> e, V3<S> a, V3<S> b, V3<S> g[4]) {
   V3<S> n1 = cross(e, a), n2 = cross(b, e);
   S le = dsqrt(dot(e, e));
-  S r1 = one_over<REV>(S(dot(n1, n1))), r2 = one_over<REV>(S(dot(n2, n2))), rl = one_over<REV>(le);
+  S r1 = one_over<FAST>(S(dot(n1, n1))), r2 = one_over<FAST>(S(dot(n2, n2))), rl = one_over<FAST>(le);
   V3<S> s1 = {n1.x * r1, n1.y * r1, n1.z * r1};
   V3<S> s2 = {n2.x * r2, n2.y * r2, n2.z * r2};
   S c1 = dot(a, e) * rl, c2 = dot(b, e) * rl;
@@ -96,17 +98,17 @@ template <class S, bool REV = false> __device__ __forceinline__ void bend_gradie
   g[0] = -(g[1] + g[2] + g[3]);
 }
 template <class T> struct BendEval { T C; V3<T> g[4]; bool ok; };
-template <class T, bool REV = false> __device__ __forceinline__ BendEval<T> bend_eval(V3<T> e, V3<T> a, V3<T> b,
+template <class T, bool FAST = false> __device__ __forceinline__ BendEval<T> bend_eval(V3<T> e, V3<T> a, V3<T> b,
                                                                                   T theta0) {
   BendEval<T> r;
   V3<T> n1 = cross(e, a), n2 = cross(b, e);
   T le2 = dot(e, e), q1 = dot(n1, n1), q2 = dot(n2, n2);
   r.ok = le2 > T(0) && q1 > T(0) && q2 > T(0);
   T le = sqrt(le2);
-  T y = dot(cross(n1, n2), e) * recip<REV>(le);   // 1/|e| is the quotient the gradient forms too
+  T y = dot(cross(n1, n2), e) * recip<FAST>(le);   // 1/|e| is the quotient the gradient forms too
   T x = dot(n1, n2);
   r.C = atan2(y, x) - theta0;
-  bend_gradient<T, REV>(e, a, b, r.g);
+  bend_gradient<T, FAST>(e, a, b, r.g);
   return r;
 }
 // Hessian of theta times gbar: directional derivative of the gradient along

@@ -88,11 +88,11 @@ template <class T, bool TAPE>
 __device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T lb, Vec4<T>* tape, bool& moved) {
   V3<T> r = xyz(a) - xyz(b);
   if (TAPE) *tape = Vec4<T>{r.x, r.y, r.z, lb};
-  DistEval<T> ev = dist_eval(r, rest);
+  DistEval<T> ev = dist_eval<T, true>(r, rest);
   T Dn = a.w + b.w + a_t;
   moved = ev.ok && Dn > T(0);
   if (!moved) return lb;
-  T dl = (-ev.C - a_t * lb) / Dn;
+  T dl = (-ev.C - a_t * lb) * rcp_fast(Dn);
   T sa = a.w * dl, sb = b.w * dl;
   a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
   b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
@@ -111,13 +111,13 @@ __device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<
     tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
     reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
   }
-  BendEval<T> ev = bend_eval(e, a, b, theta0);
+  BendEval<T> ev = bend_eval<T, true>(e, a, b, theta0);
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += p[k].w * dot(ev.g[k], ev.g[k]);
   moved = ev.ok && Dn > T(0);
   if (!moved) return lb;
-  T dl = (-ev.C - a_t * lb) / Dn;
+  T dl = (-ev.C - a_t * lb) * rcp_fast(Dn);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     T s = p[k].w * dl;
@@ -310,7 +310,7 @@ __device__ __forceinline__ bool dist_rev(Vec4<T>& A, Vec4<T>& Bv, Vec4<T> tp, T 
   T Dn = A.w + Bv.w + a_t;
   if (!(ev.ok && Dn > T(0))) return false;
   T lb = tp.w;
-  const T iD = rcp_rev(Dn);
+  const T iD = rcp_fast(Dn);
   T dl = (-ev.C - a_t * lb) * iD;
   V3<T> xa = xyz(A), xb = xyz(Bv);
   T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
@@ -341,7 +341,7 @@ __device__ __forceinline__ bool bend_rev(Vec4<T> P[4], const Vec4<T>* tape, int 
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += w[k] * dot(ev.g[k], ev.g[k]);
   if (!(ev.ok && Dn > T(0))) return false;
-  const T iD = rcp_rev(Dn);
+  const T iD = rcp_fast(Dn);
   T dl = (-ev.C - a_t * lb) * iD;
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
