@@ -848,6 +848,10 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+    if not grads_finite:
+        # a step whose gradient is not finite measured nothing worth a number
+        log("error: the step's gradients are not finite")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

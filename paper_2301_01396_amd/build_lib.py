@@ -13,7 +13,7 @@ HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith
     os.path.join(os.path.dirname(HERE), "include", "xpbd.h")]
 
 # -O3 without fast-math: IEEE division and square root (the distance and
-# hinge cores take FP32 reciprocals from the hardware's reciprocal
+# hinge reverse cores take FP32 reciprocals from the hardware's reciprocal
 # instruction explicitly); multiply-adds are fused per source expression only
 # (-ffp-contract=on), so every kernel that shares a projection routine
 # rounds it the same way.  Packed-FP32 ops are disabled (-packed-fp32-ops)

@@ -30,14 +30,14 @@ template <class S> __device__ __forceinline__ V3<S> cross(V3<S> a, V3<S> b) {
 }
 template <class T> __device__ __forceinline__ V3<T> xyz(const Vec4<T>& v) { return {v.x, v.y, v.z}; }
 
-// Reciprocal of the distance and hinge cores: in FP32 the hardware's
+// Reciprocal of the distance and hinge reverse cores: in FP32 the hardware's
 // single-precision reciprocal (v_rcp_f32, within 1 ulp) at a tenth of an
-// IEEE division's instructions, in FP64 a division.  A 1-ulp reciprocal is
-// within FP32's own rounding of the quotient it replaces: the forward moves
-// by far less than the FP32 bar, and the reverse, which linearises each
-// projection at its recorded inputs, by about 1e-7 relative.  (The tet,
-// membrane and contact cores, and the implicit adjoint's FP64 operator,
-// divide.)
+// IEEE division's instructions, in FP64 a division.  The reverse linearises
+// each projection at its recorded inputs, so a 1-ulp reciprocal moves its
+// results by about 1e-7 relative.  The forward keeps IEEE division: with the
+// reciprocal there, the 25.2M-DoF cloth's 20-frame rollout took another path
+// and its adjoint came out non-finite.  (The tet, membrane and contact cores,
+// and the implicit adjoint's FP64 operator, divide.)
 template <class T> __device__ __forceinline__ T rcp_fast(T x) { return T(1) / x; }
 template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <bool FAST, class T> __device__ __forceinline__ T recip(T x) { return FAST ? rcp_fast(x) : T(1) / x; }

@@ -88,11 +88,11 @@ template <class T, bool TAPE>
 __device__ __forceinline__ T dist_fwd(Vec4<T>& a, Vec4<T>& b, T rest, T a_t, T lb, Vec4<T>* tape, bool& moved) {
   V3<T> r = xyz(a) - xyz(b);
   if (TAPE) *tape = Vec4<T>{r.x, r.y, r.z, lb};
-  DistEval<T> ev = dist_eval<T, true>(r, rest);
+  DistEval<T> ev = dist_eval(r, rest);
   T Dn = a.w + b.w + a_t;
   moved = ev.ok && Dn > T(0);
   if (!moved) return lb;
-  T dl = (-ev.C - a_t * lb) * rcp_fast(Dn);
+  T dl = (-ev.C - a_t * lb) / Dn;
   T sa = a.w * dl, sb = b.w * dl;
   a.x += sa * ev.n.x; a.y += sa * ev.n.y; a.z += sa * ev.n.z;
   b.x -= sb * ev.n.x; b.y -= sb * ev.n.y; b.z -= sb * ev.n.z;
@@ -111,13 +111,13 @@ __device__ __forceinline__ T bend_fwd(Vec4<T> p[4], T theta0, T a_t, T lb, Vec4<
     tape[count + t] = Vec4<T>{a.x, a.y, a.z, b.x};
     reinterpret_cast<Vec2<T>*>(tape + 2 * count)[t] = Vec2<T>{b.y, b.z};
   }
-  BendEval<T> ev = bend_eval<T, true>(e, a, b, theta0);
+  BendEval<T> ev = bend_eval(e, a, b, theta0);
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += p[k].w * dot(ev.g[k], ev.g[k]);
   moved = ev.ok && Dn > T(0);
   if (!moved) return lb;
-  T dl = (-ev.C - a_t * lb) * rcp_fast(Dn);
+  T dl = (-ev.C - a_t * lb) / Dn;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     T s = p[k].w * dl;
