@@ -38,6 +38,15 @@ import numpy as np
 DIST, BEND, TET, CONTACT, TRI, BODY = 0, 1, 2, 3, 4, 5
 TYPE_NAMES = {DIST: "dist", BEND: "bend", TET: "tet", CONTACT: "contact"}
 GRAVITY = (0.0, -9.81, 0.0)
+# Lattice spacing (m) of the tet-box workloads.  With 2 substeps of 1/120 s
+# and 20 iterations, the deviatoric constraint sqrt(tr F^T F), which never
+# vanishes and is held at rest only by the hydrostatic one, is projected
+# hard when the tets are small against the step: on a 1/64 m lattice of this
+# material (E ~ 1e5 Pa, 1000 kg/m^3) the box sags by its own height and
+# inverts tets within a frame, and the exact gradient grows past FP64's range
+# over 20 frames.  At 0.25 m the 64^3 box settles by about 4% with no tet
+# inverted (smallest volume ratio 0.59 over 20 frames).
+TET_SPACING = 0.25
 
 
 @dataclass
@@ -711,13 +720,17 @@ def config_c2_membrane(n_frames: int = 30, target: bool = False, n: int = 256, t
     the distance constraints (Sec. 5.1's cloth model), dihedral bending and
     the sphere; per-triangle coefficients (C00, C01, C11, C22) =
     (4e3, 6e2, 2e3, 8e2) N/m x U[0.7, 1.3] (seed 1, seed 2 for the target);
-    8 membrane sets, 12 bending sets, 1 contact set per iteration.  tile > 0:
+    8 membrane sets, 12 bending sets, 1 contact set per iteration.  Mass
+    from an areal density of 0.2 kg/m^2 (3.1 mg per vertex): with the grid's
+    unit mass per vertex these coefficients let the 65 t sheet stretch
+    several-fold under its own weight over 30 frames.  tile > 0:
     a tiled schedule with LDS groups, tiles + border segments + corners
     (``tiling="lines"``, 16 x 16 by default: 668 ms per step against 780 ms
     with one launch per set on MI355X) or four colours of whole tiles
     (``"quads"``); 0: the untiled sets."""
     sc = membrane_cloth(n=n, frames=n_frames, substeps=4, iterations=30, sphere=True, pinned=(),
                         seed=2 if target else 1)
+    sc.inv_mass = np.where(sc.inv_mass > 0, (n - 1) ** 2 / 0.2, 0.0)
     if tile:
         (tile_cloth_lines if tiling == "lines" else tile_cloth_quads)(sc, n, n, tile)
     sc.sphere = (0.0, -0.35, 0.0, 0.3)
@@ -752,10 +765,11 @@ def config_c2_body(n_frames: int = 30, target: bool = False, n: int = 256, body_
 
 
 def config_c3(n_frames: int = 20, target: bool = False, n: int = 64, tile: int = 0) -> Scene:
-    """64^3-cube tet box (5 tets per cube), bottom pinned, Neo-Hookean,
-    dt 1/60, 2 substeps, 20 iterations.  tile > 0: tiled schedule (8 shifted
-    tilings of tile^3 cubes)."""
-    sc = tet_box(n)
+    """64^3-cube tet box (5 tets per cube) on a TET_SPACING lattice (16 m
+    across), density 1000 kg/m^3, bottom pinned, Neo-Hookean, dt 1/60,
+    2 substeps, 20 iterations.  tile > 0: tiled schedule (8 shifted tilings
+    of tile^3 cubes)."""
+    sc = tet_box(n, size=n * TET_SPACING)
     if tile:
         tile_box(sc, n, tile)
     E, nu = tet_material(1, sc.n_tet)

@@ -434,7 +434,7 @@ def make_mix(n: int, qps: float, seed: int = 6, frames=(30, 120), size_mu=np.log
             sc.tet_E = np.zeros(0)
         else:
             m = max(1, int(round(sizes[i] ** (1.0 / 3.0))) - 1)
-            sc = scenes.tet_box(m)
+            sc = scenes.tet_box(m, size=m * scenes.TET_SPACING)
             sc.tet_E, sc.tet_nu = scenes.tet_material(int(pseed[i]), sc.n_tet)
             sc.dist_alpha, sc.bend_alpha = np.zeros(0), np.zeros(0)
         sc.dt, sc.substeps, sc.iterations = 1.0 / 60.0, substeps, iterations

@@ -41,16 +41,104 @@ def test_cloth256_one_frame_lds_groups():
     print("cloth256 one frame:", errs)
 
 
+def _membrane_strained(n_frames=1):
+    """The bench's membrane cloth with a smooth seeded initial velocity
+    field (0.5 m/s, wavelengths of a third of the sheet and more): the sheet
+    would otherwise fall freely and unstrained through its first frames,
+    where every compliance gradient is zero."""
+    sc = scenes.config_c2_membrane(n_frames=n_frames)
+    sc.v0 = scenes.force_field(3, 256, 256, 1, amplitude=0.5)[0]
+    return sc
+
+
+def test_cloth256_membrane_one_frame_fp64():
+    """The 256x256 membrane cloth of the bench (orthotropic StVK triangles,
+    bending, the sphere; 0.2 kg/m^2; 16 x 16 tiles in three LDS groups),
+    strained from its first step, one full frame of 4 substeps x 30
+    iterations, FP64 on both sides.  The membrane is stiff against these
+    vertex masses (alpha~ about 1e-4 of w |grad C|^2), and the frame
+    amplifies rounding by about 1e11: the GPU and the reference, both FP64
+    with different operation orders, agree to 1.8e-9 in the positions (L2;
+    5.6e-8 largest element) and to 2.73e-5 in every gradient group, the same
+    figure in each (the difference lies along one direction).  Bars:
+    positions 1e-8 (L2) and 1e-7 (largest element), gradients 1e-4.  The
+    small membrane meshes of the parity suite pin the same kernels tightly."""
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    needs_gpu()
+    sc = _membrane_strained()
+    sim = Simulator(sc, dtype=torch.float64)
+    assert sim.info()["n_groups_lds"] > 0    # FP64 tiles of one group exceed LDS
+    ref = reference_case(sc, 1, n_threads=THREADS, noise=0.01)
+    got = gpu_case(sim, 1, ref)
+    errs = compare(sc, ref, got, 1e-8, 1e-4, pos_max_tol=1e-7)
+    print("cloth256 membrane one frame fp64:", errs)
+
+
+def test_cloth256_membrane_one_frame_fp32_positions():
+    """The same frame in FP32.  At 0.2 kg/m^2 the membrane is stiff against
+    the vertex masses (alpha~ about 1e-4 of w |grad C|^2), and FP32 storage
+    alone (the reference run with its state rounded to FP32 after every
+    write) moves every gradient group of this frame by more than its size:
+    the GPU positions must be within twice that reference's L2 distance
+    from the FP64 one (never held to less than 1e-5); the FP32 gradients of
+    this workload are parity unpinned (the FP64 test above pins the same
+    kernels)."""
+    sc = _membrane_strained()
+    sim = _sim(sc)
+    xf, _, _ = O.forward(O.OracleScene(sc, n_threads=THREADS), 1)
+    xe32, _, _ = O.forward(O.OracleScene(sc, emulate_f32=True, n_threads=THREADS), 1)
+    intrinsic = rel(xe32, xf)
+    gx, _, _ = sim.forward(1)
+    err = rel(gx.double().cpu().numpy(), xf)
+    print("cloth256 membrane fp32 positions:", err, "intrinsic", intrinsic, flush=True)
+    assert err <= max(1e-5, 2 * intrinsic)
+
+
+def test_cloth256_membrane_benchmark_rollout_fp32_against_fp64():
+    """The bench's whole membrane-cloth step: 30 frames (the sheet falls onto
+    the sphere and drapes), goal on the last frame against the cloth with
+    the seed-2 coefficients, gradients of the membrane coefficients; FP32
+    against the same step in FP64 on the GPU.  The drape is chaotic at FP32
+    resolution and the coefficient gradient lies below it (measured: last
+    frame positions 4.3e-3 apart in L2, the loss 0.3 and dL/dcoef 3e4 of
+    their FP64 values), so what is held: the loss and every gradient element
+    finite, and the last frame's positions within 1e-2 of FP64."""
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    needs_gpu()
+    sc, tg_sc = scenes.config_c2_membrane(), scenes.config_c2_membrane(target=True)
+    F = sc.n_frames
+    mask = np.zeros(F, np.uint8)
+    mask[F - 1] = 1
+    out = {}
+    for dt in (torch.float32, torch.float64):
+        tsim = Simulator(tg_sc, dtype=dt)
+        tg, _, _ = tsim.forward(F)
+        tg = tg.clone()
+        tsim.close()
+        sim = Simulator(sc, dtype=dt)
+        xf, _, _ = sim.forward(F, for_adjoint=True)
+        loss, dL = sim.goal_l2(xf, tg, mask)
+        g = sim.adjoint(dL, mask)
+        torch.cuda.synchronize()
+        out[dt] = (float(loss.cpu()), g["tri_coef"].double().cpu().numpy(), xf[-1].double().cpu().numpy(),
+                   all(bool(torch.isfinite(v).all()) for v in g.values() if v is not None))
+        sim.close()
+        del sim, tsim, tg, xf, dL, g
+        torch.cuda.empty_cache()
+    (l32, g32, x32, fin32), (l64, g64, x64, _) = out[torch.float32], out[torch.float64]
+    print(f"cloth256 membrane 30 frames: loss FP32 {l32:.10e} FP64 {l64:.10e}; last frame positions relative L2 "
+          f"{rel(x32, x64):.2e}; dL/dcoef L2 FP64 {np.linalg.norm(g64):.4e} FP32 {np.linalg.norm(g32):.4e}", flush=True)
+    assert np.isfinite(l32) and fin32
+    assert rel(x32, x64) <= 1e-2
+
+
 def test_tetbox64_one_frame_fp64():
-    """64^3-cube tet box (1.31M tets, the bench's sets and set sizes), one
-    frame with 2 substeps x 3 iterations, FP64 on both sides.  These stiff
-    tets (alpha~ far below w |grad C|^2, few iterations) make the exact
-    gradient of the rollout amplify rounding enormously: the reference run
-    with FP32 storage rounding misses its own FP64 gradient by more than the
-    gradient's size, and two FP64 evaluations with different operation
-    order agree to about 1e-6 in the gradients and 7e-10 in the worst
-    position.  Positions must agree to 1e-10 (L2) and 1e-8 (largest element),
-    gradients to 1e-5."""
+    """64^3-cube tet box (1.31M tets on a 0.25 m lattice, the bench's sets
+    and set sizes), one frame with 2 substeps x 3 iterations, FP64 on both
+    sides: positions within 1e-10 (L2) and 1e-8 (largest element),
+    gradients within 1e-5."""
     import torch
     from paper_2301_01396_amd.lib import Simulator
     needs_gpu()
@@ -63,42 +151,73 @@ def test_tetbox64_one_frame_fp64():
     print("tetbox64 fp64:", errs)
 
 
-def test_tetbox64_softer_fp32():
-    """The same 1.31M-tet box and schedule with Young's moduli scaled by
-    1e-2, where the rollout is well conditioned (FP32 storage rounding in the
-    reference moves its gradients by 3.5e-4): FP32 on the GPU, positions to
-    1e-5 and every gradient group to 1e-3."""
+def test_tetbox64_one_frame_fp32():
+    """The bench's tet box at its configured moduli, one frame of 2 substeps
+    x 3 iterations, FP32 on the GPU.  On the 16 m box FP32 storage of the
+    positions alone moves the exact gradients by 3.1-4.4e-3 (the reference
+    run with its state rounded to FP32 after every write, against the FP64
+    one), and two FP32 evaluations differ by about a quarter of that, so, as
+    for the 25.2M-DoF cloth's benchmark structure, the FP32-storage
+    reference is the bar: positions within 1e-5 of it, every gradient group
+    within 1e-3 of it or within its own distance from the FP64 reference,
+    whichever is larger (L2 and largest element alike; measured 1.07-1.16e-3
+    L2), and within twice that distance of the plain FP64 reference, never
+    less than 1e-3."""
     sc = scenes.config_c3(n_frames=1)
     sc.iterations = 3
-    sc.tet_E = sc.tet_E * 1e-2
     sim = _sim(sc)
-    ref = reference_case(sc, 1, n_threads=THREADS, noise=1e-3)
+    ref = reference_case(sc, 1, n_threads=THREADS, noise=1e-3, emulate_f32=True)
+    plain = reference_case(sc, 1, n_threads=THREADS, targets=ref["targets"])
     got = gpu_case(sim, 1, ref)
-    errs = compare(sc, ref, got, 1e-5, 1e-3)
-    print("tetbox64 softer fp32:", errs)
+    _c4_report("tetbox64 one frame fp32", ref, plain, got)
+    errs = compare(sc, ref, got, 1e-5, float("inf"), grad_max_tol=float("inf"))
+    for k, r in ref["grads"].items():
+        if k not in got["grads"] or r.size == 0 or np.linalg.norm(r) == 0:
+            continue
+        intrinsic, intrinsic_max = rel(r, plain["grads"][k]), max_err(r, plain["grads"][k])
+        assert errs[k] <= max(1e-3, intrinsic), (k, errs[k], intrinsic)
+        assert errs[k + "_max"] <= max(1e-3, intrinsic_max), (k, errs[k + "_max"], intrinsic_max)
+        assert rel(got["grads"][k], plain["grads"][k]) <= max(1e-3, 2 * intrinsic), (k, intrinsic)
 
 
-def test_tetbox64_one_frame_fp32_positions():
-    """Same rollout in FP32 at the configured moduli.  Here FP32 storage
-    alone (the reference run with its state rounded to FP32 after every
-    write) moves the positions by 3.3e-4 (L2) and single vertices by up to
-    5e-2 of the box size in one frame, and its gradients by more than their
-    size: the rollout is chaotic at FP32 resolution.  So the GPU positions
-    must be within twice that intrinsic L2 error of the FP64 reference (and
-    never worse than 1e-5 where it is smaller); single vertices and the FP32
-    gradients are parity unpinned at these moduli (the FP64 test above and
-    the softer FP32 test pin the same kernels)."""
-    sc = scenes.config_c3(n_frames=1)
-    sc.iterations = 3
-    sim = _sim(sc)
-    xf, _, _ = O.forward(O.OracleScene(sc, n_threads=THREADS), 1)
-    xe32, _, _ = O.forward(O.OracleScene(sc, emulate_f32=True, n_threads=THREADS), 1)
-    intrinsic = rel(xe32, xf)
-    gx, _, _ = sim.forward(1)
-    err = rel(gx.double().cpu().numpy(), xf)
-    print("tetbox64 fp32 positions:", err, "intrinsic", intrinsic, "largest element",
-          max_err(gx.double().cpu().numpy(), xf), "intrinsic", max_err(xe32, xf))
-    assert err <= max(1e-5, 2 * intrinsic)
+def test_tetbox64_benchmark_rollout_fp32_against_fp64():
+    """The bench's whole tet-box step: 20 frames of 2 substeps x 20
+    iterations, goal on the last frame against the box with the seed-2
+    moduli, dL/dE; FP32 against the same step in FP64 on the GPU (the
+    reference takes minutes for 20 frames of 1.31M tets).  Loss and every
+    gradient element finite; the loss within 1e-2 and dL/dE within 5e-2
+    relative L2 of FP64 (measured, from FP32 storage over 800 substep
+    iterations on the 16 m box: 1.4e-5 in the last frame's positions,
+    2.9e-3 in the loss, 1.5e-2 in dL/dE)."""
+    import torch
+    from paper_2301_01396_amd.lib import Simulator
+    needs_gpu()
+    sc, tg_sc = scenes.config_c3(), scenes.config_c3(target=True)
+    F = sc.n_frames
+    mask = np.zeros(F, np.uint8)
+    mask[F - 1] = 1
+    out = {}
+    for dt in (torch.float32, torch.float64):
+        tsim = Simulator(tg_sc, dtype=dt)
+        tg, _, _ = tsim.forward(F)
+        tg = tg.clone()
+        tsim.close()
+        sim = Simulator(sc, dtype=dt)
+        xf, _, _ = sim.forward(F, for_adjoint=True)
+        loss, dL = sim.goal_l2(xf, tg, mask)
+        g = sim.adjoint(dL, mask)
+        torch.cuda.synchronize()
+        out[dt] = (float(loss.cpu()), g["tet_E"].double().cpu().numpy(), xf[-1].double().cpu().numpy())
+        sim.close()
+        del sim, tsim, tg, xf, dL, g
+        torch.cuda.empty_cache()
+    (l32, g32, x32), (l64, g64, x64) = out[torch.float32], out[torch.float64]
+    print(f"tetbox64 20 frames: loss FP32 {l32:.10e} FP64 {l64:.10e} relative {abs(l32 - l64) / abs(l64):.2e}; "
+          f"last frame positions relative L2 {rel(x32, x64):.2e}; dL/dE L2 {np.linalg.norm(g64):.4e}, FP32 "
+          f"relative L2 {rel(g32, g64):.2e}, largest element {max_err(g32, g64):.2e}", flush=True)
+    assert np.isfinite(l32) and np.isfinite(g32).all()
+    assert abs(l32 - l64) <= 1e-2 * abs(l64)
+    assert rel(g32, g64) <= 5e-2
 
 
 def _c4_reference(sc, F, mask, seed):
@@ -113,7 +232,7 @@ def _c4_reference(sc, F, mask, seed):
 def _c4_report(name, ref, plain, got):
     out = {"x_frames": (rel(got["x_frames"], ref["x_frames"]), rel(got["x_frames"], plain["x_frames"]))}
     for k, r in ref["grads"].items():
-        if r.size and np.linalg.norm(r) > 0:
+        if k in got["grads"] and r.size and np.linalg.norm(r) > 0:
             out[k] = (rel(got["grads"][k], r), rel(got["grads"][k], plain["grads"][k]),
                       rel(r, plain["grads"][k]))
     print(name, "(error against the FP32-storage reference, against the plain FP64 one, and the FP32-storage "
