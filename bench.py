@@ -177,7 +177,9 @@ HBM_PEAK_GBS = 8000.0
 # what the parity tests establish for each workload's results, by dtype
 ACCURACY = {
     ("c1", "f64"): "positions and gradients within 1e-10 / 1e-8 of the FP64 reference (full rollout)",
-    ("c2", "f32"): "one full frame at full size: positions 1e-5, every gradient group 1e-3 of the FP64 reference",
+    ("c2", "f32"): "one full frame at full size: positions 1e-5, every gradient group 1e-3 of the FP64 reference; "
+                   "the 30-frame drape is chaotic at FP32 resolution (gradients of the whole step differ from FP64 "
+                   "by order one): run --dtype f64 for digits",
     ("c4", "f32"): "full size, the benchmark's adjoint structure: positions 1e-5, gradients 1e-3 of the "
                    "reference with FP32 state storage (the plain FP64 reference differs from both by 3.5e-3 "
                    "in dL/dalpha)",
