@@ -12,12 +12,10 @@ SOURCES = [os.path.join(CSRC, "xpbd.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "xpbd.h")]
 
-# -O3 without fast-math: IEEE division and square root (the distance and
-# hinge reverse cores take FP32 reciprocals from the hardware's reciprocal
-# instruction explicitly); multiply-adds are fused per source expression only
-# (-ffp-contract=on), so every kernel that shares a projection routine
-# rounds it the same way.  Packed-FP32 ops are disabled (-packed-fp32-ops)
-# for the device code.
+# -O3 without fast-math: IEEE division and square root; multiply-adds are
+# fused per source expression only (-ffp-contract=on), so every kernel that
+# shares a projection routine rounds it the same way.  Packed-FP32 ops are
+# disabled (-packed-fp32-ops) for the device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",

@@ -30,30 +30,21 @@ template <class S> __device__ __forceinline__ V3<S> cross(V3<S> a, V3<S> b) {
 }
 template <class T> __device__ __forceinline__ V3<T> xyz(const Vec4<T>& v) { return {v.x, v.y, v.z}; }
 
-// Reciprocal of the distance and hinge reverse cores: in FP32 the hardware's
-// single-precision reciprocal (v_rcp_f32, within 1 ulp) at a tenth of an
-// IEEE division's instructions, in FP64 a division.  The reverse linearises
-// each projection at its recorded inputs, so a 1-ulp reciprocal moves its
-// results by about 1e-7 relative.  The forward keeps IEEE division: with the
-// reciprocal there, the 25.2M-DoF cloth's 20-frame rollout took another path
-// and its adjoint came out non-finite.  (The tet, membrane and contact cores,
-// and the implicit adjoint's FP64 operator, divide.)
-template <class T> __device__ __forceinline__ T rcp_fast(T x) { return T(1) / x; }
-template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <bool FAST, class T> __device__ __forceinline__ T recip(T x) { return FAST ? rcp_fast(x) : T(1) / x; }
-
 // ----------------------------------------------------------------- duals
-// (value, directional derivative) pairs for the dihedral Hessian-vector
-// product of the reverse (reciprocals by rcp_fast)
+// (value, directional derivative) pairs for the dihedral Hessian-vector product
 template <class T> struct Dual { T v, d; };
 template <class T> __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
 template <class T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
 template <class T> __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
 template <class T> __device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class T> __device__ __forceinline__ Dual<T> operator/(Dual<T> a, Dual<T> b) {
+  T q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
 template <class T> __device__ __forceinline__ Dual<T> operator*(T s, Dual<T> a) { return {s * a.v, s * a.d}; }
 template <class T> __device__ __forceinline__ Dual<T> dsqrt(Dual<T> a) {
   T r = sqrt(a.v);
-  return {r, T(0.5) * a.d * rcp_fast(r)};
+  return {r, T(0.5) * a.d * (T(1) / r)};   // 1/r is the quotient the gradient forms next
 }
 template <class T> __device__ __forceinline__ T dsqrt(T a) { return sqrt(a); }
 template <class T> __device__ __forceinline__ T val(T a) { return a; }
@@ -62,14 +53,13 @@ template <class T> __device__ __forceinline__ T scal(T s, T) { return s; }
 
 // ----------------------------------------------------------------- distance
 // C = |r| - L, grad_i = n, grad_j = -n (n = r/|r|).
-// FAST: reciprocal by rcp_fast
 template <class T> struct DistEval { T C, len, inv; V3<T> n; bool ok; };
-template <class T, bool FAST = false> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L) {
+template <class T> __device__ __forceinline__ DistEval<T> dist_eval(V3<T> r, T L) {
   DistEval<T> e;
   T l2 = dot(r, r);
   e.ok = l2 > T(0);
   e.len = sqrt(l2);
-  e.inv = recip<FAST>(e.len);
+  e.inv = T(1) / e.len;
   e.n = e.inv * r;
   e.C = e.len - L;
   return e;
@@ -80,15 +70,15 @@ template <class T, bool FAST = false> __device__ __forceinline__ DistEval<T> dis
 // theta = atan2(((n1 x n2) . e)/|e|, n1 . n2).
 // grad x2 = -|e| n1/|n1|^2, grad x3 = -|e| n2/|n2|^2,
 // grad x1 = (a.e/|e|) n1/|n1|^2 + (b.e/|e|) n2/|n2|^2, grad x0 = -(sum).
-template <bool FAST, class S> __device__ __forceinline__ S one_over(S x) { return recip<FAST>(x); }
-template <bool FAST, class T> __device__ __forceinline__ Dual<T> one_over(Dual<T> x) {
-  T r = rcp_fast(x.v);
+template <class S> __device__ __forceinline__ S one_over(S x) { return S(1) / x; }
+template <class T> __device__ __forceinline__ Dual<T> one_over(Dual<T> x) {
+  T r = T(1) / x.v;
   return {r, -x.d * r * r};
 }
-template <class S, bool FAST = false> __device__ __forceinline__ void bend_gradient(V3<S> e, V3<S> a, V3<S> b, V3<S> g[4]) {
+template <class S> __device__ __forceinline__ void bend_gradient(V3<S> e, V3<S> a, V3<S> b, V3<S> g[4]) {
   V3<S> n1 = cross(e, a), n2 = cross(b, e);
   S le = dsqrt(dot(e, e));
-  S r1 = one_over<FAST>(S(dot(n1, n1))), r2 = one_over<FAST>(S(dot(n2, n2))), rl = one_over<FAST>(le);
+  S r1 = one_over(S(dot(n1, n1))), r2 = one_over(S(dot(n2, n2))), rl = one_over(le);
   V3<S> s1 = {n1.x * r1, n1.y * r1, n1.z * r1};
   V3<S> s2 = {n2.x * r2, n2.y * r2, n2.z * r2};
   S c1 = dot(a, e) * rl, c2 = dot(b, e) * rl;
@@ -98,17 +88,16 @@ template <class S, bool FAST = false> __device__ __forceinline__ void bend_gradi
   g[0] = -(g[1] + g[2] + g[3]);
 }
 template <class T> struct BendEval { T C; V3<T> g[4]; bool ok; };
-template <class T, bool FAST = false> __device__ __forceinline__ BendEval<T> bend_eval(V3<T> e, V3<T> a, V3<T> b,
-                                                                                  T theta0) {
+template <class T> __device__ __forceinline__ BendEval<T> bend_eval(V3<T> e, V3<T> a, V3<T> b, T theta0) {
   BendEval<T> r;
   V3<T> n1 = cross(e, a), n2 = cross(b, e);
   T le2 = dot(e, e), q1 = dot(n1, n1), q2 = dot(n2, n2);
   r.ok = le2 > T(0) && q1 > T(0) && q2 > T(0);
   T le = sqrt(le2);
-  T y = dot(cross(n1, n2), e) * recip<FAST>(le);   // 1/|e| is the quotient the gradient forms too
+  T y = dot(cross(n1, n2), e) * (T(1) / le);   // 1/|e| is the quotient the gradient forms too
   T x = dot(n1, n2);
   r.C = atan2(y, x) - theta0;
-  bend_gradient<T, FAST>(e, a, b, r.g);
+  bend_gradient<T>(e, a, b, r.g);
   return r;
 }
 // Hessian of theta times gbar: directional derivative of the gradient along

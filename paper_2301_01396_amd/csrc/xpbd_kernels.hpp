@@ -306,12 +306,12 @@ __device__ __forceinline__ T proj_adjoint(const V3<T> g[N], const T w[N], T iD, 
 // A and Bv hold (xbar, w) of the two vertices; returns true if they changed.
 template <class T>
 __device__ __forceinline__ bool dist_rev(Vec4<T>& A, Vec4<T>& Bv, Vec4<T> tp, T rest, T a_t, T& lbar, T& ab) {
-  DistEval<T> ev = dist_eval<T, true>(V3<T>{tp.x, tp.y, tp.z}, rest);
+  DistEval<T> ev = dist_eval(V3<T>{tp.x, tp.y, tp.z}, rest);
   T Dn = A.w + Bv.w + a_t;
   if (!(ev.ok && Dn > T(0))) return false;
   T lb = tp.w;
-  const T iD = rcp_fast(Dn);
-  T dl = (-ev.C - a_t * lb) * iD;
+  T dl = (-ev.C - a_t * lb) / Dn;
+  const T iD = T(1) / Dn;
   V3<T> xa = xyz(A), xb = xyz(Bv);
   T dlb = lbar + A.w * dot(ev.n, xa) - Bv.w * dot(ev.n, xb);
   // Hessian of |r| is P / |r| (P = I - n n^T); the D-path part of gbar is
@@ -335,14 +335,14 @@ __device__ __forceinline__ bool bend_rev(Vec4<T> P[4], const Vec4<T>* tape, int 
   Vec2<T> tC = reinterpret_cast<const Vec2<T>*>(tape + 2 * count)[t];
   V3<T> e = {tA.x, tA.y, tA.z}, a = {tB.x, tB.y, tB.z}, b = {tB.w, tC.x, tC.y};
   T lb = tA.w;
-  BendEval<T> ev = bend_eval<T, true>(e, a, b, theta0);
+  BendEval<T> ev = bend_eval(e, a, b, theta0);
   T w[4] = {P[0].w, P[1].w, P[2].w, P[3].w};
   T Dn = a_t;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Dn += w[k] * dot(ev.g[k], ev.g[k]);
   if (!(ev.ok && Dn > T(0))) return false;
-  const T iD = rcp_fast(Dn);
-  T dl = (-ev.C - a_t * lb) * iD;
+  T dl = (-ev.C - a_t * lb) / Dn;
+  const T iD = T(1) / Dn;
   V3<T> xb[4] = {xyz(P[0]), xyz(P[1]), xyz(P[2]), xyz(P[3])};
   V3<T> gb[4], hv[4];
   T dlb = proj_adjoint<T, 4>(ev.g, w, iD, dl, lbar, xb, gb);
