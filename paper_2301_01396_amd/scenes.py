@@ -45,7 +45,7 @@ GRAVITY = (0.0, -9.81, 0.0)
 # material (E ~ 1e5 Pa, 1000 kg/m^3) the box sags by its own height and
 # inverts tets within a frame, and the exact gradient grows past FP64's range
 # over 20 frames.  At 0.25 m the 64^3 box settles by about 4% with no tet
-# inverted (smallest volume ratio 0.59 over 20 frames).
+# inverted (smallest volume ratio 0.59 at frame 20).
 TET_SPACING = 0.25
 
 

@@ -30,8 +30,8 @@ def _tet_box_min_ratio(spacing, n=8, frames=20):
 def test_tet_box_on_the_workload_lattice_keeps_every_tet_uninverted():
     """8^3 cubes on the workload's 0.25 m lattice with its moduli and
     schedule: over 20 frames no tet's volume falls below 40% of its rest
-    volume (measured 61%); on a 1/64 m lattice the same box inverts tets
-    (smallest ratio below 0)."""
+    volume (measured 60%); on a 1/64 m lattice the same box inverts tets
+    (smallest ratio -0.50)."""
     assert scenes.TET_SPACING == 0.25
     assert _tet_box_min_ratio(scenes.TET_SPACING) > 0.4
     assert _tet_box_min_ratio(1.0 / 64.0) < 0.0
