@@ -159,6 +159,10 @@ struct xpbd_ctx_s {
   int* contact_vid = nullptr;
   int* contact_order = nullptr;   // per contact set: set-local items by ascending vertex
   void* w = nullptr;              // [V] inverse mass (T)
+  // two device copies of the per-set kernels' parameter block (kDevBlk bytes
+  // each): [0] written and read by forward substeps, [1] by reverse substeps,
+  // so the adjoint's recompute stream and reverse stream never share one
+  void* dev_blk = nullptr;
   // per forward
   void* dist_at = nullptr; void* bend_at = nullptr;
   void* tet_atD = nullptr; void* tet_atH = nullptr; void* tet_gamma = nullptr;
@@ -433,7 +437,7 @@ template <class T> struct Ops {
   }
 
   // ------------------------------------------------------------ plain launches (one per set)
-  static void project(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, V4* tape, hipStream_t st) {
+  static void project(xpbd_ctx c, const Dev<T>* D, const SetInfo& si, bool first, V4* tape, hipStream_t st) {
     if (si.count == 0) return;
     const int bs = c->block;
     unsigned nb = nblocks(si.count, bs);
@@ -463,7 +467,7 @@ template <class T> struct Ops {
     prof_end(c, st, ev, on);
   }
 
-  static void reverse(xpbd_ctx c, const Dev<T>& D, const SetInfo& si, bool first, bool last, const V4* tape,
+  static void reverse(xpbd_ctx c, const Dev<T>* D, const SetInfo& si, bool first, bool last, const V4* tape,
                       hipStream_t st) {
     if (si.count == 0) return;
     const int bs = c->block;
@@ -639,6 +643,12 @@ template <class T> struct Ops {
     for (const void* k : ks) HIPCHK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
 
+  // device copy `which` of the per-set kernels' parameter block
+  static Dev<T>* dev_block(xpbd_ctx c, int which) {
+    static_assert(sizeof(Dev<T>) <= kDevBlk, "parameter block larger than its device slot");
+    return (Dev<T>*)((char*)c->dev_blk + (size_t)which * kDevBlk);
+  }
+
   // body pairing of global substep gsub (frame * S + substep)
   static int* pairs_of(xpbd_ctx c, int gsub) {
     if (!c->n_bc) return nullptr;
@@ -659,6 +669,9 @@ template <class T> struct Ops {
                                                             c->grid, c->b_radius * c->b_radius, (int*)D.bpair);
       check_launch();
     }
+    Dev<T>* blk = dev_block(c, 0);
+    k_store_dev<T><<<1, 64, 0, st>>>(D, blk);
+    check_launch();
     const int ns = (int)c->sets.size();
     for (int it = 0; it < c->K; ++it) {
       Range sweep_("xpbd sweep");
@@ -671,7 +684,7 @@ template <class T> struct Ops {
           continue;
         }
         const SetInfo& si = c->sets[k];
-        project(c, D, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
+        project(c, blk, si, it == 0, slot >= 0 ? tape_at(c, slot, it, si) : nullptr, st);
       }
     }
     k_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
@@ -683,6 +696,9 @@ template <class T> struct Ops {
     Range range_("xpbd reverse substep");
     Dev<T> D = D0;
     if (c->n_bc) D.bpair = pairs_of(c, gsub);
+    Dev<T>* blk = dev_block(c, 1);
+    k_store_dev<T><<<1, 64, 0, st>>>(D, blk);
+    check_launch();
     k_rev_velocity<T><<<nblocks(c->V), kBlock, 0, st>>>(D);
     check_launch();
     for (int it = c->K - 1; it >= 0; --it) {
@@ -696,7 +712,7 @@ template <class T> struct Ops {
           continue;
         }
         const SetInfo& si = c->sets[k];
-        reverse(c, D, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), st);
+        reverse(c, blk, si, it == c->K - 1, it == 0, tape_at(c, slot, it, si), st);
       }
     }
     if (c->K > 0 && dsph)
@@ -1407,6 +1423,7 @@ void build(xpbd_ctx c, const xpbd_mesh_desc* m, const xpbd_constraint_desc* cd, 
   const size_t T_ = c->tsz;
   const size_t V4b = 4 * T_;
   c->w = c->alloc(V * T_);
+  c->dev_blk = c->alloc(2 * kDevBlk);
   c->X = c->alloc(V * V4b);
   c->Vv = c->alloc(V * V4b);
   c->Xp = c->alloc(V * V4b);

@@ -30,6 +30,8 @@ constexpr int kBlock = 256;
 // per-set kernels accept any power-of-two workgroup size up to this
 // (chosen per context; every size computes the same result)
 constexpr int kMaxBlock = 1024;
+// bytes of each device copy of the per-set kernels' parameter block (Dev)
+constexpr size_t kDevBlk = 1024;
 
 template <class T> struct TetRec {
   const int4* idx;
@@ -812,11 +814,16 @@ __device__ __forceinline__ int thread_item(int count) {
   return t < count ? t : -1;
 }
 
+// The per-set kernels read the parameter block from device memory (stored
+// once per substep by k_store_dev): a launch then carries a pointer and three
+// words of arguments instead of the whole block, which matters where the
+// step is a long chain of short dependent launches.
 #define XPBD_SET_KERNEL(NAME, ITEM, TAPE_T)                                                              \
   template <class T, bool F1, bool F2>                                                                   \
-  __global__ __launch_bounds__(kMaxBlock) void NAME(Dev<T> D, int begin, int count, TAPE_T* tape) {      \
+  __global__ __launch_bounds__(kMaxBlock) void NAME(const Dev<T>* __restrict__ Dp, int begin, int count, \
+                                                    TAPE_T* tape) {                                      \
     int t = thread_item(count);                                                                          \
-    if (t >= 0) ITEM<T, F1, F2>(D, begin, count, t, tape);                                               \
+    if (t >= 0) ITEM<T, F1, F2>(*Dp, begin, count, t, tape);                                             \
   }
 XPBD_SET_KERNEL(k_dist, dist_item, Vec4<T>)
 XPBD_SET_KERNEL(k_bend, bend_item, Vec4<T>)
@@ -831,6 +838,11 @@ XPBD_SET_KERNEL(k_contact_rev, contact_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_tri_rev, tri_rev_item, const Vec4<T>)
 XPBD_SET_KERNEL(k_body_rev, body_rev_item, const Vec4<T>)
 #undef XPBD_SET_KERNEL
+
+// one thread stores the parameter block the per-set kernels of a substep read
+template <class T> __global__ __launch_bounds__(64) void k_store_dev(Dev<T> D, Dev<T>* __restrict__ out) {
+  if (threadIdx.x == 0) *out = D;
+}
 
 template <class T> __global__ __launch_bounds__(kBlock) void k_predict(Dev<T> D, const T* f) {
   int k = blockIdx.x * kBlock + threadIdx.x;
